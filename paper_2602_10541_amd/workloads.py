@@ -1,0 +1,287 @@
+"""Seeded synthetic workloads for the FastLSQ hot path.
+
+This module draws inputs only: the frozen features (W, b), collocation points,
+test points, and the manufactured solutions with the PDE data derived from them
+by hand.  It performs none of the method's arithmetic (no assembly, no solve,
+no evaluation of the random-feature expansion), so both the HIP path and the
+CPU oracle can take their inputs from here.
+
+Feature draws follow Section 2.1 / Algorithm 1 (W_j ~ N(0, sigma^2 I),
+b_j ~ U(0, 2 pi)); collocation sampling follows Algorithm 1 (interior points in
+the box, boundary points on its faces).  Every stream comes from
+``numpy.random.SeedSequence(seed).spawn`` so each input is reproducible
+independently of the others; the test set uses ``seed + 1`` (Section 3.1: test
+points from a different seed).
+
+Operators are lists of ``(coef, alpha)`` terms meaning ``sum coef * D^alpha``;
+this is the linear operator of Eq. (2)/(3) written as data.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+import math
+
+import numpy as np
+
+TWO_PI = 2.0 * math.pi
+PI = math.pi
+
+# Stream order inside SeedSequence(seed).spawn(len(STREAMS)).
+STREAMS = ("W", "b", "interior", "boundary", "initial", "obs", "hyp")
+
+# Boundary / initial-condition row weight (Section 3.1, lambda = 100).
+LAM_BC = 100.0
+# Tikhonov weight on ||beta||^2 (Section 2.4 / 3.1, mu = 1e-10).
+MU = 1e-10
+
+
+@dataclass
+class Block:
+    """One row block of the augmented system of Eq. (3).
+
+    ``x`` is ``n x d`` row-major float64, ``terms`` the operator applied on these
+    rows, ``weight`` multiplies both the rows and the data (lambda for boundary
+    rows, 1 for interior rows), ``rhs`` is the unweighted data f or g.
+    """
+    name: str
+    x: np.ndarray
+    terms: list
+    weight: float
+    rhs: np.ndarray
+
+    @property
+    def n(self) -> int:
+        return int(self.x.shape[0])
+
+
+@dataclass
+class Problem:
+    name: str
+    d: int
+    n_feat: int
+    W: np.ndarray          # n_feat x d
+    b: np.ndarray          # n_feat
+    blocks: list
+    mu: float = MU
+    normalize: bool = True
+    x_test: np.ndarray | None = None
+    u_test: np.ndarray | None = None
+    # Pointwise nonlinearity N(u) = sum_k poly[k] u^k on block ``nonlin_block``.
+    nonlin_poly: tuple | None = None
+    nonlin_block: int = -1
+    extras: dict = field(default_factory=dict)
+
+    @property
+    def n_rows(self) -> int:
+        return sum(bl.n for bl in self.blocks)
+
+
+def _rngs(seed: int) -> dict:
+    kids = np.random.SeedSequence(seed).spawn(len(STREAMS))
+    return {name: np.random.Generator(np.random.PCG64(k)) for name, k in zip(STREAMS, kids)}
+
+
+def _unit(d: int, k: int) -> tuple:
+    a = [0] * d
+    a[k] = 1
+    return tuple(a)
+
+
+def _twice(d: int, k: int) -> tuple:
+    a = [0] * d
+    a[k] = 2
+    return tuple(a)
+
+
+def laplacian_terms(d: int, dims, scale: float = 1.0) -> list:
+    """``scale * sum_{k in dims} D^{2 e_k}``."""
+    return [(float(scale), _twice(d, k)) for k in dims]
+
+
+def identity_terms(d: int) -> list:
+    return [(1.0, tuple([0] * d))]
+
+
+def sample_box(rng, n: int, d: int) -> np.ndarray:
+    return rng.uniform(0.0, 1.0, size=(n, d))
+
+
+def sample_faces(rng, n: int, d: int, dims) -> np.ndarray:
+    """Uniform points on the faces {x_k = 0} and {x_k = 1}, k in ``dims``.
+
+    A face is drawn uniformly among the 2*len(dims) faces, then the point is
+    uniform on it (faces of the unit box all have unit measure, so this is
+    uniform on their union).  Coordinates outside ``dims`` stay uniform in [0,1].
+    """
+    dims = list(dims)
+    x = rng.uniform(0.0, 1.0, size=(n, d))
+    face = rng.integers(0, 2 * len(dims), size=n)
+    rows = np.arange(n)
+    x[rows, np.asarray(dims)[face // 2]] = (face % 2).astype(np.float64)
+    return x
+
+
+def draw_features(rngs, n_feat: int, sigma) -> tuple:
+    sigma = np.broadcast_to(np.asarray(sigma, dtype=np.float64), (len(np.atleast_1d(sigma)),))
+    d = sigma.shape[0]
+    W = rngs["W"].normal(0.0, 1.0, size=(n_feat, d)) * sigma[None, :]
+    b = rngs["b"].uniform(0.0, TWO_PI, size=n_feat)
+    return np.ascontiguousarray(W), b
+
+
+def _prod_sin(x: np.ndarray, dims) -> np.ndarray:
+    out = np.ones(x.shape[0])
+    for k in dims:
+        out = out * np.sin(PI * x[:, k])
+    return out
+
+
+# ---------------------------------------------------------------------------
+# The five workloads (shapes, distributions and manufactured solutions).
+# ``n_feat`` / ``counts`` override the sizes for small test instances.
+# ---------------------------------------------------------------------------
+
+def poisson(d: int, n_feat: int, sigma: float, n_int: int, n_bc: int, seed: int = 0,
+            name: str = "poisson", n_test: int = 5000) -> Problem:
+    """-Laplace(u) = f on [0,1]^d, u = prod_k sin(pi x_k), Dirichlet data u."""
+    r = _rngs(seed)
+    W, b = draw_features(r, n_feat, [sigma] * d)
+    xi = sample_box(r["interior"], n_int, d)
+    xb = sample_faces(r["boundary"], n_bc, d, range(d))
+    u = lambda x: _prod_sin(x, range(d))
+    f = d * PI * PI * u(xi)
+    blocks = [
+        Block("interior", xi, laplacian_terms(d, range(d), -1.0), 1.0, f),
+        Block("boundary", xb, identity_terms(d), LAM_BC, u(xb)),
+    ]
+    xt = sample_box(np.random.default_rng(seed + 1), n_test, d)
+    return Problem(name, d, n_feat, W, b, blocks, x_test=xt, u_test=u(xt),
+                   extras={"sigma": sigma, "exact": "prod_k sin(pi x_k)"})
+
+
+def reaction_diffusion(n_feat: int = 2048, sigma: float = 5.0, n_int: int = 16384,
+                       n_bc: int = 2048, seed: int = 0, n_test: int = 5000) -> Problem:
+    """-Laplace(u) + u^3 - u = f on [0,1]^2, u = sin(2 pi x) cos(pi y).
+
+    Laplace(u) = -5 pi^2 u, so f = 5 pi^2 u + u^3 - u.  Linear part
+    L = -Laplace - I, nonlinearity N(u) = u^3 on the interior rows.
+    """
+    d = 2
+    r = _rngs(seed)
+    W, b = draw_features(r, n_feat, [sigma] * d)
+    xi = sample_box(r["interior"], n_int, d)
+    xb = sample_faces(r["boundary"], n_bc, d, range(d))
+    u = lambda x: np.sin(2 * PI * x[:, 0]) * np.cos(PI * x[:, 1])
+    ui = u(xi)
+    f = 5 * PI * PI * ui + ui ** 3 - ui
+    terms = laplacian_terms(d, range(d), -1.0) + [(-1.0, (0, 0))]
+    blocks = [
+        Block("interior", xi, terms, 1.0, f),
+        Block("boundary", xb, identity_terms(d), LAM_BC, u(xb)),
+    ]
+    xt = sample_box(np.random.default_rng(seed + 1), n_test, d)
+    return Problem("reaction_diffusion_2d", d, n_feat, W, b, blocks, x_test=xt, u_test=u(xt),
+                   nonlin_poly=(0.0, 0.0, 0.0, 1.0), nonlin_block=0,
+                   extras={"sigma": sigma, "exact": "sin(2 pi x) cos(pi y)"})
+
+
+def heat(n_feat: int = 8192, sigma=(3.0, 3.0, 3.0, 1.5), n_int: int = 65536, n_ic: int = 16384,
+         n_bc: int = 16384, n_query: int = 1 << 20, seed: int = 0, kappa: float = 0.1,
+         n_test: int = 5000) -> Problem:
+    """u_t = kappa Laplace_x u on [0,1]^3 x [0,1], coordinates (x, y, z, t).
+
+    u = exp(-0.3 pi^2 t) prod_k sin(pi x_k) with kappa = 0.1 solves it exactly
+    (u_t = -0.3 pi^2 u, Laplace_x u = -3 pi^2 u), so the interior data is 0.
+    """
+    d = 4
+    r = _rngs(seed)
+    W, b = draw_features(r, n_feat, sigma)
+    xi = sample_box(r["interior"], n_int, d)
+    xic = sample_box(r["initial"], n_ic, d)
+    xic[:, 3] = 0.0
+    xbc = sample_faces(r["boundary"], n_bc, d, range(3))
+    u = lambda x: np.exp(-0.3 * PI * PI * x[:, 3]) * _prod_sin(x, range(3))
+    terms = [(1.0, (0, 0, 0, 1))] + laplacian_terms(d, range(3), -kappa)
+    blocks = [
+        Block("interior", xi, terms, 1.0, np.zeros(n_int)),
+        Block("initial", xic, identity_terms(d), LAM_BC, u(xic)),
+        Block("boundary", xbc, identity_terms(d), LAM_BC, u(xbc)),
+    ]
+    t_rng = np.random.default_rng(seed + 1)
+    xt = sample_box(t_rng, n_test, d)
+    xq = None
+    if n_query:
+        xq = np.random.default_rng(seed + 2).uniform(0.0, 1.0, size=(n_query, d))
+    return Problem("heat_3d_t", d, n_feat, W, b, blocks, x_test=xt, u_test=u(xt),
+                   extras={"sigma": tuple(sigma), "kappa": kappa, "x_query": xq,
+                           "exact": "exp(-0.3 pi^2 t) prod_k sin(pi x_k)"})
+
+
+def gaussian_source(x: np.ndarray, theta) -> np.ndarray:
+    """s(x; theta) = a exp(-|x - c|^2 / (2 w^2)) over the spatial coordinates (x, y)."""
+    a, cx, cy, w = theta
+    r2 = (x[:, 0] - cx) ** 2 + (x[:, 1] - cy) ** 2
+    return a * np.exp(-r2 / (2.0 * w * w))
+
+
+THETA_TRUE = (1.0, 0.4, 0.6, 0.1)
+
+
+def inverse_heat(n_feat: int = 2048, sigma: float = 4.0, n_int: int = 8192, n_ic: int = 2048,
+                 n_bc: int = 2048, n_obs: int = 400, n_hyp: int = 64, seed: int = 0,
+                 kappa: float = 0.05) -> Problem:
+    """u_t = kappa Laplace_x u + s(x; theta) on [0,1]^2 x [0,1], zero initial and boundary data.
+
+    Interior operator d/dt - kappa Laplace_x; the interior data is the source
+    s(x; theta), which the inverse loop replaces per hypothesis.  Coordinates
+    are (x, y, t).  Observation points are uniform in space-time; the noisy
+    data needs the forward solution at the true theta and is built by the
+    caller with :func:`add_noise`.
+    """
+    d = 3
+    r = _rngs(seed)
+    W, b = draw_features(r, n_feat, [sigma] * d)
+    xi = sample_box(r["interior"], n_int, d)
+    xic = sample_box(r["initial"], n_ic, d)
+    xic[:, 2] = 0.0
+    xbc = sample_faces(r["boundary"], n_bc, d, range(2))
+    terms = [(1.0, (0, 0, 1))] + laplacian_terms(d, range(2), -kappa)
+    blocks = [
+        Block("interior", xi, terms, 1.0, gaussian_source(xi, THETA_TRUE)),
+        Block("initial", xic, identity_terms(d), LAM_BC, np.zeros(n_ic)),
+        Block("boundary", xbc, identity_terms(d), LAM_BC, np.zeros(n_bc)),
+    ]
+    x_obs = sample_box(r["obs"], n_obs, d)
+    hyp = r["hyp"]
+    theta0 = np.stack([hyp.uniform(0.5, 1.5, n_hyp), hyp.uniform(0.2, 0.8, n_hyp),
+                       hyp.uniform(0.2, 0.8, n_hyp), hyp.uniform(0.05, 0.2, n_hyp)], axis=1)
+    noise = r["obs"].standard_normal(n_obs)
+    return Problem("inverse_heat_2d_t", d, n_feat, W, b, blocks,
+                   extras={"sigma": sigma, "kappa": kappa, "x_obs": x_obs, "theta0": theta0,
+                           "theta_true": THETA_TRUE, "noise": noise})
+
+
+def add_noise(u_clean: np.ndarray, noise: np.ndarray, level: float = 0.01) -> np.ndarray:
+    """d_k = u_k + level * RMS(u) * xi_k (relative Gaussian noise)."""
+    rms = float(np.sqrt(np.mean(u_clean ** 2)))
+    return u_clean + level * rms * noise
+
+
+# Named full-size workloads.
+def config(name: str, seed: int = 0, **kw) -> Problem:
+    if name == "poisson2d":      # 2000 interior + 400 boundary, N = 500, sigma = 3, fp64
+        return poisson(2, kw.pop("n_feat", 500), 3.0, kw.pop("n_int", 2000), kw.pop("n_bc", 400),
+                       seed=seed, name="poisson_2d", **kw)
+    if name == "poisson6d":      # 32768 interior + 8192 boundary, N = 4096, sigma = 2
+        return poisson(6, kw.pop("n_feat", 4096), 2.0, kw.pop("n_int", 32768), kw.pop("n_bc", 8192),
+                       seed=seed, name="poisson_6d", **kw)
+    if name == "reaction2d":
+        return reaction_diffusion(seed=seed, **kw)
+    if name == "heat4d":
+        return heat(seed=seed, **kw)
+    if name == "inverse3d":
+        return inverse_heat(seed=seed, **kw)
+    raise KeyError(name)
+
+
+CONFIG_NAMES = ("poisson2d", "poisson6d", "reaction2d", "heat4d", "inverse3d")
