@@ -1,0 +1,228 @@
+/*
+ * fastlsq.h -- C ABI of the MI355X (gfx950) FastLSQ hot path.
+ *
+ * The method (arXiv 2602.10541):
+ *   u_N(x) = (1/sqrt(N)) sum_j beta_j sin(W_j . x + b_j)                     Eq. (1)
+ *   D^alpha phi_j(x) = (prod_k W_jk^alpha_k) Phi_{|alpha| mod 4}(W_j . x + b_j) Eq. (2)
+ *   with Phi_0..3 = sin, cos, -sin, -cos
+ *   A = [A_pde; lambda A_bc], rhs = [f; lambda g]                              Eq. (3)
+ *   beta = argmin ||A beta - rhs||^2 + mu ||beta||^2                          Sections 2.3-2.5
+ *   Newton: J delta = -R, beta += alpha delta, each step a Tikhonov LSQ        Eq. (4)-(5)
+ *
+ * Conventions for every call:
+ *   - Arrays named "device" are caller-owned device pointers on the context's
+ *     device; "host" arrays are caller-owned host memory.  The library only
+ *     allocates its own workspace (owned by the context) and opaque factor
+ *     objects (owned by the caller, released with flsq_factor_free).
+ *   - Matrices are row-major float64 unless stated otherwise.
+ *   - Every call is ordered on the context's HIP stream.  Calls whose control
+ *     flow needs device results (refinement, Newton, factorisation status)
+ *     synchronise that stream before returning; all outputs are valid on return.
+ *   - A non-zero status means the outputs are unspecified; flsq_last_error()
+ *     returns a text description.  Invalid arguments are rejected before any
+ *     kernel is launched.
+ *   - Calls on one context must not overlap (one host thread per context).
+ */
+#ifndef FASTLSQ_H
+#define FASTLSQ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FLSQ_OK = 0,
+    FLSQ_EINVAL = 1,       /* bad argument (sizes, null pointer, multi-index beyond d) */
+    FLSQ_ENOTSPD = 2,      /* Cholesky met a non-positive pivot after all shift retries */
+    FLSQ_ENOCONV = 3,      /* refinement / Newton hit its iteration limit (outputs hold the last iterate) */
+    FLSQ_EHIP = 4,         /* a HIP runtime call failed */
+    FLSQ_ENOMEM = 5,       /* workspace allocation failed */
+    FLSQ_ENONFINITE = 6    /* a NaN or Inf was found in an input or in the result */
+} flsq_status;
+
+/* Arithmetic of the bulk Gram product G = A^T A (Section 2.3, normal equations). */
+typedef enum {
+    FLSQ_PREC_FP64 = 0,          /* FP64 assembly, FP64 MFMA Gram, FP64 Cholesky + refinement */
+    FLSQ_PREC_FP32_REFINE = 1,   /* FP32 assembly + FP32 MFMA Gram -> FP64 Cholesky preconditioner, FP64 refinement */
+    FLSQ_PREC_BF16X3_REFINE = 2  /* FP32 entries split into bf16 hi + lo, three bf16 MFMA products, FP32 accumulate */
+} flsq_precision;
+
+#define FLSQ_MAX_DIM 8
+
+/* One term coef * D^alpha of a linear operator (Eq. (2)); alpha[k] = 0 for k >= d. */
+typedef struct {
+    double coef;
+    uint8_t alpha[FLSQ_MAX_DIM];
+} flsq_term;
+
+/* A linear operator sum_t terms[t].coef * D^{terms[t].alpha}; terms is host memory. */
+typedef struct {
+    const flsq_term* terms;
+    int32_t n_terms;
+} flsq_op;
+
+/* Frozen features (Eq. (1)): W device n_feat x d, b device n_feat; normalize = 1 applies 1/sqrt(N). */
+typedef struct {
+    int32_t d;
+    int32_t n_feat;
+    const double* W;
+    const double* b;
+    int32_t normalize;
+} flsq_basis;
+
+/* One row block of Eq. (3): rows A_ij = weight * op[phi_j](x_i), data weight * rhs_i.
+ * x: device n_rows x d; rhs: device n_rows (unweighted f or g), may be NULL for calls
+ * that take no data. */
+typedef struct {
+    int64_t n_rows;
+    const double* x;
+    flsq_op op;
+    double weight;
+    const double* rhs;
+} flsq_rows;
+
+typedef struct {
+    double mu;            /* Tikhonov weight on ||beta||^2 (absolute) */
+    int32_t prec;         /* flsq_precision */
+    int32_t max_refine;   /* CGLS refinement iterations after the Cholesky solve (>= 0) */
+    double refine_tol;    /* stop when ||step|| <= refine_tol * ||beta|| */
+    double shift_rel;     /* initial Cholesky diagonal shift relative to max diag(G) for the
+                             FP32 / BF16x3 preconditioner (0 = automatic) */
+} flsq_solve_opts;
+
+typedef struct {
+    int32_t refine_iters;   /* refinement iterations performed */
+    int32_t chol_retries;   /* Cholesky restarts with a larger shift */
+    double shift;           /* absolute diagonal shift used in the factor (0 for FP64 unless retried) */
+    double grad_norm0;      /* ||A^T (rhs - A beta) - mu beta|| after the Cholesky solve */
+    double grad_norm;       /* same, at the returned beta */
+    double last_step_rel;   /* ||last refinement step|| / ||beta|| */
+    double t_gram_ms, t_chol_ms, t_refine_ms, t_total_ms;
+} flsq_solve_info;
+
+typedef struct flsq_ctx flsq_ctx;
+typedef struct flsq_factor flsq_factor;
+
+/* Context bound to HIP device `device` and stream `hip_stream` (a hipStream_t; NULL = the
+ * default stream).  Returns FLSQ_EHIP if the device cannot be selected. */
+flsq_status flsq_create(flsq_ctx** ctx, int device, void* hip_stream);
+void flsq_destroy(flsq_ctx* ctx);
+const char* flsq_last_error(const flsq_ctx* ctx);
+/* Library version and the offload architecture it was built for (static strings). */
+const char* flsq_build_info(void);
+
+/* Assembly to HBM (Eq. (2)-(3)): A_out is device P x n_feat row-major, P = sum of block rows,
+ * float64 if fp32 == 0, float32 otherwise; rhs_out (nullable) device P float64 = weight * rhs.
+ * A debugging / checking path: the solvers never write A to memory. */
+flsq_status flsq_assemble(flsq_ctx* ctx, const flsq_basis* basis, const flsq_rows* blocks, int32_t n_blocks,
+                          int32_t fp32, void* A_out, double* rhs_out);
+
+/* Gram product of the stacked blocks without forming A (fused assembly + MFMA):
+ * G_out device n_feat x n_feat float64 (full symmetric) = A^T A computed in precision `prec`
+ * (mu is NOT added).  c_out (nullable) device n_feat = A^T rhs_w computed in FP64. */
+flsq_status flsq_gram(flsq_ctx* ctx, const flsq_basis* basis, const flsq_rows* blocks, int32_t n_blocks,
+                      int32_t prec, double* G_out, double* c_out);
+
+/* Linear solve (Algorithm 1 with the Tikhonov weight of Section 2.4): beta_out device n_feat.
+ * Normal equations (A^T A + mu I) beta = A^T rhs_w: Gram in opts->prec, FP64 Cholesky, then
+ * CGLS refinement with FP64 matrix-free products A v and A^T y, preconditioned by the factor.
+ * info may be NULL.  Returns FLSQ_ENOCONV if refinement did not reach refine_tol within
+ * max_refine iterations (beta_out then holds the last iterate). */
+flsq_status flsq_solve_linear(flsq_ctx* ctx, const flsq_basis* basis, const flsq_rows* blocks, int32_t n_blocks,
+                              const flsq_solve_opts* opts, double* beta_out, flsq_solve_info* info);
+
+/* Factor object (Section 2.5: "gradients flow through the pre-factored linear solve";
+ * the inverse application factors once and reuses the factor for every right-hand side).
+ * Copies the basis and block geometry to the device; the caller's arrays may be freed after. */
+flsq_status flsq_factorize(flsq_ctx* ctx, const flsq_basis* basis, const flsq_rows* blocks, int32_t n_blocks,
+                           const flsq_solve_opts* opts, flsq_factor** F, flsq_solve_info* info);
+void flsq_factor_free(flsq_factor* F);
+/* Number of rows P and features N of a factor (host outputs). */
+flsq_status flsq_factor_shape(const flsq_factor* F, int64_t* n_rows, int32_t* n_feat);
+
+/* Multi-RHS least squares with the cached factor: rhs_rows device P x K (already weighted,
+ * i.e. rows of the stacked right-hand side), beta_out device n_feat x K. */
+flsq_status flsq_factor_solve(flsq_ctx* ctx, const flsq_factor* F, const double* rhs_rows, int32_t K,
+                              double* beta_out, flsq_solve_info* info);
+/* out = (A^T A + mu I)^{-1} V, V and out device n_feat x K, refined with FP64 matrix-free products. */
+flsq_status flsq_factor_solve_normal(flsq_ctx* ctx, const flsq_factor* F, const double* V, int32_t K,
+                                     double* out);
+/* out = A V (device P x K) and out = A^T Y (device n_feat x K), FP64, matrix-free. */
+flsq_status flsq_apply_A(flsq_ctx* ctx, const flsq_factor* F, const double* V, int32_t K, double* out);
+flsq_status flsq_apply_At(flsq_ctx* ctx, const flsq_factor* F, const double* Y, int32_t K, double* out);
+
+/* Evaluation of D^alpha u_N at query points (Eq. (1)-(2)).
+ * beta: device n_feat float64.  xq: device n_q x d, float32 if xq_is_fp32 else float64.
+ * alphas: host n_alpha x d uint8 multi-indices.  out: device n_q x n_alpha, same dtype as xq. */
+flsq_status flsq_evaluate(flsq_ctx* ctx, const flsq_basis* basis, const double* beta, int64_t n_q,
+                          const void* xq, int32_t xq_is_fp32, const uint8_t* alphas, int32_t n_alpha,
+                          void* out);
+
+/* Pointwise nonlinearity N(u) = sum_k poly[k] u^k (host array) applied on one row block. */
+typedef struct {
+    int32_t n_poly;
+    const double* poly;
+} flsq_nonlin;
+
+typedef struct {
+    flsq_solve_opts lin;    /* per-step linear solve */
+    double tol_dbeta;       /* stop when ||alpha delta||_2 < tol_dbeta */
+    int32_t max_iter;       /* Newton steps after the warm start */
+    double armijo_c;        /* sufficient decrease ||R(beta + a d)|| <= (1 - c a) ||R(beta)|| */
+    int32_t max_halvings;   /* backtracking halvings before the smallest step is taken */
+    int32_t warm_start;     /* 1: beta_inout is overwritten by the linear solve with N dropped */
+} flsq_newton_opts;
+
+typedef struct {
+    int32_t iters;                   /* Newton steps taken */
+    int32_t converged;               /* ||alpha delta|| < tol_dbeta reached */
+    double res_norm[64];             /* ||R|| at the start of each step */
+    double alpha[64];
+    double step_norm[64];            /* ||alpha delta|| */
+    double du_rel[64];               /* ||Delta u|| / ||u|| at collocation rows */
+    int32_t halvings[64];
+    double t_total_ms;
+} flsq_newton_trace;
+
+/* Newton-Raphson for L[u] + N(u) = f (Section 2.4).  The nonlinearity acts on block
+ * `nonlin_block`, whose operator must contain only even-order terms (the Jacobian
+ * row coefficient N'(u_i) multiplies phi_j = sin, Eq. (2) with |alpha| = 0).
+ * beta_inout: device n_feat.  trace may be NULL.  max_iter <= 64. */
+flsq_status flsq_solve_newton(flsq_ctx* ctx, const flsq_basis* basis, const flsq_rows* blocks, int32_t n_blocks,
+                              int32_t nonlin_block, const flsq_nonlin* nonlin, const flsq_newton_opts* opts,
+                              double* beta_inout, flsq_newton_trace* trace);
+
+/* ---- Inverse heat-source support (Section 2.5 and the inverse heat-source application) ----
+ * Source s(x; theta) = a exp(-((x0 - cx)^2 + (x1 - cy)^2) / (2 w^2)), theta = (a, cx, cy, w).
+ * The factor F is built for the full system; the source acts on its first `n_src_rows` rows
+ * (the interior block, row weight `src_weight`), the remaining rows carry zero data. */
+
+/* Misfit and gradients for K hypotheses in one call:
+ *   B = (A^T A + mu I)^{-1} A^T rhs(theta_h)   (refined with the cached factor)
+ *   U = H B, H_kj = phi_j(x_obs,k) (with 1/sqrt(N)), L_h = mean_k (U_kh - data_k)^2
+ *   Lam = (A^T A + mu I)^{-1} H^T (2/n_obs)(U - data)
+ *   dL_h/dtheta_h = (A Lam_h)^T d rhs_h / d theta_h
+ *   dL_h/dkappa   = (A_k Lam_h)^T (rhs_h - A B_h) - (A Lam_h)^T (A_k B_h)
+ * where A_k = dA/dkappa: the interior operator is d/dt - kappa Laplace_x, so A_k is the
+ * row-block assembly of +(sum_k D^{2 e_k}) over `n_lap_dims` leading coordinates, negated.
+ * thetas: device K x 4; x_obs: device n_obs x d; data: device n_obs.
+ * loss_out: device K; grad_theta_out: device K x 4; grad_kappa_out: device K (nullable). */
+flsq_status flsq_inverse_loss_grad(flsq_ctx* ctx, const flsq_factor* F, int64_t n_src_rows, double src_weight,
+                                   int32_t n_lap_dims, const double* thetas, int32_t K, int64_t n_obs,
+                                   const double* x_obs, const double* data, double* loss_out,
+                                   double* grad_theta_out, double* grad_kappa_out);
+
+/* Batched Adam step on K x P parameters (all device arrays, updated in place):
+ * m = b1 m + (1 - b1) g; v = b2 v + (1 - b2) g^2; p -= lr * (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps);
+ * then p[:, clamp_col] = max(p[:, clamp_col], clamp_min) when clamp_col >= 0. */
+flsq_status flsq_adam_step(flsq_ctx* ctx, double* params, const double* grads, double* m, double* v, int32_t K,
+                           int32_t P, int32_t t, double lr, double b1, double b2, double eps, int32_t clamp_col,
+                           double clamp_min);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FASTLSQ_H */

@@ -1,0 +1,973 @@
+// libfastlsq: C ABI and host drivers of the MI355X FastLSQ hot path.
+//
+// Drivers (all FP64 control, kernels in k_*.hip):
+//   solve:   Gram (fused assembly + MFMA) -> + mu I -> blocked Cholesky G = U^T U
+//            -> beta0 = U^{-1} U^{-T} A^T rhs -> CGLS refinement with FP64 matrix-free
+//            products, preconditioned by U (Sections 2.3-2.5: Tikhonov least squares).
+//   newton:  warm start (linear part), then per step residual R and Jacobian row
+//            coefficient N'(u) (FP64), Gram of J, factor, solve J delta = -R in the
+//            Tikhonov sense, Armijo backtracking on ||R|| (Section 2.4, Eq. (4)-(5)).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/fastlsq.h"
+#include "flsq_launch.h"
+
+using namespace flsq;
+
+namespace {
+
+// ------------------------------------------------------------------ device buffers
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  hipError_t ensure(size_t b) {
+    if (b <= bytes && p) return hipSuccess;
+    release();
+    if (b == 0) b = 256;
+    hipError_t e = hipMalloc(&p, b);
+    if (e != hipSuccess) {
+      p = nullptr;
+      return e;
+    }
+    bytes = b;
+    return hipSuccess;
+  }
+  template <typename T>
+  T* as() const { return static_cast<T*>(p); }
+};
+
+struct Err {
+  flsq_status st;
+  std::string msg;
+};
+
+#define CHECK_HIP(expr)                                                                   \
+  do {                                                                                    \
+    hipError_t e__ = (expr);                                                              \
+    if (e__ != hipSuccess)                                                                \
+      return Err{e__ == hipErrorOutOfMemory ? FLSQ_ENOMEM : FLSQ_EHIP,                    \
+                 std::string(#expr) + ": " + hipGetErrorString(e__)};                     \
+  } while (0)
+
+#define CHECK_ERR(expr)              \
+  do {                               \
+    Err e__ = (expr);                \
+    if (e__.st != FLSQ_OK) return e__; \
+  } while (0)
+
+inline Err ok() { return Err{FLSQ_OK, ""}; }
+inline Err fail(flsq_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  return Err{s, buf};
+}
+
+double now_ms() {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// ------------------------------------------------------------------ problem on the device
+struct System {
+  int d = 0, n = 0, n_blocks = 0;
+  int64_t P = 0;
+  double norm = 1.0;
+  std::vector<int64_t> row0;          // per block
+  std::vector<int64_t> rows;
+  std::vector<double> weight;
+  std::vector<int> even;              // operator has even-order terms only
+  DevBuf Wt, Wt32, bvec, amp, ph, amp32, ph32, Xt, Xt32, row_block, rhs_w, chunks, runs;
+  int n_chunks = 0, n_runs = 0;
+  // Gram plan
+  int nt = 0, n_wg = 0, max_seg = 0;
+  int64_t total_units = 0, units_per_wg = 0;
+  DevBuf slot_ptr, slots;
+
+  Geo geo() const {
+    Geo g;
+    g.d = d;
+    g.n = n;
+    g.P = P;
+    g.n_blocks = n_blocks;
+    g.Wt = Wt.as<double>();
+    g.Wt32 = Wt32.as<float>();
+    g.amp = amp.as<double>();
+    g.ph = ph.as<double>();
+    g.amp32 = amp32.as<float>();
+    g.ph32 = ph32.as<float>();
+    g.Xt = Xt.as<double>();
+    g.Xt32 = Xt32.as<float>();
+    g.row_block = row_block.as<int32_t>();
+    return g;
+  }
+  PassGeo pass() const {
+    PassGeo pg;
+    pg.g = geo();
+    pg.runs = runs.as<Chunk>();
+    pg.n_runs = n_runs;
+    return pg;
+  }
+};
+
+}  // namespace
+
+struct flsq_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int n_cu = 256;
+  std::string err;
+  std::map<std::string, DevBuf> ws;
+  System sys;                        // cached system of the last solve_linear / gram / newton call
+};
+
+struct flsq_factor {
+  int device = 0;
+  System sys;
+  DevBuf U;                          // upper Cholesky factor, n x n row-major
+  double mu = 0.0;
+  double shift = 0.0;
+  int max_refine = 0;
+  double refine_tol = 0.0;
+};
+
+namespace {
+
+DevBuf& wsb(flsq_ctx* c, const std::string& name) { return c->ws[name]; }
+
+template <typename T>
+Err ws_get(flsq_ctx* c, const std::string& name, size_t count, T** out) {
+  DevBuf& b = wsb(c, name);
+  CHECK_HIP(b.ensure(count * sizeof(T)));
+  *out = b.as<T>();
+  return ok();
+}
+
+Err set_status(flsq_ctx* c, const Err& e) {
+  if (c) c->err = e.msg;
+  return e;
+}
+
+// ------------------------------------------------------------------ validation
+Err check_basis(const flsq_basis* b) {
+  if (!b) return fail(FLSQ_EINVAL, "basis is NULL");
+  if (b->d < 1 || b->d > FLSQ_MAX_DIM) return fail(FLSQ_EINVAL, "basis.d = %d outside [1, %d]", b->d, FLSQ_MAX_DIM);
+  if (b->n_feat < 1) return fail(FLSQ_EINVAL, "basis.n_feat = %d < 1", b->n_feat);
+  if (!b->W || !b->b) return fail(FLSQ_EINVAL, "basis.W or basis.b is NULL");
+  return ok();
+}
+
+Err check_op(const flsq_op& op, int d, int bi) {
+  if (op.n_terms < 1 || op.n_terms > 32) return fail(FLSQ_EINVAL, "block %d: n_terms = %d outside [1, 32]", bi, op.n_terms);
+  if (!op.terms) return fail(FLSQ_EINVAL, "block %d: terms is NULL", bi);
+  for (int t = 0; t < op.n_terms; ++t) {
+    for (int k = d; k < FLSQ_MAX_DIM; ++k)
+      if (op.terms[t].alpha[k] != 0)
+        return fail(FLSQ_EINVAL, "block %d term %d: multi-index has alpha[%d] = %d beyond d = %d", bi, t, k,
+                    op.terms[t].alpha[k], d);
+    if (!std::isfinite(op.terms[t].coef)) return fail(FLSQ_ENONFINITE, "block %d term %d: coefficient not finite", bi, t);
+  }
+  return ok();
+}
+
+Err check_blocks(const flsq_rows* blocks, int n_blocks, int d, bool need_rhs) {
+  if (n_blocks < 1 || !blocks) return fail(FLSQ_EINVAL, "need at least one row block");
+  int64_t P = 0;
+  for (int i = 0; i < n_blocks; ++i) {
+    const flsq_rows& r = blocks[i];
+    if (r.n_rows < 0) return fail(FLSQ_EINVAL, "block %d: n_rows < 0", i);
+    if (r.n_rows > 0 && !r.x) return fail(FLSQ_EINVAL, "block %d: x is NULL", i);
+    if (need_rhs && r.n_rows > 0 && !r.rhs) return fail(FLSQ_EINVAL, "block %d: rhs is NULL", i);
+    if (!std::isfinite(r.weight)) return fail(FLSQ_ENONFINITE, "block %d: weight not finite", i);
+    CHECK_ERR(check_op(r.op, d, i));
+    P += r.n_rows;
+  }
+  if (P < 1) return fail(FLSQ_EINVAL, "no rows");
+  if (P > (int64_t)0x7fffffff) return fail(FLSQ_EINVAL, "more than 2^31 - 1 rows");
+  return ok();
+}
+
+Err check_finite_dev(flsq_ctx* c, const double* p, int64_t n, const char* what) {
+  int* flag;
+  CHECK_ERR(ws_get(c, "nf_flag", 1, &flag));
+  CHECK_HIP(hipMemsetAsync(flag, 0, sizeof(int), c->stream));
+  CHECK_HIP(launch_count_nonfinite(p, n, flag, c->stream));
+  int h = 0;
+  CHECK_HIP(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  CHECK_HIP(hipStreamSynchronize(c->stream));
+  if (h) return fail(FLSQ_ENONFINITE, "%s contains NaN or Inf", what);
+  return ok();
+}
+
+// ------------------------------------------------------------------ system setup
+std::vector<Chunk> make_runs(const System& s, int run_rows) {
+  std::vector<Chunk> v;
+  for (int b = 0; b < s.n_blocks; ++b) {
+    for (int64_t r = 0; r < s.rows[b]; r += run_rows) {
+      Chunk c;
+      c.row0 = (int32_t)(s.row0[b] + r);
+      c.nrows = (int32_t)std::min<int64_t>(run_rows, s.rows[b] - r);
+      c.block = b;
+      c.pad = 0;
+      v.push_back(c);
+    }
+  }
+  return v;
+}
+
+Err build_system(flsq_ctx* c, System& s, const flsq_basis* basis, const flsq_rows* blocks, int n_blocks,
+                 bool need_rhs) {
+  CHECK_ERR(check_basis(basis));
+  CHECK_ERR(check_blocks(blocks, n_blocks, basis->d, need_rhs));
+  hipStream_t st = c->stream;
+  s.d = basis->d;
+  s.n = basis->n_feat;
+  s.n_blocks = n_blocks;
+  s.norm = basis->normalize ? 1.0 / std::sqrt((double)s.n) : 1.0;
+  s.row0.assign(n_blocks, 0);
+  s.rows.assign(n_blocks, 0);
+  s.weight.assign(n_blocks, 0.0);
+  s.even.assign(n_blocks, 1);
+  int64_t P = 0;
+  for (int i = 0; i < n_blocks; ++i) {
+    s.row0[i] = P;
+    s.rows[i] = blocks[i].n_rows;
+    s.weight[i] = blocks[i].weight;
+    for (int t = 0; t < blocks[i].op.n_terms; ++t) {
+      int ord = 0;
+      for (int k = 0; k < s.d; ++k) ord += blocks[i].op.terms[t].alpha[k];
+      if (ord & 1) s.even[i] = 0;
+    }
+    P += blocks[i].n_rows;
+  }
+  s.P = P;
+  const int n = s.n, d = s.d;
+  CHECK_HIP(s.Wt.ensure(sizeof(double) * d * n));
+  CHECK_HIP(s.Wt32.ensure(sizeof(float) * d * n));
+  CHECK_HIP(s.bvec.ensure(sizeof(double) * n));
+  CHECK_HIP(s.amp.ensure(sizeof(double) * n_blocks * n));
+  CHECK_HIP(s.ph.ensure(sizeof(double) * n_blocks * n));
+  CHECK_HIP(s.amp32.ensure(sizeof(float) * n_blocks * n));
+  CHECK_HIP(s.ph32.ensure(sizeof(float) * n_blocks * n));
+  CHECK_HIP(s.Xt.ensure(sizeof(double) * d * P));
+  CHECK_HIP(s.Xt32.ensure(sizeof(float) * d * P));
+  CHECK_HIP(s.row_block.ensure(sizeof(int32_t) * P));
+  CHECK_HIP(s.rhs_w.ensure(sizeof(double) * P));
+
+  CHECK_HIP(launch_transpose(basis->W, n, d, s.Wt.as<double>(), s.Wt32.as<float>(), n, st));
+  CHECK_HIP(hipMemcpyAsync(s.bvec.p, basis->b, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+  for (int i = 0; i < n_blocks; ++i) {
+    const flsq_rows& r = blocks[i];
+    OpTerms op;
+    memset(&op, 0, sizeof op);
+    op.n_terms = r.op.n_terms;
+    for (int t = 0; t < op.n_terms; ++t) {
+      op.coef[t] = r.op.terms[t].coef;
+      for (int k = 0; k < kMaxDim; ++k) op.alpha[t][k] = r.op.terms[t].alpha[k];
+    }
+    CHECK_HIP(launch_prep_block(op, r.weight, s.norm, d, n, basis->W, basis->b, s.amp.as<double>() + (int64_t)i * n,
+                                s.ph.as<double>() + (int64_t)i * n, s.amp32.as<float>() + (int64_t)i * n,
+                                s.ph32.as<float>() + (int64_t)i * n, st));
+    if (r.n_rows > 0) {
+      CHECK_HIP(launch_transpose(r.x, r.n_rows, d, s.Xt.as<double>() + s.row0[i], s.Xt32.as<float>() + s.row0[i], P,
+                                 st));
+      CHECK_HIP(launch_fill_i32(s.row_block.as<int32_t>() + s.row0[i], r.n_rows, i, st));
+      CHECK_HIP(launch_scale_copy(r.rhs, s.rhs_w.as<double>() + s.row0[i], r.n_rows, r.weight, st));
+    }
+  }
+  // Gram chunks and pass runs (block-aligned), Gram stream-K plan
+  std::vector<Chunk> ch = make_runs(s, gram_chunk_rows());
+  std::vector<Chunk> rn = make_runs(s, pass_rows());
+  s.n_chunks = (int)ch.size();
+  s.n_runs = (int)rn.size();
+  CHECK_HIP(s.chunks.ensure(sizeof(Chunk) * ch.size()));
+  CHECK_HIP(s.runs.ensure(sizeof(Chunk) * rn.size()));
+  CHECK_HIP(hipMemcpyAsync(s.chunks.p, ch.data(), sizeof(Chunk) * ch.size(), hipMemcpyHostToDevice, st));
+  CHECK_HIP(hipMemcpyAsync(s.runs.p, rn.data(), sizeof(Chunk) * rn.size(), hipMemcpyHostToDevice, st));
+
+  const int T = gram_tile();
+  s.nt = (n + T - 1) / T;
+  const int64_t n_tiles = (int64_t)s.nt * (s.nt + 1) / 2;
+  s.total_units = n_tiles * s.n_chunks;
+  const int slots_hw = c->n_cu * std::max(1, gram_occupancy(0));
+  const int64_t min_units = 8;
+  int64_t nwg = std::min<int64_t>(slots_hw, (s.total_units + min_units - 1) / min_units);
+  nwg = std::max<int64_t>(1, nwg);
+  s.units_per_wg = (s.total_units + nwg - 1) / nwg;
+  s.n_wg = (int)((s.total_units + s.units_per_wg - 1) / s.units_per_wg);
+  s.max_seg = (int)((s.units_per_wg + s.n_chunks - 1) / s.n_chunks) + 1;
+  std::vector<std::vector<int32_t>> per_tile(n_tiles);
+  for (int w = 0; w < s.n_wg; ++w) {
+    int64_t u = (int64_t)w * s.units_per_wg;
+    const int64_t ue = std::min(u + s.units_per_wg, s.total_units);
+    int seg = 0;
+    while (u < ue) {
+      const int64_t t = u / s.n_chunks;
+      const int64_t c0 = u % s.n_chunks;
+      const int64_t c1 = std::min<int64_t>(s.n_chunks, c0 + (ue - u));
+      per_tile[t].push_back(w * s.max_seg + seg);
+      ++seg;
+      u += c1 - c0;
+    }
+    if (seg > s.max_seg) return fail(FLSQ_EINVAL, "internal: Gram plan segment overflow");
+  }
+  std::vector<int32_t> ptr(n_tiles + 1, 0), sl;
+  for (int64_t t = 0; t < n_tiles; ++t) {
+    ptr[t + 1] = ptr[t] + (int32_t)per_tile[t].size();
+    sl.insert(sl.end(), per_tile[t].begin(), per_tile[t].end());
+  }
+  CHECK_HIP(s.slot_ptr.ensure(sizeof(int32_t) * ptr.size()));
+  CHECK_HIP(s.slots.ensure(sizeof(int32_t) * std::max<size_t>(1, sl.size())));
+  CHECK_HIP(hipMemcpyAsync(s.slot_ptr.p, ptr.data(), sizeof(int32_t) * ptr.size(), hipMemcpyHostToDevice, st));
+  CHECK_HIP(hipMemcpyAsync(s.slots.p, sl.data(), sizeof(int32_t) * sl.size(), hipMemcpyHostToDevice, st));
+  // the host vectors go out of scope: make the copies complete first
+  CHECK_HIP(hipStreamSynchronize(st));
+  CHECK_ERR(check_finite_dev(c, s.Xt.as<double>(), (int64_t)d * P, "collocation points"));
+  CHECK_ERR(check_finite_dev(c, s.Wt.as<double>(), (int64_t)d * n, "W"));
+  CHECK_ERR(check_finite_dev(c, s.bvec.as<double>(), n, "b"));
+  if (need_rhs) CHECK_ERR(check_finite_dev(c, s.rhs_w.as<double>(), P, "right-hand side"));
+  return ok();
+}
+
+// ------------------------------------------------------------------ Gram
+// G (n x n) gets the Gram product of the stacked rows; upper triangle only unless mirror.
+Err run_gram(flsq_ctx* c, const System& s, int prec, const double* rho, double* G, int mirror, double diag_add) {
+  const int T = gram_tile();
+  const size_t part_elems = (size_t)s.n_wg * s.max_seg * T * T;
+  void* partial;
+  if (prec == FLSQ_PREC_FP64) {
+    double* p;
+    CHECK_ERR(ws_get(c, "gram_partial", part_elems, &p));
+    partial = p;
+  } else {
+    float* p;
+    CHECK_ERR(ws_get(c, "gram_partial", part_elems, &p));
+    partial = p;
+  }
+  float* rho32 = nullptr;
+  if (rho && prec != FLSQ_PREC_FP64) {
+    CHECK_ERR(ws_get(c, "rho32", (size_t)s.P, &rho32));
+    CHECK_HIP(launch_to_f32(rho, rho32, s.P, c->stream));
+  }
+  GramLaunch L;
+  L.g = s.geo();
+  L.prec = prec == FLSQ_PREC_FP64 ? 0 : 1;
+  L.rho = rho;
+  L.rho32 = rho32;
+  L.chunks = s.chunks.as<Chunk>();
+  L.n_chunks = s.n_chunks;
+  L.nt = s.nt;
+  L.total_units = s.total_units;
+  L.units_per_wg = s.units_per_wg;
+  L.max_seg = s.max_seg;
+  L.n_wg = s.n_wg;
+  L.partial = partial;
+  CHECK_HIP(launch_gram(L, c->stream));
+  CHECK_HIP(launch_gram_reduce(L.prec, partial, s.slot_ptr.as<int32_t>(), s.slots.as<int32_t>(), s.nt, s.n, G, mirror,
+                               diag_add, c->stream));
+  return ok();
+}
+
+// ------------------------------------------------------------------ Cholesky
+// In-place upper Cholesky of G (only the upper triangle is read).  Returns info > 0 at
+// the first non-positive pivot (1-based column).
+Err cholesky(flsq_ctx* c, double* G, int n, int* info_host) {
+  int* info;
+  CHECK_ERR(ws_get(c, "chol_info", 1, &info));
+  CHECK_HIP(hipMemsetAsync(info, 0, sizeof(int), c->stream));
+  for (int k0 = 0; k0 < n; k0 += kNb) {
+    CHECK_HIP(launch_potrf_diag(G, n, k0, info, 0.0, c->stream));
+    CHECK_HIP(launch_trsm_row(G, n, k0, c->stream));
+    CHECK_HIP(launch_syrk(G, n, k0, c->stream));
+  }
+  CHECK_HIP(hipMemcpyAsync(info_host, info, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  CHECK_HIP(hipStreamSynchronize(c->stream));
+  return ok();
+}
+
+// X = (U^T U)^{-1} Y for K columns (Y preserved).
+Err chol_solve(flsq_ctx* c, const double* U, int n, const double* Y, double* X, int K) {
+  double *t1, *t2;
+  CHECK_ERR(ws_get(c, "cs_t1", (size_t)n * K, &t1));
+  CHECK_ERR(ws_get(c, "cs_t2", (size_t)n * K, &t2));
+  CHECK_HIP(hipMemcpyAsync(t1, Y, sizeof(double) * n * K, hipMemcpyDeviceToDevice, c->stream));
+  CHECK_HIP(launch_trsv_fwd(U, n, t1, t2, K, c->stream));   // t2 = U^{-T} Y
+  CHECK_HIP(launch_trsv_bwd(U, n, t2, X, K, c->stream));    // X = U^{-1} t2
+  return ok();
+}
+
+// Factor G_src + diag_add I into U.  For the FP64 Gram the first attempt uses no shift;
+// a failed pivot retries with growing shifts relative to max diag(G).  Returns the shift used.
+Err factor_with_retries(flsq_ctx* c, const double* Gsrc, double* U, int n, double mu, double shift0_rel,
+                        double* shift_used, int* retries) {
+  double* dmax;
+  CHECK_ERR(ws_get(c, "diag_max", 1, &dmax));
+  CHECK_HIP(launch_diag_max(Gsrc, n, dmax, c->stream));
+  double dm = 0.0;
+  CHECK_HIP(hipMemcpyAsync(&dm, dmax, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  CHECK_HIP(hipStreamSynchronize(c->stream));
+  if (!std::isfinite(dm)) return fail(FLSQ_ENONFINITE, "Gram diagonal is not finite");
+  double rel = shift0_rel;
+  *retries = 0;
+  for (int attempt = 0; attempt < 8; ++attempt) {
+    const double shift = rel * dm;
+    CHECK_HIP(launch_copy_upper(Gsrc, U, n, mu + shift, c->stream));
+    int info = 0;
+    CHECK_ERR(cholesky(c, U, n, &info));
+    if (info == 0) {
+      *shift_used = shift;
+      return ok();
+    }
+    ++*retries;
+    rel = (rel == 0.0) ? 1e-15 : rel * 10.0;
+  }
+  return fail(FLSQ_ENOTSPD, "Cholesky failed: Gram + mu I not positive definite after %d shift retries", *retries);
+}
+
+// ------------------------------------------------------------------ CGLS refinement
+// Minimise ||Y - A X||^2 + mu ||X||^2 column-wise, starting from X, preconditioned by U
+// (U^T U ~ A^T A + mu I).  Y is P x K (weighted data).  On return X is refined.
+struct RefineOut {
+  int iters = 0;
+  double grad0 = 0.0, grad = 0.0, last_step = 0.0;
+  bool converged = false;
+};
+
+Err host_cols(flsq_ctx* c, const double* dev, int K, std::vector<double>& h) {
+  h.resize(K);
+  CHECK_HIP(hipMemcpyAsync(h.data(), dev, sizeof(double) * K, hipMemcpyDeviceToHost, c->stream));
+  CHECK_HIP(hipStreamSynchronize(c->stream));
+  return ok();
+}
+
+Err to_dev_cols(flsq_ctx* c, const std::vector<double>& h, double* dev) {
+  CHECK_HIP(hipMemcpyAsync(dev, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice, c->stream));
+  CHECK_HIP(hipStreamSynchronize(c->stream));
+  return ok();
+}
+
+Err cgls_refine(flsq_ctx* c, const System& s, const double* rho, const double* U, double mu, const double* Y, int K,
+                double* X, int max_iter, double tol, bool want_grad, RefineOut* ro) {
+  const int n = s.n;
+  const int64_t P = s.P;
+  const PassGeo pg = s.pass();
+  double *sres, *q, *g, *z, *p, *dots, *dwork, *colwork, *scal;
+  CHECK_ERR(ws_get(c, "cg_s", (size_t)P * K, &sres));
+  CHECK_ERR(ws_get(c, "cg_q", (size_t)P * K, &q));
+  CHECK_ERR(ws_get(c, "cg_g", (size_t)n * K, &g));
+  CHECK_ERR(ws_get(c, "cg_z", (size_t)n * K, &z));
+  CHECK_ERR(ws_get(c, "cg_p", (size_t)n * K, &p));
+  CHECK_ERR(ws_get(c, "cg_dots", (size_t)8 * K, &dots));
+  CHECK_ERR(ws_get(c, "cg_dwork", (size_t)512 * K + 64, &dwork));
+  CHECK_ERR(ws_get(c, "cg_colwork", pass_work_elems(n, s.n_runs, K) + 64, &colwork));
+  CHECK_ERR(ws_get(c, "cg_scal", (size_t)K, &scal));
+  hipStream_t st = c->stream;
+  std::vector<double> gam, del, tmp, tmp2, alpha(K), beta(K), stepn(K), xn(K);
+
+  // s = Y - A X ; g = A^T s - mu X
+  CHECK_HIP(launch_rowpass_runs(pg, rho, X, K, Y, -1.0, 1.0, sres, st));
+  CHECK_HIP(launch_colpass_runs(pg, rho, sres, K, X, 1.0, -mu, g, colwork, st));
+  if (want_grad) {
+    CHECK_HIP(launch_dot_cols(g, g, n, K, dots, dwork, st));
+    CHECK_ERR(host_cols(c, dots, K, tmp));
+    double m = 0;
+    for (double v : tmp) m = std::max(m, std::sqrt(v));
+    ro->grad0 = m;
+  }
+  ro->iters = 0;
+  ro->converged = (max_iter == 0);
+  if (max_iter == 0) {
+    ro->grad = ro->grad0;
+    return ok();
+  }
+  CHECK_ERR(chol_solve(c, U, n, g, z, K));
+  CHECK_HIP(hipMemcpyAsync(p, z, sizeof(double) * n * K, hipMemcpyDeviceToDevice, st));
+  CHECK_HIP(launch_dot_cols(g, z, n, K, dots, dwork, st));
+  CHECK_ERR(host_cols(c, dots, K, gam));
+  for (int it = 0; it < max_iter; ++it) {
+    // q = A p ; delta = ||q||^2 + mu ||p||^2
+    CHECK_HIP(launch_rowpass_runs(pg, rho, p, K, nullptr, 1.0, 0.0, q, st));
+    CHECK_HIP(launch_dot_cols(q, q, P, K, dots, dwork, st));
+    CHECK_HIP(launch_dot_cols(p, p, n, K, dots + K, dwork, st));
+    CHECK_ERR(host_cols(c, dots, 2 * K, tmp));
+    for (int k = 0; k < K; ++k) {
+      const double dl = tmp[k] + mu * tmp[K + k];
+      alpha[k] = (dl > 0.0 && gam[k] > 0.0) ? gam[k] / dl : 0.0;
+      stepn[k] = std::fabs(alpha[k]) * std::sqrt(tmp[K + k]);
+    }
+    CHECK_ERR(to_dev_cols(c, alpha, scal));
+    CHECK_HIP(launch_axpy_cols(scal, p, X, n, K, 1.0, st));
+    CHECK_HIP(launch_axpy_cols(scal, q, sres, P, K, -1.0, st));
+    ro->iters = it + 1;
+    CHECK_HIP(launch_dot_cols(X, X, n, K, dots, dwork, st));
+    CHECK_ERR(host_cols(c, dots, K, tmp2));
+    double worst = 0.0;
+    for (int k = 0; k < K; ++k) worst = std::max(worst, stepn[k] / std::max(std::sqrt(tmp2[k]), 1e-300));
+    ro->last_step = worst;
+    if (worst <= tol) {
+      ro->converged = true;
+      break;
+    }
+    if (it + 1 == max_iter) break;
+    CHECK_HIP(launch_colpass_runs(pg, rho, sres, K, X, 1.0, -mu, g, colwork, st));
+    CHECK_ERR(chol_solve(c, U, n, g, z, K));
+    CHECK_HIP(launch_dot_cols(g, z, n, K, dots, dwork, st));
+    CHECK_ERR(host_cols(c, dots, K, tmp));
+    for (int k = 0; k < K; ++k) {
+      beta[k] = gam[k] > 0.0 ? tmp[k] / gam[k] : 0.0;
+      gam[k] = tmp[k];
+    }
+    CHECK_ERR(to_dev_cols(c, beta, scal));
+    CHECK_HIP(launch_xpby_cols(z, scal, p, n, K, st));
+  }
+  if (want_grad) {
+    CHECK_HIP(launch_colpass_runs(pg, rho, sres, K, X, 1.0, -mu, g, colwork, st));
+    CHECK_HIP(launch_dot_cols(g, g, n, K, dots, dwork, st));
+    CHECK_ERR(host_cols(c, dots, K, tmp));
+    double m = 0;
+    for (double v : tmp) m = std::max(m, std::sqrt(v));
+    ro->grad = m;
+  }
+  return ok();
+}
+
+// ------------------------------------------------------------------ one full solve on a built system
+struct SolveParams {
+  double mu = 0.0;
+  int prec = FLSQ_PREC_FP64;
+  int max_refine = 0;
+  double refine_tol = 0.0;
+  double shift_rel = 0.0;
+};
+
+SolveParams params_of(const flsq_solve_opts* o) {
+  SolveParams p;
+  if (o) {
+    p.mu = o->mu;
+    p.prec = o->prec;
+    p.max_refine = o->max_refine;
+    p.refine_tol = o->refine_tol;
+    p.shift_rel = o->shift_rel;
+  }
+  return p;
+}
+
+Err check_params(const SolveParams& p) {
+  if (!(p.mu >= 0.0) || !std::isfinite(p.mu)) return fail(FLSQ_EINVAL, "mu must be finite and >= 0");
+  if (p.prec != FLSQ_PREC_FP64 && p.prec != FLSQ_PREC_FP32_REFINE && p.prec != FLSQ_PREC_BF16X3_REFINE)
+    return fail(FLSQ_EINVAL, "unknown precision %d", p.prec);
+  if (p.prec == FLSQ_PREC_BF16X3_REFINE) return fail(FLSQ_EINVAL, "BF16x3 Gram is not available in this build");
+  if (p.max_refine < 0 || p.max_refine > 100000) return fail(FLSQ_EINVAL, "max_refine out of range");
+  if (!(p.refine_tol >= 0.0)) return fail(FLSQ_EINVAL, "refine_tol must be >= 0");
+  if (!(p.shift_rel >= 0.0) || p.shift_rel > 1.0) return fail(FLSQ_EINVAL, "shift_rel must be in [0, 1]");
+  return ok();
+}
+
+// Gram + factor into U.
+Err gram_and_factor(flsq_ctx* c, const System& s, const double* rho, const SolveParams& sp, double* U,
+                    flsq_solve_info* info) {
+  const int n = s.n;
+  double* G;
+  CHECK_ERR(ws_get(c, "G", (size_t)n * n, &G));
+  const double t0 = now_ms();
+  CHECK_ERR(run_gram(c, s, sp.prec, rho, G, 0, 0.0));
+  CHECK_HIP(hipStreamSynchronize(c->stream));
+  const double t1 = now_ms();
+  double shift = 0.0;
+  int retries = 0;
+  const double rel0 = (sp.prec == FLSQ_PREC_FP64) ? sp.shift_rel : (sp.shift_rel > 0.0 ? sp.shift_rel : 1e-6);
+  CHECK_ERR(factor_with_retries(c, G, U, n, sp.mu, rel0, &shift, &retries));
+  const double t2 = now_ms();
+  if (info) {
+    info->t_gram_ms = t1 - t0;
+    info->t_chol_ms = t2 - t1;
+    info->shift = shift;
+    info->chol_retries = retries;
+  }
+  return ok();
+}
+
+Err solve_on_system(flsq_ctx* c, const System& s, const double* rho, const SolveParams& sp, const double* Yw, int K,
+                    double* X, flsq_solve_info* info, bool* converged) {
+  const int n = s.n;
+  const double t0 = now_ms();
+  double* U;
+  CHECK_ERR(ws_get(c, "U", (size_t)n * n, &U));
+  CHECK_ERR(gram_and_factor(c, s, rho, sp, U, info));
+  const double t1 = now_ms();
+  // X0 = (U^T U)^{-1} A^T Y
+  double *cvec, *colwork;
+  CHECK_ERR(ws_get(c, "cvec", (size_t)n * K, &cvec));
+  CHECK_ERR(ws_get(c, "colwork0", pass_work_elems(n, s.n_runs, K) + 64, &colwork));
+  CHECK_HIP(launch_colpass_runs(s.pass(), rho, Yw, K, nullptr, 1.0, 0.0, cvec, colwork, c->stream));
+  CHECK_ERR(chol_solve(c, U, n, cvec, X, K));
+  RefineOut ro;
+  CHECK_ERR(cgls_refine(c, s, rho, U, sp.mu, Yw, K, X, sp.max_refine, sp.refine_tol, info != nullptr, &ro));
+  CHECK_HIP(hipStreamSynchronize(c->stream));
+  const double t2 = now_ms();
+  if (info) {
+    info->refine_iters = ro.iters;
+    info->grad_norm0 = ro.grad0;
+    info->grad_norm = ro.grad;
+    info->last_step_rel = ro.last_step;
+    info->t_refine_ms = t2 - t1;
+  }
+  if (converged) *converged = ro.converged;
+  return ok();
+}
+
+flsq_status finish(flsq_ctx* c, const Err& e) {
+  if (c) c->err = e.msg;
+  return e.st;
+}
+
+}  // namespace
+
+// =====================================================================================
+// C ABI
+// =====================================================================================
+extern "C" {
+
+flsq_status flsq_create(flsq_ctx** ctx, int device, void* hip_stream) {
+  if (!ctx) return FLSQ_EINVAL;
+  *ctx = nullptr;
+  int n_dev = 0;
+  if (hipGetDeviceCount(&n_dev) != hipSuccess || n_dev == 0) return FLSQ_EHIP;
+  if (device < 0 || device >= n_dev) return FLSQ_EINVAL;
+  if (hipSetDevice(device) != hipSuccess) return FLSQ_EHIP;
+  flsq_ctx* c = new flsq_ctx();
+  c->device = device;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+    c->n_cu = prop.multiProcessorCount;
+  *ctx = c;
+  return FLSQ_OK;
+}
+
+void flsq_destroy(flsq_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  delete ctx;
+}
+
+const char* flsq_last_error(const flsq_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+const char* flsq_build_info(void) { return "libfastlsq 0.1 (HIP, gfx950)"; }
+
+flsq_status flsq_assemble(flsq_ctx* ctx, const flsq_basis* basis, const flsq_rows* blocks, int32_t n_blocks,
+                          int32_t fp32, void* A_out, double* rhs_out) {
+  if (!ctx) return FLSQ_EINVAL;
+  if (hipSetDevice(ctx->device) != hipSuccess) return finish(ctx, fail(FLSQ_EHIP, "hipSetDevice failed"));
+  if (!A_out) return finish(ctx, fail(FLSQ_EINVAL, "A_out is NULL"));
+  Err e = build_system(ctx, ctx->sys, basis, blocks, n_blocks, rhs_out != nullptr);
+  if (e.st != FLSQ_OK) return finish(ctx, e);
+  const System& s = ctx->sys;
+  hipError_t he = launch_assemble(s.geo(), fp32 ? 1 : 0, A_out, ctx->stream);
+  if (he == hipSuccess && rhs_out)
+    he = hipMemcpyAsync(rhs_out, s.rhs_w.p, sizeof(double) * s.P, hipMemcpyDeviceToDevice, ctx->stream);
+  if (he == hipSuccess) he = hipStreamSynchronize(ctx->stream);
+  if (he != hipSuccess) return finish(ctx, fail(FLSQ_EHIP, "assemble: %s", hipGetErrorString(he)));
+  return finish(ctx, ok());
+}
+
+flsq_status flsq_gram(flsq_ctx* ctx, const flsq_basis* basis, const flsq_rows* blocks, int32_t n_blocks, int32_t prec,
+                      double* G_out, double* c_out) {
+  if (!ctx) return FLSQ_EINVAL;
+  if (hipSetDevice(ctx->device) != hipSuccess) return finish(ctx, fail(FLSQ_EHIP, "hipSetDevice failed"));
+  if (!G_out) return finish(ctx, fail(FLSQ_EINVAL, "G_out is NULL"));
+  SolveParams sp;
+  sp.prec = prec;
+  Err e = check_params(sp);
+  if (e.st != FLSQ_OK) return finish(ctx, e);
+  e = build_system(ctx, ctx->sys, basis, blocks, n_blocks, c_out != nullptr);
+  if (e.st != FLSQ_OK) return finish(ctx, e);
+  const System& s = ctx->sys;
+  e = run_gram(ctx, s, prec, nullptr, G_out, 1, 0.0);
+  if (e.st != FLSQ_OK) return finish(ctx, e);
+  if (c_out) {
+    double* colwork;
+    e = ws_get(ctx, "colwork0", pass_work_elems(s.n, s.n_runs, 1) + 64, &colwork);
+    if (e.st != FLSQ_OK) return finish(ctx, e);
+    hipError_t he = launch_colpass_runs(s.pass(), nullptr, s.rhs_w.as<double>(), 1, nullptr, 1.0, 0.0, c_out, colwork,
+                                        ctx->stream);
+    if (he != hipSuccess) return finish(ctx, fail(FLSQ_EHIP, "colpass: %s", hipGetErrorString(he)));
+  }
+  hipError_t he = hipStreamSynchronize(ctx->stream);
+  if (he != hipSuccess) return finish(ctx, fail(FLSQ_EHIP, "gram: %s", hipGetErrorString(he)));
+  return finish(ctx, ok());
+}
+
+flsq_status flsq_solve_linear(flsq_ctx* ctx, const flsq_basis* basis, const flsq_rows* blocks, int32_t n_blocks,
+                              const flsq_solve_opts* opts, double* beta_out, flsq_solve_info* info) {
+  if (!ctx) return FLSQ_EINVAL;
+  if (hipSetDevice(ctx->device) != hipSuccess) return finish(ctx, fail(FLSQ_EHIP, "hipSetDevice failed"));
+  if (!beta_out) return finish(ctx, fail(FLSQ_EINVAL, "beta_out is NULL"));
+  const double t0 = now_ms();
+  SolveParams sp = params_of(opts);
+  Err e = check_params(sp);
+  if (e.st != FLSQ_OK) return finish(ctx, e);
+  if (info) memset(info, 0, sizeof *info);
+  e = build_system(ctx, ctx->sys, basis, blocks, n_blocks, true);
+  if (e.st != FLSQ_OK) return finish(ctx, e);
+  bool conv = true;
+  e = solve_on_system(ctx, ctx->sys, nullptr, sp, ctx->sys.rhs_w.as<double>(), 1, beta_out, info, &conv);
+  if (e.st != FLSQ_OK) return finish(ctx, e);
+  e = check_finite_dev(ctx, beta_out, ctx->sys.n, "beta");
+  if (e.st != FLSQ_OK) return finish(ctx, e);
+  if (info) info->t_total_ms = now_ms() - t0;
+  if (!conv && sp.refine_tol > 0.0)
+    return finish(ctx, fail(FLSQ_ENOCONV, "refinement did not reach refine_tol in %d iterations", sp.max_refine));
+  return finish(ctx, ok());
+}
+
+flsq_status flsq_factorize(flsq_ctx* ctx, const flsq_basis* basis, const flsq_rows* blocks, int32_t n_blocks,
+                           const flsq_solve_opts* opts, flsq_factor** F, flsq_solve_info* info) {
+  if (!ctx || !F) return FLSQ_EINVAL;
+  *F = nullptr;
+  if (hipSetDevice(ctx->device) != hipSuccess) return finish(ctx, fail(FLSQ_EHIP, "hipSetDevice failed"));
+  SolveParams sp = params_of(opts);
+  Err e = check_params(sp);
+  if (e.st != FLSQ_OK) return finish(ctx, e);
+  if (info) memset(info, 0, sizeof *info);
+  flsq_factor* f = new flsq_factor();
+  f->device = ctx->device;
+  e = build_system(ctx, f->sys, basis, blocks, n_blocks, false);
+  if (e.st == FLSQ_OK) {
+    hipError_t he = f->U.ensure(sizeof(double) * f->sys.n * f->sys.n);
+    if (he != hipSuccess) e = fail(FLSQ_ENOMEM, "factor allocation failed");
+  }
+  if (e.st == FLSQ_OK) e = gram_and_factor(ctx, f->sys, nullptr, sp, f->U.as<double>(), info);
+  if (e.st != FLSQ_OK) {
+    delete f;
+    return finish(ctx, e);
+  }
+  f->mu = sp.mu;
+  f->shift = info ? info->shift : 0.0;
+  f->max_refine = sp.max_refine;
+  f->refine_tol = sp.refine_tol;
+  *F = f;
+  return finish(ctx, ok());
+}
+
+void flsq_factor_free(flsq_factor* F) {
+  if (!F) return;
+  (void)hipSetDevice(F->device);
+  delete F;
+}
+
+flsq_status flsq_factor_shape(const flsq_factor* F, int64_t* n_rows, int32_t* n_feat) {
+  if (!F) return FLSQ_EINVAL;
+  if (n_rows) *n_rows = F->sys.P;
+  if (n_feat) *n_feat = F->sys.n;
+  return FLSQ_OK;
+}
+
+flsq_status flsq_factor_solve(flsq_ctx* ctx, const flsq_factor* F, const double* rhs_rows, int32_t K,
+                              double* beta_out, flsq_solve_info* info) {
+  if (!ctx || !F) return FLSQ_EINVAL;
+  if (hipSetDevice(ctx->device) != hipSuccess) return finish(ctx, fail(FLSQ_EHIP, "hipSetDevice failed"));
+  if (!rhs_rows || !beta_out) return finish(ctx, fail(FLSQ_EINVAL, "NULL rhs_rows or beta_out"));
+  if (K < 1 || K > 64) return finish(ctx, fail(FLSQ_EINVAL, "K = %d outside [1, 64]", K));
+  if (info) memset(info, 0, sizeof *info);
+  const double t0 = now_ms();
+  const System& s = F->sys;
+  double *cvec, *colwork;
+  Err e = ws_get(ctx, "cvec", (size_t)s.n * K, &cvec);
+  if (e.st == FLSQ_OK) e = ws_get(ctx, "colwork0", pass_work_elems(s.n, s.n_runs, K) + 64, &colwork);
+  if (e.st != FLSQ_OK) return finish(ctx, e);
+  hipError_t he = launch_colpass_runs(s.pass(), nullptr, rhs_rows, K, nullptr, 1.0, 0.0, cvec, colwork, ctx->stream);
+  if (he != hipSuccess) return finish(ctx, fail(FLSQ_EHIP, "colpass: %s", hipGetErrorString(he)));
+  e = chol_solve(ctx, F->U.as<double>(), s.n, cvec, beta_out, K);
+  if (e.st != FLSQ_OK) return finish(ctx, e);
+  RefineOut ro;
+  e = cgls_refine(ctx, s, nullptr, F->U.as<double>(), F->mu, rhs_rows, K, beta_out, F->max_refine, F->refine_tol,
+                  info != nullptr, &ro);
+  if (e.st != FLSQ_OK) return finish(ctx, e);
+  he = hipStreamSynchronize(ctx->stream);
+  if (he != hipSuccess) return finish(ctx, fail(FLSQ_EHIP, "factor_solve: %s", hipGetErrorString(he)));
+  if (info) {
+    info->refine_iters = ro.iters;
+    info->grad_norm0 = ro.grad0;
+    info->grad_norm = ro.grad;
+    info->last_step_rel = ro.last_step;
+    info->shift = F->shift;
+    info->t_total_ms = now_ms() - t0;
+  }
+  return finish(ctx, ok());
+}
+
+flsq_status flsq_factor_solve_normal(flsq_ctx* ctx, const flsq_factor* F, const double* V, int32_t K, double* out) {
+  if (!ctx || !F) return FLSQ_EINVAL;
+  if (hipSetDevice(ctx->device) != hipSuccess) return finish(ctx, fail(FLSQ_EHIP, "hipSetDevice failed"));
+  if (!V || !out) return finish(ctx, fail(FLSQ_EINVAL, "NULL V or out"));
+  if (K < 1 || K > 64) return finish(ctx, fail(FLSQ_EINVAL, "K = %d outside [1, 64]", K));
+  const System& s = F->sys;
+  const int n = s.n;
+  const PassGeo pg = s.pass();
+  hipStream_t st = ctx->stream;
+  // preconditioned CG on (A^T A + mu I) X = V with FP64 matrix-free operator
+  double *r, *z, *p, *ap, *tP, *dots, *dwork, *colwork, *scal;
+  Err e = ok();
+  if (e.st == FLSQ_OK) e = ws_get(ctx, "pcg_r", (size_t)n * K, &r);
+  if (e.st == FLSQ_OK) e = ws_get(ctx, "pcg_z", (size_t)n * K, &z);
+  if (e.st == FLSQ_OK) e = ws_get(ctx, "pcg_p", (size_t)n * K, &p);
+  if (e.st == FLSQ_OK) e = ws_get(ctx, "pcg_ap", (size_t)n * K, &ap);
+  if (e.st == FLSQ_OK) e = ws_get(ctx, "pcg_tp", (size_t)s.P * K, &tP);
+  if (e.st == FLSQ_OK) e = ws_get(ctx, "pcg_dots", (size_t)4 * K, &dots);
+  if (e.st == FLSQ_OK) e = ws_get(ctx, "pcg_dwork", (size_t)512 * K + 64, &dwork);
+  if (e.st == FLSQ_OK) e = ws_get(ctx, "pcg_colwork", pass_work_elems(n, s.n_runs, K) + 64, &colwork);
+  if (e.st == FLSQ_OK) e = ws_get(ctx, "pcg_scal", (size_t)K, &scal);
+  if (e.st != FLSQ_OK) return finish(ctx, e);
+  auto apply_normal = [&](const double* x, double* y) -> Err {   // y = A^T A x + mu x
+    CHECK_HIP(launch_rowpass_runs(pg, nullptr, x, K, nullptr, 1.0, 0.0, tP, st));
+    CHECK_HIP(launch_colpass_runs(pg, nullptr, tP, K, x, 1.0, F->mu, y, colwork, st));
+    return ok();
+  };
+  auto body = [&]() -> Err {
+    CHECK_ERR(chol_solve(ctx, F->U.as<double>(), n, V, out, K));
+    if (F->max_refine == 0) return ok();
+    std::vector<double> gam, tmp, tmp2, alpha(K), beta(K);
+    CHECK_ERR(apply_normal(out, ap));
+    CHECK_HIP(hipMemcpyAsync(r, V, sizeof(double) * n * K, hipMemcpyDeviceToDevice, st));
+    std::vector<double> ones(K, 1.0);
+    CHECK_ERR(to_dev_cols(ctx, ones, scal));
+    CHECK_HIP(launch_axpy_cols(scal, ap, r, n, K, -1.0, st));
+    CHECK_ERR(chol_solve(ctx, F->U.as<double>(), n, r, z, K));
+    CHECK_HIP(hipMemcpyAsync(p, z, sizeof(double) * n * K, hipMemcpyDeviceToDevice, st));
+    CHECK_HIP(launch_dot_cols(r, z, n, K, dots, dwork, st));
+    CHECK_ERR(host_cols(ctx, dots, K, gam));
+    for (int it = 0; it < F->max_refine; ++it) {
+      CHECK_ERR(apply_normal(p, ap));
+      CHECK_HIP(launch_dot_cols(p, ap, n, K, dots, dwork, st));
+      CHECK_HIP(launch_dot_cols(p, p, n, K, dots + K, dwork, st));
+      CHECK_HIP(launch_dot_cols(out, out, n, K, dots + 2 * K, dwork, st));
+      CHECK_ERR(host_cols(ctx, dots, 3 * K, tmp));
+      double worst = 0.0;
+      for (int k = 0; k < K; ++k) {
+        alpha[k] = (tmp[k] > 0.0 && gam[k] > 0.0) ? gam[k] / tmp[k] : 0.0;
+        worst = std::max(worst, std::fabs(alpha[k]) * std::sqrt(tmp[K + k]) /
+                                    std::max(std::sqrt(tmp[2 * K + k]), 1e-300));
+      }
+      CHECK_ERR(to_dev_cols(ctx, alpha, scal));
+      CHECK_HIP(launch_axpy_cols(scal, p, out, n, K, 1.0, st));
+      if (worst <= F->refine_tol || it + 1 == F->max_refine) break;
+      CHECK_HIP(launch_axpy_cols(scal, ap, r, n, K, -1.0, st));
+      CHECK_ERR(chol_solve(ctx, F->U.as<double>(), n, r, z, K));
+      CHECK_HIP(launch_dot_cols(r, z, n, K, dots, dwork, st));
+      CHECK_ERR(host_cols(ctx, dots, K, tmp2));
+      for (int k = 0; k < K; ++k) {
+        beta[k] = gam[k] > 0.0 ? tmp2[k] / gam[k] : 0.0;
+        gam[k] = tmp2[k];
+      }
+      CHECK_ERR(to_dev_cols(ctx, beta, scal));
+      CHECK_HIP(launch_xpby_cols(z, scal, p, n, K, st));
+    }
+    return ok();
+  };
+  e = body();
+  if (e.st != FLSQ_OK) return finish(ctx, e);
+  hipError_t he = hipStreamSynchronize(st);
+  if (he != hipSuccess) return finish(ctx, fail(FLSQ_EHIP, "solve_normal: %s", hipGetErrorString(he)));
+  return finish(ctx, ok());
+}
+
+flsq_status flsq_apply_A(flsq_ctx* ctx, const flsq_factor* F, const double* V, int32_t K, double* out) {
+  if (!ctx || !F) return FLSQ_EINVAL;
+  if (hipSetDevice(ctx->device) != hipSuccess) return finish(ctx, fail(FLSQ_EHIP, "hipSetDevice failed"));
+  if (!V || !out) return finish(ctx, fail(FLSQ_EINVAL, "NULL V or out"));
+  if (K < 1 || K > 64) return finish(ctx, fail(FLSQ_EINVAL, "K = %d outside [1, 64]", K));
+  hipError_t he = launch_rowpass_runs(F->sys.pass(), nullptr, V, K, nullptr, 1.0, 0.0, out, ctx->stream);
+  if (he == hipSuccess) he = hipStreamSynchronize(ctx->stream);
+  if (he != hipSuccess) return finish(ctx, fail(FLSQ_EHIP, "apply_A: %s", hipGetErrorString(he)));
+  return finish(ctx, ok());
+}
+
+flsq_status flsq_apply_At(flsq_ctx* ctx, const flsq_factor* F, const double* Y, int32_t K, double* out) {
+  if (!ctx || !F) return FLSQ_EINVAL;
+  if (hipSetDevice(ctx->device) != hipSuccess) return finish(ctx, fail(FLSQ_EHIP, "hipSetDevice failed"));
+  if (!Y || !out) return finish(ctx, fail(FLSQ_EINVAL, "NULL Y or out"));
+  if (K < 1 || K > 64) return finish(ctx, fail(FLSQ_EINVAL, "K = %d outside [1, 64]", K));
+  double* colwork;
+  Err e = ws_get(ctx, "colwork0", pass_work_elems(F->sys.n, F->sys.n_runs, K) + 64, &colwork);
+  if (e.st != FLSQ_OK) return finish(ctx, e);
+  hipError_t he = launch_colpass_runs(F->sys.pass(), nullptr, Y, K, nullptr, 1.0, 0.0, out, colwork, ctx->stream);
+  if (he == hipSuccess) he = hipStreamSynchronize(ctx->stream);
+  if (he != hipSuccess) return finish(ctx, fail(FLSQ_EHIP, "apply_At: %s", hipGetErrorString(he)));
+  return finish(ctx, ok());
+}
+
+flsq_status flsq_evaluate(flsq_ctx* ctx, const flsq_basis* basis, const double* beta, int64_t n_q, const void* xq,
+                          int32_t xq_is_fp32, const uint8_t* alphas, int32_t n_alpha, void* out) {
+  if (!ctx) return FLSQ_EINVAL;
+  if (hipSetDevice(ctx->device) != hipSuccess) return finish(ctx, fail(FLSQ_EHIP, "hipSetDevice failed"));
+  Err e = check_basis(basis);
+  if (e.st != FLSQ_OK) return finish(ctx, e);
+  if (!beta || (n_q > 0 && (!xq || !out))) return finish(ctx, fail(FLSQ_EINVAL, "NULL beta, xq or out"));
+  if (n_q < 0) return finish(ctx, fail(FLSQ_EINVAL, "n_q < 0"));
+  if (n_alpha < 1 || n_alpha > 8 || !alphas) return finish(ctx, fail(FLSQ_EINVAL, "n_alpha = %d outside [1, 8]", n_alpha));
+  const int d = basis->d, n = basis->n_feat;
+  uint32_t mask = 0;
+  for (int a = 0; a < n_alpha; ++a) {
+    int ord = 0;
+    for (int k = 0; k < d; ++k) ord += alphas[a * d + k];
+    if (ord & 1) mask |= 1u << a;
+  }
+  double *Wt, *coef;
+  float *Wt32, *coef32, *b32;
+  uint8_t* al;
+  e = ws_get(ctx, "ev_Wt", (size_t)d * n, &Wt);
+  if (e.st == FLSQ_OK) e = ws_get(ctx, "ev_coef", (size_t)n_alpha * n, &coef);
+  if (e.st == FLSQ_OK) e = ws_get(ctx, "ev_Wt32", (size_t)d * n, &Wt32);
+  if (e.st == FLSQ_OK) e = ws_get(ctx, "ev_coef32", (size_t)n_alpha * n, &coef32);
+  if (e.st == FLSQ_OK) e = ws_get(ctx, "ev_b32", (size_t)n, &b32);
+  if (e.st == FLSQ_OK) e = ws_get(ctx, "ev_alpha", (size_t)n_alpha * d, &al);
+  if (e.st != FLSQ_OK) return finish(ctx, e);
+  hipError_t he = hipMemcpyAsync(al, alphas, (size_t)n_alpha * d, hipMemcpyHostToDevice, ctx->stream);
+  if (he == hipSuccess) he = launch_transpose(basis->W, n, d, Wt, nullptr, n, ctx->stream);
+  EvalArgs a;
+  a.d = d;
+  a.n = n;
+  a.n_alpha = n_alpha;
+  a.n_q = n_q;
+  a.Wt = Wt;
+  a.b = basis->b;
+  a.beta = beta;
+  a.alphas = al;
+  a.xq = xq;
+  a.out = out;
+  a.fp32 = xq_is_fp32 ? 1 : 0;
+  a.norm = basis->normalize ? 1.0 / std::sqrt((double)n) : 1.0;
+  a.coef = coef;
+  a.coef32 = coef32;
+  a.Wt32 = Wt32;
+  a.b32 = b32;
+  a.cos_mask = mask;
+  if (he == hipSuccess) he = launch_evaluate(a, ctx->stream);
+  if (he == hipSuccess) he = hipStreamSynchronize(ctx->stream);
+  if (he != hipSuccess) return finish(ctx, fail(FLSQ_EHIP, "evaluate: %s", hipGetErrorString(he)));
+  return finish(ctx, ok());
+}
+
+}  // extern "C"

@@ -1,0 +1,121 @@
+// Host-side launchers of the gfx950 kernels (internal to libfastlsq).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "flsq_device.h"
+
+namespace flsq {
+
+// ---- coefficient preparation, layout transforms, assembly to HBM, evaluation
+struct OpTerms {
+  int n_terms;
+  double coef[32];
+  uint8_t alpha[32][kMaxDim];
+};
+hipError_t launch_prep_block(const OpTerms& op, double weight, double norm, int d, int n, const double* W,
+                             const double* b, double* amp, double* ph, float* amp32, float* ph32,
+                             hipStream_t s);
+hipError_t launch_transpose(const double* X, int64_t rows, int d, double* Xt, float* Xt32, int64_t ld_out,
+                            hipStream_t s);
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
+hipError_t launch_scale_copy(const double* src, double* dst, int64_t n, double scale, hipStream_t s);
+hipError_t launch_assemble(const Geo& g, int fp32, void* A, hipStream_t s);
+hipError_t launch_to_f32(const double* src, float* dst, int64_t n, hipStream_t s);
+
+struct EvalArgs {
+  int d, n, n_alpha;
+  int64_t n_q;
+  const double* Wt;        // d x n
+  const double* b;
+  const double* beta;
+  const uint8_t* alphas;   // device n_alpha x d
+  const void* xq;          // n_q x d
+  void* out;               // n_q x n_alpha
+  int fp32;
+  double norm;
+  double* coef;            // workspace n_alpha x n (double)
+  float* coef32;           // workspace n_alpha x n
+  float* Wt32;             // workspace d x n
+  float* b32;              // workspace n
+  uint32_t cos_mask;       // bit a set when |alpha_a| is odd
+};
+hipError_t launch_evaluate(const EvalArgs& a, hipStream_t s);
+
+// ---- fused Gram
+struct GramLaunch {
+  Geo g;
+  int prec;                 // 0 fp64, 1 fp32
+  const double* rho;
+  const float* rho32;
+  const Chunk* chunks;
+  int n_chunks;
+  int nt;
+  int64_t total_units;
+  int64_t units_per_wg;
+  int max_seg;
+  int n_wg;
+  void* partial;
+};
+int gram_tile();
+int gram_chunk_rows();
+int gram_occupancy(int prec);
+hipError_t launch_gram(const GramLaunch& L, hipStream_t s);
+hipError_t launch_gram_reduce(int prec, const void* partial, const int32_t* slot_ptr, const int32_t* slots,
+                              int nt, int n, double* G, int mirror, double diag_add, hipStream_t s);
+
+// ---- matrix-free FP64 products over the stacked rows (A recomputed per entry)
+struct PassGeo {
+  Geo g;
+  const Chunk* runs;   // block-aligned runs of at most pass_rows() rows
+  int n_runs;
+};
+int pass_rows();
+size_t pass_work_elems(int n, int n_runs, int K);
+// out[i][c] = beta_y * Y[i][c] + alpha * sum_j A_ij V[j][c]   (Y nullable)
+hipError_t launch_rowpass_runs(const PassGeo& pg, const double* rho, const double* V, int K, const double* Y,
+                               double alpha, double beta_y, double* out, hipStream_t s);
+// out[j][c] = beta_v * V[j][c] + alpha * sum_i A_ij Y[i][c]   (V nullable)
+hipError_t launch_colpass_runs(const PassGeo& pg, const double* rho, const double* Y, int K, const double* V,
+                               double alpha, double beta_v, double* out, double* work, hipStream_t s);
+// Newton residual R_i = (A beta)_i + w N(u_i) - data_i; rho_i = w N'(u_i) norm; u_i on the nonlinear block.
+hipError_t launch_newton_residual_runs(const PassGeo& pg, const double* beta, const double* data_w,
+                                       int nonlin_block, const double* poly, int n_poly, double w_nl, double norm,
+                                       double* R, double* rho_out, double* u_out, hipStream_t s);
+
+// ---- dense FP64 linear algebra on the upper Cholesky factor (row-major, G = U^T U)
+constexpr int kNb = 64;
+hipError_t launch_potrf_diag(double* G, int n, int k0, int* info, double shift, hipStream_t s);
+hipError_t launch_trsm_row(double* G, int n, int k0, hipStream_t s);
+hipError_t launch_syrk(double* G, int n, int k0, hipStream_t s);
+// Solves with the factor (Y n x K row-major is consumed as scratch, the solution goes to X):
+// U^T X = Y (forward) and U X = Y (backward).
+hipError_t launch_trsv_fwd(const double* U, int n, double* Y, double* X, int K, hipStream_t s);
+hipError_t launch_trsv_bwd(const double* U, int n, double* Y, double* X, int K, hipStream_t s);
+hipError_t launch_copy_upper(const double* src, double* dst, int n, double diag_add, hipStream_t s);
+hipError_t launch_diag_max(const double* G, int n, double* out, hipStream_t s);
+
+// ---- small vector kernels
+// out[c] = sum_i x[i][c] * y[i][c] over n rows, K columns (deterministic two-stage).
+hipError_t launch_dot_cols(const double* x, const double* y, int64_t n, int K, double* out, double* work,
+                           hipStream_t s);
+// y[i][c] += a[c] * x[i][c]
+hipError_t launch_axpy_cols(const double* a, const double* x, double* y, int64_t n, int K, double sign,
+                            hipStream_t s);
+// p[i][c] = z[i][c] + b[c] * p[i][c]
+hipError_t launch_xpby_cols(const double* z, const double* b, double* p, int64_t n, int K, hipStream_t s);
+hipError_t launch_count_nonfinite(const double* x, int64_t n, int* flag, hipStream_t s);
+
+
+// ---- inverse heat-source support
+hipError_t launch_source(const double* Xt, int64_t P, int64_t n_src, double weight, const double* thetas, int K,
+                         double* Rhs, hipStream_t s);
+hipError_t launch_source_grad_dot(const double* Xt, int64_t P, int64_t n_src, double weight, const double* thetas,
+                                  int K, const double* AL, double* grad, double* work, hipStream_t s);
+hipError_t launch_misfit(const double* U, const double* data, int64_t n_obs, int K, double* loss, double* gu,
+                         hipStream_t s);
+hipError_t launch_adam(double* p, const double* g, double* m, double* v, int K, int P, int t, double lr, double b1,
+                       double b2, double eps, int clamp_col, double clamp_min, hipStream_t s);
+
+}  // namespace flsq

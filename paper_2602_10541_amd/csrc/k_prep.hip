@@ -1,0 +1,266 @@
+// Operator folding, layout transforms, assembly to HBM and evaluation of u_N.
+#include "flsq_device.h"
+#include "flsq_launch.h"
+
+namespace flsq {
+
+// Per feature j of one row block with weight w and operator sum_t c_t D^{alpha_t}:
+//   S_j = w * norm * sum_t c_t W_j^{alpha_t} s(|alpha_t|),  s = +1, 0, -1, 0 for |alpha| = 0, 1, 2, 3 mod 4
+//   C_j = w * norm * sum_t c_t W_j^{alpha_t} c(|alpha_t|),  c =  0, +1, 0, -1
+// (Eq. (2): Phi_0..3 = sin, cos, -sin, -cos), so that A_ij = S_j sin z_ij + C_j cos z_ij.
+// Folded to amplitude/phase: even-order operators keep (amp, ph) = (S, b); otherwise
+// (amp, ph) = (hypot(S, C), b + atan2(C, S)).
+__global__ void k_prep_block(OpTerms op, double scale, int d, int n, const double* __restrict__ W,
+                             const double* __restrict__ b, double* amp, double* ph, float* amp32, float* ph32) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  double S = 0.0, Cc = 0.0;
+  bool even = true;
+  for (int t = 0; t < op.n_terms; ++t) {
+    double mono = 1.0;
+    int ord = 0;
+    for (int k = 0; k < d; ++k) {
+      const int a = op.alpha[t][k];
+      ord += a;
+      const double wk = W[(int64_t)j * d + k];
+      for (int p = 0; p < a; ++p) mono *= wk;
+    }
+    const double v = op.coef[t] * mono;
+    switch (ord & 3) {
+      case 0: S += v; break;
+      case 1: Cc += v; break;
+      case 2: S -= v; break;
+      default: Cc -= v; break;
+    }
+    if (ord & 1) even = false;
+  }
+  S *= scale;
+  Cc *= scale;
+  double a, p;
+  if (even) {
+    a = S;
+    p = b[j];
+  } else {
+    a = hypot(S, Cc);
+    p = b[j] + atan2(Cc, S);
+  }
+  amp[j] = a;
+  ph[j] = p;
+  amp32[j] = (float)a;
+  ph32[j] = (float)p;
+}
+
+hipError_t launch_prep_block(const OpTerms& op, double weight, double norm, int d, int n, const double* W,
+                             const double* b, double* amp, double* ph, float* amp32, float* ph32, hipStream_t s) {
+  hipLaunchKernelGGL(k_prep_block, dim3((n + 255) / 256), dim3(256), 0, s, op, weight * norm, d, n, W, b, amp, ph,
+                     amp32, ph32);
+  return hipGetLastError();
+}
+
+// X (rows x d, row-major) -> Xt[k * ld_out + i] in FP64 and FP32.
+__global__ void k_transpose(const double* __restrict__ X, int64_t rows, int d, double* Xt, float* Xt32,
+                            int64_t ld_out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= rows) return;
+  for (int k = 0; k < d; ++k) {
+    const double v = X[i * d + k];
+    Xt[(int64_t)k * ld_out + i] = v;
+    if (Xt32) Xt32[(int64_t)k * ld_out + i] = (float)v;
+  }
+}
+
+hipError_t launch_transpose(const double* X, int64_t rows, int d, double* Xt, float* Xt32, int64_t ld_out,
+                            hipStream_t s) {
+  if (rows == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_transpose, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, s, X, rows, d, Xt, Xt32,
+                     ld_out);
+  return hipGetLastError();
+}
+
+__global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+__global__ void k_scale_copy(const double* src, double* dst, int64_t n, double scale) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src ? scale * src[i] : 0.0;
+}
+
+hipError_t launch_scale_copy(const double* src, double* dst, int64_t n, double scale, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scale_copy, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src, dst, n, scale);
+  return hipGetLastError();
+}
+
+__global__ void k_to_f32(const double* src, float* dst, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = (float)src[i];
+}
+
+hipError_t launch_to_f32(const double* src, float* dst, int64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_to_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src, dst, n);
+  return hipGetLastError();
+}
+
+// A[i][j] with the same arithmetic as the fused Gram kernels (FP64 or FP32).
+__global__ void k_assemble(Geo g, int fp32, void* A) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = blockIdx.y;
+  if (j >= g.n) return;
+  const int blk = g.row_block[i];
+  if (fp32) {
+    float z = 0.f;
+    for (int k = 0; k < g.d; ++k) z = fmaf(g.Wt32[(int64_t)k * g.n + j], g.Xt32[(int64_t)k * g.P + i], z);
+    const float v = g.amp32[(int64_t)blk * g.n + j] * sin_f32(z + g.ph32[(int64_t)blk * g.n + j]);
+    ((float*)A)[i * g.n + j] = v;
+  } else {
+    double z = 0.0;
+    for (int k = 0; k < g.d; ++k) z = fma(g.Wt[(int64_t)k * g.n + j], g.Xt[(int64_t)k * g.P + i], z);
+    const double v = g.amp[(int64_t)blk * g.n + j] * sin_f64(z + g.ph[(int64_t)blk * g.n + j]);
+    ((double*)A)[i * g.n + j] = v;
+  }
+}
+
+hipError_t launch_assemble(const Geo& g, int fp32, void* A, hipStream_t s) {
+  int64_t r0 = 0;
+  while (r0 < g.P) {  // grid.y is limited to 65535 rows per launch
+    const int64_t rows = (g.P - r0 < 65535) ? g.P - r0 : 65535;
+    Geo gg = g;
+    // shift the row view: rows [r0, r0 + rows)
+    gg.Xt = g.Xt + r0;
+    gg.Xt32 = g.Xt32 + r0;
+    gg.row_block = g.row_block + r0;
+    void* Ab = fp32 ? (void*)((float*)A + r0 * g.n) : (void*)((double*)A + r0 * g.n);
+    hipLaunchKernelGGL(k_assemble, dim3((g.n + 255) / 256, (unsigned)rows), dim3(256), 0, s, gg, fp32, Ab);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    r0 += rows;
+  }
+  return hipSuccess;
+}
+
+// ---------------------------------------------------------------------------------
+// Evaluation (Eq. (1)-(2)): out[q][a] = norm * sum_j beta_j W_j^{alpha_a} Phi_{|alpha_a|}(z_qj).
+// coef[a][j] = norm * beta_j * W_j^{alpha_a} * (+1 | -1) with the sign of Phi folded in, so
+// every output needs only sin z (even order) or cos z (odd order).
+// ---------------------------------------------------------------------------------
+__global__ void k_eval_coef(int d, int n, int n_alpha, const double* __restrict__ Wt, const double* __restrict__ b,
+                            const double* __restrict__ beta, const uint8_t* __restrict__ alphas, double norm,
+                            double* coef, float* coef32, float* Wt32, float* b32) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  for (int a = 0; a < n_alpha; ++a) {
+    double mono = 1.0;
+    int ord = 0;
+    for (int k = 0; k < d; ++k) {
+      const int e = alphas[a * d + k];
+      ord += e;
+      for (int p = 0; p < e; ++p) mono *= Wt[(int64_t)k * n + j];
+    }
+    const double sgn = ((ord & 3) >= 2) ? -1.0 : 1.0;
+    const double c = norm * beta[j] * mono * sgn;
+    coef[(int64_t)a * n + j] = c;
+    coef32[(int64_t)a * n + j] = (float)c;
+  }
+  for (int k = 0; k < d; ++k) Wt32[(int64_t)k * n + j] = (float)Wt[(int64_t)k * n + j];
+  b32[j] = (float)b[j];
+}
+
+constexpr int kEvalThreads = 256;
+constexpr int kEvalFeat = 256;     // features staged per LDS round
+constexpr int kEvalPts = 2;        // query points per thread
+
+template <int D, typename T>
+__global__ __launch_bounds__(kEvalThreads) void k_evaluate(int n, int n_alpha, int64_t n_q, const T* __restrict__ Wt,
+                                                           const T* __restrict__ b, const T* __restrict__ coef,
+                                                           uint32_t cos_mask, const T* __restrict__ xq,
+                                                           T* __restrict__ out) {
+  constexpr int kMaxA = 8;
+  __shared__ T sF[kEvalFeat][D + 1 + kMaxA];
+  const int64_t q0 = ((int64_t)blockIdx.x * kEvalThreads + threadIdx.x) * kEvalPts;
+  T x[kEvalPts][D];
+  T acc[kEvalPts][kMaxA];
+#pragma unroll
+  for (int p = 0; p < kEvalPts; ++p) {
+    const int64_t q = q0 + p;
+#pragma unroll
+    for (int k = 0; k < D; ++k) x[p][k] = (q < n_q) ? xq[q * D + k] : T(0);
+#pragma unroll
+    for (int a = 0; a < kMaxA; ++a) acc[p][a] = T(0);
+  }
+  for (int j0 = 0; j0 < n; j0 += kEvalFeat) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < kEvalFeat; e += kEvalThreads) {
+      const int j = j0 + e;
+      const bool ok = j < n;
+#pragma unroll
+      for (int k = 0; k < D; ++k) sF[e][k] = ok ? Wt[(int64_t)k * n + j] : T(0);
+      sF[e][D] = ok ? b[j] : T(0);
+#pragma unroll
+      for (int a = 0; a < kMaxA; ++a) sF[e][D + 1 + a] = (ok && a < n_alpha) ? coef[(int64_t)a * n + j] : T(0);
+    }
+    __syncthreads();
+    const int jn = (n - j0 < kEvalFeat) ? n - j0 : kEvalFeat;
+    for (int jj = 0; jj < jn; ++jj) {
+#pragma unroll
+      for (int p = 0; p < kEvalPts; ++p) {
+        T z = T(0);
+#pragma unroll
+        for (int k = 0; k < D; ++k) z = fma(sF[jj][k], x[p][k], z);
+        z += sF[jj][D];
+        T sv, cv;
+        if constexpr (sizeof(T) == 8)
+          sincos_f64(z, &sv, &cv);
+        else
+          sincos_f32(z, &sv, &cv);
+#pragma unroll
+        for (int a = 0; a < kMaxA; ++a)
+          if (a < n_alpha) acc[p][a] = fma(sF[jj][D + 1 + a], ((cos_mask >> a) & 1u) ? cv : sv, acc[p][a]);
+      }
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < kEvalPts; ++p) {
+    const int64_t q = q0 + p;
+    if (q < n_q)
+#pragma unroll
+      for (int a = 0; a < kMaxA; ++a)
+        if (a < n_alpha) out[q * n_alpha + a] = acc[p][a];
+  }
+}
+
+#define FLSQ_EVAL_CASE(DIM)                                                                              \
+  case DIM:                                                                                              \
+    if (a.fp32)                                                                                          \
+      hipLaunchKernelGGL((k_evaluate<DIM, float>), dim3(grid), dim3(kEvalThreads), 0, s, a.n, a.n_alpha, \
+                         a.n_q, a.Wt32, a.b32, a.coef32, mask, (const float*)a.xq, (float*)a.out);       \
+    else                                                                                                 \
+      hipLaunchKernelGGL((k_evaluate<DIM, double>), dim3(grid), dim3(kEvalThreads), 0, s, a.n, a.n_alpha, \
+                         a.n_q, a.Wt, a.b, a.coef, mask, (const double*)a.xq, (double*)a.out);           \
+    break;
+
+hipError_t launch_evaluate(const EvalArgs& a, hipStream_t s) {
+  const uint32_t mask = a.cos_mask;
+  hipLaunchKernelGGL(k_eval_coef, dim3((a.n + 255) / 256), dim3(256), 0, s, a.d, a.n, a.n_alpha, a.Wt, a.b, a.beta,
+                     a.alphas, a.norm, a.coef, a.coef32, a.Wt32, a.b32);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || a.n_q == 0) return e;
+  const int64_t pts_per_wg = (int64_t)kEvalThreads * kEvalPts;
+  const unsigned grid = (unsigned)((a.n_q + pts_per_wg - 1) / pts_per_wg);
+  switch (a.d) {
+    FLSQ_EVAL_CASE(1) FLSQ_EVAL_CASE(2) FLSQ_EVAL_CASE(3) FLSQ_EVAL_CASE(4)
+    FLSQ_EVAL_CASE(5) FLSQ_EVAL_CASE(6) FLSQ_EVAL_CASE(7) FLSQ_EVAL_CASE(8)
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace flsq

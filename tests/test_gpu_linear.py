@@ -1,0 +1,254 @@
+"""GPU parity of the linear path (assembly, Gram, Tikhonov solve, evaluation) against the CPU oracle.
+
+Every test calls the HIP library through its C ABI (ctypes binding) and compares
+with the oracle on the same seeded inputs.  Bars: scaled entry error <= 1e-12
+(FP64) / 1e-5 (FP32); u at the 5000 test points within 1e-7 relative L2 of the
+oracle's Householder-QR solution for the FP64 path.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2602_10541_amd import workloads as wl
+from tests.gpu_util import amplitude_bound, context, rel_l2, require_gpu
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _small_problems():
+    # several 128-feature tiles with a ragged tail, blocks not multiples of 32 / 64 rows
+    return [
+        wl.poisson(2, 300, 3.0, 1000, 237, seed=1, name="p2", n_test=500),
+        wl.poisson(6, 333, 2.0, 777, 301, seed=2, name="p6", n_test=500),
+        wl.heat(n_feat=257, n_int=900, n_ic=133, n_bc=190, n_query=0, seed=3, n_test=500),
+        wl.inverse_heat(n_feat=130, n_int=500, n_ic=70, n_bc=65, n_obs=50, n_hyp=4, seed=4),
+    ]
+
+
+def _dev(prob):
+    _, fl = require_gpu()
+    return fl.DeviceProblem(prob)
+
+
+@pytest.mark.parametrize("fp32", [False, True])
+def test_assembly_matches_oracle(fp32):
+    torch, fl = require_gpu()
+    ctx = context()
+    for prob in _small_problems():
+        dp = _dev(prob)
+        P, N = dp.n_rows, prob.n_feat
+        A = torch.empty((P, N), dtype=torch.float32 if fp32 else torch.float64, device="cuda")
+        rhs = torch.empty(P, dtype=torch.float64, device="cuda")
+        fl.flsq_assemble(ctx, dp.basis, dp.rows, A, rhs, fp32=fp32)
+        A = A.double().cpu().numpy()
+        r0 = 0
+        for bl in prob.blocks:
+            ref = oracle.assemble(prob.W, prob.b, bl.x, bl.terms, bl.weight, prob.normalize)
+            s = amplitude_bound(prob.W, bl.terms, bl.weight, prob.normalize)
+            e = np.abs(A[r0:r0 + bl.n] - ref) / np.maximum(s, 1e-300)[None, :]
+            bar = 1e-5 if fp32 else 1e-12
+            assert e.max() <= bar, (prob.name, bl.name, fp32, e.max())
+            r0 += bl.n
+        ref_rhs = np.concatenate([bl.weight * bl.rhs for bl in prob.blocks])
+        np.testing.assert_array_equal(rhs.cpu().numpy(), ref_rhs)
+
+
+def test_sin_accuracy_wide_phase():
+    """sin(w x + b) for |z| up to ~400 against numpy's double sin (identity operator, no normalisation)."""
+    torch, fl = require_gpu()
+    ctx = context()
+    rng = np.random.default_rng(0)
+    W = rng.uniform(-200, 200, size=(512, 1))
+    b = rng.uniform(0, 2 * math.pi, size=512)
+    x = rng.uniform(0, 1, size=(96, 1))
+    Wt = torch.tensor(W, dtype=torch.float64, device="cuda")
+    bt = torch.tensor(b, dtype=torch.float64, device="cuda")
+    xt = torch.tensor(x, dtype=torch.float64, device="cuda")
+    basis = fl.make_basis(Wt, bt, normalize=False)
+    rows = fl.make_rows([(xt, [(1.0, (0,))], 1.0, None)], 1)
+    for fp32, tol in ((False, 2e-15), (True, 1e-6)):
+        A = torch.empty((96, 512), dtype=torch.float32 if fp32 else torch.float64, device="cuda")
+        fl.flsq_assemble(ctx, basis, rows, A, None, fp32=fp32)
+        z = x @ W.T + b
+        if fp32:  # the float32 phase the kernel forms: round(w x) + b, both in float32
+            z = ((x.astype(np.float32) @ W.T.astype(np.float32)) + b.astype(np.float32)[None, :]).astype(np.float64)
+        err = np.abs(A.double().cpu().numpy() - np.sin(z))
+        assert err.max() <= tol, (fp32, err.max())
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_gram_matches_oracle(prec):
+    torch, fl = require_gpu()
+    ctx = context()
+    for prob in _small_problems():
+        dp = _dev(prob)
+        N = prob.n_feat
+        G = torch.empty((N, N), dtype=torch.float64, device="cuda")
+        c = torch.empty(N, dtype=torch.float64, device="cuda")
+        fl.flsq_gram(ctx, dp.basis, dp.rows, prec, G, c)
+        A, r = oracle.assemble_system(prob)
+        Gref = A.T @ A
+        Gg = G.cpu().numpy()
+        err = np.linalg.norm(Gg - Gref) / np.linalg.norm(Gref)
+        bar = 1e-13 if prec == 0 else 2e-6
+        assert err <= bar, (prob.name, prec, err)
+        np.testing.assert_allclose(Gg, Gg.T, rtol=0, atol=0)
+        cref = A.T @ r
+        assert rel_l2(c.cpu().numpy(), cref) <= 1e-13
+
+
+def _solve(dp, prob, prec=0, max_refine=10, tol=1e-12):
+    torch, fl = require_gpu()
+    ctx = context()
+    beta = torch.empty(prob.n_feat, dtype=torch.float64, device="cuda")
+    st, info = fl.flsq_solve_linear(ctx, dp.basis, dp.rows, fl.solve_opts(prob.mu, prec, max_refine, tol), beta)
+    return st, info, beta.cpu().numpy()
+
+
+@pytest.mark.parametrize("idx", [0, 1, 2])
+def test_solve_linear_small_matches_oracle(idx):
+    prob = _small_problems()[idx]
+    dp = _dev(prob)
+    st, info, beta = _solve(dp, prob)
+    ref = oracle.solve_linear(prob)
+    zero = [tuple([0] * prob.d)]
+    u = oracle.evaluate(prob.W, prob.b, beta, prob.x_test, zero)[:, 0]
+    uref = oracle.evaluate(prob.W, prob.b, ref, prob.x_test, zero)[:, 0]
+    assert rel_l2(u, uref) <= 1e-7, (prob.name, rel_l2(u, uref), info.as_dict())
+    # first-order optimality of the Tikhonov problem, checked with the oracle's assembly
+    A, r = oracle.assemble_system(prob)
+    g = A.T @ (r - A @ beta) - prob.mu * beta
+    assert np.linalg.norm(g) <= 1e-8 * np.linalg.norm(A.T @ r)
+
+
+def test_solve_linear_poisson2d_full():
+    """2D Poisson, N = 500, 2000 + 400 rows, FP64 end to end."""
+    prob = wl.config("poisson2d")
+    dp = _dev(prob)
+    st, info, beta = _solve(dp, prob)
+    gold = np.load(os.path.join(GOLDEN, "poisson2d.npz"))
+    u = oracle.evaluate(prob.W, prob.b, beta, prob.x_test, [(0, 0)])[:, 0]
+    assert rel_l2(u, gold["u_test"]) <= 1e-7, (rel_l2(u, gold["u_test"]), info.as_dict())
+    assert rel_l2(u, prob.u_test) <= 1e-6
+
+
+def test_solve_linear_poisson6d_full():
+    """6D Poisson at full size (N = 4096, 32768 + 8192 rows): FP64 path vs the oracle's stored solution."""
+    path = os.path.join(GOLDEN, "poisson6d.npz")
+    if not os.path.exists(path):
+        pytest.skip("golden values not generated")
+    prob = wl.config("poisson6d")
+    dp = _dev(prob)
+    st, info, beta = _solve(dp, prob)
+    gold = np.load(path)
+    u = oracle.evaluate(prob.W, prob.b, beta, prob.x_test, [tuple([0] * 6)])[:, 0]
+    assert rel_l2(u, gold["u_test"]) <= 1e-7, (rel_l2(u, gold["u_test"]), info.as_dict())
+    A, r = oracle.assemble_system(prob)
+    res = A @ beta - r
+    obj = res @ res + prob.mu * beta @ beta
+    assert obj <= float(gold["objective"]) * (1 + 1e-9)
+
+
+def test_fp32_preconditioned_path_well_conditioned():
+    """FP32 Gram as a preconditioner reaches the FP64 answer on a well-conditioned 6D case."""
+    prob = wl.poisson(6, 512, 2.0, 4000, 1000, seed=5, name="p6w", n_test=500)
+    dp = _dev(prob)
+    st, info, beta = _solve(dp, prob, prec=1, max_refine=60, tol=1e-13)
+    ref = oracle.solve_linear(prob)
+    u = oracle.evaluate(prob.W, prob.b, beta, prob.x_test, [tuple([0] * 6)])[:, 0]
+    uref = oracle.evaluate(prob.W, prob.b, ref, prob.x_test, [tuple([0] * 6)])[:, 0]
+    assert rel_l2(u, uref) <= 1e-7, (rel_l2(u, uref), info.as_dict())
+
+
+@pytest.mark.parametrize("fp32", [False, True])
+def test_evaluate_matches_oracle(fp32):
+    torch, fl = require_gpu()
+    ctx = context()
+    rng = np.random.default_rng(9)
+    for d, N, Q in ((2, 300, 1000), (4, 257, 777), (6, 129, 513)):
+        W = rng.normal(0, 3, size=(N, d))
+        b = rng.uniform(0, 2 * math.pi, N)
+        beta = rng.normal(size=N)
+        xq = rng.uniform(0, 1, size=(Q, d))
+        alphas = [tuple([0] * d)] + [tuple(1 if i == k else 0 for i in range(d)) for k in range(d)]
+        alphas.append(tuple([2] + [0] * (d - 1)))
+        alphas = alphas[:8]
+        ref = oracle.evaluate(W, b, beta, xq, alphas)
+        Wt = torch.tensor(W, dtype=torch.float64, device="cuda")
+        bt = torch.tensor(b, dtype=torch.float64, device="cuda")
+        bet = torch.tensor(beta, dtype=torch.float64, device="cuda")
+        dt = torch.float32 if fp32 else torch.float64
+        xt = torch.tensor(xq, dtype=dt, device="cuda")
+        out = torch.empty((Q, len(alphas)), dtype=dt, device="cuda")
+        fl.flsq_evaluate(ctx, fl.make_basis(Wt, bt), bet, xt, alphas, out)
+        got = out.double().cpu().numpy()
+        # scale of output a: norm * sum_j |beta_j| |W_j^alpha|
+        for a, al in enumerate(alphas):
+            mono = np.prod(np.abs(W) ** np.array(al)[None, :], axis=1)
+            scale = np.sum(np.abs(beta) * mono) / math.sqrt(N)
+            if fp32:
+                xr = xq.astype(np.float32).astype(np.float64)
+                ref_a = oracle.evaluate(W, b, beta, xr, [al])[:, 0]
+                bar = 2e-5
+            else:
+                ref_a = ref[:, a]
+                bar = 1e-13
+            e = np.abs(got[:, a] - ref_a).max() / scale
+            assert e <= bar, (d, al, fp32, e)
+
+
+# ----------------------------------------------------------------------------- failure handling
+
+def test_rejects_multi_index_beyond_d():
+    torch, fl = require_gpu()
+    ctx = context()
+    prob = wl.poisson(2, 64, 2.0, 100, 20, seed=1, n_test=10)
+    dp = _dev(prob)
+    bad = fl.make_rows([(dp.xs[0], [(1.0, (0, 0, 1))], 1.0, dp.rhs[0])], 2)
+    beta = torch.empty(64, dtype=torch.float64, device="cuda")
+    with pytest.raises(fl.FlsqError) as ei:
+        fl.flsq_solve_linear(ctx, dp.basis, bad, fl.solve_opts(1e-10), beta)
+    assert ei.value.status == fl.FLSQ_EINVAL
+
+
+def test_rejects_nan_points():
+    torch, fl = require_gpu()
+    ctx = context()
+    prob = wl.poisson(2, 64, 2.0, 100, 20, seed=1, n_test=10)
+    prob.blocks[0].x[5, 1] = float("nan")
+    dp = _dev(prob)
+    beta = torch.empty(64, dtype=torch.float64, device="cuda")
+    with pytest.raises(fl.FlsqError) as ei:
+        fl.flsq_solve_linear(ctx, dp.basis, dp.rows, fl.solve_opts(1e-10), beta)
+    assert ei.value.status == fl.FLSQ_ENONFINITE
+
+
+def test_duplicated_features_without_tikhonov():
+    """mu = 0 with two identical features: the Gram is singular; the solve shifts or reports ENOTSPD."""
+    torch, fl = require_gpu()
+    ctx = context()
+    prob = wl.poisson(2, 64, 2.0, 300, 60, seed=1, n_test=10)
+    prob.W[1] = prob.W[0]
+    prob.b[1] = prob.b[0]
+    prob.mu = 0.0
+    dp = _dev(prob)
+    beta = torch.empty(64, dtype=torch.float64, device="cuda")
+    st, info = fl.flsq_solve_linear(ctx, dp.basis, dp.rows, fl.solve_opts(0.0, 0, 5, 1e-12), beta, check=False)
+    assert st in (fl.FLSQ_OK, fl.FLSQ_ENOTSPD, fl.FLSQ_ENOCONV)
+    if st != fl.FLSQ_ENOTSPD:
+        assert info.chol_retries >= 1 and info.shift > 0
+        assert np.all(np.isfinite(beta.cpu().numpy()))
+
+
+def test_max_refine_limit_reports_noconv():
+    torch, fl = require_gpu()
+    ctx = context()
+    prob = wl.poisson(6, 256, 2.0, 2000, 500, seed=1, n_test=10)
+    dp = _dev(prob)
+    beta = torch.empty(256, dtype=torch.float64, device="cuda")
+    st, info = fl.flsq_solve_linear(ctx, dp.basis, dp.rows, fl.solve_opts(1e-10, 1, 1, 1e-30), beta, check=False)
+    assert st == fl.FLSQ_ENOCONV and info.refine_iters == 1
