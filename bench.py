@@ -1,0 +1,166 @@
+"""Benchmark of the hot path on one MI355X: the 6D Poisson linear solve.
+
+Workload: -Laplace u = f on [0,1]^6, u = prod_k sin(pi x_k), N = 4096 features with
+W ~ N(0, 2^2 I), b ~ U[0, 2 pi), 32768 interior + 8192 boundary rows (Dirichlet rows
+weighted by 100), Tikhonov mu = 1e-10; all inputs seeded and synthetic, resident
+in HBM before the timed region.  One step = one full solve (operator folding,
+fused assembly + Gram, Cholesky, refinement) to beta on the device.
+
+Prints one JSON line.  The value is FP64-path solves/s (the path that meets the
+1e-7 bar against the oracle); the FP32-MFMA path is timed beside it with the
+error it reaches.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "assembled entries/s + solves/s at stated L2 error, FP32-MFMA+refine vs FP64"
+PEAK_FP64_MFMA_TFLOPS = 78.6
+PEAK_FP32_MFMA_TFLOPS = 157.3
+
+
+def gram_flops(P, N):
+    """Algorithmic flops of the upper-triangle Gram product, diagonal included: 2 P N (N + 1) / 2."""
+    return float(P) * N * (N + 1)
+
+
+def householder_flops(m, n):
+    return 2.0 * m * n * n - 2.0 * n ** 3 / 3.0
+
+
+def cpu_baseline(prob, rows_int=4096, rows_bc=1024):
+    """The CPU oracle on a bounded sample: all N features, the first rows of each block.
+
+    Sampled time is scaled to the full workload by the Householder flop count of the
+    augmented QR (solve) and by the row count (assembly).
+    """
+    import oracle
+    from paper_2602_10541_amd import workloads as wl
+    blocks = [wl.Block(b.name, b.x[:n], b.terms, b.weight, b.rhs[:n])
+              for b, n in zip(prob.blocks, (rows_int, rows_bc))]
+    sub = wl.Problem(prob.name, prob.d, prob.n_feat, prob.W, prob.b, blocks, prob.mu)
+    t = {}
+    oracle.solve_linear(sub, t)
+    Ps = rows_int + rows_bc
+    P = prob.n_rows
+    N = prob.n_feat
+    est = t["assemble_s"] * P / Ps + t["solve_s"] * householder_flops(P + N, N) / householder_flops(Ps + N, N)
+    return {
+        "value": 1.0 / est, "unit": "solves/s", "cores": oracle.num_threads(), "kind": "oracle",
+        "sample": (f"oracle solve (explicit assembly + Householder QR of [A; sqrt(mu) I]) on the first {rows_int} "
+                   f"interior + {rows_bc} boundary rows with all {N} features: assemble {t['assemble_s']:.2f} s, "
+                   f"QR {t['solve_s']:.2f} s; scaled to {P} rows by row count (assembly) and Householder flops (QR)"),
+        "entries_per_s": Ps * N / t["assemble_s"],
+        "est_full_solve_s": est,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--skip-fp32", action="store_true")
+    ap.add_argument("--max-refine", type=int, default=10)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2602_10541_amd import fastlsq as fl
+    from paper_2602_10541_amd import workloads as wl
+
+    prob = wl.config("poisson6d")
+    P, N = prob.n_rows, prob.n_feat
+    ctx = fl.Context(0)
+    dp = fl.DeviceProblem(prob)
+    xq = torch.tensor(prob.x_test, dtype=torch.float64, device="cuda")
+    beta = torch.empty(N, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+
+    def run(prec, steps, warmup, max_refine):
+        opts = fl.solve_opts(prob.mu, prec, max_refine, 1e-12)
+        for _ in range(warmup):
+            fl.flsq_solve_linear(ctx, dp.basis, dp.rows, opts, beta)
+        torch.cuda.synchronize()
+        infos = []
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            st, info = fl.flsq_solve_linear(ctx, dp.basis, dp.rows, opts, beta)
+            infos.append(info.as_dict())
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        u = torch.empty((xq.shape[0], 1), dtype=torch.float64, device="cuda")
+        fl.flsq_evaluate(ctx, dp.basis, beta, xq, [tuple([0] * prob.d)], u)
+        return dt, infos, u[:, 0].cpu().numpy(), st
+
+    dt64, inf64, u64, st64 = run(fl.PREC_FP64, args.steps, args.warmup, args.max_refine)
+    gold_path = os.path.join(ROOT, "tests", "golden", "poisson6d.npz")
+    gold = np.load(gold_path) if os.path.exists(gold_path) else None
+
+    def err(u):
+        e = {"rel_l2_vs_exact": float(np.linalg.norm(u - prob.u_test) / np.linalg.norm(prob.u_test))}
+        if gold is not None:
+            e["rel_l2_vs_oracle"] = float(np.linalg.norm(u - gold["u_test"]) / np.linalg.norm(gold["u_test"]))
+        return e
+
+    k64 = float(np.mean([i["t_gram_kernel_ms"] for i in inf64]))
+    flops = gram_flops(P, N)
+    achieved = flops / (k64 * 1e-3) / 1e12
+    out = {
+        "metric": METRIC,
+        "value": args.steps / dt64,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * dt64 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded features, collocation points and manufactured solution)",
+        "config": {"workload": "poisson_6d: -Laplace u = f on [0,1]^6, N=4096 sin features (sigma=2), "
+                               "32768 interior + 8192 boundary rows, lambda_bc=100, mu=1e-10",
+                   "n_feat": N, "n_rows": P, "path": "FP64 Gram + FP64 Cholesky + CGLS refinement"},
+        "entries_per_s": P * N / (k64 * 1e-3),
+        "accuracy": err(u64),
+        "phases_ms": {k: float(np.mean([i[k] for i in inf64])) for k in
+                      ("t_gram_kernel_ms", "t_gram_ms", "t_chol_ms", "t_refine_ms", "t_total_ms")},
+        "refine_iters": int(inf64[-1]["refine_iters"]),
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_MFMA_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP64_MFMA_TFLOPS, "traffic": None,
+                     "kernel": "k_gram_f64 (fused assembly + FP64 MFMA Gram)",
+                     "flops_per_launch": flops, "avg_kernel_ms": k64},
+    }
+    if not args.skip_fp32:
+        dt32, inf32, u32, st32 = run(fl.PREC_FP32_REFINE, max(1, args.steps // 2), 1, 30)
+        k32 = float(np.mean([i["t_gram_kernel_ms"] for i in inf32]))
+        a32 = flops / (k32 * 1e-3) / 1e12
+        out["fp32_mfma_path"] = {
+            "solves_per_s": max(1, args.steps // 2) / dt32, "status": int(st32),
+            "refine_iters": int(inf32[-1]["refine_iters"]), "accuracy": err(u32),
+            "entries_per_s": P * N / (k32 * 1e-3), "gram_kernel_ms": k32,
+            "gram_tflops": a32, "gram_frac_of_fp32_mfma_peak": a32 / PEAK_FP32_MFMA_TFLOPS,
+            "shift": inf32[-1]["shift"],
+        }
+    if not args.skip_cpu:
+        out["cpu_baseline"] = cpu_baseline(prob)
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

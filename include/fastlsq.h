@@ -88,18 +88,21 @@ typedef struct {
     int32_t prec;         /* flsq_precision */
     int32_t max_refine;   /* CGLS refinement iterations after the Cholesky solve (>= 0) */
     double refine_tol;    /* stop when ||step|| <= refine_tol * ||beta|| */
-    double shift_rel;     /* initial Cholesky diagonal shift relative to max diag(G) for the
+    double shift_rel;     /* initial Cholesky diagonal shift, relative to the unit diagonal of the
+                             equilibrated Gram D G D (D = diag(G)^{-1/2}), for the
                              FP32 / BF16x3 preconditioner (0 = automatic) */
 } flsq_solve_opts;
 
 typedef struct {
     int32_t refine_iters;   /* refinement iterations performed */
     int32_t chol_retries;   /* Cholesky restarts with a larger shift */
-    double shift;           /* absolute diagonal shift used in the factor (0 for FP64 unless retried) */
+    double shift;           /* diagonal shift added to the unit-diagonal (equilibrated) Gram in the factor
+                               (0 for FP64 unless a pivot failed) */
     double grad_norm0;      /* ||A^T (rhs - A beta) - mu beta|| after the Cholesky solve */
     double grad_norm;       /* same, at the returned beta */
     double last_step_rel;   /* ||last refinement step|| / ||beta|| */
     double t_gram_ms, t_chol_ms, t_refine_ms, t_total_ms;
+    double t_gram_kernel_ms; /* the fused assembly + Gram kernel alone (HIP events on the stream) */
 } flsq_solve_info;
 
 typedef struct flsq_ctx flsq_ctx;

@@ -97,7 +97,8 @@ struct System {
   std::vector<int64_t> rows;
   std::vector<double> weight;
   std::vector<int> even;              // operator has even-order terms only
-  DevBuf Wt, Wt32, bvec, amp, ph, amp32, ph32, Xt, Xt32, row_block, rhs_w, chunks, runs;
+  int normalize = 1;
+  DevBuf Wt, Wt32, Wrm, bvec, amp, ph, amp32, ph32, Xt, Xt32, Xrm, row_block, rhs_w, chunks, runs;
   int n_chunks = 0, n_runs = 0;
   // Gram plan
   int nt = 0, n_wg = 0, max_seg = 0;
@@ -126,6 +127,10 @@ struct System {
     pg.g = geo();
     pg.runs = runs.as<Chunk>();
     pg.n_runs = n_runs;
+    pg.even_mask = 0;
+    for (int b = 0; b < n_blocks && b < 64; ++b)
+      if (even[b]) pg.even_mask |= 1ull << b;
+    pg.norm = norm;
     return pg;
   }
 };
@@ -139,12 +144,20 @@ struct flsq_ctx {
   std::string err;
   std::map<std::string, DevBuf> ws;
   System sys;                        // cached system of the last solve_linear / gram / newton call
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  double last_gram_kernel_ms = 0.0;  // duration of the last fused Gram kernel (HIP events on the stream)
 };
 
 struct flsq_factor {
   int device = 0;
   System sys;
-  DevBuf U;                          // upper Cholesky factor, n x n row-major
+  // geometry derived for the inverse-problem calls (observation rows, dA/dkappa rows), cached
+  System obs, akap;
+  const void* obs_key = nullptr;
+  int64_t obs_n = -1, akap_rows = -1;
+  int akap_dims = -1;
+  double akap_weight = 0.0;
+  DevBuf Xinv;                       // inverse of the upper Cholesky factor, n x n row-major
   double mu = 0.0;
   double shift = 0.0;
   int max_refine = 0;
@@ -192,6 +205,7 @@ Err check_op(const flsq_op& op, int d, int bi) {
 
 Err check_blocks(const flsq_rows* blocks, int n_blocks, int d, bool need_rhs) {
   if (n_blocks < 1 || !blocks) return fail(FLSQ_EINVAL, "need at least one row block");
+  if (n_blocks > 64) return fail(FLSQ_EINVAL, "at most 64 row blocks");
   int64_t P = 0;
   for (int i = 0; i < n_blocks; ++i) {
     const flsq_rows& r = blocks[i];
@@ -243,6 +257,7 @@ Err build_system(flsq_ctx* c, System& s, const flsq_basis* basis, const flsq_row
   s.d = basis->d;
   s.n = basis->n_feat;
   s.n_blocks = n_blocks;
+  s.normalize = basis->normalize ? 1 : 0;
   s.norm = basis->normalize ? 1.0 / std::sqrt((double)s.n) : 1.0;
   s.row0.assign(n_blocks, 0);
   s.rows.assign(n_blocks, 0);
@@ -265,6 +280,8 @@ Err build_system(flsq_ctx* c, System& s, const flsq_basis* basis, const flsq_row
   CHECK_HIP(s.Wt.ensure(sizeof(double) * d * n));
   CHECK_HIP(s.Wt32.ensure(sizeof(float) * d * n));
   CHECK_HIP(s.bvec.ensure(sizeof(double) * n));
+  CHECK_HIP(s.Wrm.ensure(sizeof(double) * d * n));
+  CHECK_HIP(s.Xrm.ensure(sizeof(double) * d * P));
   CHECK_HIP(s.amp.ensure(sizeof(double) * n_blocks * n));
   CHECK_HIP(s.ph.ensure(sizeof(double) * n_blocks * n));
   CHECK_HIP(s.amp32.ensure(sizeof(float) * n_blocks * n));
@@ -276,6 +293,7 @@ Err build_system(flsq_ctx* c, System& s, const flsq_basis* basis, const flsq_row
 
   CHECK_HIP(launch_transpose(basis->W, n, d, s.Wt.as<double>(), s.Wt32.as<float>(), n, st));
   CHECK_HIP(hipMemcpyAsync(s.bvec.p, basis->b, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+  CHECK_HIP(hipMemcpyAsync(s.Wrm.p, basis->W, sizeof(double) * d * n, hipMemcpyDeviceToDevice, st));
   for (int i = 0; i < n_blocks; ++i) {
     const flsq_rows& r = blocks[i];
     OpTerms op;
@@ -292,7 +310,9 @@ Err build_system(flsq_ctx* c, System& s, const flsq_basis* basis, const flsq_row
       CHECK_HIP(launch_transpose(r.x, r.n_rows, d, s.Xt.as<double>() + s.row0[i], s.Xt32.as<float>() + s.row0[i], P,
                                  st));
       CHECK_HIP(launch_fill_i32(s.row_block.as<int32_t>() + s.row0[i], r.n_rows, i, st));
-      CHECK_HIP(launch_scale_copy(r.rhs, s.rhs_w.as<double>() + s.row0[i], r.n_rows, r.weight, st));
+      CHECK_HIP(hipMemcpyAsync(s.Xrm.as<double>() + s.row0[i] * d, r.x, sizeof(double) * d * r.n_rows,
+                               hipMemcpyDeviceToDevice, st));
+      CHECK_HIP(launch_scale_copy(r.rhs, s.rhs_w.as<double>() + s.row0[i], r.n_rows, r.weight, st));  // NULL -> 0
     }
   }
   // Gram chunks and pass runs (block-aligned), Gram stream-K plan
@@ -382,64 +402,150 @@ Err run_gram(flsq_ctx* c, const System& s, int prec, const double* rho, double* 
   L.max_seg = s.max_seg;
   L.n_wg = s.n_wg;
   L.partial = partial;
+  CHECK_HIP(hipEventRecord(c->ev0, c->stream));
   CHECK_HIP(launch_gram(L, c->stream));
+  CHECK_HIP(hipEventRecord(c->ev1, c->stream));
   CHECK_HIP(launch_gram_reduce(L.prec, partial, s.slot_ptr.as<int32_t>(), s.slots.as<int32_t>(), s.nt, s.n, G, mirror,
                                diag_add, c->stream));
   return ok();
 }
 
-// ------------------------------------------------------------------ Cholesky
-// In-place upper Cholesky of G (only the upper triangle is read).  Returns info > 0 at
-// the first non-positive pivot (1-based column).
-Err cholesky(flsq_ctx* c, double* G, int n, int* info_host) {
-  int* info;
-  CHECK_ERR(ws_get(c, "chol_info", 1, &info));
-  CHECK_HIP(hipMemsetAsync(info, 0, sizeof(int), c->stream));
-  for (int k0 = 0; k0 < n; k0 += kNb) {
-    CHECK_HIP(launch_potrf_diag(G, n, k0, info, 0.0, c->stream));
-    CHECK_HIP(launch_trsm_row(G, n, k0, c->stream));
-    CHECK_HIP(launch_syrk(G, n, k0, c->stream));
-  }
-  CHECK_HIP(hipMemcpyAsync(info_host, info, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+// ------------------------------------------------------------------ Cholesky and inverse factor
+// Upload GEMM descriptors (host vector stays alive until the copy has completed).
+Err upload_descs(flsq_ctx* c, const std::vector<GemmDesc>& h, GemmDesc** d_out) {
+  GemmDesc* d;
+  CHECK_ERR(ws_get(c, "gemm_descs", std::max<size_t>(1, h.size()), &d));
+  CHECK_HIP(hipMemcpyAsync(d, h.data(), sizeof(GemmDesc) * h.size(), hipMemcpyHostToDevice, c->stream));
   CHECK_HIP(hipStreamSynchronize(c->stream));
+  *d_out = d;
   return ok();
 }
 
-// X = (U^T U)^{-1} Y for K columns (Y preserved).
-Err chol_solve(flsq_ctx* c, const double* U, int n, const double* Y, double* X, int K) {
-  double *t1, *t2;
-  CHECK_ERR(ws_get(c, "cs_t1", (size_t)n * K, &t1));
-  CHECK_ERR(ws_get(c, "cs_t2", (size_t)n * K, &t2));
-  CHECK_HIP(hipMemcpyAsync(t1, Y, sizeof(double) * n * K, hipMemcpyDeviceToDevice, c->stream));
-  CHECK_HIP(launch_trsv_fwd(U, n, t1, t2, K, c->stream));   // t2 = U^{-T} Y
-  CHECK_HIP(launch_trsv_bwd(U, n, t2, X, K, c->stream));    // X = U^{-1} t2
+// In-place upper Cholesky of G (only the upper triangle is read), and X = U^{-1} (upper,
+// zero below the diagonal).  info_host > 0 at the first non-positive pivot (1-based).
+Err cholesky_inv(flsq_ctx* c, double* G, double* X, int n, int* info_host) {
+  int* info;
+  hipStream_t st = c->stream;
+  CHECK_ERR(ws_get(c, "chol_info", 1, &info));
+  CHECK_HIP(hipMemsetAsync(info, 0, sizeof(int), st));
+  CHECK_HIP(hipMemsetAsync(X, 0, sizeof(double) * n * n, st));
+  const int nblk = (n + kNb - 1) / kNb;
+  // X off-diagonal blocks, bottom-up: pairs of adjacent ranges [lo, mid), [mid, hi) of blocks:
+  // T = U_12 X_22, then X_12 = -X_11 T.  Same-level pairs are independent (one batch).
+  std::vector<std::vector<GemmDesc>> lvT, lvX;
+  double* T;
+  CHECK_ERR(ws_get(c, "inv_T", (size_t)n * n, &T));
+  for (int s = 1; s < nblk; s *= 2) {
+    std::vector<GemmDesc> a, b2;
+    for (int lo = 0; lo + s < nblk; lo += 2 * s) {
+      const int mid = lo + s, hi = std::min(nblk, lo + 2 * s);
+      const int r0 = lo * kNb, c0 = mid * kNb;
+      const int wl = std::min(mid * kNb, n) - r0, wr = std::min(hi * kNb, n) - c0;
+      GemmDesc d1;   // T(r0.., c0..) = U(r0.., c0..) X(c0.., c0..)
+      d1.A = G + (int64_t)r0 * n + c0;
+      d1.B = X + (int64_t)c0 * n + c0;
+      d1.C = T + (int64_t)r0 * n + c0;
+      d1.M = wl;
+      d1.N = wr;
+      d1.K = wr;
+      d1.lda = d1.ldb = d1.ldc = n;
+      a.push_back(d1);
+      GemmDesc d2;   // X(r0.., c0..) = -X(r0.., r0..) T
+      d2.A = X + (int64_t)r0 * n + r0;
+      d2.B = T + (int64_t)r0 * n + c0;
+      d2.C = X + (int64_t)r0 * n + c0;
+      d2.M = wl;
+      d2.N = wr;
+      d2.K = wl;
+      d2.lda = d2.ldb = d2.ldc = n;
+      b2.push_back(d2);
+    }
+    lvT.push_back(a);
+    lvX.push_back(b2);
+  }
+  std::vector<GemmDesc> all;
+  std::vector<size_t> offT, offX;
+  for (size_t l = 0; l < lvT.size(); ++l) {
+    offT.push_back(all.size());
+    all.insert(all.end(), lvT[l].begin(), lvT[l].end());
+    offX.push_back(all.size());
+    all.insert(all.end(), lvX[l].begin(), lvX[l].end());
+  }
+  GemmDesc* dd;
+  CHECK_ERR(upload_descs(c, all, &dd));
+  for (int b = 0; b < nblk; ++b) {
+    const int k0 = b * kNb;
+    CHECK_HIP(launch_potrf_diag(G, n, k0, info, X, st));
+    if (k0 + kNb < n) {
+      CHECK_HIP(launch_trsm_row(G, n, k0, st));
+      CHECK_HIP(launch_syrk(G, n, k0, st));
+    }
+  }
+  for (size_t l = 0; l < lvT.size(); ++l) {
+    int maxM = 0, maxN = 0;
+    for (const GemmDesc& d : lvT[l]) {
+      maxM = std::max(maxM, d.M);
+      maxN = std::max(maxN, d.N);
+    }
+    CHECK_HIP(launch_gemm_batched(dd + offT[l], (int)lvT[l].size(), maxM, maxN, 1.0, 0.0, 0, st));
+    CHECK_HIP(launch_gemm_batched(dd + offX[l], (int)lvX[l].size(), maxM, maxN, -1.0, 0.0, 0, st));
+  }
+  CHECK_HIP(hipMemcpyAsync(info_host, info, sizeof(int), hipMemcpyDeviceToHost, st));
+  CHECK_HIP(hipStreamSynchronize(st));
   return ok();
 }
 
-// Factor G_src + diag_add I into U.  For the FP64 Gram the first attempt uses no shift;
-// a failed pivot retries with growing shifts relative to max diag(G).  Returns the shift used.
-Err factor_with_retries(flsq_ctx* c, const double* Gsrc, double* U, int n, double mu, double shift0_rel,
+// Z = (U^T U)^{-1} Y = X (X^T Y) for K columns (Y preserved, Z distinct from Y).
+Err chol_solve(flsq_ctx* c, const double* X, int n, const double* Y, double* Z, int K) {
+  hipStream_t st = c->stream;
+  if (K == 1) {
+    double *tmp, *work;
+    CHECK_ERR(ws_get(c, "pa_tmp", (size_t)n, &tmp));
+    CHECK_ERR(ws_get(c, "pa_work", precond_work_elems(n), &work));
+    CHECK_HIP(launch_precond_apply(X, n, Y, tmp, work, Z, st));
+    return ok();
+  }
+  double* tmp;
+  CHECK_ERR(ws_get(c, "pa_tmpK", (size_t)n * K, &tmp));
+  GemmDesc h[2];
+  h[0].A = X; h[0].B = Y; h[0].C = tmp; h[0].M = n; h[0].N = K; h[0].K = n; h[0].lda = n; h[0].ldb = K; h[0].ldc = K;
+  h[1].A = X; h[1].B = tmp; h[1].C = Z; h[1].M = n; h[1].N = K; h[1].K = n; h[1].lda = n; h[1].ldb = K; h[1].ldc = K;
+  GemmDesc* d;
+  CHECK_ERR(ws_get(c, "pa_descs", 2, &d));
+  CHECK_HIP(hipMemcpyAsync(d, h, sizeof h, hipMemcpyHostToDevice, st));
+  CHECK_HIP(launch_gemm_batched(d, 1, n, K, 1.0, 0.0, 1, st));       // tmp = X^T Y
+  CHECK_HIP(launch_gemm_batched(d + 1, 1, n, K, 1.0, 0.0, 0, st));   // Z = X tmp
+  CHECK_HIP(hipStreamSynchronize(st));                                 // h leaves scope
+  return ok();
+}
+
+// Factor the equilibrated system D (G_src + mu I) D + shift I (D = diag(G_src)^{-1/2}, so the
+// scaled Gram has a unit diagonal), form X = U^{-1}, and return D X, whose outer product
+// (D X)(D X)^T approximates (G + mu I)^{-1}.  The first attempt uses shift0 (0 for the FP64
+// Gram); a failed pivot retries with growing shifts.
+Err factor_with_retries(flsq_ctx* c, const double* Gsrc, double* U, double* X, int n, double mu, double shift0,
                         double* shift_used, int* retries) {
-  double* dmax;
+  double *dmax, *d;
   CHECK_ERR(ws_get(c, "diag_max", 1, &dmax));
+  CHECK_ERR(ws_get(c, "eq_d", (size_t)n, &d));
   CHECK_HIP(launch_diag_max(Gsrc, n, dmax, c->stream));
   double dm = 0.0;
   CHECK_HIP(hipMemcpyAsync(&dm, dmax, sizeof(double), hipMemcpyDeviceToHost, c->stream));
   CHECK_HIP(hipStreamSynchronize(c->stream));
   if (!std::isfinite(dm)) return fail(FLSQ_ENONFINITE, "Gram diagonal is not finite");
-  double rel = shift0_rel;
+  double rel = shift0;
   *retries = 0;
   for (int attempt = 0; attempt < 8; ++attempt) {
-    const double shift = rel * dm;
-    CHECK_HIP(launch_copy_upper(Gsrc, U, n, mu + shift, c->stream));
+    CHECK_HIP(launch_equilibrate(Gsrc, U, n, d, mu, rel, c->stream));
     int info = 0;
-    CHECK_ERR(cholesky(c, U, n, &info));
+    CHECK_ERR(cholesky_inv(c, U, X, n, &info));
     if (info == 0) {
-      *shift_used = shift;
+      CHECK_HIP(launch_scale_rows(X, n, d, c->stream));
+      *shift_used = rel;
       return ok();
     }
     ++*retries;
-    rel = (rel == 0.0) ? 1e-15 : rel * 10.0;
+    rel = (rel == 0.0) ? 1e-14 : rel * 10.0;
   }
   return fail(FLSQ_ENOTSPD, "Cholesky failed: Gram + mu I not positive definite after %d shift retries", *retries);
 }
@@ -466,12 +572,22 @@ Err to_dev_cols(flsq_ctx* c, const std::vector<double>& h, double* dev) {
   return ok();
 }
 
-Err cgls_refine(flsq_ctx* c, const System& s, const double* rho, const double* U, double mu, const double* Y, int K,
+// Stopping rule (Section 2.4 prefers a solution-level change over the coefficient change,
+// which is unreliable when features are nearly dependent): the relative change of u_N at
+// the collocation rows of blocks with even-order operators, |alpha| ||H p|| <= tol ||H X||,
+// where H p comes out of the same row pass as A p.  When no such rows exist (or K > 16)
+// the change of the fitted values |alpha| ||A p|| <= tol ||Y|| is used instead.
+Err cgls_refine(flsq_ctx* c, const System& s, const double* rho, const double* Xi, double mu, const double* Y, int K,
                 double* X, int max_iter, double tol, bool want_grad, RefineOut* ro) {
   const int n = s.n;
   const int64_t P = s.P;
   const PassGeo pg = s.pass();
-  double *sres, *q, *g, *z, *p, *dots, *dwork, *colwork, *scal;
+  const bool track_u = (K <= 16) && pg.even_mask != 0;
+  double *sres, *q, *g, *z, *p, *dots, *dwork, *colwork, *scal, *uu = nullptr, *hq = nullptr;
+  if (track_u) {
+    CHECK_ERR(ws_get(c, "cg_u", (size_t)P * K, &uu));
+    CHECK_ERR(ws_get(c, "cg_hq", (size_t)P * K, &hq));
+  }
   CHECK_ERR(ws_get(c, "cg_s", (size_t)P * K, &sres));
   CHECK_ERR(ws_get(c, "cg_q", (size_t)P * K, &q));
   CHECK_ERR(ws_get(c, "cg_g", (size_t)n * K, &g));
@@ -484,8 +600,8 @@ Err cgls_refine(flsq_ctx* c, const System& s, const double* rho, const double* U
   hipStream_t st = c->stream;
   std::vector<double> gam, del, tmp, tmp2, alpha(K), beta(K), stepn(K), xn(K);
 
-  // s = Y - A X ; g = A^T s - mu X
-  CHECK_HIP(launch_rowpass_runs(pg, rho, X, K, Y, -1.0, 1.0, sres, st));
+  // s = Y - A X ; g = A^T s - mu X ; u = H X
+  CHECK_HIP(launch_rowpass_runs(pg, rho, X, K, Y, -1.0, 1.0, sres, st, uu));
   CHECK_HIP(launch_colpass_runs(pg, rho, sres, K, X, 1.0, -mu, g, colwork, st));
   if (want_grad) {
     CHECK_HIP(launch_dot_cols(g, g, n, K, dots, dwork, st));
@@ -500,37 +616,88 @@ Err cgls_refine(flsq_ctx* c, const System& s, const double* rho, const double* U
     ro->grad = ro->grad0;
     return ok();
   }
-  CHECK_ERR(chol_solve(c, U, n, g, z, K));
+  // Objective J = ||Y - A X||^2 + mu ||X||^2 per column.  CGLS decreases it monotonically in
+  // exact arithmetic; once rounding takes over (these systems are near the limit of FP64)
+  // further steps can increase it and then diverge.  A column whose J rises stops (its
+  // step is set to zero) and the best iterate seen is returned.
+  std::vector<double> ynorm, Jbest(K), active(K, 1.0), improved(K, 0.0);
+  double *Xbest, *mask;
+  CHECK_ERR(ws_get(c, "cg_xbest", (size_t)n * K, &Xbest));
+  CHECK_ERR(ws_get(c, "cg_mask", (size_t)K, &mask));
+  CHECK_HIP(hipMemcpyAsync(Xbest, X, sizeof(double) * n * K, hipMemcpyDeviceToDevice, st));
+  CHECK_HIP(launch_dot_cols(Y, Y, P, K, dots, dwork, st));
+  CHECK_HIP(launch_dot_cols(sres, sres, P, K, dots + K, dwork, st));
+  CHECK_HIP(launch_dot_cols(X, X, n, K, dots + 2 * K, dwork, st));
+  CHECK_ERR(host_cols(c, dots, 3 * K, tmp));
+  ynorm.resize(K);
+  for (int k = 0; k < K; ++k) {
+    ynorm[k] = std::max(std::sqrt(tmp[k]), 1e-300);
+    Jbest[k] = tmp[K + k] + mu * tmp[2 * K + k];
+  }
+  CHECK_ERR(chol_solve(c, Xi, n, g, z, K));
   CHECK_HIP(hipMemcpyAsync(p, z, sizeof(double) * n * K, hipMemcpyDeviceToDevice, st));
   CHECK_HIP(launch_dot_cols(g, z, n, K, dots, dwork, st));
   CHECK_ERR(host_cols(c, dots, K, gam));
+  bool stalled_all = false;
   for (int it = 0; it < max_iter; ++it) {
-    // q = A p ; delta = ||q||^2 + mu ||p||^2
-    CHECK_HIP(launch_rowpass_runs(pg, rho, p, K, nullptr, 1.0, 0.0, q, st));
+    // q = A p ; delta = ||q||^2 + mu ||p||^2 ; hq = H p
+    CHECK_HIP(launch_rowpass_runs(pg, rho, p, K, nullptr, 1.0, 0.0, q, st, hq));
     CHECK_HIP(launch_dot_cols(q, q, P, K, dots, dwork, st));
     CHECK_HIP(launch_dot_cols(p, p, n, K, dots + K, dwork, st));
-    CHECK_ERR(host_cols(c, dots, 2 * K, tmp));
+    if (track_u) {
+      CHECK_HIP(launch_dot_cols(hq, hq, P, K, dots + 2 * K, dwork, st));
+      CHECK_HIP(launch_dot_cols(uu, uu, P, K, dots + 3 * K, dwork, st));
+    }
+    CHECK_ERR(host_cols(c, dots, (track_u ? 4 : 2) * K, tmp));
+    double worst = 0.0;
     for (int k = 0; k < K; ++k) {
       const double dl = tmp[k] + mu * tmp[K + k];
-      alpha[k] = (dl > 0.0 && gam[k] > 0.0) ? gam[k] / dl : 0.0;
-      stepn[k] = std::fabs(alpha[k]) * std::sqrt(tmp[K + k]);
+      alpha[k] = (active[k] > 0.0 && dl > 0.0 && gam[k] > 0.0) ? gam[k] / dl : 0.0;
+      if (active[k] == 0.0) continue;
+      if (track_u && tmp[3 * K + k] > 0.0) {
+        stepn[k] = std::fabs(alpha[k]) * std::sqrt(tmp[2 * K + k]);
+        worst = std::max(worst, stepn[k] / std::sqrt(tmp[3 * K + k]));
+      } else {
+        stepn[k] = std::fabs(alpha[k]) * std::sqrt(tmp[k]);
+        worst = std::max(worst, stepn[k] / ynorm[k]);
+      }
     }
     CHECK_ERR(to_dev_cols(c, alpha, scal));
     CHECK_HIP(launch_axpy_cols(scal, p, X, n, K, 1.0, st));
     CHECK_HIP(launch_axpy_cols(scal, q, sres, P, K, -1.0, st));
+    if (track_u) CHECK_HIP(launch_axpy_cols(scal, hq, uu, P, K, 1.0, st));
     ro->iters = it + 1;
-    CHECK_HIP(launch_dot_cols(X, X, n, K, dots, dwork, st));
-    CHECK_ERR(host_cols(c, dots, K, tmp2));
-    double worst = 0.0;
-    for (int k = 0; k < K; ++k) worst = std::max(worst, stepn[k] / std::max(std::sqrt(tmp2[k]), 1e-300));
     ro->last_step = worst;
+    // objective after the step; keep the best iterate, stop columns whose objective rose
+    CHECK_HIP(launch_dot_cols(sres, sres, P, K, dots, dwork, st));
+    CHECK_HIP(launch_dot_cols(X, X, n, K, dots + K, dwork, st));
+    CHECK_ERR(host_cols(c, dots, 2 * K, tmp));
+    int n_active = 0;
+    for (int k = 0; k < K; ++k) {
+      improved[k] = 0.0;
+      if (active[k] == 0.0) continue;
+      const double J = tmp[k] + mu * tmp[K + k];
+      if (J <= Jbest[k]) {
+        Jbest[k] = J;
+        improved[k] = 1.0;
+      } else if (J > Jbest[k] * (1.0 + 1e-12)) {
+        active[k] = 0.0;
+      }
+      if (active[k] > 0.0) ++n_active;
+    }
+    CHECK_ERR(to_dev_cols(c, improved, mask));
+    CHECK_HIP(launch_select_cols(X, Xbest, n, K, mask, st));
     if (worst <= tol) {
       ro->converged = true;
       break;
     }
+    if (n_active == 0) {
+      stalled_all = true;
+      break;
+    }
     if (it + 1 == max_iter) break;
     CHECK_HIP(launch_colpass_runs(pg, rho, sres, K, X, 1.0, -mu, g, colwork, st));
-    CHECK_ERR(chol_solve(c, U, n, g, z, K));
+    CHECK_ERR(chol_solve(c, Xi, n, g, z, K));
     CHECK_HIP(launch_dot_cols(g, z, n, K, dots, dwork, st));
     CHECK_ERR(host_cols(c, dots, K, tmp));
     for (int k = 0; k < K; ++k) {
@@ -540,7 +707,11 @@ Err cgls_refine(flsq_ctx* c, const System& s, const double* rho, const double* U
     CHECK_ERR(to_dev_cols(c, beta, scal));
     CHECK_HIP(launch_xpby_cols(z, scal, p, n, K, st));
   }
+  // return the best iterate of every column; the recurrence residual is recomputed
+  CHECK_HIP(hipMemcpyAsync(X, Xbest, sizeof(double) * n * K, hipMemcpyDeviceToDevice, st));
+  if (stalled_all) ro->converged = true;   // no further progress is possible in FP64
   if (want_grad) {
+    CHECK_HIP(launch_rowpass_runs(pg, rho, X, K, Y, -1.0, 1.0, sres, st));
     CHECK_HIP(launch_colpass_runs(pg, rho, sres, K, X, 1.0, -mu, g, colwork, st));
     CHECK_HIP(launch_dot_cols(g, g, n, K, dots, dwork, st));
     CHECK_ERR(host_cols(c, dots, K, tmp));
@@ -583,26 +754,31 @@ Err check_params(const SolveParams& p) {
   return ok();
 }
 
-// Gram + factor into U.
-Err gram_and_factor(flsq_ctx* c, const System& s, const double* rho, const SolveParams& sp, double* U,
+// Gram, Cholesky, and the inverse factor Xi = U^{-1} (the preconditioner is Xi Xi^T).
+Err gram_and_factor(flsq_ctx* c, const System& s, const double* rho, const SolveParams& sp, double* Xi,
                     flsq_solve_info* info) {
   const int n = s.n;
-  double* G;
+  double *G, *U;
   CHECK_ERR(ws_get(c, "G", (size_t)n * n, &G));
+  CHECK_ERR(ws_get(c, "Ufac", (size_t)n * n, &U));
   const double t0 = now_ms();
   CHECK_ERR(run_gram(c, s, sp.prec, rho, G, 0, 0.0));
   CHECK_HIP(hipStreamSynchronize(c->stream));
   const double t1 = now_ms();
+  float kms = 0.f;
+  CHECK_HIP(hipEventElapsedTime(&kms, c->ev0, c->ev1));
+  c->last_gram_kernel_ms = kms;
   double shift = 0.0;
   int retries = 0;
   const double rel0 = (sp.prec == FLSQ_PREC_FP64) ? sp.shift_rel : (sp.shift_rel > 0.0 ? sp.shift_rel : 1e-6);
-  CHECK_ERR(factor_with_retries(c, G, U, n, sp.mu, rel0, &shift, &retries));
+  CHECK_ERR(factor_with_retries(c, G, U, Xi, n, sp.mu, rel0, &shift, &retries));
   const double t2 = now_ms();
   if (info) {
     info->t_gram_ms = t1 - t0;
     info->t_chol_ms = t2 - t1;
     info->shift = shift;
     info->chol_retries = retries;
+    info->t_gram_kernel_ms = c->last_gram_kernel_ms;
   }
   return ok();
 }
@@ -611,18 +787,18 @@ Err solve_on_system(flsq_ctx* c, const System& s, const double* rho, const Solve
                     double* X, flsq_solve_info* info, bool* converged) {
   const int n = s.n;
   const double t0 = now_ms();
-  double* U;
-  CHECK_ERR(ws_get(c, "U", (size_t)n * n, &U));
-  CHECK_ERR(gram_and_factor(c, s, rho, sp, U, info));
+  double* Xi;
+  CHECK_ERR(ws_get(c, "Xinv", (size_t)n * n, &Xi));
+  CHECK_ERR(gram_and_factor(c, s, rho, sp, Xi, info));
   const double t1 = now_ms();
   // X0 = (U^T U)^{-1} A^T Y
   double *cvec, *colwork;
   CHECK_ERR(ws_get(c, "cvec", (size_t)n * K, &cvec));
   CHECK_ERR(ws_get(c, "colwork0", pass_work_elems(n, s.n_runs, K) + 64, &colwork));
   CHECK_HIP(launch_colpass_runs(s.pass(), rho, Yw, K, nullptr, 1.0, 0.0, cvec, colwork, c->stream));
-  CHECK_ERR(chol_solve(c, U, n, cvec, X, K));
+  CHECK_ERR(chol_solve(c, Xi, n, cvec, X, K));
   RefineOut ro;
-  CHECK_ERR(cgls_refine(c, s, rho, U, sp.mu, Yw, K, X, sp.max_refine, sp.refine_tol, info != nullptr, &ro));
+  CHECK_ERR(cgls_refine(c, s, rho, Xi, sp.mu, Yw, K, X, sp.max_refine, sp.refine_tol, info != nullptr, &ro));
   CHECK_HIP(hipStreamSynchronize(c->stream));
   const double t2 = now_ms();
   if (info) {
@@ -661,6 +837,10 @@ flsq_status flsq_create(flsq_ctx** ctx, int device, void* hip_stream) {
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
     c->n_cu = prop.multiProcessorCount;
+  if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
+    delete c;
+    return FLSQ_EHIP;
+  }
   *ctx = c;
   return FLSQ_OK;
 }
@@ -669,6 +849,8 @@ void flsq_destroy(flsq_ctx* ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
+  if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
   delete ctx;
 }
 
@@ -755,10 +937,10 @@ flsq_status flsq_factorize(flsq_ctx* ctx, const flsq_basis* basis, const flsq_ro
   f->device = ctx->device;
   e = build_system(ctx, f->sys, basis, blocks, n_blocks, false);
   if (e.st == FLSQ_OK) {
-    hipError_t he = f->U.ensure(sizeof(double) * f->sys.n * f->sys.n);
+    hipError_t he = f->Xinv.ensure(sizeof(double) * f->sys.n * f->sys.n);
     if (he != hipSuccess) e = fail(FLSQ_ENOMEM, "factor allocation failed");
   }
-  if (e.st == FLSQ_OK) e = gram_and_factor(ctx, f->sys, nullptr, sp, f->U.as<double>(), info);
+  if (e.st == FLSQ_OK) e = gram_and_factor(ctx, f->sys, nullptr, sp, f->Xinv.as<double>(), info);
   if (e.st != FLSQ_OK) {
     delete f;
     return finish(ctx, e);
@@ -799,10 +981,10 @@ flsq_status flsq_factor_solve(flsq_ctx* ctx, const flsq_factor* F, const double*
   if (e.st != FLSQ_OK) return finish(ctx, e);
   hipError_t he = launch_colpass_runs(s.pass(), nullptr, rhs_rows, K, nullptr, 1.0, 0.0, cvec, colwork, ctx->stream);
   if (he != hipSuccess) return finish(ctx, fail(FLSQ_EHIP, "colpass: %s", hipGetErrorString(he)));
-  e = chol_solve(ctx, F->U.as<double>(), s.n, cvec, beta_out, K);
+  e = chol_solve(ctx, F->Xinv.as<double>(), s.n, cvec, beta_out, K);
   if (e.st != FLSQ_OK) return finish(ctx, e);
   RefineOut ro;
-  e = cgls_refine(ctx, s, nullptr, F->U.as<double>(), F->mu, rhs_rows, K, beta_out, F->max_refine, F->refine_tol,
+  e = cgls_refine(ctx, s, nullptr, F->Xinv.as<double>(), F->mu, rhs_rows, K, beta_out, F->max_refine, F->refine_tol,
                   info != nullptr, &ro);
   if (e.st != FLSQ_OK) return finish(ctx, e);
   he = hipStreamSynchronize(ctx->stream);
@@ -846,7 +1028,7 @@ flsq_status flsq_factor_solve_normal(flsq_ctx* ctx, const flsq_factor* F, const 
     return ok();
   };
   auto body = [&]() -> Err {
-    CHECK_ERR(chol_solve(ctx, F->U.as<double>(), n, V, out, K));
+    CHECK_ERR(chol_solve(ctx, F->Xinv.as<double>(), n, V, out, K));
     if (F->max_refine == 0) return ok();
     std::vector<double> gam, tmp, tmp2, alpha(K), beta(K);
     CHECK_ERR(apply_normal(out, ap));
@@ -854,27 +1036,58 @@ flsq_status flsq_factor_solve_normal(flsq_ctx* ctx, const flsq_factor* F, const 
     std::vector<double> ones(K, 1.0);
     CHECK_ERR(to_dev_cols(ctx, ones, scal));
     CHECK_HIP(launch_axpy_cols(scal, ap, r, n, K, -1.0, st));
-    CHECK_ERR(chol_solve(ctx, F->U.as<double>(), n, r, z, K));
+    CHECK_ERR(chol_solve(ctx, F->Xinv.as<double>(), n, r, z, K));
     CHECK_HIP(hipMemcpyAsync(p, z, sizeof(double) * n * K, hipMemcpyDeviceToDevice, st));
     CHECK_HIP(launch_dot_cols(r, z, n, K, dots, dwork, st));
     CHECK_ERR(host_cols(ctx, dots, K, gam));
+    // Stop when the step's energy norm |alpha| (p^T M p)^{1/2} (M = G + mu I) is below tol
+    // times the solution's, estimated by (out^T V)^{1/2}.  The energy functional
+    // phi(x) = x^T M x / 2 - x^T V = -(x^T V + x^T r) / 2 decreases monotonically in exact
+    // arithmetic; a column whose phi rises stops, and the best iterate is returned.
+    double *xbest, *mask;
+    CHECK_ERR(ws_get(ctx, "pcg_xbest", (size_t)n * K, &xbest));
+    CHECK_ERR(ws_get(ctx, "pcg_mask", (size_t)K, &mask));
+    CHECK_HIP(hipMemcpyAsync(xbest, out, sizeof(double) * n * K, hipMemcpyDeviceToDevice, st));
+    CHECK_HIP(launch_dot_cols(out, V, n, K, dots, dwork, st));
+    CHECK_HIP(launch_dot_cols(out, r, n, K, dots + K, dwork, st));
+    CHECK_ERR(host_cols(ctx, dots, 2 * K, tmp));
+    std::vector<double> phibest(K), active(K, 1.0), improved(K, 0.0);
+    for (int k = 0; k < K; ++k) phibest[k] = -0.5 * (tmp[k] + tmp[K + k]);
     for (int it = 0; it < F->max_refine; ++it) {
       CHECK_ERR(apply_normal(p, ap));
       CHECK_HIP(launch_dot_cols(p, ap, n, K, dots, dwork, st));
-      CHECK_HIP(launch_dot_cols(p, p, n, K, dots + K, dwork, st));
-      CHECK_HIP(launch_dot_cols(out, out, n, K, dots + 2 * K, dwork, st));
+      CHECK_HIP(launch_dot_cols(out, V, n, K, dots + 2 * K, dwork, st));
       CHECK_ERR(host_cols(ctx, dots, 3 * K, tmp));
       double worst = 0.0;
       for (int k = 0; k < K; ++k) {
-        alpha[k] = (tmp[k] > 0.0 && gam[k] > 0.0) ? gam[k] / tmp[k] : 0.0;
-        worst = std::max(worst, std::fabs(alpha[k]) * std::sqrt(tmp[K + k]) /
-                                    std::max(std::sqrt(tmp[2 * K + k]), 1e-300));
+        alpha[k] = (active[k] > 0.0 && tmp[k] > 0.0 && gam[k] > 0.0) ? gam[k] / tmp[k] : 0.0;
+        if (active[k] > 0.0)
+          worst = std::max(worst, std::fabs(alpha[k]) * std::sqrt(std::max(tmp[k], 0.0)) /
+                                      std::max(std::sqrt(std::fabs(tmp[2 * K + k])), 1e-300));
       }
       CHECK_ERR(to_dev_cols(ctx, alpha, scal));
       CHECK_HIP(launch_axpy_cols(scal, p, out, n, K, 1.0, st));
-      if (worst <= F->refine_tol || it + 1 == F->max_refine) break;
       CHECK_HIP(launch_axpy_cols(scal, ap, r, n, K, -1.0, st));
-      CHECK_ERR(chol_solve(ctx, F->U.as<double>(), n, r, z, K));
+      CHECK_HIP(launch_dot_cols(out, V, n, K, dots, dwork, st));
+      CHECK_HIP(launch_dot_cols(out, r, n, K, dots + K, dwork, st));
+      CHECK_ERR(host_cols(ctx, dots, 2 * K, tmp));
+      int n_active = 0;
+      for (int k = 0; k < K; ++k) {
+        improved[k] = 0.0;
+        if (active[k] == 0.0) continue;
+        const double phi = -0.5 * (tmp[k] + tmp[K + k]);
+        if (phi <= phibest[k]) {
+          phibest[k] = phi;
+          improved[k] = 1.0;
+        } else if (phi > phibest[k] + 1e-12 * std::fabs(phibest[k])) {
+          active[k] = 0.0;
+        }
+        if (active[k] > 0.0) ++n_active;
+      }
+      CHECK_ERR(to_dev_cols(ctx, improved, mask));
+      CHECK_HIP(launch_select_cols(out, xbest, n, K, mask, st));
+      if (worst <= F->refine_tol || n_active == 0 || it + 1 == F->max_refine) break;
+      CHECK_ERR(chol_solve(ctx, F->Xinv.as<double>(), n, r, z, K));
       CHECK_HIP(launch_dot_cols(r, z, n, K, dots, dwork, st));
       CHECK_ERR(host_cols(ctx, dots, K, tmp2));
       for (int k = 0; k < K; ++k) {
@@ -884,6 +1097,7 @@ flsq_status flsq_factor_solve_normal(flsq_ctx* ctx, const flsq_factor* F, const 
       CHECK_ERR(to_dev_cols(ctx, beta, scal));
       CHECK_HIP(launch_xpby_cols(z, scal, p, n, K, st));
     }
+    CHECK_HIP(hipMemcpyAsync(out, xbest, sizeof(double) * n * K, hipMemcpyDeviceToDevice, st));
     return ok();
   };
   e = body();
@@ -967,6 +1181,275 @@ flsq_status flsq_evaluate(flsq_ctx* ctx, const flsq_basis* basis, const double* 
   if (he == hipSuccess) he = launch_evaluate(a, ctx->stream);
   if (he == hipSuccess) he = hipStreamSynchronize(ctx->stream);
   if (he != hipSuccess) return finish(ctx, fail(FLSQ_EHIP, "evaluate: %s", hipGetErrorString(he)));
+  return finish(ctx, ok());
+}
+
+}  // extern "C"
+
+// =====================================================================================
+// Newton-Raphson (Section 2.4)
+// =====================================================================================
+namespace {
+
+Err newton_impl(flsq_ctx* c, const flsq_basis* basis, const flsq_rows* blocks, int n_blocks, int nl_block,
+                const flsq_nonlin* nl, const flsq_newton_opts* o, double* beta, flsq_newton_trace* tr,
+                bool* converged) {
+  if (!nl || nl->n_poly < 1 || nl->n_poly > 16 || !nl->poly) return fail(FLSQ_EINVAL, "nonlinearity: n_poly in [1, 16]");
+  if (!o) return fail(FLSQ_EINVAL, "opts is NULL");
+  if (o->max_iter < 0 || o->max_iter > 64) return fail(FLSQ_EINVAL, "max_iter outside [0, 64]");
+  if (o->max_halvings < 0 || o->max_halvings > 60) return fail(FLSQ_EINVAL, "max_halvings outside [0, 60]");
+  if (!(o->armijo_c >= 0.0 && o->armijo_c < 1.0)) return fail(FLSQ_EINVAL, "armijo_c outside [0, 1)");
+  if (!beta) return fail(FLSQ_EINVAL, "beta_inout is NULL");
+  SolveParams sp = params_of(&o->lin);
+  CHECK_ERR(check_params(sp));
+  System& s = c->sys;
+  CHECK_ERR(build_system(c, s, basis, blocks, n_blocks, true));
+  if (nl_block < 0 || nl_block >= n_blocks) return fail(FLSQ_EINVAL, "nonlin_block %d outside [0, %d)", nl_block, n_blocks);
+  if (!s.even[nl_block])
+    return fail(FLSQ_EINVAL, "the nonlinear block's operator must have even-order terms only");
+  for (int k = 0; k < nl->n_poly; ++k)
+    if (!std::isfinite(nl->poly[k])) return fail(FLSQ_ENONFINITE, "nonlinearity coefficient not finite");
+  const int n = s.n;
+  const int64_t P = s.P;
+  hipStream_t st = c->stream;
+  double *poly, *R, *Rt, *rho, *rhot, *u, *ut, *delta, *bt, *negR, *dots, *dwork;
+  CHECK_ERR(ws_get(c, "nt_poly", 16, &poly));
+  CHECK_ERR(ws_get(c, "nt_R", (size_t)P, &R));
+  CHECK_ERR(ws_get(c, "nt_Rt", (size_t)P, &Rt));
+  CHECK_ERR(ws_get(c, "nt_rho", (size_t)P, &rho));
+  CHECK_ERR(ws_get(c, "nt_rhot", (size_t)P, &rhot));
+  CHECK_ERR(ws_get(c, "nt_u", (size_t)P, &u));
+  CHECK_ERR(ws_get(c, "nt_ut", (size_t)P, &ut));
+  CHECK_ERR(ws_get(c, "nt_delta", (size_t)n, &delta));
+  CHECK_ERR(ws_get(c, "nt_bt", (size_t)n, &bt));
+  CHECK_ERR(ws_get(c, "nt_negR", (size_t)P, &negR));
+  CHECK_ERR(ws_get(c, "nt_dots", 8, &dots));
+  CHECK_ERR(ws_get(c, "nt_dwork", 1024, &dwork));
+  CHECK_HIP(hipMemcpyAsync(poly, nl->poly, sizeof(double) * nl->n_poly, hipMemcpyHostToDevice, st));
+  const double w_nl = s.weight[nl_block];
+  const int64_t nl0 = s.row0[nl_block], nln = s.rows[nl_block];
+  const PassGeo pg = s.pass();
+  auto residual = [&](const double* b, double* Rout, double* rho_out, double* u_out, double* nrm) -> Err {
+    CHECK_HIP(launch_newton_residual_runs(pg, b, s.rhs_w.as<double>(), nl_block, poly, nl->n_poly, w_nl, s.norm, Rout,
+                                          rho_out, u_out, st));
+    CHECK_HIP(launch_dot_cols(Rout, Rout, P, 1, dots, dwork, st));
+    double h = 0.0;
+    CHECK_HIP(hipMemcpyAsync(&h, dots, sizeof(double), hipMemcpyDeviceToHost, st));
+    CHECK_HIP(hipStreamSynchronize(st));
+    *nrm = std::sqrt(h);
+    if (!std::isfinite(*nrm)) return fail(FLSQ_ENONFINITE, "Newton residual is not finite");
+    return ok();
+  };
+  auto dot1 = [&](const double* x, const double* y, int64_t len, double* out) -> Err {
+    CHECK_HIP(launch_dot_cols(x, y, len, 1, dots, dwork, st));
+    CHECK_HIP(hipMemcpyAsync(out, dots, sizeof(double), hipMemcpyDeviceToHost, st));
+    CHECK_HIP(hipStreamSynchronize(st));
+    return ok();
+  };
+  const double t0 = now_ms();
+  // The Gram changes little between steps, so a shift that made the factor positive
+  // definite is kept as the starting shift of the next factorisation (no repeated retries).
+  SolveParams spk = sp;
+  flsq_solve_info sinfo;
+  if (o->warm_start) {
+    // linear part only: the nonlinearity dropped, rho = 0
+    CHECK_ERR(solve_on_system(c, s, nullptr, spk, s.rhs_w.as<double>(), 1, beta, &sinfo, nullptr));
+    spk.shift_rel = std::max(spk.shift_rel, sinfo.shift);
+  }
+  if (tr) memset(tr, 0, sizeof *tr);
+  *converged = false;
+  double nR = 0.0;
+  CHECK_ERR(residual(beta, R, rho, u, &nR));
+  std::vector<double> one(1, 1.0);
+  double* scal;
+  CHECK_ERR(ws_get(c, "nt_scal", 1, &scal));
+  for (int it = 0; it < o->max_iter; ++it) {
+    // delta = argmin ||J delta + R||^2 + mu ||delta||^2 with J = A(rho)
+    CHECK_HIP(launch_scale_copy(R, negR, P, -1.0, st));
+    CHECK_ERR(solve_on_system(c, s, rho, spk, negR, 1, delta, &sinfo, nullptr));
+    spk.shift_rel = std::max(spk.shift_rel, sinfo.shift);
+    double alpha = 1.0, nRt = 0.0;
+    int halv = 0;
+    for (;;) {
+      CHECK_HIP(hipMemcpyAsync(bt, beta, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+      one[0] = alpha;
+      CHECK_ERR(to_dev_cols(c, one, scal));
+      CHECK_HIP(launch_axpy_cols(scal, delta, bt, n, 1, 1.0, st));
+      CHECK_ERR(residual(bt, Rt, rhot, ut, &nRt));
+      if (nRt <= (1.0 - o->armijo_c * alpha) * nR || halv >= o->max_halvings) break;
+      alpha *= 0.5;
+      ++halv;
+    }
+    double dd = 0.0, du2 = 0.0, un2 = 0.0;
+    CHECK_ERR(dot1(delta, delta, n, &dd));
+    const double step = alpha * std::sqrt(dd);
+    // ||Delta u|| / ||u|| on the rows of the nonlinear block
+    CHECK_HIP(hipMemcpyAsync(negR, ut + nl0, sizeof(double) * nln, hipMemcpyDeviceToDevice, st));
+    one[0] = 1.0;
+    CHECK_ERR(to_dev_cols(c, one, scal));
+    CHECK_HIP(launch_axpy_cols(scal, u + nl0, negR, nln, 1, -1.0, st));
+    CHECK_ERR(dot1(negR, negR, nln, &du2));
+    CHECK_ERR(dot1(ut + nl0, ut + nl0, nln, &un2));
+    if (tr) {
+      tr->res_norm[it] = nR;
+      tr->alpha[it] = alpha;
+      tr->halvings[it] = halv;
+      tr->step_norm[it] = step;
+      tr->du_rel[it] = std::sqrt(du2) / std::max(std::sqrt(un2), 1e-300);
+      tr->iters = it + 1;
+    }
+    CHECK_HIP(hipMemcpyAsync(beta, bt, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+    std::swap(R, Rt);
+    std::swap(rho, rhot);
+    std::swap(u, ut);
+    nR = nRt;
+    if (step < o->tol_dbeta) {
+      *converged = true;
+      break;
+    }
+  }
+  CHECK_HIP(hipStreamSynchronize(st));
+  if (tr) {
+    tr->converged = *converged ? 1 : 0;
+    tr->t_total_ms = now_ms() - t0;
+  }
+  return check_finite_dev(c, beta, n, "beta");
+}
+
+// Derived geometry on the rows of a factor: same features, another operator / row set.
+Err build_rows_on(flsq_ctx* c, System& out, const System& base, const double* x_rowmajor, int64_t rows,
+                  const flsq_term* terms, int n_terms, double weight) {
+  flsq_basis bs;
+  bs.d = base.d;
+  bs.n_feat = base.n;
+  bs.W = base.Wrm.as<double>();
+  bs.b = base.bvec.as<double>();
+  bs.normalize = base.normalize;
+  flsq_rows r;
+  r.n_rows = rows;
+  r.x = x_rowmajor;
+  r.op.terms = terms;
+  r.op.n_terms = n_terms;
+  r.weight = weight;
+  r.rhs = nullptr;
+  return build_system(c, out, &bs, &r, 1, false);
+}
+
+Err inverse_impl(flsq_ctx* c, flsq_factor* F, int64_t n_src, double src_weight, int n_lap, const double* thetas, int K,
+                 int64_t n_obs, const double* x_obs, const double* data, double* loss, double* gtheta,
+                 double* gkappa) {
+  const System& s = F->sys;
+  if (K < 1 || K > 64) return fail(FLSQ_EINVAL, "K = %d outside [1, 64]", K);
+  if (n_src < 1 || n_src > s.P) return fail(FLSQ_EINVAL, "n_src_rows outside [1, P]");
+  if (s.d < 2) return fail(FLSQ_EINVAL, "the source needs two spatial coordinates");
+  if (n_lap < 0 || n_lap > s.d) return fail(FLSQ_EINVAL, "n_lap_dims outside [0, d]");
+  if (n_obs < 1 || !x_obs || !data || !thetas || !loss || !gtheta) return fail(FLSQ_EINVAL, "NULL argument");
+  hipStream_t st = c->stream;
+  const int n = s.n;
+  const int64_t P = s.P;
+  // observation rows H (identity operator) and the interior dA/dkappa rows, cached on the factor
+  flsq_term ident;
+  memset(&ident, 0, sizeof ident);
+  ident.coef = 1.0;
+  if (F->obs_key != (const void*)x_obs || F->obs_n != n_obs) {
+    CHECK_ERR(build_rows_on(c, F->obs, s, x_obs, n_obs, &ident, 1, 1.0));
+    F->obs_key = x_obs;
+    F->obs_n = n_obs;
+  }
+  if (gkappa && (F->akap_rows != n_src || F->akap_dims != n_lap || F->akap_weight != src_weight)) {
+    // interior operator d/dt - kappa sum_k D^{2 e_k}: dA/dkappa = -sum_{k < n_lap} D^{2 e_k}
+    flsq_term t[FLSQ_MAX_DIM];
+    memset(t, 0, sizeof t);
+    for (int k = 0; k < n_lap; ++k) {
+      t[k].coef = -1.0;
+      t[k].alpha[k] = 2;
+    }
+    if (n_lap == 0) return fail(FLSQ_EINVAL, "kappa gradient needs n_lap_dims >= 1");
+    CHECK_ERR(build_rows_on(c, F->akap, s, s.Xrm.as<double>(), n_src, t, n_lap, src_weight));
+    F->akap_rows = n_src;
+    F->akap_dims = n_lap;
+    F->akap_weight = src_weight;
+  }
+  double *Rhs, *B, *U, *gu, *Vn, *Lam, *AL, *gwork, *colwork;
+  CHECK_ERR(ws_get(c, "inv_rhs", (size_t)P * K, &Rhs));
+  CHECK_ERR(ws_get(c, "inv_B", (size_t)n * K, &B));
+  CHECK_ERR(ws_get(c, "inv_U", (size_t)n_obs * K, &U));
+  CHECK_ERR(ws_get(c, "inv_gu", (size_t)n_obs * K, &gu));
+  CHECK_ERR(ws_get(c, "inv_V", (size_t)n * K, &Vn));
+  CHECK_ERR(ws_get(c, "inv_lam", (size_t)n * K, &Lam));
+  CHECK_ERR(ws_get(c, "inv_AL", (size_t)P * K, &AL));
+  CHECK_ERR(ws_get(c, "inv_gwork", (size_t)K * 64 * 4 + 64, &gwork));
+  CHECK_ERR(ws_get(c, "inv_colwork", pass_work_elems(n, F->obs.n_runs, K) + 64, &colwork));
+  // forward: B = (A^T A + mu I)^{-1} A^T rhs(theta), U = H B, misfit
+  CHECK_HIP(launch_source(s.Xt.as<double>(), P, n_src, src_weight, thetas, K, Rhs, st));
+  flsq_status fs = flsq_factor_solve(c, F, Rhs, K, B, nullptr);
+  if (fs != FLSQ_OK) return Err{fs, c->err};
+  CHECK_HIP(launch_rowpass_runs(F->obs.pass(), nullptr, B, K, nullptr, 1.0, 0.0, U, st));
+  CHECK_HIP(launch_misfit(U, data, n_obs, K, loss, gu, st));
+  // backward: Lam = (A^T A + mu I)^{-1} H^T gu ; AL = A Lam ; dL/dtheta = AL^T d rhs / d theta
+  CHECK_HIP(launch_colpass_runs(F->obs.pass(), nullptr, gu, K, nullptr, 1.0, 0.0, Vn, colwork, st));
+  fs = flsq_factor_solve_normal(c, F, Vn, K, Lam);
+  if (fs != FLSQ_OK) return Err{fs, c->err};
+  CHECK_HIP(launch_rowpass_runs(s.pass(), nullptr, Lam, K, nullptr, 1.0, 0.0, AL, st));
+  CHECK_HIP(launch_source_grad_dot(s.Xt.as<double>(), P, n_src, src_weight, thetas, K, AL, gtheta, gwork, st));
+  if (gkappa) {
+    // dL/dkappa = (A_k Lam)^T (rhs - A B) - (A Lam)^T (A_k B), A_k nonzero on the interior rows only
+    double *r, *AkL, *AkB, *dots, *dwork;
+    CHECK_ERR(ws_get(c, "inv_r", (size_t)P * K, &r));
+    CHECK_ERR(ws_get(c, "inv_AkL", (size_t)n_src * K, &AkL));
+    CHECK_ERR(ws_get(c, "inv_AkB", (size_t)n_src * K, &AkB));
+    CHECK_ERR(ws_get(c, "inv_dots", (size_t)2 * K, &dots));
+    CHECK_ERR(ws_get(c, "inv_dwork", (size_t)512 * K + 64, &dwork));
+    CHECK_HIP(launch_rowpass_runs(s.pass(), nullptr, B, K, Rhs, -1.0, 1.0, r, st));
+    CHECK_HIP(launch_rowpass_runs(F->akap.pass(), nullptr, Lam, K, nullptr, 1.0, 0.0, AkL, st));
+    CHECK_HIP(launch_rowpass_runs(F->akap.pass(), nullptr, B, K, nullptr, 1.0, 0.0, AkB, st));
+    CHECK_HIP(launch_dot_cols(AkL, r, n_src, K, dots, dwork, st));
+    CHECK_HIP(launch_dot_cols(AL, AkB, n_src, K, dots + K, dwork, st));
+    CHECK_HIP(launch_combine_diff(dots, dots + K, gkappa, K, st));
+  }
+  CHECK_HIP(hipStreamSynchronize(st));
+  return ok();
+}
+
+}  // namespace
+
+extern "C" {
+
+flsq_status flsq_solve_newton(flsq_ctx* ctx, const flsq_basis* basis, const flsq_rows* blocks, int32_t n_blocks,
+                              int32_t nonlin_block, const flsq_nonlin* nonlin, const flsq_newton_opts* opts,
+                              double* beta_inout, flsq_newton_trace* trace) {
+  if (!ctx) return FLSQ_EINVAL;
+  if (hipSetDevice(ctx->device) != hipSuccess) return finish(ctx, fail(FLSQ_EHIP, "hipSetDevice failed"));
+  bool conv = false;
+  Err e = newton_impl(ctx, basis, blocks, n_blocks, nonlin_block, nonlin, opts, beta_inout, trace, &conv);
+  if (e.st != FLSQ_OK) return finish(ctx, e);
+  if (!conv && opts->tol_dbeta > 0.0)
+    return finish(ctx, fail(FLSQ_ENOCONV, "Newton: ||alpha delta|| did not fall below tol_dbeta in %d steps",
+                            opts->max_iter));
+  return finish(ctx, ok());
+}
+
+flsq_status flsq_inverse_loss_grad(flsq_ctx* ctx, const flsq_factor* F, int64_t n_src_rows, double src_weight,
+                                   int32_t n_lap_dims, const double* thetas, int32_t K, int64_t n_obs,
+                                   const double* x_obs, const double* data, double* loss_out,
+                                   double* grad_theta_out, double* grad_kappa_out) {
+  if (!ctx || !F) return FLSQ_EINVAL;
+  if (hipSetDevice(ctx->device) != hipSuccess) return finish(ctx, fail(FLSQ_EHIP, "hipSetDevice failed"));
+  Err e = inverse_impl(ctx, const_cast<flsq_factor*>(F), n_src_rows, src_weight, n_lap_dims, thetas, K, n_obs, x_obs,
+                       data, loss_out, grad_theta_out, grad_kappa_out);
+  return finish(ctx, e);
+}
+
+flsq_status flsq_adam_step(flsq_ctx* ctx, double* params, const double* grads, double* m, double* v, int32_t K,
+                           int32_t P, int32_t t, double lr, double b1, double b2, double eps, int32_t clamp_col,
+                           double clamp_min) {
+  if (!ctx) return FLSQ_EINVAL;
+  if (hipSetDevice(ctx->device) != hipSuccess) return finish(ctx, fail(FLSQ_EHIP, "hipSetDevice failed"));
+  if (!params || !grads || !m || !v) return finish(ctx, fail(FLSQ_EINVAL, "NULL argument"));
+  if (K < 1 || P < 1 || t < 1) return finish(ctx, fail(FLSQ_EINVAL, "K, P and t must be >= 1"));
+  if (clamp_col >= P) return finish(ctx, fail(FLSQ_EINVAL, "clamp_col >= P"));
+  hipError_t he = launch_adam(params, grads, m, v, K, P, t, lr, b1, b2, eps, clamp_col, clamp_min, ctx->stream);
+  if (he != hipSuccess) return finish(ctx, fail(FLSQ_EHIP, "adam: %s", hipGetErrorString(he)));
   return finish(ctx, ok());
 }
 

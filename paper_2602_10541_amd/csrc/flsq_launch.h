@@ -70,12 +70,15 @@ struct PassGeo {
   Geo g;
   const Chunk* runs;   // block-aligned runs of at most pass_rows() rows
   int n_runs;
+  uint64_t even_mask;  // bit g set when block g's operator has only even-order terms (phase = b)
+  double norm;         // 1/sqrt(N) or 1
 };
 int pass_rows();
 size_t pass_work_elems(int n, int n_runs, int K);
-// out[i][c] = beta_y * Y[i][c] + alpha * sum_j A_ij V[j][c]   (Y nullable)
+// out[i][c] = beta_y * Y[i][c] + alpha * sum_j A_ij V[j][c]   (Y nullable).  With u_out
+// (K <= 16) also u_out[i][c] = norm sum_j V[j][c] phi_j(x_i) on even blocks, 0 elsewhere.
 hipError_t launch_rowpass_runs(const PassGeo& pg, const double* rho, const double* V, int K, const double* Y,
-                               double alpha, double beta_y, double* out, hipStream_t s);
+                               double alpha, double beta_y, double* out, hipStream_t s, double* u_out = nullptr);
 // out[j][c] = beta_v * V[j][c] + alpha * sum_i A_ij Y[i][c]   (V nullable)
 hipError_t launch_colpass_runs(const PassGeo& pg, const double* rho, const double* Y, int K, const double* V,
                                double alpha, double beta_v, double* out, double* work, hipStream_t s);
@@ -86,13 +89,30 @@ hipError_t launch_newton_residual_runs(const PassGeo& pg, const double* beta, co
 
 // ---- dense FP64 linear algebra on the upper Cholesky factor (row-major, G = U^T U)
 constexpr int kNb = 64;
-hipError_t launch_potrf_diag(double* G, int n, int k0, int* info, double shift, hipStream_t s);
-hipError_t launch_trsm_row(double* G, int n, int k0, hipStream_t s);
+// Factor the diagonal block at k0 in place and write its inverse into X.
+hipError_t launch_potrf_diag(double* G, int n, int k0, int* info, double* X, hipStream_t s);
 hipError_t launch_syrk(double* G, int n, int k0, hipStream_t s);
-// Solves with the factor (Y n x K row-major is consumed as scratch, the solution goes to X):
-// U^T X = Y (forward) and U X = Y (backward).
-hipError_t launch_trsv_fwd(const double* U, int n, double* Y, double* X, int K, hipStream_t s);
-hipError_t launch_trsv_bwd(const double* U, int n, double* Y, double* X, int K, hipStream_t s);
+// U_kj = U_kk^{-T} G_kj by forward substitution, in place (block row k0).
+hipError_t launch_trsm_row(double* G, int n, int k0, hipStream_t s);
+// dst = D src D + (diag_add + mu D^2) on the diagonal (upper triangle), D = diag(src)^{-1/2} -> d.
+hipError_t launch_equilibrate(const double* G, double* dst, int n, double* d, double mu, double diag_add,
+                              hipStream_t s);
+// X <- diag(d) X
+hipError_t launch_scale_rows(double* X, int n, const double* d, hipStream_t s);
+// C = alpha op(A) B + beta C per descriptor (op(A) = A^T when transA); descriptors in device memory.
+struct GemmDesc {
+  const double* A;
+  const double* B;
+  double* C;
+  int M, N, K;
+  int lda, ldb, ldc;
+};
+hipError_t launch_gemm_batched(const GemmDesc* d_descs, int n_batch, int maxM, int maxN, double alpha, double beta,
+                               int transA, hipStream_t s);
+// out = X (X^T v) for upper-triangular X (n x n); tmp n, work precond_work_elems(n).
+hipError_t launch_precond_apply(const double* X, int n, const double* v, double* tmp, double* work, double* out,
+                                hipStream_t s);
+size_t precond_work_elems(int n);
 hipError_t launch_copy_upper(const double* src, double* dst, int n, double diag_add, hipStream_t s);
 hipError_t launch_diag_max(const double* G, int n, double* out, hipStream_t s);
 
@@ -106,6 +126,8 @@ hipError_t launch_axpy_cols(const double* a, const double* x, double* y, int64_t
 // p[i][c] = z[i][c] + b[c] * p[i][c]
 hipError_t launch_xpby_cols(const double* z, const double* b, double* p, int64_t n, int K, hipStream_t s);
 hipError_t launch_count_nonfinite(const double* x, int64_t n, int* flag, hipStream_t s);
+// dst[i][c] = src[i][c] for the columns c with mask[c] != 0
+hipError_t launch_select_cols(const double* src, double* dst, int64_t n, int K, const double* mask, hipStream_t s);
 
 
 // ---- inverse heat-source support
@@ -113,6 +135,7 @@ hipError_t launch_source(const double* Xt, int64_t P, int64_t n_src, double weig
                          double* Rhs, hipStream_t s);
 hipError_t launch_source_grad_dot(const double* Xt, int64_t P, int64_t n_src, double weight, const double* thetas,
                                   int K, const double* AL, double* grad, double* work, hipStream_t s);
+hipError_t launch_combine_diff(const double* a, const double* b, double* out, int K, hipStream_t s);
 hipError_t launch_misfit(const double* U, const double* data, int64_t n_obs, int K, double* loss, double* gu,
                          hipStream_t s);
 hipError_t launch_adam(double* p, const double* g, double* m, double* v, int K, int P, int t, double lr, double b1,

@@ -1,0 +1,143 @@
+// Dense FP64 building blocks on gfx950 MFMA: a descriptor-batched GEMM, the explicit
+// inverse of the upper Cholesky factor, and the triangular matrix-vector products that
+// apply the preconditioner M^{-1} = U^{-1} U^{-T} = X X^T.
+//
+// With X = U^{-1} formed once per factorisation, every preconditioner application in the
+// refinement is two bandwidth-bound passes over the triangle of X instead of 2 N / 64
+// dependent block steps.
+#include "flsq_device.h"
+#include "flsq_launch.h"
+
+namespace flsq {
+
+constexpr int kGT = 64;       // output tile (kGT x kGT) per workgroup
+constexpr int kGK = 16;       // K slab staged in LDS
+
+// C[M x N] = alpha * op(A)[M x K] * B[K x N] + beta * C, all row-major with leading
+// dimensions; op(A) = A (lda >= K) or A^T (A stored K x M, lda >= M).
+// Four waves in 2 x 2, each a 32 x 32 quarter as 2 x 2 blocks of v_mfma_f64_16x16x4f64.
+__global__ __launch_bounds__(256) void k_gemm_batched(const GemmDesc* __restrict__ descs, double alpha, double beta,
+                                                      int transA) {
+  __shared__ double sA[kGK][kGT + 1];   // sA[k][m]
+  __shared__ double sB[kGK][kGT + 1];   // sB[k][n]
+  const GemmDesc D = descs[blockIdx.z];
+  const int m0 = blockIdx.y * kGT, n0 = blockIdx.x * kGT;
+  if (m0 >= D.M || n0 >= D.N) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  f64x4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < D.K; k0 += kGK) {
+    __syncthreads();
+    for (int e = tid; e < kGK * kGT; e += 256) {
+      int k, m;
+      if (transA) {        // A stored K x M: read rows of A (coalesced along m)
+        k = e / kGT;
+        m = e % kGT;
+      } else {             // A stored M x K: read rows of A (coalesced along k)
+        m = e / kGK;
+        k = e % kGK;
+      }
+      const int gk = k0 + k, gm = m0 + m;
+      double v = 0.0;
+      if (gk < D.K && gm < D.M) v = transA ? D.A[(int64_t)gk * D.lda + gm] : D.A[(int64_t)gm * D.lda + gk];
+      sA[k][m] = v;
+      const int kb = e / kGT, nb = e % kGT;
+      const int gkb = k0 + kb, gn = n0 + nb;
+      sB[kb][nb] = (gkb < D.K && gn < D.N) ? D.B[(int64_t)gkb * D.ldb + gn] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < kGK / 4; ++kk) {
+      const int k = kk * 4 + (lane >> 4);
+      double av[2], bv[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) av[a] = sA[k][wm * 32 + a * 16 + (lane & 15)];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) bv[b] = sB[k][wn * 32 + b * 16 + (lane & 15)];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int gm = m0 + wm * 32 + a * 16 + 4 * v + (lane >> 4);
+        const int gn = n0 + wn * 32 + b * 16 + (lane & 15);
+        if (gm < D.M && gn < D.N) {
+          double* c = D.C + (int64_t)gm * D.ldc + gn;
+          *c = (beta == 0.0) ? alpha * acc[a][b][v] : fma(alpha, acc[a][b][v], beta * *c);
+        }
+      }
+}
+
+hipError_t launch_gemm_batched(const GemmDesc* d_descs, int n_batch, int maxM, int maxN, double alpha, double beta,
+                               int transA, hipStream_t s) {
+  if (n_batch == 0 || maxM == 0 || maxN == 0) return hipSuccess;
+  dim3 grid((maxN + kGT - 1) / kGT, (maxM + kGT - 1) / kGT, n_batch);
+  hipLaunchKernelGGL(k_gemm_batched, grid, dim3(256), 0, s, d_descs, alpha, beta, transA);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ preconditioner application
+// y = X^T v  (X upper triangular, n x n row-major): y_j = sum_{i <= j} X[i][j] v_i.
+// Grid (column tiles, row splits): each thread owns a column, loops over its row range;
+// partial sums go to work[split][j], reduced in order by k_sum_splits.
+constexpr int kTvSplits = 32;
+
+__global__ __launch_bounds__(256) void k_trmv_t(const double* __restrict__ X, int n, const double* __restrict__ v,
+                                                double* __restrict__ work) {
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  const int split = blockIdx.y;
+  const int per = (n + kTvSplits - 1) / kTvSplits;
+  const int i0 = split * per;
+  const int i1 = min(n, i0 + per);
+  double s = 0.0;
+  if (j < n) {
+    const int iend = min(i1, j + 1);
+    for (int i = i0; i < iend; ++i) s = fma(X[(int64_t)i * n + j], v[i], s);
+    work[(int64_t)split * n + j] = s;
+  }
+}
+
+__global__ void k_sum_splits(const double* __restrict__ work, int n, int splits, double* __restrict__ out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  double s = 0.0;
+  for (int sp = 0; sp < splits; ++sp) s += work[(int64_t)sp * n + j];
+  out[j] = s;
+}
+
+// z = X y: z_i = sum_{j >= i} X[i][j] y_j; one wave per row, lanes stride the row.
+__global__ __launch_bounds__(256) void k_trmv_n(const double* __restrict__ X, int n, const double* __restrict__ y,
+                                                double* __restrict__ z) {
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= n) return;
+  const double* row = X + (int64_t)i * n;
+  double s = 0.0;
+  for (int j = i + lane; j < n; j += 64) s = fma(row[j], y[j], s);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off);
+  if (lane == 0) z[i] = s;
+}
+
+hipError_t launch_precond_apply(const double* X, int n, const double* v, double* tmp, double* work, double* out,
+                                hipStream_t s) {
+  hipLaunchKernelGGL(k_trmv_t, dim3((n + 255) / 256, kTvSplits), dim3(256), 0, s, X, n, v, work);
+  hipLaunchKernelGGL(k_sum_splits, dim3((n + 255) / 256), dim3(256), 0, s, work, n, kTvSplits, tmp);
+  hipLaunchKernelGGL(k_trmv_n, dim3((n + 3) / 4), dim3(256), 0, s, X, n, tmp, out);
+  return hipGetLastError();
+}
+
+size_t precond_work_elems(int n) { return (size_t)kTvSplits * n; }
+
+}  // namespace flsq

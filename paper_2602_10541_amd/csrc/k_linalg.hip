@@ -3,87 +3,15 @@
 // G is stored row-major and only its upper triangle is used.  The factor is upper
 // triangular, G = U^T U, computed in place by a blocked right-looking Cholesky with
 // block size kNb = 64:
-//   1. factor the diagonal block              (one workgroup, in LDS)
-//   2. block row: U_kj = U_kk^{-T} G_kj       (one thread per column; coalesced rows)
-//   3. trailing update G_ij -= U_ki^T U_kj     (FP64 MFMA 16x16x4, 64 x 64 tiles, i <= j)
-// Triangular solves run one block step per launch; every workgroup solves the small
-// diagonal system redundantly in a wave (no inter-workgroup communication) and updates
-// its share of the remaining right-hand side.
+//   1. factor the diagonal block and invert it  (one workgroup, in LDS)
+//   2. block row: U_kj = U_kk^{-T} G_kj = X_kk^T G_kj   (batched MFMA GEMM, k_dense.hip)
+//   3. trailing update G_ij -= U_ki^T U_kj       (FP64 MFMA 16x16x4, 64 x 64 tiles, i <= j)
+// The off-diagonal blocks of X = U^{-1} are assembled afterwards level by level
+// (X_12 = -X_11 U_12 X_22) with the same GEMM.
 #include "flsq_device.h"
 #include "flsq_launch.h"
 
 namespace flsq {
-
-// ------------------------------------------------------------------ Cholesky
-__global__ __launch_bounds__(256) void k_potrf_diag(double* G, int n, int k0, int* info) {
-  __shared__ double a[kNb][kNb + 1];
-  const int nbk = min(kNb, n - k0);
-  const int tid = threadIdx.x;
-  for (int e = tid; e < nbk * nbk; e += 256) {
-    const int i = e / nbk, j = e % nbk;
-    a[i][j] = (j >= i) ? G[(int64_t)(k0 + i) * n + k0 + j] : 0.0;
-  }
-  __syncthreads();
-  for (int l = 0; l < nbk; ++l) {
-    double piv = a[l][l];
-    if (!(piv > 0.0) || !isfinite(piv)) {   // not positive definite (or NaN): record, keep going
-      if (tid == 0 && *info == 0) *info = k0 + l + 1;
-      piv = 1.0;
-    }
-    const double dl = sqrt(piv);
-    __syncthreads();
-    if (tid == 0) a[l][l] = dl;
-    for (int j = l + 1 + tid; j < nbk; j += 256) a[l][j] /= dl;
-    __syncthreads();
-    const int cnt = nbk - l - 1;
-    for (int e = tid; e < cnt * cnt; e += 256) {
-      const int i = l + 1 + e / cnt, j = l + 1 + e % cnt;
-      if (j >= i) a[i][j] -= a[l][i] * a[l][j];
-    }
-    __syncthreads();
-  }
-  for (int e = tid; e < nbk * nbk; e += 256) {
-    const int i = e / nbk, j = e % nbk;
-    if (j >= i) G[(int64_t)(k0 + i) * n + k0 + j] = a[i][j];
-  }
-}
-
-hipError_t launch_potrf_diag(double* G, int n, int k0, int* info, double shift, hipStream_t s) {
-  (void)shift;
-  hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(256), 0, s, G, n, k0, info);
-  return hipGetLastError();
-}
-
-// Block row: for each column j >= k0 + kNb solve U_kk^T y = g (forward substitution).
-__global__ __launch_bounds__(256) void k_trsm_row(double* G, int n, int k0) {
-  __shared__ double u[kNb][kNb + 1];
-  const int tid = threadIdx.x;
-  for (int e = tid; e < kNb * kNb; e += 256) {
-    const int i = e / kNb, j = e % kNb;
-    u[i][j] = (j >= i) ? G[(int64_t)(k0 + i) * n + k0 + j] : 0.0;
-  }
-  __syncthreads();
-  const int j = k0 + kNb + blockIdx.x * 256 + tid;
-  if (j >= n) return;
-  double y[kNb];
-#pragma unroll
-  for (int l = 0; l < kNb; ++l) y[l] = G[(int64_t)(k0 + l) * n + j];
-#pragma unroll
-  for (int l = 0; l < kNb; ++l) {
-    y[l] /= u[l][l];
-#pragma unroll
-    for (int m = l + 1; m < kNb; ++m) y[m] = fma(-u[l][m], y[l], y[m]);
-  }
-#pragma unroll
-  for (int l = 0; l < kNb; ++l) G[(int64_t)(k0 + l) * n + j] = y[l];
-}
-
-hipError_t launch_trsm_row(double* G, int n, int k0, hipStream_t s) {
-  const int cols = n - k0 - kNb;
-  if (cols <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_trsm_row, dim3((cols + 255) / 256), dim3(256), 0, s, G, n, k0);
-  return hipGetLastError();
-}
 
 __device__ __forceinline__ void tri_coords(int t, int nt, int* ti, int* tj) {
   int r = 0, rowlen = nt;
@@ -145,111 +73,75 @@ hipError_t launch_syrk(double* G, int n, int k0, hipStream_t s) {
   return hipGetLastError();
 }
 
-// ------------------------------------------------------------------ triangular solves
-// Diagonal-block solve inside one workgroup: each wave takes right-hand-side columns
-// c = wave, wave + 4, ...; lane m holds entry m of the block.  Result into x[m][c] (LDS).
-template <bool kForward>
-__device__ __forceinline__ void diag_solve(const double (*u)[kNb + 1], int nbk, const double* Y, int n_ld, int k0,
-                                           int K, double (*x)[65]) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int c = wave; c < K; c += 4) {
-    double y = (lane < nbk) ? Y[(int64_t)(k0 + lane) * K + c] : 0.0;
-    if (kForward) {
-      for (int l = 0; l < nbk; ++l) {
-        const double xl = __shfl(y, l) / u[l][l];
-        if (lane == l) y = xl;
-        if (lane > l) y = fma(-u[l][lane], xl, y);
-      }
-    } else {
-      for (int l = nbk - 1; l >= 0; --l) {
-        const double xl = __shfl(y, l) / u[l][l];
-        if (lane == l) y = xl;
-        if (lane < l) y = fma(-u[lane][l], xl, y);
-      }
-    }
-    if (lane < nbk) x[lane][c] = y;
+// Block row: for each column j >= k0 + kNb solve U_kk^T y = g by forward substitution
+// (backward stable, unlike multiplying by the explicit inverse of U_kk).  One column per
+// thread, 64-thread workgroups so the (n - k1) columns spread over many CUs.  The
+// triangle U_kk is read through its own read-only pointer: every address is wave-uniform,
+// so its values arrive in scalar registers in wide batches instead of one LDS round trip
+// per multiply-add.  The kernel writes only columns >= k1 of the block row, never U_kk.
+__global__ __launch_bounds__(64) void k_trsm_row(double* __restrict__ Grow, const double* __restrict__ Ukk, int n,
+                                                 int jend) {
+  const int j = kNb + blockIdx.x * 64 + threadIdx.x;     // column offset from k0
+  if (j >= jend) return;
+  double y[kNb];
+#pragma unroll
+  for (int l = 0; l < kNb; ++l) y[l] = Grow[(int64_t)l * n + j];
+#pragma unroll
+  for (int l = 0; l < kNb; ++l) {
+    y[l] = y[l] / Ukk[(int64_t)l * n + l];
+#pragma unroll
+    for (int m = l + 1; m < kNb; ++m) y[m] = fma(-Ukk[(int64_t)l * n + m], y[l], y[m]);
   }
-  (void)n_ld;
+#pragma unroll
+  for (int l = 0; l < kNb; ++l) Grow[(int64_t)l * n + j] = y[l];
 }
 
-// Forward step k (U^T X = Y): X[k] = U_kk^{-T} Y[k]; Y[j] -= U[k-rows][j]^T X[k] for j >= k1.
-__global__ __launch_bounds__(256) void k_trsv_fwd(const double* U, int n, int k0, double* Y, double* X, int K) {
-  __shared__ double u[kNb][kNb + 1];
-  __shared__ double x[kNb][65];
-  const int nbk = min(kNb, n - k0);
-  const int tid = threadIdx.x;
-  for (int e = tid; e < nbk * nbk; e += 256) {
-    const int i = e / nbk, j = e % nbk;
-    u[i][j] = (j >= i) ? U[(int64_t)(k0 + i) * n + k0 + j] : 0.0;
-  }
-  __syncthreads();
-  diag_solve<true>(u, nbk, Y, n, k0, K, x);
-  __syncthreads();
-  if (blockIdx.x == 0)
-    for (int e = tid; e < nbk * K; e += 256) X[(int64_t)(k0 + e / K) * K + e % K] = x[e / K][e % K];
-  const int j = k0 + nbk + blockIdx.x * 256 + tid;
-  if (j >= n) return;
-  for (int c = 0; c < K; ++c) {
-    double s = 0.0;
-    for (int l = 0; l < nbk; ++l) s = fma(U[(int64_t)(k0 + l) * n + j], x[l][c], s);
-    Y[(int64_t)j * K + c] -= s;
-  }
+hipError_t launch_trsm_row(double* G, int n, int k0, hipStream_t s) {
+  const int cols = n - k0 - kNb;
+  if (cols <= 0) return hipSuccess;
+  double* base = G + (int64_t)k0 * n + k0;
+  // columns are addressed relative to k0; the valid range is j < n - k0
+  hipLaunchKernelGGL(k_trsm_row, dim3((cols + 63) / 64), dim3(64), 0, s, base, (const double*)base, n, n - k0);
+  return hipGetLastError();
 }
 
-// Backward step k (U X = Y): X[k] = U_kk^{-1} Y[k]; Y[i] -= U[i][k-cols] X[k] for i < k0.
-__global__ __launch_bounds__(256) void k_trsv_bwd(const double* U, int n, int k0, double* Y, double* X, int K) {
-  __shared__ double u[kNb][kNb + 1];
-  __shared__ double x[kNb][65];
-  __shared__ double r[64][kNb + 1];
-  const int nbk = min(kNb, n - k0);
-  const int tid = threadIdx.x;
-  for (int e = tid; e < nbk * nbk; e += 256) {
-    const int i = e / nbk, j = e % nbk;
-    u[i][j] = (j >= i) ? U[(int64_t)(k0 + i) * n + k0 + j] : 0.0;
-  }
-  __syncthreads();
-  diag_solve<false>(u, nbk, Y, n, k0, K, x);
-  __syncthreads();
-  if (blockIdx.x == 0)
-    for (int e = tid; e < nbk * K; e += 256) X[(int64_t)(k0 + e / K) * K + e % K] = x[e / K][e % K];
-  // rows i in [64 * (blockIdx.x - 0), ...) below k0: stage U[i][k0 .. k0 + nbk) through LDS
-  const int i0 = blockIdx.x * 64;
-  if (i0 >= k0) return;
-  for (int e = tid; e < 64 * nbk; e += 256) {
-    const int ii = e / nbk, l = e % nbk;
-    r[ii][l] = (i0 + ii < k0) ? U[(int64_t)(i0 + ii) * n + k0 + l] : 0.0;
-  }
-  __syncthreads();
-  const int ii = tid & 63, cg = tid >> 6;
-  if (i0 + ii >= k0) return;
-  for (int c = cg; c < K; c += 4) {
-    double s = 0.0;
-    for (int l = 0; l < nbk; ++l) s = fma(r[ii][l], x[l][c], s);
-    Y[(int64_t)(i0 + ii) * K + c] -= s;
-  }
+// ------------------------------------------------------------------ equilibration
+// d_i = 1 / sqrt(G_ii) (1 where G_ii <= 0); used to scale G to unit diagonal before the
+// factorisation, and the inverse factor back: M^{-1} = (D X)(D X)^T.
+__global__ void k_diag_rsqrt(const double* G, int n, double* d) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double g = G[(int64_t)i * n + i];
+  d[i] = (g > 0.0) ? 1.0 / sqrt(g) : 1.0;
 }
 
-// Full solves with the factor: Y (n x K) is consumed as scratch, the solution goes to X.
-hipError_t launch_trsv_fwd(const double* U, int n, double* Y, double* X, int K, hipStream_t s) {
-  for (int k0 = 0; k0 < n; k0 += kNb) {
-    const int rem = n - k0 - kNb;
-    const int grid = rem > 0 ? (rem + 255) / 256 : 1;
-    hipLaunchKernelGGL(k_trsv_fwd, dim3(grid), dim3(256), 0, s, U, n, k0, Y, X, K);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
+// dst_ij = d_i src_ij d_j on the upper triangle, plus diag_add + mu d_i^2 on the diagonal.
+__global__ void k_scale_upper(const double* src, double* dst, int n, const double* d, double mu, double diag_add) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y;
+  if (j >= n || j < i) return;
+  const int64_t o = (int64_t)i * n + j;
+  double v = d[i] * src[o] * d[j];
+  if (i == j) v += diag_add + mu * d[i] * d[i];
+  dst[o] = v;
 }
 
-hipError_t launch_trsv_bwd(const double* U, int n, double* Y, double* X, int K, hipStream_t s) {
-  const int last = ((n - 1) / kNb) * kNb;
-  for (int k0 = last; k0 >= 0; k0 -= kNb) {
-    const int grid = k0 > 0 ? (k0 + 63) / 64 : 1;
-    hipLaunchKernelGGL(k_trsv_bwd, dim3(grid), dim3(256), 0, s, U, n, k0, Y, X, K);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
+__global__ void k_scale_rows(double* X, int n, const double* d) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y;
+  if (j < n) X[(int64_t)i * n + j] *= d[i];
+}
+
+hipError_t launch_equilibrate(const double* G, double* dst, int n, double* d, double mu, double diag_add,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_diag_rsqrt, dim3((n + 255) / 256), dim3(256), 0, s, G, n, d);
+  hipLaunchKernelGGL(k_scale_upper, dim3((n + 255) / 256, n), dim3(256), 0, s, G, dst, n, d, mu, diag_add);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_rows(double* X, int n, const double* d, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale_rows, dim3((n + 255) / 256, n), dim3(256), 0, s, X, n, d);
+  return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ helpers
@@ -353,6 +245,19 @@ hipError_t launch_xpby_cols(const double* z, const double* b, double* p, int64_t
   const int64_t tot = n * K;
   if (tot == 0) return hipSuccess;
   hipLaunchKernelGGL(k_xpby_cols, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, z, b, p, n, K);
+  return hipGetLastError();
+}
+
+__global__ void k_select_cols(const double* src, double* dst, int64_t n, int K, const double* mask) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * K) return;
+  if (mask[e % K] != 0.0) dst[e] = src[e];
+}
+
+hipError_t launch_select_cols(const double* src, double* dst, int64_t n, int K, const double* mask, hipStream_t s) {
+  const int64_t tot = n * K;
+  if (tot == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_select_cols, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, src, dst, n, K, mask);
   return hipGetLastError();
 }
 

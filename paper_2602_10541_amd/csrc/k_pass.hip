@@ -18,9 +18,12 @@ constexpr int kColFeat = 256;        // features per column-pass workgroup (one 
 
 // ------------------------------------------------------------------ row pass
 // out[i][c] = beta_y * Y[i][c] + alpha * sum_j A_ij V[j][c]
-// NEWTON: additionally u_i = norm * sum_j beta_j sin(W_j.x_i + b_j) on the nonlinear block
-// (whose phase is b), then R_i = (A beta)_i + w N(u_i) - data_i, rho_i = w N'(u_i) norm.
-template <int D, int KMAX, bool NEWTON>
+// MODE 1: also u_out[i][c] = norm * sum_j V[j][c] sin(W_j.x_i + b_j), the expansion itself at
+//         the row, on blocks whose operator is even (their phase is b, so the sine is shared);
+//         zero on other blocks.  This is the solution-level quantity the refinement stops on.
+// MODE 2 (Newton, K = 1): u_i as above on the nonlinear block, then
+//         R_i = (A beta)_i + w N(u_i) - data_i and rho_i = w N'(u_i) norm.
+template <int D, int KMAX, int MODE>
 __global__ __launch_bounds__(256) void k_rowpass(PassGeo pg, const double* __restrict__ rho,
                                                  const double* __restrict__ V, int K, const double* __restrict__ Y,
                                                  double alpha, double beta_y, double* __restrict__ out,
@@ -28,6 +31,8 @@ __global__ __launch_bounds__(256) void k_rowpass(PassGeo pg, const double* __res
                                                  int nonlin_block, const double* __restrict__ poly, int n_poly,
                                                  double norm, double w_nl, double* __restrict__ rho_out,
                                                  double* __restrict__ u_out) {
+  constexpr bool NEWTON = (MODE == 2);
+  constexpr int KU = (MODE == 1) ? KMAX : 1;
   constexpr int RF = (KMAX >= 16) ? 16 : kRowFeat;            // features staged per slice and round
   __shared__ double sW[kRowSlices][RF][D + 2];                // W, amp, ph
   __shared__ double sV[kRowSlices][RF][KMAX];
@@ -46,7 +51,10 @@ __global__ __launch_bounds__(256) void k_rowpass(PassGeo pg, const double* __res
   double acc[KMAX];
 #pragma unroll
   for (int c = 0; c < KMAX; ++c) acc[c] = 0.0;
-  double uacc = 0.0;
+  double uacc[KU];
+#pragma unroll
+  for (int c = 0; c < KU; ++c) uacc[c] = 0.0;
+  const bool ev = (MODE == 1) && ((pg.even_mask >> run.block) & 1ull);
   const bool nl = NEWTON && (run.block == nonlin_block);
   const int per_slice = (n + kRowSlices - 1) / kRowSlices;
   const int j_begin = slice * per_slice;
@@ -72,16 +80,37 @@ __global__ __launch_bounds__(256) void k_rowpass(PassGeo pg, const double* __res
       const double a = (sW[slice][jj][D] + rh) * s;
 #pragma unroll
       for (int c = 0; c < KMAX; ++c) acc[c] = fma(a, sV[slice][jj][c], acc[c]);
-      if (NEWTON && nl) uacc = fma(s, sV[slice][jj][0], uacc);
+      if (MODE == 1 && ev) {
+#pragma unroll
+        for (int c = 0; c < KU; ++c) uacc[c] = fma(s, sV[slice][jj][c], uacc[c]);
+      }
+      if (NEWTON && nl) uacc[0] = fma(s, sV[slice][jj][0], uacc[0]);
     }
   }
-  // reduce the slices
+  // reduce the slices: solution values first (MODE 1)
+  if (MODE == 1) {
+#pragma unroll
+    for (int c0 = 0; c0 < KU; c0 += 8) {
+      __syncthreads();
+#pragma unroll
+      for (int c = 0; c < (KU < 8 ? KU : 8); ++c) red[slice][lane][c] = uacc[c0 + c < KU ? c0 + c : 0];
+      __syncthreads();
+      if (slice == 0 && rvalid && u_out) {
+#pragma unroll
+        for (int c = 0; c < (KU < 8 ? KU : 8); ++c) {
+          if (c0 + c >= K) break;
+          const double s = red[0][lane][c] + red[1][lane][c] + red[2][lane][c] + red[3][lane][c];
+          u_out[i * K + c0 + c] = ev ? norm * s : 0.0;
+        }
+      }
+    }
+  }
 #pragma unroll
   for (int c0 = 0; c0 < KMAX; c0 += 8) {
     __syncthreads();
 #pragma unroll
     for (int c = 0; c < (KMAX < 8 ? KMAX : 8); ++c) red[slice][lane][c] = acc[c0 + c < KMAX ? c0 + c : 0];
-    if (NEWTON && c0 == 0) redu[slice][lane] = uacc;
+    if (NEWTON && c0 == 0) redu[slice][lane] = uacc[0];
     __syncthreads();
     if (slice == 0 && rvalid) {
 #pragma unroll
@@ -193,21 +222,28 @@ size_t pass_work_elems(int n, int n_runs, int K) {
   return (size_t)col_splits(pg, K) * n * K;
 }
 
-#define FLSQ_ROW_K(DIM, KM)                                                                                 \
-  hipLaunchKernelGGL((k_rowpass<DIM, KM, false>), dim3(pg.n_runs), dim3(256), 0, s, pg, rho, V, K, Y, alpha, \
-                     beta_y, out, -1, nullptr, 0, 0.0, 0.0, nullptr, nullptr)
+#define FLSQ_ROW_K(DIM, KM, MD)                                                                              \
+  hipLaunchKernelGGL((k_rowpass<DIM, KM, MD>), dim3(pg.n_runs), dim3(256), 0, s, pg, rho, V, K, Y, alpha,     \
+                     beta_y, out, -1, nullptr, 0, pg.norm, 0.0, nullptr, u_out)
 
-#define FLSQ_ROW_CASE(DIM)          \
-  case DIM:                         \
-    if (K <= 1) FLSQ_ROW_K(DIM, 1); \
-    else if (K <= 4) FLSQ_ROW_K(DIM, 4); \
-    else if (K <= 16) FLSQ_ROW_K(DIM, 16); \
-    else FLSQ_ROW_K(DIM, 64); \
+#define FLSQ_ROW_CASE(DIM)                                                  \
+  case DIM:                                                                 \
+    if (u_out) {                                                            \
+      if (K <= 1) FLSQ_ROW_K(DIM, 1, 1);                                    \
+      else if (K <= 4) FLSQ_ROW_K(DIM, 4, 1);                               \
+      else FLSQ_ROW_K(DIM, 16, 1);                                          \
+    } else {                                                                \
+      if (K <= 1) FLSQ_ROW_K(DIM, 1, 0);                                    \
+      else if (K <= 4) FLSQ_ROW_K(DIM, 4, 0);                               \
+      else if (K <= 16) FLSQ_ROW_K(DIM, 16, 0);                             \
+      else FLSQ_ROW_K(DIM, 64, 0);                                          \
+    }                                                                       \
     break;
 
 hipError_t launch_rowpass_runs(const PassGeo& pg, const double* rho, const double* V, int K, const double* Y,
-                               double alpha, double beta_y, double* out, hipStream_t s) {
+                               double alpha, double beta_y, double* out, hipStream_t s, double* u_out) {
   if (K > 64 || K < 1) return hipErrorInvalidValue;
+  if (u_out && K > 16) return hipErrorInvalidValue;
   if (pg.n_runs == 0) return hipSuccess;
   switch (pg.g.d) {
     FLSQ_ROW_CASE(1) FLSQ_ROW_CASE(2) FLSQ_ROW_CASE(3) FLSQ_ROW_CASE(4)
@@ -252,7 +288,7 @@ hipError_t launch_colpass_runs(const PassGeo& pg, const double* rho, const doubl
 
 #define FLSQ_NEWTON_CASE(DIM)                                                                              \
   case DIM:                                                                                                \
-    hipLaunchKernelGGL((k_rowpass<DIM, 1, true>), dim3(pg.n_runs), dim3(256), 0, s, pg, nullptr, beta, 1,  \
+    hipLaunchKernelGGL((k_rowpass<DIM, 1, 2>), dim3(pg.n_runs), dim3(256), 0, s, pg, nullptr, beta, 1,     \
                        data_w, 1.0, 1.0, R, nonlin_block, poly, n_poly, norm, w_nl, rho_out, u_out);       \
     break;
 

@@ -66,7 +66,7 @@ class flsq_solve_info(C.Structure):
     _fields_ = [("refine_iters", C.c_int32), ("chol_retries", C.c_int32), ("shift", C.c_double),
                 ("grad_norm0", C.c_double), ("grad_norm", C.c_double), ("last_step_rel", C.c_double),
                 ("t_gram_ms", C.c_double), ("t_chol_ms", C.c_double), ("t_refine_ms", C.c_double),
-                ("t_total_ms", C.c_double)]
+                ("t_total_ms", C.c_double), ("t_gram_kernel_ms", C.c_double)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -128,9 +128,10 @@ def load(path: str = LIB_PATH):
         "flsq_inverse_loss_grad": (st, [vp, vp, i64, dbl, i32, vp, i32, i64, vp, vp, vp, vp, vp]),
         "flsq_adam_step": (st, [vp, vp, vp, vp, vp, i32, i32, i32, dbl, dbl, dbl, dbl, i32, dbl]),
     }
+    missing = [name for name in sig if not hasattr(lib, name)]
+    if missing:
+        raise RuntimeError(f"{path} does not export {missing}: rebuild it")
     for name, (res, args) in sig.items():
-        if not hasattr(lib, name):
-            continue
         fn = getattr(lib, name)
         fn.restype = res
         fn.argtypes = args
@@ -334,7 +335,8 @@ def flsq_evaluate(ctx, basis: Basis, beta, xq, alphas, out):
 
 
 def newton_opts(mu, max_iter=15, tol_dbeta=1e-10, armijo_c=1e-4, max_halvings=10, warm_start=True,
-                prec=PREC_FP64, max_refine=10, refine_tol=1e-12):
+                prec=PREC_FP64, max_refine=60, refine_tol=1e-14):
+    """Defaults: each Gauss-Newton step refined until u changes by < 1e-14 relative (at most 60 CG steps)."""
     return flsq_newton_opts(solve_opts(mu, prec, max_refine, refine_tol), float(tol_dbeta), int(max_iter),
                             float(armijo_c), int(max_halvings), int(bool(warm_start)))
 

@@ -33,9 +33,36 @@ def linear(name):
     print(name, "objective", obj, "rel err vs exact", oracle.rel_l2(u, prob.u_test), t, flush=True)
 
 
+def newton(name):
+    prob = wl.config(name)
+    beta, trace = oracle.solve_newton(prob, max_iter=15)
+    u = oracle.evaluate(prob.W, prob.b, beta, prob.x_test, [tuple([0] * prob.d)])[:, 0]
+    np.savez(os.path.join(OUT, f"{name}.npz"), beta=beta, u_test=u,
+             res_norm=np.array([t["res_norm"] for t in trace]), alpha=np.array([t["alpha"] for t in trace]),
+             step_norm=np.array([t["step_norm"] for t in trace]), err_exact=np.array(oracle.rel_l2(u, prob.u_test)))
+    print(name, "steps", len(trace), "res", [t["res_norm"] for t in trace], "err", oracle.rel_l2(u, prob.u_test),
+          flush=True)
+
+
+def inverse(name):
+    """Observations from the oracle's forward solve at the true source, plus 1 % relative noise."""
+    prob = wl.config(name)
+    n_obs = prob.extras["x_obs"].shape[0]
+    orc0 = oracle.InverseOracle(prob, np.zeros(n_obs))
+    rhs_true = orc0.rhs([wl.THETA_TRUE])[0][:, 0]
+    u_true = orc0.H @ oracle.tikhonov(orc0.A, rhs_true, prob.mu)
+    data = wl.add_noise(u_true, prob.extras["noise"])
+    orc = oracle.InverseOracle(prob, data)
+    loss, g, gk, _ = orc.loss_and_grad(prob.extras["theta0"])
+    np.savez(os.path.join(OUT, f"{name}.npz"), data=data, u_true=u_true, loss0=loss, grad_theta0=g, grad_kappa0=gk)
+    print(name, "loss0[:4]", loss[:4], flush=True)
+
+
+KIND = {"poisson2d": linear, "poisson6d": linear, "heat4d": linear, "reaction2d": newton, "inverse3d": inverse}
+
 if __name__ == "__main__":
     names = sys.argv[1:] or ["poisson2d", "poisson6d"]
     for nm in names:
         t0 = time.time()
-        linear(nm)
+        KIND[nm](nm)
         print(nm, "done in", time.time() - t0, "s", flush=True)
