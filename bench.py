@@ -38,7 +38,7 @@ def householder_flops(m, n):
     return 2.0 * m * n * n - 2.0 * n ** 3 / 3.0
 
 
-def cpu_baseline(prob, rows_int=4096, rows_bc=1024):
+def cpu_baseline(prob, rows_int=12288, rows_bc=3072):
     """The CPU oracle on a bounded sample: all N features, the first rows of each block.
 
     Sampled time is scaled to the full workload by the Householder flop count of the
