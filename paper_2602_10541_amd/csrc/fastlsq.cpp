@@ -473,14 +473,13 @@ Err cholesky_inv(flsq_ctx* c, double* G, double* X, int n, int* info_host) {
   }
   GemmDesc* dd;
   CHECK_ERR(upload_descs(c, all, &dd));
-  for (int b = 0; b < nblk; ++b) {
-    const int k0 = b * kNb;
-    CHECK_HIP(launch_potrf_diag(G, n, k0, info, X, st));
-    if (k0 + kNb < n) {
-      CHECK_HIP(launch_trsm_row(G, n, k0, st));
-      CHECK_HIP(launch_syrk(G, n, k0, st));
-    }
+  // block 0 first; every trailing update also factors the next diagonal block
+  CHECK_HIP(launch_potrf(G, n, 0, info, st));
+  for (int k0 = 0; k0 + kNb < n; k0 += kNb) {
+    CHECK_HIP(launch_trsm_row(G, n, k0, st));
+    CHECK_HIP(launch_syrk_potrf(G, n, k0, info, st));
   }
+  CHECK_HIP(launch_trinv_diag(G, n, X, st));
   for (size_t l = 0; l < lvT.size(); ++l) {
     int maxM = 0, maxN = 0;
     for (const GemmDesc& d : lvT[l]) {

@@ -1,0 +1,316 @@
+// Blocked right-looking Cholesky G = U^T U of the regularised Gram (upper triangle,
+// row-major, in place) and the inverses X_kk = U_kk^{-1} of its diagonal blocks.
+//
+// Block size kNb = 64.  For each block row k (host loop in fastlsq.cpp):
+//   k_trsm_row    U_kj = U_kk^{-T} G_kj for every block column j > k (forward substitution)
+//   k_syrk_potrf  G_ij -= U_ki^T U_kj over the trailing upper triangle (FP64 MFMA), and the
+//                 workgroup that owns the next diagonal block factors it right after updating it
+// Block 0 is factored by k_potrf before the loop; k_trinv inverts all diagonal blocks in one
+// launch afterwards (they are independent once U is known).
+//
+// The 64 x 64 factorisation runs on one 256-thread workgroup: wave q keeps rows
+// 16q .. 16q + 15 of the block (lane j: column j) in registers.  Rows are produced four at
+// a time by the wave that owns them: the pivots and the coupling entries U_{l,i} inside a
+// group move between lanes with register reads only.  The group's rows are published to
+// LDS (each LDS row is written once) and, after one barrier, every wave applies a rank-4
+// update to its rows below the group, reading the row entries as broadcasts.
+#include "flsq_device.h"
+#include "flsq_launch.h"
+
+namespace flsq {
+
+__device__ __forceinline__ double lane_bcast(double v, int lane) {
+  const long long u = __double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u & 0xffffffffll), lane);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)((unsigned long long)u >> 32), lane);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// 1 / sqrt(x) for x > 0: hardware estimate plus two Newton steps r <- r (3 - x r^2) / 2.
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  double r = __builtin_amdgcn_rsq(x);
+  r = r * fma(-0.5 * x, r * r, 1.5);
+  return r * fma(-0.5 * x, r * r, 1.5);
+}
+
+// Factor the diagonal block at k0 in place; all 256 threads of the workgroup call it
+// (S: kNb * kNb doubles of LDS, sbad: one int of LDS).  A short last block (nbk < 64) is
+// padded with the identity, which leaves the leading nbk x nbk factor unchanged.  A
+// non-positive or non-finite pivot is recorded in *info (1-based global index, first
+// failure) and replaced by 1 so every step completes.  Entries below the diagonal are scratch.
+__device__ __forceinline__ void potrf64_wg(double* G, int n, int k0, int* info, double* S, int* sbad) {
+  const int nbk = min(kNb, n - k0);
+  const int j = threadIdx.x & 63;
+  const int q = threadIdx.x >> 6;
+  double* base = G + (int64_t)k0 * n + k0 + j;
+  double v[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int i = 16 * q + r;
+    v[r] = (j < nbk && i < nbk && i <= j) ? base[(int64_t)i * n] : (i == j ? 1.0 : 0.0);
+  }
+  if (threadIdx.x == 0) *sbad = -1;
+#pragma unroll
+  for (int L = 0; L < kNb; L += 4) {
+    if (q == (L >> 4)) {
+      int bad = -1;
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const int l = L + a;
+        const double diag = lane_bcast(v[l & 15], l);
+        const bool fail = !(diag > 0.0) || !isfinite(diag);
+        bad = (fail && bad < 0) ? l : bad;
+        const double piv = fail ? 1.0 : diag;
+        const double r = rsqrt_nr(piv);
+        const double ulj = (j > l) ? v[l & 15] * r : ((j == l) ? piv * r : 0.0);
+        v[l & 15] = ulj;
+        S[l * kNb + j] = ulj;
+#pragma unroll
+        for (int i = l + 1; i < L + 4; ++i) v[i & 15] = fma(-lane_bcast(ulj, i), ulj, v[i & 15]);
+      }
+      if (j == 0 && bad >= 0 && *sbad < 0) *sbad = bad;
+    }
+    __syncthreads();
+    if (L + 4 < kNb) {
+      // all operands first (one batch of LDS reads in flight), then the multiply-adds
+      double uj[4], ui[4][16];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        uj[a] = S[(L + a) * kNb + j];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) ui[a][r] = S[(L + a) * kNb + 16 * q + r];
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int i = 16 * q + r;
+        if (i >= L + 4) {
+          double x = v[r];
+#pragma unroll
+          for (int a = 0; a < 4; ++a) x = fma(-ui[a][r], uj[a], x);
+          v[r] = x;
+        }
+      }
+    }
+  }
+  const int bad = *sbad;
+  if (threadIdx.x == 0 && bad >= 0 && bad < nbk && *info == 0) *info = k0 + bad + 1;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int i = 16 * q + r;
+    if (j < nbk && i <= j) base[(int64_t)i * n] = v[r];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_potrf(double* G, int n, int k0, int* info) {
+  __shared__ double S[kNb * kNb];
+  __shared__ int sbad;
+  potrf64_wg(G, n, k0, info, S, &sbad);
+}
+
+// Block row: y = U_kk^{-T} g for every column j >= k0 + kNb by forward substitution
+// (backward stable, unlike a product with the explicit inverse of U_kk).  Written with the
+// unit-diagonal factor: U_kk = D V, D = diag(U_kk), so y = D^{-1} z with z = V^{-T} g,
+// z_m = g_m - sum_{l < m} V_lm z_l.
+//
+// Lane m of a wave holds row m; each wave solves kTrsmCols columns at once (independent
+// chains).  Step l reads z_l from lane l (a register broadcast) and every lane applies
+// one multiply-add per column with its V_lm, which is zero for m <= l so the update
+// needs no mask.  V (strictly upper, scaled rows) sits in LDS; the workgroup's
+// 64 x (4 kTrsmCols) slab of G moves through LDS so that global accesses stay coalesced.
+constexpr int kTrsmCols = 4;
+constexpr int kTrsmWaves = 4;
+constexpr int kTrsmSlab = kTrsmCols * kTrsmWaves;   // 16 columns per workgroup
+
+__global__ __launch_bounds__(256) void k_trsm_row(double* G, int n, int k0) {
+  __shared__ double V[kNb][kNb + 1];
+  __shared__ double Y[kNb][kTrsmSlab + 1];
+  __shared__ double rinv[kNb];
+  const int t = threadIdx.x;
+  const int64_t jbase = (int64_t)k0 + kNb + (int64_t)blockIdx.x * kTrsmSlab;
+  // stage U_kk (always a full 64 x 64 block here): thread t covers column t % 64 of rows t / 64 + 4 r
+  {
+    const int c = t & 63;
+#pragma unroll
+    for (int r = 0; r < kNb / 4; ++r) {
+      const int l = (t >> 6) + 4 * r;
+      V[l][c] = G[(int64_t)(k0 + l) * n + k0 + c];
+    }
+  }
+  // stage the slab: 16 threads per row, 16 rows per pass
+  {
+    const int c = t & (kTrsmSlab - 1);
+    const int64_t j = jbase + c;
+#pragma unroll
+    for (int r = 0; r < kNb / 16; ++r) {
+      const int l = (t >> 4) + 16 * r;
+      Y[l][c] = (j < n) ? G[(int64_t)(k0 + l) * n + j] : 0.0;
+    }
+  }
+  __syncthreads();
+  if (t < kNb) rinv[t] = 1.0 / V[t][t];
+  __syncthreads();
+  // V_lm = U_lm / U_ll for m > l, 0 on and below the diagonal
+  {
+    const int c = t & 63;
+#pragma unroll
+    for (int r = 0; r < kNb / 4; ++r) {
+      const int l = (t >> 6) + 4 * r;
+      V[l][c] = (c > l) ? V[l][c] * rinv[l] : 0.0;
+    }
+  }
+  __syncthreads();
+  const int m = t & 63, w = t >> 6;
+  double z[kTrsmCols];
+#pragma unroll
+  for (int c = 0; c < kTrsmCols; ++c) z[c] = Y[m][w * kTrsmCols + c];
+#pragma unroll
+  for (int l = 0; l < kNb - 1; ++l) {
+    const double v = V[l][m];
+#pragma unroll
+    for (int c = 0; c < kTrsmCols; ++c) z[c] = fma(-v, lane_bcast(z[c], l), z[c]);
+  }
+  const double rm = rinv[m];
+#pragma unroll
+  for (int c = 0; c < kTrsmCols; ++c) Y[m][w * kTrsmCols + c] = z[c] * rm;
+  __syncthreads();
+  {
+    const int c = t & (kTrsmSlab - 1);
+    const int64_t j = jbase + c;
+    if (j < n) {
+#pragma unroll
+      for (int r = 0; r < kNb / 16; ++r) {
+        const int l = (t >> 4) + 16 * r;
+        G[(int64_t)(k0 + l) * n + j] = Y[l][c];
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ void tri_coords(int t, int nt, int* ti, int* tj) {
+  int r = 0, rowlen = nt;
+  while (t >= rowlen) {
+    t -= rowlen;
+    ++r;
+    --rowlen;
+  }
+  *ti = r;
+  *tj = r + t;
+}
+
+// Trailing update of the upper triangle G_ij -= sum_l U_{k0+l,i} U_{k0+l,j}, i <= j, over
+// rows and columns [k0 + kNb, n), in 128 x 128 tiles (ti <= tj), one workgroup per tile:
+// wave w computes the 64 x 64 quadrant (w / 2, w % 2) with FP64 MFMA 16x16x4, operands read
+// straight from the panel rows into the MFMA register layout.  Workgroup 0 owns tile (0, 0),
+// whose leading 64 x 64 quadrant is the next diagonal block: after its update the workgroup factors it.
+__global__ __launch_bounds__(256, 1) void k_syrk_potrf(double* G, int n, int k0, int* info) {
+  __shared__ double S[kNb * kNb];
+  __shared__ int sbad;
+  const int k1 = k0 + kNb;
+  const int nt = (n - k1 + 127) / 128;
+  int ti, tj;
+  tri_coords(blockIdx.x, nt, &ti, &tj);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int qi = wave >> 1, qj = wave & 1;
+  const int i0 = k1 + ti * 128 + qi * 64, j0 = k1 + tj * 128 + qj * 64;
+  const bool active = !(ti == tj && qi > qj) && i0 < n && j0 < n;
+  if (active) {
+    const double* panel = G + (int64_t)k0 * n;
+    const int r16 = lane & 15, k4 = lane >> 4;
+    f64x4 acc[4][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[r][c] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+    for (int kk = 0; kk < kNb / 4; ++kk) {
+      const double* prow = panel + (int64_t)(4 * kk + k4) * n;
+      double a[4], b[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int ci = i0 + 16 * r + r16, cj = j0 + 16 * r + r16;
+        a[r] = (ci < n) ? prow[ci] : 0.0;
+        b[r] = (cj < n) ? prow[cj] : 0.0;
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[r], b[c], acc[r][c], 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = i0 + 16 * r + 4 * v + k4;
+          const int j = j0 + 16 * c + r16;
+          if (i < n && j < n && j >= i) G[(int64_t)i * n + j] -= acc[r][c][v];
+        }
+  }
+  if (blockIdx.x == 0) {
+    __syncthreads();
+    potrf64_wg(G, n, k1, info, S, &sbad);
+  }
+}
+
+// X_kk = U_kk^{-1} for every diagonal block (one wave per block): lane j solves U x = e_j
+// by back substitution, x_i = (delta_ij - sum_{m > i} U_im x_m) / U_ii, with U_kk in LDS
+// (identity-padded past n).  Only the diagonal blocks of X are written.
+__global__ __launch_bounds__(64) void k_trinv(const double* G, int n, double* X) {
+  __shared__ double U[kNb][kNb];
+  __shared__ double rinv[kNb];
+  const int k0 = blockIdx.x * kNb;
+  const int nbk = min(kNb, n - k0);
+  const int t = threadIdx.x;
+#pragma unroll 16
+  for (int l = 0; l < kNb; ++l) {
+    double v = (l == t) ? 1.0 : 0.0;
+    if (l < nbk && t < nbk && t >= l) v = G[(int64_t)(k0 + l) * n + k0 + t];
+    U[l][t] = v;
+  }
+  __syncthreads();
+  rinv[t] = 1.0 / U[t][t];
+  __syncthreads();
+  double x[kNb];
+#pragma unroll
+  for (int i = kNb - 1; i >= 0; --i) {
+    double s = (i == t) ? 1.0 : 0.0;
+#pragma unroll
+    for (int m = i + 1; m < kNb; ++m) s = fma(-U[i][m], x[m], s);
+    x[i] = s * rinv[i];
+  }
+  if (t < nbk) {
+#pragma unroll
+    for (int i = 0; i < kNb; ++i)
+      if (i < nbk) X[(int64_t)(k0 + i) * n + k0 + t] = x[i];
+  }
+}
+
+hipError_t launch_potrf(double* G, int n, int k0, int* info, hipStream_t s) {
+  hipLaunchKernelGGL(k_potrf, dim3(1), dim3(256), 0, s, G, n, k0, info);
+  return hipGetLastError();
+}
+
+hipError_t launch_trsm_row(double* G, int n, int k0, hipStream_t s) {
+  const int cols = n - k0 - kNb;
+  if (cols <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_trsm_row, dim3((cols + kTrsmSlab - 1) / kTrsmSlab), dim3(256), 0, s, G, n, k0);
+  return hipGetLastError();
+}
+
+hipError_t launch_syrk_potrf(double* G, int n, int k0, int* info, hipStream_t s) {
+  const int rem = n - k0 - kNb;
+  if (rem <= 0) return hipSuccess;
+  const int nt = (rem + 127) / 128;
+  hipLaunchKernelGGL(k_syrk_potrf, dim3(nt * (nt + 1) / 2), dim3(256), 0, s, G, n, k0, info);
+  return hipGetLastError();
+}
+
+hipError_t launch_trinv_diag(const double* G, int n, double* X, hipStream_t s) {
+  const int nblk = (n + kNb - 1) / kNb;
+  hipLaunchKernelGGL(k_trinv, dim3(nblk), dim3(64), 0, s, G, n, X);
+  return hipGetLastError();
+}
+
+}  // namespace flsq

@@ -1,109 +1,11 @@
-// Dense FP64 linear algebra for the regularised normal equations (A^T A + mu I) beta = A^T rhs.
-//
-// G is stored row-major and only its upper triangle is used.  The factor is upper
-// triangular, G = U^T U, computed in place by a blocked right-looking Cholesky with
-// block size kNb = 64:
-//   1. factor the diagonal block and invert it  (one workgroup, in LDS)
-//   2. block row: U_kj = U_kk^{-T} G_kj = X_kk^T G_kj   (batched MFMA GEMM, k_dense.hip)
-//   3. trailing update G_ij -= U_ki^T U_kj       (FP64 MFMA 16x16x4, 64 x 64 tiles, i <= j)
-// The off-diagonal blocks of X = U^{-1} are assembled afterwards level by level
-// (X_12 = -X_11 U_12 X_22) with the same GEMM.
+// Dense FP64 helpers around the Cholesky factor of the regularised normal equations
+// (A^T A + mu I) beta = A^T rhs: diagonal equilibration, copies, norms, and the small
+// column-wise vector kernels of the CGLS / PCG iterations.  The factorisation itself is
+// in k_chol.hip, the products with the explicit inverse factor in k_dense.hip.
 #include "flsq_device.h"
 #include "flsq_launch.h"
 
 namespace flsq {
-
-__device__ __forceinline__ void tri_coords(int t, int nt, int* ti, int* tj) {
-  int r = 0, rowlen = nt;
-  while (t >= rowlen) {
-    t -= rowlen;
-    ++r;
-    --rowlen;
-  }
-  *ti = r;
-  *tj = r + t;
-}
-
-// Trailing update of the upper triangle: G[i][j] -= sum_l U[k0+l][i] U[k0+l][j], k1 <= i <= j.
-__global__ __launch_bounds__(256) void k_syrk(double* G, int n, int k0) {
-  __shared__ double pI[kNb][64 + 1];
-  __shared__ double pJ[kNb][64 + 1];
-  const int k1 = k0 + kNb;
-  const int nt = (n - k1 + 63) / 64;
-  int ti, tj;
-  tri_coords(blockIdx.x, nt, &ti, &tj);
-  const int i0 = k1 + ti * 64, j0 = k1 + tj * 64;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int e = tid; e < kNb * 64; e += 256) {
-    const int l = e / 64, c = e % 64;
-    const int64_t row = (int64_t)(k0 + l) * n;
-    pI[l][c] = (i0 + c < n) ? G[row + i0 + c] : 0.0;
-    pJ[l][c] = (j0 + c < n) ? G[row + j0 + c] : 0.0;
-  }
-  __syncthreads();
-  f64x4 acc[4];
-#pragma unroll
-  for (int b = 0; b < 4; ++b) acc[b] = f64x4{0.0, 0.0, 0.0, 0.0};
-  // wave w owns output block-row w (16 rows), four 16-column blocks
-#pragma unroll
-  for (int kk = 0; kk < kNb / 4; ++kk) {
-    const int l = kk * 4 + (lane >> 4);
-    const double av = pI[l][wave * 16 + (lane & 15)];
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const double bv = pJ[l][b * 16 + (lane & 15)];
-      acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[b], 0, 0, 0);
-    }
-  }
-#pragma unroll
-  for (int b = 0; b < 4; ++b)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int i = i0 + wave * 16 + 4 * v + (lane >> 4);
-      const int j = j0 + b * 16 + (lane & 15);
-      if (i < n && j < n && j >= i) G[(int64_t)i * n + j] -= acc[b][v];
-    }
-}
-
-hipError_t launch_syrk(double* G, int n, int k0, hipStream_t s) {
-  const int rem = n - k0 - kNb;
-  if (rem <= 0) return hipSuccess;
-  const int nt = (rem + 63) / 64;
-  hipLaunchKernelGGL(k_syrk, dim3(nt * (nt + 1) / 2), dim3(256), 0, s, G, n, k0);
-  return hipGetLastError();
-}
-
-// Block row: for each column j >= k0 + kNb solve U_kk^T y = g by forward substitution
-// (backward stable, unlike multiplying by the explicit inverse of U_kk).  One column per
-// thread, 64-thread workgroups so the (n - k1) columns spread over many CUs.  The
-// triangle U_kk is read through its own read-only pointer: every address is wave-uniform,
-// so its values arrive in scalar registers in wide batches instead of one LDS round trip
-// per multiply-add.  The kernel writes only columns >= k1 of the block row, never U_kk.
-__global__ __launch_bounds__(64) void k_trsm_row(double* __restrict__ Grow, const double* __restrict__ Ukk, int n,
-                                                 int jend) {
-  const int j = kNb + blockIdx.x * 64 + threadIdx.x;     // column offset from k0
-  if (j >= jend) return;
-  double y[kNb];
-#pragma unroll
-  for (int l = 0; l < kNb; ++l) y[l] = Grow[(int64_t)l * n + j];
-#pragma unroll
-  for (int l = 0; l < kNb; ++l) {
-    y[l] = y[l] / Ukk[(int64_t)l * n + l];
-#pragma unroll
-    for (int m = l + 1; m < kNb; ++m) y[m] = fma(-Ukk[(int64_t)l * n + m], y[l], y[m]);
-  }
-#pragma unroll
-  for (int l = 0; l < kNb; ++l) Grow[(int64_t)l * n + j] = y[l];
-}
-
-hipError_t launch_trsm_row(double* G, int n, int k0, hipStream_t s) {
-  const int cols = n - k0 - kNb;
-  if (cols <= 0) return hipSuccess;
-  double* base = G + (int64_t)k0 * n + k0;
-  // columns are addressed relative to k0; the valid range is j < n - k0
-  hipLaunchKernelGGL(k_trsm_row, dim3((cols + 63) / 64), dim3(64), 0, s, base, (const double*)base, n, n - k0);
-  return hipGetLastError();
-}
 
 // ------------------------------------------------------------------ equilibration
 // d_i = 1 / sqrt(G_ii) (1 where G_ii <= 0); used to scale G to unit diagonal before the
