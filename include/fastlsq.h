@@ -46,7 +46,11 @@ typedef enum {
 typedef enum {
     FLSQ_PREC_FP64 = 0,          /* FP64 assembly, FP64 MFMA Gram, FP64 Cholesky + refinement */
     FLSQ_PREC_FP32_REFINE = 1,   /* FP32 assembly + FP32 MFMA Gram -> FP64 Cholesky preconditioner, FP64 refinement */
-    FLSQ_PREC_BF16X3_REFINE = 2  /* FP32 entries split into bf16 hi + lo, three bf16 MFMA products, FP32 accumulate */
+    FLSQ_PREC_BF16X3_REFINE = 2, /* FP32 entries split into bf16 hi + lo, three bf16 MFMA products, FP32 accumulate */
+    FLSQ_PREC_INT8_CRT = 3       /* FP64 entries rounded to ~42-bit integers (per-feature scale), Gram of their
+                                    residues modulo 13 coprime odd moduli on the int8 matrix cores (exact
+                                    int32 sums), Chinese-remainder reconstruction to FP64; then the FP64
+                                    Cholesky + refinement of FLSQ_PREC_FP64.  Needs P <= 133 000 rows. */
 } flsq_precision;
 
 #define FLSQ_MAX_DIM 8
@@ -102,7 +106,8 @@ typedef struct {
     double grad_norm;       /* same, at the returned beta */
     double last_step_rel;   /* ||last refinement step|| / ||beta|| */
     double t_gram_ms, t_chol_ms, t_refine_ms, t_total_ms;
-    double t_gram_kernel_ms; /* the fused assembly + Gram kernel alone (HIP events on the stream) */
+    double t_gram_kernel_ms; /* the matrix-core Gram kernel alone (HIP events on the stream): the fused
+                                assembly + Gram kernel for FP64 / FP32, the int8 tile kernel for INT8_CRT */
 } flsq_solve_info;
 
 typedef struct flsq_ctx flsq_ctx;

@@ -371,7 +371,95 @@ Err build_system(flsq_ctx* c, System& s, const flsq_basis* basis, const flsq_row
 
 // ------------------------------------------------------------------ Gram
 // G (n x n) gets the Gram product of the stacked rows; upper triangle only unless mirror.
+// Moduli of the int8 Gram: the 13 largest pairwise coprime odd numbers <= 255 (product
+// ~2^102.2), with their inverses modulo each other for the Garner reconstruction.
+const I8Moduli& i8_moduli() {
+  static I8Moduli M = [] {
+    I8Moduli m{};
+    const int list[13] = {255, 253, 251, 247, 241, 239, 233, 229, 227, 223, 217, 211, 199};
+    m.n_mod = 13;
+    for (int t = 0; t < m.n_mod; ++t) {
+      m.ip[t] = list[t];
+      m.p[t] = list[t];
+      m.inv_p[t] = 1.0 / list[t];
+    }
+    for (int a = 0; a < m.n_mod; ++a)
+      for (int k = 0; k < m.n_mod; ++k) {
+        int inv = 0;
+        if (a < k)
+          for (int x = 1; x < m.ip[k]; ++x)
+            if ((m.ip[a] % m.ip[k]) * x % m.ip[k] == 1) {
+              inv = x;
+              break;
+            }
+        m.cinv[a][k] = inv;
+      }
+    return m;
+  }();
+  return M;
+}
+
+// Integer bits B of the scaled entries: 2^(2B) P_pad < M / 2 keeps every Gram entry inside
+// the range the residues determine; one bit of margin.
+int i8_bits(int64_t P_pad) {
+  const I8Moduli& M = i8_moduli();
+  double log2m = 0.0;
+  for (int t = 0; t < M.n_mod; ++t) log2m += std::log2((double)M.ip[t]);
+  const int B = (int)std::floor((log2m - 1.0 - std::log2((double)P_pad)) / 2.0) - 1;
+  return std::min(B, 52);
+}
+
+constexpr int64_t kI8MaxRows = 133000;   // 127^2 * rows < 2^31: exact int32 sums
+
+Err run_gram_i8(flsq_ctx* c, const System& s, const double* rho, double* G, int mirror, double diag_add) {
+  const int T = i8_tile(), KBR = i8_kblock();
+  const int n = s.n;
+  const int nt = (n + T - 1) / T, n_pad = nt * T, n_tiles = nt * (nt + 1) / 2;
+  const int64_t P_pad = (s.P + 2 * KBR - 1) / (2 * KBR) * (2 * KBR);
+  if (P_pad > kI8MaxRows)
+    return fail(FLSQ_EINVAL, "INT8_CRT Gram supports at most %lld rows (got %lld)", (long long)kI8MaxRows,
+                (long long)s.P);
+  const int KB = (int)(P_pad / KBR);
+  const I8Moduli& M = i8_moduli();
+  const int B = i8_bits(P_pad);
+  int8_t* R;
+  int32_t* Gt;
+  double *inv_scale, *scale, *rho_max;
+  CHECK_ERR(ws_get(c, "i8_R", (size_t)M.n_mod * KB * n_pad * KBR, &R));
+  CHECK_ERR(ws_get(c, "i8_Gt", (size_t)M.n_mod * n_tiles * T * T, &Gt));
+  CHECK_ERR(ws_get(c, "i8_inv", (size_t)n, &inv_scale));
+  CHECK_ERR(ws_get(c, "i8_scale", (size_t)n, &scale));
+  CHECK_ERR(ws_get(c, "i8_rhomax", 1, &rho_max));
+  const hipStream_t st = c->stream;
+  CHECK_HIP(launch_i8_scale(s.amp.as<double>(), s.n_blocks, n, rho, s.P, rho_max, B, inv_scale, scale, st));
+  CHECK_HIP(launch_i8_residues(s.geo(), rho, inv_scale, M, n_pad, KB, R, st));
+  I8GemmJob J;
+  J.R = R;
+  J.n_pad = n_pad;
+  J.KB = KB;
+  J.nt = nt;
+  J.n_tiles = n_tiles;
+  J.n_mod = M.n_mod;
+  J.out = Gt;
+  CHECK_HIP(hipEventRecord(c->ev0, st));
+  CHECK_HIP(launch_gram_i8(J, st));
+  CHECK_HIP(hipEventRecord(c->ev1, st));
+  I8CrtJob Cj;
+  Cj.M = M;
+  Cj.Gt = Gt;
+  Cj.scale = scale;
+  Cj.n = n;
+  Cj.nt = nt;
+  Cj.n_tiles = n_tiles;
+  Cj.G = G;
+  Cj.mirror = mirror;
+  Cj.diag_add = diag_add;
+  CHECK_HIP(launch_i8_crt(Cj, st));
+  return ok();
+}
+
 Err run_gram(flsq_ctx* c, const System& s, int prec, const double* rho, double* G, int mirror, double diag_add) {
+  if (prec == FLSQ_PREC_INT8_CRT) return run_gram_i8(c, s, rho, G, mirror, diag_add);
   const int T = gram_tile();
   const size_t part_elems = (size_t)s.n_wg * s.max_seg * T * T;
   void* partial;
@@ -744,7 +832,8 @@ SolveParams params_of(const flsq_solve_opts* o) {
 
 Err check_params(const SolveParams& p) {
   if (!(p.mu >= 0.0) || !std::isfinite(p.mu)) return fail(FLSQ_EINVAL, "mu must be finite and >= 0");
-  if (p.prec != FLSQ_PREC_FP64 && p.prec != FLSQ_PREC_FP32_REFINE && p.prec != FLSQ_PREC_BF16X3_REFINE)
+  if (p.prec != FLSQ_PREC_FP64 && p.prec != FLSQ_PREC_FP32_REFINE && p.prec != FLSQ_PREC_BF16X3_REFINE &&
+      p.prec != FLSQ_PREC_INT8_CRT)
     return fail(FLSQ_EINVAL, "unknown precision %d", p.prec);
   if (p.prec == FLSQ_PREC_BF16X3_REFINE) return fail(FLSQ_EINVAL, "BF16x3 Gram is not available in this build");
   if (p.max_refine < 0 || p.max_refine > 100000) return fail(FLSQ_EINVAL, "max_refine out of range");
@@ -769,7 +858,8 @@ Err gram_and_factor(flsq_ctx* c, const System& s, const double* rho, const Solve
   c->last_gram_kernel_ms = kms;
   double shift = 0.0;
   int retries = 0;
-  const double rel0 = (sp.prec == FLSQ_PREC_FP64) ? sp.shift_rel : (sp.shift_rel > 0.0 ? sp.shift_rel : 1e-6);
+  const bool exact_gram = sp.prec == FLSQ_PREC_FP64 || sp.prec == FLSQ_PREC_INT8_CRT;
+  const double rel0 = exact_gram ? sp.shift_rel : (sp.shift_rel > 0.0 ? sp.shift_rel : 1e-6);
   CHECK_ERR(factor_with_retries(c, G, U, Xi, n, sp.mu, rel0, &shift, &retries));
   const double t2 = now_ms();
   if (info) {

@@ -65,6 +65,43 @@ hipError_t launch_gram(const GramLaunch& L, hipStream_t s);
 hipError_t launch_gram_reduce(int prec, const void* partial, const int32_t* slot_ptr, const int32_t* slots,
                               int nt, int n, double* G, int mirror, double diag_add, hipStream_t s);
 
+// ---- Gram from exact integer products on the int8 matrix cores (k_gram_i8.hip)
+constexpr int kI8MaxMod = 16;
+struct I8Moduli {
+  int n_mod;
+  int ip[kI8MaxMod];                 // odd, pairwise coprime, <= 255
+  double p[kI8MaxMod];
+  double inv_p[kI8MaxMod];
+  int cinv[kI8MaxMod][kI8MaxMod];    // cinv[m][k] = p_m^{-1} mod p_k for m < k
+};
+struct I8GemmJob {
+  const int8_t* R;     // residues [n_mod][KB][n_pad][64]
+  int n_pad;           // features padded to whole tiles
+  int KB;              // 64-row K blocks (even)
+  int nt, n_tiles;     // tiles per side, upper-triangle tiles
+  int n_mod;
+  int32_t* out;        // [n_mod][n_tiles][256 * 256]
+};
+struct I8CrtJob {
+  I8Moduli M;
+  const int32_t* Gt;   // k_gram_i8 output
+  const double* scale; // c_j 2^-B per feature
+  int n, nt, n_tiles;
+  double* G;           // n x n row-major, upper triangle (both with mirror)
+  int mirror;
+  double diag_add;
+};
+int i8_tile();
+int i8_kblock();
+size_t i8_gemm_lds_bytes();
+// c_j = max_g |amp_gj| + max_i |rho_i| (rho nullable; rho_max: device scalar workspace)
+hipError_t launch_i8_scale(const double* amp, int n_blocks, int n, const double* rho, int64_t P, double* rho_max,
+                           int B, double* inv_scale, double* scale, hipStream_t s);
+hipError_t launch_i8_residues(const Geo& g, const double* rho, const double* inv_scale, const I8Moduli& M, int n_pad,
+                              int KB, int8_t* R, hipStream_t s);
+hipError_t launch_gram_i8(const I8GemmJob& J, hipStream_t s);
+hipError_t launch_i8_crt(const I8CrtJob& J, hipStream_t s);
+
 // ---- matrix-free FP64 products over the stacked rows (A recomputed per entry)
 struct PassGeo {
   Geo g;

@@ -1,0 +1,312 @@
+// Gram product A^T A from exact integer products on the int8 matrix cores.
+//
+// Every entry of A (Eq. (2)-(3), amplitude/phase form of flsq_device.h) is formed in
+// FP64, scaled per feature to an integer a_ij = rint(A_ij 2^B / c_j) with |a_ij| <= 2^B
+// (c_j bounds |A_ij| over all rows: max over blocks of |amp_gj| plus max |rho_i|), and
+// represented by its balanced residues modulo a set of pairwise coprime odd moduli
+// p_t <= 255, each of which fits in int8.  For every modulus the integer Gram
+// sum_i r_ij r_il is exact in int32 (|r| <= 127, so up to 133 000 rows), and the
+// Chinese remainder theorem recovers sum_i a_ij a_il exactly as long as the product of
+// the moduli exceeds twice its magnitude.  The only rounding is that of A to B bits and
+// of the final conversion to FP64: with B ~ 42 the Gram is as accurate as an FP64
+// product, at int8 matrix-core rate.
+//
+//   k_i8_scale      c_j and 2^B / c_j per feature
+//   k_i8_residues   residues of the scaled entries, int8, K-blocked [t][kb][feature][64 rows]
+//   k_gram_i8       per modulus, the upper-triangle 256 x 256 tiles of R_t^T R_t (int32)
+//   k_i8_crt        balanced mixed-radix (Garner) reconstruction, FP64 Horner, scaling
+#include "flsq_device.h"
+#include "flsq_launch.h"
+
+namespace flsq {
+
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+typedef int i32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int kI8Tile = 256;    // features per tile side
+constexpr int kI8Kb = 64;       // rows per K block of the residue layout
+constexpr int kI8Stage = 128;   // rows per LDS stage (two K blocks)
+constexpr int kI8Pitch = kI8Stage + 16;   // LDS bytes per feature row: 16-lane reads hit distinct banks
+
+// ------------------------------------------------------------------ scales
+// rho_max (nullable): device scalar max_i |rho_i|.
+__global__ void k_i8_scale(const double* amp, int n_blocks, int n, const double* rho_max, double two_b,
+                           double* inv_scale, double* scale) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= n) return;
+  double c = 0.0;
+  for (int g = 0; g < n_blocks; ++g) c = fmax(c, fabs(amp[(int64_t)g * n + f]));
+  if (rho_max) c += *rho_max;
+  inv_scale[f] = (c > 0.0) ? two_b / c : 0.0;
+  scale[f] = (c > 0.0) ? c / two_b : 0.0;
+}
+
+// max |x_i| over n entries (one workgroup; deterministic).
+__global__ __launch_bounds__(1024) void k_absmax(const double* x, int64_t n, double* out) {
+  __shared__ double red[1024];
+  double m = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 1024) m = fmax(m, fabs(x[i]));
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = 512; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = red[0];
+}
+
+// ------------------------------------------------------------------ residues
+// Workgroup: 64 features x one 64-row K block; thread (feature tid / 4, rows 16 (tid % 4) ..).
+// R layout: R[((t * KB + kb) * n_pad + f) * 64 + r], zero for padded rows and features.
+template <int D>
+__global__ __launch_bounds__(256) void k_i8_residues(Geo g, const double* rho, const double* inv_scale,
+                                                     I8Moduli M, int n_pad, int KB, int8_t* R) {
+  __shared__ double sX[D][kI8Kb];
+  __shared__ double sRho[kI8Kb];
+  __shared__ int sBlk[kI8Kb];
+  const int kb = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int64_t i0 = (int64_t)kb * kI8Kb;
+  for (int e = tid; e < D * kI8Kb; e += 256) {
+    const int k = e / kI8Kb, r = e % kI8Kb;
+    sX[k][r] = (i0 + r < g.P) ? g.Xt[(int64_t)k * g.P + i0 + r] : 0.0;
+  }
+  if (tid < kI8Kb) {
+    const bool in = i0 + tid < g.P;
+    sRho[tid] = (rho && in) ? rho[i0 + tid] : 0.0;
+    sBlk[tid] = in ? g.row_block[i0 + tid] : -1;
+  }
+  __syncthreads();
+  const int f = blockIdx.y * 64 + tid / 4;
+  const int r0 = 16 * (tid % 4);
+  const bool fvalid = f < g.n;
+  double w[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) w[k] = fvalid ? g.Wt[(int64_t)k * g.n + f] : 0.0;
+  const double isc = fvalid ? inv_scale[f] : 0.0;
+  double a[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int blk = sBlk[r0 + r];
+    double v = 0.0;
+    if (fvalid && blk >= 0) {
+      double z = g.ph[(int64_t)blk * g.n + f];
+#pragma unroll
+      for (int k = 0; k < D; ++k) z = fma(w[k], sX[k][r0 + r], z);
+      v = rint((g.amp[(int64_t)blk * g.n + f] + sRho[r0 + r]) * sin_f64(z) * isc);
+    }
+    a[r] = v;
+  }
+  for (int t = 0; t < M.n_mod; ++t) {
+    const double p = M.p[t], ip = M.inv_p[t];
+    unsigned pk[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      unsigned word = 0;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        // a / p is never within 1/(2p) of a half-integer (a integer, p odd), so rint of the
+        // rounded quotient is exact and the remainder is exact in FP64.
+        const double x = a[4 * q + e];
+        const double rr = fma(-p, rint(x * ip), x);
+        word |= ((unsigned)(int)rr & 0xffu) << (8 * e);
+      }
+      pk[q] = word;
+    }
+    int8_t* dst = R + (((int64_t)t * KB + kb) * n_pad + f) * kI8Kb + r0;
+    *(i32x4*)dst = i32x4{(int)pk[0], (int)pk[1], (int)pk[2], (int)pk[3]};
+  }
+}
+
+// ------------------------------------------------------------------ int8 Gram tiles
+// Workgroup = one upper tile (ti <= tj) of one modulus, 4 waves in 2 x 2, each wave a
+// 128 x 128 quarter as 4 x 4 blocks of v_mfma_i32_32x32x32_i8.  Both operands are
+// residues of the same matrix with rows on the contraction axis, so a lane's 16 bytes
+// are 16 consecutive rows of one feature for the A and the B side alike.  Two LDS
+// stages of 128 rows; the next stage is fetched into registers while the current one
+// feeds the matrix cores.
+__device__ __forceinline__ void i8_tile_coords(int t, int nt, int* ti, int* tj) {
+  int r = 0, rowlen = nt;
+  while (t >= rowlen) {
+    t -= rowlen;
+    ++r;
+    --rowlen;
+  }
+  *ti = r;
+  *tj = r + t;
+}
+
+__global__ __launch_bounds__(256, 1) void k_gram_i8(I8GemmJob J) {
+  extern __shared__ __align__(16) unsigned char smem[];   // [2 stages][2 panels][256][kI8Pitch]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  // XCD-aware order: consecutive workgroup ids go to different XCDs, so give each XCD a
+  // contiguous range of (modulus-major) tiles, whose row panels it then shares in L2.
+  const int total = J.n_tiles * J.n_mod;
+  int wg = blockIdx.x;
+  const int full = (total / 8) * 8;
+  if (wg < full) wg = (wg % 8) * (total / 8) + wg / 8;
+  const int t = wg / J.n_tiles, tile = wg % J.n_tiles;
+  int ti, tj;
+  i8_tile_coords(tile, J.nt, &ti, &tj);
+  const int8_t* baseA = J.R + ((int64_t)t * J.KB * J.n_pad + (int64_t)ti * kI8Tile) * kI8Kb;
+  const int8_t* baseB = J.R + ((int64_t)t * J.KB * J.n_pad + (int64_t)tj * kI8Tile) * kI8Kb;
+  const int64_t kb_stride = (int64_t)J.n_pad * kI8Kb;
+
+  // stage loader: 2 panels x 2 K blocks x 16 KB = 64 KB, 16 x 16 B per thread
+  i32x4 stg[16];
+  auto fetch = [&](int s) {
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int panel = q >> 3, kbsub = (q >> 2) & 1, part = q & 3;
+      const int8_t* src = (panel ? baseB : baseA) + (int64_t)(2 * s + kbsub) * kb_stride + part * 4096 + tid * 16;
+      stg[q] = *(const i32x4*)src;
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int panel = q >> 3, kbsub = (q >> 2) & 1, part = q & 3;
+      const int o = part * 4096 + tid * 16;            // byte offset inside the 16 KB K block
+      const int f = o >> 6, byte = o & 63;
+      unsigned char* dst = smem + ((buf * 2 + panel) * kI8Tile + f) * kI8Pitch + kbsub * kI8Kb + byte;
+      *(i32x4*)dst = stg[q];
+    }
+  };
+
+  i32x16 acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[a][b][v] = 0;
+
+  const int n_stage = J.KB / 2;
+  fetch(0);
+  stash(0);
+  __syncthreads();
+  for (int s = 0; s < n_stage; ++s) {
+    const int buf = s & 1;
+    if (s + 1 < n_stage) fetch(s + 1);
+    const unsigned char* pA = smem + ((buf * 2 + 0) * kI8Tile) * kI8Pitch;
+    const unsigned char* pB = smem + ((buf * 2 + 1) * kI8Tile) * kI8Pitch;
+#pragma unroll
+    for (int ks = 0; ks < kI8Stage / 32; ++ks) {
+      const int off = ks * 32 + 16 * (lane >> 5);
+      i32x4 av[4], bv[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) av[a] = *(const i32x4*)(pA + (wm * 128 + a * 32 + (lane & 31)) * kI8Pitch + off);
+#pragma unroll
+      for (int b = 0; b < 4; ++b) bv[b] = *(const i32x4*)(pB + (wn * 128 + b * 32 + (lane & 31)) * kI8Pitch + off);
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(av[a], bv[b], acc[a][b], 0, 0, 0);
+    }
+    if (s + 1 < n_stage) stash(buf ^ 1);
+    __syncthreads();
+  }
+  // 32 x 32 block layout: slot v is row 8 (v / 4) + 4 (lane / 32) + v % 4, column lane % 32
+  int32_t* out = J.out + ((int64_t)t * J.n_tiles + tile) * (kI8Tile * kI8Tile);
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int row = wm * 128 + a * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        const int col = wn * 128 + b * 32 + (lane & 31);
+        out[row * kI8Tile + col] = acc[a][b][v];
+      }
+}
+
+// ------------------------------------------------------------------ reconstruction
+__device__ __forceinline__ int bal_mod(int x, int p) {
+  int r = x % p;                       // (-p, p)
+  const int h = (p - 1) >> 1;
+  if (r > h) r -= p;
+  if (r < -h) r += p;
+  return r;
+}
+
+// One thread per upper-triangle entry (j <= l) of G (n x n row-major): balanced Garner
+// digits v_k of the residues, X = v_0 + p_0 (v_1 + p_1 (v_2 + ...)) evaluated from the top
+// in FP64 (a small |X| has leading zero digits, so nothing cancels), G_jl = X s_j s_l.
+__global__ void k_i8_crt(I8CrtJob J) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (l >= J.n || l < j) return;
+  const int ti = j / kI8Tile, tj = l / kI8Tile;
+  const int tile = ti * J.nt - ti * (ti - 1) / 2 + (tj - ti);
+  const int64_t e = (int64_t)tile * (kI8Tile * kI8Tile) + (j % kI8Tile) * kI8Tile + (l % kI8Tile);
+  const int64_t tstride = (int64_t)J.n_tiles * (kI8Tile * kI8Tile);
+  int v[kI8MaxMod];
+#pragma unroll
+  for (int k = 0; k < kI8MaxMod; ++k) {
+    if (k < J.M.n_mod) {
+      const int pk = J.M.ip[k];
+      int x = bal_mod(J.Gt[k * tstride + e], pk);
+#pragma unroll
+      for (int m = 0; m < kI8MaxMod; ++m)
+        if (m < k) x = bal_mod((x - v[m]) * J.M.cinv[m][k], pk);
+      v[k] = x;
+    }
+  }
+  double X = 0.0;
+#pragma unroll
+  for (int k = kI8MaxMod - 1; k >= 0; --k)
+    if (k < J.M.n_mod) X = fma(X, J.M.p[k], (double)v[k]);
+  double gv = X * J.scale[j] * J.scale[l];
+  if (j == l) gv += J.diag_add;
+  J.G[(int64_t)j * J.n + l] = gv;
+  if (J.mirror && j != l) J.G[(int64_t)l * J.n + j] = gv;
+}
+
+// ------------------------------------------------------------------ launchers
+hipError_t launch_i8_scale(const double* amp, int n_blocks, int n, const double* rho, int64_t P, double* rho_max,
+                           int B, double* inv_scale, double* scale, hipStream_t s) {
+  if (rho) hipLaunchKernelGGL(k_absmax, dim3(1), dim3(1024), 0, s, rho, P, rho_max);
+  hipLaunchKernelGGL(k_i8_scale, dim3((n + 255) / 256), dim3(256), 0, s, amp, n_blocks, n,
+                     rho ? (const double*)rho_max : nullptr, ldexp(1.0, B), inv_scale, scale);
+  return hipGetLastError();
+}
+
+hipError_t launch_i8_residues(const Geo& g, const double* rho, const double* inv_scale, const I8Moduli& M, int n_pad,
+                              int KB, int8_t* R, hipStream_t s) {
+  const dim3 grid(KB, n_pad / 64);
+  switch (g.d) {
+#define FLSQ_I8R(D) \
+  case D:           \
+    hipLaunchKernelGGL(k_i8_residues<D>, grid, dim3(256), 0, s, g, rho, inv_scale, M, n_pad, KB, R); break;
+    FLSQ_I8R(1) FLSQ_I8R(2) FLSQ_I8R(3) FLSQ_I8R(4) FLSQ_I8R(5) FLSQ_I8R(6) FLSQ_I8R(7) FLSQ_I8R(8)
+#undef FLSQ_I8R
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+size_t i8_gemm_lds_bytes() { return (size_t)2 * 2 * kI8Tile * kI8Pitch; }
+
+hipError_t launch_gram_i8(const I8GemmJob& J, hipStream_t s) {
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_gram_i8, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)i8_gemm_lds_bytes());
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(k_gram_i8, dim3(J.n_tiles * J.n_mod), dim3(256), i8_gemm_lds_bytes(), s, J);
+  return hipGetLastError();
+}
+
+hipError_t launch_i8_crt(const I8CrtJob& J, hipStream_t s) {
+  hipLaunchKernelGGL(k_i8_crt, dim3((J.n + 255) / 256, J.n), dim3(256), 0, s, J);
+  return hipGetLastError();
+}
+
+int i8_tile() { return kI8Tile; }
+int i8_kblock() { return kI8Kb; }
+
+}  // namespace flsq

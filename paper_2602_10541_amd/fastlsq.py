@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libfastlsq.so")
 FLSQ_OK, FLSQ_EINVAL, FLSQ_ENOTSPD, FLSQ_ENOCONV, FLSQ_EHIP, FLSQ_ENOMEM, FLSQ_ENONFINITE = range(7)
 STATUS_NAMES = {0: "FLSQ_OK", 1: "FLSQ_EINVAL", 2: "FLSQ_ENOTSPD", 3: "FLSQ_ENOCONV", 4: "FLSQ_EHIP",
                 5: "FLSQ_ENOMEM", 6: "FLSQ_ENONFINITE"}
-PREC_FP64, PREC_FP32_REFINE, PREC_BF16X3_REFINE = 0, 1, 2
+PREC_FP64, PREC_FP32_REFINE, PREC_BF16X3_REFINE, PREC_INT8_CRT = 0, 1, 2, 3
 MAX_DIM = 8
 
 # Every symbol the header declares (checked by the CPU test suite).

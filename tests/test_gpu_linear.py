@@ -80,7 +80,7 @@ def test_sin_accuracy_wide_phase():
         assert err.max() <= tol, (fp32, err.max())
 
 
-@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("prec", [0, 1, 3])
 def test_gram_matches_oracle(prec):
     torch, fl = require_gpu()
     ctx = context()
@@ -94,7 +94,9 @@ def test_gram_matches_oracle(prec):
         Gref = A.T @ A
         Gg = G.cpu().numpy()
         err = np.linalg.norm(Gg - Gref) / np.linalg.norm(Gref)
-        bar = 1e-13 if prec == 0 else 2e-6
+        # INT8_CRT rounds each entry to >= 41 bits of its feature's amplitude bound (|delta| <=
+        # 2^-42 c_j); the Gram error is then a few 1e-13 of ||G||_F at most.
+        bar = {0: 1e-13, 1: 2e-6, 3: 5e-13}[prec]
         assert err <= bar, (prob.name, prec, err)
         np.testing.assert_allclose(Gg, Gg.T, rtol=0, atol=0)
         cref = A.T @ r
@@ -109,11 +111,12 @@ def _solve(dp, prob, prec=0, max_refine=10, tol=1e-12):
     return st, info, beta.cpu().numpy()
 
 
+@pytest.mark.parametrize("prec", [0, 3])
 @pytest.mark.parametrize("idx", [0, 1, 2])
-def test_solve_linear_small_matches_oracle(idx):
+def test_solve_linear_small_matches_oracle(idx, prec):
     prob = _small_problems()[idx]
     dp = _dev(prob)
-    st, info, beta = _solve(dp, prob)
+    st, info, beta = _solve(dp, prob, prec=prec, max_refine=30)
     ref = oracle.solve_linear(prob)
     zero = [tuple([0] * prob.d)]
     u = oracle.evaluate(prob.W, prob.b, beta, prob.x_test, zero)[:, 0]
@@ -125,25 +128,28 @@ def test_solve_linear_small_matches_oracle(idx):
     assert np.linalg.norm(g) <= 1e-8 * np.linalg.norm(A.T @ r)
 
 
-def test_solve_linear_poisson2d_full():
-    """2D Poisson, N = 500, 2000 + 400 rows, FP64 end to end."""
+@pytest.mark.parametrize("prec", [0, 3])
+def test_solve_linear_poisson2d_full(prec):
+    """2D Poisson, N = 500, 2000 + 400 rows: FP64 end to end, and the int8-CRT Gram."""
     prob = wl.config("poisson2d")
     dp = _dev(prob)
-    st, info, beta = _solve(dp, prob)
+    st, info, beta = _solve(dp, prob, prec=prec, max_refine=30)
     gold = np.load(os.path.join(GOLDEN, "poisson2d.npz"))
     u = oracle.evaluate(prob.W, prob.b, beta, prob.x_test, [(0, 0)])[:, 0]
     assert rel_l2(u, gold["u_test"]) <= 1e-7, (rel_l2(u, gold["u_test"]), info.as_dict())
     assert rel_l2(u, prob.u_test) <= 1e-6
 
 
-def test_solve_linear_poisson6d_full():
-    """6D Poisson at full size (N = 4096, 32768 + 8192 rows): FP64 path vs the oracle's stored solution."""
+@pytest.mark.parametrize("prec", [0, 3])
+def test_solve_linear_poisson6d_full(prec):
+    """6D Poisson at full size (N = 4096, 32768 + 8192 rows): FP64 and int8-CRT Gram paths vs the
+    oracle's stored solution."""
     path = os.path.join(GOLDEN, "poisson6d.npz")
     if not os.path.exists(path):
         pytest.skip("golden values not generated")
     prob = wl.config("poisson6d")
     dp = _dev(prob)
-    st, info, beta = _solve(dp, prob)
+    st, info, beta = _solve(dp, prob, prec=prec, max_refine=30)
     gold = np.load(path)
     u = oracle.evaluate(prob.W, prob.b, beta, prob.x_test, [tuple([0] * 6)])[:, 0]
     assert rel_l2(u, gold["u_test"]) <= 1e-7, (rel_l2(u, gold["u_test"]), info.as_dict())
@@ -252,3 +258,14 @@ def test_max_refine_limit_reports_noconv():
     beta = torch.empty(256, dtype=torch.float64, device="cuda")
     st, info = fl.flsq_solve_linear(ctx, dp.basis, dp.rows, fl.solve_opts(1e-10, 1, 1, 1e-30), beta, check=False)
     assert st == fl.FLSQ_ENOCONV and info.refine_iters == 1
+
+
+def test_int8_crt_rejects_too_many_rows():
+    """The int8 Gram needs exact int32 sums of 127^2-bounded products: at most 133 000 rows."""
+    torch, fl = require_gpu()
+    prob = wl.poisson(2, 64, 3.0, 140000, 1000, seed=9, name="big", n_test=10)
+    dp = _dev(prob)
+    ctx = context()
+    beta = torch.empty(prob.n_feat, dtype=torch.float64, device="cuda")
+    st, info = fl.flsq_solve_linear(ctx, dp.basis, dp.rows, fl.solve_opts(prob.mu, 3), beta, check=False)
+    assert st == fl.FLSQ_EINVAL and "133000" in ctx.last_error()
