@@ -3,12 +3,13 @@
 Workload: -Laplace u = f on [0,1]^6, u = prod_k sin(pi x_k), N = 4096 features with
 W ~ N(0, 2^2 I), b ~ U[0, 2 pi), 32768 interior + 8192 boundary rows (Dirichlet rows
 weighted by 100), Tikhonov mu = 1e-10; all inputs seeded and synthetic, resident
-in HBM before the timed region.  One step = one full solve (operator folding,
-fused assembly + Gram, Cholesky, refinement) to beta on the device.
+in HBM before the timed region.  One step = one full solve (operator folding, Gram,
+Cholesky, refinement) to beta on the device.
 
-Prints one JSON line.  The value is FP64-path solves/s (the path that meets the
-1e-7 bar against the oracle); the FP32-MFMA path is timed beside it with the
-error it reaches.
+Prints one JSON line.  The value is the solves/s of the mixed-precision path (int8
+matrix-core Gram of exact residues + FP64 Cholesky and refinement), which meets the
+1e-7 bar against the FP64 oracle; the all-FP64 GPU path and the FP32-MFMA
+preconditioned path are timed beside it, each with the error it reaches.
 """
 from __future__ import annotations
 
@@ -27,11 +28,18 @@ sys.path.insert(0, ROOT)
 METRIC = "assembled entries/s + solves/s at stated L2 error, FP32-MFMA+refine vs FP64"
 PEAK_FP64_MFMA_TFLOPS = 78.6
 PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_INT8_MFMA_TOPS = 5000.0
+N_MODULI = 13
 
 
 def gram_flops(P, N):
     """Algorithmic flops of the upper-triangle Gram product, diagonal included: 2 P N (N + 1) / 2."""
     return float(P) * N * (N + 1)
+
+
+def int8_gram_ops(P, N):
+    """Algorithmic int8 operations of the residue Gram: per modulus the upper triangle, 2 P N (N + 1) / 2."""
+    return float(N_MODULI) * P * N * (N + 1)
 
 
 def householder_flops(m, n):
@@ -65,6 +73,29 @@ def cpu_baseline(prob, rows_int=12288, rows_bc=3072):
     }
 
 
+def time_path(fl, ctx, dp, prob, prec, steps, warmup, max_refine, xq):
+    """Solves/s of one precision path plus its phase times, from `steps` back-to-back solves."""
+    import torch
+    beta = torch.empty(prob.n_feat, dtype=torch.float64, device="cuda")
+    opts = fl.solve_opts(prob.mu, prec, max_refine, 1e-12)
+    for _ in range(warmup):
+        fl.flsq_solve_linear(ctx, dp.basis, dp.rows, opts, beta)
+    torch.cuda.synchronize()
+    infos = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        st, info = fl.flsq_solve_linear(ctx, dp.basis, dp.rows, opts, beta)
+        infos.append(info.as_dict())
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    u = torch.empty((xq.shape[0], 1), dtype=torch.float64, device="cuda")
+    fl.flsq_evaluate(ctx, dp.basis, beta, xq, [tuple([0] * prob.d)], u)
+    phases = {k: float(np.mean([i[k] for i in infos])) for k in
+              ("t_gram_kernel_ms", "t_gram_ms", "t_chol_ms", "t_refine_ms", "t_total_ms")}
+    return {"dt": dt, "steps": steps, "status": int(st), "u": u[:, 0].cpu().numpy(), "phases_ms": phases,
+            "refine_iters": int(infos[-1]["refine_iters"]), "shift": float(infos[-1]["shift"])}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -72,7 +103,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-fp32", action="store_true")
-    ap.add_argument("--max-refine", type=int, default=10)
+    ap.add_argument("--skip-fp64", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
@@ -87,26 +118,7 @@ def main():
     ctx = fl.Context(0)
     dp = fl.DeviceProblem(prob)
     xq = torch.tensor(prob.x_test, dtype=torch.float64, device="cuda")
-    beta = torch.empty(N, dtype=torch.float64, device="cuda")
     torch.cuda.synchronize()
-
-    def run(prec, steps, warmup, max_refine):
-        opts = fl.solve_opts(prob.mu, prec, max_refine, 1e-12)
-        for _ in range(warmup):
-            fl.flsq_solve_linear(ctx, dp.basis, dp.rows, opts, beta)
-        torch.cuda.synchronize()
-        infos = []
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            st, info = fl.flsq_solve_linear(ctx, dp.basis, dp.rows, opts, beta)
-            infos.append(info.as_dict())
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        u = torch.empty((xq.shape[0], 1), dtype=torch.float64, device="cuda")
-        fl.flsq_evaluate(ctx, dp.basis, beta, xq, [tuple([0] * prob.d)], u)
-        return dt, infos, u[:, 0].cpu().numpy(), st
-
-    dt64, inf64, u64, st64 = run(fl.PREC_FP64, args.steps, args.warmup, args.max_refine)
     gold_path = os.path.join(ROOT, "tests", "golden", "poisson6d.npz")
     gold = np.load(gold_path) if os.path.exists(gold_path) else None
 
@@ -116,45 +128,61 @@ def main():
             e["rel_l2_vs_oracle"] = float(np.linalg.norm(u - gold["u_test"]) / np.linalg.norm(gold["u_test"]))
         return e
 
-    k64 = float(np.mean([i["t_gram_kernel_ms"] for i in inf64]))
-    flops = gram_flops(P, N)
-    achieved = flops / (k64 * 1e-3) / 1e12
+    mix = time_path(fl, ctx, dp, prob, fl.PREC_INT8_CRT, args.steps, args.warmup, 30, xq)
+    k8 = mix["phases_ms"]["t_gram_kernel_ms"]
+    ops8 = int8_gram_ops(P, N)
+    ach8 = ops8 / (k8 * 1e-3) / 1e12
     out = {
         "metric": METRIC,
-        "value": args.steps / dt64,
+        "value": mix["steps"] / mix["dt"],
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * dt64 / args.steps,
+        "ms_per_step": 1e3 * mix["dt"] / mix["steps"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "i8+f64",
         "data": "synthetic (seeded features, collocation points and manufactured solution)",
         "config": {"workload": "poisson_6d: -Laplace u = f on [0,1]^6, N=4096 sin features (sigma=2), "
                                "32768 interior + 8192 boundary rows, lambda_bc=100, mu=1e-10",
-                   "n_feat": N, "n_rows": P, "path": "FP64 Gram + FP64 Cholesky + CGLS refinement"},
-        "entries_per_s": P * N / (k64 * 1e-3),
-        "accuracy": err(u64),
-        "phases_ms": {k: float(np.mean([i[k] for i in inf64])) for k in
-                      ("t_gram_kernel_ms", "t_gram_ms", "t_chol_ms", "t_refine_ms", "t_total_ms")},
-        "refine_iters": int(inf64[-1]["refine_iters"]),
-        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_MFMA_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64_MFMA_TFLOPS, "traffic": None,
-                     "kernel": "k_gram_f64 (fused assembly + FP64 MFMA Gram)",
-                     "flops_per_launch": flops, "avg_kernel_ms": k64},
+                   "n_feat": N, "n_rows": P,
+                   "path": "int8-MFMA Gram of exact residues (13 moduli, CRT to FP64) + FP64 Cholesky + CGLS"},
+        "entries_per_s": P * N / (mix["phases_ms"]["t_gram_ms"] * 1e-3),
+        "accuracy": err(mix["u"]),
+        "status": mix["status"],
+        "phases_ms": mix["phases_ms"],
+        "refine_iters": mix["refine_iters"],
+        "roofline": {"bound": "mfma", "achieved": ach8, "peak": PEAK_INT8_MFMA_TOPS, "unit": "TOP/s",
+                     "frac": ach8 / PEAK_INT8_MFMA_TOPS, "traffic": None,
+                     "kernel": "k_gram_i8 (int8 MFMA residue Gram, 13 moduli)",
+                     "ops_per_launch": ops8, "avg_kernel_ms": k8},
     }
+    if not args.skip_fp64:
+        f64 = time_path(fl, ctx, dp, prob, fl.PREC_FP64, args.steps, args.warmup, 10, xq)
+        k64 = f64["phases_ms"]["t_gram_kernel_ms"]
+        flops = gram_flops(P, N)
+        a64 = flops / (k64 * 1e-3) / 1e12
+        out["fp64_path"] = {
+            "solves_per_s": f64["steps"] / f64["dt"], "status": f64["status"], "accuracy": err(f64["u"]),
+            "phases_ms": f64["phases_ms"], "refine_iters": f64["refine_iters"],
+            "entries_per_s": P * N / (f64["phases_ms"]["t_gram_ms"] * 1e-3),
+            "roofline": {"bound": "mfma", "achieved": a64, "peak": PEAK_FP64_MFMA_TFLOPS, "unit": "TFLOP/s",
+                         "frac": a64 / PEAK_FP64_MFMA_TFLOPS, "kernel": "k_gram_f64 (fused assembly + FP64 MFMA Gram)",
+                         "flops_per_launch": flops, "avg_kernel_ms": k64},
+        }
+        out["speedup_vs_fp64_path"] = out["value"] / out["fp64_path"]["solves_per_s"]
     if not args.skip_fp32:
-        dt32, inf32, u32, st32 = run(fl.PREC_FP32_REFINE, max(1, args.steps // 2), 1, 30)
-        k32 = float(np.mean([i["t_gram_kernel_ms"] for i in inf32]))
-        a32 = flops / (k32 * 1e-3) / 1e12
+        n32 = max(1, args.steps // 2)
+        f32 = time_path(fl, ctx, dp, prob, fl.PREC_FP32_REFINE, n32, 1, 30, xq)
+        k32 = f32["phases_ms"]["t_gram_kernel_ms"]
+        a32 = gram_flops(P, N) / (k32 * 1e-3) / 1e12
         out["fp32_mfma_path"] = {
-            "solves_per_s": max(1, args.steps // 2) / dt32, "status": int(st32),
-            "refine_iters": int(inf32[-1]["refine_iters"]), "accuracy": err(u32),
-            "entries_per_s": P * N / (k32 * 1e-3), "gram_kernel_ms": k32,
+            "solves_per_s": n32 / f32["dt"], "status": f32["status"], "accuracy": err(f32["u"]),
+            "refine_iters": f32["refine_iters"], "shift": f32["shift"], "phases_ms": f32["phases_ms"],
+            "entries_per_s": P * N / (f32["phases_ms"]["t_gram_ms"] * 1e-3),
             "gram_tflops": a32, "gram_frac_of_fp32_mfma_peak": a32 / PEAK_FP32_MFMA_TFLOPS,
-            "shift": inf32[-1]["shift"],
         }
     if not args.skip_cpu:
         out["cpu_baseline"] = cpu_baseline(prob)

@@ -382,6 +382,8 @@ const I8Moduli& i8_moduli() {
       m.ip[t] = list[t];
       m.p[t] = list[t];
       m.inv_p[t] = 1.0 / list[t];
+      m.pf[t] = (float)list[t];
+      m.inv_pf[t] = 1.0f / (float)list[t];
     }
     for (int a = 0; a < m.n_mod; ++a)
       for (int k = 0; k < m.n_mod; ++k) {
@@ -431,6 +433,14 @@ Err run_gram_i8(flsq_ctx* c, const System& s, const double* rho, double* G, int 
   CHECK_ERR(ws_get(c, "i8_scale", (size_t)n, &scale));
   CHECK_ERR(ws_get(c, "i8_rhomax", 1, &rho_max));
   const hipStream_t st = c->stream;
+  int2* order;
+  CHECK_ERR(ws_get(c, "i8_order", (size_t)n_tiles, &order));
+  {
+    std::vector<int2> h(n_tiles);
+    i8_tile_order(nt, h.data());
+    CHECK_HIP(hipMemcpyAsync(order, h.data(), sizeof(int2) * n_tiles, hipMemcpyHostToDevice, st));
+    CHECK_HIP(hipStreamSynchronize(st));
+  }
   CHECK_HIP(launch_i8_scale(s.amp.as<double>(), s.n_blocks, n, rho, s.P, rho_max, B, inv_scale, scale, st));
   CHECK_HIP(launch_i8_residues(s.geo(), rho, inv_scale, M, n_pad, KB, R, st));
   I8GemmJob J;
@@ -440,6 +450,7 @@ Err run_gram_i8(flsq_ctx* c, const System& s, const double* rho, double* G, int 
   J.nt = nt;
   J.n_tiles = n_tiles;
   J.n_mod = M.n_mod;
+  J.order = order;
   J.out = Gt;
   CHECK_HIP(hipEventRecord(c->ev0, st));
   CHECK_HIP(launch_gram_i8(J, st));

@@ -72,6 +72,8 @@ struct I8Moduli {
   int ip[kI8MaxMod];                 // odd, pairwise coprime, <= 255
   double p[kI8MaxMod];
   double inv_p[kI8MaxMod];
+  float pf[kI8MaxMod];
+  float inv_pf[kI8MaxMod];
   int cinv[kI8MaxMod][kI8MaxMod];    // cinv[m][k] = p_m^{-1} mod p_k for m < k
 };
 struct I8GemmJob {
@@ -80,8 +82,11 @@ struct I8GemmJob {
   int KB;              // 64-row K blocks (even)
   int nt, n_tiles;     // tiles per side, upper-triangle tiles
   int n_mod;
-  int32_t* out;        // [n_mod][n_tiles][256 * 256]
+  const int2* order;   // n_tiles (ti, tj) pairs: the order in which tiles are taken
+  int32_t* out;        // [n_mod][n_tiles][256 * 256], tile slot = row-major upper-triangle index
 };
+// 4 x 4 super-tile order of the upper-triangle tiles of an nt x nt tile grid.
+void i8_tile_order(int nt, int2* out);
 struct I8CrtJob {
   I8Moduli M;
   const int32_t* Gt;   // k_gram_i8 output

@@ -25,8 +25,6 @@ typedef int i32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int kI8Tile = 256;    // features per tile side
 constexpr int kI8Kb = 64;       // rows per K block of the residue layout
-constexpr int kI8Stage = 128;   // rows per LDS stage (two K blocks)
-constexpr int kI8Pitch = kI8Stage + 16;   // LDS bytes per feature row: 16-lane reads hit distinct banks
 
 // ------------------------------------------------------------------ scales
 // rho_max (nullable): device scalar max_i |rho_i|.
@@ -122,57 +120,79 @@ __global__ __launch_bounds__(256) void k_i8_residues(Geo g, const double* rho, c
 // Workgroup = one upper tile (ti <= tj) of one modulus, 4 waves in 2 x 2, each wave a
 // 128 x 128 quarter as 4 x 4 blocks of v_mfma_i32_32x32x32_i8.  Both operands are
 // residues of the same matrix with rows on the contraction axis, so a lane's 16 bytes
-// are 16 consecutive rows of one feature for the A and the B side alike.  Two LDS
-// stages of 128 rows; the next stage is fetched into registers while the current one
-// feeds the matrix cores.
-__device__ __forceinline__ void i8_tile_coords(int t, int nt, int* ti, int* tj) {
-  int r = 0, rowlen = nt;
-  while (t >= rowlen) {
-    t -= rowlen;
-    ++r;
-    --rowlen;
-  }
-  *ti = r;
-  *tj = r + t;
+// are 16 consecutive rows of one feature for the A and the B side alike.
+//
+// Tiles are taken in the order of J.order (4 x 4 super-tiles, modulus-major), and
+// consecutive workgroup ids, which the hardware deals round-robin to the 8 XCDs, are
+// remapped so that each XCD works through a contiguous stretch of that order: the
+// workgroups resident on one XCD then share row and column panels in its L2.
+//
+// Pipeline: a ring of kI8Ring LDS slots, one 64-row K block each, filled by direct
+// global-to-LDS loads (no staging registers) up to kI8Ring - 1 blocks ahead of the
+// matrix cores.  Each wave waits for its own loads of a block with an explicit vmcnt and
+// a plain s_barrier then makes every wave's loads visible.  A slot is refilled only after
+// the barrier that follows the last reads of the block it held.  In a slot, panel p holds 256
+// features x 4 granules of 16 bytes (16 rows each); granule g of feature f sits at
+// position 4 f + (g ^ ((f >> 2) & 3)), so the 16-lane passes of the operand reads hit
+// distinct LDS banks.
+constexpr int kI8Ring = 4;
+constexpr int kI8Slot = 2 * kI8Tile * kI8Kb;     // bytes per ring slot (two panels)
+
+#define FLSQ_VMCNT(n) __builtin_amdgcn_s_waitcnt(((n) & 15) | (((n) >> 4) << 14) | (7 << 4) | (15 << 8))
+#define FLSQ_SBARRIER() asm volatile("s_barrier" ::: "memory")
+
+__device__ __forceinline__ int i8_swz(int f, int g) { return 4 * f + (g ^ ((f >> 2) & 3)); }
+
+__device__ __forceinline__ void i8_dma(unsigned char* smem, const int8_t* baseA, const int8_t* baseB,
+                                       int64_t kb_stride, int kb, int wave, int lane) {
+  unsigned char* slot = smem + (kb % kI8Ring) * kI8Slot;
+#pragma unroll
+  for (int panel = 0; panel < 2; ++panel)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      // one instruction of a wave fills 64 consecutive granules (1 KB) of the panel
+      const int p = (q * 4 + wave) * 64 + lane;
+      const int f = p >> 2, g = (p & 3) ^ ((f >> 2) & 3);
+      const int8_t* src = (panel ? baseB : baseA) + (int64_t)kb * kb_stride + f * kI8Kb + g * 16;
+      unsigned char* dst = slot + panel * (kI8Tile * kI8Kb) + (q * 4 + wave) * 1024;
+      __builtin_amdgcn_global_load_lds((const void*)src, (__attribute__((address_space(3))) void*)dst, 16, 0, 0);
+    }
+}
+
+// Operand fragments of one 32-row group (ks) of K block kb: 4 A and 4 B blocks.
+__device__ __forceinline__ void i8_frags(i32x4 (&av)[4], i32x4 (&bv)[4], const unsigned char* smem, int kb, int ks,
+                                         int wm, int wn, int lane) {
+  const unsigned char* pA = smem + (kb % kI8Ring) * kI8Slot;
+  const unsigned char* pB = pA + kI8Tile * kI8Kb;
+  const int g = 2 * ks + (lane >> 5);
+#pragma unroll
+  for (int a = 0; a < 4; ++a) av[a] = *(const i32x4*)(pA + 16 * i8_swz(wm * 128 + a * 32 + (lane & 31), g));
+#pragma unroll
+  for (int b = 0; b < 4; ++b) bv[b] = *(const i32x4*)(pB + 16 * i8_swz(wn * 128 + b * 32 + (lane & 31), g));
+}
+
+__device__ __forceinline__ void i8_mma16(i32x16 (&acc)[4][4], const i32x4 (&av)[4], const i32x4 (&bv)[4]) {
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(av[a], bv[b], acc[a][b], 0, 0, 0);
 }
 
 __global__ __launch_bounds__(256, 1) void k_gram_i8(I8GemmJob J) {
-  extern __shared__ __align__(16) unsigned char smem[];   // [2 stages][2 panels][256][kI8Pitch]
+  extern __shared__ __align__(16) unsigned char smem[];   // kI8Ring slots of kI8Slot bytes
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  // XCD-aware order: consecutive workgroup ids go to different XCDs, so give each XCD a
-  // contiguous range of (modulus-major) tiles, whose row panels it then shares in L2.
   const int total = J.n_tiles * J.n_mod;
   int wg = blockIdx.x;
   const int full = (total / 8) * 8;
   if (wg < full) wg = (wg % 8) * (total / 8) + wg / 8;
-  const int t = wg / J.n_tiles, tile = wg % J.n_tiles;
-  int ti, tj;
-  i8_tile_coords(tile, J.nt, &ti, &tj);
+  const int t = wg / J.n_tiles;
+  const int2 tc = J.order[wg % J.n_tiles];
+  const int ti = tc.x, tj = tc.y;
+  const int tile = ti * J.nt - ti * (ti - 1) / 2 + (tj - ti);   // row-major slot of (ti, tj)
   const int8_t* baseA = J.R + ((int64_t)t * J.KB * J.n_pad + (int64_t)ti * kI8Tile) * kI8Kb;
   const int8_t* baseB = J.R + ((int64_t)t * J.KB * J.n_pad + (int64_t)tj * kI8Tile) * kI8Kb;
   const int64_t kb_stride = (int64_t)J.n_pad * kI8Kb;
-
-  // stage loader: 2 panels x 2 K blocks x 16 KB = 64 KB, 16 x 16 B per thread
-  i32x4 stg[16];
-  auto fetch = [&](int s) {
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int panel = q >> 3, kbsub = (q >> 2) & 1, part = q & 3;
-      const int8_t* src = (panel ? baseB : baseA) + (int64_t)(2 * s + kbsub) * kb_stride + part * 4096 + tid * 16;
-      stg[q] = *(const i32x4*)src;
-    }
-  };
-  auto stash = [&](int buf) {
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int panel = q >> 3, kbsub = (q >> 2) & 1, part = q & 3;
-      const int o = part * 4096 + tid * 16;            // byte offset inside the 16 KB K block
-      const int f = o >> 6, byte = o & 63;
-      unsigned char* dst = smem + ((buf * 2 + panel) * kI8Tile + f) * kI8Pitch + kbsub * kI8Kb + byte;
-      *(i32x4*)dst = stg[q];
-    }
-  };
 
   i32x16 acc[4][4];
 #pragma unroll
@@ -182,31 +202,43 @@ __global__ __launch_bounds__(256, 1) void k_gram_i8(I8GemmJob J) {
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[a][b][v] = 0;
 
-  const int n_stage = J.KB / 2;
-  fetch(0);
-  stash(0);
-  __syncthreads();
-  for (int s = 0; s < n_stage; ++s) {
-    const int buf = s & 1;
-    if (s + 1 < n_stage) fetch(s + 1);
-    const unsigned char* pA = smem + ((buf * 2 + 0) * kI8Tile) * kI8Pitch;
-    const unsigned char* pB = smem + ((buf * 2 + 1) * kI8Tile) * kI8Pitch;
+  const int nkb = J.KB;
 #pragma unroll
-    for (int ks = 0; ks < kI8Stage / 32; ++ks) {
-      const int off = ks * 32 + 16 * (lane >> 5);
-      i32x4 av[4], bv[4];
-#pragma unroll
-      for (int a = 0; a < 4; ++a) av[a] = *(const i32x4*)(pA + (wm * 128 + a * 32 + (lane & 31)) * kI8Pitch + off);
-#pragma unroll
-      for (int b = 0; b < 4; ++b) bv[b] = *(const i32x4*)(pB + (wn * 128 + b * 32 + (lane & 31)) * kI8Pitch + off);
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(av[a], bv[b], acc[a][b], 0, 0, 0);
+  for (int kb = 0; kb < kI8Ring - 1; ++kb)
+    if (kb < nkb) i8_dma(smem, baseA, baseB, kb_stride, kb, wave, lane);
+  // Wait until block kb has landed in LDS for every wave: each wave's own loads of it are
+  // done once at most those of the (up to two) later blocks already issued remain.
+  auto block_ready = [&](int kb) {
+    if (kb + 2 < nkb) {
+      FLSQ_VMCNT(16);
+    } else if (kb + 1 < nkb) {
+      FLSQ_VMCNT(8);
+    } else {
+      FLSQ_VMCNT(0);
     }
-    if (s + 1 < n_stage) stash(buf ^ 1);
-    __syncthreads();
+    FLSQ_SBARRIER();
+  };
+  i32x4 a0[4], b0[4], a1[4], b1[4];
+  block_ready(0);
+  if (kI8Ring - 1 < nkb) i8_dma(smem, baseA, baseB, kb_stride, kI8Ring - 1, wave, lane);
+  i8_frags(a0, b0, smem, 0, 0, wm, wn, lane);
+  // Per block: the second group's fragments load under the first group's products; the
+  // next block's barrier, its refill of the slot freed by the previous block, and its
+  // first fragments happen under the second group's products.
+  // (the last block is peeled off so that the loop body has no join between the loads of
+  // the next block's fragments and their use: the LDS counter then waits for exactly the
+  // fragments each group needs)
+  for (int kb = 0; kb + 1 < nkb; ++kb) {
+    i8_frags(a1, b1, smem, kb, 1, wm, wn, lane);
+    i8_mma16(acc, a0, b0);
+    block_ready(kb + 1);
+    if (kb + kI8Ring < nkb) i8_dma(smem, baseA, baseB, kb_stride, kb + kI8Ring, wave, lane);
+    i8_frags(a0, b0, smem, kb + 1, 0, wm, wn, lane);
+    i8_mma16(acc, a1, b1);
   }
+  i8_frags(a1, b1, smem, nkb - 1, 1, wm, wn, lane);
+  i8_mma16(acc, a0, b0);
+  i8_mma16(acc, a1, b1);
   // 32 x 32 block layout: slot v is row 8 (v / 4) + 4 (lane / 32) + v % 4, column lane % 32
   int32_t* out = J.out + ((int64_t)t * J.n_tiles + tile) * (kI8Tile * kI8Tile);
 #pragma unroll
@@ -222,12 +254,16 @@ __global__ __launch_bounds__(256, 1) void k_gram_i8(I8GemmJob J) {
 }
 
 // ------------------------------------------------------------------ reconstruction
-__device__ __forceinline__ int bal_mod(int x, int p) {
-  int r = x % p;                       // (-p, p)
-  const int h = (p - 1) >> 1;
-  if (r > h) r -= p;
-  if (r < -h) r += p;
-  return r;
+// Balanced remainders r = x - p rint(x / p) in [-(p-1)/2, (p-1)/2] (p odd): x / p is never a
+// half-integer, and the rounded quotient lies within far less than 1/(2p) of the exact
+// one, so rint is exact; the remainder is then exact in the format (|x| < 2^24 for FP32).
+__device__ __forceinline__ int bal_mod_f32(int x, float p, float ip) {
+  const float fx = (float)x;
+  return (int)fmaf(-p, rintf(fx * ip), fx);
+}
+__device__ __forceinline__ int bal_mod_f64(int x, double p, double ip) {
+  const double fx = (double)x;
+  return (int)fma(-p, rint(fx * ip), fx);
 }
 
 // One thread per upper-triangle entry (j <= l) of G (n x n row-major): balanced Garner
@@ -245,11 +281,12 @@ __global__ void k_i8_crt(I8CrtJob J) {
 #pragma unroll
   for (int k = 0; k < kI8MaxMod; ++k) {
     if (k < J.M.n_mod) {
-      const int pk = J.M.ip[k];
-      int x = bal_mod(J.Gt[k * tstride + e], pk);
+      const float pk = J.M.pf[k], ipk = J.M.inv_pf[k];
+      // |sum| < 2^31: the first reduction in FP64, the digit recurrence (|x| < 2^16) in FP32
+      int x = bal_mod_f64(J.Gt[k * tstride + e], J.M.p[k], J.M.inv_p[k]);
 #pragma unroll
       for (int m = 0; m < kI8MaxMod; ++m)
-        if (m < k) x = bal_mod((x - v[m]) * J.M.cinv[m][k], pk);
+        if (m < k) x = bal_mod_f32((x - v[m]) * J.M.cinv[m][k], pk, ipk);
       v[k] = x;
     }
   }
@@ -287,7 +324,7 @@ hipError_t launch_i8_residues(const Geo& g, const double* rho, const double* inv
   return hipGetLastError();
 }
 
-size_t i8_gemm_lds_bytes() { return (size_t)2 * 2 * kI8Tile * kI8Pitch; }
+size_t i8_gemm_lds_bytes() { return (size_t)kI8Ring * kI8Slot; }
 
 hipError_t launch_gram_i8(const I8GemmJob& J, hipStream_t s) {
   static bool attr_set = false;
@@ -304,6 +341,15 @@ hipError_t launch_gram_i8(const I8GemmJob& J, hipStream_t s) {
 hipError_t launch_i8_crt(const I8CrtJob& J, hipStream_t s) {
   hipLaunchKernelGGL(k_i8_crt, dim3((J.n + 255) / 256, J.n), dim3(256), 0, s, J);
   return hipGetLastError();
+}
+
+void i8_tile_order(int nt, int2* out) {
+  int k = 0;
+  for (int si = 0; si < nt; si += 4)
+    for (int sj = si; sj < nt; sj += 4)
+      for (int ti = si; ti < si + 4 && ti < nt; ++ti)
+        for (int tj = sj; tj < sj + 4 && tj < nt; ++tj)
+          if (ti <= tj) out[k++] = make_int2(ti, tj);
 }
 
 int i8_tile() { return kI8Tile; }
