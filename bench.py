@@ -42,6 +42,21 @@ def int8_gram_ops(P, N):
     return float(N_MODULI) * P * N * (N + 1)
 
 
+def measured_traffic(profile_md, kernel_src):
+    """HBM bytes per launch from a committed counter summary, or None once the kernel source
+    differs from the one the counters were taken on."""
+    import hashlib
+    try:
+        text = open(os.path.join(ROOT, profile_md)).read()
+        src = open(os.path.join(ROOT, kernel_src), "rb").read()
+    except OSError:
+        return None
+    fields = dict(line.strip().split(": ", 1) for line in text.splitlines() if line.startswith("    ") and ": " in line)
+    if fields.get("source_sha256") != hashlib.sha256(src).hexdigest():
+        return None
+    return float(fields["traffic_bytes_per_launch"])
+
+
 def householder_flops(m, n):
     return 2.0 * m * n * n - 2.0 * n ** 3 / 3.0
 
@@ -104,12 +119,24 @@ def main():
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-fp32", action="store_true")
     ap.add_argument("--skip-fp64", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device-to-device copy of BYTES (HBM-counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
     import torch
+    if args.copy_probe:
+        # reference kernel of known traffic: reads and writes exactly BYTES each, 3 times
+        src = torch.empty(args.copy_probe // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": args.copy_probe}), flush=True)
+        return
     from paper_2602_10541_amd import fastlsq as fl
     from paper_2602_10541_amd import workloads as wl
 
@@ -155,7 +182,11 @@ def main():
         "phases_ms": mix["phases_ms"],
         "refine_iters": mix["refine_iters"],
         "roofline": {"bound": "mfma", "achieved": ach8, "peak": PEAK_INT8_MFMA_TOPS, "unit": "TOP/s",
-                     "frac": ach8 / PEAK_INT8_MFMA_TOPS, "traffic": None,
+                     "frac": ach8 / PEAK_INT8_MFMA_TOPS,
+                     "traffic": measured_traffic("profiles/k_gram_i8_poisson6d_hbm_traffic.md",
+                                                 "paper_2602_10541_amd/csrc/k_gram_i8.hip"),
+                     "traffic_source": "profiles/k_gram_i8_poisson6d_hbm_traffic.md (FETCH_SIZE + WRITE_SIZE, "
+                                       "copy-calibrated; null if the kernel changed since)",
                      "kernel": "k_gram_i8 (int8 MFMA residue Gram, 13 moduli)",
                      "ops_per_launch": ops8, "avg_kernel_ms": k8},
     }
