@@ -29,6 +29,8 @@ METRIC = "assembled entries/s + solves/s at stated L2 error, FP32-MFMA+refine vs
 PEAK_FP64_MFMA_TFLOPS = 78.6
 PEAK_FP32_MFMA_TFLOPS = 157.3
 PEAK_INT8_MFMA_TOPS = 5000.0
+PEAK_BF16_MFMA_TFLOPS = 2500.0
+PEAK_HBM_BYTES = 8.0e12
 N_MODULI = 13
 
 
@@ -111,6 +113,37 @@ def time_path(fl, ctx, dp, prob, prec, steps, warmup, max_refine, xq):
             "refine_iters": int(infos[-1]["refine_iters"]), "shift": float(infos[-1]["shift"])}
 
 
+def bench_evaluate(fl, ctx, reps=5):
+    """u, u_x, u_y, u_z, u_t at the 2^20 FP32 query points of the 3D + t heat workload (N = 8192,
+    sigma = (3, 3, 3, 1.5)); beta is a seeded stand-in (timing does not depend on its values)."""
+    import torch
+    from paper_2602_10541_amd import workloads as wl
+    prob = wl.config("heat4d")
+    Q, N = prob.extras["x_query"].shape[0], prob.n_feat
+    W = torch.tensor(prob.W, dtype=torch.float64, device="cuda")
+    b = torch.tensor(prob.b, dtype=torch.float64, device="cuda")
+    beta = torch.tensor(np.random.default_rng(0).normal(size=N), dtype=torch.float64, device="cuda")
+    xq = torch.tensor(prob.extras["x_query"], dtype=torch.float32, device="cuda")
+    alphas = [(0, 0, 0, 0), (1, 0, 0, 0), (0, 1, 0, 0), (0, 0, 1, 0), (0, 0, 0, 1)]
+    out = torch.empty((Q, len(alphas)), dtype=torch.float32, device="cuda")
+    basis = fl.make_basis(W, b)
+    fl.flsq_evaluate(ctx, basis, beta, xq, alphas, out)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fl.flsq_evaluate(ctx, basis, beta, xq, alphas, out)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    hbm = Q * (4 + len(alphas)) * 4.0
+    pairs = float(Q) * N
+    return {"workload": "heat_3d+t evaluate: N=8192, Q=1048576 FP32 points, outputs u,u_x,u_y,u_z,u_t",
+            "ms": ms, "points_per_s": Q / (ms * 1e-3), "pairs_per_s": pairs / (ms * 1e-3),
+            "hbm_bytes": hbm, "hbm_gb_s": hbm / (ms * 1e-3) / 1e9, "hbm_frac": hbm / (ms * 1e-3) / PEAK_HBM_BYTES,
+            "bound": "alu (one FP32 sincos + d + outputs FMAs per point-feature pair; not HBM)"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -119,6 +152,7 @@ def main():
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-fp32", action="store_true")
     ap.add_argument("--skip-fp64", action="store_true")
+    ap.add_argument("--skip-eval", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (HBM-counter calibration)")
     args = ap.parse_args()
@@ -215,6 +249,19 @@ def main():
             "entries_per_s": P * N / (f32["phases_ms"]["t_gram_ms"] * 1e-3),
             "gram_tflops": a32, "gram_frac_of_fp32_mfma_peak": a32 / PEAK_FP32_MFMA_TFLOPS,
         }
+    if not args.skip_fp32:
+        nb = max(1, args.steps // 2)
+        bf = time_path(fl, ctx, dp, prob, fl.PREC_BF16X3_REFINE, nb, 1, 30, xq)
+        kb = bf["phases_ms"]["t_gram_kernel_ms"]
+        out["bf16x3_path"] = {
+            "solves_per_s": nb / bf["dt"], "status": bf["status"], "accuracy": err(bf["u"]),
+            "refine_iters": bf["refine_iters"], "shift": bf["shift"], "phases_ms": bf["phases_ms"],
+            "entries_per_s": P * N / (bf["phases_ms"]["t_gram_ms"] * 1e-3),
+            "gram_fp32_equiv_tflops": gram_flops(P, N) / (kb * 1e-3) / 1e12,
+            "gram_bf16_frac_of_peak": 3 * gram_flops(P, N) / (kb * 1e-3) / 1e12 / PEAK_BF16_MFMA_TFLOPS,
+        }
+    if not args.skip_eval:
+        out["evaluate_c4"] = bench_evaluate(fl, ctx)
     if not args.skip_cpu:
         out["cpu_baseline"] = cpu_baseline(prob)
     print(json.dumps(out), flush=True)

@@ -490,7 +490,7 @@ Err run_gram(flsq_ctx* c, const System& s, int prec, const double* rho, double* 
   }
   GramLaunch L;
   L.g = s.geo();
-  L.prec = prec == FLSQ_PREC_FP64 ? 0 : 1;
+  L.prec = prec == FLSQ_PREC_FP64 ? 0 : (prec == FLSQ_PREC_FP32_REFINE ? 1 : 2);
   L.rho = rho;
   L.rho32 = rho32;
   L.chunks = s.chunks.as<Chunk>();
@@ -846,7 +846,6 @@ Err check_params(const SolveParams& p) {
   if (p.prec != FLSQ_PREC_FP64 && p.prec != FLSQ_PREC_FP32_REFINE && p.prec != FLSQ_PREC_BF16X3_REFINE &&
       p.prec != FLSQ_PREC_INT8_CRT)
     return fail(FLSQ_EINVAL, "unknown precision %d", p.prec);
-  if (p.prec == FLSQ_PREC_BF16X3_REFINE) return fail(FLSQ_EINVAL, "BF16x3 Gram is not available in this build");
   if (p.max_refine < 0 || p.max_refine > 100000) return fail(FLSQ_EINVAL, "max_refine out of range");
   if (!(p.refine_tol >= 0.0)) return fail(FLSQ_EINVAL, "refine_tol must be >= 0");
   if (!(p.shift_rel >= 0.0) || p.shift_rel > 1.0) return fail(FLSQ_EINVAL, "shift_rel must be in [0, 1]");

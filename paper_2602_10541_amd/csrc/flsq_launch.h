@@ -46,7 +46,7 @@ hipError_t launch_evaluate(const EvalArgs& a, hipStream_t s);
 // ---- fused Gram
 struct GramLaunch {
   Geo g;
-  int prec;                 // 0 fp64, 1 fp32
+  int prec;                 // 0 fp64, 1 fp32, 2 bf16x3
   const double* rho;
   const float* rho32;
   const Chunk* chunks;

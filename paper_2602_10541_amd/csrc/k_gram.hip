@@ -243,10 +243,148 @@ __global__ __launch_bounds__(kThreads, 2) void k_gram_f32(GramJob J) {
   }
 }
 
+// ------------------------------------------------------------------ BF16x3
+// Same decomposition as the FP32 kernel; each FP32 entry a is split into bf16 parts
+// hi = bf16(a), lo = bf16(a - hi) (round to nearest even; a - hi is exact in FP32), and
+// the Gram is accumulated in FP32 from three v_mfma_f32_32x32x16_bf16 products per block,
+// hi.hi + hi.lo + lo.hi (the dropped lo.lo term and the bf16 rounding of lo leave about
+// 2^-16 relative per product).  Slabs are stored feature-major, 8 consecutive rows of one
+// feature per 16-byte operand; a 16-byte pad per feature row keeps the operand reads of
+// 16 consecutive features on distinct LDS banks.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+constexpr int kBfPitch = kChunk + 8;   // bf16 elements per feature row (80 bytes)
+
+__device__ __forceinline__ unsigned bf16_bits_rne(float v) {
+  const unsigned u = __float_as_uint(v);
+  return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+
+template <int D>
+__global__ __launch_bounds__(kThreads, 2) void k_gram_bf16x3(GramJob J) {
+  __shared__ __align__(16) unsigned short sH[2][kTile][kBfPitch];
+  __shared__ __align__(16) unsigned short sL[2][kTile][kBfPitch];
+  __shared__ float sX[D][kChunk];
+  __shared__ float sRho[kChunk];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int n = J.g.n;
+  const int64_t P = J.g.P;
+
+  int64_t u = (int64_t)blockIdx.x * J.units_per_wg;
+  const int64_t u_end = min(u + J.units_per_wg, J.total_units);
+  int seg = 0;
+  while (u < u_end) {
+    const int tile = (int)(u / J.n_chunks);
+    const int c0 = (int)(u % J.n_chunks);
+    const int c1 = (int)min((int64_t)J.n_chunks, (int64_t)c0 + (u_end - u));
+    int ti, tj;
+    tile_coords(tile, J.nt, &ti, &tj);
+    const bool diag = (ti == tj);
+    const int fl = tid % kTile;
+    const int set = tid / kTile;
+    const int f = (diag || set == 0) ? ti * kTile + fl : tj * kTile + fl;
+    const bool fvalid = f < n;
+    float w[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) w[k] = fvalid ? J.g.Wt32[(int64_t)k * n + f] : 0.f;
+
+    f32x16 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[a][b][v] = 0.f;
+
+    for (int c = c0; c < c1; ++c) {
+      const Chunk ch = J.chunks[c];
+      __syncthreads();
+      for (int e = tid; e < D * kChunk; e += kThreads) {
+        const int k = e / kChunk, r = e % kChunk;
+        sX[k][r] = (r < ch.nrows) ? J.g.Xt32[(int64_t)k * P + ch.row0 + r] : 0.f;
+      }
+      if (tid < kChunk) sRho[tid] = (J.rho32 && tid < ch.nrows) ? J.rho32[ch.row0 + tid] : 0.f;
+      __syncthreads();
+      const float amp = fvalid ? J.g.amp32[(int64_t)ch.block * n + f] : 0.f;
+      const float ph = fvalid ? J.g.ph32[(int64_t)ch.block * n + f] : 0.f;
+      const int r_begin = diag ? set * (kChunk / 2) : 0;
+      const int r_count = diag ? kChunk / 2 : kChunk;
+      const int dst = diag ? 0 : set;
+      for (int r8 = 0; r8 < r_count; r8 += 8) {
+        unsigned hw[4], lw[4];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int r = r_begin + r8 + q;
+          float z = 0.f;
+#pragma unroll
+          for (int k = 0; k < D; ++k) z = fmaf(w[k], sX[k][r], z);
+          const float v = (r < ch.nrows) ? (amp + sRho[r]) * sin_f32(z + ph) : 0.f;
+          const unsigned hb = bf16_bits_rne(v);
+          const unsigned lb = bf16_bits_rne(v - __uint_as_float(hb << 16));
+          if (q & 1) {
+            hw[q >> 1] |= hb << 16;
+            lw[q >> 1] |= lb << 16;
+          } else {
+            hw[q >> 1] = hb;
+            lw[q >> 1] = lb;
+          }
+        }
+        *(u32x4*)&sH[dst][fl][r_begin + r8] = u32x4{hw[0], hw[1], hw[2], hw[3]};
+        *(u32x4*)&sL[dst][fl][r_begin + r8] = u32x4{lw[0], lw[1], lw[2], lw[3]};
+      }
+      __syncthreads();
+      const int lset = diag ? 0 : 1;
+#pragma unroll
+      for (int ks = 0; ks < kChunk / 16; ++ks) {
+        const int k0 = ks * 16 + 8 * (lane >> 5);
+        bf16x8 ah[2], al[2], bh[2], bl[2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+          const int fa = wm * 64 + a * 32 + (lane & 31);
+          ah[a] = *(const bf16x8*)&sH[0][fa][k0];
+          al[a] = *(const bf16x8*)&sL[0][fa][k0];
+        }
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          const int fb = wn * 64 + b * 32 + (lane & 31);
+          bh[b] = *(const bf16x8*)&sH[lset][fb][k0];
+          bl[b] = *(const bf16x8*)&sL[lset][fb][k0];
+        }
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b) {
+            acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bh[b], acc[a][b], 0, 0, 0);
+            acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bl[b], acc[a][b], 0, 0, 0);
+            acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[a], bh[b], acc[a][b], 0, 0, 0);
+          }
+      }
+    }
+    // slot v of a 32x32 block is row 8 (v / 4) + 4 (lane / 32) + v % 4, column lane % 32
+    float* out = (float*)J.partial + ((int64_t)blockIdx.x * J.max_seg + seg) * (kTile * kTile);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int row = wm * 64 + a * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+          const int col = wn * 64 + b * 32 + (lane & 31);
+          out[row * kTile + col] = acc[a][b][v];
+        }
+    ++seg;
+    u += (c1 - c0);
+  }
+}
+
 // ------------------------------------------------------------------ reduction
 // For tile t, sum its partial slots (listed in slot_ptr / slots, in workgroup order)
-// in FP64 and store the upper-triangle tile into G (row-major n x n, lda = n).  With
-// `mirror`, the transposed tile is stored into the lower triangle too.
+// in FP64 and store the upper triangle of G (row-major n x n, lda = n).  With `mirror`,
+// the lower triangle receives the transpose of the upper one (exactly symmetric G).
 template <typename T>
 __global__ __launch_bounds__(256) void k_gram_reduce(const T* partial, const int32_t* slot_ptr,
                                                      const int32_t* slots, int nt, int n, double* G,
@@ -265,18 +403,18 @@ __global__ __launch_bounds__(256) void k_gram_reduce(const T* partial, const int
       double s = 0.0;
       for (int q = s0; q < s1; ++q) s += (double)partial[(int64_t)slots[q] * (kTile * kTile) + (br + r) * kTile + bc + c];
       const int gi = ti * kTile + br + r, gj = tj * kTile + bc + c;
-      if (gi < n && gj < n) {
-        if (gi == gj) s += diag_add;
-        G[(int64_t)gi * n + gj] = s;
-      }
+      if (gi == gj) s += diag_add;
+      // in a diagonal tile only the upper triangle is taken (the kernels may round the two
+      // triangles differently); the lower one is its mirror
+      if (gi < n && gj < n && gj >= gi) G[(int64_t)gi * n + gj] = s;
       tr[r][c] = s;
     }
     __syncthreads();
-    if (mirror && ti != tj) {
+    if (mirror) {
       for (int e = tid; e < 32 * 32; e += 256) {
         const int r = e / 32, c = e % 32;   // store G[tj*T + bc + r][ti*T + br + c] = tile[br + c][bc + r]
         const int gi = tj * kTile + bc + r, gj = ti * kTile + br + c;
-        if (gi < n && gj < n) G[(int64_t)gi * n + gj] = tr[c][r];
+        if (gi < n && gj < n && gi > gj) G[(int64_t)gi * n + gj] = tr[c][r];
       }
     }
     __syncthreads();
@@ -322,17 +460,25 @@ hipError_t launch_gram(const GramLaunch& L, hipStream_t stream) {
       FLSQ_GRAM_CASE(7, k_gram_f64) FLSQ_GRAM_CASE(8, k_gram_f64)
       default: return hipErrorInvalidValue;
     }
-  } else {
+  } else if (L.prec == 1) {
     switch (L.g.d) {
       FLSQ_GRAM_CASE(1, k_gram_f32) FLSQ_GRAM_CASE(2, k_gram_f32) FLSQ_GRAM_CASE(3, k_gram_f32)
       FLSQ_GRAM_CASE(4, k_gram_f32) FLSQ_GRAM_CASE(5, k_gram_f32) FLSQ_GRAM_CASE(6, k_gram_f32)
       FLSQ_GRAM_CASE(7, k_gram_f32) FLSQ_GRAM_CASE(8, k_gram_f32)
       default: return hipErrorInvalidValue;
     }
+  } else {
+    switch (L.g.d) {
+      FLSQ_GRAM_CASE(1, k_gram_bf16x3) FLSQ_GRAM_CASE(2, k_gram_bf16x3) FLSQ_GRAM_CASE(3, k_gram_bf16x3)
+      FLSQ_GRAM_CASE(4, k_gram_bf16x3) FLSQ_GRAM_CASE(5, k_gram_bf16x3) FLSQ_GRAM_CASE(6, k_gram_bf16x3)
+      FLSQ_GRAM_CASE(7, k_gram_bf16x3) FLSQ_GRAM_CASE(8, k_gram_bf16x3)
+      default: return hipErrorInvalidValue;
+    }
   }
   return hipGetLastError();
 }
 
+// prec: 0 FP64 partials, otherwise FP32 partials
 hipError_t launch_gram_reduce(int prec, const void* partial, const int32_t* slot_ptr, const int32_t* slots,
                               int nt, int n, double* G, int mirror, double diag_add, hipStream_t stream) {
   const int n_tiles = nt * (nt + 1) / 2;

@@ -170,8 +170,10 @@ __global__ void k_eval_coef(int d, int n, int n_alpha, const double* __restrict_
     coef[(int64_t)a * n + j] = c;
     coef32[(int64_t)a * n + j] = (float)c;
   }
-  for (int k = 0; k < d; ++k) Wt32[(int64_t)k * n + j] = (float)Wt[(int64_t)k * n + j];
-  b32[j] = (float)b[j];
+  // the FP32 kernel works with the phase in revolutions: W / 2 pi and b / 2 pi, scaled in FP64
+  constexpr double kInv2Pi = 0.15915494309189533577;
+  for (int k = 0; k < d; ++k) Wt32[(int64_t)k * n + j] = (float)(Wt[(int64_t)k * n + j] * kInv2Pi);
+  b32[j] = (float)(b[j] * kInv2Pi);
 }
 
 constexpr int kEvalThreads = 256;
@@ -237,11 +239,92 @@ __global__ __launch_bounds__(kEvalThreads) void k_evaluate(int n, int n_alpha, i
   }
 }
 
+// FP32 evaluation.  The phase is formed in revolutions, z = (W / 2 pi) . x + b / 2 pi, reduced to
+// [-1/2, 1/2] and passed to the hardware sine and cosine (v_sin_f32 / v_cos_f32 take their
+// argument in revolutions), one of each per (point, feature) pair.  Outputs are visited with
+// the sine-type ones (even |alpha|) first, so each pair costs d + 2 multiply-adds for the phase
+// and reduction, two transcendental ops and one multiply-add per output.
+struct EvalOrder {
+  int n_sin;                 // outputs [0, n_sin) use sin z, the rest cos z
+  int perm[8];               // visiting slot -> output column (and coefficient row)
+};
+constexpr int kEvalPts32 = 4;
+
+template <int D, int NA>
+__global__ __launch_bounds__(kEvalThreads) void k_evaluate_f32(int n, int64_t n_q,
+                                                               const float* __restrict__ Wr,
+                                                               const float* __restrict__ br,
+                                                               const float* __restrict__ coef, EvalOrder ord,
+                                                               const float* __restrict__ xq,
+                                                               float* __restrict__ out) {
+  __shared__ float sF[kEvalFeat][D + 1 + NA];
+  const int64_t q0 = ((int64_t)blockIdx.x * kEvalThreads + threadIdx.x) * kEvalPts32;
+  float x[kEvalPts32][D];
+  float acc[kEvalPts32][NA];
+#pragma unroll
+  for (int p = 0; p < kEvalPts32; ++p) {
+    const int64_t q = q0 + p;
+#pragma unroll
+    for (int k = 0; k < D; ++k) x[p][k] = (q < n_q) ? xq[q * D + k] : 0.f;
+#pragma unroll
+    for (int a = 0; a < NA; ++a) acc[p][a] = 0.f;
+  }
+  for (int j0 = 0; j0 < n; j0 += kEvalFeat) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < kEvalFeat; e += kEvalThreads) {
+      const int j = j0 + e;
+      const bool ok = j < n;
+#pragma unroll
+      for (int k = 0; k < D; ++k) sF[e][k] = ok ? Wr[(int64_t)k * n + j] : 0.f;
+      sF[e][D] = ok ? br[j] : 0.f;
+#pragma unroll
+      for (int a = 0; a < NA; ++a) sF[e][D + 1 + a] = ok ? coef[(int64_t)ord.perm[a] * n + j] : 0.f;
+    }
+    __syncthreads();
+    const int jn = (n - j0 < kEvalFeat) ? n - j0 : kEvalFeat;
+    for (int jj = 0; jj < jn; ++jj) {
+#pragma unroll
+      for (int p = 0; p < kEvalPts32; ++p) {
+        float z = sF[jj][D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) z = fmaf(sF[jj][k], x[p][k], z);
+        z -= rintf(z);
+        const float sv = __builtin_amdgcn_sinf(z);
+        const float cv = __builtin_amdgcn_cosf(z);
+#pragma unroll
+        for (int a = 0; a < NA; ++a) acc[p][a] = fmaf(sF[jj][D + 1 + a], (a < ord.n_sin) ? sv : cv, acc[p][a]);
+      }
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < kEvalPts32; ++p) {
+    const int64_t q = q0 + p;
+    if (q < n_q)
+#pragma unroll
+      for (int a = 0; a < NA; ++a) out[q * NA + ord.perm[a]] = acc[p][a];
+  }
+}
+
+template <int D>
+hipError_t launch_evaluate_f32(const EvalArgs& a, const EvalOrder& ord, unsigned grid, hipStream_t s) {
+  switch (a.n_alpha) {
+#define FLSQ_EV32(NA)                                                                                       \
+  case NA:                                                                                                 \
+    hipLaunchKernelGGL((k_evaluate_f32<D, NA>), dim3(grid), dim3(kEvalThreads), 0, s, a.n, a.n_q, a.Wt32, a.b32, \
+                       a.coef32, ord, (const float*)a.xq, (float*)a.out);                                  \
+    break;
+    FLSQ_EV32(1) FLSQ_EV32(2) FLSQ_EV32(3) FLSQ_EV32(4) FLSQ_EV32(5) FLSQ_EV32(6) FLSQ_EV32(7) FLSQ_EV32(8)
+#undef FLSQ_EV32
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 #define FLSQ_EVAL_CASE(DIM)                                                                              \
   case DIM:                                                                                              \
     if (a.fp32)                                                                                          \
-      hipLaunchKernelGGL((k_evaluate<DIM, float>), dim3(grid), dim3(kEvalThreads), 0, s, a.n, a.n_alpha, \
-                         a.n_q, a.Wt32, a.b32, a.coef32, mask, (const float*)a.xq, (float*)a.out);       \
+      return launch_evaluate_f32<DIM>(a, ord, grid32, s);                                                \
     else                                                                                                 \
       hipLaunchKernelGGL((k_evaluate<DIM, double>), dim3(grid), dim3(kEvalThreads), 0, s, a.n, a.n_alpha, \
                          a.n_q, a.Wt, a.b, a.coef, mask, (const double*)a.xq, (double*)a.out);           \
@@ -253,8 +336,18 @@ hipError_t launch_evaluate(const EvalArgs& a, hipStream_t s) {
                      a.alphas, a.norm, a.coef, a.coef32, a.Wt32, a.b32);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || a.n_q == 0) return e;
+  EvalOrder ord{};
+  int k = 0;
+  for (int t = 0; t < a.n_alpha; ++t)
+    if (!((mask >> t) & 1u)) ord.perm[k++] = t;
+  ord.n_sin = k;
+  for (int t = 0; t < a.n_alpha; ++t)
+    if ((mask >> t) & 1u) ord.perm[k++] = t;
+  for (; k < 8; ++k) ord.perm[k] = 0;
   const int64_t pts_per_wg = (int64_t)kEvalThreads * kEvalPts;
   const unsigned grid = (unsigned)((a.n_q + pts_per_wg - 1) / pts_per_wg);
+  const int64_t pts_per_wg32 = (int64_t)kEvalThreads * kEvalPts32;
+  const unsigned grid32 = (unsigned)((a.n_q + pts_per_wg32 - 1) / pts_per_wg32);
   switch (a.d) {
     FLSQ_EVAL_CASE(1) FLSQ_EVAL_CASE(2) FLSQ_EVAL_CASE(3) FLSQ_EVAL_CASE(4)
     FLSQ_EVAL_CASE(5) FLSQ_EVAL_CASE(6) FLSQ_EVAL_CASE(7) FLSQ_EVAL_CASE(8)

@@ -1,0 +1,73 @@
+"""Heat equation in 3D + t at full size (N = 8192 features, 65536 interior + 16384 initial +
+16384 boundary rows): the int8-CRT and FP64 solves against the oracle's stored Householder-QR
+solution, and the FP32 evaluation of u, u_x, u_y, u_z, u_t at 1,048,576 query points, checked on a
+seeded sample of the points against the oracle's FP64 evaluation.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2602_10541_amd import workloads as wl
+from tests.gpu_util import context, rel_l2, require_gpu
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "heat4d.npz")
+ALPHAS = [(0, 0, 0, 0), (1, 0, 0, 0), (0, 1, 0, 0), (0, 0, 1, 0), (0, 0, 0, 1)]
+
+
+@pytest.fixture(scope="module")
+def c4():
+    if not os.path.exists(GOLDEN):
+        pytest.skip("golden values not generated")
+    torch, fl = require_gpu()
+    prob = wl.config("heat4d")
+    return prob, fl.DeviceProblem(prob), np.load(GOLDEN)
+
+
+@pytest.mark.parametrize("prec", [3, 0])
+def test_heat4d_solve_matches_oracle(c4, prec):
+    torch, fl = require_gpu()
+    prob, dp, gold = c4
+    ctx = context()
+    beta = torch.empty(prob.n_feat, dtype=torch.float64, device="cuda")
+    st, info = fl.flsq_solve_linear(ctx, dp.basis, dp.rows, fl.solve_opts(prob.mu, prec, 30, 1e-12), beta)
+    b = beta.cpu().numpy()
+    u = oracle.evaluate(prob.W, prob.b, b, prob.x_test, [ALPHAS[0]])[:, 0]
+    assert rel_l2(u, gold["u_test"]) <= 1e-7, (prec, rel_l2(u, gold["u_test"]), info.as_dict())
+    # the manufactured-solution error is the oracle's (recorded with the golden values)
+    assert abs(rel_l2(u, prob.u_test) - float(gold["err_exact"])) <= 1e-6
+
+
+def test_heat4d_evaluate_1m_points(c4):
+    """FP32 outputs at all 2^20 query points; every output of 4000 sampled points within 2e-5 of
+    norm * sum_j |beta_j| |W_j^alpha| (the FP32 rounding scale of a sum of N products) of the
+    oracle evaluated at the FP32-rounded points."""
+    torch, fl = require_gpu()
+    prob, dp, gold = c4
+    ctx = context()
+    xq = prob.extras["x_query"]
+    assert xq.shape == (1 << 20, 4)
+    beta = gold["beta"]
+    xt = torch.tensor(xq, dtype=torch.float32, device="cuda")
+    bt = torch.tensor(beta, dtype=torch.float64, device="cuda")
+    out = torch.empty((xq.shape[0], len(ALPHAS)), dtype=torch.float32, device="cuda")
+    fl.flsq_evaluate(ctx, dp.basis, bt, xt, ALPHAS, out)
+    got = out.double().cpu().numpy()
+    assert np.isfinite(got).all()
+    idx = np.random.default_rng(17).choice(xq.shape[0], 4000, replace=False)
+    xr = xq[idx].astype(np.float32).astype(np.float64)
+    ref = oracle.evaluate(prob.W, prob.b, beta, xr, ALPHAS)
+    for a, al in enumerate(ALPHAS):
+        mono = np.prod(np.abs(prob.W) ** np.array(al)[None, :], axis=1)
+        scale = np.sum(np.abs(beta) * mono) / math.sqrt(prob.n_feat)
+        e = np.abs(got[idx, a] - ref[:, a]).max() / scale
+        assert e <= 2e-5, (al, e)
+    # the FP64 variant at the test points reproduces the oracle's u to rounding
+    xd = torch.tensor(prob.x_test, dtype=torch.float64, device="cuda")
+    u64 = torch.empty((prob.x_test.shape[0], 1), dtype=torch.float64, device="cuda")
+    fl.flsq_evaluate(ctx, dp.basis, bt, xd, [ALPHAS[0]], u64)
+    scale0 = np.sum(np.abs(beta)) / math.sqrt(prob.n_feat)
+    assert np.abs(u64[:, 0].cpu().numpy() - gold["u_test"]).max() <= 1e-13 * scale0

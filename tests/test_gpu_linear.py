@@ -80,7 +80,7 @@ def test_sin_accuracy_wide_phase():
         assert err.max() <= tol, (fp32, err.max())
 
 
-@pytest.mark.parametrize("prec", [0, 1, 3])
+@pytest.mark.parametrize("prec", [0, 1, 2, 3])
 def test_gram_matches_oracle(prec):
     torch, fl = require_gpu()
     ctx = context()
@@ -96,7 +96,8 @@ def test_gram_matches_oracle(prec):
         err = np.linalg.norm(Gg - Gref) / np.linalg.norm(Gref)
         # INT8_CRT rounds each entry to >= 41 bits of its feature's amplitude bound (|delta| <=
         # 2^-42 c_j); the Gram error is then a few 1e-13 of ||G||_F at most.
-        bar = {0: 1e-13, 1: 2e-6, 3: 5e-13}[prec]
+        # BF16x3 keeps hi.hi + hi.lo + lo.hi of a 2 x 8-bit split: about 2^-16 per product.
+        bar = {0: 1e-13, 1: 2e-6, 2: 1e-4, 3: 5e-13}[prec]
         assert err <= bar, (prob.name, prec, err)
         np.testing.assert_allclose(Gg, Gg.T, rtol=0, atol=0)
         cref = A.T @ r
@@ -159,11 +160,12 @@ def test_solve_linear_poisson6d_full(prec):
     assert obj <= float(gold["objective"]) * (1 + 1e-9)
 
 
-def test_fp32_preconditioned_path_well_conditioned():
-    """FP32 Gram as a preconditioner reaches the FP64 answer on a well-conditioned 6D case."""
+@pytest.mark.parametrize("prec", [1, 2])
+def test_fp32_preconditioned_path_well_conditioned(prec):
+    """FP32 and BF16x3 Grams as preconditioners reach the FP64 answer on a well-conditioned 6D case."""
     prob = wl.poisson(6, 512, 2.0, 4000, 1000, seed=5, name="p6w", n_test=500)
     dp = _dev(prob)
-    st, info, beta = _solve(dp, prob, prec=1, max_refine=60, tol=1e-13)
+    st, info, beta = _solve(dp, prob, prec=prec, max_refine=80, tol=1e-13)
     ref = oracle.solve_linear(prob)
     u = oracle.evaluate(prob.W, prob.b, beta, prob.x_test, [tuple([0] * 6)])[:, 0]
     uref = oracle.evaluate(prob.W, prob.b, ref, prob.x_test, [tuple([0] * 6)])[:, 0]
