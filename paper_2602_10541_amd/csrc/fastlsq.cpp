@@ -548,6 +548,7 @@ Err cholesky_inv(flsq_ctx* c, double* G, double* X, int n, int* info_host) {
       d1.N = wr;
       d1.K = wr;
       d1.lda = d1.ldb = d1.ldc = n;
+      d1.tri = 1;   // X22 is upper triangular
       a.push_back(d1);
       GemmDesc d2;   // X(r0.., c0..) = -X(r0.., r0..) T
       d2.A = X + (int64_t)r0 * n + r0;
@@ -557,6 +558,7 @@ Err cholesky_inv(flsq_ctx* c, double* G, double* X, int n, int* info_host) {
       d2.N = wr;
       d2.K = wl;
       d2.lda = d2.ldb = d2.ldc = n;
+      d2.tri = 2;   // X11 is upper triangular
       b2.push_back(d2);
     }
     lvT.push_back(a);
@@ -585,8 +587,8 @@ Err cholesky_inv(flsq_ctx* c, double* G, double* X, int n, int* info_host) {
       maxM = std::max(maxM, d.M);
       maxN = std::max(maxN, d.N);
     }
-    CHECK_HIP(launch_gemm_batched(dd + offT[l], (int)lvT[l].size(), maxM, maxN, 1.0, 0.0, 0, st));
-    CHECK_HIP(launch_gemm_batched(dd + offX[l], (int)lvX[l].size(), maxM, maxN, -1.0, 0.0, 0, st));
+    CHECK_HIP(launch_gemm_tri(dd + offT[l], (int)lvT[l].size(), maxM, maxN, 1.0, st));
+    CHECK_HIP(launch_gemm_tri(dd + offX[l], (int)lvX[l].size(), maxM, maxN, -1.0, st));
   }
   CHECK_HIP(hipMemcpyAsync(info_host, info, sizeof(int), hipMemcpyDeviceToHost, st));
   CHECK_HIP(hipStreamSynchronize(st));
@@ -605,7 +607,7 @@ Err chol_solve(flsq_ctx* c, const double* X, int n, const double* Y, double* Z, 
   }
   double* tmp;
   CHECK_ERR(ws_get(c, "pa_tmpK", (size_t)n * K, &tmp));
-  GemmDesc h[2];
+  GemmDesc h[2] = {};
   h[0].A = X; h[0].B = Y; h[0].C = tmp; h[0].M = n; h[0].N = K; h[0].K = n; h[0].lda = n; h[0].ldb = K; h[0].ldc = K;
   h[1].A = X; h[1].B = tmp; h[1].C = Z; h[1].M = n; h[1].N = K; h[1].K = n; h[1].lda = n; h[1].ldb = K; h[1].ldc = K;
   GemmDesc* d;

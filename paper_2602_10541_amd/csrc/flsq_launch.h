@@ -151,9 +151,12 @@ struct GemmDesc {
   double* C;
   int M, N, K;
   int lda, ldb, ldc;
+  int tri;             // launch_gemm_tri only: 1 B upper triangular, 2 A upper triangular, 0 dense
 };
 hipError_t launch_gemm_batched(const GemmDesc* d_descs, int n_batch, int maxM, int maxN, double alpha, double beta,
                                int transA, hipStream_t s);
+// C = alpha A B with one upper-triangular operand (desc.tri), skipping its zero blocks.
+hipError_t launch_gemm_tri(const GemmDesc* d_descs, int n_batch, int maxM, int maxN, double alpha, hipStream_t s);
 // out = X (X^T v) for upper-triangular X (n x n); tmp n, work precond_work_elems(n).
 hipError_t launch_precond_apply(const double* X, int n, const double* v, double* tmp, double* work, double* out,
                                 hipStream_t s);

@@ -200,22 +200,50 @@ __device__ __forceinline__ void tri_coords(int t, int nt, int* ti, int* tj) {
 
 // Trailing update of the upper triangle G_ij -= sum_l U_{k0+l,i} U_{k0+l,j}, i <= j, over
 // rows and columns [k0 + kNb, n), in 128 x 128 tiles (ti <= tj), one workgroup per tile:
-// wave w computes the 64 x 64 quadrant (w / 2, w % 2) with FP64 MFMA 16x16x4, operands read
-// straight from the panel rows into the MFMA register layout.  Workgroup 0 owns tile (0, 0),
-// whose leading 64 x 64 quadrant is the next diagonal block: after its update the workgroup factors it.
+// wave w computes the 64 x 64 quadrant (w / 2, w % 2) with FP64 MFMA 16x16x4.
+//
+// Both 64 x 128 panel slices of the tile are fetched at once with direct global-to-LDS
+// loads (all in flight together), laid out in the order the matrix cores consume them: the
+// operand of k-step kk and 16-column block c is 64 consecutive doubles, lane l holding
+// panel row 4 kk + l / 16 and column 16 c + l % 16, so every operand read is one
+// contiguous, conflict-free 512-byte access.  Workgroup 0 owns tile (0, 0), whose leading 64 x 64 quadrant is the next
+// diagonal block: after its update the workgroup factors it, reusing the same LDS.
+constexpr int kSyrkPanel = 16 * 8 * 64;   // doubles per 64 x 128 panel slice
+
+__device__ __forceinline__ void syrk_fetch_panel(const double* G, int n, int k0, int c0, double* dst, int wave,
+                                                 int lane) {
+  // 256 instructions of 256 bytes (64 lanes x 4 bytes) per panel; instruction q fills doubles
+  // [32 q, 32 q + 32) of the operand-ordered slice, lane pairs moving the two halves of a
+  // double (4-byte pieces keep every source in bounds and aligned for any n).  Columns
+  // past n repeat column n - 1: their products are never stored.
+  for (int q = wave; q < kSyrkPanel / 32; q += 4) {
+    const int p = 32 * q + (lane >> 1);
+    const int blk = p >> 6, l = p & 63;              // operand block kk * 8 + c, MFMA lane l
+    const int kk = blk >> 3, c = blk & 7;
+    const int row = 4 * kk + (l >> 4), col = min(c0 + 16 * c + (l & 15), n - 1);
+    const char* src = (const char*)(G + (int64_t)(k0 + row) * n + col) + 4 * (lane & 1);
+    __builtin_amdgcn_global_load_lds((const void*)src, (__attribute__((address_space(3))) void*)(dst + 32 * q), 4, 0,
+                                     0);
+  }
+}
+
 __global__ __launch_bounds__(256, 1) void k_syrk_potrf(double* G, int n, int k0, int* info) {
-  __shared__ double S[kNb * kNb];
-  __shared__ int sbad;
+  extern __shared__ __align__(16) double smem_d[];     // A and B panels, then the factorisation scratch
   const int k1 = k0 + kNb;
   const int nt = (n - k1 + 127) / 128;
   int ti, tj;
   tri_coords(blockIdx.x, nt, &ti, &tj);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int qi = wave >> 1, qj = wave & 1;
+  double* sPa = smem_d;
+  double* sPb = (ti == tj) ? smem_d : smem_d + kSyrkPanel;
+  syrk_fetch_panel(G, n, k0, k1 + ti * 128, sPa, wave, lane);
+  if (ti != tj) syrk_fetch_panel(G, n, k0, k1 + tj * 128, sPb, wave, lane);
+  __builtin_amdgcn_s_waitcnt(0);   // this wave's loads have landed in LDS
+  __syncthreads();
   const int i0 = k1 + ti * 128 + qi * 64, j0 = k1 + tj * 128 + qj * 64;
   const bool active = !(ti == tj && qi > qj) && i0 < n && j0 < n;
   if (active) {
-    const double* panel = G + (int64_t)k0 * n;
     const int r16 = lane & 15, k4 = lane >> 4;
     f64x4 acc[4][4];
 #pragma unroll
@@ -224,19 +252,20 @@ __global__ __launch_bounds__(256, 1) void k_syrk_potrf(double* G, int n, int k0,
       for (int c = 0; c < 4; ++c) acc[r][c] = f64x4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll 4
     for (int kk = 0; kk < kNb / 4; ++kk) {
-      const double* prow = panel + (int64_t)(4 * kk + k4) * n;
       double a[4], b[4];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int ci = i0 + 16 * r + r16, cj = j0 + 16 * r + r16;
-        a[r] = (ci < n) ? prow[ci] : 0.0;
-        b[r] = (cj < n) ? prow[cj] : 0.0;
+        a[r] = sPa[(kk * 8 + qi * 4 + r) * 64 + lane];
+        b[r] = sPb[(kk * 8 + qj * 4 + r) * 64 + lane];
       }
 #pragma unroll
       for (int r = 0; r < 4; ++r)
 #pragma unroll
         for (int c = 0; c < 4; ++c) acc[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[r], b[c], acc[r][c], 0, 0, 0);
     }
+    // read all 64 old values first: interleaved loads and stores to G would be kept in
+    // program order (they may alias) and each load would wait out a full memory round trip
+    double old[4][4][4];
 #pragma unroll
     for (int r = 0; r < 4; ++r)
 #pragma unroll
@@ -245,12 +274,22 @@ __global__ __launch_bounds__(256, 1) void k_syrk_potrf(double* G, int n, int k0,
         for (int v = 0; v < 4; ++v) {
           const int i = i0 + 16 * r + 4 * v + k4;
           const int j = j0 + 16 * c + r16;
-          if (i < n && j < n && j >= i) G[(int64_t)i * n + j] -= acc[r][c][v];
+          old[r][c][v] = (i < n && j < n && j >= i) ? G[(int64_t)i * n + j] : 0.0;
+        }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = i0 + 16 * r + 4 * v + k4;
+          const int j = j0 + 16 * c + r16;
+          if (i < n && j < n && j >= i) G[(int64_t)i * n + j] = old[r][c][v] - acc[r][c][v];
         }
   }
   if (blockIdx.x == 0) {
-    __syncthreads();
-    potrf64_wg(G, n, k1, info, S, &sbad);
+    __syncthreads();   // tile (0, 0) stored; the panels are no longer read
+    potrf64_wg(G, n, k1, info, smem_d, (int*)(smem_d + kNb * kNb));
   }
 }
 
@@ -302,8 +341,15 @@ hipError_t launch_trsm_row(double* G, int n, int k0, hipStream_t s) {
 hipError_t launch_syrk_potrf(double* G, int n, int k0, int* info, hipStream_t s) {
   const int rem = n - k0 - kNb;
   if (rem <= 0) return hipSuccess;
+  const size_t lds = sizeof(double) * 2 * kSyrkPanel;   // 128 KB: two panel slices
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_syrk_potrf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
   const int nt = (rem + 127) / 128;
-  hipLaunchKernelGGL(k_syrk_potrf, dim3(nt * (nt + 1) / 2), dim3(256), 0, s, G, n, k0, info);
+  hipLaunchKernelGGL(k_syrk_potrf, dim3(nt * (nt + 1) / 2), dim3(256), lds, s, G, n, k0, info);
   return hipGetLastError();
 }
 

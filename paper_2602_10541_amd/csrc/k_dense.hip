@@ -87,6 +87,94 @@ hipError_t launch_gemm_batched(const GemmDesc* d_descs, int n_batch, int maxM, i
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ triangular-aware GEMM
+// C = alpha A B per descriptor (row-major, no transposes) for the explicit inverse factor,
+// where one operand is upper triangular: desc.tri = 1 means B[k][n] = 0 for k > n, so an
+// output tile with columns < n0 + 128 needs k < n0 + 128; desc.tri = 2 means A[m][k] = 0 for
+// k < m, so a tile with rows >= m0 needs k >= m0.  128 x 128 tiles, 4 waves in 2 x 2, each a
+// 64 x 64 quarter as 4 x 4 blocks of v_mfma_f64_16x16x4f64; 16-deep K slices staged in LDS,
+// the next slice fetched into registers while the current one is multiplied.
+constexpr int kTT = 128;
+constexpr int kTK = 16;
+
+__global__ __launch_bounds__(256) void k_gemm_tri(const GemmDesc* __restrict__ descs, double alpha) {
+  __shared__ double sA[kTK][kTT + 1];   // sA[k][m]
+  __shared__ double sB[kTK][kTT + 1];   // sB[k][n]
+  const GemmDesc D = descs[blockIdx.z];
+  const int m0 = blockIdx.y * kTT, n0 = blockIdx.x * kTT;
+  if (m0 >= D.M || n0 >= D.N) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  int kbeg = 0, kend = D.K;
+  if (D.tri == 1) kend = min(kend, n0 + kTT);
+  if (D.tri == 2) kbeg = (m0 / kTK) * kTK;
+  f64x4 acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+  // per slice each thread moves 8 entries of A (row m = e / 16, k = e % 16: 128-byte row pieces)
+  // and 8 of B (row k = e / 128, column n = e % 128)
+  double ra[8], rb[8];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int e = tid + 256 * q;
+      const int m = e / kTK, k = e % kTK;
+      const int gm = m0 + m, gk = k0 + k;
+      ra[q] = (gm < D.M && gk < kend) ? D.A[(int64_t)gm * D.lda + gk] : 0.0;
+      const int kb = e / kTT, nb = e % kTT;
+      const int gkb = k0 + kb, gn = n0 + nb;
+      rb[q] = (gkb < kend && gn < D.N) ? D.B[(int64_t)gkb * D.ldb + gn] : 0.0;
+    }
+  };
+  auto stash = [&]() {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int e = tid + 256 * q;
+      sA[e % kTK][e / kTK] = ra[q];
+      sB[e / kTT][e % kTT] = rb[q];
+    }
+  };
+  if (kbeg < kend) fetch(kbeg);
+  for (int k0 = kbeg; k0 < kend; k0 += kTK) {
+    __syncthreads();
+    stash();
+    __syncthreads();
+    if (k0 + kTK < kend) fetch(k0 + kTK);
+#pragma unroll
+    for (int kk = 0; kk < kTK / 4; ++kk) {
+      const int k = kk * 4 + (lane >> 4);
+      double av[4], bv[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) av[a] = sA[k][wm * 64 + a * 16 + (lane & 15)];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) bv[b] = sB[k][wn * 64 + b * 16 + (lane & 15)];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int gm = m0 + wm * 64 + a * 16 + 4 * v + (lane >> 4);
+        const int gn = n0 + wn * 64 + b * 16 + (lane & 15);
+        if (gm < D.M && gn < D.N) D.C[(int64_t)gm * D.ldc + gn] = alpha * acc[a][b][v];
+      }
+}
+
+hipError_t launch_gemm_tri(const GemmDesc* d_descs, int n_batch, int maxM, int maxN, double alpha, hipStream_t s) {
+  if (n_batch == 0 || maxM == 0 || maxN == 0) return hipSuccess;
+  dim3 grid((maxN + kTT - 1) / kTT, (maxM + kTT - 1) / kTT, n_batch);
+  hipLaunchKernelGGL(k_gemm_tri, grid, dim3(256), 0, s, d_descs, alpha);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ preconditioner application
 // y = X^T v  (X upper triangular, n x n row-major): y_j = sum_{i <= j} X[i][j] v_i.
 // Grid (column tiles, row splits): each thread owns a column, loops over its row range;
