@@ -144,6 +144,106 @@ def bench_evaluate(fl, ctx, reps=5):
             "bound": "alu (one FP32 sincos + d + outputs FMAs per point-feature pair; not HBM)"}
 
 
+def _gold(name):
+    path = os.path.join(ROOT, "tests", "golden", f"{name}.npz")
+    return np.load(path) if os.path.exists(path) else None
+
+
+def bench_c1(fl, ctx, steps=20):
+    """2D Poisson (N = 500, 2400 rows): latency-bound small solve, both exact-Gram paths."""
+    import torch
+    from paper_2602_10541_amd import workloads as wl
+    prob = wl.config("poisson2d")
+    dp = fl.DeviceProblem(prob)
+    xq = torch.tensor(prob.x_test, dtype=torch.float64, device="cuda")
+    gold = _gold("poisson2d")
+    res = {"workload": "poisson_2d: N=500 (sigma=3), 2000 interior + 400 boundary rows, mu=1e-10"}
+    for name, prec in (("int8_crt", fl.PREC_INT8_CRT), ("fp64", fl.PREC_FP64)):
+        r = time_path(fl, ctx, dp, prob, prec, steps, 3, 30, xq)
+        e = {"rel_l2_vs_exact": float(np.linalg.norm(r["u"] - prob.u_test) / np.linalg.norm(prob.u_test))}
+        if gold is not None:
+            e["rel_l2_vs_oracle"] = float(np.linalg.norm(r["u"] - gold["u_test"]) / np.linalg.norm(gold["u_test"]))
+        res[name] = {"us_per_solve": 1e6 * r["dt"] / r["steps"], "solves_per_s": r["steps"] / r["dt"],
+                     "accuracy": e, "refine_iters": r["refine_iters"]}
+    return res
+
+
+def bench_c3(fl, ctx):
+    """Reaction-diffusion -Laplace u + u^3 - u = f (N = 2048, 18432 rows): one full Gauss-Newton solve
+    (warm start + steps to |alpha delta| < 1e-10, at most 15) per Gram precision."""
+    import torch
+    from paper_2602_10541_amd import workloads as wl
+    prob = wl.config("reaction2d")
+    dp = fl.DeviceProblem(prob)
+    gold = _gold("reaction2d")
+    res = {"workload": "reaction_diffusion_2d: N=2048 (sigma=5), 16384 interior + 2048 boundary rows, <=15 steps"}
+    for name, prec in (("int8_crt", fl.PREC_INT8_CRT), ("fp64", fl.PREC_FP64)):
+        opts = fl.newton_opts(prob.mu, max_iter=15, tol_dbeta=1e-10, prec=prec)
+        beta = torch.zeros(prob.n_feat, dtype=torch.float64, device="cuda")
+        fl.flsq_solve_newton(ctx, dp.basis, dp.rows, prob.nonlin_block, prob.nonlin_poly, opts, beta)   # warm-up
+        beta.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, tr = fl.flsq_solve_newton(ctx, dp.basis, dp.rows, prob.nonlin_block, prob.nonlin_poly, opts, beta)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        steps = tr.as_list()
+        xq = torch.tensor(prob.x_test, dtype=torch.float64, device="cuda")
+        u = torch.empty((xq.shape[0], 1), dtype=torch.float64, device="cuda")
+        fl.flsq_evaluate(ctx, dp.basis, beta, xq, [(0, 0)], u)
+        u = u[:, 0].cpu().numpy()
+        e = {"rel_l2_vs_exact": float(np.linalg.norm(u - prob.u_test) / np.linalg.norm(prob.u_test))}
+        if gold is not None:
+            e["rel_l2_vs_oracle"] = float(np.linalg.norm(u - gold["u_test"]) / np.linalg.norm(gold["u_test"]))
+        res[name] = {"ms_total": 1e3 * dt, "newton_steps": len(steps), "ms_per_step": 1e3 * dt / max(1, len(steps) + 1),
+                     "final_res_norm": steps[-1]["res_norm"] if steps else None, "status": int(st), "accuracy": e}
+    return res
+
+
+def bench_c5(fl, ctx, reps=5):
+    """Inverse heat source (N = 2048, 12288 rows, 400 observations): factor once, then loss and
+    adjoint gradients for 64 source hypotheses per call (one Adam step's work)."""
+    import torch
+    from paper_2602_10541_amd import workloads as wl
+    from paper_2602_10541_amd.autograd import InverseProblem
+    prob = wl.config("inverse3d")
+    gold = _gold("inverse3d")
+    if gold is None:
+        return None
+    dp = fl.DeviceProblem(prob)
+    kappa, d = prob.extras["kappa"], prob.d
+    t_axis = tuple([0] * (d - 1) + [1])
+    interior = [(1.0, t_axis)] + [(-kappa, tuple(2 if i == k else 0 for i in range(d))) for k in range(d - 1)]
+    rows = dp.rows_with_terms([interior] + [bl.terms for bl in prob.blocks[1:]])
+    xo = torch.tensor(prob.extras["x_obs"], dtype=torch.float64, device="cuda")
+    dd = torch.tensor(gold["data"], dtype=torch.float64, device="cuda")
+    th = torch.tensor(prob.extras["theta0"], dtype=torch.float64, device="cuda")
+    res = {"workload": "inverse_heat_2d+t: N=2048 (sigma=4), 12288 rows, 400 observations, 64 hypotheses"}
+    for name, prec in (("int8_crt", fl.PREC_INT8_CRT), ("fp64", fl.PREC_FP64)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        F = fl.flsq_factorize(ctx, dp.basis, rows, fl.solve_opts(prob.mu, prec, 20, 1e-13))
+        torch.cuda.synchronize()
+        t_fac = time.perf_counter() - t0
+        ip = InverseProblem(ctx, F, prob.blocks[0].n, prob.blocks[0].weight, d - 1, xo, dd)
+        ip.loss_and_grad(th)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            loss, g, gk = ip.loss_and_grad(th)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        g = g.cpu().numpy()
+        res[name] = {"factorize_ms": 1e3 * t_fac, "ms_per_loss_and_grad_64": 1e3 * dt,
+                     "gradient_evals_per_s": th.shape[0] / dt,
+                     "grad_rel_err_vs_oracle": float(np.linalg.norm(g - gold["grad_theta0"]) /
+                                                     np.linalg.norm(gold["grad_theta0"])),
+                     "loss_rel_err_vs_oracle": float(np.max(np.abs(loss.cpu().numpy() - gold["loss0"]) /
+                                                            np.abs(gold["loss0"])))}
+        F.free()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -153,6 +253,7 @@ def main():
     ap.add_argument("--skip-fp32", action="store_true")
     ap.add_argument("--skip-fp64", action="store_true")
     ap.add_argument("--skip-eval", action="store_true")
+    ap.add_argument("--skip-configs", action="store_true", help="skip the other configurations' side measurements")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (HBM-counter calibration)")
     args = ap.parse_args()
@@ -262,6 +363,10 @@ def main():
         }
     if not args.skip_eval:
         out["evaluate_c4"] = bench_evaluate(fl, ctx)
+    if not args.skip_configs:
+        out["poisson2d_c1"] = bench_c1(fl, ctx)
+        out["newton_c3"] = bench_c3(fl, ctx)
+        out["inverse_c5"] = bench_c5(fl, ctx)
     if not args.skip_cpu:
         out["cpu_baseline"] = cpu_baseline(prob)
     print(json.dumps(out), flush=True)

@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cfloat>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -721,6 +722,7 @@ Err cgls_refine(flsq_ctx* c, const System& s, const double* rho, const double* X
   // further steps can increase it and then diverge.  A column whose J rises stops (its
   // step is set to zero) and the best iterate seen is returned.
   std::vector<double> ynorm, Jbest(K), active(K, 1.0), improved(K, 0.0);
+  std::vector<int> stagnant(K, 0);
   double *Xbest, *mask;
   CHECK_ERR(ws_get(c, "cg_xbest", (size_t)n * K, &Xbest));
   CHECK_ERR(ws_get(c, "cg_mask", (size_t)K, &mask));
@@ -772,17 +774,22 @@ Err cgls_refine(flsq_ctx* c, const System& s, const double* rho, const double* X
     CHECK_HIP(launch_dot_cols(sres, sres, P, K, dots, dwork, st));
     CHECK_HIP(launch_dot_cols(X, X, n, K, dots + K, dwork, st));
     CHECK_ERR(host_cols(c, dots, 2 * K, tmp));
+    // a column also stops once its objective has failed to drop by more than a few units in
+    // the last place for two iterations in a row: FP64 can no longer resolve its progress
     int n_active = 0;
     for (int k = 0; k < K; ++k) {
       improved[k] = 0.0;
       if (active[k] == 0.0) continue;
       const double J = tmp[k] + mu * tmp[K + k];
+      const bool resolved = (Jbest[k] - J) > 4.0 * DBL_EPSILON * Jbest[k];
       if (J <= Jbest[k]) {
         Jbest[k] = J;
         improved[k] = 1.0;
       } else if (J > Jbest[k] * (1.0 + 1e-12)) {
         active[k] = 0.0;
       }
+      stagnant[k] = resolved ? 0 : stagnant[k] + 1;
+      if (stagnant[k] >= 2) active[k] = 0.0;
       if (active[k] > 0.0) ++n_active;
     }
     CHECK_ERR(to_dev_cols(c, improved, mask));
@@ -1153,6 +1160,7 @@ flsq_status flsq_factor_solve_normal(flsq_ctx* ctx, const flsq_factor* F, const 
     CHECK_HIP(launch_dot_cols(out, r, n, K, dots + K, dwork, st));
     CHECK_ERR(host_cols(ctx, dots, 2 * K, tmp));
     std::vector<double> phibest(K), active(K, 1.0), improved(K, 0.0);
+    std::vector<int> stagnant(K, 0);
     for (int k = 0; k < K; ++k) phibest[k] = -0.5 * (tmp[k] + tmp[K + k]);
     for (int it = 0; it < F->max_refine; ++it) {
       CHECK_ERR(apply_normal(p, ap));
@@ -1172,17 +1180,22 @@ flsq_status flsq_factor_solve_normal(flsq_ctx* ctx, const flsq_factor* F, const 
       CHECK_HIP(launch_dot_cols(out, V, n, K, dots, dwork, st));
       CHECK_HIP(launch_dot_cols(out, r, n, K, dots + K, dwork, st));
       CHECK_ERR(host_cols(ctx, dots, 2 * K, tmp));
+      // as in the refinement: a column whose energy has not dropped by more than a few
+      // units in the last place for two iterations in a row is done
       int n_active = 0;
       for (int k = 0; k < K; ++k) {
         improved[k] = 0.0;
         if (active[k] == 0.0) continue;
         const double phi = -0.5 * (tmp[k] + tmp[K + k]);
+        const bool resolved = (phibest[k] - phi) > 4.0 * DBL_EPSILON * std::fabs(phibest[k]);
         if (phi <= phibest[k]) {
           phibest[k] = phi;
           improved[k] = 1.0;
         } else if (phi > phibest[k] + 1e-12 * std::fabs(phibest[k])) {
           active[k] = 0.0;
         }
+        stagnant[k] = resolved ? 0 : stagnant[k] + 1;
+        if (stagnant[k] >= 2) active[k] = 0.0;
         if (active[k] > 0.0) ++n_active;
       }
       CHECK_ERR(to_dev_cols(ctx, improved, mask));

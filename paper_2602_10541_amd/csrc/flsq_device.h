@@ -45,10 +45,10 @@ __device__ __forceinline__ double sin_f64(double x) {
   p = fma(p, r2, 1.0 / 120.0);                     // 1/5!
   p = fma(p, r2, -1.0 / 6.0);                      // -1/3!
   const double s = fma(r * r2, p, r);
-  return (static_cast<int64_t>(k) & 1) ? -s : s;
+  return (static_cast<int>(k) & 1) ? -s : s;   // |k| < 2^31 for |x| < 2^30: the conversion is exact
 }
 
-// sin and cos together: x = k pi/2 + r, |r| <= pi/4.
+// sin and cos together for |x| < 2^30: x = k pi/2 + r, |r| <= pi/4.
 // sin to r^17 (omitted (pi/4)^19/19! < 1e-19), cos to r^18 (omitted (pi/4)^20/20! < 1e-21).
 __device__ __forceinline__ void sincos_f64(double x, double* s_out, double* c_out) {
   const double k2Pi = 0.63661977236758134308;      // 2/pi
@@ -77,7 +77,7 @@ __device__ __forceinline__ void sincos_f64(double x, double* s_out, double* c_ou
   pc = fma(pc, r2, -1.0 / 24.0);                   // -1/4!
   pc = fma(pc, r2, 0.5);
   const double c = fma(-r2, pc, 1.0);
-  const int q = static_cast<int>(static_cast<int64_t>(k) & 3);
+  const int q = static_cast<int>(k) & 3;           // |k| < 2^31 for |x| < 2^30
   const double sv = (q & 1) ? c : s;
   const double cv = (q & 1) ? s : c;
   *s_out = (q & 2) ? -sv : sv;

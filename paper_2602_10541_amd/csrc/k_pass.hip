@@ -194,14 +194,28 @@ __global__ __launch_bounds__(256) void k_colpass(PassGeo pg, const double* __res
     for (int c = 0; c < K && c < KMAX; ++c) part[((int64_t)split * n + j) * K + c] = acc[c];
 }
 
-__global__ void k_colpass_reduce(const double* part, int n_split, int n, int K, const double* V, double alpha,
-                                 double beta_v, double* out) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (int64_t)n * K) return;
+// out[e] = alpha * sum_sp part[sp][e] + beta_v * V[e].  Workgroup: 64 outputs x 4 groups of
+// splits (group g sums splits g, g + 4, ...); the four group sums are added in a fixed
+// order, so the result is deterministic.
+__global__ __launch_bounds__(256) void k_colpass_reduce(const double* __restrict__ part, int n_split, int n, int K,
+                                                        const double* __restrict__ V, double alpha, double beta_v,
+                                                        double* __restrict__ out) {
+  __shared__ double red[4][64];
+  const int o = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  const int64_t e = (int64_t)blockIdx.x * 64 + o;
+  const int64_t nk = (int64_t)n * K;
   double s = 0.0;
-  for (int sp = 0; sp < n_split; ++sp) s += part[(int64_t)sp * n * K + e];
-  const double v = V ? V[e] : 0.0;
-  out[e] = fma(alpha, s, beta_v * v);
+  if (e < nk) {
+#pragma unroll 8
+    for (int sp = grp; sp < n_split; sp += 4) s += part[(int64_t)sp * nk + e];
+  }
+  red[grp][o] = s;
+  __syncthreads();
+  if (grp == 0 && e < nk) {
+    const double t = (red[0][o] + red[1][o]) + (red[2][o] + red[3][o]);
+    const double v = V ? V[e] : 0.0;
+    out[e] = fma(alpha, t, beta_v * v);
+  }
 }
 
 // ------------------------------------------------------------------ launchers
@@ -281,7 +295,7 @@ hipError_t launch_colpass_runs(const PassGeo& pg, const double* rho, const doubl
     if (e != hipSuccess) return e;
   }
   const int64_t tot = (int64_t)n * K;
-  hipLaunchKernelGGL(k_colpass_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, work,
+  hipLaunchKernelGGL(k_colpass_reduce, dim3((unsigned)((tot + 63) / 64)), dim3(256), 0, s, work,
                      pg.n_runs > 0 ? splits : 0, n, K, V, alpha, beta_v, out);
   return hipGetLastError();
 }

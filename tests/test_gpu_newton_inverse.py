@@ -13,12 +13,12 @@ pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
-def _newton_gpu(prob, max_iter=15):
+def _newton_gpu(prob, max_iter=15, prec=0):
     torch, fl = require_gpu()
     ctx = context()
     dp = fl.DeviceProblem(prob)
     beta = torch.zeros(prob.n_feat, dtype=torch.float64, device="cuda")
-    opts = fl.newton_opts(prob.mu, max_iter=max_iter, tol_dbeta=1e-10)
+    opts = fl.newton_opts(prob.mu, max_iter=max_iter, tol_dbeta=1e-10, prec=prec)
     st, tr = fl.flsq_solve_newton(ctx, dp.basis, dp.rows, prob.nonlin_block, prob.nonlin_poly, opts, beta)
     return st, tr, beta.cpu().numpy()
 
@@ -39,7 +39,8 @@ def test_newton_small_matches_oracle():
     assert rel_l2(u, prob.u_test) <= 2e-6
 
 
-def test_newton_full_reaction_diffusion():
+@pytest.mark.parametrize("prec", [0, 3])
+def test_newton_full_reaction_diffusion(prec):
     """-Laplace u + u^3 - u = f, N = 2048, 16384 + 2048 rows, 15 steps: against the oracle's stored run.
 
     Each Gauss-Newton step is a Tikhonov solve whose normal equations sit at the limit of
@@ -53,7 +54,7 @@ def test_newton_full_reaction_diffusion():
         pytest.skip("golden values not generated")
     gold = np.load(path)
     prob = wl.config("reaction2d")
-    st, tr, beta = _newton_gpu(prob)
+    st, tr, beta = _newton_gpu(prob, prec=prec)
     u = oracle.evaluate(prob.W, prob.b, beta, prob.x_test, [(0, 0)])[:, 0]
     steps = tr.as_list()
     res = np.array([s["res_norm"] for s in steps][:len(gold["res_norm"])])
@@ -79,7 +80,7 @@ def test_newton_rejects_odd_operator_on_nonlinear_block():
 
 # ----------------------------------------------------------------------------- adjoint
 
-def _inverse_setup(prob, data, refine_tol=1e-13, max_refine=20):
+def _inverse_setup(prob, data, refine_tol=1e-13, max_refine=20, prec=0):
     torch, fl = require_gpu()
     from paper_2602_10541_amd.autograd import InverseProblem
     ctx = context()
@@ -89,7 +90,7 @@ def _inverse_setup(prob, data, refine_tol=1e-13, max_refine=20):
     t_axis = tuple([0] * (d - 1) + [1])
     interior = [(1.0, t_axis)] + [(-kappa, tuple(2 if i == k else 0 for i in range(d))) for k in range(d - 1)]
     rows = dp.rows_with_terms([interior] + [bl.terms for bl in prob.blocks[1:]])
-    F = fl.flsq_factorize(ctx, dp.basis, rows, fl.solve_opts(prob.mu, 0, max_refine, refine_tol))
+    F = fl.flsq_factorize(ctx, dp.basis, rows, fl.solve_opts(prob.mu, prec, max_refine, refine_tol))
     xo = torch.tensor(prob.extras["x_obs"], dtype=torch.float64, device="cuda")
     dd = torch.tensor(data, dtype=torch.float64, device="cuda")
     return InverseProblem(ctx, F, prob.blocks[0].n, prob.blocks[0].weight, d - 1, xo, dd), dp
@@ -183,15 +184,17 @@ def test_adam_matches_reference_formula():
     np.testing.assert_allclose(p.cpu().numpy(), ref, rtol=1e-14, atol=1e-15)
 
 
-def test_inverse_full_size_gradients():
-    """Inverse heat source at full size (N = 2048, 12288 rows, 64 hypotheses, 400 observations)."""
+@pytest.mark.parametrize("prec", [0, 3])
+def test_inverse_full_size_gradients(prec):
+    """Inverse heat source at full size (N = 2048, 12288 rows, 64 hypotheses, 400 observations),
+    factor from the FP64 and from the int8-CRT Gram."""
     path = os.path.join(GOLDEN, "inverse3d.npz")
     if not os.path.exists(path):
         pytest.skip("golden values not generated")
     torch, fl = require_gpu()
     gold = np.load(path)
     prob = wl.config("inverse3d")
-    ip, _ = _inverse_setup(prob, gold["data"])
+    ip, _ = _inverse_setup(prob, gold["data"], prec=prec)
     th = torch.tensor(prob.extras["theta0"], dtype=torch.float64, device="cuda")
     loss, g, gk = ip.loss_and_grad(th)
     np.testing.assert_allclose(loss.cpu().numpy(), gold["loss0"], rtol=1e-6)
