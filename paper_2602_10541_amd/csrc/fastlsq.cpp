@@ -99,8 +99,8 @@ struct System {
   std::vector<double> weight;
   std::vector<int> even;              // operator has even-order terms only
   int normalize = 1;
-  DevBuf Wt, Wt32, Wrm, bvec, amp, ph, amp32, ph32, Xt, Xt32, Xrm, row_block, rhs_w, chunks, runs;
-  int n_chunks = 0, n_runs = 0;
+  DevBuf Wt, Wt32, Wrm, bvec, amp, ph, amp32, ph32, Xt, Xt32, Xrm, row_block, rhs_w, chunks, runs, wide, frec;
+  int n_chunks = 0, n_runs = 0, n_wide = 0;
   // Gram plan
   int nt = 0, n_wg = 0, max_seg = 0;
   int64_t total_units = 0, units_per_wg = 0;
@@ -121,6 +121,7 @@ struct System {
     g.Xt = Xt.as<double>();
     g.Xt32 = Xt32.as<float>();
     g.row_block = row_block.as<int32_t>();
+    g.frec = frec.as<double>();
     return g;
   }
   PassGeo pass() const {
@@ -128,6 +129,8 @@ struct System {
     pg.g = geo();
     pg.runs = runs.as<Chunk>();
     pg.n_runs = n_runs;
+    pg.wide = wide.as<Chunk>();
+    pg.n_wide = n_wide;
     pg.even_mask = 0;
     for (int b = 0; b < n_blocks && b < 64; ++b)
       if (even[b]) pg.even_mask |= 1ull << b;
@@ -316,15 +319,22 @@ Err build_system(flsq_ctx* c, System& s, const flsq_basis* basis, const flsq_row
       CHECK_HIP(launch_scale_copy(r.rhs, s.rhs_w.as<double>() + s.row0[i], r.n_rows, r.weight, st));  // NULL -> 0
     }
   }
+  CHECK_HIP(s.frec.ensure(sizeof(double) * n_blocks * n * frec_stride(d)));
+  CHECK_HIP(launch_pack_features(s.Wrm.as<double>(), s.amp.as<double>(), s.ph.as<double>(), n_blocks, n, d,
+                                 s.frec.as<double>(), st));
   // Gram chunks and pass runs (block-aligned), Gram stream-K plan
   std::vector<Chunk> ch = make_runs(s, gram_chunk_rows());
   std::vector<Chunk> rn = make_runs(s, pass_rows());
+  std::vector<Chunk> wd = make_runs(s, wide_rows());
   s.n_chunks = (int)ch.size();
   s.n_runs = (int)rn.size();
+  s.n_wide = (int)wd.size();
   CHECK_HIP(s.chunks.ensure(sizeof(Chunk) * ch.size()));
   CHECK_HIP(s.runs.ensure(sizeof(Chunk) * rn.size()));
+  CHECK_HIP(s.wide.ensure(sizeof(Chunk) * wd.size()));
   CHECK_HIP(hipMemcpyAsync(s.chunks.p, ch.data(), sizeof(Chunk) * ch.size(), hipMemcpyHostToDevice, st));
   CHECK_HIP(hipMemcpyAsync(s.runs.p, rn.data(), sizeof(Chunk) * rn.size(), hipMemcpyHostToDevice, st));
+  CHECK_HIP(hipMemcpyAsync(s.wide.p, wd.data(), sizeof(Chunk) * wd.size(), hipMemcpyHostToDevice, st));
 
   const int T = gram_tile();
   s.nt = (n + T - 1) / T;
@@ -606,16 +616,37 @@ Err chol_solve(flsq_ctx* c, const double* X, int n, const double* Y, double* Z, 
     CHECK_HIP(launch_precond_apply(X, n, Y, tmp, work, Z, st));
     return ok();
   }
-  double* tmp;
+  // K > 1: T = X^T Y, then Z = X T, each as a split-K batched GEMM (contraction chunks of
+  // kChunkK rows as separate descriptors, so that tall-skinny products fill the chip) and
+  // a fixed-order sum of the partial products.
+  constexpr int kChunkK = 256;
+  const int n_split = (n + kChunkK - 1) / kChunkK;
+  double *tmp, *part;
   CHECK_ERR(ws_get(c, "pa_tmpK", (size_t)n * K, &tmp));
-  GemmDesc h[2] = {};
-  h[0].A = X; h[0].B = Y; h[0].C = tmp; h[0].M = n; h[0].N = K; h[0].K = n; h[0].lda = n; h[0].ldb = K; h[0].ldc = K;
-  h[1].A = X; h[1].B = tmp; h[1].C = Z; h[1].M = n; h[1].N = K; h[1].K = n; h[1].lda = n; h[1].ldb = K; h[1].ldc = K;
+  CHECK_ERR(ws_get(c, "pa_partK", (size_t)n_split * n * K, &part));
+  std::vector<GemmDesc> h(2 * n_split);
+  for (int sp = 0; sp < n_split; ++sp) {
+    const int k0 = sp * kChunkK, kc = std::min(kChunkK, n - k0);
+    GemmDesc& t = h[sp];            // part[sp] = X[k0.., :]^T Y[k0.., :]
+    t = GemmDesc{};
+    t.A = X + (int64_t)k0 * n; t.lda = n;
+    t.B = Y + (int64_t)k0 * K; t.ldb = K;
+    t.C = part + (int64_t)sp * n * K; t.ldc = K;
+    t.M = n; t.N = K; t.K = kc;
+    GemmDesc& z = h[n_split + sp];  // part[sp] = X[:, k0..] T[k0.., :]
+    z = GemmDesc{};
+    z.A = X + k0; z.lda = n;
+    z.B = tmp + (int64_t)k0 * K; z.ldb = K;
+    z.C = part + (int64_t)sp * n * K; z.ldc = K;
+    z.M = n; z.N = K; z.K = kc;
+  }
   GemmDesc* d;
-  CHECK_ERR(ws_get(c, "pa_descs", 2, &d));
-  CHECK_HIP(hipMemcpyAsync(d, h, sizeof h, hipMemcpyHostToDevice, st));
-  CHECK_HIP(launch_gemm_batched(d, 1, n, K, 1.0, 0.0, 1, st));       // tmp = X^T Y
-  CHECK_HIP(launch_gemm_batched(d + 1, 1, n, K, 1.0, 0.0, 0, st));   // Z = X tmp
+  CHECK_ERR(ws_get(c, "pa_descs", h.size(), &d));
+  CHECK_HIP(hipMemcpyAsync(d, h.data(), sizeof(GemmDesc) * h.size(), hipMemcpyHostToDevice, st));
+  CHECK_HIP(launch_gemm_batched(d, n_split, n, K, 1.0, 0.0, 1, st));             // partials of X^T Y
+  CHECK_HIP(launch_sum_partials(part, n_split, (int64_t)n * K, tmp, st));
+  CHECK_HIP(launch_gemm_batched(d + n_split, n_split, n, K, 1.0, 0.0, 0, st));   // partials of X T
+  CHECK_HIP(launch_sum_partials(part, n_split, (int64_t)n * K, Z, st));
   CHECK_HIP(hipStreamSynchronize(st));                                 // h leaves scope
   return ok();
 }
@@ -649,6 +680,16 @@ Err factor_with_retries(flsq_ctx* c, const double* Gsrc, double* U, double* X, i
     rel = (rel == 0.0) ? 1e-14 : rel * 10.0;
   }
   return fail(FLSQ_ENOTSPD, "Cholesky failed: Gram + mu I not positive definite after %d shift retries", *retries);
+}
+
+// Row pass with the workspace the many-column (MFMA) variant needs.
+Err row_pass(flsq_ctx* c, const PassGeo& pg, const double* rho, const double* V, int K, const double* Y, double alpha,
+             double beta_y, double* out, double* u_out = nullptr) {
+  double* work = nullptr;
+  const size_t we = rowpass_work_elems(pg, K);
+  if (we) CHECK_ERR(ws_get(c, "rp_work", we, &work));
+  CHECK_HIP(launch_rowpass_runs(pg, rho, V, K, Y, alpha, beta_y, out, c->stream, u_out, work));
+  return ok();
 }
 
 // ------------------------------------------------------------------ CGLS refinement
@@ -702,7 +743,7 @@ Err cgls_refine(flsq_ctx* c, const System& s, const double* rho, const double* X
   std::vector<double> gam, del, tmp, tmp2, alpha(K), beta(K), stepn(K), xn(K);
 
   // s = Y - A X ; g = A^T s - mu X ; u = H X
-  CHECK_HIP(launch_rowpass_runs(pg, rho, X, K, Y, -1.0, 1.0, sres, st, uu));
+  CHECK_ERR(row_pass(c, pg, rho, X, K, Y, -1.0, 1.0, sres, uu));
   CHECK_HIP(launch_colpass_runs(pg, rho, sres, K, X, 1.0, -mu, g, colwork, st));
   if (want_grad) {
     CHECK_HIP(launch_dot_cols(g, g, n, K, dots, dwork, st));
@@ -721,7 +762,8 @@ Err cgls_refine(flsq_ctx* c, const System& s, const double* rho, const double* X
   // exact arithmetic; once rounding takes over (these systems are near the limit of FP64)
   // further steps can increase it and then diverge.  A column whose J rises stops (its
   // step is set to zero) and the best iterate seen is returned.
-  std::vector<double> ynorm, Jbest(K), active(K, 1.0), improved(K, 0.0);
+  std::vector<double> ynorm, Jbest(K), active(K, 1.0), improved(K, 0.0), relstep(K, 0.0),
+      minstep(K, HUGE_VAL);
   std::vector<int> stagnant(K, 0);
   double *Xbest, *mask;
   CHECK_ERR(ws_get(c, "cg_xbest", (size_t)n * K, &Xbest));
@@ -743,7 +785,7 @@ Err cgls_refine(flsq_ctx* c, const System& s, const double* rho, const double* X
   bool stalled_all = false;
   for (int it = 0; it < max_iter; ++it) {
     // q = A p ; delta = ||q||^2 + mu ||p||^2 ; hq = H p
-    CHECK_HIP(launch_rowpass_runs(pg, rho, p, K, nullptr, 1.0, 0.0, q, st, hq));
+    CHECK_ERR(row_pass(c, pg, rho, p, K, nullptr, 1.0, 0.0, q, hq));
     CHECK_HIP(launch_dot_cols(q, q, P, K, dots, dwork, st));
     CHECK_HIP(launch_dot_cols(p, p, n, K, dots + K, dwork, st));
     if (track_u) {
@@ -758,11 +800,12 @@ Err cgls_refine(flsq_ctx* c, const System& s, const double* rho, const double* X
       if (active[k] == 0.0) continue;
       if (track_u && tmp[3 * K + k] > 0.0) {
         stepn[k] = std::fabs(alpha[k]) * std::sqrt(tmp[2 * K + k]);
-        worst = std::max(worst, stepn[k] / std::sqrt(tmp[3 * K + k]));
+        relstep[k] = stepn[k] / std::sqrt(tmp[3 * K + k]);
       } else {
         stepn[k] = std::fabs(alpha[k]) * std::sqrt(tmp[k]);
-        worst = std::max(worst, stepn[k] / ynorm[k]);
+        relstep[k] = stepn[k] / ynorm[k];
       }
+      worst = std::max(worst, relstep[k]);
     }
     CHECK_ERR(to_dev_cols(c, alpha, scal));
     CHECK_HIP(launch_axpy_cols(scal, p, X, n, K, 1.0, st));
@@ -774,16 +817,23 @@ Err cgls_refine(flsq_ctx* c, const System& s, const double* rho, const double* X
     CHECK_HIP(launch_dot_cols(sres, sres, P, K, dots, dwork, st));
     CHECK_HIP(launch_dot_cols(X, X, n, K, dots + K, dwork, st));
     CHECK_ERR(host_cols(c, dots, 2 * K, tmp));
-    // a column also stops once its objective has failed to drop by more than a few units in
-    // the last place for two iterations in a row: FP64 can no longer resolve its progress
+    // A column also stops once, for two iterations in a row, neither its objective dropped
+    // by more than a few units in the last place nor its step shrank below half the smallest
+    // step so far: FP64 no longer resolves its progress.  The objective alone is not enough:
+    // it is quadratic in the error, so it stops resolving progress at a relative error of
+    // about the square root of the unit roundoff, while the step keeps shrinking until the
+    // rounding floor.  An objective within a few ulps of the best counts as a tie and takes
+    // the newer iterate.
     int n_active = 0;
     for (int k = 0; k < K; ++k) {
       improved[k] = 0.0;
       if (active[k] == 0.0) continue;
       const double J = tmp[k] + mu * tmp[K + k];
-      const bool resolved = (Jbest[k] - J) > 4.0 * DBL_EPSILON * Jbest[k];
-      if (J <= Jbest[k]) {
-        Jbest[k] = J;
+      const double ulps = 4.0 * DBL_EPSILON * Jbest[k];
+      const bool resolved = (Jbest[k] - J) > ulps || relstep[k] < 0.5 * minstep[k];
+      minstep[k] = std::min(minstep[k], relstep[k]);
+      if (J <= Jbest[k] + ulps) {
+        Jbest[k] = std::min(Jbest[k], J);
         improved[k] = 1.0;
       } else if (J > Jbest[k] * (1.0 + 1e-12)) {
         active[k] = 0.0;
@@ -818,7 +868,7 @@ Err cgls_refine(flsq_ctx* c, const System& s, const double* rho, const double* X
   CHECK_HIP(hipMemcpyAsync(X, Xbest, sizeof(double) * n * K, hipMemcpyDeviceToDevice, st));
   if (stalled_all) ro->converged = true;   // no further progress is possible in FP64
   if (want_grad) {
-    CHECK_HIP(launch_rowpass_runs(pg, rho, X, K, Y, -1.0, 1.0, sres, st));
+    CHECK_ERR(row_pass(c, pg, rho, X, K, Y, -1.0, 1.0, sres));
     CHECK_HIP(launch_colpass_runs(pg, rho, sres, K, X, 1.0, -mu, g, colwork, st));
     CHECK_HIP(launch_dot_cols(g, g, n, K, dots, dwork, st));
     CHECK_ERR(host_cols(c, dots, K, tmp));
@@ -1131,7 +1181,7 @@ flsq_status flsq_factor_solve_normal(flsq_ctx* ctx, const flsq_factor* F, const 
   if (e.st == FLSQ_OK) e = ws_get(ctx, "pcg_scal", (size_t)K, &scal);
   if (e.st != FLSQ_OK) return finish(ctx, e);
   auto apply_normal = [&](const double* x, double* y) -> Err {   // y = A^T A x + mu x
-    CHECK_HIP(launch_rowpass_runs(pg, nullptr, x, K, nullptr, 1.0, 0.0, tP, st));
+    CHECK_ERR(row_pass(ctx, pg, nullptr, x, K, nullptr, 1.0, 0.0, tP));
     CHECK_HIP(launch_colpass_runs(pg, nullptr, tP, K, x, 1.0, F->mu, y, colwork, st));
     return ok();
   };
@@ -1151,7 +1201,8 @@ flsq_status flsq_factor_solve_normal(flsq_ctx* ctx, const flsq_factor* F, const 
     // Stop when the step's energy norm |alpha| (p^T M p)^{1/2} (M = G + mu I) is below tol
     // times the solution's, estimated by (out^T V)^{1/2}.  The energy functional
     // phi(x) = x^T M x / 2 - x^T V = -(x^T V + x^T r) / 2 decreases monotonically in exact
-    // arithmetic; a column whose phi rises stops, and the best iterate is returned.
+    // arithmetic; a column whose phi clearly rises stops, and its last iterate before the
+    // rise is returned.
     double *xbest, *mask;
     CHECK_ERR(ws_get(ctx, "pcg_xbest", (size_t)n * K, &xbest));
     CHECK_ERR(ws_get(ctx, "pcg_mask", (size_t)K, &mask));
@@ -1159,7 +1210,7 @@ flsq_status flsq_factor_solve_normal(flsq_ctx* ctx, const flsq_factor* F, const 
     CHECK_HIP(launch_dot_cols(out, V, n, K, dots, dwork, st));
     CHECK_HIP(launch_dot_cols(out, r, n, K, dots + K, dwork, st));
     CHECK_ERR(host_cols(ctx, dots, 2 * K, tmp));
-    std::vector<double> phibest(K), active(K, 1.0), improved(K, 0.0);
+    std::vector<double> phibest(K), active(K, 1.0), improved(K, 0.0), relstep(K, 0.0), minstep(K, HUGE_VAL);
     std::vector<int> stagnant(K, 0);
     for (int k = 0; k < K; ++k) phibest[k] = -0.5 * (tmp[k] + tmp[K + k]);
     for (int it = 0; it < F->max_refine; ++it) {
@@ -1170,9 +1221,11 @@ flsq_status flsq_factor_solve_normal(flsq_ctx* ctx, const flsq_factor* F, const 
       double worst = 0.0;
       for (int k = 0; k < K; ++k) {
         alpha[k] = (active[k] > 0.0 && tmp[k] > 0.0 && gam[k] > 0.0) ? gam[k] / tmp[k] : 0.0;
-        if (active[k] > 0.0)
-          worst = std::max(worst, std::fabs(alpha[k]) * std::sqrt(std::max(tmp[k], 0.0)) /
-                                      std::max(std::sqrt(std::fabs(tmp[2 * K + k])), 1e-300));
+        if (active[k] > 0.0) {
+          relstep[k] = std::fabs(alpha[k]) * std::sqrt(std::max(tmp[k], 0.0)) /
+                       std::max(std::sqrt(std::fabs(tmp[2 * K + k])), 1e-300);
+          worst = std::max(worst, relstep[k]);
+        }
       }
       CHECK_ERR(to_dev_cols(ctx, alpha, scal));
       CHECK_HIP(launch_axpy_cols(scal, p, out, n, K, 1.0, st));
@@ -1180,18 +1233,27 @@ flsq_status flsq_factor_solve_normal(flsq_ctx* ctx, const flsq_factor* F, const 
       CHECK_HIP(launch_dot_cols(out, V, n, K, dots, dwork, st));
       CHECK_HIP(launch_dot_cols(out, r, n, K, dots + K, dwork, st));
       CHECK_ERR(host_cols(ctx, dots, 2 * K, tmp));
-      // as in the refinement: a column whose energy has not dropped by more than a few
-      // units in the last place for two iterations in a row is done
+      // A column is done once, for two iterations in a row, neither its energy phi dropped
+      // by more than a few units in the last place nor its step shrank below half the
+      // smallest so far: FP64 no longer resolves its progress (phi is quadratic in the error
+      // and stops resolving it long before the step does).  phi is formed from dot products
+      // whose terms cancel (x^T V is far smaller than |x|^T |V|), so its rounding noise can
+      // reach 1e-12 relative while the error still falls by orders of magnitude: only a rise
+      // above sqrt(eps) relative (an energy-norm error near 1e-4), far above that noise,
+      // counts as divergence.
       int n_active = 0;
+      const double rise = std::sqrt(DBL_EPSILON);
       for (int k = 0; k < K; ++k) {
         improved[k] = 0.0;
         if (active[k] == 0.0) continue;
         const double phi = -0.5 * (tmp[k] + tmp[K + k]);
-        const bool resolved = (phibest[k] - phi) > 4.0 * DBL_EPSILON * std::fabs(phibest[k]);
-        if (phi <= phibest[k]) {
-          phibest[k] = phi;
+        const bool resolved =
+            (phibest[k] - phi) > 4.0 * DBL_EPSILON * std::fabs(phibest[k]) || relstep[k] < 0.5 * minstep[k];
+        minstep[k] = std::min(minstep[k], relstep[k]);
+        if (phi <= phibest[k] + rise * std::fabs(phibest[k])) {
+          phibest[k] = std::min(phibest[k], phi);
           improved[k] = 1.0;
-        } else if (phi > phibest[k] + 1e-12 * std::fabs(phibest[k])) {
+        } else {
           active[k] = 0.0;
         }
         stagnant[k] = resolved ? 0 : stagnant[k] + 1;
@@ -1226,8 +1288,9 @@ flsq_status flsq_apply_A(flsq_ctx* ctx, const flsq_factor* F, const double* V, i
   if (hipSetDevice(ctx->device) != hipSuccess) return finish(ctx, fail(FLSQ_EHIP, "hipSetDevice failed"));
   if (!V || !out) return finish(ctx, fail(FLSQ_EINVAL, "NULL V or out"));
   if (K < 1 || K > 64) return finish(ctx, fail(FLSQ_EINVAL, "K = %d outside [1, 64]", K));
-  hipError_t he = launch_rowpass_runs(F->sys.pass(), nullptr, V, K, nullptr, 1.0, 0.0, out, ctx->stream);
-  if (he == hipSuccess) he = hipStreamSynchronize(ctx->stream);
+  Err e = row_pass(ctx, F->sys.pass(), nullptr, V, K, nullptr, 1.0, 0.0, out);
+  if (e.st != FLSQ_OK) return finish(ctx, e);
+  hipError_t he = hipStreamSynchronize(ctx->stream);
   if (he != hipSuccess) return finish(ctx, fail(FLSQ_EHIP, "apply_A: %s", hipGetErrorString(he)));
   return finish(ctx, ok());
 }
@@ -1343,9 +1406,11 @@ Err newton_impl(flsq_ctx* c, const flsq_basis* basis, const flsq_rows* blocks, i
   const double w_nl = s.weight[nl_block];
   const int64_t nl0 = s.row0[nl_block], nln = s.rows[nl_block];
   const PassGeo pg = s.pass();
+  double* rpwork = nullptr;
+  if (const size_t we = rowpass_work_elems(pg, 1)) CHECK_ERR(ws_get(c, "nt_rpwork", we, &rpwork));
   auto residual = [&](const double* b, double* Rout, double* rho_out, double* u_out, double* nrm) -> Err {
     CHECK_HIP(launch_newton_residual_runs(pg, b, s.rhs_w.as<double>(), nl_block, poly, nl->n_poly, w_nl, s.norm, Rout,
-                                          rho_out, u_out, st));
+                                          rho_out, u_out, rpwork, st));
     CHECK_HIP(launch_dot_cols(Rout, Rout, P, 1, dots, dwork, st));
     double h = 0.0;
     CHECK_HIP(hipMemcpyAsync(&h, dots, sizeof(double), hipMemcpyDeviceToHost, st));
@@ -1498,13 +1563,13 @@ Err inverse_impl(flsq_ctx* c, flsq_factor* F, int64_t n_src, double src_weight, 
   CHECK_HIP(launch_source(s.Xt.as<double>(), P, n_src, src_weight, thetas, K, Rhs, st));
   flsq_status fs = flsq_factor_solve(c, F, Rhs, K, B, nullptr);
   if (fs != FLSQ_OK) return Err{fs, c->err};
-  CHECK_HIP(launch_rowpass_runs(F->obs.pass(), nullptr, B, K, nullptr, 1.0, 0.0, U, st));
+  CHECK_ERR(row_pass(c, F->obs.pass(), nullptr, B, K, nullptr, 1.0, 0.0, U));
   CHECK_HIP(launch_misfit(U, data, n_obs, K, loss, gu, st));
   // backward: Lam = (A^T A + mu I)^{-1} H^T gu ; AL = A Lam ; dL/dtheta = AL^T d rhs / d theta
   CHECK_HIP(launch_colpass_runs(F->obs.pass(), nullptr, gu, K, nullptr, 1.0, 0.0, Vn, colwork, st));
   fs = flsq_factor_solve_normal(c, F, Vn, K, Lam);
   if (fs != FLSQ_OK) return Err{fs, c->err};
-  CHECK_HIP(launch_rowpass_runs(s.pass(), nullptr, Lam, K, nullptr, 1.0, 0.0, AL, st));
+  CHECK_ERR(row_pass(c, s.pass(), nullptr, Lam, K, nullptr, 1.0, 0.0, AL));
   CHECK_HIP(launch_source_grad_dot(s.Xt.as<double>(), P, n_src, src_weight, thetas, K, AL, gtheta, gwork, st));
   if (gkappa) {
     // dL/dkappa = (A_k Lam)^T (rhs - A B) - (A Lam)^T (A_k B), A_k nonzero on the interior rows only
@@ -1514,9 +1579,9 @@ Err inverse_impl(flsq_ctx* c, flsq_factor* F, int64_t n_src, double src_weight, 
     CHECK_ERR(ws_get(c, "inv_AkB", (size_t)n_src * K, &AkB));
     CHECK_ERR(ws_get(c, "inv_dots", (size_t)2 * K, &dots));
     CHECK_ERR(ws_get(c, "inv_dwork", (size_t)512 * K + 64, &dwork));
-    CHECK_HIP(launch_rowpass_runs(s.pass(), nullptr, B, K, Rhs, -1.0, 1.0, r, st));
-    CHECK_HIP(launch_rowpass_runs(F->akap.pass(), nullptr, Lam, K, nullptr, 1.0, 0.0, AkL, st));
-    CHECK_HIP(launch_rowpass_runs(F->akap.pass(), nullptr, B, K, nullptr, 1.0, 0.0, AkB, st));
+    CHECK_ERR(row_pass(c, s.pass(), nullptr, B, K, Rhs, -1.0, 1.0, r));
+    CHECK_ERR(row_pass(c, F->akap.pass(), nullptr, Lam, K, nullptr, 1.0, 0.0, AkL));
+    CHECK_ERR(row_pass(c, F->akap.pass(), nullptr, B, K, nullptr, 1.0, 0.0, AkB));
     CHECK_HIP(launch_dot_cols(AkL, r, n_src, K, dots, dwork, st));
     CHECK_HIP(launch_dot_cols(AL, AkB, n_src, K, dots + K, dwork, st));
     CHECK_HIP(launch_combine_diff(dots, dots + K, gkappa, K, st));

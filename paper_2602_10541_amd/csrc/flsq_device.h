@@ -158,7 +158,11 @@ struct Geo {
   const double* Xt;      // d x P
   const float* Xt32;
   const int32_t* row_block;   // P
+  const double* frec;         // n_blocks x n records {W_j (d), amp_gj, ph_gj, 0...}, frec_stride(d) doubles each
 };
+
+// Doubles per feature record: 8 up to d = 6 (one 64-byte scalar load), else 16.
+__host__ __device__ constexpr int frec_stride(int d) { return d + 2 <= 8 ? 8 : 16; }
 
 // A run of rows that lies inside one block: rows [row0, row0 + nrows).
 struct Chunk {

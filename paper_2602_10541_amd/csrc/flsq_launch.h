@@ -19,6 +19,8 @@ hipError_t launch_prep_block(const OpTerms& op, double weight, double norm, int 
                              hipStream_t s);
 hipError_t launch_transpose(const double* X, int64_t rows, int d, double* Xt, float* Xt32, int64_t ld_out,
                             hipStream_t s);
+hipError_t launch_pack_features(const double* Wrm, const double* amp, const double* ph, int n_blocks, int n, int d,
+                                double* rec, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_scale_copy(const double* src, double* dst, int64_t n, double scale, hipStream_t s);
 hipError_t launch_assemble(const Geo& g, int fp32, void* A, hipStream_t s);
@@ -112,22 +114,29 @@ struct PassGeo {
   Geo g;
   const Chunk* runs;   // block-aligned runs of at most pass_rows() rows
   int n_runs;
+  const Chunk* wide;   // block-aligned runs of at most wide_rows() rows (row pass, K <= 16)
+  int n_wide;
   uint64_t even_mask;  // bit g set when block g's operator has only even-order terms (phase = b)
   double norm;         // 1/sqrt(N) or 1
 };
 int pass_rows();
+int wide_rows();
 size_t pass_work_elems(int n, int n_runs, int K);
 // out[i][c] = beta_y * Y[i][c] + alpha * sum_j A_ij V[j][c]   (Y nullable).  With u_out
 // (K <= 16) also u_out[i][c] = norm sum_j V[j][c] phi_j(x_i) on even blocks, 0 elsewhere.
+// work: rowpass_work_elems(pg, K) doubles (feature-group partials; many-column partials).
 hipError_t launch_rowpass_runs(const PassGeo& pg, const double* rho, const double* V, int K, const double* Y,
-                               double alpha, double beta_y, double* out, hipStream_t s, double* u_out = nullptr);
+                               double alpha, double beta_y, double* out, hipStream_t s, double* u_out = nullptr,
+                               double* work = nullptr);
+size_t rowpass_work_elems(const PassGeo& pg, int K);
 // out[j][c] = beta_v * V[j][c] + alpha * sum_i A_ij Y[i][c]   (V nullable)
 hipError_t launch_colpass_runs(const PassGeo& pg, const double* rho, const double* Y, int K, const double* V,
                                double alpha, double beta_v, double* out, double* work, hipStream_t s);
 // Newton residual R_i = (A beta)_i + w N(u_i) - data_i; rho_i = w N'(u_i) norm; u_i on the nonlinear block.
+// work: rowpass_work_elems(pg, 1) doubles.
 hipError_t launch_newton_residual_runs(const PassGeo& pg, const double* beta, const double* data_w,
                                        int nonlin_block, const double* poly, int n_poly, double w_nl, double norm,
-                                       double* R, double* rho_out, double* u_out, hipStream_t s);
+                                       double* R, double* rho_out, double* u_out, double* work, hipStream_t s);
 
 // ---- dense FP64 linear algebra on the upper Cholesky factor (row-major, G = U^T U)
 constexpr int kNb = 64;
@@ -155,6 +164,8 @@ struct GemmDesc {
 };
 hipError_t launch_gemm_batched(const GemmDesc* d_descs, int n_batch, int maxM, int maxN, double alpha, double beta,
                                int transA, hipStream_t s);
+// out[e] = sum_s part[s * len + e] (fixed summation order)
+hipError_t launch_sum_partials(const double* part, int n_split, int64_t len, double* out, hipStream_t s);
 // C = alpha A B with one upper-triangular operand (desc.tri), skipping its zero blocks.
 hipError_t launch_gemm_tri(const GemmDesc* d_descs, int n_batch, int maxM, int maxN, double alpha, hipStream_t s);
 // out = X (X^T v) for upper-triangular X (n x n); tmp n, work precond_work_elems(n).

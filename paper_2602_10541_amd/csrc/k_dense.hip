@@ -175,6 +175,27 @@ hipError_t launch_gemm_tri(const GemmDesc* d_descs, int n_batch, int maxM, int m
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ split-K partial sums
+// out[e] = sum_s part[s][e] for e < len, s < n_split.  Workgroup: 64 entries x 4 groups of
+// splits (group g sums splits g, g + 4, ...); the group sums are added in a fixed order.
+__global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__ part, int n_split, int64_t len,
+                                                      double* __restrict__ out) {
+  __shared__ double red[4][64];
+  const int o = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  const int64_t e = (int64_t)blockIdx.x * 64 + o;
+  double s = 0.0;
+  if (e < len)
+    for (int sp = grp; sp < n_split; sp += 4) s += part[(int64_t)sp * len + e];
+  red[grp][o] = s;
+  __syncthreads();
+  if (grp == 0 && e < len) out[e] = (red[0][o] + red[1][o]) + (red[2][o] + red[3][o]);
+}
+
+hipError_t launch_sum_partials(const double* part, int n_split, int64_t len, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_sum_partials, dim3((unsigned)((len + 63) / 64)), dim3(256), 0, s, part, n_split, len, out);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ preconditioner application
 // y = X^T v  (X upper triangular, n x n row-major): y_j = sum_{i <= j} X[i][j] v_i.
 // Grid (column tiles, row splits): each thread owns a column, loops over its row range;

@@ -83,19 +83,29 @@ hipError_t launch_diag_max(const double* G, int n, double* out, hipStream_t s) {
 constexpr int kDotWg = 256;
 constexpr int kDotBlocks = 512;
 
-__global__ void k_dot_stage1(const double* x, const double* y, int64_t n, int K, double* work) {
-  __shared__ double red[256];
-  for (int c = 0; c < K; ++c) {
+// Stage 1 of out[c] = sum_i x[i][c] y[i][c]: for columns in chunks of up to 256, thread t of
+// a workgroup owns column c = t % kc and walks rows t / kc, t / kc + R, ... (R = 256 / kc rows
+// per step, so a step reads R whole rows, coalesced); the R partial sums of a column are
+// added in a fixed order.
+__global__ __launch_bounds__(kDotWg) void k_dot_stage1(const double* __restrict__ x, const double* __restrict__ y,
+                                                       int64_t n, int K, double* __restrict__ work) {
+  __shared__ double red[kDotWg];
+  const int t = threadIdx.x;
+  for (int cb = 0; cb < K; cb += kDotWg) {
+    const int kc = min(kDotWg, K - cb);
+    const int R = kDotWg / kc;
+    const int c = t % kc, r = t / kc;
     double s = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * kDotWg + threadIdx.x; i < n; i += (int64_t)gridDim.x * kDotWg)
-      s = fma(x[i * K + c], y[i * K + c], s);
-    red[threadIdx.x] = s;
+    if (r < R)
+      for (int64_t i = (int64_t)blockIdx.x * R + r; i < n; i += (int64_t)gridDim.x * R)
+        s = fma(x[i * K + cb + c], y[i * K + cb + c], s);
+    red[t] = s;
     __syncthreads();
-    for (int st = 128; st > 0; st >>= 1) {
-      if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
-      __syncthreads();
+    if (t < kc) {
+      double acc = 0.0;
+      for (int rr = 0; rr < R; ++rr) acc += red[rr * kc + t];
+      work[(int64_t)(cb + t) * gridDim.x + blockIdx.x] = acc;
     }
-    if (threadIdx.x == 0) work[(int64_t)c * gridDim.x + blockIdx.x] = red[0];
     __syncthreads();
   }
 }
@@ -116,7 +126,7 @@ __global__ void k_dot_stage2(const double* work, int nblk, int K, double* out) {
 
 hipError_t launch_dot_cols(const double* x, const double* y, int64_t n, int K, double* out, double* work,
                            hipStream_t s) {
-  int64_t nb = (n + kDotWg - 1) / kDotWg;
+  const int64_t nb = (n * K + kDotWg - 1) / kDotWg;   // one step of a workgroup reads kDotWg entries
   const int nblk = (int)(nb < kDotBlocks ? (nb > 0 ? nb : 1) : kDotBlocks);
   hipLaunchKernelGGL(k_dot_stage1, dim3(nblk), dim3(kDotWg), 0, s, x, y, n, K, work);
   hipLaunchKernelGGL(k_dot_stage2, dim3(K), dim3(256), 0, s, work, nblk, K, out);

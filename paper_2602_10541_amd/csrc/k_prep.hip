@@ -147,6 +147,27 @@ hipError_t launch_assemble(const Geo& g, int fp32, void* A, hipStream_t s) {
   return hipSuccess;
 }
 
+// Feature records for the matrix-free passes: rec[g][j] = {W_j, amp_gj, ph_gj, 0, ...}, so
+// that a wave reads everything it needs about one feature with a single scalar load.
+__global__ void k_pack_features(const double* __restrict__ Wrm, const double* __restrict__ amp,
+                                const double* __restrict__ ph, int n, int d, double* __restrict__ rec) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int g = blockIdx.y;
+  if (j >= n) return;
+  const int rs = frec_stride(d);
+  double* r = rec + ((int64_t)g * n + j) * rs;
+  for (int k = 0; k < d; ++k) r[k] = Wrm[(int64_t)j * d + k];
+  r[d] = amp[(int64_t)g * n + j];
+  r[d + 1] = ph[(int64_t)g * n + j];
+  for (int k = d + 2; k < rs; ++k) r[k] = 0.0;
+}
+
+hipError_t launch_pack_features(const double* Wrm, const double* amp, const double* ph, int n_blocks, int n, int d,
+                                double* rec, hipStream_t s) {
+  hipLaunchKernelGGL(k_pack_features, dim3((n + 255) / 256, n_blocks), dim3(256), 0, s, Wrm, amp, ph, n, d, rec);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------------
 // Evaluation (Eq. (1)-(2)): out[q][a] = norm * sum_j beta_j W_j^{alpha_a} Phi_{|alpha_a|}(z_qj).
 // coef[a][j] = norm * beta_j * W_j^{alpha_a} * (+1 | -1) with the sign of Phi folded in, so
