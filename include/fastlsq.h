@@ -95,6 +95,8 @@ typedef struct {
     double shift_rel;     /* initial Cholesky diagonal shift, relative to the unit diagonal of the
                              equilibrated Gram D G D (D = diag(G)^{-1/2}), for the
                              FP32 / BF16x3 preconditioner (0 = automatic) */
+    int32_t report_grad;  /* nonzero: fill flsq_solve_info.grad_norm at the returned beta (two extra
+                             matrix-free passes); otherwise grad_norm repeats grad_norm0 */
 } flsq_solve_opts;
 
 typedef struct {
@@ -103,7 +105,7 @@ typedef struct {
     double shift;           /* diagonal shift added to the unit-diagonal (equilibrated) Gram in the factor
                                (0 for FP64 unless a pivot failed) */
     double grad_norm0;      /* ||A^T (rhs - A beta) - mu beta|| after the Cholesky solve */
-    double grad_norm;       /* same, at the returned beta */
+    double grad_norm;       /* same, at the returned beta (when opts.report_grad is set) */
     double last_step_rel;   /* ||last refinement step|| / ||beta|| */
     double t_gram_ms, t_chol_ms, t_refine_ms, t_total_ms;
     double t_gram_kernel_ms; /* the matrix-core Gram kernel alone (HIP events on the stream): the fused

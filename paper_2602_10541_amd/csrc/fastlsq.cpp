@@ -119,6 +119,7 @@ struct System {
     g.amp32 = amp32.as<float>();
     g.ph32 = ph32.as<float>();
     g.Xt = Xt.as<double>();
+    g.Xrm = Xrm.as<double>();
     g.Xt32 = Xt32.as<float>();
     g.row_block = row_block.as<int32_t>();
     g.frec = frec.as<double>();
@@ -166,6 +167,7 @@ struct flsq_factor {
   double shift = 0.0;
   int max_refine = 0;
   double refine_tol = 0.0;
+  bool report_grad = false;
 };
 
 namespace {
@@ -708,10 +710,25 @@ Err host_cols(flsq_ctx* c, const double* dev, int K, std::vector<double>& h) {
   return ok();
 }
 
-Err to_dev_cols(flsq_ctx* c, const std::vector<double>& h, double* dev) {
-  CHECK_HIP(hipMemcpyAsync(dev, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice, c->stream));
-  CHECK_HIP(hipStreamSynchronize(c->stream));
-  return ok();
+// Per-column scalars for the kernel arguments (K <= 64).
+ColScalars cols(const std::vector<double>& h) {
+  ColScalars c{};
+  for (size_t k = 0; k < h.size() && k < 64; ++k) c.v[k] = h[k];
+  return c;
+}
+
+ColScalars cols1(double v) {
+  ColScalars c{};
+  c.v[0] = v;
+  return c;
+}
+
+// Bit k set where h[k] != 0 (K <= 64).
+uint64_t col_mask(const std::vector<double>& h) {
+  uint64_t m = 0;
+  for (size_t k = 0; k < h.size() && k < 64; ++k)
+    if (h[k] != 0.0) m |= 1ull << k;
+  return m;
 }
 
 // Stopping rule (Section 2.4 prefers a solution-level change over the coefficient change,
@@ -720,12 +737,12 @@ Err to_dev_cols(flsq_ctx* c, const std::vector<double>& h, double* dev) {
 // where H p comes out of the same row pass as A p.  When no such rows exist (or K > 16)
 // the change of the fitted values |alpha| ||A p|| <= tol ||Y|| is used instead.
 Err cgls_refine(flsq_ctx* c, const System& s, const double* rho, const double* Xi, double mu, const double* Y, int K,
-                double* X, int max_iter, double tol, bool want_grad, RefineOut* ro) {
+                double* X, int max_iter, double tol, bool want_grad0, bool want_grad, RefineOut* ro) {
   const int n = s.n;
   const int64_t P = s.P;
   const PassGeo pg = s.pass();
   const bool track_u = (K <= 16) && pg.even_mask != 0;
-  double *sres, *q, *g, *z, *p, *dots, *dwork, *colwork, *scal, *uu = nullptr, *hq = nullptr;
+  double *sres, *q, *g, *z, *p, *dots, *dwork, *colwork, *uu = nullptr, *hq = nullptr;
   if (track_u) {
     CHECK_ERR(ws_get(c, "cg_u", (size_t)P * K, &uu));
     CHECK_ERR(ws_get(c, "cg_hq", (size_t)P * K, &hq));
@@ -738,14 +755,13 @@ Err cgls_refine(flsq_ctx* c, const System& s, const double* rho, const double* X
   CHECK_ERR(ws_get(c, "cg_dots", (size_t)8 * K, &dots));
   CHECK_ERR(ws_get(c, "cg_dwork", (size_t)512 * K + 64, &dwork));
   CHECK_ERR(ws_get(c, "cg_colwork", pass_work_elems(n, s.n_runs, K) + 64, &colwork));
-  CHECK_ERR(ws_get(c, "cg_scal", (size_t)K, &scal));
   hipStream_t st = c->stream;
   std::vector<double> gam, del, tmp, tmp2, alpha(K), beta(K), stepn(K), xn(K);
 
   // s = Y - A X ; g = A^T s - mu X ; u = H X
   CHECK_ERR(row_pass(c, pg, rho, X, K, Y, -1.0, 1.0, sres, uu));
   CHECK_HIP(launch_colpass_runs(pg, rho, sres, K, X, 1.0, -mu, g, colwork, st));
-  if (want_grad) {
+  if (want_grad0) {
     CHECK_HIP(launch_dot_cols(g, g, n, K, dots, dwork, st));
     CHECK_ERR(host_cols(c, dots, K, tmp));
     double m = 0;
@@ -765,9 +781,8 @@ Err cgls_refine(flsq_ctx* c, const System& s, const double* rho, const double* X
   std::vector<double> ynorm, Jbest(K), active(K, 1.0), improved(K, 0.0), relstep(K, 0.0),
       minstep(K, HUGE_VAL);
   std::vector<int> stagnant(K, 0);
-  double *Xbest, *mask;
+  double* Xbest;
   CHECK_ERR(ws_get(c, "cg_xbest", (size_t)n * K, &Xbest));
-  CHECK_ERR(ws_get(c, "cg_mask", (size_t)K, &mask));
   CHECK_HIP(hipMemcpyAsync(Xbest, X, sizeof(double) * n * K, hipMemcpyDeviceToDevice, st));
   CHECK_HIP(launch_dot_cols(Y, Y, P, K, dots, dwork, st));
   CHECK_HIP(launch_dot_cols(sres, sres, P, K, dots + K, dwork, st));
@@ -807,10 +822,10 @@ Err cgls_refine(flsq_ctx* c, const System& s, const double* rho, const double* X
       }
       worst = std::max(worst, relstep[k]);
     }
-    CHECK_ERR(to_dev_cols(c, alpha, scal));
-    CHECK_HIP(launch_axpy_cols(scal, p, X, n, K, 1.0, st));
-    CHECK_HIP(launch_axpy_cols(scal, q, sres, P, K, -1.0, st));
-    if (track_u) CHECK_HIP(launch_axpy_cols(scal, hq, uu, P, K, 1.0, st));
+    const ColScalars al = cols(alpha);
+    CHECK_HIP(launch_axpy_cols(al, p, X, n, K, 1.0, st));
+    CHECK_HIP(launch_axpy_cols(al, q, sres, P, K, -1.0, st));
+    if (track_u) CHECK_HIP(launch_axpy_cols(al, hq, uu, P, K, 1.0, st));
     ro->iters = it + 1;
     ro->last_step = worst;
     // objective after the step; keep the best iterate, stop columns whose objective rose
@@ -842,8 +857,7 @@ Err cgls_refine(flsq_ctx* c, const System& s, const double* rho, const double* X
       if (stagnant[k] >= 2) active[k] = 0.0;
       if (active[k] > 0.0) ++n_active;
     }
-    CHECK_ERR(to_dev_cols(c, improved, mask));
-    CHECK_HIP(launch_select_cols(X, Xbest, n, K, mask, st));
+    CHECK_HIP(launch_select_cols(X, Xbest, n, K, col_mask(improved), st));
     if (worst <= tol) {
       ro->converged = true;
       break;
@@ -861,8 +875,7 @@ Err cgls_refine(flsq_ctx* c, const System& s, const double* rho, const double* X
       beta[k] = gam[k] > 0.0 ? tmp[k] / gam[k] : 0.0;
       gam[k] = tmp[k];
     }
-    CHECK_ERR(to_dev_cols(c, beta, scal));
-    CHECK_HIP(launch_xpby_cols(z, scal, p, n, K, st));
+    CHECK_HIP(launch_xpby_cols(z, cols(beta), p, n, K, st));
   }
   // return the best iterate of every column; the recurrence residual is recomputed
   CHECK_HIP(hipMemcpyAsync(X, Xbest, sizeof(double) * n * K, hipMemcpyDeviceToDevice, st));
@@ -886,6 +899,7 @@ struct SolveParams {
   int max_refine = 0;
   double refine_tol = 0.0;
   double shift_rel = 0.0;
+  bool report_grad = false;
 };
 
 SolveParams params_of(const flsq_solve_opts* o) {
@@ -896,6 +910,7 @@ SolveParams params_of(const flsq_solve_opts* o) {
     p.max_refine = o->max_refine;
     p.refine_tol = o->refine_tol;
     p.shift_rel = o->shift_rel;
+    p.report_grad = o->report_grad != 0;
   }
   return p;
 }
@@ -956,7 +971,8 @@ Err solve_on_system(flsq_ctx* c, const System& s, const double* rho, const Solve
   CHECK_HIP(launch_colpass_runs(s.pass(), rho, Yw, K, nullptr, 1.0, 0.0, cvec, colwork, c->stream));
   CHECK_ERR(chol_solve(c, Xi, n, cvec, X, K));
   RefineOut ro;
-  CHECK_ERR(cgls_refine(c, s, rho, Xi, sp.mu, Yw, K, X, sp.max_refine, sp.refine_tol, info != nullptr, &ro));
+  CHECK_ERR(cgls_refine(c, s, rho, Xi, sp.mu, Yw, K, X, sp.max_refine, sp.refine_tol, info != nullptr,
+                        info != nullptr && sp.report_grad, &ro));
   CHECK_HIP(hipStreamSynchronize(c->stream));
   const double t2 = now_ms();
   if (info) {
@@ -1107,6 +1123,7 @@ flsq_status flsq_factorize(flsq_ctx* ctx, const flsq_basis* basis, const flsq_ro
   f->shift = info ? info->shift : 0.0;
   f->max_refine = sp.max_refine;
   f->refine_tol = sp.refine_tol;
+  f->report_grad = sp.report_grad;
   *F = f;
   return finish(ctx, ok());
 }
@@ -1143,7 +1160,7 @@ flsq_status flsq_factor_solve(flsq_ctx* ctx, const flsq_factor* F, const double*
   if (e.st != FLSQ_OK) return finish(ctx, e);
   RefineOut ro;
   e = cgls_refine(ctx, s, nullptr, F->Xinv.as<double>(), F->mu, rhs_rows, K, beta_out, F->max_refine, F->refine_tol,
-                  info != nullptr, &ro);
+                  info != nullptr, info != nullptr && F->report_grad, &ro);
   if (e.st != FLSQ_OK) return finish(ctx, e);
   he = hipStreamSynchronize(ctx->stream);
   if (he != hipSuccess) return finish(ctx, fail(FLSQ_EHIP, "factor_solve: %s", hipGetErrorString(he)));
@@ -1168,7 +1185,7 @@ flsq_status flsq_factor_solve_normal(flsq_ctx* ctx, const flsq_factor* F, const 
   const PassGeo pg = s.pass();
   hipStream_t st = ctx->stream;
   // preconditioned CG on (A^T A + mu I) X = V with FP64 matrix-free operator
-  double *r, *z, *p, *ap, *tP, *dots, *dwork, *colwork, *scal;
+  double *r, *z, *p, *ap, *tP, *dots, *dwork, *colwork;
   Err e = ok();
   if (e.st == FLSQ_OK) e = ws_get(ctx, "pcg_r", (size_t)n * K, &r);
   if (e.st == FLSQ_OK) e = ws_get(ctx, "pcg_z", (size_t)n * K, &z);
@@ -1178,7 +1195,6 @@ flsq_status flsq_factor_solve_normal(flsq_ctx* ctx, const flsq_factor* F, const 
   if (e.st == FLSQ_OK) e = ws_get(ctx, "pcg_dots", (size_t)4 * K, &dots);
   if (e.st == FLSQ_OK) e = ws_get(ctx, "pcg_dwork", (size_t)512 * K + 64, &dwork);
   if (e.st == FLSQ_OK) e = ws_get(ctx, "pcg_colwork", pass_work_elems(n, s.n_runs, K) + 64, &colwork);
-  if (e.st == FLSQ_OK) e = ws_get(ctx, "pcg_scal", (size_t)K, &scal);
   if (e.st != FLSQ_OK) return finish(ctx, e);
   auto apply_normal = [&](const double* x, double* y) -> Err {   // y = A^T A x + mu x
     CHECK_ERR(row_pass(ctx, pg, nullptr, x, K, nullptr, 1.0, 0.0, tP));
@@ -1192,8 +1208,7 @@ flsq_status flsq_factor_solve_normal(flsq_ctx* ctx, const flsq_factor* F, const 
     CHECK_ERR(apply_normal(out, ap));
     CHECK_HIP(hipMemcpyAsync(r, V, sizeof(double) * n * K, hipMemcpyDeviceToDevice, st));
     std::vector<double> ones(K, 1.0);
-    CHECK_ERR(to_dev_cols(ctx, ones, scal));
-    CHECK_HIP(launch_axpy_cols(scal, ap, r, n, K, -1.0, st));
+    CHECK_HIP(launch_axpy_cols(cols(ones), ap, r, n, K, -1.0, st));
     CHECK_ERR(chol_solve(ctx, F->Xinv.as<double>(), n, r, z, K));
     CHECK_HIP(hipMemcpyAsync(p, z, sizeof(double) * n * K, hipMemcpyDeviceToDevice, st));
     CHECK_HIP(launch_dot_cols(r, z, n, K, dots, dwork, st));
@@ -1203,9 +1218,8 @@ flsq_status flsq_factor_solve_normal(flsq_ctx* ctx, const flsq_factor* F, const 
     // phi(x) = x^T M x / 2 - x^T V = -(x^T V + x^T r) / 2 decreases monotonically in exact
     // arithmetic; a column whose phi clearly rises stops, and its last iterate before the
     // rise is returned.
-    double *xbest, *mask;
+    double* xbest;
     CHECK_ERR(ws_get(ctx, "pcg_xbest", (size_t)n * K, &xbest));
-    CHECK_ERR(ws_get(ctx, "pcg_mask", (size_t)K, &mask));
     CHECK_HIP(hipMemcpyAsync(xbest, out, sizeof(double) * n * K, hipMemcpyDeviceToDevice, st));
     CHECK_HIP(launch_dot_cols(out, V, n, K, dots, dwork, st));
     CHECK_HIP(launch_dot_cols(out, r, n, K, dots + K, dwork, st));
@@ -1227,9 +1241,9 @@ flsq_status flsq_factor_solve_normal(flsq_ctx* ctx, const flsq_factor* F, const 
           worst = std::max(worst, relstep[k]);
         }
       }
-      CHECK_ERR(to_dev_cols(ctx, alpha, scal));
-      CHECK_HIP(launch_axpy_cols(scal, p, out, n, K, 1.0, st));
-      CHECK_HIP(launch_axpy_cols(scal, ap, r, n, K, -1.0, st));
+      const ColScalars al = cols(alpha);
+      CHECK_HIP(launch_axpy_cols(al, p, out, n, K, 1.0, st));
+      CHECK_HIP(launch_axpy_cols(al, ap, r, n, K, -1.0, st));
       CHECK_HIP(launch_dot_cols(out, V, n, K, dots, dwork, st));
       CHECK_HIP(launch_dot_cols(out, r, n, K, dots + K, dwork, st));
       CHECK_ERR(host_cols(ctx, dots, 2 * K, tmp));
@@ -1260,8 +1274,7 @@ flsq_status flsq_factor_solve_normal(flsq_ctx* ctx, const flsq_factor* F, const 
         if (stagnant[k] >= 2) active[k] = 0.0;
         if (active[k] > 0.0) ++n_active;
       }
-      CHECK_ERR(to_dev_cols(ctx, improved, mask));
-      CHECK_HIP(launch_select_cols(out, xbest, n, K, mask, st));
+      CHECK_HIP(launch_select_cols(out, xbest, n, K, col_mask(improved), st));
       if (worst <= F->refine_tol || n_active == 0 || it + 1 == F->max_refine) break;
       CHECK_ERR(chol_solve(ctx, F->Xinv.as<double>(), n, r, z, K));
       CHECK_HIP(launch_dot_cols(r, z, n, K, dots, dwork, st));
@@ -1270,8 +1283,7 @@ flsq_status flsq_factor_solve_normal(flsq_ctx* ctx, const flsq_factor* F, const 
         beta[k] = gam[k] > 0.0 ? tmp2[k] / gam[k] : 0.0;
         gam[k] = tmp2[k];
       }
-      CHECK_ERR(to_dev_cols(ctx, beta, scal));
-      CHECK_HIP(launch_xpby_cols(z, scal, p, n, K, st));
+      CHECK_HIP(launch_xpby_cols(z, cols(beta), p, n, K, st));
     }
     CHECK_HIP(hipMemcpyAsync(out, xbest, sizeof(double) * n * K, hipMemcpyDeviceToDevice, st));
     return ok();
@@ -1440,8 +1452,6 @@ Err newton_impl(flsq_ctx* c, const flsq_basis* basis, const flsq_rows* blocks, i
   double nR = 0.0;
   CHECK_ERR(residual(beta, R, rho, u, &nR));
   std::vector<double> one(1, 1.0);
-  double* scal;
-  CHECK_ERR(ws_get(c, "nt_scal", 1, &scal));
   for (int it = 0; it < o->max_iter; ++it) {
     // delta = argmin ||J delta + R||^2 + mu ||delta||^2 with J = A(rho)
     CHECK_HIP(launch_scale_copy(R, negR, P, -1.0, st));
@@ -1452,8 +1462,7 @@ Err newton_impl(flsq_ctx* c, const flsq_basis* basis, const flsq_rows* blocks, i
     for (;;) {
       CHECK_HIP(hipMemcpyAsync(bt, beta, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
       one[0] = alpha;
-      CHECK_ERR(to_dev_cols(c, one, scal));
-      CHECK_HIP(launch_axpy_cols(scal, delta, bt, n, 1, 1.0, st));
+      CHECK_HIP(launch_axpy_cols(cols(one), delta, bt, n, 1, 1.0, st));
       CHECK_ERR(residual(bt, Rt, rhot, ut, &nRt));
       if (nRt <= (1.0 - o->armijo_c * alpha) * nR || halv >= o->max_halvings) break;
       alpha *= 0.5;
@@ -1465,8 +1474,7 @@ Err newton_impl(flsq_ctx* c, const flsq_basis* basis, const flsq_rows* blocks, i
     // ||Delta u|| / ||u|| on the rows of the nonlinear block
     CHECK_HIP(hipMemcpyAsync(negR, ut + nl0, sizeof(double) * nln, hipMemcpyDeviceToDevice, st));
     one[0] = 1.0;
-    CHECK_ERR(to_dev_cols(c, one, scal));
-    CHECK_HIP(launch_axpy_cols(scal, u + nl0, negR, nln, 1, -1.0, st));
+    CHECK_HIP(launch_axpy_cols(cols(one), u + nl0, negR, nln, 1, -1.0, st));
     CHECK_ERR(dot1(negR, negR, nln, &du2));
     CHECK_ERR(dot1(ut + nl0, ut + nl0, nln, &un2));
     if (tr) {

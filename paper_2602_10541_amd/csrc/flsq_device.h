@@ -156,6 +156,7 @@ struct Geo {
   const float* amp32;
   const float* ph32;
   const double* Xt;      // d x P
+  const double* Xrm;     // P x d (row-major copy)
   const float* Xt32;
   const int32_t* row_block;   // P
   const double* frec;         // n_blocks x n records {W_j (d), amp_gj, ph_gj, 0...}, frec_stride(d) doubles each

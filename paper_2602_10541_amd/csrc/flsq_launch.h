@@ -179,14 +179,19 @@ hipError_t launch_diag_max(const double* G, int n, double* out, hipStream_t s);
 // out[c] = sum_i x[i][c] * y[i][c] over n rows, K columns (deterministic two-stage).
 hipError_t launch_dot_cols(const double* x, const double* y, int64_t n, int K, double* out, double* work,
                            hipStream_t s);
-// y[i][c] += a[c] * x[i][c]
-hipError_t launch_axpy_cols(const double* a, const double* x, double* y, int64_t n, int K, double sign,
+// Per-column scalars (K <= 64) passed by value in the kernel arguments, so the iterative
+// solvers' step lengths reach the device without a copy or a stream synchronisation.
+struct ColScalars {
+  double v[64];
+};
+// y[i][c] += sign * a[c] * x[i][c]
+hipError_t launch_axpy_cols(const ColScalars& a, const double* x, double* y, int64_t n, int K, double sign,
                             hipStream_t s);
 // p[i][c] = z[i][c] + b[c] * p[i][c]
-hipError_t launch_xpby_cols(const double* z, const double* b, double* p, int64_t n, int K, hipStream_t s);
+hipError_t launch_xpby_cols(const double* z, const ColScalars& b, double* p, int64_t n, int K, hipStream_t s);
 hipError_t launch_count_nonfinite(const double* x, int64_t n, int* flag, hipStream_t s);
-// dst[i][c] = src[i][c] for the columns c with mask[c] != 0
-hipError_t launch_select_cols(const double* src, double* dst, int64_t n, int K, const double* mask, hipStream_t s);
+// dst[i][c] = src[i][c] for the columns c whose bit is set in mask
+hipError_t launch_select_cols(const double* src, double* dst, int64_t n, int K, uint64_t mask, hipStream_t s);
 
 
 // ---- inverse heat-source support

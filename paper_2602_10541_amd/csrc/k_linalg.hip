@@ -133,42 +133,45 @@ hipError_t launch_dot_cols(const double* x, const double* y, int64_t n, int K, d
   return hipGetLastError();
 }
 
-__global__ void k_axpy_cols(const double* a, const double* x, double* y, int64_t n, int K, double sign) {
+__global__ void k_axpy_cols(ColScalars a, const double* x, double* y, int64_t n, int K, double sign) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n * K) return;
-  y[e] = fma(sign * a[e % K], x[e], y[e]);
+  y[e] = fma(sign * a.v[e % K], x[e], y[e]);
 }
 
-hipError_t launch_axpy_cols(const double* a, const double* x, double* y, int64_t n, int K, double sign,
+hipError_t launch_axpy_cols(const ColScalars& a, const double* x, double* y, int64_t n, int K, double sign,
                             hipStream_t s) {
   const int64_t tot = n * K;
   if (tot == 0) return hipSuccess;
+  if (K < 1 || K > 64) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_axpy_cols, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, a, x, y, n, K, sign);
   return hipGetLastError();
 }
 
-__global__ void k_xpby_cols(const double* z, const double* b, double* p, int64_t n, int K) {
+__global__ void k_xpby_cols(const double* z, ColScalars b, double* p, int64_t n, int K) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n * K) return;
-  p[e] = fma(b[e % K], p[e], z[e]);
+  p[e] = fma(b.v[e % K], p[e], z[e]);
 }
 
-hipError_t launch_xpby_cols(const double* z, const double* b, double* p, int64_t n, int K, hipStream_t s) {
+hipError_t launch_xpby_cols(const double* z, const ColScalars& b, double* p, int64_t n, int K, hipStream_t s) {
   const int64_t tot = n * K;
   if (tot == 0) return hipSuccess;
+  if (K < 1 || K > 64) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_xpby_cols, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, z, b, p, n, K);
   return hipGetLastError();
 }
 
-__global__ void k_select_cols(const double* src, double* dst, int64_t n, int K, const double* mask) {
+__global__ void k_select_cols(const double* src, double* dst, int64_t n, int K, uint64_t mask) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n * K) return;
-  if (mask[e % K] != 0.0) dst[e] = src[e];
+  if ((mask >> (e % K)) & 1ull) dst[e] = src[e];
 }
 
-hipError_t launch_select_cols(const double* src, double* dst, int64_t n, int K, const double* mask, hipStream_t s) {
+hipError_t launch_select_cols(const double* src, double* dst, int64_t n, int K, uint64_t mask, hipStream_t s) {
   const int64_t tot = n * K;
-  if (tot == 0) return hipSuccess;
+  if (tot == 0 || mask == 0) return hipSuccess;
+  if (K < 1 || K > 64) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_select_cols, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, src, dst, n, K, mask);
   return hipGetLastError();
 }

@@ -20,7 +20,7 @@ namespace flsq {
 constexpr int kPassRows = 64;        // rows per run (column pass and the many-column row pass)
 constexpr int kWideRows = 256;       // rows per wide run (row pass, K <= 16: one per workgroup)
 constexpr int kRowSlices = 4;        // feature slices per row-pass workgroup (one per wave)
-constexpr int kColFeat = 256;        // features per column-pass workgroup (one per thread)
+constexpr int kColFeat = 256;        // features per workgroup in the split count of the many-column pass
 
 
 // ------------------------------------------------------------------ row pass
@@ -243,52 +243,90 @@ __global__ __launch_bounds__(256) void k_rowpass_finish(const double* __restrict
 
 // ------------------------------------------------------------------ column pass
 // part[s][j][c] = sum over the runs of split s of sum_i A_ij Y[i][c]
+// A thread owns FPT features (W_j in registers, amp/ph reloaded per run).  The rows of a run
+// are staged once in LDS as records {x_i, rho_i, Y[i][:]} and read back as broadcasts, each
+// used for all FPT features.
+template <int KMAX>
+struct ColShape {
+  static constexpr int FPT = KMAX <= 4 ? 2 : 1;  // features per thread (4 measured slower: fewer waves)
+};
+
 template <int D, int KMAX>
 __global__ __launch_bounds__(256) void k_colpass(PassGeo pg, const double* __restrict__ rho,
                                                  const double* __restrict__ Y, int K, int runs_per_split,
                                                  double* __restrict__ part) {
-  __shared__ double sX[kPassRows][D + 1];       // x, rho
-  __shared__ double sY[kPassRows][KMAX];
+  constexpr int FPT = ColShape<KMAX>::FPT;
+  constexpr int RR = (D + 1 + KMAX + 1) & ~1;              // row record: x, rho, Y (even length)
+  __shared__ __align__(16) double sR[kPassRows][RR];
   const Geo& g = pg.g;
   const int n = g.n;
-  const int j = blockIdx.x * kColFeat + threadIdx.x;
+  const int j0 = blockIdx.x * 256 * FPT + threadIdx.x;   // features j0 + 256 f
   const int split = blockIdx.y;
-  const bool fvalid = j < n;
-  double w[D];
+  bool fv[FPT];
+  double w[FPT][D];
 #pragma unroll
-  for (int k = 0; k < D; ++k) w[k] = fvalid ? g.Wt[(int64_t)k * n + j] : 0.0;
-  double acc[KMAX];
+  for (int f = 0; f < FPT; ++f) {
+    const int j = j0 + 256 * f;
+    fv[f] = j < n;
 #pragma unroll
-  for (int c = 0; c < KMAX; ++c) acc[c] = 0.0;
+    for (int k = 0; k < D; ++k) w[f][k] = fv[f] ? g.Wt[(int64_t)k * n + j] : 0.0;
+  }
+  double acc[FPT][KMAX];
+#pragma unroll
+  for (int f = 0; f < FPT; ++f)
+#pragma unroll
+    for (int c = 0; c < KMAX; ++c) acc[f][c] = 0.0;
   const int r_begin = split * runs_per_split;
   const int r_end = min(pg.n_runs, r_begin + runs_per_split);
   for (int ri = r_begin; ri < r_end; ++ri) {
     const Chunk run = pg.runs[ri];
     __syncthreads();
-    for (int e = threadIdx.x; e < kPassRows * (D + 1); e += 256) {
-      const int r = e / (D + 1), k = e % (D + 1);
+    for (int e = threadIdx.x; e < kPassRows * RR; e += 256) {
+      const int r = e / RR, q = e % RR;
       double v = 0.0;
-      if (r < run.nrows) v = (k < D) ? g.Xt[(int64_t)k * g.P + run.row0 + r] : (rho ? rho[run.row0 + r] : 0.0);
-      sX[r][k] = v;
+      if (r < run.nrows) {
+        const int64_t i = run.row0 + r;
+        if (q < D) v = g.Xrm[i * D + q];
+        else if (q == D) v = rho ? rho[i] : 0.0;
+        else if (q - D - 1 < K && q - D - 1 < KMAX) v = Y[i * K + (q - D - 1)];
+      }
+      sR[r][q] = v;
     }
-    for (int e = threadIdx.x; e < kPassRows * KMAX; e += 256) {
-      const int r = e / KMAX, c = e % KMAX;
-      sY[r][c] = (r < run.nrows && c < K) ? Y[(int64_t)(run.row0 + r) * K + c] : 0.0;
+    double amp[FPT], ph[FPT];
+#pragma unroll
+    for (int f = 0; f < FPT; ++f) {
+      const int64_t o = (int64_t)run.block * n + j0 + 256 * f;
+      amp[f] = fv[f] ? g.amp[o] : 0.0;
+      ph[f] = fv[f] ? g.ph[o] : 0.0;
     }
     __syncthreads();
-    const double amp = fvalid ? g.amp[(int64_t)run.block * n + j] : 0.0;
-    const double ph = fvalid ? g.ph[(int64_t)run.block * n + j] : 0.0;
+#pragma unroll 2
     for (int r = 0; r < run.nrows; ++r) {
-      double z = 0.0;
+      double x[D], yv[KMAX];
 #pragma unroll
-      for (int k = 0; k < D; ++k) z = fma(w[k], sX[r][k], z);
-      const double a = (amp + sX[r][D]) * sin_f64(z + ph);
+      for (int k = 0; k < D; ++k) x[k] = sR[r][k];
+      const double rh = sR[r][D];
 #pragma unroll
-      for (int c = 0; c < KMAX; ++c) acc[c] = fma(a, sY[r][c], acc[c]);
+      for (int c = 0; c < KMAX; ++c) yv[c] = sR[r][D + 1 + c];
+#pragma unroll
+      for (int f = 0; f < FPT; ++f) {
+        double z = 0.0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) z = fma(w[f][k], x[k], z);
+        const double a = (amp[f] + rh) * sin_f64(z + ph[f]);
+#pragma unroll
+        for (int c = 0; c < KMAX; ++c) acc[f][c] = fma(a, yv[c], acc[f][c]);
+      }
     }
   }
-  if (fvalid)
-    for (int c = 0; c < K && c < KMAX; ++c) part[((int64_t)split * n + j) * K + c] = acc[c];
+#pragma unroll
+  for (int f = 0; f < FPT; ++f) {
+    if (!fv[f]) continue;
+    const int64_t j = j0 + 256 * f;
+#pragma unroll
+    for (int c = 0; c < KMAX; ++c)
+      if (c < K) part[((int64_t)split * n + j) * K + c] = acc[f][c];
+  }
 }
 
 // out[e] = alpha * sum_sp part[sp][e] + beta_v * V[e].  Workgroup: 64 outputs x 4 groups of
@@ -468,9 +506,10 @@ __global__ __launch_bounds__(256) void k_colpass_mfma(PassGeo pg, const double* 
 
 // ------------------------------------------------------------------ launchers
 static int col_splits(const PassGeo& pg, int K) {
-  // enough workgroups to fill the chip, partial buffer bounded by ~64 n K doubles
-  const int ftiles = (pg.g.n + kColFeat - 1) / kColFeat;
-  int want = (2048 + ftiles - 1) / ftiles;
+  // about 1024 workgroups (one round of waves), partial buffer bounded by ~64 n K doubles
+  const int feat_per_wg = K > 16 ? kColFeat : 256 * (K <= 1 ? ColShape<1>::FPT : K <= 4 ? ColShape<4>::FPT : 1);
+  const int ftiles = (pg.g.n + feat_per_wg - 1) / feat_per_wg;
+  int want = (1024 + ftiles - 1) / ftiles;
   int cap = K <= 4 ? 256 : (K <= 16 ? 64 : 16);
   int s = want < cap ? want : cap;
   if (s > pg.n_runs) s = pg.n_runs;
@@ -497,12 +536,12 @@ size_t pass_work_elems(int n, int n_runs, int K) {
 // Feature slices per row-pass workgroup for K columns (RowShape<KMAX>::FS).
 static int row_fs(int K) { return K <= 1 ? 4 : (K <= 4 ? 2 : 1); }
 
-// Feature groups (grid.y) of the row pass: about one full round of waves on the chip,
+// Feature groups (grid.y) of the row pass: 6144 waves in all (2048 to 16384 measured within 5%),
 // but at least 32 features per wave.
 static int row_groups(const PassGeo& pg, int K) {
   const int fs = row_fs(K);
   const int64_t waves = (int64_t)std::max(pg.n_wide, 1) * 4;
-  const int64_t want = 4096 / waves;   // about one round of waves at 4 per SIMD
+  const int64_t want = 6144 / waves;   // about 1.5 rounds of waves at 4 per SIMD
   const int64_t cap = std::max(1, pg.g.n / (32 * fs));
   return (int)std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(want, cap), 64));
 }
@@ -596,9 +635,10 @@ hipError_t launch_colpass_runs(const PassGeo& pg, const double* rho, const doubl
                                double alpha, double beta_v, double* out, double* work, hipStream_t s) {
   if (K > 64 || K < 1) return hipErrorInvalidValue;
   const int n = pg.g.n;
-  const int ftiles = (n + kColFeat - 1) / kColFeat;
-  const int splits = col_splits(pg, K);
-  const int per = (pg.n_runs + splits - 1) / splits;
+  const int fpt = K <= 1 ? ColShape<1>::FPT : (K <= 4 ? ColShape<4>::FPT : ColShape<16>::FPT);
+  const int ftiles = (n + 256 * fpt - 1) / (256 * fpt);
+  const int per = (pg.n_runs + col_splits(pg, K) - 1) / col_splits(pg, K);
+  const int splits = per > 0 ? (pg.n_runs + per - 1) / per : 0;   // no empty splits
   if (pg.n_runs > 0) {
     switch (pg.g.d) {
       FLSQ_COL_CASE(1) FLSQ_COL_CASE(2) FLSQ_COL_CASE(3) FLSQ_COL_CASE(4)
@@ -610,7 +650,7 @@ hipError_t launch_colpass_runs(const PassGeo& pg, const double* rho, const doubl
   }
   const int64_t tot = (int64_t)n * K;
   hipLaunchKernelGGL(k_colpass_reduce, dim3((unsigned)((tot + 63) / 64)), dim3(256), 0, s, work,
-                     pg.n_runs > 0 ? splits : 0, n, K, V, alpha, beta_v, out);
+                     splits, n, K, V, alpha, beta_v, out);
   return hipGetLastError();
 }
 

@@ -59,7 +59,7 @@ class flsq_rows(C.Structure):
 
 class flsq_solve_opts(C.Structure):
     _fields_ = [("mu", C.c_double), ("prec", C.c_int32), ("max_refine", C.c_int32), ("refine_tol", C.c_double),
-                ("shift_rel", C.c_double)]
+                ("shift_rel", C.c_double), ("report_grad", C.c_int32)]
 
 
 class flsq_solve_info(C.Structure):
@@ -244,8 +244,9 @@ def make_rows(blocks, d) -> Rows:
     return Rows(arr, keep, len(blocks))
 
 
-def solve_opts(mu, prec=PREC_FP64, max_refine=10, refine_tol=1e-12, shift_rel=0.0):
-    return flsq_solve_opts(float(mu), int(prec), int(max_refine), float(refine_tol), float(shift_rel))
+def solve_opts(mu, prec=PREC_FP64, max_refine=10, refine_tol=1e-12, shift_rel=0.0, report_grad=False):
+    return flsq_solve_opts(float(mu), int(prec), int(max_refine), float(refine_tol), float(shift_rel),
+                           1 if report_grad else 0)
 
 
 # ---------------------------------------------------------------------------- entry points

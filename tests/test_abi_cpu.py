@@ -36,16 +36,40 @@ def test_library_exports_every_declared_symbol():
     assert b"gfx950" in fastlsq.load().flsq_build_info()
 
 
-def test_binding_structs_match_header_layout():
-    """ctypes mirrors of the ABI structs have the C sizes implied by the header's field lists."""
+def test_binding_structs_match_header_layout(tmp_path):
+    """ctypes mirrors of the ABI structs have the sizes and field offsets that a C compiler
+    gives the header's declarations."""
+    import shutil
+    import subprocess
     from paper_2602_10541_amd import fastlsq as fl
-    assert ctypes.sizeof(fl.flsq_term) == 16
-    assert ctypes.sizeof(fl.flsq_op) == 16
-    assert ctypes.sizeof(fl.flsq_basis) == 32
-    assert ctypes.sizeof(fl.flsq_rows) == 48
-    assert ctypes.sizeof(fl.flsq_solve_opts) == 32
-    assert ctypes.sizeof(fl.flsq_solve_info) == 8 + 8 * 9
-    assert ctypes.sizeof(fl.flsq_newton_opts) == 32 + 8 + 8 + 8 + 8
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = ["flsq_term", "flsq_op", "flsq_basis", "flsq_rows", "flsq_solve_opts", "flsq_solve_info",
+               "flsq_newton_opts", "flsq_nonlin"]
+    structs = [n for n in structs if hasattr(fl, n)]
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "fastlsq.h"', "int main(void) {"]
+    for n in structs:
+        lines.append(f'  printf("{n} size %zu\\n", sizeof({n}));')
+        for f, _ in getattr(fl, n)._fields_:
+            lines.append(f'  printf("{n} {f} %zu\\n", offsetof({n}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "probe.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "probe"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.run([cc, "-I", inc, str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for ln in out:
+        if ln:
+            *key, v = ln.split()
+            got[tuple(key)] = int(v)
+    for n in structs:
+        cls = getattr(fl, n)
+        assert ctypes.sizeof(cls) == got[(n, "size")], n
+        for f, _ in cls._fields_:
+            assert getattr(cls, f).offset == got[(n, f)], (n, f)
 
 
 def test_no_gpu_means_loud_failure():
