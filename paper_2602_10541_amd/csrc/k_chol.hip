@@ -8,12 +8,15 @@
 // Block 0 is factored by k_potrf before the loop; k_trinv inverts all diagonal blocks in one
 // launch afterwards (they are independent once U is known).
 //
-// The 64 x 64 factorisation runs on one 256-thread workgroup: wave q keeps rows
-// 16q .. 16q + 15 of the block (lane j: column j) in registers.  Rows are produced four at
-// a time by the wave that owns them: the pivots and the coupling entries U_{l,i} inside a
-// group move between lanes with register reads only.  The group's rows are published to
-// LDS (each LDS row is written once) and, after one barrier, every wave applies a rank-4
-// update to its rows below the group, reading the row entries as broadcasts.
+// The 64 x 64 factorisation runs on one 256-thread workgroup and keeps the block in the
+// FP64 MFMA 16x16x4 accumulator layout: wave q holds rows 16q .. 16q + 15 as four 16 x 16
+// tiles (lane l, slot v: row 16q + 4v + l / 16, column 16c + l % 16).  Rows are factored four
+// at a time by the wave that owns them: the group's four rows pass through LDS into a
+// lane-per-column layout, where the four pivots and the couplings inside the group need only
+// register reads; the finished rows are published to LDS, and after one barrier
+// every wave applies their rank-4 update to its rows below the group as one MFMA per tile.
+// The same layout lets the trailing-update kernel apply the last block row's update to the
+// next diagonal block in registers and go straight on to its factorisation.
 #include "flsq_device.h"
 #include "flsq_launch.h"
 
@@ -33,79 +36,92 @@ __device__ __forceinline__ double rsqrt_nr(double x) {
   return r * fma(-0.5 * x, r * r, 1.5);
 }
 
-// Factor the diagonal block at k0 in place; all 256 threads of the workgroup call it
-// (S: kNb * kNb doubles of LDS, sbad: one int of LDS).  A short last block (nbk < 64) is
-// padded with the identity, which leaves the leading nbk x nbk factor unchanged.  A
-// non-positive or non-finite pivot is recorded in *info (1-based global index, first
-// failure) and replaced by 1 so every step completes.  Entries below the diagonal are scratch.
-__device__ __forceinline__ void potrf64_wg(double* G, int n, int k0, int* info, double* S, int* sbad) {
+// Diagonal block at k0 into the accumulator layout (wave q: rows 16q + 4v + l / 16, columns
+// 16c + l % 16).  Only the upper triangle is read; a short last block (nbk < 64) is padded
+// with the identity, which leaves the leading nbk x nbk factor unchanged.
+__device__ __forceinline__ void potrf64_load(const double* G, int n, int k0, f64x4 acc[4]) {
   const int nbk = min(kNb, n - k0);
-  const int j = threadIdx.x & 63;
-  const int q = threadIdx.x >> 6;
-  double* base = G + (int64_t)k0 * n + k0 + j;
-  double v[16];
+  const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+  const double* base = G + (int64_t)k0 * n + k0;
 #pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const int i = 16 * q + r;
-    v[r] = (j < nbk && i < nbk && i <= j) ? base[(int64_t)i * n] : (i == j ? 1.0 : 0.0);
-  }
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = 16 * q + 4 * v + (lane >> 4), j = 16 * c + (lane & 15);
+      acc[c][v] = (i < nbk && j < nbk && i <= j) ? base[(int64_t)i * n + j] : (i == j ? 1.0 : 0.0);
+    }
+}
+
+// Factor the block held in acc (all 256 threads; S: kNb * kNb doubles of LDS, sbad: one int
+// of LDS) and store the upper triangle of U_kk at k0.  A non-positive or non-finite pivot is
+// recorded in *info (1-based global index, first failure) and replaced by 1 so every step
+// completes.  Entries below the diagonal are never stored.
+__device__ __forceinline__ void potrf64_factor(f64x4 acc[4], double* G, int n, int k0, int* info, double* S,
+                                               int* sbad) {
+  const int nbk = min(kNb, n - k0);
+  const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+  const int r16 = lane & 15, k4 = lane >> 4;
+  double* base = G + (int64_t)k0 * n + k0;
   if (threadIdx.x == 0) *sbad = -1;
 #pragma unroll
-  for (int L = 0; L < kNb; L += 4) {
-    if (q == (L >> 4)) {
+  for (int g = 0; g < kNb / 4; ++g) {
+    const int L = 4 * g, q0 = g >> 2, v0 = g & 3;
+    if (q == q0) {
+      // rows L .. L + 3 (slot v0 of the four tiles) to one column per lane, through LDS
+#pragma unroll
+      for (int c = 0; c < 4; ++c) S[(L + k4) * kNb + 16 * c + r16] = acc[c][v0];
+      double x[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) x[a] = S[(L + a) * kNb + lane];
       int bad = -1;
 #pragma unroll
       for (int a = 0; a < 4; ++a) {
         const int l = L + a;
-        const double diag = lane_bcast(v[l & 15], l);
+        const double diag = lane_bcast(x[a], l);
         const bool fail = !(diag > 0.0) || !isfinite(diag);
         bad = (fail && bad < 0) ? l : bad;
         const double piv = fail ? 1.0 : diag;
         const double r = rsqrt_nr(piv);
-        const double ulj = (j > l) ? v[l & 15] * r : ((j == l) ? piv * r : 0.0);
-        v[l & 15] = ulj;
-        S[l * kNb + j] = ulj;
+        const double u = (lane > l) ? x[a] * r : ((lane == l) ? piv * r : 0.0);
+        x[a] = u;
 #pragma unroll
-        for (int i = l + 1; i < L + 4; ++i) v[i & 15] = fma(-lane_bcast(ulj, i), ulj, v[i & 15]);
+        for (int b = a + 1; b < 4; ++b) x[b] = fma(-lane_bcast(u, L + b), u, x[b]);
       }
-      if (j == 0 && bad >= 0 && *sbad < 0) *sbad = bad;
+#pragma unroll
+      for (int a = 0; a < 4; ++a) S[(L + a) * kNb + lane] = x[a];
+      if (lane == 0 && bad >= 0 && *sbad < 0) *sbad = bad;
     }
     __syncthreads();
-    if (L + 4 < kNb) {
-      // all operands first (one batch of LDS reads in flight), then the multiply-adds
-      double uj[4], ui[4][16];
+    if (g + 1 < kNb / 4 && q >= q0) {
+      // rows below the group: tile (q, c) -= U_{L..L+3, rows}^T U_{L..L+3, cols}; rows of the
+      // owner wave at or above the group get a zero operand and stay as they are
+      const double ar = S[(L + k4) * kNb + 16 * q + r16];
+      const double a_op = (16 * q + r16 > L + 3) ? -ar : 0.0;
 #pragma unroll
-      for (int a = 0; a < 4; ++a) {
-        uj[a] = S[(L + a) * kNb + j];
-#pragma unroll
-        for (int r = 0; r < 16; ++r) ui[a][r] = S[(L + a) * kNb + 16 * q + r];
-      }
-      __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int i = 16 * q + r;
-        if (i >= L + 4) {
-          double x = v[r];
-#pragma unroll
-          for (int a = 0; a < 4; ++a) x = fma(-ui[a][r], uj[a], x);
-          v[r] = x;
-        }
+      for (int c = 0; c < 4; ++c) {
+        if (c < q) continue;   // below the diagonal: never read
+        const double b_op = S[(L + k4) * kNb + 16 * c + r16];
+        acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_op, b_op, acc[c], 0, 0, 0);
       }
     }
+  }
+  // every row of U_kk is final in S (the last group's barrier above); store the upper
+  // triangle once, here: a global store inside the loop would make every barrier wait for it
+#pragma unroll
+  for (int r = 0; r < kNb / 4; ++r) {
+    const int i = 4 * r + q;
+    if (i < nbk && lane >= i && lane < nbk) base[(int64_t)i * n + lane] = S[i * kNb + lane];
   }
   const int bad = *sbad;
   if (threadIdx.x == 0 && bad >= 0 && bad < nbk && *info == 0) *info = k0 + bad + 1;
-#pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const int i = 16 * q + r;
-    if (j < nbk && i <= j) base[(int64_t)i * n] = v[r];
-  }
 }
 
 __global__ __launch_bounds__(256) void k_potrf(double* G, int n, int k0, int* info) {
   __shared__ double S[kNb * kNb];
   __shared__ int sbad;
-  potrf64_wg(G, n, k0, info, S, &sbad);
+  f64x4 acc[4];
+  potrf64_load(G, n, k0, acc);
+  potrf64_factor(acc, G, n, k0, info, S, &sbad);
 }
 
 // Block row: y = U_kk^{-T} g for every column j >= k0 + kNb by forward substitution
@@ -206,8 +222,13 @@ __device__ __forceinline__ void tri_coords(int t, int nt, int* ti, int* tj) {
 // loads (all in flight together), laid out in the order the matrix cores consume them: the
 // operand of k-step kk and 16-column block c is 64 consecutive doubles, lane l holding
 // panel row 4 kk + l / 16 and column 16 c + l % 16, so every operand read is one
-// contiguous, conflict-free 512-byte access.  Workgroup 0 owns tile (0, 0), whose leading 64 x 64 quadrant is the next
-// diagonal block: after its update the workgroup factors it, reusing the same LDS.
+// contiguous, conflict-free 512-byte access.
+//
+// Workgroup 0 owns the next diagonal block (quadrant (0, 0) of tile (0, 0), which the tile's
+// own workgroup skips): it loads the block straight into the accumulator layout of the
+// factorisation, applies the update there and factors it without a round trip through
+// memory, so the critical path of a step is one 64-deep update of one block plus its
+// factorisation.
 constexpr int kSyrkPanel = 16 * 8 * 64;   // doubles per 64 x 128 panel slice
 
 __device__ __forceinline__ void syrk_fetch_panel(const double* G, int n, int k0, int c0, double* dst, int wave,
@@ -228,12 +249,32 @@ __device__ __forceinline__ void syrk_fetch_panel(const double* G, int n, int k0,
 }
 
 __global__ __launch_bounds__(256, 1) void k_syrk_potrf(double* G, int n, int k0, int* info) {
-  extern __shared__ __align__(16) double smem_d[];     // A and B panels, then the factorisation scratch
+  extern __shared__ __align__(16) double smem_d[];     // A and B panels; diagonal block: panel, then S
   const int k1 = k0 + kNb;
   const int nt = (n - k1 + 127) / 128;
-  int ti, tj;
-  tri_coords(blockIdx.x, nt, &ti, &tj);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (blockIdx.x == 0) {
+    // the next diagonal block: its update in registers, then its factorisation
+    double* sP = smem_d;
+    syrk_fetch_panel(G, n, k0, k1, sP, wave, lane);
+    f64x4 acc[4];
+    potrf64_load(G, n, k1, acc);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < kNb / 4; ++kk) {
+      const double a = -sP[(kk * 8 + wave) * 64 + lane];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        if (c < wave) continue;
+        acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, sP[(kk * 8 + c) * 64 + lane], acc[c], 0, 0, 0);
+      }
+    }
+    potrf64_factor(acc, G, n, k1, info, smem_d + kSyrkPanel, (int*)(smem_d + kSyrkPanel + kNb * kNb));
+    return;
+  }
+  int ti, tj;
+  tri_coords(blockIdx.x - 1, nt, &ti, &tj);
   const int qi = wave >> 1, qj = wave & 1;
   double* sPa = smem_d;
   double* sPb = (ti == tj) ? smem_d : smem_d + kSyrkPanel;
@@ -242,7 +283,8 @@ __global__ __launch_bounds__(256, 1) void k_syrk_potrf(double* G, int n, int k0,
   __builtin_amdgcn_s_waitcnt(0);   // this wave's loads have landed in LDS
   __syncthreads();
   const int i0 = k1 + ti * 128 + qi * 64, j0 = k1 + tj * 128 + qj * 64;
-  const bool active = !(ti == tj && qi > qj) && i0 < n && j0 < n;
+  // quadrant (0, 0) of tile (0, 0) is the next diagonal block (workgroup 0)
+  const bool active = !(ti == tj && qi > qj) && !(ti == 0 && tj == 0 && qi == 0 && qj == 0) && i0 < n && j0 < n;
   if (active) {
     const int r16 = lane & 15, k4 = lane >> 4;
     f64x4 acc[4][4];
@@ -286,10 +328,6 @@ __global__ __launch_bounds__(256, 1) void k_syrk_potrf(double* G, int n, int k0,
           const int j = j0 + 16 * c + r16;
           if (i < n && j < n && j >= i) G[(int64_t)i * n + j] = old[r][c][v] - acc[r][c][v];
         }
-  }
-  if (blockIdx.x == 0) {
-    __syncthreads();   // tile (0, 0) stored; the panels are no longer read
-    potrf64_wg(G, n, k1, info, smem_d, (int*)(smem_d + kNb * kNb));
   }
 }
 
@@ -349,7 +387,7 @@ hipError_t launch_syrk_potrf(double* G, int n, int k0, int* info, hipStream_t s)
     attr_set = true;
   }
   const int nt = (rem + 127) / 128;
-  hipLaunchKernelGGL(k_syrk_potrf, dim3(nt * (nt + 1) / 2), dim3(256), lds, s, G, n, k0, info);
+  hipLaunchKernelGGL(k_syrk_potrf, dim3(1 + nt * (nt + 1) / 2), dim3(256), lds, s, G, n, k0, info);
   return hipGetLastError();
 }
 
