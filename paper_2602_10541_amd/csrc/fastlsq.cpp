@@ -594,14 +594,21 @@ Err cholesky_inv(flsq_ctx* c, double* G, double* X, int n, int* info_host) {
     CHECK_HIP(launch_syrk_potrf(G, n, k0, info, st));
   }
   CHECK_HIP(launch_trinv_diag(G, n, X, st));
+  // split-K partials of the sparse levels: at most n^2 doubles (the full-level products hold
+  // M N <= n^2 / 4 per pair, up to 4 splits at the top level)
+  double* gwork;
+  const size_t gwork_elems = (size_t)n * n;
+  CHECK_ERR(ws_get(c, "chol_gwork", gwork_elems, &gwork));
   for (size_t l = 0; l < lvT.size(); ++l) {
-    int maxM = 0, maxN = 0;
+    int maxM = 0, maxN = 0, maxKT = 0, maxKX = 0;
     for (const GemmDesc& d : lvT[l]) {
       maxM = std::max(maxM, d.M);
       maxN = std::max(maxN, d.N);
+      maxKT = std::max(maxKT, d.K);
     }
-    CHECK_HIP(launch_gemm_tri(dd + offT[l], (int)lvT[l].size(), maxM, maxN, 1.0, st));
-    CHECK_HIP(launch_gemm_tri(dd + offX[l], (int)lvX[l].size(), maxM, maxN, -1.0, st));
+    for (const GemmDesc& d : lvX[l]) maxKX = std::max(maxKX, d.K);
+    CHECK_HIP(launch_gemm_tri(dd + offT[l], (int)lvT[l].size(), maxM, maxN, maxKT, 1.0, gwork, gwork_elems, st));
+    CHECK_HIP(launch_gemm_tri(dd + offX[l], (int)lvX[l].size(), maxM, maxN, maxKX, -1.0, gwork, gwork_elems, st));
   }
   CHECK_HIP(hipMemcpyAsync(info_host, info, sizeof(int), hipMemcpyDeviceToHost, st));
   CHECK_HIP(hipStreamSynchronize(st));

@@ -166,8 +166,11 @@ hipError_t launch_gemm_batched(const GemmDesc* d_descs, int n_batch, int maxM, i
                                int transA, hipStream_t s);
 // out[e] = sum_s part[s * len + e] (fixed summation order)
 hipError_t launch_sum_partials(const double* part, int n_split, int64_t len, double* out, hipStream_t s);
-// C = alpha A B with one upper-triangular operand (desc.tri), skipping its zero blocks.
-hipError_t launch_gemm_tri(const GemmDesc* d_descs, int n_batch, int maxM, int maxN, double alpha, hipStream_t s);
+// C = alpha A B with one upper-triangular operand (desc.tri), skipping its zero blocks.  K is
+// split across workgroups when the batch has too few tiles to fill the chip; the partials
+// use work (work_elems doubles; NULL: no split).
+hipError_t launch_gemm_tri(const GemmDesc* d_descs, int n_batch, int maxM, int maxN, int maxK, double alpha,
+                           double* work, size_t work_elems, hipStream_t s);
 // out = X (X^T v) for upper-triangular X (n x n); tmp n, work precond_work_elems(n).
 hipError_t launch_precond_apply(const double* X, int n, const double* v, double* tmp, double* work, double* out,
                                 hipStream_t s);

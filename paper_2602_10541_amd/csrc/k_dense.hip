@@ -8,6 +8,8 @@
 #include "flsq_device.h"
 #include "flsq_launch.h"
 
+#include <algorithm>
+
 namespace flsq {
 
 constexpr int kGT = 64;       // output tile (kGT x kGT) per workgroup
@@ -96,11 +98,19 @@ hipError_t launch_gemm_batched(const GemmDesc* d_descs, int n_batch, int maxM, i
 // the next slice fetched into registers while the current one is multiplied.
 constexpr int kTT = 128;
 constexpr int kTK = 16;
+constexpr int kTPad = 2;   // LDS row padding (doubles): 1 leaves bank conflicts in the transposing stash
 
-__global__ __launch_bounds__(256) void k_gemm_tri(const GemmDesc* __restrict__ descs, double alpha) {
-  __shared__ double sA[kTK][kTT + 1];   // sA[k][m]
-  __shared__ double sB[kTK][kTT + 1];   // sB[k][n]
-  const GemmDesc D = descs[blockIdx.z];
+// blockIdx.z = desc * nsplit + split.  With nsplit == 1 the tile goes to C (times alpha);
+// otherwise split s covers K range [s kper, (s + 1) kper) and its unscaled partial tile goes to
+// part[(blockIdx.z * maxM + m) * maxN + n] (zeros where the range is empty), summed by
+// k_gemm_tri_reduce.
+// Two workgroups per CU (accumulators in VGPRs): measured 17% faster than one with AGPRs.
+__global__ __launch_bounds__(256, 2) void k_gemm_tri(const GemmDesc* __restrict__ descs, double alpha, int nsplit,
+                                                  int kper, int maxM, int maxN, double* __restrict__ part) {
+  __shared__ double sA[kTK][kTT + kTPad];   // sA[k][m]
+  __shared__ double sB[kTK][kTT + kTPad];   // sB[k][n]
+  const int split = blockIdx.z % nsplit;
+  const GemmDesc D = descs[blockIdx.z / nsplit];
   const int m0 = blockIdx.y * kTT, n0 = blockIdx.x * kTT;
   if (m0 >= D.M || n0 >= D.N) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -108,6 +118,10 @@ __global__ __launch_bounds__(256) void k_gemm_tri(const GemmDesc* __restrict__ d
   int kbeg = 0, kend = D.K;
   if (D.tri == 1) kend = min(kend, n0 + kTT);
   if (D.tri == 2) kbeg = (m0 / kTK) * kTK;
+  if (nsplit > 1) {
+    kbeg = max(kbeg, split * kper);
+    kend = min(kend, (split + 1) * kper);
+  }
   f64x4 acc[4][4];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
@@ -115,10 +129,11 @@ __global__ __launch_bounds__(256) void k_gemm_tri(const GemmDesc* __restrict__ d
     for (int b = 0; b < 4; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
   // per slice each thread moves 8 entries of A (row m = e / 16, k = e % 16: 128-byte row pieces)
   // and 8 of B (row k = e / 128, column n = e % 128)
-  double ra[8], rb[8];
+  constexpr int kQ = kTK * kTT / 256;
+  double ra[kQ], rb[kQ];
   auto fetch = [&](int k0) {
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
+    for (int q = 0; q < kQ; ++q) {
       const int e = tid + 256 * q;
       const int m = e / kTK, k = e % kTK;
       const int gm = m0 + m, gk = k0 + k;
@@ -130,7 +145,7 @@ __global__ __launch_bounds__(256) void k_gemm_tri(const GemmDesc* __restrict__ d
   };
   auto stash = [&]() {
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
+    for (int q = 0; q < kQ; ++q) {
       const int e = tid + 256 * q;
       sA[e % kTK][e / kTK] = ra[q];
       sB[e / kTT][e % kTT] = rb[q];
@@ -164,14 +179,49 @@ __global__ __launch_bounds__(256) void k_gemm_tri(const GemmDesc* __restrict__ d
       for (int v = 0; v < 4; ++v) {
         const int gm = m0 + wm * 64 + a * 16 + 4 * v + (lane >> 4);
         const int gn = n0 + wn * 64 + b * 16 + (lane & 15);
-        if (gm < D.M && gn < D.N) D.C[(int64_t)gm * D.ldc + gn] = alpha * acc[a][b][v];
+        if (gm < D.M && gn < D.N) {
+          if (nsplit == 1) D.C[(int64_t)gm * D.ldc + gn] = alpha * acc[a][b][v];
+          else part[((int64_t)blockIdx.z * maxM + gm) * maxN + gn] = acc[a][b][v];
+        }
       }
 }
 
-hipError_t launch_gemm_tri(const GemmDesc* d_descs, int n_batch, int maxM, int maxN, double alpha, hipStream_t s) {
+// C[m][n] = alpha * sum_s part[desc][s][m][n] in split order.
+__global__ __launch_bounds__(256) void k_gemm_tri_reduce(const GemmDesc* __restrict__ descs, double alpha, int nsplit,
+                                                         int maxM, int maxN, const double* __restrict__ part) {
+  const GemmDesc D = descs[blockIdx.y];
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int m = (int)(e / maxN), n = (int)(e % maxN);
+  if (m >= D.M || n >= D.N) return;
+  const int64_t plane = (int64_t)maxM * maxN;
+  const double* p = part + (int64_t)blockIdx.y * nsplit * plane + e;
+  double acc = 0.0;
+  for (int sp = 0; sp < nsplit; ++sp) acc += p[sp * plane];
+  D.C[(int64_t)m * D.ldc + n] = alpha * acc;
+}
+
+// Split count: about 1024 workgroups in all, K ranges of at least 64, partials within
+// work_elems doubles.
+int gemm_tri_splits(int n_batch, int maxM, int maxN, int maxK, size_t work_elems) {
+  const int64_t tiles = (int64_t)((maxN + kTT - 1) / kTT) * ((maxM + kTT - 1) / kTT) * n_batch;
+  int ns = (int)std::min<int64_t>(std::max<int64_t>(1, (1024 + tiles - 1) / std::max<int64_t>(tiles, 1)), 64);
+  ns = std::min(ns, std::max(1, maxK / 64));
+  while (ns > 1 && (size_t)ns * n_batch * (size_t)maxM * maxN > work_elems) --ns;
+  return ns;
+}
+
+hipError_t launch_gemm_tri(const GemmDesc* d_descs, int n_batch, int maxM, int maxN, int maxK, double alpha,
+                           double* work, size_t work_elems, hipStream_t s) {
   if (n_batch == 0 || maxM == 0 || maxN == 0) return hipSuccess;
-  dim3 grid((maxN + kTT - 1) / kTT, (maxM + kTT - 1) / kTT, n_batch);
-  hipLaunchKernelGGL(k_gemm_tri, grid, dim3(256), 0, s, d_descs, alpha);
+  const int ns = work ? gemm_tri_splits(n_batch, maxM, maxN, maxK, work_elems) : 1;
+  const int kper = ((maxK + ns - 1) / ns + kTK - 1) / kTK * kTK;
+  dim3 grid((maxN + kTT - 1) / kTT, (maxM + kTT - 1) / kTT, n_batch * ns);
+  hipLaunchKernelGGL(k_gemm_tri, grid, dim3(256), 0, s, d_descs, alpha, ns, kper, maxM, maxN, work);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || ns == 1) return e;
+  const int64_t plane = (int64_t)maxM * maxN;
+  hipLaunchKernelGGL(k_gemm_tri_reduce, dim3((unsigned)((plane + 255) / 256), n_batch), dim3(256), 0, s, d_descs,
+                     alpha, ns, maxM, maxN, work);
   return hipGetLastError();
 }
 

@@ -10,7 +10,7 @@
 // chain of FMAs from zero in k order, then (amp_gj + rho_i) * sin(z + ph_gj).  The refinement
 // and the adjoint solve apply A and A^T in separate kernels; if the two disagreed even in the
 // last place, the operator they form would no longer be A^T A for one A, and on these
-// systems (cond(A)^2 near 1/eps) that asymmetry is amplified by 1/lambda_min into the
+// systems (cond(A)^2 near 1/eps) that asymmetry can be amplified by 1/lambda_min into the
 // solution.
 #include "flsq_device.h"
 #include "flsq_launch.h"
