@@ -408,6 +408,7 @@ const I8Moduli& i8_moduli() {
               break;
             }
         m.cinv[a][k] = inv;
+        m.cinvf[a][k] = (float)inv;
       }
     return m;
   }();

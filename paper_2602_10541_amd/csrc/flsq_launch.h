@@ -77,6 +77,7 @@ struct I8Moduli {
   float pf[kI8MaxMod];
   float inv_pf[kI8MaxMod];
   int cinv[kI8MaxMod][kI8MaxMod];    // cinv[m][k] = p_m^{-1} mod p_k for m < k
+  float cinvf[kI8MaxMod][kI8MaxMod]; // the same as floats (exact)
 };
 struct I8GemmJob {
   const int8_t* R;     // residues [n_mod][KB][n_pad][64]

@@ -107,8 +107,8 @@ constexpr int kTPad = 2;   // LDS row padding (doubles): 1 leaves bank conflicts
 // Two workgroups per CU (accumulators in VGPRs): measured 17% faster than one with AGPRs.
 __global__ __launch_bounds__(256, 2) void k_gemm_tri(const GemmDesc* __restrict__ descs, double alpha, int nsplit,
                                                   int kper, int maxM, int maxN, double* __restrict__ part) {
-  __shared__ double sA[kTK][kTT + kTPad];   // sA[k][m]
-  __shared__ double sB[kTK][kTT + kTPad];   // sB[k][n]
+  __shared__ double sA[2][kTK][kTT + kTPad];   // sA[buf][k][m]
+  __shared__ double sB[2][kTK][kTT + kTPad];   // sB[buf][k][n]
   const int split = blockIdx.z % nsplit;
   const GemmDesc D = descs[blockIdx.z / nsplit];
   const int m0 = blockIdx.y * kTT, n0 = blockIdx.x * kTT;
@@ -143,33 +143,42 @@ __global__ __launch_bounds__(256, 2) void k_gemm_tri(const GemmDesc* __restrict_
       rb[q] = (gkb < kend && gn < D.N) ? D.B[(int64_t)gkb * D.ldb + gn] : 0.0;
     }
   };
-  auto stash = [&]() {
+  auto stash = [&](int buf) {
 #pragma unroll
     for (int q = 0; q < kQ; ++q) {
       const int e = tid + 256 * q;
-      sA[e % kTK][e / kTK] = ra[q];
-      sB[e / kTT][e % kTT] = rb[q];
+      sA[buf][e % kTK][e / kTK] = ra[q];
+      sB[buf][e / kTT][e % kTT] = rb[q];
     }
   };
-  if (kbeg < kend) fetch(kbeg);
-  for (int k0 = kbeg; k0 < kend; k0 += kTK) {
-    __syncthreads();
-    stash();
-    __syncthreads();
-    if (k0 + kTK < kend) fetch(k0 + kTK);
+  // Two LDS buffers: slice s is read from buffer s & 1 while slice s + 1 is stashed into
+  // the other one and slice s + 2 is fetched into registers; one barrier per slice.
+  if (kbeg < kend) {
+    fetch(kbeg);
+    stash(0);
+    if (kbeg + kTK < kend) fetch(kbeg + kTK);
+  }
+  __syncthreads();
+  int buf = 0;
+  for (int k0 = kbeg; k0 < kend; k0 += kTK, buf ^= 1) {
 #pragma unroll
     for (int kk = 0; kk < kTK / 4; ++kk) {
       const int k = kk * 4 + (lane >> 4);
       double av[4], bv[4];
 #pragma unroll
-      for (int a = 0; a < 4; ++a) av[a] = sA[k][wm * 64 + a * 16 + (lane & 15)];
+      for (int a = 0; a < 4; ++a) av[a] = sA[buf][k][wm * 64 + a * 16 + (lane & 15)];
 #pragma unroll
-      for (int b = 0; b < 4; ++b) bv[b] = sB[k][wn * 64 + b * 16 + (lane & 15)];
+      for (int b = 0; b < 4; ++b) bv[b] = sB[buf][k][wn * 64 + b * 16 + (lane & 15)];
 #pragma unroll
       for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
     }
+    if (k0 + kTK < kend) {
+      stash(buf ^ 1);   // slice k0 + kTK; that buffer's last reads were before the previous barrier
+      if (k0 + 2 * kTK < kend) fetch(k0 + 2 * kTK);
+    }
+    __syncthreads();
   }
 #pragma unroll
   for (int a = 0; a < 4; ++a)

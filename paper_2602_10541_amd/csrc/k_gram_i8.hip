@@ -257,14 +257,11 @@ __global__ __launch_bounds__(256, 1) void k_gram_i8(I8GemmJob J) {
 // Balanced remainders r = x - p rint(x / p) in [-(p-1)/2, (p-1)/2] (p odd): x / p is never a
 // half-integer, and the rounded quotient lies within far less than 1/(2p) of the exact
 // one, so rint is exact; the remainder is then exact in the format (|x| < 2^24 for FP32).
-__device__ __forceinline__ int bal_mod_f32(int x, float p, float ip) {
-  const float fx = (float)x;
-  return (int)fmaf(-p, rintf(fx * ip), fx);
-}
 __device__ __forceinline__ int bal_mod_f64(int x, double p, double ip) {
   const double fx = (double)x;
   return (int)fma(-p, rint(fx * ip), fx);
 }
+__device__ __forceinline__ float bal_modf(float y, float p, float ip) { return fmaf(-p, rintf(y * ip), y); }
 
 // One thread per upper-triangle entry (j <= l) of G (n x n row-major): balanced Garner
 // digits v_k of the residues, X = v_0 + p_0 (v_1 + p_1 (v_2 + ...)) evaluated from the top
@@ -277,16 +274,18 @@ __global__ void k_i8_crt(I8CrtJob J) {
   const int tile = ti * J.nt - ti * (ti - 1) / 2 + (tj - ti);
   const int64_t e = (int64_t)tile * (kI8Tile * kI8Tile) + (j % kI8Tile) * kI8Tile + (l % kI8Tile);
   const int64_t tstride = (int64_t)J.n_tiles * (kI8Tile * kI8Tile);
-  int v[kI8MaxMod];
+  float v[kI8MaxMod];
 #pragma unroll
   for (int k = 0; k < kI8MaxMod; ++k) {
     if (k < J.M.n_mod) {
       const float pk = J.M.pf[k], ipk = J.M.inv_pf[k];
-      // |sum| < 2^31: the first reduction in FP64, the digit recurrence (|x| < 2^16) in FP32
-      int x = bal_mod_f64(J.Gt[k * tstride + e], J.M.p[k], J.M.inv_p[k]);
+      // |sum| < 2^31: the first reduction in FP64; the digit recurrence stays in FP32, where
+      // every value is an integer below 2^16 in magnitude (|x - v| < 255, cinv < 255), so
+      // each product and remainder is exact
+      float x = (float)bal_mod_f64(J.Gt[k * tstride + e], J.M.p[k], J.M.inv_p[k]);
 #pragma unroll
       for (int m = 0; m < kI8MaxMod; ++m)
-        if (m < k) x = bal_mod_f32((x - v[m]) * J.M.cinv[m][k], pk, ipk);
+        if (m < k) x = bal_modf((x - v[m]) * J.M.cinvf[m][k], pk, ipk);
       v[k] = x;
     }
   }
