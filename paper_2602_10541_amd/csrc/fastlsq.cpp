@@ -760,11 +760,11 @@ Err cgls_refine(flsq_ctx* c, const System& s, const double* rho, const double* X
   CHECK_ERR(ws_get(c, "cg_g", (size_t)n * K, &g));
   CHECK_ERR(ws_get(c, "cg_z", (size_t)n * K, &z));
   CHECK_ERR(ws_get(c, "cg_p", (size_t)n * K, &p));
-  CHECK_ERR(ws_get(c, "cg_dots", (size_t)8 * K, &dots));
+  CHECK_ERR(ws_get(c, "cg_dots", (size_t)12 * K, &dots));
   CHECK_ERR(ws_get(c, "cg_dwork", (size_t)512 * K + 64, &dwork));
   CHECK_ERR(ws_get(c, "cg_colwork", pass_work_elems(n, s.n_runs, K) + 64, &colwork));
   hipStream_t st = c->stream;
-  std::vector<double> gam, del, tmp, tmp2, alpha(K), beta(K), stepn(K), xn(K);
+  std::vector<double> tmp, stepn(K);
 
   // s = Y - A X ; g = A^T s - mu X ; u = H X
   CHECK_ERR(row_pass(c, pg, rho, X, K, Y, -1.0, 1.0, sres, uu));
@@ -801,57 +801,65 @@ Err cgls_refine(flsq_ctx* c, const System& s, const double* rho, const double* X
     ynorm[k] = std::max(std::sqrt(tmp[k]), 1e-300);
     Jbest[k] = tmp[K + k] + mu * tmp[2 * K + k];
   }
+  // Per-column scalars stay on the device: gam | alpha | beta | qq | pp | hq.hq | u.u | s.s | X.X |
+  // gam_new.  The host reads alpha, the step norms and the objective once per iteration; the
+  // step lengths and the direction update never wait for it.
+  double* d_gam = dots;
+  double *d_alpha = dots + K, *d_beta = dots + 2 * K, *d_qq = dots + 3 * K, *d_pp = dots + 4 * K;
+  double *d_hh = dots + 5 * K, *d_uu = dots + 6 * K, *d_ss = dots + 7 * K, *d_xx = dots + 8 * K;
+  double* d_gnew = dots + 9 * K;
   CHECK_ERR(chol_solve(c, Xi, n, g, z, K));
   CHECK_HIP(hipMemcpyAsync(p, z, sizeof(double) * n * K, hipMemcpyDeviceToDevice, st));
-  CHECK_HIP(launch_dot_cols(g, z, n, K, dots, dwork, st));
-  CHECK_ERR(host_cols(c, dots, K, gam));
+  CHECK_HIP(launch_dot_cols(g, z, n, K, d_gam, dwork, st));
   bool stalled_all = false;
+  std::vector<double> hs(8 * K);
   for (int it = 0; it < max_iter; ++it) {
-    // q = A p ; delta = ||q||^2 + mu ||p||^2 ; hq = H p
+    // q = A p ; delta = ||q||^2 + mu ||p||^2 ; hq = H p ; alpha = gam / delta
     CHECK_ERR(row_pass(c, pg, rho, p, K, nullptr, 1.0, 0.0, q, hq));
-    CHECK_HIP(launch_dot_cols(q, q, P, K, dots, dwork, st));
-    CHECK_HIP(launch_dot_cols(p, p, n, K, dots + K, dwork, st));
+    CHECK_HIP(launch_dot_cols(q, q, P, K, d_qq, dwork, st));
+    CHECK_HIP(launch_dot_cols(p, p, n, K, d_pp, dwork, st));
     if (track_u) {
-      CHECK_HIP(launch_dot_cols(hq, hq, P, K, dots + 2 * K, dwork, st));
-      CHECK_HIP(launch_dot_cols(uu, uu, P, K, dots + 3 * K, dwork, st));
+      CHECK_HIP(launch_dot_cols(hq, hq, P, K, d_hh, dwork, st));
+      CHECK_HIP(launch_dot_cols(uu, uu, P, K, d_uu, dwork, st));
     }
-    CHECK_ERR(host_cols(c, dots, (track_u ? 4 : 2) * K, tmp));
+    CHECK_HIP(launch_cg_alpha(d_gam, d_qq, d_pp, mu, col_mask(active), K, d_alpha, st));
+    CHECK_HIP(launch_axpy_cols_dev(d_alpha, p, X, n, K, 1.0, st));
+    CHECK_HIP(launch_axpy_cols_dev(d_alpha, q, sres, P, K, -1.0, st));
+    if (track_u) CHECK_HIP(launch_axpy_cols_dev(d_alpha, hq, uu, P, K, 1.0, st));
+    // objective after the step
+    CHECK_HIP(launch_dot_cols(sres, sres, P, K, d_ss, dwork, st));
+    CHECK_HIP(launch_dot_cols(X, X, n, K, d_xx, dwork, st));
+    CHECK_HIP(hipMemcpyAsync(hs.data(), d_alpha, sizeof(double) * 8 * K, hipMemcpyDeviceToHost, st));
+    CHECK_HIP(hipStreamSynchronize(st));
+    const double* h_alpha = hs.data();
+    const double *h_qq = hs.data() + 2 * K, *h_hh = hs.data() + 4 * K, *h_uu = hs.data() + 5 * K;
+    const double *h_ss = hs.data() + 6 * K, *h_xx = hs.data() + 7 * K;
     double worst = 0.0;
     for (int k = 0; k < K; ++k) {
-      const double dl = tmp[k] + mu * tmp[K + k];
-      alpha[k] = (active[k] > 0.0 && dl > 0.0 && gam[k] > 0.0) ? gam[k] / dl : 0.0;
       if (active[k] == 0.0) continue;
-      if (track_u && tmp[3 * K + k] > 0.0) {
-        stepn[k] = std::fabs(alpha[k]) * std::sqrt(tmp[2 * K + k]);
-        relstep[k] = stepn[k] / std::sqrt(tmp[3 * K + k]);
+      if (track_u && h_uu[k] > 0.0) {
+        stepn[k] = std::fabs(h_alpha[k]) * std::sqrt(h_hh[k]);
+        relstep[k] = stepn[k] / std::sqrt(h_uu[k]);
       } else {
-        stepn[k] = std::fabs(alpha[k]) * std::sqrt(tmp[k]);
+        stepn[k] = std::fabs(h_alpha[k]) * std::sqrt(h_qq[k]);
         relstep[k] = stepn[k] / ynorm[k];
       }
       worst = std::max(worst, relstep[k]);
     }
-    const ColScalars al = cols(alpha);
-    CHECK_HIP(launch_axpy_cols(al, p, X, n, K, 1.0, st));
-    CHECK_HIP(launch_axpy_cols(al, q, sres, P, K, -1.0, st));
-    if (track_u) CHECK_HIP(launch_axpy_cols(al, hq, uu, P, K, 1.0, st));
     ro->iters = it + 1;
     ro->last_step = worst;
-    // objective after the step; keep the best iterate, stop columns whose objective rose
-    CHECK_HIP(launch_dot_cols(sres, sres, P, K, dots, dwork, st));
-    CHECK_HIP(launch_dot_cols(X, X, n, K, dots + K, dwork, st));
-    CHECK_ERR(host_cols(c, dots, 2 * K, tmp));
-    // A column also stops once, for two iterations in a row, neither its objective dropped
-    // by more than a few units in the last place nor its step shrank below half the smallest
-    // step so far: FP64 no longer resolves its progress.  The objective alone is not enough:
-    // it is quadratic in the error, so it stops resolving progress at a relative error of
-    // about the square root of the unit roundoff, while the step keeps shrinking until the
-    // rounding floor.  An objective within a few ulps of the best counts as a tie and takes
-    // the newer iterate.
+    // Keep the best iterate, stop columns whose objective rose.  A column also stops once,
+    // for two iterations in a row, neither its objective dropped by more than a few units in
+    // the last place nor its step shrank below half the smallest step so far: FP64 no longer
+    // resolves its progress.  The objective alone is not enough: it is quadratic in the
+    // error, so it stops resolving progress at a relative error of about the square root of
+    // the unit roundoff, while the step keeps shrinking until the rounding floor.  An
+    // objective within a few ulps of the best counts as a tie and takes the newer iterate.
     int n_active = 0;
     for (int k = 0; k < K; ++k) {
       improved[k] = 0.0;
       if (active[k] == 0.0) continue;
-      const double J = tmp[k] + mu * tmp[K + k];
+      const double J = h_ss[k] + mu * h_xx[k];
       const double ulps = 4.0 * DBL_EPSILON * Jbest[k];
       const bool resolved = (Jbest[k] - J) > ulps || relstep[k] < 0.5 * minstep[k];
       minstep[k] = std::min(minstep[k], relstep[k]);
@@ -875,15 +883,12 @@ Err cgls_refine(flsq_ctx* c, const System& s, const double* rho, const double* X
       break;
     }
     if (it + 1 == max_iter) break;
+    // g = A^T s - mu X ; z = M^{-1} g ; beta = (g.z) / gam ; p = z + beta p
     CHECK_HIP(launch_colpass_runs(pg, rho, sres, K, X, 1.0, -mu, g, colwork, st));
     CHECK_ERR(chol_solve(c, Xi, n, g, z, K));
-    CHECK_HIP(launch_dot_cols(g, z, n, K, dots, dwork, st));
-    CHECK_ERR(host_cols(c, dots, K, tmp));
-    for (int k = 0; k < K; ++k) {
-      beta[k] = gam[k] > 0.0 ? tmp[k] / gam[k] : 0.0;
-      gam[k] = tmp[k];
-    }
-    CHECK_HIP(launch_xpby_cols(z, cols(beta), p, n, K, st));
+    CHECK_HIP(launch_dot_cols(g, z, n, K, d_gnew, dwork, st));
+    CHECK_HIP(launch_cg_beta(d_gnew, d_gam, K, d_beta, st));
+    CHECK_HIP(launch_xpby_cols_dev(z, d_beta, p, n, K, st));
   }
   // return the best iterate of every column; the recurrence residual is recomputed
   CHECK_HIP(hipMemcpyAsync(X, Xbest, sizeof(double) * n * K, hipMemcpyDeviceToDevice, st));
@@ -1200,7 +1205,7 @@ flsq_status flsq_factor_solve_normal(flsq_ctx* ctx, const flsq_factor* F, const 
   if (e.st == FLSQ_OK) e = ws_get(ctx, "pcg_p", (size_t)n * K, &p);
   if (e.st == FLSQ_OK) e = ws_get(ctx, "pcg_ap", (size_t)n * K, &ap);
   if (e.st == FLSQ_OK) e = ws_get(ctx, "pcg_tp", (size_t)s.P * K, &tP);
-  if (e.st == FLSQ_OK) e = ws_get(ctx, "pcg_dots", (size_t)4 * K, &dots);
+  if (e.st == FLSQ_OK) e = ws_get(ctx, "pcg_dots", (size_t)10 * K, &dots);
   if (e.st == FLSQ_OK) e = ws_get(ctx, "pcg_dwork", (size_t)512 * K + 64, &dwork);
   if (e.st == FLSQ_OK) e = ws_get(ctx, "pcg_colwork", pass_work_elems(n, s.n_runs, K) + 64, &colwork);
   if (e.st != FLSQ_OK) return finish(ctx, e);
@@ -1212,15 +1217,19 @@ flsq_status flsq_factor_solve_normal(flsq_ctx* ctx, const flsq_factor* F, const 
   auto body = [&]() -> Err {
     CHECK_ERR(chol_solve(ctx, F->Xinv.as<double>(), n, V, out, K));
     if (F->max_refine == 0) return ok();
-    std::vector<double> gam, tmp, tmp2, alpha(K), beta(K);
+    std::vector<double> tmp;
     CHECK_ERR(apply_normal(out, ap));
     CHECK_HIP(hipMemcpyAsync(r, V, sizeof(double) * n * K, hipMemcpyDeviceToDevice, st));
     std::vector<double> ones(K, 1.0);
     CHECK_HIP(launch_axpy_cols(cols(ones), ap, r, n, K, -1.0, st));
+    // Per-column scalars stay on the device: gam | alpha | beta | p.Mp | x.V before the step |
+    // x.V | x.r | gam_new; the host reads them once per iteration.
+    double* d_gam = dots;
+    double *d_alpha = dots + K, *d_beta = dots + 2 * K, *d_pap = dots + 3 * K, *d_xv0 = dots + 4 * K;
+    double *d_xv = dots + 5 * K, *d_xr = dots + 6 * K, *d_gnew = dots + 7 * K;
     CHECK_ERR(chol_solve(ctx, F->Xinv.as<double>(), n, r, z, K));
     CHECK_HIP(hipMemcpyAsync(p, z, sizeof(double) * n * K, hipMemcpyDeviceToDevice, st));
-    CHECK_HIP(launch_dot_cols(r, z, n, K, dots, dwork, st));
-    CHECK_ERR(host_cols(ctx, dots, K, gam));
+    CHECK_HIP(launch_dot_cols(r, z, n, K, d_gam, dwork, st));
     // Stop when the step's energy norm |alpha| (p^T M p)^{1/2} (M = G + mu I) is below tol
     // times the solution's, estimated by (out^T V)^{1/2}.  The energy functional
     // phi(x) = x^T M x / 2 - x^T V = -(x^T V + x^T r) / 2 decreases monotonically in exact
@@ -1229,32 +1238,34 @@ flsq_status flsq_factor_solve_normal(flsq_ctx* ctx, const flsq_factor* F, const 
     double* xbest;
     CHECK_ERR(ws_get(ctx, "pcg_xbest", (size_t)n * K, &xbest));
     CHECK_HIP(hipMemcpyAsync(xbest, out, sizeof(double) * n * K, hipMemcpyDeviceToDevice, st));
-    CHECK_HIP(launch_dot_cols(out, V, n, K, dots, dwork, st));
-    CHECK_HIP(launch_dot_cols(out, r, n, K, dots + K, dwork, st));
-    CHECK_ERR(host_cols(ctx, dots, 2 * K, tmp));
+    CHECK_HIP(launch_dot_cols(out, V, n, K, d_xv, dwork, st));
+    CHECK_HIP(launch_dot_cols(out, r, n, K, d_xr, dwork, st));
+    CHECK_ERR(host_cols(ctx, d_xv, 2 * K, tmp));
     std::vector<double> phibest(K), active(K, 1.0), improved(K, 0.0), relstep(K, 0.0), minstep(K, HUGE_VAL);
     std::vector<int> stagnant(K, 0);
     for (int k = 0; k < K; ++k) phibest[k] = -0.5 * (tmp[k] + tmp[K + k]);
+    std::vector<double> hs(6 * K);
     for (int it = 0; it < F->max_refine; ++it) {
       CHECK_ERR(apply_normal(p, ap));
-      CHECK_HIP(launch_dot_cols(p, ap, n, K, dots, dwork, st));
-      CHECK_HIP(launch_dot_cols(out, V, n, K, dots + 2 * K, dwork, st));
-      CHECK_ERR(host_cols(ctx, dots, 3 * K, tmp));
+      CHECK_HIP(launch_dot_cols(p, ap, n, K, d_pap, dwork, st));
+      CHECK_HIP(launch_dot_cols(out, V, n, K, d_xv0, dwork, st));
+      CHECK_HIP(launch_cg_alpha(d_gam, d_pap, nullptr, 0.0, col_mask(active), K, d_alpha, st));
+      CHECK_HIP(launch_axpy_cols_dev(d_alpha, p, out, n, K, 1.0, st));
+      CHECK_HIP(launch_axpy_cols_dev(d_alpha, ap, r, n, K, -1.0, st));
+      CHECK_HIP(launch_dot_cols(out, V, n, K, d_xv, dwork, st));
+      CHECK_HIP(launch_dot_cols(out, r, n, K, d_xr, dwork, st));
+      CHECK_HIP(hipMemcpyAsync(hs.data(), d_alpha, sizeof(double) * 6 * K, hipMemcpyDeviceToHost, st));
+      CHECK_HIP(hipStreamSynchronize(st));
+      const double *h_alpha = hs.data(), *h_pap = hs.data() + 2 * K, *h_xv0 = hs.data() + 3 * K;
+      const double *h_xv = hs.data() + 4 * K, *h_xr = hs.data() + 5 * K;
       double worst = 0.0;
       for (int k = 0; k < K; ++k) {
-        alpha[k] = (active[k] > 0.0 && tmp[k] > 0.0 && gam[k] > 0.0) ? gam[k] / tmp[k] : 0.0;
         if (active[k] > 0.0) {
-          relstep[k] = std::fabs(alpha[k]) * std::sqrt(std::max(tmp[k], 0.0)) /
-                       std::max(std::sqrt(std::fabs(tmp[2 * K + k])), 1e-300);
+          relstep[k] = std::fabs(h_alpha[k]) * std::sqrt(std::max(h_pap[k], 0.0)) /
+                       std::max(std::sqrt(std::fabs(h_xv0[k])), 1e-300);
           worst = std::max(worst, relstep[k]);
         }
       }
-      const ColScalars al = cols(alpha);
-      CHECK_HIP(launch_axpy_cols(al, p, out, n, K, 1.0, st));
-      CHECK_HIP(launch_axpy_cols(al, ap, r, n, K, -1.0, st));
-      CHECK_HIP(launch_dot_cols(out, V, n, K, dots, dwork, st));
-      CHECK_HIP(launch_dot_cols(out, r, n, K, dots + K, dwork, st));
-      CHECK_ERR(host_cols(ctx, dots, 2 * K, tmp));
       // A column is done once, for two iterations in a row, neither its energy phi dropped
       // by more than a few units in the last place nor its step shrank below half the
       // smallest so far: FP64 no longer resolves its progress (phi is quadratic in the error
@@ -1268,7 +1279,7 @@ flsq_status flsq_factor_solve_normal(flsq_ctx* ctx, const flsq_factor* F, const 
       for (int k = 0; k < K; ++k) {
         improved[k] = 0.0;
         if (active[k] == 0.0) continue;
-        const double phi = -0.5 * (tmp[k] + tmp[K + k]);
+        const double phi = -0.5 * (h_xv[k] + h_xr[k]);
         const bool resolved =
             (phibest[k] - phi) > 4.0 * DBL_EPSILON * std::fabs(phibest[k]) || relstep[k] < 0.5 * minstep[k];
         minstep[k] = std::min(minstep[k], relstep[k]);
@@ -1285,13 +1296,9 @@ flsq_status flsq_factor_solve_normal(flsq_ctx* ctx, const flsq_factor* F, const 
       CHECK_HIP(launch_select_cols(out, xbest, n, K, col_mask(improved), st));
       if (worst <= F->refine_tol || n_active == 0 || it + 1 == F->max_refine) break;
       CHECK_ERR(chol_solve(ctx, F->Xinv.as<double>(), n, r, z, K));
-      CHECK_HIP(launch_dot_cols(r, z, n, K, dots, dwork, st));
-      CHECK_ERR(host_cols(ctx, dots, K, tmp2));
-      for (int k = 0; k < K; ++k) {
-        beta[k] = gam[k] > 0.0 ? tmp2[k] / gam[k] : 0.0;
-        gam[k] = tmp2[k];
-      }
-      CHECK_HIP(launch_xpby_cols(z, cols(beta), p, n, K, st));
+      CHECK_HIP(launch_dot_cols(r, z, n, K, d_gnew, dwork, st));
+      CHECK_HIP(launch_cg_beta(d_gnew, d_gam, K, d_beta, st));
+      CHECK_HIP(launch_xpby_cols_dev(z, d_beta, p, n, K, st));
     }
     CHECK_HIP(hipMemcpyAsync(out, xbest, sizeof(double) * n * K, hipMemcpyDeviceToDevice, st));
     return ok();

@@ -194,6 +194,15 @@ hipError_t launch_axpy_cols(const ColScalars& a, const double* x, double* y, int
 // p[i][c] = z[i][c] + b[c] * p[i][c]
 hipError_t launch_xpby_cols(const double* z, const ColScalars& b, double* p, int64_t n, int K, hipStream_t s);
 hipError_t launch_count_nonfinite(const double* x, int64_t n, int* flag, hipStream_t s);
+// The same with the scalars in device memory (K doubles), for the device-resident CG scalars.
+hipError_t launch_axpy_cols_dev(const double* a, const double* x, double* y, int64_t n, int K, double sign,
+                                hipStream_t s);
+hipError_t launch_xpby_cols_dev(const double* z, const double* b, double* p, int64_t n, int K, hipStream_t s);
+// alpha[k] = gam[k] / (d1[k] + mu d2[k]) on the columns set in active with both positive, else 0
+// (d2 nullable); beta[k] = gam_new[k] / gam[k] (0 if gam[k] <= 0), then gam[k] = gam_new[k].
+hipError_t launch_cg_alpha(const double* gam, const double* d1, const double* d2, double mu, uint64_t active, int K,
+                           double* alpha, hipStream_t s);
+hipError_t launch_cg_beta(const double* gam_new, double* gam, int K, double* beta, hipStream_t s);
 // dst[i][c] = src[i][c] for the columns c whose bit is set in mask
 hipError_t launch_select_cols(const double* src, double* dst, int64_t n, int K, uint64_t mask, hipStream_t s);
 

@@ -162,6 +162,66 @@ hipError_t launch_xpby_cols(const double* z, const ColScalars& b, double* p, int
   return hipGetLastError();
 }
 
+// Device-resident per-column scalars of the CG recurrences (the host reads them once per
+// iteration for its stopping decisions instead of round-tripping each one).
+__global__ void k_axpy_cols_dev(const double* __restrict__ a, const double* x, double* y, int64_t n, int K,
+                                double sign) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * K) return;
+  y[e] = fma(sign * a[e % K], x[e], y[e]);
+}
+
+hipError_t launch_axpy_cols_dev(const double* a, const double* x, double* y, int64_t n, int K, double sign,
+                                hipStream_t s) {
+  const int64_t tot = n * K;
+  if (tot == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_axpy_cols_dev, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, a, x, y, n, K, sign);
+  return hipGetLastError();
+}
+
+__global__ void k_xpby_cols_dev(const double* z, const double* __restrict__ b, double* p, int64_t n, int K) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * K) return;
+  p[e] = fma(b[e % K], p[e], z[e]);
+}
+
+hipError_t launch_xpby_cols_dev(const double* z, const double* b, double* p, int64_t n, int K, hipStream_t s) {
+  const int64_t tot = n * K;
+  if (tot == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_xpby_cols_dev, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, z, b, p, n, K);
+  return hipGetLastError();
+}
+
+// alpha_k = gam_k / (d1_k + mu d2_k) for active columns with both positive, else 0 (d2 nullable).
+__global__ void k_cg_alpha(const double* gam, const double* d1, const double* d2, double mu, uint64_t active, int K,
+                           double* alpha) {
+  const int k = threadIdx.x;
+  if (k >= K) return;
+  const double dl = d1[k] + (d2 ? mu * d2[k] : 0.0);
+  alpha[k] = (((active >> k) & 1ull) && dl > 0.0 && gam[k] > 0.0) ? gam[k] / dl : 0.0;
+}
+
+// beta_k = gam_new_k / gam_k (0 when gam_k <= 0), then gam_k = gam_new_k.
+__global__ void k_cg_beta(const double* gam_new, double* gam, int K, double* beta) {
+  const int k = threadIdx.x;
+  if (k >= K) return;
+  beta[k] = gam[k] > 0.0 ? gam_new[k] / gam[k] : 0.0;
+  gam[k] = gam_new[k];
+}
+
+hipError_t launch_cg_alpha(const double* gam, const double* d1, const double* d2, double mu, uint64_t active, int K,
+                           double* alpha, hipStream_t s) {
+  if (K < 1 || K > 64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(64), 0, s, gam, d1, d2, mu, active, K, alpha);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_beta(const double* gam_new, double* gam, int K, double* beta, hipStream_t s) {
+  if (K < 1 || K > 64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(64), 0, s, gam_new, gam, K, beta);
+  return hipGetLastError();
+}
+
 __global__ void k_select_cols(const double* src, double* dst, int64_t n, int K, uint64_t mask) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n * K) return;

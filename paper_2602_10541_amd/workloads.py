@@ -27,7 +27,7 @@ TWO_PI = 2.0 * math.pi
 PI = math.pi
 
 # Stream order inside SeedSequence(seed).spawn(len(STREAMS)).
-STREAMS = ("W", "b", "interior", "boundary", "initial", "obs", "hyp")
+STREAMS = ("W", "b", "interior", "boundary", "initial", "obs", "hyp", "sweep")
 
 # Boundary / initial-condition row weight (Section 3.1, lambda = 100).
 LAM_BC = 100.0
@@ -268,6 +268,42 @@ def add_noise(u_clean: np.ndarray, noise: np.ndarray, level: float = 0.01) -> np
 
 
 # Named full-size workloads.
+def helmholtz_sweep(n_feat: int = 1500, sigma: float = 10.0, n_int: int = 4800, n_bc: int = 1200,
+                    k: float = 10.0, n_rhs: int = 64, seed: int = 0, n_test: int = 500) -> Problem:
+    """Laplace u + k^2 u = 0 on [0,1]^2 with a sweep of Dirichlet data: the plane waves
+    u_s = cos(k (cos t_s x + sin t_s y) + r_s), t_s and r_s uniform in [0, 2 pi), solve it
+    exactly, so only the boundary rows' data change from one right-hand side to the next.
+
+    The blocks carry u_0's data; ``extras["rhs_rows"]`` holds all n_rhs weighted right-hand
+    sides (P x n_rhs, rows in block order) and ``extras["u_test_sweep"]`` the exact values at
+    the test points (n_test x n_rhs).
+    """
+    d = 2
+    r = _rngs(seed)
+    W, b = draw_features(r, n_feat, [sigma] * d)
+    xi = sample_box(r["interior"], n_int, d)
+    xb = sample_faces(r["boundary"], n_bc, d, range(d))
+    th = r["sweep"].uniform(0.0, TWO_PI, size=n_rhs)
+    ph = r["sweep"].uniform(0.0, TWO_PI, size=n_rhs)
+
+    def waves(x):
+        return np.cos(k * (np.outer(x[:, 0], np.cos(th)) + np.outer(x[:, 1], np.sin(th))) + ph[None, :])
+
+    gb = waves(xb)
+    terms = laplacian_terms(d, range(d), 1.0) + [(k * k, (0, 0))]
+    blocks = [
+        Block("interior", xi, terms, 1.0, np.zeros(n_int)),
+        Block("boundary", xb, identity_terms(d), LAM_BC, gb[:, 0].copy()),
+    ]
+    rhs_rows = np.concatenate([np.zeros((n_int, n_rhs)), LAM_BC * gb], axis=0)
+    xt = sample_box(np.random.default_rng(seed + 1), n_test, d)
+    ut = waves(xt)
+    return Problem("helmholtz_2d_sweep", d, n_feat, W, b, blocks, x_test=xt, u_test=ut[:, 0].copy(),
+                   extras={"sigma": sigma, "k": k, "rhs_rows": np.ascontiguousarray(rhs_rows),
+                           "u_test_sweep": ut, "theta": th, "phase": ph,
+                           "exact": "cos(k (cos t_s x + sin t_s y) + r_s)"})
+
+
 def config(name: str, seed: int = 0, **kw) -> Problem:
     if name == "poisson2d":      # 2000 interior + 400 boundary, N = 500, sigma = 3, fp64
         return poisson(2, kw.pop("n_feat", 500), 3.0, kw.pop("n_int", 2000), kw.pop("n_bc", 400),
@@ -281,6 +317,8 @@ def config(name: str, seed: int = 0, **kw) -> Problem:
         return heat(seed=seed, **kw)
     if name == "inverse3d":
         return inverse_heat(seed=seed, **kw)
+    if name == "helmholtz_sweep":   # matrix caching: 64 boundary-data sweeps, N = 1500, 6000 rows
+        return helmholtz_sweep(seed=seed, **kw)
     raise KeyError(name)
 
 

@@ -58,7 +58,26 @@ def inverse(name):
     print(name, "loss0[:4]", loss[:4], flush=True)
 
 
-KIND = {"poisson2d": linear, "poisson6d": linear, "heat4d": linear, "reaction2d": newton, "inverse3d": inverse}
+def sweep(name):
+    """All right-hand sides of the sweep from one Householder QR of [A; sqrt(mu) I] (the oracle's
+    Tikhonov solve with a matrix right-hand side), u at the test points for each."""
+    prob = wl.config(name)
+    A, _ = oracle.assemble_system(prob)
+    Y = prob.extras["rhs_rows"]
+    t0 = time.time()
+    B = oracle.tikhonov(A, Y, prob.mu)
+    solve_s = time.time() - t0
+    U = np.stack([oracle.evaluate(prob.W, prob.b, B[:, s], prob.x_test, [tuple([0] * prob.d)])[:, 0]
+                  for s in range(B.shape[1])], axis=1)
+    ex = prob.extras["u_test_sweep"]
+    err = np.linalg.norm(U - ex, axis=0) / np.linalg.norm(ex, axis=0)
+    np.savez(os.path.join(OUT, f"{name}.npz"), u_test=U, err_exact=err, solve_s=np.array(solve_s),
+             threads=np.array(oracle.num_threads()))
+    print(name, "rel err vs exact: max", err.max(), "median", np.median(err), "QR + solve", solve_s, "s", flush=True)
+
+
+KIND = {"poisson2d": linear, "poisson6d": linear, "heat4d": linear, "reaction2d": newton, "inverse3d": inverse,
+        "helmholtz_sweep": sweep}
 
 if __name__ == "__main__":
     names = sys.argv[1:] or ["poisson2d", "poisson6d"]

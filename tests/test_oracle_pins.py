@@ -238,6 +238,33 @@ def test_linear_poisson_manufactured_band():
     assert np.linalg.norm(g - prob.mu * beta) < 1e-6 * np.linalg.norm(A.T @ r)
 
 
+def test_helmholtz_sweep_manufactured_and_columns():
+    """The sweep's plane waves solve Laplace u + k^2 u = 0 (central differences), its boundary
+    data are the waves on the faces, and one multi-right-hand-side oracle solve gives each
+    column's single solve and a small error against the exact waves (band only)."""
+    prob = wl.helmholtz_sweep(n_feat=300, n_int=1200, n_bc=300, n_rhs=4, seed=2, n_test=400)
+    k, th, ph = prob.extras["k"], prob.extras["theta"], prob.extras["phase"]
+    wave = lambda x, y, s: np.cos(k * (math.cos(th[s]) * x + math.sin(th[s]) * y) + ph[s])
+    rng = np.random.default_rng(0)
+    h = 1e-4
+    for s in range(4):
+        x, y = rng.uniform(0.1, 0.9, 2)
+        lap = (wave(x + h, y, s) + wave(x - h, y, s) + wave(x, y + h, s) + wave(x, y - h, s) - 4 * wave(x, y, s)) / h**2
+        assert abs(lap + k * k * wave(x, y, s)) < 1e-4 * k * k
+    xb = prob.blocks[1].x
+    Y = prob.extras["rhs_rows"]
+    assert np.all(np.isclose(np.min(np.minimum(xb, 1 - xb), axis=1), 0.0))
+    for s in range(4):
+        np.testing.assert_allclose(Y[prob.blocks[0].n:, s], wl.LAM_BC * wave(xb[:, 0], xb[:, 1], s), rtol=0, atol=1e-12)
+        assert np.all(Y[:prob.blocks[0].n, s] == 0.0)
+    A, _ = oracle.assemble_system(prob)
+    B = oracle.tikhonov(A, Y, prob.mu)
+    for s in range(4):
+        np.testing.assert_allclose(B[:, s], oracle.tikhonov(A, Y[:, s], prob.mu), rtol=1e-9, atol=1e-9 * np.abs(B[:, s]).max())
+        u = oracle.evaluate(prob.W, prob.b, B[:, s], prob.x_test, [(0, 0)])[:, 0]
+        assert oracle.rel_l2(u, prob.extras["u_test_sweep"][:, s]) < 1e-4
+
+
 # ---------------------------------------------------------------- Newton
 
 def _tiny_reaction(n_feat=300, n_int=900, n_bc=200, sigma=4.0):
