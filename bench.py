@@ -59,6 +59,16 @@ def measured_traffic(profile_md, kernel_src):
     return float(fields["traffic_bytes_per_launch"])
 
 
+def host_cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def householder_flops(m, n):
     return 2.0 * m * n * n - 2.0 * n ** 3 / 3.0
 
@@ -82,6 +92,7 @@ def cpu_baseline(prob, rows_int=12288, rows_bc=3072):
     est = t["assemble_s"] * P / Ps + t["solve_s"] * householder_flops(P + N, N) / householder_flops(Ps + N, N)
     return {
         "value": 1.0 / est, "unit": "solves/s", "cores": oracle.num_threads(), "kind": "oracle",
+        "host_cpu": host_cpu_model(),
         "sample": (f"oracle solve (explicit assembly + Householder QR of [A; sqrt(mu) I]) on the first {rows_int} "
                    f"interior + {rows_bc} boundary rows with all {N} features: assemble {t['assemble_s']:.2f} s, "
                    f"QR {t['solve_s']:.2f} s; scaled to {P} rows by row count (assembly) and Householder flops (QR)"),
