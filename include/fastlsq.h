@@ -91,7 +91,11 @@ typedef struct {
     double mu;            /* Tikhonov weight on ||beta||^2 (absolute) */
     int32_t prec;         /* flsq_precision */
     int32_t max_refine;   /* CGLS refinement iterations after the Cholesky solve (>= 0) */
-    double refine_tol;    /* stop when ||step|| <= refine_tol * ||beta|| */
+    double refine_tol;    /* a column stops when the change of its solution at the collocation rows of
+                             even-order blocks (else of its fitted values A beta), relative to their
+                             size, is below refine_tol -- or is predicted to be at the next step, once
+                             the changes fall at least 10x per iteration; also when FP64 no longer
+                             resolves progress (see flsq_solve_info.refine_iters) */
     double shift_rel;     /* initial Cholesky diagonal shift, relative to the unit diagonal of the
                              equilibrated Gram D G D (D = diag(G)^{-1/2}), for the
                              FP32 / BF16x3 preconditioner (0 = automatic) */
@@ -106,7 +110,7 @@ typedef struct {
                                (0 for FP64 unless a pivot failed) */
     double grad_norm0;      /* ||A^T (rhs - A beta) - mu beta|| after the Cholesky solve */
     double grad_norm;       /* same, at the returned beta (when opts.report_grad is set) */
-    double last_step_rel;   /* ||last refinement step|| / ||beta|| */
+    double last_step_rel;   /* relative size of the last refinement step, in the measure refine_tol uses */
     double t_gram_ms, t_chol_ms, t_refine_ms, t_total_ms;
     double t_gram_kernel_ms; /* the matrix-core Gram kernel alone (HIP events on the stream): the fused
                                 assembly + Gram kernel for FP64 / FP32, the int8 tile kernel for INT8_CRT */
