@@ -72,3 +72,22 @@ def test_sweep_single_rhs_matches_batched(sweep):
         assert rel_l2(u1, gold["u_test"][:, s]) <= 1e-7
         assert rel_l2(u1, Ub[:, s]) <= 1e-8
     F.free()
+
+
+@pytest.mark.parametrize("K", [2, 4, 5, 16, 17])
+def test_sweep_column_counts_cover_pass_variants(sweep, K):
+    """K right-hand sides at once for the column counts at the edges of the pass kernels'
+    variants (1-4 and 5-16 columns on the vector passes, 17+ on the matrix-core passes): each
+    column within 1e-7 of the oracle."""
+    torch, fl = require_gpu()
+    prob, dp, gold = sweep
+    ctx = context()
+    F = fl.flsq_factorize(ctx, dp.basis, dp.rows, fl.solve_opts(prob.mu, 3, 30, 1e-12))
+    cols = list(range(0, 64, 64 // K))[:K] if K <= 16 else list(range(K))
+    Y = torch.tensor(prob.extras["rhs_rows"][:, cols], dtype=torch.float64, device="cuda").contiguous()
+    B = torch.empty((prob.n_feat, K), dtype=torch.float64, device="cuda")
+    fl.flsq_factor_solve(ctx, F, Y, B)
+    U = _u_cols(fl, torch, ctx, dp, prob, B)
+    errs = [rel_l2(U[:, i], gold["u_test"][:, s]) for i, s in enumerate(cols)]
+    assert max(errs) <= 1e-7, (K, max(errs))
+    F.free()
