@@ -362,3 +362,80 @@ class InverseOracle:
         Rhs, _ = self.rhs(thetas)
         B = tikhonov(self.A, Rhs, self.prob.mu).reshape(self.A.shape[1], -1)
         return np.mean((self.H @ B - self.data[:, None]) ** 2, axis=0)
+
+
+# ---------------------------------------------------------------------------
+# Learnable bandwidth (the paper's reparameterisation appendix): W_j = L What_j with a
+# lower-triangular L, outer loss ||A(L) beta*(L) - b||^2 at the Tikhonov solution
+# ---------------------------------------------------------------------------
+
+def _phi(order, z):
+    """Phi_{order mod 4} of Eq. (2): sin, cos, -sin, -cos."""
+    o = order % 4
+    if o == 0:
+        return np.sin(z)
+    if o == 1:
+        return np.cos(z)
+    if o == 2:
+        return -np.sin(z)
+    return -np.cos(z)
+
+
+def assemble_dW(W, b, x, terms, p, scale_j, weight=1.0, normalize=True) -> np.ndarray:
+    """d A_ij / d W_jp times scale_j, written out from Eq. (2):
+    d/dW_jp [W_j^alpha Phi_|alpha|(W_j . x + b_j)]
+        = alpha_p W_j^(alpha - e_p) Phi_|alpha|(z) + W_j^alpha Phi_|alpha|+1(z) x_ip."""
+    W, b, x = _f64(W), _f64(b), _f64(x)
+    n_feat, d = W.shape
+    z = x @ W.T + b[None, :]
+    out = np.zeros((x.shape[0], n_feat))
+    for c, a in terms:
+        order = int(sum(a))
+        mono = np.ones(n_feat)
+        for k in range(d):
+            mono = mono * W[:, k] ** a[k]
+        if a[p] > 0:
+            dmono = np.full(n_feat, float(a[p]))
+            for k in range(d):
+                dmono = dmono * W[:, k] ** (a[k] - (1 if k == p else 0))
+            out += c * dmono[None, :] * _phi(order, z)
+        out += c * mono[None, :] * _phi(order + 1, z) * x[:, p][:, None]
+    norm = 1.0 / np.sqrt(n_feat) if normalize else 1.0
+    return weight * norm * out * _f64(scale_j)[None, :]
+
+
+def lower_index(d):
+    """(p, q) pairs of a lower-triangular d x d matrix in packed row-major order."""
+    return [(p, q) for p in range(d) for q in range(p + 1)]
+
+
+def bandwidth_loss_and_grad(prob, What, L):
+    """Outer loss Lo(L) = ||A beta* - b||^2 with beta* = argmin ||A beta - b||^2 + mu ||beta||^2 and
+    A = A(W = What L^T), and its gradient with respect to the entries L_pq, p >= q.
+
+    With r = b - A beta*, M = A^T A + mu I and A^T r = mu beta* (the normal equations),
+    dLo/dL_pq = -2 r^T A' beta* - 2 mu beta*^T d beta*/dL_pq, and
+    d beta*/dL_pq = M^{-1} (A'^T r - A^T A' beta*), so with lam = M^{-1} beta*
+    dLo/dL_pq = -2 [r^T A' beta* + mu (r^T A' lam - (A lam)^T A' beta*)],  A' = dA/dL_pq.
+    """
+    What, L = _f64(What), _f64(L)
+    d = What.shape[1]
+    W = What @ L.T
+    blocks = prob.blocks
+    As, rs = [], []
+    for bl in blocks:
+        As.append(assemble(W, prob.b, bl.x, bl.terms, bl.weight, prob.normalize))
+        rs.append(bl.weight * _f64(bl.rhs))
+    A, rhs = np.vstack(As), np.concatenate(rs)
+    beta, R = tikhonov(A, rhs, prob.mu, return_r=True)
+    r = rhs - A @ beta
+    loss = float(r @ r)
+    lam = trisolve(R, trisolve(R, beta, transpose=True), transpose=False)
+    Alam = A @ lam
+    grad = []
+    for p, q in lower_index(d):
+        dA = np.vstack([assemble_dW(W, prob.b, bl.x, bl.terms, p, What[:, q], bl.weight, prob.normalize)
+                        for bl in blocks])
+        dAb = dA @ beta
+        grad.append(-2.0 * (r @ dAb + prob.mu * (r @ (dA @ lam) - Alam @ dAb)))
+    return loss, np.array(grad), beta

@@ -304,6 +304,28 @@ def helmholtz_sweep(n_feat: int = 1500, sigma: float = 10.0, n_int: int = 4800, 
                            "exact": "cos(k (cos t_s x + sin t_s y) + r_s)"})
 
 
+def helmholtz_bandwidth(n_feat: int = 500, sigma0: float = 5.0, n_int: int = 2000, n_bc: int = 400,
+                        k: float = 10.0, seed: int = 0, n_test: int = 500) -> Problem:
+    """The learnable-bandwidth workload: Laplace u + k^2 u = f on [0,1]^2 with the exact solution
+    u = sin(k x) sin(k y) (f = -k^2 u, Dirichlet data u), whose frequency k sqrt(2) lies well above
+    the starting bandwidth.  ``W`` holds the frozen base draws What_j ~ N(0, I) (bandwidth 1); the
+    weights used are L What_j, starting from ``extras["L0"]`` = sigma0 I."""
+    d = 2
+    r = _rngs(seed)
+    W, b = draw_features(r, n_feat, [1.0] * d)
+    xi = sample_box(r["interior"], n_int, d)
+    xb = sample_faces(r["boundary"], n_bc, d, range(d))
+    u = lambda x: np.sin(k * x[:, 0]) * np.sin(k * x[:, 1])
+    terms = laplacian_terms(d, range(d), 1.0) + [(k * k, (0, 0))]
+    blocks = [
+        Block("interior", xi, terms, 1.0, -k * k * u(xi)),
+        Block("boundary", xb, identity_terms(d), LAM_BC, u(xb)),
+    ]
+    xt = sample_box(np.random.default_rng(seed + 1), n_test, d)
+    return Problem("helmholtz_2d_bandwidth", d, n_feat, W, b, blocks, x_test=xt, u_test=u(xt),
+                   extras={"sigma0": sigma0, "k": k, "L0": sigma0 * np.eye(d), "exact": "sin(k x) sin(k y)"})
+
+
 def config(name: str, seed: int = 0, **kw) -> Problem:
     if name == "poisson2d":      # 2000 interior + 400 boundary, N = 500, sigma = 3, fp64
         return poisson(2, kw.pop("n_feat", 500), 3.0, kw.pop("n_int", 2000), kw.pop("n_bc", 400),
@@ -319,6 +341,8 @@ def config(name: str, seed: int = 0, **kw) -> Problem:
         return inverse_heat(seed=seed, **kw)
     if name == "helmholtz_sweep":   # matrix caching: 64 boundary-data sweeps, N = 1500, 6000 rows
         return helmholtz_sweep(seed=seed, **kw)
+    if name == "helmholtz_bandwidth":   # learnable bandwidth: N = 500 base draws, sigma0 = 5, k = 10
+        return helmholtz_bandwidth(seed=seed, **kw)
     raise KeyError(name)
 
 
