@@ -228,6 +228,25 @@ flsq_status flsq_inverse_loss_grad(flsq_ctx* ctx, const flsq_factor* F, int64_t 
                                    const double* x_obs, const double* data, double* loss_out,
                                    double* grad_theta_out, double* grad_kappa_out);
 
+/* ---- Learnable bandwidth (the reparameterisation appendix, Eq. for W_j = L What_j) ----
+ * base: the frozen draws, base->W = What (device n_feat x d row-major) and base->b; the
+ *   weights actually used are W_j = L What_j.  The scalar bandwidth is L = sigma I.
+ * L: host d x d row-major, lower triangular (entries above the diagonal must be 0).
+ * blocks: the stacked operator rows with their data (rhs required), as for flsq_solve_linear.
+ * opts: the inner solve (Tikhonov weight mu, Gram precision, refinement), as for flsq_factorize.
+ * Outputs: beta_out device n_feat, the inner solution beta* = (A^T A + mu I)^{-1} A^T rhs_w;
+ *   loss_out host scalar, the outer loss ||A beta* - rhs_w||^2 (rows weighted, mu term excluded);
+ *   grad_out host d(d+1)/2, dLoss/dL_pq for q <= p packed row by row ((0,0), (1,0), (1,1), ...),
+ *   the exact derivative of that loss through the regularised inner solve:
+ *     dLoss/dL_pq = -2 [ r^T A' beta* + mu ( r^T A' lam - (A lam)^T A' beta* ) ],
+ *   r = rhs_w - A beta*, lam = (A^T A + mu I)^{-1} beta*, A' = dA/dL_pq (Eq. (2) differentiated
+ *   in W: a quarter-period phase shift, so every A' product is a matrix-free FP64 pass).
+ * Errors: FLSQ_EINVAL for NULL arguments, a non-lower-triangular L or invalid blocks;
+ *   FLSQ_ENONFINITE for a non-finite L; solver errors as for flsq_factorize / flsq_factor_solve. */
+flsq_status flsq_bandwidth_loss_grad(flsq_ctx* ctx, const flsq_basis* base, const double* L, const flsq_rows* blocks,
+                                     int32_t n_blocks, const flsq_solve_opts* opts, double* beta_out,
+                                     double* loss_out, double* grad_out);
+
 /* Batched Adam step on K x P parameters (all device arrays, updated in place):
  * m = b1 m + (1 - b1) g; v = b2 v + (1 - b2) g^2; p -= lr * (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps);
  * then p[:, clamp_col] = max(p[:, clamp_col], clamp_min) when clamp_col >= 0. */

@@ -17,6 +17,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -1625,6 +1626,133 @@ Err inverse_impl(flsq_ctx* c, flsq_factor* F, int64_t n_src, double src_weight, 
   return ok();
 }
 
+// Learnable bandwidth (the paper's reparameterisation appendix): W_j = L What_j, outer loss
+// Lo = ||A beta* - b||^2 at the Tikhonov solution.  With r = b - A beta*, M = A^T A + mu I,
+// lam = M^{-1} beta* and A' = dA/dL_pq (using A^T r = mu beta*):
+//   dLo/dL_pq = -2 [r^T A' beta* + mu (r^T A' lam - (A lam)^T A' beta*)].
+// dA_ij/dL_pq = What_jq dA_ij/dW_jp, and from Eq. (2)
+//   d/dW_jp [W^a Phi_|a|(z)] = a_p W^(a - e_p) Phi_|a|(z) + W^a Phi_|a|+1(z) x_ip,
+// two operators in the folded form with a quarter-period phase shift (Phi_{k+1}(z) =
+// Phi_k(z + pi/2)): T1_p with terms (c a_p, a - e_p), and T2 = the operator itself; the x_ip
+// factor weights the rows and What_jq the feature vector, so every form is a row pass.
+Err shift_phase(flsq_ctx* c, System& s, double delta) {
+  CHECK_HIP(launch_add_phase(s.ph.as<double>(), (int64_t)s.n_blocks * s.n, delta, c->stream));
+  CHECK_HIP(launch_pack_features(s.Wrm.as<double>(), s.amp.as<double>(), s.ph.as<double>(), s.n_blocks, s.n, s.d,
+                                 s.frec.as<double>(), c->stream));
+  return ok();
+}
+
+Err bandwidth_impl(flsq_ctx* c, const flsq_basis* base, const double* L, const flsq_rows* blocks, int n_blocks,
+                   const flsq_solve_opts* opts, double* beta, double* loss_out, double* grad_out) {
+  CHECK_ERR(check_basis(base));
+  if (!L || !beta || !loss_out || !grad_out || !opts) return fail(FLSQ_EINVAL, "NULL argument");
+  if (!blocks || n_blocks < 1) return fail(FLSQ_EINVAL, "need at least one row block");
+  for (int i = 0; i < n_blocks; ++i)
+    if (!blocks[i].rhs && blocks[i].n_rows > 0) return fail(FLSQ_EINVAL, "block %d has no data (rhs)", i);
+  const int d = base->d, n = base->n_feat;
+  for (int p = 0; p < d; ++p)
+    for (int q = 0; q < d; ++q) {
+      if (!std::isfinite(L[p * d + q])) return fail(FLSQ_ENONFINITE, "L is not finite");
+      if (q > p && L[p * d + q] != 0.0) return fail(FLSQ_EINVAL, "L must be lower triangular");
+    }
+  hipStream_t st = c->stream;
+  double* W;
+  CHECK_ERR(ws_get(c, "bw_W", (size_t)n * d, &W));
+  LowerMat Lm{};
+  for (int p = 0; p < d; ++p)
+    for (int q = 0; q <= p; ++q) Lm.v[p * kMaxDim + q] = L[p * d + q];
+  CHECK_HIP(launch_apply_lower(base->W, n, d, Lm, W, st));
+  flsq_basis bs = *base;
+  bs.W = W;
+  flsq_factor* F = nullptr;
+  flsq_status fs = flsq_factorize(c, &bs, blocks, n_blocks, opts, &F, nullptr);
+  if (fs != FLSQ_OK) return Err{fs, c->err};
+  std::unique_ptr<flsq_factor, void (*)(flsq_factor*)> guard(F, flsq_factor_free);
+  const System& s = F->sys;
+  const int64_t P = s.P;
+  const int K = 2 * d;
+  fs = flsq_factor_solve(c, F, s.rhs_w.as<double>(), 1, beta, nullptr);
+  if (fs != FLSQ_OK) return Err{fs, c->err};
+  double *r, *lam, *Alam, *V, *Y, *sums, *work;
+  CHECK_ERR(ws_get(c, "bw_r", (size_t)P, &r));
+  CHECK_ERR(ws_get(c, "bw_lam", (size_t)n, &lam));
+  CHECK_ERR(ws_get(c, "bw_alam", (size_t)P, &Alam));
+  CHECK_ERR(ws_get(c, "bw_V", (size_t)n * K, &V));
+  CHECK_ERR(ws_get(c, "bw_Y", (size_t)P * K, &Y));
+  CHECK_ERR(ws_get(c, "bw_sums", (size_t)2 * K, &sums));
+  CHECK_ERR(ws_get(c, "bw_work", (size_t)512 * K + 64, &work));
+  // r = b - A beta* and the loss
+  CHECK_ERR(row_pass(c, s.pass(), nullptr, beta, 1, s.rhs_w.as<double>(), -1.0, 1.0, r));
+  std::vector<double> h;
+  CHECK_HIP(launch_dot_cols(r, r, P, 1, sums, work, st));
+  CHECK_ERR(host_cols(c, sums, 1, h));
+  const double loss = h[0];
+  // lam = M^{-1} beta*, A lam, and the feature-scaled vectors [beta* What_q | lam What_q]
+  fs = flsq_factor_solve_normal(c, F, beta, 1, lam);
+  if (fs != FLSQ_OK) return Err{fs, c->err};
+  CHECK_ERR(row_pass(c, s.pass(), nullptr, lam, 1, nullptr, 1.0, 0.0, Alam));
+  CHECK_HIP(launch_scaled_cols(beta, lam, base->W, n, d, V, st));
+  const double* X = s.Xrm.as<double>();
+  const double mu = F->mu;
+  // T2: the operator itself, a quarter period on; its forms carry the x_ip row weights
+  std::vector<double> s3((size_t)d * K), s4((size_t)d * K);
+  {
+    System T2;
+    CHECK_ERR(build_system(c, T2, &bs, blocks, n_blocks, false));
+    CHECK_ERR(shift_phase(c, T2, 0.5 * M_PI));
+    CHECK_ERR(row_pass(c, T2.pass(), nullptr, V, K, nullptr, 1.0, 0.0, Y));
+    for (int p = 0; p < d; ++p) {
+      CHECK_HIP(launch_wsum_cols(Y, P, K, r, X, d, p, sums, work, st));
+      CHECK_HIP(launch_wsum_cols(Y, P, K, Alam, X, d, p, sums + K, work, st));
+      CHECK_ERR(host_cols(c, sums, 2 * K, h));
+      for (int k = 0; k < K; ++k) {
+        s3[(size_t)p * K + k] = h[k];
+        s4[(size_t)p * K + k] = h[K + k];
+      }
+    }
+  }
+  std::vector<double> grad;
+  for (int p = 0; p < d; ++p) {
+    // T1_p: terms (c a_p, a - e_p) of every block (a zero term where no alpha has a p component)
+    std::vector<std::vector<flsq_term>> terms(n_blocks);
+    std::vector<flsq_rows> rows(blocks, blocks + n_blocks);
+    for (int i = 0; i < n_blocks; ++i) {
+      for (int t = 0; t < blocks[i].op.n_terms; ++t) {
+        const flsq_term& tm = blocks[i].op.terms[t];
+        if (tm.alpha[p] == 0) continue;
+        flsq_term nt = tm;
+        nt.coef = tm.coef * tm.alpha[p];
+        nt.alpha[p] = (uint8_t)(tm.alpha[p] - 1);
+        terms[i].push_back(nt);
+      }
+      if (terms[i].empty()) {
+        flsq_term zt;
+        memset(&zt, 0, sizeof zt);
+        terms[i].push_back(zt);
+      }
+      rows[i].op.terms = terms[i].data();
+      rows[i].op.n_terms = (int32_t)terms[i].size();
+    }
+    System T1;
+    CHECK_ERR(build_system(c, T1, &bs, rows.data(), n_blocks, false));
+    CHECK_ERR(shift_phase(c, T1, 0.5 * M_PI));
+    CHECK_ERR(row_pass(c, T1.pass(), nullptr, V, K, nullptr, 1.0, 0.0, Y));
+    CHECK_HIP(launch_wsum_cols(Y, P, K, r, nullptr, 0, 0, sums, work, st));
+    CHECK_HIP(launch_wsum_cols(Y, P, K, Alam, nullptr, 0, 0, sums + K, work, st));
+    CHECK_ERR(host_cols(c, sums, 2 * K, h));
+    for (int q = 0; q <= p; ++q) {
+      const double rb = h[q] + s3[(size_t)p * K + q];              // r^T A' beta*
+      const double rl = h[d + q] + s3[(size_t)p * K + d + q];      // r^T A' lam
+      const double lb = h[K + q] + s4[(size_t)p * K + q];          // (A lam)^T A' beta*
+      grad.push_back(-2.0 * (rb + mu * (rl - lb)));
+    }
+  }
+  *loss_out = loss;
+  for (size_t k = 0; k < grad.size(); ++k) grad_out[k] = grad[k];
+  CHECK_HIP(hipStreamSynchronize(st));
+  return ok();
+}
+
 }  // namespace
 
 extern "C" {
@@ -1651,6 +1779,15 @@ flsq_status flsq_inverse_loss_grad(flsq_ctx* ctx, const flsq_factor* F, int64_t 
   if (hipSetDevice(ctx->device) != hipSuccess) return finish(ctx, fail(FLSQ_EHIP, "hipSetDevice failed"));
   Err e = inverse_impl(ctx, const_cast<flsq_factor*>(F), n_src_rows, src_weight, n_lap_dims, thetas, K, n_obs, x_obs,
                        data, loss_out, grad_theta_out, grad_kappa_out);
+  return finish(ctx, e);
+}
+
+flsq_status flsq_bandwidth_loss_grad(flsq_ctx* ctx, const flsq_basis* base, const double* L, const flsq_rows* blocks,
+                                     int32_t n_blocks, const flsq_solve_opts* opts, double* beta_out, double* loss_out,
+                                     double* grad_out) {
+  if (!ctx) return FLSQ_EINVAL;
+  if (hipSetDevice(ctx->device) != hipSuccess) return finish(ctx, fail(FLSQ_EHIP, "hipSetDevice failed"));
+  Err e = bandwidth_impl(ctx, base, L, blocks, n_blocks, opts, beta_out, loss_out, grad_out);
   return finish(ctx, e);
 }
 

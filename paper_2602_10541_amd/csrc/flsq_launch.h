@@ -21,6 +21,15 @@ hipError_t launch_transpose(const double* X, int64_t rows, int d, double* Xt, fl
                             hipStream_t s);
 hipError_t launch_pack_features(const double* Wrm, const double* amp, const double* ph, int n_blocks, int n, int d,
                                 double* rec, hipStream_t s);
+// Learnable bandwidth: W[j] = L What[j] (L lower triangular, row-major kMaxDim x kMaxDim by
+// value), ph += delta over count entries, V = [beta_j What_jc | lam_j What_jc] (n x 2d).
+struct LowerMat {
+  double v[kMaxDim * kMaxDim];
+};
+hipError_t launch_apply_lower(const double* What, int n, int d, const LowerMat& Lm, double* W, hipStream_t s);
+hipError_t launch_add_phase(double* ph, int64_t count, double delta, hipStream_t s);
+hipError_t launch_scaled_cols(const double* beta, const double* lam, const double* What, int n, int d, double* V,
+                              hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_scale_copy(const double* src, double* dst, int64_t n, double scale, hipStream_t s);
 hipError_t launch_assemble(const Geo& g, int fp32, void* A, hipStream_t s);
@@ -183,6 +192,10 @@ hipError_t launch_diag_max(const double* G, int n, double* out, hipStream_t s);
 // out[c] = sum_i x[i][c] * y[i][c] over n rows, K columns (deterministic two-stage).
 hipError_t launch_dot_cols(const double* x, const double* y, int64_t n, int K, double* out, double* work,
                            hipStream_t s);
+// out[c] = sum_i u_i s_i Y[i][c] (Y n x K row-major), s_i = X[i * ldx + xcol] or 1 when X is NULL
+// (deterministic two-stage reduction; work as for launch_dot_cols).
+hipError_t launch_wsum_cols(const double* Y, int64_t n, int K, const double* u, const double* X, int ldx, int xcol,
+                           double* out, double* work, hipStream_t s);
 // Per-column scalars (K <= 64) passed by value in the kernel arguments, so the iterative
 // solvers' step lengths reach the device without a copy or a stream synchronisation.
 struct ColScalars {

@@ -110,6 +110,34 @@ __global__ __launch_bounds__(kDotWg) void k_dot_stage1(const double* __restrict_
   }
 }
 
+// Weighted column sums: work[c][blk] = partial sums over the rows of sum_i u_i s_i Y[i][c], with
+// s_i = X[i * ldx + xcol] (or 1 without X); same column-chunked layout as k_dot_stage1.
+__global__ __launch_bounds__(kDotWg) void k_wsum_stage1(const double* __restrict__ Y, int64_t n, int K,
+                                                        const double* __restrict__ u, const double* __restrict__ X,
+                                                        int ldx, int xcol, double* __restrict__ work) {
+  __shared__ double red[kDotWg];
+  const int t = threadIdx.x;
+  for (int cb = 0; cb < K; cb += kDotWg) {
+    const int kc = min(kDotWg, K - cb);
+    const int R = kDotWg / kc;
+    const int c = t % kc, r = t / kc;
+    double s = 0.0;
+    if (r < R)
+      for (int64_t i = (int64_t)blockIdx.x * R + r; i < n; i += (int64_t)gridDim.x * R) {
+        const double w = X ? u[i] * X[i * ldx + xcol] : u[i];
+        s = fma(w, Y[i * K + cb + c], s);
+      }
+    red[t] = s;
+    __syncthreads();
+    if (t < kc) {
+      double acc = 0.0;
+      for (int rr = 0; rr < R; ++rr) acc += red[rr * kc + t];
+      work[(int64_t)(cb + t) * gridDim.x + blockIdx.x] = acc;
+    }
+    __syncthreads();
+  }
+}
+
 __global__ void k_dot_stage2(const double* work, int nblk, int K, double* out) {
   __shared__ double red[256];
   const int c = blockIdx.x;
@@ -129,6 +157,15 @@ hipError_t launch_dot_cols(const double* x, const double* y, int64_t n, int K, d
   const int64_t nb = (n * K + kDotWg - 1) / kDotWg;   // one step of a workgroup reads kDotWg entries
   const int nblk = (int)(nb < kDotBlocks ? (nb > 0 ? nb : 1) : kDotBlocks);
   hipLaunchKernelGGL(k_dot_stage1, dim3(nblk), dim3(kDotWg), 0, s, x, y, n, K, work);
+  hipLaunchKernelGGL(k_dot_stage2, dim3(K), dim3(256), 0, s, work, nblk, K, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_wsum_cols(const double* Y, int64_t n, int K, const double* u, const double* X, int ldx, int xcol,
+                           double* out, double* work, hipStream_t s) {
+  const int64_t nb = (n * K + kDotWg - 1) / kDotWg;
+  const int nblk = (int)(nb < kDotBlocks ? (nb > 0 ? nb : 1) : kDotBlocks);
+  hipLaunchKernelGGL(k_wsum_stage1, dim3(nblk), dim3(kDotWg), 0, s, Y, n, K, u, X, ldx, xcol, work);
   hipLaunchKernelGGL(k_dot_stage2, dim3(K), dim3(256), 0, s, work, nblk, K, out);
   return hipGetLastError();
 }

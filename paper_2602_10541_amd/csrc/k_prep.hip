@@ -169,6 +169,55 @@ hipError_t launch_pack_features(const double* Wrm, const double* amp, const doub
 }
 
 // ---------------------------------------------------------------------------------
+// Learnable bandwidth (reparameterisation W_j = L What_j): the weights from the base draws,
+// a phase shift of a built system (d/dz of every entry: sin(z + ph) -> sin(z + ph + pi/2)),
+// and the feature-scaled right-hand sides of the bilinear forms.
+// ---------------------------------------------------------------------------------
+__global__ void k_apply_lower(const double* __restrict__ What, int n, int d, LowerMat Lm, double* __restrict__ W) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  for (int k = 0; k < d; ++k) {
+    double s = 0.0;
+    for (int m = 0; m <= k; ++m) s = fma(Lm.v[k * kMaxDim + m], What[(int64_t)j * d + m], s);
+    W[(int64_t)j * d + k] = s;
+  }
+}
+
+hipError_t launch_apply_lower(const double* What, int n, int d, const LowerMat& Lm, double* W, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_apply_lower, dim3((n + 255) / 256), dim3(256), 0, s, What, n, d, Lm, W);
+  return hipGetLastError();
+}
+
+__global__ void k_add_phase(double* ph, int64_t count, double delta) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < count) ph[e] += delta;
+}
+
+hipError_t launch_add_phase(double* ph, int64_t count, double delta, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_add_phase, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, ph, count, delta);
+  return hipGetLastError();
+}
+
+// V[j][c] = beta_j What_jc for c < d, lam_j What_j(c - d) for d <= c < 2d
+__global__ void k_scaled_cols(const double* __restrict__ beta, const double* __restrict__ lam,
+                              const double* __restrict__ What, int n, int d, double* __restrict__ V) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)n * 2 * d) return;
+  const int j = (int)(e / (2 * d)), c = (int)(e % (2 * d));
+  V[e] = (c < d ? beta[j] : lam[j]) * What[(int64_t)j * d + (c < d ? c : c - d)];
+}
+
+hipError_t launch_scaled_cols(const double* beta, const double* lam, const double* What, int n, int d, double* V,
+                              hipStream_t s) {
+  const int64_t tot = (int64_t)n * 2 * d;
+  if (tot == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scaled_cols, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, beta, lam, What, n, d, V);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------
 // Evaluation (Eq. (1)-(2)): out[q][a] = norm * sum_j beta_j W_j^{alpha_a} Phi_{|alpha_a|}(z_qj).
 // coef[a][j] = norm * beta_j * W_j^{alpha_a} * (+1 | -1) with the sign of Phi folded in, so
 // every output needs only sin z (even order) or cos z (odd order).

@@ -29,7 +29,7 @@ EXPORTS = (
     "flsq_create", "flsq_destroy", "flsq_last_error", "flsq_build_info", "flsq_assemble", "flsq_gram",
     "flsq_solve_linear", "flsq_factorize", "flsq_factor_free", "flsq_factor_shape", "flsq_factor_solve",
     "flsq_factor_solve_normal", "flsq_apply_A", "flsq_apply_At", "flsq_evaluate", "flsq_solve_newton",
-    "flsq_inverse_loss_grad", "flsq_adam_step",
+    "flsq_inverse_loss_grad", "flsq_bandwidth_loss_grad", "flsq_adam_step",
 )
 
 
@@ -126,6 +126,8 @@ def load(path: str = LIB_PATH):
                                    C.POINTER(flsq_nonlin), C.POINTER(flsq_newton_opts), vp,
                                    C.POINTER(flsq_newton_trace)]),
         "flsq_inverse_loss_grad": (st, [vp, vp, i64, dbl, i32, vp, i32, i64, vp, vp, vp, vp, vp]),
+        "flsq_bandwidth_loss_grad": (st, [vp, C.POINTER(flsq_basis), C.POINTER(dbl), C.POINTER(flsq_rows), i32,
+                                          C.POINTER(flsq_solve_opts), vp, C.POINTER(dbl), C.POINTER(dbl)]),
         "flsq_adam_step": (st, [vp, vp, vp, vp, vp, i32, i32, i32, dbl, dbl, dbl, dbl, i32, dbl]),
     }
     missing = [name for name in sig if not hasattr(lib, name)]
@@ -360,6 +362,20 @@ def flsq_inverse_loss_grad(ctx, F: Factor, n_src_rows, src_weight, n_lap_dims, t
         ctx.h, F.h, int(n_src_rows), float(src_weight), int(n_lap_dims), _ptr(thetas), int(thetas.shape[0]),
         int(x_obs.shape[0]), _ptr(x_obs), _ptr(data), _ptr(loss_out), _ptr(grad_theta_out),
         _ptr(grad_kappa_out)))
+
+
+def flsq_bandwidth_loss_grad(ctx, base: Basis, L, rows: Rows, opts: flsq_solve_opts, beta_out):
+    """Outer loss ||A(L) beta* - b||^2 and its gradient in the lower-triangular L (packed row by row),
+    with W_j = L What_j for the frozen draws in `base`.  L: host d x d (any array-like)."""
+    import numpy as np
+    Lh = np.ascontiguousarray(np.asarray(L, dtype=np.float64))
+    d = Lh.shape[0]
+    loss = C.c_double()
+    grad = (C.c_double * (d * (d + 1) // 2))()
+    ctx.check(ctx.lib.flsq_bandwidth_loss_grad(
+        ctx.h, C.byref(base.struct), Lh.ctypes.data_as(C.POINTER(C.c_double)), rows.array, rows.n_blocks,
+        C.byref(opts), _ptr(beta_out), C.byref(loss), grad))
+    return loss.value, np.array(grad[:], dtype=np.float64)
 
 
 def flsq_adam_step(ctx, params, grads, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8, clamp_col=-1, clamp_min=0.0):
