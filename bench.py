@@ -292,6 +292,64 @@ def bench_c3(fl, ctx):
     return res
 
 
+def bench_bandwidth(fl, ctx, reps=20):
+    """Learnable bandwidth (Helmholtz 2D, k = 10, N = 500 base draws, 2000 interior + 400 boundary
+    rows): the outer loss and its L gradient through the exact inner solve, per evaluation, and the
+    80-step AdamW run on the scalar bandwidth from sigma0 = 5 (lr 0.1) against the oracle's."""
+    import torch
+    from paper_2602_10541_amd import workloads as wl
+    from paper_2602_10541_amd.bandwidth import LearnableBandwidth
+    prob = wl.config("helmholtz_bandwidth")
+    gold = _gold("helmholtz_bandwidth")
+    dp = fl.DeviceProblem(prob)
+    beta = torch.empty(prob.n_feat, dtype=torch.float64, device="cuda")
+    res = {"workload": "helmholtz_2d bandwidth: Laplace u + 100 u = f on [0,1]^2, u = sin(10x) sin(10y), N=500 "
+                       "base draws What ~ N(0, I), W = L What, 2000 interior + 400 boundary rows, mu=1e-10",
+           "paper_context": "80 AdamW steps (lr 0.1) on sigma from 5, N=500, loss 2.1e-2 -> 8.1e-8 "
+                            "(the paper's learnable-bandwidth results; its own Helmholtz data)"}
+    for name, prec in (("fp64", fl.PREC_FP64), ("int8_crt", fl.PREC_INT8_CRT)):
+        opts = fl.solve_opts(prob.mu, prec, 30, 1e-12)
+
+        def ev(L):
+            return fl.flsq_bandwidth_loss_grad(ctx, dp.basis, L, dp.rows, opts, beta)
+        L0 = prob.extras["L0"]
+        ev(L0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            loss, grad = ev(L0)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        r = {"ms_per_loss_and_grad": 1e3 * dt, "loss_sigma0": loss}
+        if gold is not None:
+            r["grad_rel_err_vs_oracle"] = float(np.abs(grad - gold["grad0"]).max() / np.abs(gold["grad0"]).max())
+            r["loss_rel_err_vs_oracle"] = float(abs(loss - gold["loss0"]) / gold["loss0"])
+        if name == "fp64":
+            lb = LearnableBandwidth(ctx, dp.basis, dp.rows, opts, prob.d, scalar=True)
+            t0 = time.perf_counter()
+            sigs, losses, _ = lb.fit_adamw([prob.extras["sigma0"]], steps=80, lr=0.1)
+            t_adam = time.perf_counter() - t0
+            sigs = sigs[:, 0]
+            r["adamw_80"] = {"total_s": t_adam, "sigma_final": float(sigs[-1]), "loss_first": float(losses[0]),
+                             "loss_last": float(losses[-1])}
+            if gold is not None:
+                r["adamw_80"]["max_sigma_rel_diff_vs_oracle"] = float(np.abs(sigs - gold["adamw_sigma"]).max() /
+                                                                      sigs.max())
+        res[name] = r
+    return res
+
+
+def cpu_bandwidth_baseline():
+    """One oracle evaluation of the learnable-bandwidth loss and gradient (explicit assembly of A and
+    of dA/dL_pq, Householder QR) on the same workload."""
+    import oracle
+    from paper_2602_10541_amd import workloads as wl
+    prob = wl.config("helmholtz_bandwidth")
+    t0 = time.perf_counter()
+    oracle.bandwidth_loss_and_grad(prob, prob.W, prob.extras["L0"])
+    return {"s_per_loss_and_grad": time.perf_counter() - t0, "cores": oracle.num_threads(), "kind": "oracle"}
+
+
 def bench_c5(fl, ctx, reps=5):
     """Inverse heat source (N = 2048, 12288 rows, 400 observations): factor once, then loss and
     adjoint gradients for 64 source hypotheses per call (one Adam step's work)."""
@@ -463,8 +521,11 @@ def main():
         out["newton_c3"] = bench_c3(fl, ctx)
         out["inverse_c5"] = bench_c5(fl, ctx)
         out["rhs_sweep_cached"] = bench_sweep(fl, ctx)
+        out["learnable_bandwidth"] = bench_bandwidth(fl, ctx)
     if not args.skip_cpu:
         out["cpu_baseline"] = cpu_baseline(prob)
+        if "learnable_bandwidth" in out:
+            out["learnable_bandwidth"]["cpu_oracle"] = cpu_bandwidth_baseline()
     print(json.dumps(out), flush=True)
     ctx.close()
 
