@@ -439,3 +439,140 @@ def bandwidth_loss_and_grad(prob, What, L):
         dAb = dA @ beta
         grad.append(-2.0 * (r @ dAb + prob.mu * (r @ (dA @ lam) - Alam @ dAb)))
     return loss, np.array(grad), beta
+
+
+# ---------------------------------------------------------------------------
+# Row-dependent coefficients (the coil operator of the applications section,
+# nu Laplace u + grad nu . grad u) and nonlinearities that involve first
+# derivatives (steady Burgers u u' - nu u'' of the Newton experiments, solved by
+# continuation in nu as Section 2.4 describes)
+# ---------------------------------------------------------------------------
+
+def assemble_var(W, b, x, channels, weight=1.0, normalize=True) -> np.ndarray:
+    """A_ij = weight * sum_t a_t(x_i) * L_t[phi_j](x_i): each channel is (terms, a) with a the
+    per-row coefficient array (None = 1) and L_t the constant-coefficient operator of Eq. (2)."""
+    x = _f64(x)
+    A = np.zeros((x.shape[0], _f64(W).shape[0]))
+    for terms, a in channels:
+        At = assemble(W, b, x, terms, weight, normalize)
+        A += At if a is None else _f64(a)[:, None] * At
+    return A
+
+
+def assemble_var_system(prob):
+    As, rs = [], []
+    for bl in prob.blocks:
+        As.append(assemble_var(prob.W, prob.b, bl.x, bl.channels, bl.weight, prob.normalize))
+        rs.append(bl.weight * _f64(bl.rhs))
+    return np.vstack(As), np.concatenate(rs)
+
+
+def solve_linear_var(prob):
+    """The Tikhonov least-squares solve of Eq. (3) with row-dependent coefficients."""
+    A, r = assemble_var_system(prob)
+    return tikhonov(A, r, prob.mu)
+
+
+def nonlin_grad_value(poly, adv, u, du):
+    """N(u, grad u) = sum_k poly_k u^k + sum_t c_t u^{m_t} d_{axis_t} u, and its partial
+    derivatives: dN/du (an array) and dN/d(d_k u) per axis k (a dict)."""
+    poly = tuple(poly or ())
+    val = _poly(poly, u) if poly else np.zeros_like(u)
+    dval_u = _dpoly(poly, u) if len(poly) > 1 else np.zeros_like(u)
+    dval_g = {}
+    for c, m, ax in adv:
+        g = du[ax]
+        val = val + c * u ** m * g
+        if m > 0:
+            dval_u = dval_u + c * m * u ** (m - 1) * g
+        dval_g[ax] = dval_g.get(ax, 0.0) + c * u ** m
+    return val, dval_u, dval_g
+
+
+def _axes(prob):
+    return sorted({ax for _, _, ax in prob.nonlin_adv})
+
+
+def newton_var_residual(prob, beta):
+    """R_i = w (sum_t a_t(x_i) L_t[u_N](x_i) + N(u_N, grad u_N)(x_i) - data_i), stacked, with u_N
+    and its first derivatives at every row of the nonlinear block; also u_N at every row."""
+    d = prob.d
+    zero = tuple([0] * d)
+    unit = [tuple(1 if k == ax else 0 for k in range(d)) for ax in range(d)]
+    parts, us = [], []
+    for bi, bl in enumerate(prob.blocks):
+        Lu = np.zeros(bl.x.shape[0])
+        for terms, a in bl.channels:
+            v = apply_operator(prob.W, prob.b, beta, bl.x, terms, prob.normalize)
+            Lu = Lu + (v if a is None else _f64(a) * v)
+        ev = evaluate(prob.W, prob.b, beta, bl.x, [zero] + unit, prob.normalize)
+        u = ev[:, 0]
+        if bi == prob.nonlin_block:
+            val, _, _ = nonlin_grad_value(prob.nonlin_poly, prob.nonlin_adv, u, {k: ev[:, 1 + k] for k in range(d)})
+            Lu = Lu + val
+        parts.append(bl.weight * (Lu - _f64(bl.rhs)))
+        us.append(u)
+    return np.concatenate(parts), us
+
+
+def newton_var_jacobian(prob, beta):
+    """J_ij = dR_i/dbeta_j: the linear rows, plus on the nonlinear block
+    w (dN/du phi_j(x_i) + sum_k dN/d(d_k u) d_k phi_j(x_i)) (Section 2.4: the Jacobian keeps the
+    closed form of Eq. (2))."""
+    d = prob.d
+    zero = tuple([0] * d)
+    unit = [tuple(1 if k == ax else 0 for k in range(d)) for ax in range(d)]
+    Js = []
+    for bi, bl in enumerate(prob.blocks):
+        J = assemble_var(prob.W, prob.b, bl.x, bl.channels, bl.weight, prob.normalize)
+        if bi == prob.nonlin_block:
+            ev = evaluate(prob.W, prob.b, beta, bl.x, [zero] + unit, prob.normalize)
+            _, du_, dg = nonlin_grad_value(prob.nonlin_poly, prob.nonlin_adv, ev[:, 0],
+                                           {k: ev[:, 1 + k] for k in range(d)})
+            J = J + du_[:, None] * assemble(prob.W, prob.b, bl.x, [(1.0, zero)], bl.weight, prob.normalize)
+            for ax, coef in dg.items():
+                J = J + _f64(coef)[:, None] * assemble(prob.W, prob.b, bl.x, [(1.0, unit[ax])], bl.weight,
+                                                       prob.normalize)
+        Js.append(J)
+    return np.vstack(Js)
+
+
+def solve_newton_var(prob, beta0=None, max_iter=30, tol_du=1e-10, tol_dbeta=0.0, armijo_c=1e-4, max_halvings=10):
+    """Newton-Raphson of Section 2.4 with its refinements: warm start from the linear part
+    (nonlinearity dropped) unless beta0 is given, the Tikhonov step, Armijo backtracking on the
+    residual norm, and the solution-level stop ||Delta u|| / ||u|| < tol_du at the collocation
+    points (or ||alpha delta|| < tol_dbeta)."""
+    beta = solve_linear_var(prob) if beta0 is None else _f64(beta0).copy()
+    trace = []
+    for it in range(max_iter):
+        R, us = newton_var_residual(prob, beta)
+        nR = float(np.linalg.norm(R))
+        J = newton_var_jacobian(prob, beta)
+        delta = tikhonov(J, -R, prob.mu)
+        alpha, halv = 1.0, 0
+        while True:
+            Rt, _ = newton_var_residual(prob, beta + alpha * delta)
+            if np.linalg.norm(Rt) <= (1.0 - armijo_c * alpha) * nR or halv >= max_halvings:
+                break
+            alpha *= 0.5
+            halv += 1
+        step = alpha * delta
+        beta = beta + step
+        u_old = np.concatenate(us)
+        u_new = np.concatenate(newton_var_residual(prob, beta)[1])
+        du_rel = float(np.linalg.norm(u_new - u_old) / max(np.linalg.norm(u_new), 1e-300))
+        trace.append(dict(it=it, res_norm=nR, alpha=alpha, halvings=halv, step_norm=float(np.linalg.norm(step)),
+                          du_rel=du_rel))
+        if du_rel < tol_du or np.linalg.norm(step) < tol_dbeta:
+            break
+    return beta, trace
+
+
+def continuation(make_problem, params, **newton_kw):
+    """Homotopy (Section 2.4): solve the problems make_problem(p) for p in order, each from the
+    previous solution; the first from its own linear warm start."""
+    beta, traces = None, []
+    for p in params:
+        beta, tr = solve_newton_var(make_problem(p), beta0=beta, **newton_kw)
+        traces.append(tr)
+    return beta, traces

@@ -55,6 +55,22 @@ class Block:
 
 
 @dataclass
+class VarBlock:
+    """A row block whose operator has row-dependent coefficients:
+    sum_t a_t(x_i) L_t[u](x_i), with ``channels`` = [(terms_t, a_t)] (a_t an n-array, or None
+    for 1); ``weight`` and ``rhs`` as for Block."""
+    name: str
+    x: np.ndarray
+    channels: list
+    weight: float
+    rhs: np.ndarray
+
+    @property
+    def n(self) -> int:
+        return int(self.x.shape[0])
+
+
+@dataclass
 class Problem:
     name: str
     d: int
@@ -69,6 +85,8 @@ class Problem:
     # Pointwise nonlinearity N(u) = sum_k poly[k] u^k on block ``nonlin_block``.
     nonlin_poly: tuple | None = None
     nonlin_block: int = -1
+    # First-derivative terms of the nonlinearity: sum_t c_t u^{m_t} d_{axis_t} u, as (c, m, axis).
+    nonlin_adv: tuple = ()
     extras: dict = field(default_factory=dict)
 
     @property
@@ -326,6 +344,58 @@ def helmholtz_bandwidth(n_feat: int = 500, sigma0: float = 5.0, n_int: int = 200
                    extras={"sigma0": sigma0, "k": k, "L0": sigma0 * np.eye(d), "exact": "sin(k x) sin(k y)"})
 
 
+BURGERS_STAGES = (1.0, 0.5, 0.2, 0.1)
+
+
+def burgers_1d(nu: float = 0.1, n_feat: int = 1000, sigma: float = 10.0, n_int: int = 4000, seed: int = 0,
+               n_test: int = 2000) -> Problem:
+    """Steady viscous Burgers u u' - nu u'' = 0 on [0, 1] with Dirichlet data from its exact
+    solution u = -tanh((x - 1/2) / (2 nu)); the nonlinearity u u' acts on the interior rows.
+    The continuation of Section 2.4 solves it for nu in ``BURGERS_STAGES``, each stage from the
+    previous one's solution; every stage has the same features and points."""
+    d = 1
+    r = _rngs(seed)
+    W, b = draw_features(r, n_feat, [sigma])
+    xi = sample_box(r["interior"], n_int, d)
+    xb = np.array([[0.0], [1.0]])
+    u = lambda x: -np.tanh((x[:, 0] - 0.5) / (2.0 * nu))
+    blocks = [
+        VarBlock("interior", xi, [([(-nu, (2,))], None)], 1.0, np.zeros(n_int)),
+        VarBlock("boundary", xb, [(identity_terms(d), None)], LAM_BC, u(xb)),
+    ]
+    xt = sample_box(np.random.default_rng(seed + 1), n_test, d)
+    return Problem("burgers_1d", d, n_feat, W, b, blocks, x_test=xt, u_test=u(xt), nonlin_block=0,
+                   nonlin_adv=((1.0, 1, 0),), extras={"sigma": sigma, "nu": nu, "exact": "-tanh((x - 1/2) / (2 nu))"})
+
+
+def varcoef_2d(n_feat: int = 1500, sigma: float = 3.0, n_int: int = 6000, n_bc: int = 1200, seed: int = 0,
+               n_test: int = 5000) -> Problem:
+    """A coil-type operator with a variable coefficient: nu Laplace u + grad nu . grad u = g on
+    [0,1]^2 with nu = 1 + sin(2 pi x) cos(pi y) / 2, exact u = sin(pi x) cos(2 pi y), g derived from
+    u by hand, Dirichlet data u.  Interior channels: (Laplace, nu), (d_x, nu_x), (d_y, nu_y)."""
+    d = 2
+    r = _rngs(seed)
+    W, b = draw_features(r, n_feat, [sigma] * d)
+    xi = sample_box(r["interior"], n_int, d)
+    xb = sample_faces(r["boundary"], n_bc, d, range(d))
+    X, Y = xi[:, 0], xi[:, 1]
+    nu = 1.0 + 0.5 * np.sin(2 * PI * X) * np.cos(PI * Y)
+    nu_x = PI * np.cos(2 * PI * X) * np.cos(PI * Y)
+    nu_y = -0.5 * PI * np.sin(2 * PI * X) * np.sin(PI * Y)
+    u = lambda x: np.sin(PI * x[:, 0]) * np.cos(2 * PI * x[:, 1])
+    ux = PI * np.cos(PI * X) * np.cos(2 * PI * Y)
+    uy = -2 * PI * np.sin(PI * X) * np.sin(2 * PI * Y)
+    g = nu * (-5 * PI * PI * u(xi)) + nu_x * ux + nu_y * uy
+    channels = [(laplacian_terms(d, range(d), 1.0), nu), ([(1.0, (1, 0))], nu_x), ([(1.0, (0, 1))], nu_y)]
+    blocks = [
+        VarBlock("interior", xi, channels, 1.0, g),
+        VarBlock("boundary", xb, [(identity_terms(d), None)], LAM_BC, u(xb)),
+    ]
+    xt = sample_box(np.random.default_rng(seed + 1), n_test, d)
+    return Problem("varcoef_2d", d, n_feat, W, b, blocks, x_test=xt, u_test=u(xt),
+                   extras={"sigma": sigma, "exact": "sin(pi x) cos(2 pi y)", "nu": "1 + sin(2 pi x) cos(pi y) / 2"})
+
+
 def config(name: str, seed: int = 0, **kw) -> Problem:
     if name == "poisson2d":      # 2000 interior + 400 boundary, N = 500, sigma = 3, fp64
         return poisson(2, kw.pop("n_feat", 500), 3.0, kw.pop("n_int", 2000), kw.pop("n_bc", 400),
@@ -341,6 +411,10 @@ def config(name: str, seed: int = 0, **kw) -> Problem:
         return inverse_heat(seed=seed, **kw)
     if name == "helmholtz_sweep":   # matrix caching: 64 boundary-data sweeps, N = 1500, 6000 rows
         return helmholtz_sweep(seed=seed, **kw)
+    if name == "burgers1d":             # steady Burgers, nu = 0.1 (the last continuation stage), N = 1000
+        return burgers_1d(seed=seed, **kw)
+    if name == "varcoef2d":             # coil-type variable-coefficient operator, N = 1500, 7200 rows
+        return varcoef_2d(seed=seed, **kw)
     if name == "helmholtz_bandwidth":   # learnable bandwidth: N = 500 base draws, sigma0 = 5, k = 10
         return helmholtz_bandwidth(seed=seed, **kw)
     raise KeyError(name)
