@@ -247,6 +247,68 @@ flsq_status flsq_bandwidth_loss_grad(flsq_ctx* ctx, const flsq_basis* base, cons
                                      int32_t n_blocks, const flsq_solve_opts* opts, double* beta_out,
                                      double* loss_out, double* grad_out);
 
+/* ---- Row-dependent coefficients (the coil operator nu Laplace A + grad nu . grad A of the
+ * applications section) and nonlinearities with first derivatives (steady Burgers u u' - nu u''
+ * of the Newton experiments, Section 2.4) ----
+ * A row block whose operator is sum_t a_t(x) L_t with constant-coefficient operators L_t
+ * (Eq. (2) per channel) and per-row coefficients a_t:
+ *   A_ij = weight * sum_t a_t(x_i) L_t[phi_j](x_i),   data weight * rhs_i.
+ * These operators are assembled explicitly to HBM (row-major and transposed, 16 P N bytes) and
+ * solved through the Gram of the stored matrix on the FP64 matrix cores, the FP64 Cholesky of
+ * flsq_solve_linear and CGLS refinement with the stored matrix; only FLSQ_PREC_FP64 is accepted. */
+#define FLSQ_MAX_CHANNELS 8
+
+typedef struct {
+    flsq_op op;              /* L_t (host terms) */
+    const double* coef;      /* device n_rows: a_t(x_i) for the block's rows; NULL means a_t = 1 */
+} flsq_channel;
+
+typedef struct {
+    int64_t n_rows;
+    const double* x;         /* device n_rows x d */
+    double weight;
+    const double* rhs;       /* device n_rows (unweighted data); required by the solvers */
+    int32_t n_channels;      /* 1 .. FLSQ_MAX_CHANNELS */
+    const flsq_channel* channels;   /* host array of n_channels */
+} flsq_vrows;
+
+/* A_out device P x n_feat (row-major, P = sum of block rows) = the stacked weighted operator
+ * rows; rhs_out (nullable) device P = weight * rhs. */
+flsq_status flsq_assemble_var(flsq_ctx* ctx, const flsq_basis* basis, const flsq_vrows* blocks, int32_t n_blocks,
+                              double* A_out, double* rhs_out);
+
+/* beta_out device n_feat = argmin ||A beta - rhs_w||^2 + mu ||beta||^2 for the stacked blocks
+ * (opts->prec must be FLSQ_PREC_FP64).  info may be NULL; FLSQ_ENOCONV as for flsq_solve_linear. */
+flsq_status flsq_solve_linear_var(flsq_ctx* ctx, const flsq_basis* basis, const flsq_vrows* blocks,
+                                  int32_t n_blocks, const flsq_solve_opts* opts, double* beta_out,
+                                  flsq_solve_info* info);
+
+/* N(u, grad u) = sum_k poly[k] u^k + sum_t adv_coef[t] u^{adv_pow[t]} d_{adv_axis[t]} u
+ * (host arrays; n_poly <= 8, n_adv <= 8, adv_pow >= 0, 0 <= adv_axis < d).  Steady Burgers:
+ * n_poly = 0, one advection term (1, 1, 0). */
+typedef struct {
+    int32_t n_poly;
+    const double* poly;
+    int32_t n_adv;
+    const double* adv_coef;
+    const int32_t* adv_pow;
+    const int32_t* adv_axis;
+} flsq_nonlin_grad;
+
+/* Newton-Raphson (Section 2.4) for sum_t a_t L_t[u] + N(u, grad u) = f, N acting on block
+ * `nonlin_block`: residual R_i = w (L[u_N](x_i) + N(u_N, grad u_N)(x_i) - data_i), Jacobian rows
+ * L[phi_j] + dN/du phi_j + sum_k dN/d(d_k u) d_k phi_j in closed form, each step the Tikhonov
+ * least squares of Eq. (5) with Armijo backtracking (opts->armijo_c, opts->max_halvings).
+ * Warm start (opts->warm_start = 1): beta_inout is overwritten by the linear solve with N dropped;
+ * otherwise beta_inout is the starting point (continuation in a parameter passes each stage's
+ * solution to the next).  Stops when ||Delta u|| / ||u|| at every collocation row < tol_du, or
+ * ||alpha delta|| < opts->tol_dbeta; FLSQ_ENOCONV if neither within opts->max_iter (<= 64) steps.
+ * opts->lin.prec must be FLSQ_PREC_FP64.  trace may be NULL. */
+flsq_status flsq_solve_newton_var(flsq_ctx* ctx, const flsq_basis* basis, const flsq_vrows* blocks,
+                                  int32_t n_blocks, int32_t nonlin_block, const flsq_nonlin_grad* nonlin,
+                                  const flsq_newton_opts* opts, double tol_du, double* beta_inout,
+                                  flsq_newton_trace* trace);
+
 /* Batched Adam step on K x P parameters (all device arrays, updated in place):
  * m = b1 m + (1 - b1) g; v = b2 v + (1 - b2) g^2; p -= lr * (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps);
  * then p[:, clamp_col] = max(p[:, clamp_col], clamp_min) when clamp_col >= 0. */

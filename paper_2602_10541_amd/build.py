@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libfastlsq.so")
-SOURCES = ["fastlsq.cpp", "k_prep.hip", "k_gram.hip", "k_linalg.hip", "k_pass.hip", "k_inverse.hip", "k_dense.hip", "k_chol.hip", "k_gram_i8.hip"]
+SOURCES = ["fastlsq.cpp", "k_prep.hip", "k_gram.hip", "k_linalg.hip", "k_pass.hip", "k_inverse.hip", "k_dense.hip", "k_chol.hip", "k_gram_i8.hip", "k_var.hip"]
 ARCH = os.environ.get("FLSQ_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

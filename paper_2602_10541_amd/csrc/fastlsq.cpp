@@ -754,13 +754,71 @@ double predicted_step(int it, double prev, double cur) {
 // the collocation rows of blocks with even-order operators, |alpha| ||H p|| <= tol ||H X||,
 // where H p comes out of the same row pass as A p.  When no such rows exist (or K > 16)
 // the change of the fitted values |alpha| ||A p|| <= tol ||Y|| is used instead.
-Err cgls_refine(flsq_ctx* c, const System& s, const double* rho, const double* Xi, double mu, const double* Y, int K,
-                double* X, int max_iter, double tol, bool want_grad0, bool want_grad, RefineOut* ro) {
-  const int n = s.n;
-  const int64_t P = s.P;
-  const PassGeo pg = s.pass();
-  const bool track_u = (K <= 16) && pg.even_mask != 0;
-  double *sres, *q, *g, *z, *p, *dots, *dwork, *colwork, *uu = nullptr, *hq = nullptr;
+// The operator the refinement applies: out = beta_y Y + alpha A V (and, optionally, the
+// solution values u = H V on even-order blocks) and out = beta_v V + alpha A^T Y.
+struct LsqOp {
+  int n = 0;
+  int64_t P = 0;
+  virtual bool track_u(int K) const = 0;
+  virtual Err apply(flsq_ctx* c, const double* V, int K, const double* Y, double alpha, double beta_y, double* out,
+                    double* u_out) const = 0;
+  virtual Err applyT(flsq_ctx* c, const double* Y, int K, const double* V, double alpha, double beta_v,
+                     double* out) const = 0;
+  virtual ~LsqOp() = default;
+};
+
+// A recomputed in FP64 by the row and column passes (matrix-free).
+struct PassOp final : LsqOp {
+  PassGeo pg;
+  const double* rho;
+  int n_runs;
+  PassOp(const System& s, const double* r) : pg(s.pass()), rho(r), n_runs(s.n_runs) {
+    n = s.n;
+    P = s.P;
+  }
+  bool track_u(int K) const override { return K <= 16 && pg.even_mask != 0; }
+  Err apply(flsq_ctx* c, const double* V, int K, const double* Y, double alpha, double beta_y, double* out,
+            double* u_out) const override {
+    return row_pass(c, pg, rho, V, K, Y, alpha, beta_y, out, u_out);
+  }
+  Err applyT(flsq_ctx* c, const double* Y, int K, const double* V, double alpha, double beta_v,
+             double* out) const override {
+    double* colwork;
+    CHECK_ERR(ws_get(c, "cg_colwork", pass_work_elems(n, n_runs, K) + 64, &colwork));
+    CHECK_HIP(launch_colpass_runs(pg, rho, Y, K, V, alpha, beta_v, out, colwork, c->stream));
+    return ok();
+  }
+};
+
+// A stored in HBM, row-major (P x n) and transposed (n x P); one column.
+struct DenseOp final : LsqOp {
+  const double* A;
+  const double* At;
+  DenseOp(const double* a, const double* at, int n_, int64_t P_) : A(a), At(at) {
+    n = n_;
+    P = P_;
+  }
+  bool track_u(int) const override { return false; }
+  Err apply(flsq_ctx* c, const double* V, int K, const double* Y, double alpha, double beta_y, double* out,
+            double*) const override {
+    if (K != 1) return fail(FLSQ_EINVAL, "internal: the stored-matrix operator takes one column");
+    CHECK_HIP(launch_rowdot(A, P, n, n, V, Y, alpha, beta_y, out, c->stream));
+    return ok();
+  }
+  Err applyT(flsq_ctx* c, const double* Y, int K, const double* V, double alpha, double beta_v,
+             double* out) const override {
+    if (K != 1) return fail(FLSQ_EINVAL, "internal: the stored-matrix operator takes one column");
+    CHECK_HIP(launch_rowdot(At, n, P, P, Y, V, alpha, beta_v, out, c->stream));
+    return ok();
+  }
+};
+
+Err cgls_refine_op(flsq_ctx* c, const LsqOp& op, const double* Xi, double mu, const double* Y, int K, double* X,
+                   int max_iter, double tol, bool want_grad0, bool want_grad, RefineOut* ro) {
+  const int n = op.n;
+  const int64_t P = op.P;
+  const bool track_u = op.track_u(K);
+  double *sres, *q, *g, *z, *p, *dots, *dwork, *uu = nullptr, *hq = nullptr;
   if (track_u) {
     CHECK_ERR(ws_get(c, "cg_u", (size_t)P * K, &uu));
     CHECK_ERR(ws_get(c, "cg_hq", (size_t)P * K, &hq));
@@ -772,13 +830,12 @@ Err cgls_refine(flsq_ctx* c, const System& s, const double* rho, const double* X
   CHECK_ERR(ws_get(c, "cg_p", (size_t)n * K, &p));
   CHECK_ERR(ws_get(c, "cg_dots", (size_t)12 * K, &dots));
   CHECK_ERR(ws_get(c, "cg_dwork", (size_t)512 * K + 64, &dwork));
-  CHECK_ERR(ws_get(c, "cg_colwork", pass_work_elems(n, s.n_runs, K) + 64, &colwork));
   hipStream_t st = c->stream;
   std::vector<double> tmp, stepn(K);
 
   // s = Y - A X ; g = A^T s - mu X ; u = H X
-  CHECK_ERR(row_pass(c, pg, rho, X, K, Y, -1.0, 1.0, sres, uu));
-  CHECK_HIP(launch_colpass_runs(pg, rho, sres, K, X, 1.0, -mu, g, colwork, st));
+  CHECK_ERR(op.apply(c, X, K, Y, -1.0, 1.0, sres, uu));
+  CHECK_ERR(op.applyT(c, sres, K, X, 1.0, -mu, g));
   if (want_grad0) {
     CHECK_HIP(launch_dot_cols(g, g, n, K, dots, dwork, st));
     CHECK_ERR(host_cols(c, dots, K, tmp));
@@ -825,7 +882,7 @@ Err cgls_refine(flsq_ctx* c, const System& s, const double* rho, const double* X
   std::vector<double> hs(8 * K);
   for (int it = 0; it < max_iter; ++it) {
     // q = A p ; delta = ||q||^2 + mu ||p||^2 ; hq = H p ; alpha = gam / delta
-    CHECK_ERR(row_pass(c, pg, rho, p, K, nullptr, 1.0, 0.0, q, hq));
+    CHECK_ERR(op.apply(c, p, K, nullptr, 1.0, 0.0, q, hq));
     CHECK_HIP(launch_dot_cols(q, q, P, K, d_qq, dwork, st));
     CHECK_HIP(launch_dot_cols(p, p, n, K, d_pp, dwork, st));
     if (track_u) {
@@ -896,7 +953,7 @@ Err cgls_refine(flsq_ctx* c, const System& s, const double* rho, const double* X
     }
     if (it + 1 == max_iter) break;
     // g = A^T s - mu X ; z = M^{-1} g ; beta = (g.z) / gam ; p = z + beta p
-    CHECK_HIP(launch_colpass_runs(pg, rho, sres, K, X, 1.0, -mu, g, colwork, st));
+    CHECK_ERR(op.applyT(c, sres, K, X, 1.0, -mu, g));
     CHECK_ERR(chol_solve(c, Xi, n, g, z, K));
     CHECK_HIP(launch_dot_cols(g, z, n, K, d_gnew, dwork, st));
     CHECK_HIP(launch_cg_beta(d_gnew, d_gam, K, d_beta, st));
@@ -906,8 +963,8 @@ Err cgls_refine(flsq_ctx* c, const System& s, const double* rho, const double* X
   CHECK_HIP(hipMemcpyAsync(X, Xbest, sizeof(double) * n * K, hipMemcpyDeviceToDevice, st));
   if (stalled_all) ro->converged = true;   // no further progress is possible in FP64
   if (want_grad) {
-    CHECK_ERR(row_pass(c, pg, rho, X, K, Y, -1.0, 1.0, sres));
-    CHECK_HIP(launch_colpass_runs(pg, rho, sres, K, X, 1.0, -mu, g, colwork, st));
+    CHECK_ERR(op.apply(c, X, K, Y, -1.0, 1.0, sres, nullptr));
+    CHECK_ERR(op.applyT(c, sres, K, X, 1.0, -mu, g));
     CHECK_HIP(launch_dot_cols(g, g, n, K, dots, dwork, st));
     CHECK_ERR(host_cols(c, dots, K, tmp));
     double m = 0;
@@ -915,6 +972,11 @@ Err cgls_refine(flsq_ctx* c, const System& s, const double* rho, const double* X
     ro->grad = m;
   }
   return ok();
+}
+
+Err cgls_refine(flsq_ctx* c, const System& s, const double* rho, const double* Xi, double mu, const double* Y, int K,
+                double* X, int max_iter, double tol, bool want_grad0, bool want_grad, RefineOut* ro) {
+  return cgls_refine_op(c, PassOp(s, rho), Xi, mu, Y, K, X, max_iter, tol, want_grad0, want_grad, ro);
 }
 
 // ------------------------------------------------------------------ one full solve on a built system
@@ -1753,6 +1815,432 @@ Err bandwidth_impl(flsq_ctx* c, const flsq_basis* base, const double* L, const f
   return ok();
 }
 
+// ------------------------------------------------------------------ row-dependent coefficients
+// Blocks sum_t a_t(x) L_t: each channel folded per feature into (S, C) as Eq. (2) folds a
+// constant-coefficient operator, the per-row coefficients gathered into a T x P table.  The
+// matrix is assembled to HBM (the Gram contracts the stored rows on the FP64 matrix cores;
+// refinement products stream them), since a row-dependent coefficient on the cosine part does
+// not fit the one-sine-per-entry form of the matrix-free passes.
+struct VarSys {
+  int d = 0, n = 0, n_blocks = 0, T = 0;
+  int64_t P = 0;
+  const double* W = nullptr;
+  const double* b = nullptr;
+  std::vector<int64_t> row0, rows;
+  std::vector<double> weight;
+  std::vector<int> n_ch;
+  DevBuf X, row_block, S, C, acoef, rhs_w, terms, off, scale;
+  VarGeo geo(double* A, double* At) const {
+    VarGeo g;
+    g.d = d;
+    g.n = n;
+    g.T = T;
+    g.P = P;
+    g.W = W;
+    g.b = b;
+    g.X = X.as<double>();
+    g.row_block = row_block.as<int32_t>();
+    g.S = S.as<double>();
+    g.C = C.as<double>();
+    g.acoef = acoef.as<double>();
+    g.A = A;
+    g.At = At;
+    return g;
+  }
+  double* coef_row(int t, int64_t row) const { return acoef.as<double>() + (int64_t)t * P + row; }
+};
+
+Err check_vblocks(const flsq_vrows* blocks, int nb, int d, bool need_rhs, int max_ch) {
+  if (nb < 1 || !blocks) return fail(FLSQ_EINVAL, "need at least one row block");
+  if (nb > 64) return fail(FLSQ_EINVAL, "at most 64 row blocks");
+  int64_t P = 0;
+  for (int i = 0; i < nb; ++i) {
+    const flsq_vrows& r = blocks[i];
+    if (r.n_rows < 0) return fail(FLSQ_EINVAL, "block %d: n_rows < 0", i);
+    if (r.n_rows > 0 && !r.x) return fail(FLSQ_EINVAL, "block %d: x is NULL", i);
+    if (need_rhs && r.n_rows > 0 && !r.rhs) return fail(FLSQ_EINVAL, "block %d: rhs is NULL", i);
+    if (!std::isfinite(r.weight)) return fail(FLSQ_ENONFINITE, "block %d: weight not finite", i);
+    if (r.n_channels < 1 || r.n_channels > max_ch || !r.channels)
+      return fail(FLSQ_EINVAL, "block %d: n_channels = %d outside [1, %d]", i, r.n_channels, max_ch);
+    for (int t = 0; t < r.n_channels; ++t) CHECK_ERR(check_op(r.channels[t].op, d, i));
+    P += r.n_rows;
+  }
+  if (P < 1) return fail(FLSQ_EINVAL, "no rows");
+  if (P > (int64_t)0x7fffffff) return fail(FLSQ_EINVAL, "more than 2^31 - 1 rows");
+  return ok();
+}
+
+Err build_var(flsq_ctx* c, VarSys& s, const flsq_basis* basis, const flsq_vrows* blocks, int nb, bool need_rhs,
+              int max_ch = FLSQ_MAX_CHANNELS) {
+  CHECK_ERR(check_basis(basis));
+  CHECK_ERR(check_vblocks(blocks, nb, basis->d, need_rhs, max_ch));
+  hipStream_t st = c->stream;
+  s.d = basis->d;
+  s.n = basis->n_feat;
+  s.W = basis->W;
+  s.b = basis->b;
+  s.n_blocks = nb;
+  s.row0.assign(nb, 0);
+  s.rows.assign(nb, 0);
+  s.weight.assign(nb, 0.0);
+  s.n_ch.assign(nb, 0);
+  s.T = 0;
+  int64_t P = 0;
+  for (int i = 0; i < nb; ++i) {
+    s.row0[i] = P;
+    s.rows[i] = blocks[i].n_rows;
+    s.weight[i] = blocks[i].weight;
+    s.n_ch[i] = blocks[i].n_channels;
+    s.T = std::max(s.T, blocks[i].n_channels);
+    P += blocks[i].n_rows;
+  }
+  s.P = P;
+  const int d = s.d, n = s.n, T = s.T;
+  const double norm = basis->normalize ? 1.0 / std::sqrt((double)n) : 1.0;
+  CHECK_HIP(s.X.ensure(sizeof(double) * P * d));
+  CHECK_HIP(s.row_block.ensure(sizeof(int32_t) * P));
+  CHECK_HIP(s.acoef.ensure(sizeof(double) * T * P));
+  CHECK_HIP(s.rhs_w.ensure(sizeof(double) * P));
+  CHECK_HIP(s.S.ensure(sizeof(double) * nb * T * n));
+  CHECK_HIP(s.C.ensure(sizeof(double) * nb * T * n));
+  std::vector<VarTerm> tv;
+  std::vector<int32_t> off(1, 0);
+  std::vector<double> sc;
+  for (int i = 0; i < nb; ++i) {
+    const flsq_vrows& r = blocks[i];
+    for (int t = 0; t < T; ++t) {
+      if (t < r.n_channels) {
+        const flsq_op& op = r.channels[t].op;
+        for (int k = 0; k < op.n_terms; ++k) {
+          VarTerm vt;
+          memset(&vt, 0, sizeof vt);
+          vt.coef = op.terms[k].coef;
+          for (int q = 0; q < kMaxDim; ++q) vt.alpha[q] = op.terms[k].alpha[q];
+          tv.push_back(vt);
+        }
+      }
+      off.push_back((int32_t)tv.size());
+      sc.push_back(r.weight * norm);
+      if (r.n_rows == 0) continue;
+      double* dst = s.coef_row(t, s.row0[i]);
+      if (t < r.n_channels && r.channels[t].coef)
+        CHECK_HIP(hipMemcpyAsync(dst, r.channels[t].coef, sizeof(double) * r.n_rows, hipMemcpyDeviceToDevice, st));
+      else
+        CHECK_HIP(launch_fill_f64(dst, r.n_rows, t < r.n_channels ? 1.0 : 0.0, st));
+    }
+    if (r.n_rows > 0) {
+      CHECK_HIP(hipMemcpyAsync(s.X.as<double>() + s.row0[i] * d, r.x, sizeof(double) * d * r.n_rows,
+                               hipMemcpyDeviceToDevice, st));
+      CHECK_HIP(launch_fill_i32(s.row_block.as<int32_t>() + s.row0[i], r.n_rows, i, st));
+      CHECK_HIP(launch_scale_copy(r.rhs, s.rhs_w.as<double>() + s.row0[i], r.n_rows, r.weight, st));  // NULL -> 0
+    }
+  }
+  CHECK_HIP(s.terms.ensure(sizeof(VarTerm) * std::max<size_t>(1, tv.size())));
+  CHECK_HIP(s.off.ensure(sizeof(int32_t) * off.size()));
+  CHECK_HIP(s.scale.ensure(sizeof(double) * sc.size()));
+  if (!tv.empty())
+    CHECK_HIP(hipMemcpyAsync(s.terms.p, tv.data(), sizeof(VarTerm) * tv.size(), hipMemcpyHostToDevice, st));
+  CHECK_HIP(hipMemcpyAsync(s.off.p, off.data(), sizeof(int32_t) * off.size(), hipMemcpyHostToDevice, st));
+  CHECK_HIP(hipMemcpyAsync(s.scale.p, sc.data(), sizeof(double) * sc.size(), hipMemcpyHostToDevice, st));
+  CHECK_HIP(launch_fold_var(s.W, n, d, s.terms.as<VarTerm>(), s.off.as<int32_t>(), s.scale.as<double>(), nb * T,
+                            s.S.as<double>(), s.C.as<double>(), st));
+  CHECK_HIP(hipStreamSynchronize(st));   // the host tables go out of scope
+  CHECK_ERR(check_finite_dev(c, s.X.as<double>(), P * d, "collocation points"));
+  CHECK_ERR(check_finite_dev(c, s.acoef.as<double>(), (int64_t)T * P, "channel coefficients"));
+  CHECK_ERR(check_finite_dev(c, s.W, (int64_t)n * d, "W"));
+  CHECK_ERR(check_finite_dev(c, s.b, n, "b"));
+  if (need_rhs) CHECK_ERR(check_finite_dev(c, s.rhs_w.as<double>(), P, "right-hand side"));
+  return ok();
+}
+
+// G = At A (n x n, full) on the FP64 matrix cores, K = P split across workgroups.
+Err stored_gram(flsq_ctx* c, const double* A, const double* At, int n, int64_t P, double* G) {
+  GemmDesc h;
+  memset(&h, 0, sizeof h);
+  h.A = At;
+  h.lda = (int)P;
+  h.B = A;
+  h.ldb = n;
+  h.C = G;
+  h.ldc = n;
+  h.M = n;
+  h.N = n;
+  h.K = (int)P;
+  h.tri = 0;
+  GemmDesc* dd;
+  CHECK_ERR(upload_descs(c, std::vector<GemmDesc>(1, h), &dd));
+  double* work;
+  const size_t we = (size_t)8 * n * n;
+  CHECK_ERR(ws_get(c, "vg_work", we, &work));
+  CHECK_HIP(hipEventRecord(c->ev0, c->stream));
+  CHECK_HIP(launch_gemm_tri(dd, 1, n, n, (int)P, 1.0, work, we, c->stream));
+  CHECK_HIP(hipEventRecord(c->ev1, c->stream));
+  return ok();
+}
+
+// Tikhonov least squares with a stored matrix: Gram, Cholesky with shift retries, initial
+// solve, CGLS refinement (one right-hand side Yw, P rows).
+Err var_linear_solve(flsq_ctx* c, const double* A, const double* At, int n, int64_t P, const SolveParams& sp,
+                     const double* Yw, double* beta, flsq_solve_info* info, bool* converged) {
+  double *G, *U, *Xi, *cvec;
+  CHECK_ERR(ws_get(c, "vG", (size_t)n * n, &G));
+  CHECK_ERR(ws_get(c, "Ufac", (size_t)n * n, &U));
+  CHECK_ERR(ws_get(c, "Xinv", (size_t)n * n, &Xi));
+  CHECK_ERR(ws_get(c, "cvec", (size_t)n, &cvec));
+  const double t0 = now_ms();
+  CHECK_ERR(stored_gram(c, A, At, n, P, G));
+  CHECK_HIP(hipStreamSynchronize(c->stream));
+  const double t1 = now_ms();
+  float kms = 0.f;
+  CHECK_HIP(hipEventElapsedTime(&kms, c->ev0, c->ev1));
+  c->last_gram_kernel_ms = kms;
+  double shift = 0.0;
+  int retries = 0;
+  CHECK_ERR(factor_with_retries(c, G, U, Xi, n, sp.mu, sp.shift_rel, &shift, &retries));
+  const double t2 = now_ms();
+  CHECK_HIP(launch_rowdot(At, n, P, P, Yw, nullptr, 1.0, 0.0, cvec, c->stream));
+  CHECK_ERR(chol_solve(c, Xi, n, cvec, beta, 1));
+  RefineOut ro;
+  CHECK_ERR(cgls_refine_op(c, DenseOp(A, At, n, P), Xi, sp.mu, Yw, 1, beta, sp.max_refine, sp.refine_tol,
+                           info != nullptr, info != nullptr && sp.report_grad, &ro));
+  CHECK_HIP(hipStreamSynchronize(c->stream));
+  if (info) {
+    info->t_gram_ms = t1 - t0;
+    info->t_chol_ms = t2 - t1;
+    info->shift = shift;
+    info->chol_retries = retries;
+    info->t_gram_kernel_ms = c->last_gram_kernel_ms;
+    info->refine_iters = ro.iters;
+    info->grad_norm0 = ro.grad0;
+    info->grad_norm = ro.grad;
+    info->last_step_rel = ro.last_step;
+    info->t_refine_ms = now_ms() - t2;
+  }
+  if (converged) *converged = ro.converged;
+  return ok();
+}
+
+Err assemble_var_dev(flsq_ctx* c, const VarSys& s, const char* nameA, const char* nameAt, double** A, double** At) {
+  CHECK_ERR(ws_get(c, nameA, (size_t)s.P * s.n, A));
+  *At = nullptr;
+  if (nameAt) CHECK_ERR(ws_get(c, nameAt, (size_t)s.P * s.n, At));
+  CHECK_HIP(launch_assemble_var(s.geo(*A, *At), c->stream));
+  return ok();
+}
+
+Err linear_var_impl(flsq_ctx* c, const flsq_basis* basis, const flsq_vrows* blocks, int nb, const flsq_solve_opts* o,
+                    double* beta, flsq_solve_info* info, bool* converged) {
+  if (!beta) return fail(FLSQ_EINVAL, "beta_out is NULL");
+  SolveParams sp = params_of(o);
+  CHECK_ERR(check_params(sp));
+  if (sp.prec != FLSQ_PREC_FP64) return fail(FLSQ_EINVAL, "row-dependent coefficients: only FLSQ_PREC_FP64");
+  if (info) memset(info, 0, sizeof *info);
+  const double t0 = now_ms();
+  VarSys s;
+  CHECK_ERR(build_var(c, s, basis, blocks, nb, true));
+  double *A, *At;
+  CHECK_ERR(assemble_var_dev(c, s, "vA", "vAt", &A, &At));
+  CHECK_ERR(var_linear_solve(c, A, At, s.n, s.P, sp, s.rhs_w.as<double>(), beta, info, converged));
+  if (info) info->t_total_ms = now_ms() - t0;
+  return check_finite_dev(c, beta, s.n, "beta");
+}
+
+Err newton_var_impl(flsq_ctx* c, const flsq_basis* basis, const flsq_vrows* blocks, int nb, int nl_block,
+                    const flsq_nonlin_grad* nl, const flsq_newton_opts* o, double tol_du, double* beta,
+                    flsq_newton_trace* tr, bool* converged) {
+  if (!o) return fail(FLSQ_EINVAL, "opts is NULL");
+  if (!beta) return fail(FLSQ_EINVAL, "beta_inout is NULL");
+  if (o->max_iter < 0 || o->max_iter > 64) return fail(FLSQ_EINVAL, "max_iter outside [0, 64]");
+  if (o->max_halvings < 0 || o->max_halvings > 60) return fail(FLSQ_EINVAL, "max_halvings outside [0, 60]");
+  if (!(o->armijo_c >= 0.0 && o->armijo_c < 1.0)) return fail(FLSQ_EINVAL, "armijo_c outside [0, 1)");
+  if (!(tol_du >= 0.0)) return fail(FLSQ_EINVAL, "tol_du must be >= 0");
+  SolveParams sp = params_of(&o->lin);
+  CHECK_ERR(check_params(sp));
+  if (sp.prec != FLSQ_PREC_FP64) return fail(FLSQ_EINVAL, "row-dependent coefficients: only FLSQ_PREC_FP64");
+  CHECK_ERR(check_basis(basis));
+  const int d = basis->d;
+  if (!nl) return fail(FLSQ_EINVAL, "nonlinearity is NULL");
+  if (nl->n_poly < 0 || nl->n_poly > kMaxNlTerms || (nl->n_poly > 0 && !nl->poly))
+    return fail(FLSQ_EINVAL, "nonlinearity: n_poly in [0, %d]", kMaxNlTerms);
+  if (nl->n_adv < 0 || nl->n_adv > kMaxNlTerms || (nl->n_adv > 0 && (!nl->adv_coef || !nl->adv_pow || !nl->adv_axis)))
+    return fail(FLSQ_EINVAL, "nonlinearity: n_adv in [0, %d] with its arrays", kMaxNlTerms);
+  if (nl->n_poly + nl->n_adv < 1) return fail(FLSQ_EINVAL, "nonlinearity has no terms");
+  NlSpec spec;
+  memset(&spec, 0, sizeof spec);
+  spec.n_poly = nl->n_poly;
+  for (int k = 0; k < nl->n_poly; ++k) {
+    if (!std::isfinite(nl->poly[k])) return fail(FLSQ_ENONFINITE, "nonlinearity coefficient not finite");
+    spec.poly[k] = nl->poly[k];
+  }
+  std::vector<int> axes;
+  spec.n_adv = nl->n_adv;
+  for (int t = 0; t < nl->n_adv; ++t) {
+    if (!std::isfinite(nl->adv_coef[t])) return fail(FLSQ_ENONFINITE, "advection coefficient not finite");
+    if (nl->adv_pow[t] < 0 || nl->adv_pow[t] > 16) return fail(FLSQ_EINVAL, "advection power outside [0, 16]");
+    if (nl->adv_axis[t] < 0 || nl->adv_axis[t] >= d) return fail(FLSQ_EINVAL, "advection axis outside [0, d)");
+    int sl = (int)(std::find(axes.begin(), axes.end(), nl->adv_axis[t]) - axes.begin());
+    if (sl == (int)axes.size()) axes.push_back(nl->adv_axis[t]);
+    spec.c[t] = nl->adv_coef[t];
+    spec.m[t] = nl->adv_pow[t];
+    spec.slot[t] = sl;
+  }
+  const int ns = (int)axes.size();
+  spec.n_slots = ns;
+  if (nl_block < 0 || nl_block >= nb || !blocks)
+    return fail(FLSQ_EINVAL, "nonlin_block %d outside [0, %d)", nl_block, nb);
+  // linear operator A_L (and its transpose for the warm start)
+  VarSys L;
+  CHECK_ERR(build_var(c, L, basis, blocks, nb, true));
+  const int n = L.n;
+  const int64_t P = L.P;
+  const int64_t nl0 = L.row0[nl_block], nln = L.rows[nl_block];
+  const double w_nl = L.weight[nl_block];
+  hipStream_t st = c->stream;
+  double *AL, *ALt;
+  CHECK_ERR(assemble_var_dev(c, L, "nv_AL", "nv_ALt", &AL, &ALt));
+  // evaluation rows E: u at every row (identity, weight 1), then d_axis u on the nonlinear rows
+  flsq_term id_term;
+  memset(&id_term, 0, sizeof id_term);
+  id_term.coef = 1.0;
+  std::vector<flsq_term> dterms(ns, id_term);
+  for (int s2 = 0; s2 < ns; ++s2) dterms[s2].alpha[axes[s2]] = 1;
+  std::vector<flsq_channel> ech(1 + ns);
+  ech[0].op.terms = &id_term;
+  ech[0].op.n_terms = 1;
+  ech[0].coef = nullptr;
+  for (int s2 = 0; s2 < ns; ++s2) {
+    ech[1 + s2].op.terms = &dterms[s2];
+    ech[1 + s2].op.n_terms = 1;
+    ech[1 + s2].coef = nullptr;
+  }
+  std::vector<flsq_vrows> eb;
+  for (int i = 0; i < nb; ++i) {
+    flsq_vrows r = blocks[i];
+    r.weight = 1.0;
+    r.rhs = nullptr;
+    r.n_channels = 1;
+    r.channels = &ech[0];
+    eb.push_back(r);
+  }
+  for (int s2 = 0; s2 < ns; ++s2) {
+    flsq_vrows r = blocks[nl_block];
+    r.weight = 1.0;
+    r.rhs = nullptr;
+    r.n_channels = 1;
+    r.channels = &ech[1 + s2];
+    eb.push_back(r);
+  }
+  VarSys E;
+  CHECK_ERR(build_var(c, E, basis, eb.data(), (int)eb.size(), false));
+  const int64_t PE = E.P;
+  double *EA, *dummy;
+  CHECK_ERR(assemble_var_dev(c, E, "nv_E", nullptr, &EA, &dummy));
+  // Jacobian system: the nonlinear block gains (identity, dN/du) and (d_axis, dN/d(d_axis u))
+  std::vector<flsq_channel> jch(blocks[nl_block].channels, blocks[nl_block].channels + blocks[nl_block].n_channels);
+  const int t_rho = (int)jch.size();
+  jch.push_back(ech[0]);
+  for (int s2 = 0; s2 < ns; ++s2) jch.push_back(ech[1 + s2]);
+  std::vector<flsq_vrows> jb(blocks, blocks + nb);
+  jb[nl_block].channels = jch.data();
+  jb[nl_block].n_channels = (int32_t)jch.size();
+  VarSys Jsys;
+  CHECK_ERR(build_var(c, Jsys, basis, jb.data(), nb, true, FLSQ_MAX_CHANNELS + 1 + kMaxNlTerms));
+  double* rho_dst = Jsys.coef_row(t_rho, nl0);
+  double* kap_dst = Jsys.coef_row(t_rho + 1, nl0);
+  double *R, *Rt, *UE, *UEt, *negR, *delta, *bt, *tmp, *dots, *dwork;
+  CHECK_ERR(ws_get(c, "nv_R", (size_t)P, &R));
+  CHECK_ERR(ws_get(c, "nv_Rt", (size_t)P, &Rt));
+  CHECK_ERR(ws_get(c, "nv_UE", (size_t)PE, &UE));
+  CHECK_ERR(ws_get(c, "nv_UEt", (size_t)PE, &UEt));
+  CHECK_ERR(ws_get(c, "nv_negR", (size_t)P, &negR));
+  CHECK_ERR(ws_get(c, "nv_delta", (size_t)n, &delta));
+  CHECK_ERR(ws_get(c, "nv_bt", (size_t)n, &bt));
+  CHECK_ERR(ws_get(c, "nv_tmp", (size_t)P, &tmp));
+  CHECK_ERR(ws_get(c, "nv_dots", 8, &dots));
+  CHECK_ERR(ws_get(c, "nv_dwork", 1024, &dwork));
+  const double* data_w = L.rhs_w.as<double>();
+  auto dot1 = [&](const double* x, const double* y, int64_t len, double* out) -> Err {
+    CHECK_HIP(launch_dot_cols(x, y, len, 1, dots, dwork, st));
+    CHECK_HIP(hipMemcpyAsync(out, dots, sizeof(double), hipMemcpyDeviceToHost, st));
+    CHECK_HIP(hipStreamSynchronize(st));
+    return ok();
+  };
+  // R = A_L b - data + w N(u, grad u) on the nonlinear rows; the Jacobian coefficients of the
+  // point b go to the Jacobian system's coefficient table
+  auto residual = [&](const double* b, double* Rout, double* Uout, double* nrm) -> Err {
+    CHECK_HIP(launch_rowdot(EA, PE, n, n, b, nullptr, 1.0, 0.0, Uout, st));
+    CHECK_HIP(launch_rowdot(AL, P, n, n, b, data_w, 1.0, -1.0, Rout, st));
+    CHECK_HIP(launch_nl_var(spec, Uout, P, nl0, nln, w_nl, Rout, rho_dst, ns ? kap_dst : nullptr, P, st));
+    double h = 0.0;
+    CHECK_ERR(dot1(Rout, Rout, P, &h));
+    *nrm = std::sqrt(h);
+    if (!std::isfinite(*nrm)) return fail(FLSQ_ENONFINITE, "Newton residual is not finite");
+    return ok();
+  };
+  const double t0 = now_ms();
+  SolveParams spk = sp;
+  flsq_solve_info sinfo;
+  if (o->warm_start) {
+    CHECK_ERR(var_linear_solve(c, AL, ALt, n, P, spk, data_w, beta, &sinfo, nullptr));
+    spk.shift_rel = std::max(spk.shift_rel, sinfo.shift);
+  }
+  if (tr) memset(tr, 0, sizeof *tr);
+  *converged = false;
+  double nR = 0.0;
+  CHECK_ERR(residual(beta, R, UE, &nR));
+  std::vector<double> one(1, 1.0);
+  double *J, *Jt;
+  for (int it = 0; it < o->max_iter; ++it) {
+    CHECK_ERR(assemble_var_dev(c, Jsys, "nv_J", "nv_Jt", &J, &Jt));
+    CHECK_HIP(launch_scale_copy(R, negR, P, -1.0, st));
+    CHECK_ERR(var_linear_solve(c, J, Jt, n, P, spk, negR, delta, &sinfo, nullptr));
+    spk.shift_rel = std::max(spk.shift_rel, sinfo.shift);
+    double alpha = 1.0, nRt = 0.0;
+    int halv = 0;
+    for (;;) {
+      CHECK_HIP(hipMemcpyAsync(bt, beta, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+      one[0] = alpha;
+      CHECK_HIP(launch_axpy_cols(cols(one), delta, bt, n, 1, 1.0, st));
+      CHECK_ERR(residual(bt, Rt, UEt, &nRt));
+      if (nRt <= (1.0 - o->armijo_c * alpha) * nR || halv >= o->max_halvings) break;
+      alpha *= 0.5;
+      ++halv;
+    }
+    double dd = 0.0, du2 = 0.0, un2 = 0.0;
+    CHECK_ERR(dot1(delta, delta, n, &dd));
+    const double step = alpha * std::sqrt(dd);
+    // ||Delta u|| / ||u|| over every collocation row
+    CHECK_HIP(hipMemcpyAsync(tmp, UEt, sizeof(double) * P, hipMemcpyDeviceToDevice, st));
+    one[0] = 1.0;
+    CHECK_HIP(launch_axpy_cols(cols(one), UE, tmp, P, 1, -1.0, st));
+    CHECK_ERR(dot1(tmp, tmp, P, &du2));
+    CHECK_ERR(dot1(UEt, UEt, P, &un2));
+    const double du_rel = std::sqrt(du2) / std::max(std::sqrt(un2), 1e-300);
+    if (tr) {
+      tr->res_norm[it] = nR;
+      tr->alpha[it] = alpha;
+      tr->halvings[it] = halv;
+      tr->step_norm[it] = step;
+      tr->du_rel[it] = du_rel;
+      tr->iters = it + 1;
+    }
+    CHECK_HIP(hipMemcpyAsync(beta, bt, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+    std::swap(R, Rt);
+    std::swap(UE, UEt);
+    nR = nRt;
+    if (du_rel < tol_du || step < o->tol_dbeta) {
+      *converged = true;
+      break;
+    }
+  }
+  CHECK_HIP(hipStreamSynchronize(st));
+  if (tr) {
+    tr->converged = *converged ? 1 : 0;
+    tr->t_total_ms = now_ms() - t0;
+  }
+  return check_finite_dev(c, beta, n, "beta");
+}
+
 }  // namespace
 
 extern "C" {
@@ -1789,6 +2277,50 @@ flsq_status flsq_bandwidth_loss_grad(flsq_ctx* ctx, const flsq_basis* base, cons
   if (hipSetDevice(ctx->device) != hipSuccess) return finish(ctx, fail(FLSQ_EHIP, "hipSetDevice failed"));
   Err e = bandwidth_impl(ctx, base, L, blocks, n_blocks, opts, beta_out, loss_out, grad_out);
   return finish(ctx, e);
+}
+
+flsq_status flsq_assemble_var(flsq_ctx* ctx, const flsq_basis* basis, const flsq_vrows* blocks, int32_t n_blocks,
+                              double* A_out, double* rhs_out) {
+  if (!ctx) return FLSQ_EINVAL;
+  if (hipSetDevice(ctx->device) != hipSuccess) return finish(ctx, fail(FLSQ_EHIP, "hipSetDevice failed"));
+  if (!A_out) return finish(ctx, fail(FLSQ_EINVAL, "A_out is NULL"));
+  VarSys s;
+  Err e = build_var(ctx, s, basis, blocks, n_blocks, rhs_out != nullptr);
+  if (e.st == FLSQ_OK) {
+    hipError_t he = launch_assemble_var(s.geo(A_out, nullptr), ctx->stream);
+    if (he == hipSuccess && rhs_out)
+      he = hipMemcpyAsync(rhs_out, s.rhs_w.p, sizeof(double) * s.P, hipMemcpyDeviceToDevice, ctx->stream);
+    if (he == hipSuccess) he = hipStreamSynchronize(ctx->stream);
+    if (he != hipSuccess) e = fail(FLSQ_EHIP, "assemble_var: %s", hipGetErrorString(he));
+  }
+  return finish(ctx, e);
+}
+
+flsq_status flsq_solve_linear_var(flsq_ctx* ctx, const flsq_basis* basis, const flsq_vrows* blocks,
+                                  int32_t n_blocks, const flsq_solve_opts* opts, double* beta_out,
+                                  flsq_solve_info* info) {
+  if (!ctx) return FLSQ_EINVAL;
+  if (hipSetDevice(ctx->device) != hipSuccess) return finish(ctx, fail(FLSQ_EHIP, "hipSetDevice failed"));
+  bool conv = true;
+  Err e = linear_var_impl(ctx, basis, blocks, n_blocks, opts, beta_out, info, &conv);
+  if (e.st != FLSQ_OK) return finish(ctx, e);
+  if (!conv && opts->refine_tol > 0.0)
+    return finish(ctx, fail(FLSQ_ENOCONV, "refinement did not reach refine_tol in %d iterations", opts->max_refine));
+  return finish(ctx, ok());
+}
+
+flsq_status flsq_solve_newton_var(flsq_ctx* ctx, const flsq_basis* basis, const flsq_vrows* blocks,
+                                  int32_t n_blocks, int32_t nonlin_block, const flsq_nonlin_grad* nonlin,
+                                  const flsq_newton_opts* opts, double tol_du, double* beta_inout,
+                                  flsq_newton_trace* trace) {
+  if (!ctx) return FLSQ_EINVAL;
+  if (hipSetDevice(ctx->device) != hipSuccess) return finish(ctx, fail(FLSQ_EHIP, "hipSetDevice failed"));
+  bool conv = false;
+  Err e = newton_var_impl(ctx, basis, blocks, n_blocks, nonlin_block, nonlin, opts, tol_du, beta_inout, trace, &conv);
+  if (e.st != FLSQ_OK) return finish(ctx, e);
+  if (!conv && (tol_du > 0.0 || opts->tol_dbeta > 0.0))
+    return finish(ctx, fail(FLSQ_ENOCONV, "Newton: neither stopping rule met in %d steps", opts->max_iter));
+  return finish(ctx, ok());
 }
 
 flsq_status flsq_adam_step(flsq_ctx* ctx, double* params, const double* grads, double* m, double* v, int32_t K,

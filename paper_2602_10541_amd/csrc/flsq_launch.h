@@ -30,6 +30,42 @@ hipError_t launch_apply_lower(const double* What, int n, int d, const LowerMat& 
 hipError_t launch_add_phase(double* ph, int64_t count, double delta, hipStream_t s);
 hipError_t launch_scaled_cols(const double* beta, const double* lam, const double* What, int n, int d, double* V,
                               hipStream_t s);
+// Row-dependent-coefficient operators stored explicitly (A_ij = sum_t a_t(x_i)(S sin z + C cos z)).
+struct VarTerm {
+  double coef;
+  int32_t alpha[kMaxDim];
+};
+struct VarGeo {
+  int d, n, T;               // dimension, features, channels per block
+  int64_t P;                 // rows
+  const double* W;           // n x d
+  const double* b;           // n
+  const double* X;           // P x d
+  const int32_t* row_block;  // P
+  const double* S;           // (n_blocks * T) x n
+  const double* C;
+  const double* acoef;       // T x P
+  double* A;                 // P x n (row-major)
+  double* At;                // n x P (nullable)
+};
+hipError_t launch_fold_var(const double* W, int n, int d, const VarTerm* terms, const int32_t* off,
+                           const double* scale, int n_slots, double* S, double* C, hipStream_t s);
+hipError_t launch_assemble_var(const VarGeo& g, hipStream_t s);
+hipError_t launch_rowdot(const double* M, int64_t R, int64_t len, int64_t ld, const double* v, const double* Y,
+                         double alpha, double beta_y, double* out, hipStream_t s);
+hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t s);
+constexpr int kMaxNlTerms = 8;
+struct NlSpec {
+  int n_poly;
+  double poly[kMaxNlTerms];
+  int n_adv;
+  double c[kMaxNlTerms];
+  int m[kMaxNlTerms];
+  int slot[kMaxNlTerms];     // derivative slot of each advection term
+  int n_slots;
+};
+hipError_t launch_nl_var(const NlSpec& nl, const double* U, int64_t P, int64_t row0, int64_t rows, double w,
+                         double* R, double* rho, double* kap, int64_t kap_ld, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_scale_copy(const double* src, double* dst, int64_t n, double scale, hipStream_t s);
 hipError_t launch_assemble(const Geo& g, int fp32, void* A, hipStream_t s);

@@ -29,7 +29,8 @@ EXPORTS = (
     "flsq_create", "flsq_destroy", "flsq_last_error", "flsq_build_info", "flsq_assemble", "flsq_gram",
     "flsq_solve_linear", "flsq_factorize", "flsq_factor_free", "flsq_factor_shape", "flsq_factor_solve",
     "flsq_factor_solve_normal", "flsq_apply_A", "flsq_apply_At", "flsq_evaluate", "flsq_solve_newton",
-    "flsq_inverse_loss_grad", "flsq_bandwidth_loss_grad", "flsq_adam_step",
+    "flsq_inverse_loss_grad", "flsq_bandwidth_loss_grad", "flsq_adam_step", "flsq_assemble_var",
+    "flsq_solve_linear_var", "flsq_solve_newton_var",
 )
 
 
@@ -74,6 +75,21 @@ class flsq_solve_info(C.Structure):
 
 class flsq_nonlin(C.Structure):
     _fields_ = [("n_poly", C.c_int32), ("poly", C.POINTER(C.c_double))]
+
+
+class flsq_channel(C.Structure):
+    _fields_ = [("op", flsq_op), ("coef", C.c_void_p)]
+
+
+class flsq_vrows(C.Structure):
+    _fields_ = [("n_rows", C.c_int64), ("x", C.c_void_p), ("weight", C.c_double), ("rhs", C.c_void_p),
+                ("n_channels", C.c_int32), ("channels", C.POINTER(flsq_channel))]
+
+
+class flsq_nonlin_grad(C.Structure):
+    _fields_ = [("n_poly", C.c_int32), ("poly", C.POINTER(C.c_double)), ("n_adv", C.c_int32),
+                ("adv_coef", C.POINTER(C.c_double)), ("adv_pow", C.POINTER(C.c_int32)),
+                ("adv_axis", C.POINTER(C.c_int32))]
 
 
 class flsq_newton_opts(C.Structure):
@@ -129,6 +145,12 @@ def load(path: str = LIB_PATH):
         "flsq_bandwidth_loss_grad": (st, [vp, C.POINTER(flsq_basis), C.POINTER(dbl), C.POINTER(flsq_rows), i32,
                                           C.POINTER(flsq_solve_opts), vp, C.POINTER(dbl), C.POINTER(dbl)]),
         "flsq_adam_step": (st, [vp, vp, vp, vp, vp, i32, i32, i32, dbl, dbl, dbl, dbl, i32, dbl]),
+        "flsq_assemble_var": (st, [vp, C.POINTER(flsq_basis), C.POINTER(flsq_vrows), i32, vp, vp]),
+        "flsq_solve_linear_var": (st, [vp, C.POINTER(flsq_basis), C.POINTER(flsq_vrows), i32,
+                                       C.POINTER(flsq_solve_opts), vp, C.POINTER(flsq_solve_info)]),
+        "flsq_solve_newton_var": (st, [vp, C.POINTER(flsq_basis), C.POINTER(flsq_vrows), i32, i32,
+                                       C.POINTER(flsq_nonlin_grad), C.POINTER(flsq_newton_opts), dbl, vp,
+                                       C.POINTER(flsq_newton_trace)]),
     }
     missing = [name for name in sig if not hasattr(lib, name)]
     if missing:
@@ -246,6 +268,38 @@ def make_rows(blocks, d) -> Rows:
     return Rows(arr, keep, len(blocks))
 
 
+@dataclass
+class VRows:
+    array: object          # ctypes array of flsq_vrows
+    keep: list
+    n_blocks: int
+
+
+def make_vrows(blocks, d) -> VRows:
+    """blocks: sequence of (x [n x d float64 GPU tensor], channels, weight, rhs tensor or None), each
+    channel a (terms, coef GPU tensor of n float64 or None) pair."""
+    arr = (flsq_vrows * len(blocks))()
+    keep = []
+    for i, (x, channels, weight, rhs) in enumerate(blocks):
+        _check_f64(x, "x")
+        _check_f64(rhs, "rhs")
+        ch = (flsq_channel * len(channels))()
+        for t, (terms, coef) in enumerate(channels):
+            _check_f64(coef, "channel coefficient")
+            tt = make_terms(terms, d)
+            keep += [tt, coef]
+            ch[t].op = flsq_op(C.cast(tt, C.POINTER(flsq_term)), len(terms))
+            ch[t].coef = coef.data_ptr() if (coef is not None and coef.numel()) else None
+        keep += [x, rhs, ch]
+        arr[i].n_rows = int(x.shape[0])
+        arr[i].x = x.data_ptr() if x.numel() else None
+        arr[i].weight = float(weight)
+        arr[i].rhs = rhs.data_ptr() if (rhs is not None and rhs.numel()) else None
+        arr[i].n_channels = len(channels)
+        arr[i].channels = C.cast(ch, C.POINTER(flsq_channel))
+    return VRows(arr, keep, len(blocks))
+
+
 def solve_opts(mu, prec=PREC_FP64, max_refine=10, refine_tol=1e-12, shift_rel=0.0, report_grad=False):
     return flsq_solve_opts(float(mu), int(prec), int(max_refine), float(refine_tol), float(shift_rel),
                            1 if report_grad else 0)
@@ -356,6 +410,38 @@ def flsq_solve_newton(ctx, basis: Basis, rows: Rows, nonlin_block, poly, opts: f
     return st, tr
 
 
+def flsq_assemble_var(ctx, basis: Basis, rows: VRows, A_out, rhs_out=None):
+    return ctx.check(ctx.lib.flsq_assemble_var(ctx.h, C.byref(basis.struct), rows.array, rows.n_blocks, _ptr(A_out),
+                                               _ptr(rhs_out)))
+
+
+def flsq_solve_linear_var(ctx, basis: Basis, rows: VRows, opts: flsq_solve_opts, beta_out, check=True):
+    info = flsq_solve_info()
+    st = ctx.lib.flsq_solve_linear_var(ctx.h, C.byref(basis.struct), rows.array, rows.n_blocks, C.byref(opts),
+                                       _ptr(beta_out), C.byref(info))
+    if check and st not in (FLSQ_OK, FLSQ_ENOCONV):
+        ctx.check(st)
+    return st, info
+
+
+def flsq_solve_newton_var(ctx, basis: Basis, rows: VRows, nonlin_block, poly, adv, opts: flsq_newton_opts, tol_du,
+                          beta_inout, check=True):
+    """adv: sequence of (coef, power, axis) for the terms coef u^power d_axis u."""
+    poly = list(poly or ())
+    p = (C.c_double * max(1, len(poly)))(*[float(v) for v in poly])
+    ac = (C.c_double * max(1, len(adv)))(*[float(c) for c, _, _ in adv])
+    ap = (C.c_int32 * max(1, len(adv)))(*[int(m) for _, m, _ in adv])
+    ax = (C.c_int32 * max(1, len(adv)))(*[int(a) for _, _, a in adv])
+    nl = flsq_nonlin_grad(len(poly), C.cast(p, C.POINTER(C.c_double)), len(adv), C.cast(ac, C.POINTER(C.c_double)),
+                          C.cast(ap, C.POINTER(C.c_int32)), C.cast(ax, C.POINTER(C.c_int32)))
+    tr = flsq_newton_trace()
+    st = ctx.lib.flsq_solve_newton_var(ctx.h, C.byref(basis.struct), rows.array, rows.n_blocks, int(nonlin_block),
+                                       C.byref(nl), C.byref(opts), float(tol_du), _ptr(beta_inout), C.byref(tr))
+    if check and st not in (FLSQ_OK, FLSQ_ENOCONV):
+        ctx.check(st)
+    return st, tr
+
+
 def flsq_inverse_loss_grad(ctx, F: Factor, n_src_rows, src_weight, n_lap_dims, thetas, x_obs, data, loss_out,
                            grad_theta_out, grad_kappa_out=None):
     return ctx.check(ctx.lib.flsq_inverse_loss_grad(
@@ -406,3 +492,22 @@ class DeviceProblem:
     def rows_with_terms(self, terms_per_block):
         return make_rows([(x, t, bl.weight, r) for x, t, bl, r in
                           zip(self.xs, terms_per_block, self.prob.blocks, self.rhs)], self.prob.d)
+
+
+class DeviceVarProblem:
+    """A workloads.Problem whose blocks carry row-dependent channels, moved to the GPU."""
+
+    def __init__(self, prob, device="cuda"):
+        import torch
+        self.prob = prob
+        f64 = dict(dtype=torch.float64, device=device)
+        self.W = torch.tensor(prob.W, **f64).contiguous()
+        self.b = torch.tensor(prob.b, **f64).contiguous()
+        self.basis = make_basis(self.W, self.b, prob.normalize)
+        self.xs = [torch.tensor(bl.x, **f64).contiguous() for bl in prob.blocks]
+        self.rhs = [torch.tensor(bl.rhs, **f64).contiguous() for bl in prob.blocks]
+        self.coefs = [[None if a is None else torch.tensor(a, **f64).contiguous() for _, a in bl.channels]
+                      for bl in prob.blocks]
+        self.rows = make_vrows([(x, [(t, a) for (t, _), a in zip(bl.channels, cs)], bl.weight, r)
+                                for x, bl, cs, r in zip(self.xs, prob.blocks, self.coefs, self.rhs)], prob.d)
+        self.n_rows = sum(int(x.shape[0]) for x in self.xs)

@@ -115,8 +115,43 @@ def bandwidth(name):
           "eval", eval_s, "s", flush=True)
 
 
+def varcoef(name):
+    """The row-dependent-coefficient solve: beta and u at the test points."""
+    prob = wl.config(name)
+    t0 = time.time()
+    beta = oracle.solve_linear_var(prob)
+    solve_s = time.time() - t0
+    u = oracle.evaluate(prob.W, prob.b, beta, prob.x_test, [tuple([0] * prob.d)])[:, 0]
+    err = oracle.rel_l2(u, prob.u_test)
+    np.savez(os.path.join(OUT, f"{name}.npz"), beta=beta, u_test=u, err_exact=np.array(err), solve_s=np.array(solve_s),
+             threads=np.array(oracle.num_threads()))
+    print(name, "rel err vs exact", err, "solve", solve_s, "s", flush=True)
+
+
+BURGERS_NEWTON = dict(max_iter=20, tol_du=1e-8, armijo_c=1e-4, max_halvings=10)
+
+
+def burgers(name):
+    """Continuation nu = 1, 0.5, 0.2, 0.1 (Section 2.4), each stage's Newton from the previous
+    solution: final beta, u at the test points, and every stage's residual norms."""
+    t0 = time.time()
+    beta, traces = oracle.continuation(lambda nu: wl.burgers_1d(nu=nu), wl.BURGERS_STAGES, **BURGERS_NEWTON)
+    total_s = time.time() - t0
+    prob = wl.burgers_1d(nu=wl.BURGERS_STAGES[-1])
+    u = oracle.evaluate(prob.W, prob.b, beta, prob.x_test, [(0,)])[:, 0]
+    err = oracle.rel_l2(u, prob.u_test)
+    iters = np.array([len(t) for t in traces])
+    res = np.zeros((len(traces), BURGERS_NEWTON["max_iter"]))
+    for k, t in enumerate(traces):
+        res[k, :len(t)] = [e["res_norm"] for e in t]
+    np.savez(os.path.join(OUT, f"{name}.npz"), beta=beta, u_test=u, err_exact=np.array(err), iters=iters,
+             res_norm=res, total_s=np.array(total_s), threads=np.array(oracle.num_threads()))
+    print(name, "rel err vs exact", err, "iterations per stage", iters, "total", total_s, "s", flush=True)
+
+
 KIND = {"poisson2d": linear, "poisson6d": linear, "heat4d": linear, "reaction2d": newton, "inverse3d": inverse,
-        "helmholtz_sweep": sweep, "helmholtz_bandwidth": bandwidth}
+        "helmholtz_sweep": sweep, "helmholtz_bandwidth": bandwidth,
+        "varcoef2d": varcoef, "burgers1d": burgers}
 
 if __name__ == "__main__":
     names = sys.argv[1:] or ["poisson2d", "poisson6d"]

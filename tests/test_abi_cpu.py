@@ -46,7 +46,7 @@ def test_binding_structs_match_header_layout(tmp_path):
     if cc is None:
         pytest.skip("no C compiler")
     structs = ["flsq_term", "flsq_op", "flsq_basis", "flsq_rows", "flsq_solve_opts", "flsq_solve_info",
-               "flsq_newton_opts", "flsq_nonlin"]
+               "flsq_newton_opts", "flsq_nonlin", "flsq_channel", "flsq_vrows", "flsq_nonlin_grad"]
     structs = [n for n in structs if hasattr(fl, n)]
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "fastlsq.h"', "int main(void) {"]
     for n in structs:
