@@ -283,9 +283,9 @@ flsq_status flsq_solve_linear_var(flsq_ctx* ctx, const flsq_basis* basis, const 
                                   int32_t n_blocks, const flsq_solve_opts* opts, double* beta_out,
                                   flsq_solve_info* info);
 
-/* N(u, grad u) = sum_k poly[k] u^k + sum_t adv_coef[t] u^{adv_pow[t]} d_{adv_axis[t]} u
- * (host arrays; n_poly <= 8, n_adv <= 8, adv_pow >= 0, 0 <= adv_axis < d).  Steady Burgers:
- * n_poly = 0, one advection term (1, 1, 0). */
+/* N(u, grad u) = sum_k poly[k] u^k + exp_coef e^u + sum_t adv_coef[t] u^{adv_pow[t]} d_{adv_axis[t]} u
+ * (host arrays; n_poly <= 8, n_adv <= 8, adv_pow in [0, 16], 0 <= adv_axis < d).  Steady Burgers:
+ * n_poly = 0, one advection term (1, 1, 0); Bratu -Laplace u - lambda e^u: exp_coef = -lambda. */
 typedef struct {
     int32_t n_poly;
     const double* poly;
@@ -293,6 +293,7 @@ typedef struct {
     const double* adv_coef;
     const int32_t* adv_pow;
     const int32_t* adv_axis;
+    double exp_coef;
 } flsq_nonlin_grad;
 
 /* Newton-Raphson (Section 2.4) for sum_t a_t L_t[u] + N(u, grad u) = f, N acting on block

@@ -473,12 +473,15 @@ def solve_linear_var(prob):
     return tikhonov(A, r, prob.mu)
 
 
-def nonlin_grad_value(poly, adv, u, du):
-    """N(u, grad u) = sum_k poly_k u^k + sum_t c_t u^{m_t} d_{axis_t} u, and its partial
-    derivatives: dN/du (an array) and dN/d(d_k u) per axis k (a dict)."""
+def nonlin_grad_value(poly, adv, u, du, exp_coef=0.0):
+    """N(u, grad u) = sum_k poly_k u^k + exp_coef e^u + sum_t c_t u^{m_t} d_{axis_t} u, and its
+    partial derivatives: dN/du (an array) and dN/d(d_k u) per axis k (a dict)."""
     poly = tuple(poly or ())
     val = _poly(poly, u) if poly else np.zeros_like(u)
     dval_u = _dpoly(poly, u) if len(poly) > 1 else np.zeros_like(u)
+    if exp_coef:
+        val = val + exp_coef * np.exp(u)
+        dval_u = dval_u + exp_coef * np.exp(u)
     dval_g = {}
     for c, m, ax in adv:
         g = du[ax]
@@ -508,7 +511,8 @@ def newton_var_residual(prob, beta):
         ev = evaluate(prob.W, prob.b, beta, bl.x, [zero] + unit, prob.normalize)
         u = ev[:, 0]
         if bi == prob.nonlin_block:
-            val, _, _ = nonlin_grad_value(prob.nonlin_poly, prob.nonlin_adv, u, {k: ev[:, 1 + k] for k in range(d)})
+            val, _, _ = nonlin_grad_value(prob.nonlin_poly, prob.nonlin_adv, u, {k: ev[:, 1 + k] for k in range(d)},
+                                       prob.nonlin_exp)
             Lu = Lu + val
         parts.append(bl.weight * (Lu - _f64(bl.rhs)))
         us.append(u)
@@ -528,7 +532,7 @@ def newton_var_jacobian(prob, beta):
         if bi == prob.nonlin_block:
             ev = evaluate(prob.W, prob.b, beta, bl.x, [zero] + unit, prob.normalize)
             _, du_, dg = nonlin_grad_value(prob.nonlin_poly, prob.nonlin_adv, ev[:, 0],
-                                           {k: ev[:, 1 + k] for k in range(d)})
+                                           {k: ev[:, 1 + k] for k in range(d)}, prob.nonlin_exp)
             J = J + du_[:, None] * assemble(prob.W, prob.b, bl.x, [(1.0, zero)], bl.weight, prob.normalize)
             for ax, coef in dg.items():
                 J = J + _f64(coef)[:, None] * assemble(prob.W, prob.b, bl.x, [(1.0, unit[ax])], bl.weight,

@@ -2064,9 +2064,11 @@ Err newton_var_impl(flsq_ctx* c, const flsq_basis* basis, const flsq_vrows* bloc
     return fail(FLSQ_EINVAL, "nonlinearity: n_poly in [0, %d]", kMaxNlTerms);
   if (nl->n_adv < 0 || nl->n_adv > kMaxNlTerms || (nl->n_adv > 0 && (!nl->adv_coef || !nl->adv_pow || !nl->adv_axis)))
     return fail(FLSQ_EINVAL, "nonlinearity: n_adv in [0, %d] with its arrays", kMaxNlTerms);
-  if (nl->n_poly + nl->n_adv < 1) return fail(FLSQ_EINVAL, "nonlinearity has no terms");
+  if (!std::isfinite(nl->exp_coef)) return fail(FLSQ_ENONFINITE, "exponential coefficient not finite");
+  if (nl->n_poly + nl->n_adv < 1 && nl->exp_coef == 0.0) return fail(FLSQ_EINVAL, "nonlinearity has no terms");
   NlSpec spec;
   memset(&spec, 0, sizeof spec);
+  spec.exp_coef = nl->exp_coef;
   spec.n_poly = nl->n_poly;
   for (int k = 0; k < nl->n_poly; ++k) {
     if (!std::isfinite(nl->poly[k])) return fail(FLSQ_ENONFINITE, "nonlinearity coefficient not finite");

@@ -63,6 +63,7 @@ struct NlSpec {
   int m[kMaxNlTerms];
   int slot[kMaxNlTerms];     // derivative slot of each advection term
   int n_slots;
+  double exp_coef;           // + exp_coef e^u
 };
 hipError_t launch_nl_var(const NlSpec& nl, const double* U, int64_t P, int64_t row0, int64_t rows, double w,
                          double* R, double* rho, double* kap, int64_t kap_ld, hipStream_t s);

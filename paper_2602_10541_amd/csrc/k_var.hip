@@ -146,7 +146,7 @@ hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t s) {
   return hipGetLastError();
 }
 
-// Nonlinearity N(u, grad u) = sum_k poly_k u^k + sum_t c_t u^{m_t} d_{axis_t} u on the rows
+// Nonlinearity N(u, grad u) = sum_k poly_k u^k + e exp(u) + sum_t c_t u^{m_t} d_{axis_t} u on the rows
 // [row0, row0 + rows) of the nonlinear block (weight w).  U holds u at every row of the system
 // (first P entries) and then d_{slot axis} u on the block's rows, slot by slot.
 //   R[row0 + i] += w N                (R nullable)
@@ -163,6 +163,11 @@ __global__ void k_nl_var(NlSpec nl, const double* __restrict__ U, int64_t P, int
     val = fma(nl.poly[k], upow, val);
     if (k + 1 < nl.n_poly) dval = fma((double)(k + 1) * nl.poly[k + 1], upow, dval);
     upow *= u;
+  }
+  if (nl.exp_coef != 0.0) {
+    const double eu = nl.exp_coef * exp(u);
+    val += eu;
+    dval += eu;
   }
   double dg[kMaxNlTerms];
   for (int s = 0; s < nl.n_slots; ++s) dg[s] = 0.0;

@@ -89,7 +89,7 @@ class flsq_vrows(C.Structure):
 class flsq_nonlin_grad(C.Structure):
     _fields_ = [("n_poly", C.c_int32), ("poly", C.POINTER(C.c_double)), ("n_adv", C.c_int32),
                 ("adv_coef", C.POINTER(C.c_double)), ("adv_pow", C.POINTER(C.c_int32)),
-                ("adv_axis", C.POINTER(C.c_int32))]
+                ("adv_axis", C.POINTER(C.c_int32)), ("exp_coef", C.c_double)]
 
 
 class flsq_newton_opts(C.Structure):
@@ -425,15 +425,15 @@ def flsq_solve_linear_var(ctx, basis: Basis, rows: VRows, opts: flsq_solve_opts,
 
 
 def flsq_solve_newton_var(ctx, basis: Basis, rows: VRows, nonlin_block, poly, adv, opts: flsq_newton_opts, tol_du,
-                          beta_inout, check=True):
-    """adv: sequence of (coef, power, axis) for the terms coef u^power d_axis u."""
+                          beta_inout, check=True, exp_coef=0.0):
+    """adv: sequence of (coef, power, axis) for the terms coef u^power d_axis u; exp_coef: + exp_coef e^u."""
     poly = list(poly or ())
     p = (C.c_double * max(1, len(poly)))(*[float(v) for v in poly])
     ac = (C.c_double * max(1, len(adv)))(*[float(c) for c, _, _ in adv])
     ap = (C.c_int32 * max(1, len(adv)))(*[int(m) for _, m, _ in adv])
     ax = (C.c_int32 * max(1, len(adv)))(*[int(a) for _, _, a in adv])
     nl = flsq_nonlin_grad(len(poly), C.cast(p, C.POINTER(C.c_double)), len(adv), C.cast(ac, C.POINTER(C.c_double)),
-                          C.cast(ap, C.POINTER(C.c_int32)), C.cast(ax, C.POINTER(C.c_int32)))
+                          C.cast(ap, C.POINTER(C.c_int32)), C.cast(ax, C.POINTER(C.c_int32)), float(exp_coef))
     tr = flsq_newton_trace()
     st = ctx.lib.flsq_solve_newton_var(ctx.h, C.byref(basis.struct), rows.array, rows.n_blocks, int(nonlin_block),
                                        C.byref(nl), C.byref(opts), float(tol_du), _ptr(beta_inout), C.byref(tr))

@@ -87,6 +87,8 @@ class Problem:
     nonlin_block: int = -1
     # First-derivative terms of the nonlinearity: sum_t c_t u^{m_t} d_{axis_t} u, as (c, m, axis).
     nonlin_adv: tuple = ()
+    # Exponential term of the nonlinearity: + nonlin_exp * e^u (Bratu).
+    nonlin_exp: float = 0.0
     extras: dict = field(default_factory=dict)
 
     @property
@@ -368,6 +370,27 @@ def burgers_1d(nu: float = 0.1, n_feat: int = 1000, sigma: float = 10.0, n_int: 
                    nonlin_adv=((1.0, 1, 0),), extras={"sigma": sigma, "nu": nu, "exact": "-tanh((x - 1/2) / (2 nu))"})
 
 
+def bratu_2d(lam: float = 1.0, n_feat: int = 1500, sigma: float = 2.0, n_int: int = 6000, n_bc: int = 1200,
+             seed: int = 0, n_test: int = 5000) -> Problem:
+    """Bratu -Laplace u - lambda e^u = f on [0,1]^2 (lambda = 1, sigma = 2 as in the paper's
+    Newton table) with the exact solution u = sin(pi x) sin(pi y), f = 2 pi^2 u - lambda e^u, and
+    zero Dirichlet data; the nonlinearity -lambda e^u acts on the interior rows."""
+    d = 2
+    r = _rngs(seed)
+    W, b = draw_features(r, n_feat, [sigma] * d)
+    xi = sample_box(r["interior"], n_int, d)
+    xb = sample_faces(r["boundary"], n_bc, d, range(d))
+    u = lambda x: np.sin(PI * x[:, 0]) * np.sin(PI * x[:, 1])
+    f = 2 * PI * PI * u(xi) - lam * np.exp(u(xi))
+    blocks = [
+        VarBlock("interior", xi, [(laplacian_terms(d, range(d), -1.0), None)], 1.0, f),
+        VarBlock("boundary", xb, [(identity_terms(d), None)], LAM_BC, u(xb)),
+    ]
+    xt = sample_box(np.random.default_rng(seed + 1), n_test, d)
+    return Problem("bratu_2d", d, n_feat, W, b, blocks, x_test=xt, u_test=u(xt), nonlin_block=0, nonlin_exp=-lam,
+                   extras={"sigma": sigma, "lambda": lam, "exact": "sin(pi x) sin(pi y)"})
+
+
 def varcoef_2d(n_feat: int = 1500, sigma: float = 3.0, n_int: int = 6000, n_bc: int = 1200, seed: int = 0,
                n_test: int = 5000) -> Problem:
     """A coil-type operator with a variable coefficient: nu Laplace u + grad nu . grad u = g on
@@ -413,6 +436,8 @@ def config(name: str, seed: int = 0, **kw) -> Problem:
         return helmholtz_sweep(seed=seed, **kw)
     if name == "burgers1d":             # steady Burgers, nu = 0.1 (the last continuation stage), N = 1000
         return burgers_1d(seed=seed, **kw)
+    if name == "bratu2d":               # Bratu, lambda = 1, N = 1500, 7200 rows
+        return bratu_2d(seed=seed, **kw)
     if name == "varcoef2d":             # coil-type variable-coefficient operator, N = 1500, 7200 rows
         return varcoef_2d(seed=seed, **kw)
     if name == "helmholtz_bandwidth":   # learnable bandwidth: N = 500 base draws, sigma0 = 5, k = 10

@@ -149,9 +149,23 @@ def burgers(name):
     print(name, "rel err vs exact", err, "iterations per stage", iters, "total", total_s, "s", flush=True)
 
 
+def bratu(name):
+    """Bratu (lambda = 1) by Newton from the linear warm start, stopped at ||Delta u|| / ||u|| < 1e-8."""
+    prob = wl.config(name)
+    t0 = time.time()
+    beta, trace = oracle.solve_newton_var(prob, max_iter=20, tol_du=1e-8)
+    total_s = time.time() - t0
+    u = oracle.evaluate(prob.W, prob.b, beta, prob.x_test, [(0, 0)])[:, 0]
+    err = oracle.rel_l2(u, prob.u_test)
+    np.savez(os.path.join(OUT, f"{name}.npz"), beta=beta, u_test=u, err_exact=np.array(err),
+             res_norm=np.array([t["res_norm"] for t in trace]), du_rel=np.array([t["du_rel"] for t in trace]),
+             total_s=np.array(total_s), threads=np.array(oracle.num_threads()))
+    print(name, "rel err vs exact", err, "steps", len(trace), "total", total_s, "s", flush=True)
+
+
 KIND = {"poisson2d": linear, "poisson6d": linear, "heat4d": linear, "reaction2d": newton, "inverse3d": inverse,
         "helmholtz_sweep": sweep, "helmholtz_bandwidth": bandwidth,
-        "varcoef2d": varcoef, "burgers1d": burgers}
+        "varcoef2d": varcoef, "burgers1d": burgers, "bratu2d": bratu}
 
 if __name__ == "__main__":
     names = sys.argv[1:] or ["poisson2d", "poisson6d"]

@@ -125,3 +125,23 @@ def test_burgers_continuation_matches_oracle():
         for it in range(min(2, len(tr))):
             ref = gold["res_norm"][k, it]
             assert abs(tr[it]["res_norm"] - ref) <= 1e-5 * gold["res_norm"][k, 0], (k, it, tr[it], ref)
+
+
+def test_bratu_newton_matches_oracle():
+    """Bratu -Laplace u - e^u = f (N = 1500, 7200 rows) by Newton from the linear warm start,
+    stopped at ||Delta u|| / ||u|| < 1e-8: the same number of steps as the oracle (within one),
+    u within 1e-6 of the oracle's, and the error to the exact solution within 10 % of the oracle's."""
+    torch, fl = require_gpu()
+    from paper_2602_10541_amd.continuation import newton_opts
+    gold = _gold("bratu2d")
+    prob = wl.config("bratu2d")
+    dp = fl.DeviceVarProblem(prob)
+    beta = torch.empty(prob.n_feat, dtype=torch.float64, device="cuda")
+    st, tr = fl.flsq_solve_newton_var(context(), dp.basis, dp.rows, 0, None, (), newton_opts(prob.mu), 1e-8, beta,
+                                      exp_coef=prob.nonlin_exp)
+    got = tr.as_list()
+    assert abs(len(got) - len(gold["res_norm"])) <= 1, [g["res_norm"] for g in got]
+    assert abs(got[0]["res_norm"] - gold["res_norm"][0]) <= 1e-8 * gold["res_norm"][0]
+    u = oracle.evaluate(prob.W, prob.b, beta.cpu().numpy(), prob.x_test, [(0, 0)])[:, 0]
+    assert rel_l2(u, gold["u_test"]) <= 1e-6, rel_l2(u, gold["u_test"])
+    assert abs(rel_l2(u, prob.u_test) - float(gold["err_exact"])) <= 0.1 * float(gold["err_exact"])

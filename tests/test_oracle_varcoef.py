@@ -9,6 +9,7 @@
 - The Newton Jacobian with the u u' term against central differences of the residual, and the
   Newton solution against scipy's Levenberg-Marquardt on the same regularised residual.
 - Continuation reaches the exact Burgers solution within a band on a small instance.
+- The Bratu exponential term: its Jacobian against central differences and its data (sympy).
 """
 import math
 
@@ -127,3 +128,19 @@ def test_burgers_continuation_band():
     prob = wl.burgers_1d(nu=0.1, n_feat=200, n_int=800, n_test=500)
     u = oracle.evaluate(prob.W, prob.b, beta, prob.x_test, [(0,)])[:, 0]
     assert oracle.rel_l2(u, prob.u_test) < 3e-4   # 8e-5 at N = 200
+
+
+def test_bratu_jacobian_and_data():
+    prob = wl.bratu_2d(n_feat=50, n_int=120, n_bc=40, n_test=10)
+    x, y = sp.symbols("x y", real=True)
+    U = sp.sin(sp.pi * x) * sp.sin(sp.pi * y)
+    f = sp.lambdify((x, y), -sp.diff(U, x, 2) - sp.diff(U, y, 2) - sp.exp(U), "numpy")
+    bl = prob.blocks[0]
+    assert np.abs(f(bl.x[:, 0], bl.x[:, 1]) - bl.rhs).max() <= 1e-12 * np.abs(bl.rhs).max()
+    rng = np.random.default_rng(4)
+    beta = oracle.solve_linear_var(prob) + 0.05 * rng.normal(size=prob.n_feat)
+    J = oracle.newton_var_jacobian(prob, beta)
+    v = rng.normal(size=prob.n_feat)
+    h = 1e-6
+    fd = (oracle.newton_var_residual(prob, beta + h * v)[0] - oracle.newton_var_residual(prob, beta - h * v)[0]) / (2 * h)
+    assert np.abs(J @ v - fd).max() <= 1e-6 * np.abs(fd).max()
