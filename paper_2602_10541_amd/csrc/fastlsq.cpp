@@ -883,19 +883,41 @@ Err cgls_refine_op(flsq_ctx* c, const LsqOp& op, const double* Xi, double mu, co
   for (int it = 0; it < max_iter; ++it) {
     // q = A p ; delta = ||q||^2 + mu ||p||^2 ; hq = H p ; alpha = gam / delta
     CHECK_ERR(op.apply(c, p, K, nullptr, 1.0, 0.0, q, hq));
-    CHECK_HIP(launch_dot_cols(q, q, P, K, d_qq, dwork, st));
-    CHECK_HIP(launch_dot_cols(p, p, n, K, d_pp, dwork, st));
-    if (track_u) {
-      CHECK_HIP(launch_dot_cols(hq, hq, P, K, d_hh, dwork, st));
-      CHECK_HIP(launch_dot_cols(uu, uu, P, K, d_uu, dwork, st));
+    {
+      DotBatch db{};
+      db.K = K;
+      auto add = [&](const double* a, int64_t len, double* o) {
+        db.x[db.count] = a;
+        db.y[db.count] = a;
+        db.n[db.count] = len;
+        db.out[db.count] = o;
+        ++db.count;
+      };
+      add(q, P, d_qq);
+      add(p, n, d_pp);
+      if (track_u) {
+        add(hq, P, d_hh);
+        add(uu, P, d_uu);
+      }
+      CHECK_HIP(launch_dot_batch(db, dwork, st));
     }
     CHECK_HIP(launch_cg_alpha(d_gam, d_qq, d_pp, mu, col_mask(active), K, d_alpha, st));
     CHECK_HIP(launch_axpy_cols_dev(d_alpha, p, X, n, K, 1.0, st));
     CHECK_HIP(launch_axpy_cols_dev(d_alpha, q, sres, P, K, -1.0, st));
     if (track_u) CHECK_HIP(launch_axpy_cols_dev(d_alpha, hq, uu, P, K, 1.0, st));
     // objective after the step
-    CHECK_HIP(launch_dot_cols(sres, sres, P, K, d_ss, dwork, st));
-    CHECK_HIP(launch_dot_cols(X, X, n, K, d_xx, dwork, st));
+    {
+      DotBatch db{};
+      db.K = K;
+      db.count = 2;
+      db.x[0] = db.y[0] = sres;
+      db.n[0] = P;
+      db.out[0] = d_ss;
+      db.x[1] = db.y[1] = X;
+      db.n[1] = n;
+      db.out[1] = d_xx;
+      CHECK_HIP(launch_dot_batch(db, dwork, st));
+    }
     CHECK_HIP(hipMemcpyAsync(hs.data(), d_alpha, sizeof(double) * 8 * K, hipMemcpyDeviceToHost, st));
     CHECK_HIP(hipStreamSynchronize(st));
     const double* h_alpha = hs.data();
@@ -1321,13 +1343,37 @@ flsq_status flsq_factor_solve_normal(flsq_ctx* ctx, const flsq_factor* F, const 
     std::vector<double> hs(6 * K);
     for (int it = 0; it < F->max_refine; ++it) {
       CHECK_ERR(apply_normal(p, ap));
-      CHECK_HIP(launch_dot_cols(p, ap, n, K, d_pap, dwork, st));
-      CHECK_HIP(launch_dot_cols(out, V, n, K, d_xv0, dwork, st));
+      {
+        DotBatch db{};
+        db.K = K;
+        db.count = 2;
+        db.x[0] = p;
+        db.y[0] = ap;
+        db.n[0] = n;
+        db.out[0] = d_pap;
+        db.x[1] = out;
+        db.y[1] = V;
+        db.n[1] = n;
+        db.out[1] = d_xv0;
+        CHECK_HIP(launch_dot_batch(db, dwork, st));
+      }
       CHECK_HIP(launch_cg_alpha(d_gam, d_pap, nullptr, 0.0, col_mask(active), K, d_alpha, st));
       CHECK_HIP(launch_axpy_cols_dev(d_alpha, p, out, n, K, 1.0, st));
       CHECK_HIP(launch_axpy_cols_dev(d_alpha, ap, r, n, K, -1.0, st));
-      CHECK_HIP(launch_dot_cols(out, V, n, K, d_xv, dwork, st));
-      CHECK_HIP(launch_dot_cols(out, r, n, K, d_xr, dwork, st));
+      {
+        DotBatch db{};
+        db.K = K;
+        db.count = 2;
+        db.x[0] = out;
+        db.y[0] = V;
+        db.n[0] = n;
+        db.out[0] = d_xv;
+        db.x[1] = out;
+        db.y[1] = r;
+        db.n[1] = n;
+        db.out[1] = d_xr;
+        CHECK_HIP(launch_dot_batch(db, dwork, st));
+      }
       CHECK_HIP(hipMemcpyAsync(hs.data(), d_alpha, sizeof(double) * 6 * K, hipMemcpyDeviceToHost, st));
       CHECK_HIP(hipStreamSynchronize(st));
       const double *h_alpha = hs.data(), *h_pap = hs.data() + 2 * K, *h_xv0 = hs.data() + 3 * K;

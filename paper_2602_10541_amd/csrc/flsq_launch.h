@@ -227,6 +227,18 @@ hipError_t launch_diag_max(const double* G, int n, double* out, hipStream_t s);
 
 // ---- small vector kernels
 // out[c] = sum_i x[i][c] * y[i][c] over n rows, K columns (deterministic two-stage).
+// Up to kDotBatchMax column-dot products with a common column count K: out[p][c] = sum_i x_p[i][c] y_p[i][c].
+// Small products run in one launch (a workgroup each); larger ones as launch_dot_cols in turn.
+constexpr int kDotBatchMax = 4;
+struct DotBatch {
+  const double* x[kDotBatchMax];
+  const double* y[kDotBatchMax];
+  int64_t n[kDotBatchMax];
+  double* out[kDotBatchMax];
+  int count;
+  int K;
+};
+hipError_t launch_dot_batch(const DotBatch& b, double* work, hipStream_t s);
 hipError_t launch_dot_cols(const double* x, const double* y, int64_t n, int K, double* out, double* work,
                            hipStream_t s);
 // out[c] = sum_i u_i s_i Y[i][c] (Y n x K row-major), s_i = X[i * ldx + xcol] or 1 when X is NULL

@@ -152,8 +152,68 @@ __global__ void k_dot_stage2(const double* work, int nblk, int K, double* out) {
   if (threadIdx.x == 0) out[c] = red[0];
 }
 
+// Small products (n K <= kDotSmallMax): one 1024-thread workgroup per product writes the column
+// sums directly.  Thread t owns column c = t % kc of a chunk of kc columns and walks rows
+// t / kc, t / kc + R, ... with R the largest power of two with R kc <= 1024; the R partials of a
+// column are then added pairwise in a fixed tree.  Several products go in one launch.
+constexpr int kDotSmallWg = 1024;
+constexpr int64_t kDotSmallMax = 32768;
+
+__global__ __launch_bounds__(kDotSmallWg) void k_dot_small(DotBatch b) {
+  __shared__ double red[kDotSmallWg];
+  const int pi = blockIdx.x;
+  const double* __restrict__ x = b.x[pi];
+  const double* __restrict__ y = b.y[pi];
+  const int64_t n = b.n[pi];
+  const int K = b.K;
+  const int t = threadIdx.x;
+  for (int cb = 0; cb < K; cb += kDotSmallWg) {
+    const int kc = min(kDotSmallWg, K - cb);
+    int R = 1;
+    while (R * 2 * kc <= kDotSmallWg) R *= 2;
+    const int c = t % kc, r = t / kc;
+    double s = 0.0;
+    if (r < R)
+      for (int64_t i = r; i < n; i += R) s = fma(x[i * K + cb + c], y[i * K + cb + c], s);
+    red[t] = s;
+    __syncthreads();
+    for (int h = R / 2; h > 0; h >>= 1) {
+      if (r < h) red[r * kc + c] += red[(r + h) * kc + c];
+      __syncthreads();
+    }
+    if (t < kc) b.out[pi][cb + t] = red[t];
+    __syncthreads();
+  }
+}
+
+hipError_t launch_dot_batch(const DotBatch& b, double* work, hipStream_t s) {
+  if (b.count < 1 || b.count > kDotBatchMax || b.K < 1) return hipErrorInvalidValue;
+  bool small = true;
+  for (int p = 0; p < b.count; ++p) small = small && b.n[p] * b.K <= kDotSmallMax;
+  if (small) {
+    hipLaunchKernelGGL(k_dot_small, dim3(b.count), dim3(kDotSmallWg), 0, s, b);
+    return hipGetLastError();
+  }
+  for (int p = 0; p < b.count; ++p) {
+    hipError_t e = launch_dot_cols(b.x[p], b.y[p], b.n[p], b.K, b.out[p], work, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 hipError_t launch_dot_cols(const double* x, const double* y, int64_t n, int K, double* out, double* work,
                            hipStream_t s) {
+  if (n * K <= kDotSmallMax && K >= 1) {
+    DotBatch b{};
+    b.x[0] = x;
+    b.y[0] = y;
+    b.n[0] = n;
+    b.out[0] = out;
+    b.count = 1;
+    b.K = K;
+    hipLaunchKernelGGL(k_dot_small, dim3(1), dim3(kDotSmallWg), 0, s, b);
+    return hipGetLastError();
+  }
   const int64_t nb = (n * K + kDotWg - 1) / kDotWg;   // one step of a workgroup reads kDotWg entries
   const int nblk = (int)(nb < kDotBlocks ? (nb > 0 ? nb : 1) : kDotBlocks);
   hipLaunchKernelGGL(k_dot_stage1, dim3(nblk), dim3(kDotWg), 0, s, x, y, n, K, work);
