@@ -152,6 +152,8 @@ struct flsq_ctx {
   System sys;                        // cached system of the last solve_linear / gram / newton call
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   double last_gram_kernel_ms = 0.0;  // duration of the last fused Gram kernel (HIP events on the stream)
+  void* pinned = nullptr;            // pinned host staging for the small per-iteration read-backs
+  size_t pinned_bytes = 0;
 };
 
 struct flsq_factor {
@@ -180,6 +182,23 @@ Err ws_get(flsq_ctx* c, const std::string& name, size_t count, T** out) {
   DevBuf& b = wsb(c, name);
   CHECK_HIP(b.ensure(count * sizeof(T)));
   *out = b.as<T>();
+  return ok();
+}
+
+// Copy `bytes` from the device to host memory through the context's pinned staging buffer and
+// wait for the stream (the solvers' stopping decisions read a few scalars per iteration).
+Err read_back(flsq_ctx* c, void* host, const void* dev, size_t bytes) {
+  if (bytes > c->pinned_bytes) {
+    if (c->pinned) (void)hipHostFree(c->pinned);
+    c->pinned = nullptr;
+    c->pinned_bytes = 0;
+    const size_t want = std::max<size_t>(bytes, 64 * 1024);
+    CHECK_HIP(hipHostMalloc(&c->pinned, want, hipHostMallocDefault));
+    c->pinned_bytes = want;
+  }
+  CHECK_HIP(hipMemcpyAsync(c->pinned, dev, bytes, hipMemcpyDeviceToHost, c->stream));
+  CHECK_HIP(hipStreamSynchronize(c->stream));
+  memcpy(host, c->pinned, bytes);
   return ok();
 }
 
@@ -234,8 +253,7 @@ Err check_finite_dev(flsq_ctx* c, const double* p, int64_t n, const char* what) 
   CHECK_HIP(hipMemsetAsync(flag, 0, sizeof(int), c->stream));
   CHECK_HIP(launch_count_nonfinite(p, n, flag, c->stream));
   int h = 0;
-  CHECK_HIP(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
-  CHECK_HIP(hipStreamSynchronize(c->stream));
+  CHECK_ERR(read_back(c, &h, flag, sizeof(int)));
   if (h) return fail(FLSQ_ENONFINITE, "%s contains NaN or Inf", what);
   return ok();
 }
@@ -612,8 +630,7 @@ Err cholesky_inv(flsq_ctx* c, double* G, double* X, int n, int* info_host) {
     CHECK_HIP(launch_gemm_tri(dd + offT[l], (int)lvT[l].size(), maxM, maxN, maxKT, 1.0, gwork, gwork_elems, st));
     CHECK_HIP(launch_gemm_tri(dd + offX[l], (int)lvX[l].size(), maxM, maxN, maxKX, -1.0, gwork, gwork_elems, st));
   }
-  CHECK_HIP(hipMemcpyAsync(info_host, info, sizeof(int), hipMemcpyDeviceToHost, st));
-  CHECK_HIP(hipStreamSynchronize(st));
+  CHECK_ERR(read_back(c, info_host, info, sizeof(int)));
   return ok();
 }
 
@@ -673,8 +690,7 @@ Err factor_with_retries(flsq_ctx* c, const double* Gsrc, double* U, double* X, i
   CHECK_ERR(ws_get(c, "eq_d", (size_t)n, &d));
   CHECK_HIP(launch_diag_max(Gsrc, n, dmax, c->stream));
   double dm = 0.0;
-  CHECK_HIP(hipMemcpyAsync(&dm, dmax, sizeof(double), hipMemcpyDeviceToHost, c->stream));
-  CHECK_HIP(hipStreamSynchronize(c->stream));
+  CHECK_ERR(read_back(c, &dm, dmax, sizeof(double)));
   if (!std::isfinite(dm)) return fail(FLSQ_ENONFINITE, "Gram diagonal is not finite");
   double rel = shift0;
   *retries = 0;
@@ -714,8 +730,7 @@ struct RefineOut {
 
 Err host_cols(flsq_ctx* c, const double* dev, int K, std::vector<double>& h) {
   h.resize(K);
-  CHECK_HIP(hipMemcpyAsync(h.data(), dev, sizeof(double) * K, hipMemcpyDeviceToHost, c->stream));
-  CHECK_HIP(hipStreamSynchronize(c->stream));
+  CHECK_ERR(read_back(c, h.data(), dev, sizeof(double) * K));
   return ok();
 }
 
@@ -902,9 +917,24 @@ Err cgls_refine_op(flsq_ctx* c, const LsqOp& op, const double* Xi, double mu, co
       CHECK_HIP(launch_dot_batch(db, dwork, st));
     }
     CHECK_HIP(launch_cg_alpha(d_gam, d_qq, d_pp, mu, col_mask(active), K, d_alpha, st));
-    CHECK_HIP(launch_axpy_cols_dev(d_alpha, p, X, n, K, 1.0, st));
-    CHECK_HIP(launch_axpy_cols_dev(d_alpha, q, sres, P, K, -1.0, st));
-    if (track_u) CHECK_HIP(launch_axpy_cols_dev(d_alpha, hq, uu, P, K, 1.0, st));
+    {
+      AxpyBatch ab{};
+      ab.K = K;
+      ab.count = track_u ? 3 : 2;
+      ab.x[0] = p;
+      ab.y[0] = X;
+      ab.n[0] = n;
+      ab.sign[0] = 1.0;
+      ab.x[1] = q;
+      ab.y[1] = sres;
+      ab.n[1] = P;
+      ab.sign[1] = -1.0;
+      ab.x[2] = hq;
+      ab.y[2] = uu;
+      ab.n[2] = P;
+      ab.sign[2] = 1.0;
+      CHECK_HIP(launch_axpy_batch_dev(d_alpha, ab, st));
+    }
     // objective after the step
     {
       DotBatch db{};
@@ -918,8 +948,7 @@ Err cgls_refine_op(flsq_ctx* c, const LsqOp& op, const double* Xi, double mu, co
       db.out[1] = d_xx;
       CHECK_HIP(launch_dot_batch(db, dwork, st));
     }
-    CHECK_HIP(hipMemcpyAsync(hs.data(), d_alpha, sizeof(double) * 8 * K, hipMemcpyDeviceToHost, st));
-    CHECK_HIP(hipStreamSynchronize(st));
+    CHECK_ERR(read_back(c, hs.data(), d_alpha, sizeof(double) * 8 * K));
     const double* h_alpha = hs.data();
     const double *h_qq = hs.data() + 2 * K, *h_hh = hs.data() + 4 * K, *h_uu = hs.data() + 5 * K;
     const double *h_ss = hs.data() + 6 * K, *h_xx = hs.data() + 7 * K;
@@ -1134,6 +1163,7 @@ void flsq_destroy(flsq_ctx* ctx) {
   (void)hipStreamSynchronize(ctx->stream);
   if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
   if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+  if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   delete ctx;
 }
 
@@ -1358,8 +1388,20 @@ flsq_status flsq_factor_solve_normal(flsq_ctx* ctx, const flsq_factor* F, const 
         CHECK_HIP(launch_dot_batch(db, dwork, st));
       }
       CHECK_HIP(launch_cg_alpha(d_gam, d_pap, nullptr, 0.0, col_mask(active), K, d_alpha, st));
-      CHECK_HIP(launch_axpy_cols_dev(d_alpha, p, out, n, K, 1.0, st));
-      CHECK_HIP(launch_axpy_cols_dev(d_alpha, ap, r, n, K, -1.0, st));
+      {
+        AxpyBatch ab{};
+        ab.K = K;
+        ab.count = 2;
+        ab.x[0] = p;
+        ab.y[0] = out;
+        ab.n[0] = n;
+        ab.sign[0] = 1.0;
+        ab.x[1] = ap;
+        ab.y[1] = r;
+        ab.n[1] = n;
+        ab.sign[1] = -1.0;
+        CHECK_HIP(launch_axpy_batch_dev(d_alpha, ab, st));
+      }
       {
         DotBatch db{};
         db.K = K;
@@ -1374,8 +1416,7 @@ flsq_status flsq_factor_solve_normal(flsq_ctx* ctx, const flsq_factor* F, const 
         db.out[1] = d_xr;
         CHECK_HIP(launch_dot_batch(db, dwork, st));
       }
-      CHECK_HIP(hipMemcpyAsync(hs.data(), d_alpha, sizeof(double) * 6 * K, hipMemcpyDeviceToHost, st));
-      CHECK_HIP(hipStreamSynchronize(st));
+      CHECK_ERR(read_back(ctx, hs.data(), d_alpha, sizeof(double) * 6 * K));
       const double *h_alpha = hs.data(), *h_pap = hs.data() + 2 * K, *h_xv0 = hs.data() + 3 * K;
       const double *h_xv = hs.data() + 4 * K, *h_xr = hs.data() + 5 * K;
       double worst = 0.0;
@@ -1561,16 +1602,14 @@ Err newton_impl(flsq_ctx* c, const flsq_basis* basis, const flsq_rows* blocks, i
                                           rho_out, u_out, rpwork, st));
     CHECK_HIP(launch_dot_cols(Rout, Rout, P, 1, dots, dwork, st));
     double h = 0.0;
-    CHECK_HIP(hipMemcpyAsync(&h, dots, sizeof(double), hipMemcpyDeviceToHost, st));
-    CHECK_HIP(hipStreamSynchronize(st));
+    CHECK_ERR(read_back(c, &h, dots, sizeof(double)));
     *nrm = std::sqrt(h);
     if (!std::isfinite(*nrm)) return fail(FLSQ_ENONFINITE, "Newton residual is not finite");
     return ok();
   };
   auto dot1 = [&](const double* x, const double* y, int64_t len, double* out) -> Err {
     CHECK_HIP(launch_dot_cols(x, y, len, 1, dots, dwork, st));
-    CHECK_HIP(hipMemcpyAsync(out, dots, sizeof(double), hipMemcpyDeviceToHost, st));
-    CHECK_HIP(hipStreamSynchronize(st));
+    CHECK_ERR(read_back(c, out, dots, sizeof(double)));
     return ok();
   };
   const double t0 = now_ms();
@@ -2209,8 +2248,7 @@ Err newton_var_impl(flsq_ctx* c, const flsq_basis* basis, const flsq_vrows* bloc
   const double* data_w = L.rhs_w.as<double>();
   auto dot1 = [&](const double* x, const double* y, int64_t len, double* out) -> Err {
     CHECK_HIP(launch_dot_cols(x, y, len, 1, dots, dwork, st));
-    CHECK_HIP(hipMemcpyAsync(out, dots, sizeof(double), hipMemcpyDeviceToHost, st));
-    CHECK_HIP(hipStreamSynchronize(st));
+    CHECK_ERR(read_back(c, out, dots, sizeof(double)));
     return ok();
   };
   // R = A_L b - data + w N(u, grad u) on the nonlinear rows; the Jacobian coefficients of the

@@ -239,6 +239,17 @@ struct DotBatch {
   int K;
 };
 hipError_t launch_dot_batch(const DotBatch& b, double* work, hipStream_t s);
+// Up to kAxpyBatchMax updates y_q[i][c] += sign_q a[c] x_q[i][c] (a: device, K entries) in one launch.
+constexpr int kAxpyBatchMax = 3;
+struct AxpyBatch {
+  const double* x[kAxpyBatchMax];
+  double* y[kAxpyBatchMax];
+  int64_t n[kAxpyBatchMax];
+  double sign[kAxpyBatchMax];
+  int count;
+  int K;
+};
+hipError_t launch_axpy_batch_dev(const double* a, const AxpyBatch& b, hipStream_t s);
 hipError_t launch_dot_cols(const double* x, const double* y, int64_t n, int K, double* out, double* work,
                            hipStream_t s);
 // out[c] = sum_i u_i s_i Y[i][c] (Y n x K row-major), s_i = X[i * ldx + xcol] or 1 when X is NULL

@@ -258,7 +258,7 @@ hipError_t launch_sum_partials(const double* part, int n_split, int64_t len, dou
 // ------------------------------------------------------------------ preconditioner application
 // y = X^T v  (X upper triangular, n x n row-major): y_j = sum_{i <= j} X[i][j] v_i.
 // Grid (column tiles, row splits): each thread owns a column, loops over its row range;
-// partial sums go to work[split][j], reduced in order by k_sum_splits.
+// partial sums go to work[split][j], reduced in order by k_sum_tv_splits.
 constexpr int kTvSplits = 32;
 
 __global__ __launch_bounds__(256) void k_trmv_t(const double* __restrict__ X, int n, const double* __restrict__ v,
@@ -276,11 +276,17 @@ __global__ __launch_bounds__(256) void k_trmv_t(const double* __restrict__ X, in
   }
 }
 
-__global__ void k_sum_splits(const double* __restrict__ work, int n, int splits, double* __restrict__ out) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+// The kTvSplits partials of k_trmv_t, summed in split order: all loads of a column issued at
+// once (unrolled), 64 columns per workgroup so that small n still spreads over several CUs.
+__global__ __launch_bounds__(64) void k_sum_tv_splits(const double* __restrict__ work, int n, double* __restrict__ out) {
+  const int j = blockIdx.x * 64 + threadIdx.x;
   if (j >= n) return;
+  double v[kTvSplits];
+#pragma unroll
+  for (int sp = 0; sp < kTvSplits; ++sp) v[sp] = work[(int64_t)sp * n + j];
   double s = 0.0;
-  for (int sp = 0; sp < splits; ++sp) s += work[(int64_t)sp * n + j];
+#pragma unroll
+  for (int sp = 0; sp < kTvSplits; ++sp) s += v[sp];
   out[j] = s;
 }
 
@@ -301,7 +307,7 @@ __global__ __launch_bounds__(256) void k_trmv_n(const double* __restrict__ X, in
 hipError_t launch_precond_apply(const double* X, int n, const double* v, double* tmp, double* work, double* out,
                                 hipStream_t s) {
   hipLaunchKernelGGL(k_trmv_t, dim3((n + 255) / 256, kTvSplits), dim3(256), 0, s, X, n, v, work);
-  hipLaunchKernelGGL(k_sum_splits, dim3((n + 255) / 256), dim3(256), 0, s, work, n, kTvSplits, tmp);
+  hipLaunchKernelGGL(k_sum_tv_splits, dim3((n + 63) / 64), dim3(64), 0, s, work, n, tmp);
   hipLaunchKernelGGL(k_trmv_n, dim3((n + 3) / 4), dim3(256), 0, s, X, n, tmp, out);
   return hipGetLastError();
 }

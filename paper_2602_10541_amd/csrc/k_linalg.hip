@@ -2,6 +2,8 @@
 // (A^T A + mu I) beta = A^T rhs: diagonal equilibration, copies, norms, and the small
 // column-wise vector kernels of the CGLS / PCG iterations.  The factorisation itself is
 // in k_chol.hip, the products with the explicit inverse factor in k_dense.hip.
+#include <algorithm>
+
 #include "flsq_device.h"
 #include "flsq_launch.h"
 
@@ -273,6 +275,23 @@ hipError_t launch_axpy_cols_dev(const double* a, const double* x, double* y, int
   const int64_t tot = n * K;
   if (tot == 0) return hipSuccess;
   hipLaunchKernelGGL(k_axpy_cols_dev, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, a, x, y, n, K, sign);
+  return hipGetLastError();
+}
+
+// Several y_q += sign_q a[c] x_q updates with one device scalar vector a (one launch; grid.y = q).
+__global__ void k_axpy_batch_dev(const double* __restrict__ a, AxpyBatch b) {
+  const int q = blockIdx.y;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= b.n[q] * b.K) return;
+  b.y[q][e] = fma(b.sign[q] * a[e % b.K], b.x[q][e], b.y[q][e]);
+}
+
+hipError_t launch_axpy_batch_dev(const double* a, const AxpyBatch& b, hipStream_t s) {
+  if (b.count < 1 || b.count > kAxpyBatchMax || b.K < 1) return hipErrorInvalidValue;
+  int64_t mx = 0;
+  for (int q = 0; q < b.count; ++q) mx = std::max<int64_t>(mx, b.n[q] * b.K);
+  if (mx == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_axpy_batch_dev, dim3((unsigned)((mx + 255) / 256), b.count), dim3(256), 0, s, a, b);
   return hipGetLastError();
 }
 
