@@ -152,3 +152,14 @@ def test_bandwidth_adamw_trajectory_matches_oracle(helm):
     assert np.abs(sigs - gold["adamw_sigma"]).max() <= 1e-5 * sigs.max()
     assert np.all(np.abs(losses - gold["adamw_loss"]) <= 1e-4 * gold["adamw_loss"])
     assert losses[-1] <= 1e-2 * losses[0]
+
+
+def test_bandwidth_1d_matches_oracle():
+    """d = 1 (L is the scalar bandwidth itself): the 1D Poisson problem with base draws at unit
+    bandwidth, L = 1 (loss 1e-5; at larger L the loss falls to 1e-8 and the FP64 spread of the
+    gradient grows to 3e-4)."""
+    torch, fl = require_gpu()
+    prob = wl.poisson(1, 120, 1.0, 400, 2, seed=4, n_test=100)
+    prob.mu = 1e-6
+    dp = fl.DeviceProblem(prob)
+    _check(prob, np.array([[1.0]]), _gpu(fl, torch, dp, prob, np.array([[1.0]])))

@@ -146,3 +146,35 @@ def test_bratu_newton_matches_oracle():
     u = oracle.evaluate(prob.W, prob.b, beta.cpu().numpy(), prob.x_test, [(0, 0)])[:, 0]
     assert rel_l2(u, gold["u_test"]) <= 1e-6, rel_l2(u, gold["u_test"])
     assert abs(rel_l2(u, prob.u_test) - float(gold["err_exact"])) <= 0.1 * float(gold["err_exact"])
+
+
+def test_varcoef_3d_with_empty_block_matches_oracle():
+    """d = 3, an empty block between two non-empty ones, channel counts 2 / 1 / 1, random per-row
+    coefficients: the assembled matrix element by element and the solve's u against the oracle."""
+    torch, fl = require_gpu()
+    rng = np.random.default_rng(8)
+    d, n = 3, 150
+    W = rng.normal(0, 2.0, size=(n, d))
+    b = rng.uniform(0, 2 * np.pi, size=n)
+    xi = rng.uniform(0, 1, size=(300, d))
+    xb = rng.uniform(0, 1, size=(90, d))
+    a0 = 1.0 + rng.uniform(size=300)
+    a1 = rng.normal(size=300)
+    blocks = [
+        wl.VarBlock("interior", xi, [(wl.laplacian_terms(d, range(d), -1.0), a0), ([(1.0, (0, 0, 1))], a1)], 1.0,
+                    rng.normal(size=300)),
+        wl.VarBlock("empty", np.zeros((0, d)), [(wl.identity_terms(d), None)], 3.0, np.zeros(0)),
+        wl.VarBlock("boundary", xb, [(wl.identity_terms(d), None)], 100.0, rng.normal(size=90)),
+    ]
+    prob = wl.Problem("var3d", d, n, W, b, blocks, mu=1e-8, x_test=rng.uniform(0, 1, size=(50, d)))
+    dp = fl.DeviceVarProblem(prob)
+    A = torch.empty((dp.n_rows, n), dtype=torch.float64, device="cuda")
+    fl.flsq_assemble_var(context(), dp.basis, dp.rows, A)
+    Ao, _ = oracle.assemble_var_system(prob)
+    assert np.abs(A.cpu().numpy() - Ao).max() <= 1e-12 * np.abs(Ao).max()
+    beta = torch.empty(n, dtype=torch.float64, device="cuda")
+    fl.flsq_solve_linear_var(context(), dp.basis, dp.rows, fl.solve_opts(prob.mu, 0, 30, 1e-12), beta)
+    bo = oracle.solve_linear_var(prob)
+    u = oracle.evaluate(W, b, beta.cpu().numpy(), prob.x_test, [(0, 0, 0)])[:, 0]
+    uo = oracle.evaluate(W, b, bo, prob.x_test, [(0, 0, 0)])[:, 0]
+    assert rel_l2(u, uo) <= 1e-8, rel_l2(u, uo)
