@@ -101,6 +101,11 @@ typedef struct {
                              FP32 / BF16x3 preconditioner (0 = automatic) */
     int32_t report_grad;  /* nonzero: fill flsq_solve_info.grad_norm at the returned beta (two extra
                              matrix-free passes); otherwise grad_norm repeats grad_norm0 */
+    int32_t second_pass;  /* re-factor through the preconditioned matrix [A; sqrt(mu) I] X (formed in HBM),
+                             so that the refinement converges in a few steps where the first Cholesky
+                             needed a diagonal shift: 0 = automatic (FP64 and INT8_CRT Grams, no Newton
+                             row coefficient, a shifted first factor and 2 P N^2 <= 2e11), 1 = always
+                             (same precisions and no row coefficient), -1 = never */
 } flsq_solve_opts;
 
 typedef struct {
@@ -114,6 +119,8 @@ typedef struct {
     double t_gram_ms, t_chol_ms, t_refine_ms, t_total_ms;
     double t_gram_kernel_ms; /* the matrix-core Gram kernel alone (HIP events on the stream): the fused
                                 assembly + Gram kernel for FP64 / FP32, the int8 tile kernel for INT8_CRT */
+    int32_t second_pass;     /* 1 if the factor was refined by the second pass (opts.second_pass) */
+    double t_second_pass_ms; /* its time (included in t_chol_ms) */
 } flsq_solve_info;
 
 typedef struct flsq_ctx flsq_ctx;

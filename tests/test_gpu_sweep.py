@@ -91,3 +91,26 @@ def test_sweep_column_counts_cover_pass_variants(sweep, K):
     errs = [rel_l2(U[:, i], gold["u_test"][:, s]) for i, s in enumerate(cols)]
     assert max(errs) <= 1e-7, (K, max(errs))
     F.free()
+
+
+@pytest.mark.parametrize("second_pass", [-1, 0])
+def test_sweep_second_pass_refactor(sweep, second_pass):
+    """The equilibrated Gram of this problem needs a diagonal shift to factor.  Without the second
+    pass the single-right-hand-side refinement needs tens of CG steps; with it (automatic here) a
+    few; both land within 1e-7 of the oracle."""
+    torch, fl = require_gpu()
+    prob, dp, gold = sweep
+    ctx = context()
+    F = fl.flsq_factorize(ctx, dp.basis, dp.rows, fl.solve_opts(prob.mu, 3, 60, 1e-12, second_pass=second_pass))
+    assert F.info.chol_retries >= 1
+    assert F.info.second_pass == (1 if second_pass == 0 else 0)
+    Y = torch.tensor(prob.extras["rhs_rows"][:, 5].copy(), dtype=torch.float64, device="cuda")
+    b1 = torch.empty(prob.n_feat, dtype=torch.float64, device="cuda")
+    info = fl.flsq_factor_solve(ctx, F, Y, b1)
+    u1 = _u_cols(fl, torch, ctx, dp, prob, b1[:, None])[:, 0]
+    assert rel_l2(u1, gold["u_test"][:, 5]) <= 1e-7, (second_pass, rel_l2(u1, gold["u_test"][:, 5]), info.as_dict())
+    if second_pass == 0:
+        assert info.refine_iters <= 8, info.as_dict()
+    else:
+        assert info.refine_iters >= 20, info.as_dict()
+    F.free()
