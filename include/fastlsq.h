@@ -101,11 +101,13 @@ typedef struct {
                              FP32 / BF16x3 preconditioner (0 = automatic) */
     int32_t report_grad;  /* nonzero: fill flsq_solve_info.grad_norm at the returned beta (two extra
                              matrix-free passes); otherwise grad_norm repeats grad_norm0 */
-    int32_t second_pass;  /* re-factor through the preconditioned matrix [A; sqrt(mu) I] X (formed in HBM),
-                             so that the refinement converges in a few steps where the first Cholesky
-                             needed a diagonal shift: 0 = automatic (FP64 and INT8_CRT Grams, no Newton
-                             row coefficient, a shifted first factor and 2 P N^2 <= 2e11), 1 = always
-                             (same precisions and no row coefficient), -1 = never */
+    int32_t second_pass;  /* re-factor through the preconditioned matrix [A; sqrt(mu) I] X (A formed in
+                             HBM), so that the refinement converges in a few steps on nearly singular
+                             Grams.  0 = automatic: at factorisation when the first Cholesky needed a
+                             diagonal shift, and in the one-call solvers also after 8 refinement steps
+                             that did not converge (FP64 and INT8_CRT Grams, no Newton row coefficient,
+                             2 P N^2 <= 2e11); 1 = always (same precisions, no row coefficient);
+                             -1 = never */
 } flsq_solve_opts;
 
 typedef struct {

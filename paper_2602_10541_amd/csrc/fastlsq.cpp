@@ -1149,16 +1149,61 @@ Err second_pass_factor(flsq_ctx* c, const double* A, int64_t P, int n, double mu
   return ok();
 }
 
-bool want_second_pass(const SolveParams& sp, int retries, const double* rho, int64_t P, int n) {
+bool second_pass_allowed(const SolveParams& sp, const double* rho, int64_t P, int n) {
   if (sp.second_pass < 0 || rho) return false;
   if (sp.prec != FLSQ_PREC_FP64 && sp.prec != FLSQ_PREC_INT8_CRT) return false;
-  if (sp.second_pass > 0) return true;
-  return retries > 0 && 2.0 * (double)P * n * n <= 2e11;
+  return sp.second_pass > 0 || 2.0 * (double)P * n * n <= 2e11;
+}
+
+// Taken at factorisation: always when asked for, automatically when the first factor needed a shift.
+bool want_second_pass(const SolveParams& sp, int retries, const double* rho, int64_t P, int n) {
+  if (!second_pass_allowed(sp, rho, P, n)) return false;
+  return sp.second_pass > 0 || retries > 0;
+}
+
+// Steps of refinement after which an automatic second pass not taken at factorisation is taken
+// anyway (an unshifted factor can still leave tens of CG steps on a nearly singular Gram).
+constexpr int kLazySecondPassIters = 8;
+
+// Refinement that takes the automatic second pass late: at most kLazySecondPassIters steps with
+// the first factor; if they do not converge, re-factor through the preconditioned matrix
+// (make_A() gives A, P x n in HBM) and continue from the current iterate.
+template <class MakeA>
+Err refine_lazy(flsq_ctx* c, const LsqOp& op, const SolveParams& sp, bool lazy, MakeA make_A, double* Xi,
+                const double* Yw, int K, double* X, bool want_grad0, bool want_grad, RefineOut* ro, bool* second,
+                double* t_second) {
+  const int first = lazy ? std::min(sp.max_refine, kLazySecondPassIters) : sp.max_refine;
+  CHECK_ERR(cgls_refine_op(c, op, Xi, sp.mu, Yw, K, X, first, sp.refine_tol, want_grad0, want_grad && !lazy, ro));
+  if (!lazy || ro->converged || sp.max_refine <= first) {
+    if (lazy && want_grad) {   // the gradient at the returned point was not taken in the short run
+      RefineOut r2;
+      CHECK_ERR(cgls_refine_op(c, op, Xi, sp.mu, Yw, K, X, 0, sp.refine_tol, true, false, &r2));
+      ro->grad = r2.grad0;
+    }
+    return ok();
+  }
+  const double t0 = now_ms();
+  const double* A = nullptr;
+  CHECK_ERR(make_A(&A));
+  double shift2 = 0.0;
+  int retries2 = 0;
+  CHECK_ERR(second_pass_factor(c, A, op.P, op.n, sp.mu, Xi, &shift2, &retries2));
+  CHECK_HIP(hipStreamSynchronize(c->stream));
+  *second = true;
+  *t_second = now_ms() - t0;
+  RefineOut r2;
+  CHECK_ERR(cgls_refine_op(c, op, Xi, sp.mu, Yw, K, X, sp.max_refine - ro->iters, sp.refine_tol, false, want_grad,
+                           &r2));
+  ro->iters += r2.iters;
+  ro->converged = r2.converged;
+  ro->last_step = r2.last_step;
+  ro->grad = want_grad ? r2.grad : ro->grad0;
+  return ok();
 }
 
 // Gram, Cholesky, and the inverse factor Xi = U^{-1} (the preconditioner is Xi Xi^T).
 Err gram_and_factor(flsq_ctx* c, const System& s, const double* rho, const SolveParams& sp, double* Xi,
-                    flsq_solve_info* info) {
+                    flsq_solve_info* info, bool* second_out = nullptr) {
   const int n = s.n;
   double *G, *U;
   CHECK_ERR(ws_get(c, "G", (size_t)n * n, &G));
@@ -1188,6 +1233,7 @@ Err gram_and_factor(flsq_ctx* c, const System& s, const double* rho, const Solve
     retries += retries2;
     second = true;
   }
+  if (second_out) *second_out = second;
   const double t2 = now_ms();
   if (info) {
     info->t_gram_ms = t1 - t0;
@@ -1207,7 +1253,8 @@ Err solve_on_system(flsq_ctx* c, const System& s, const double* rho, const Solve
   const double t0 = now_ms();
   double* Xi;
   CHECK_ERR(ws_get(c, "Xinv", (size_t)n * n, &Xi));
-  CHECK_ERR(gram_and_factor(c, s, rho, sp, Xi, info));
+  bool eager = false;
+  CHECK_ERR(gram_and_factor(c, s, rho, sp, Xi, info, &eager));
   const double t1 = now_ms();
   // X0 = (U^T U)^{-1} A^T Y
   double *cvec, *colwork;
@@ -1216,8 +1263,18 @@ Err solve_on_system(flsq_ctx* c, const System& s, const double* rho, const Solve
   CHECK_HIP(launch_colpass_runs(s.pass(), rho, Yw, K, nullptr, 1.0, 0.0, cvec, colwork, c->stream));
   CHECK_ERR(chol_solve(c, Xi, n, cvec, X, K));
   RefineOut ro;
-  CHECK_ERR(cgls_refine(c, s, rho, Xi, sp.mu, Yw, K, X, sp.max_refine, sp.refine_tol, info != nullptr,
-                        info != nullptr && sp.report_grad, &ro));
+  const bool lazy = sp.second_pass == 0 && !eager && second_pass_allowed(sp, rho, s.P, n);
+  bool second = false;
+  double t_second = 0.0;
+  auto make_A = [&](const double** A) -> Err {
+    double* buf;
+    CHECK_ERR(ws_get(c, "sp_A", (size_t)s.P * n, &buf));
+    CHECK_HIP(launch_assemble(s.geo(), 0, buf, c->stream));
+    *A = buf;
+    return ok();
+  };
+  CHECK_ERR(refine_lazy(c, PassOp(s, rho), sp, lazy, make_A, Xi, Yw, K, X, info != nullptr,
+                        info != nullptr && sp.report_grad, &ro, &second, &t_second));
   CHECK_HIP(hipStreamSynchronize(c->stream));
   const double t2 = now_ms();
   if (info) {
@@ -1226,6 +1283,10 @@ Err solve_on_system(flsq_ctx* c, const System& s, const double* rho, const Solve
     info->grad_norm = ro.grad;
     info->last_step_rel = ro.last_step;
     info->t_refine_ms = t2 - t1;
+    if (second) {
+      info->second_pass = 1;
+      info->t_second_pass_ms = t_second;
+    }
   }
   if (converged) *converged = ro.converged;
   return ok();
@@ -2203,9 +2264,17 @@ Err var_linear_solve(flsq_ctx* c, const double* A, const double* At, int n, int6
   CHECK_HIP(launch_rowdot(At, n, P, P, Yw, nullptr, 1.0, 0.0, cvec, c->stream));
   CHECK_ERR(chol_solve(c, Xi, n, cvec, beta, 1));
   RefineOut ro;
-  CHECK_ERR(cgls_refine_op(c, DenseOp(A, At, n, P), Xi, sp.mu, Yw, 1, beta, sp.max_refine, sp.refine_tol,
-                           info != nullptr, info != nullptr && sp.report_grad, &ro));
+  const bool lazy = sp.second_pass == 0 && !second && second_pass_allowed(sp, nullptr, P, n);
+  double t_second = 0.0;
+  auto make_A = [&](const double** Aout) -> Err {
+    *Aout = A;
+    return ok();
+  };
+  bool late = false;
+  CHECK_ERR(refine_lazy(c, DenseOp(A, At, n, P), sp, lazy, make_A, Xi, Yw, 1, beta, info != nullptr,
+                        info != nullptr && sp.report_grad, &ro, &late, &t_second));
   CHECK_HIP(hipStreamSynchronize(c->stream));
+  if (late) second = true;
   if (info) {
     info->t_gram_ms = t1 - t0;
     info->t_chol_ms = t2 - t1;
@@ -2218,7 +2287,7 @@ Err var_linear_solve(flsq_ctx* c, const double* A, const double* At, int n, int6
     info->last_step_rel = ro.last_step;
     info->t_refine_ms = now_ms() - t2;
     info->second_pass = second ? 1 : 0;
-    info->t_second_pass_ms = second ? t2 - t2a : 0.0;
+    info->t_second_pass_ms = late ? t_second : (second ? t2 - t2a : 0.0);
   }
   if (converged) *converged = ro.converged;
   return ok();
@@ -2395,6 +2464,9 @@ Err newton_var_impl(flsq_ctx* c, const flsq_basis* basis, const flsq_vrows* bloc
   CHECK_ERR(residual(beta, R, UE, &nR));
   std::vector<double> one(1, 1.0);
   double *J, *Jt;
+  // Newton steps need no fully refined step (the outer iteration corrects it): the automatic
+  // second pass is left to the warm start; an explicit request still applies to every step.
+  if (spk.second_pass == 0) spk.second_pass = -1;
   for (int it = 0; it < o->max_iter; ++it) {
     CHECK_ERR(assemble_var_dev(c, Jsys, "nv_J", "nv_Jt", &J, &Jt));
     CHECK_HIP(launch_scale_copy(R, negR, P, -1.0, st));
