@@ -1074,7 +1074,8 @@ Err check_params(const SolveParams& p) {
 // Where the first Cholesky needed a diagonal shift, the refinement then converges in a few
 // steps instead of tens.  A: P x n row-major in HBM.
 Err second_pass_factor(flsq_ctx* c, const double* A, int64_t P, int n, double mu, double* Xi, double* shift2,
-                       int* retries2) {
+                       int* retries2, bool* applied) {
+  *applied = true;
   hipStream_t st = c->stream;
   double *Q, *G2, *U, *X2, *Xn, *work, *part;
   CHECK_ERR(ws_get(c, "sp_Q", (size_t)P * n, &Q));
@@ -1143,7 +1144,12 @@ Err second_pass_factor(flsq_ctx* c, const double* A, int64_t P, int n, double mu
   CHECK_HIP(launch_sum_partials(part, n_split, (int64_t)n * n, G2, st));
   CHECK_HIP(launch_gemm_batched(d + 1 + n_split, 1, n, n, mu, 1.0, 1, st));
   CHECK_HIP(hipStreamSynchronize(st));   // h leaves scope before the factorisation reuses the descriptors' slots
-  CHECK_ERR(factor_with_retries(c, G2, U, X2, n, 0.0, 0.0, shift2, retries2));
+  Err fe = factor_with_retries(c, G2, U, X2, n, 0.0, 0.0, shift2, retries2);
+  if (fe.st == FLSQ_ENOTSPD) {   // the first factor stays in use
+    *applied = false;
+    return ok();
+  }
+  CHECK_ERR(fe);
   CHECK_HIP(launch_gemm_tri(d + 2 + n_split, 1, n, n, n, 1.0, work, we, st));
   CHECK_HIP(hipMemcpyAsync(Xi, Xn, sizeof(double) * n * n, hipMemcpyDeviceToDevice, st));
   return ok();
@@ -1187,9 +1193,10 @@ Err refine_lazy(flsq_ctx* c, const LsqOp& op, const SolveParams& sp, bool lazy, 
   CHECK_ERR(make_A(&A));
   double shift2 = 0.0;
   int retries2 = 0;
-  CHECK_ERR(second_pass_factor(c, A, op.P, op.n, sp.mu, Xi, &shift2, &retries2));
+  bool applied = false;
+  CHECK_ERR(second_pass_factor(c, A, op.P, op.n, sp.mu, Xi, &shift2, &retries2, &applied));
   CHECK_HIP(hipStreamSynchronize(c->stream));
-  *second = true;
+  *second = applied;
   *t_second = now_ms() - t0;
   RefineOut r2;
   CHECK_ERR(cgls_refine_op(c, op, Xi, sp.mu, Yw, K, X, sp.max_refine - ro->iters, sp.refine_tol, false, want_grad,
@@ -1228,10 +1235,9 @@ Err gram_and_factor(flsq_ctx* c, const System& s, const double* rho, const Solve
     CHECK_HIP(launch_assemble(s.geo(), 0, A, c->stream));
     double shift2 = 0.0;
     int retries2 = 0;
-    CHECK_ERR(second_pass_factor(c, A, s.P, n, sp.mu, Xi, &shift2, &retries2));
+    CHECK_ERR(second_pass_factor(c, A, s.P, n, sp.mu, Xi, &shift2, &retries2, &second));
     CHECK_HIP(hipStreamSynchronize(c->stream));
     retries += retries2;
-    second = true;
   }
   if (second_out) *second_out = second;
   const double t2 = now_ms();
@@ -2255,9 +2261,8 @@ Err var_linear_solve(flsq_ctx* c, const double* A, const double* At, int n, int6
   if (want_second_pass(sp, retries, nullptr, P, n)) {
     double shift2 = 0.0;
     int retries2 = 0;
-    CHECK_ERR(second_pass_factor(c, A, P, n, sp.mu, Xi, &shift2, &retries2));
+    CHECK_ERR(second_pass_factor(c, A, P, n, sp.mu, Xi, &shift2, &retries2, &second));
     retries += retries2;
-    second = true;
   }
   CHECK_HIP(hipStreamSynchronize(c->stream));
   const double t2 = now_ms();
