@@ -502,6 +502,26 @@ def bench_c5(fl, ctx, reps=5):
                                                      np.linalg.norm(gold["grad_theta0"])),
                      "loss_rel_err_vs_oracle": float(np.max(np.abs(loss.cpu().numpy() - gold["loss0"]) /
                                                             np.abs(gold["loss0"])))}
+        if name == "int8_crt":
+            # the workload's 200 batched Adam steps (lr 1e-2, width clamped at 0.02) on the device
+            p = th.clone()
+            m = torch.zeros_like(p)
+            v = torch.zeros_like(p)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for t in range(1, 201):
+                _, gg, _ = ip.loss_and_grad(p, want_kappa=False)
+                fl.flsq_adam_step(ctx, p, gg, m, v, t, 1e-2, clamp_col=3, clamp_min=0.02)
+            lf, _, _ = ip.loss_and_grad(p, want_kappa=False)
+            torch.cuda.synchronize()
+            t_adam = time.perf_counter() - t0
+            lf = lf.cpu().numpy()
+            best = int(np.argmin(lf))
+            tt = np.asarray(prob.extras["theta_true"], dtype=np.float64)
+            res[name]["adam_200"] = {"total_s": t_adam, "best_loss": float(lf[best]),
+                                     "median_loss": float(np.median(lf)), "loss0_median": float(np.median(gold["loss0"])),
+                                     "best_theta": p[best].cpu().numpy().tolist(), "theta_true": tt.tolist(),
+                                     "best_theta_abs_err": float(np.max(np.abs(p[best].cpu().numpy() - tt)))}
         F.free()
     return res
 
