@@ -154,6 +154,10 @@ def bench_evaluate(fl, ctx, reps=5):
     return {"workload": "heat_3d+t evaluate: N=8192, Q=1048576 FP32 points, outputs u,u_x,u_y,u_z,u_t",
             "ms": ms, "points_per_s": Q / (ms * 1e-3), "pairs_per_s": pairs / (ms * 1e-3),
             "hbm_bytes": hbm, "hbm_gb_s": hbm / (ms * 1e-3) / 1e9, "hbm_frac": hbm / (ms * 1e-3) / PEAK_HBM_BYTES,
+            "traffic": measured_traffic("profiles/k_evaluate_f32_heat4d_hbm_traffic.md",
+                                        "paper_2602_10541_amd/csrc/k_prep.hip"),
+            "traffic_source": "profiles/k_evaluate_f32_heat4d_hbm_traffic.md (FETCH_SIZE + WRITE_SIZE, copy-calibrated; "
+                              "null if the source changed since)",
             "bound": "alu (one FP32 sincos + d + outputs FMAs per point-feature pair; not HBM)"}
 
 
@@ -606,6 +610,8 @@ def main():
                                                  "paper_2602_10541_amd/csrc/k_gram_i8.hip"),
                      "traffic_source": "profiles/k_gram_i8_poisson6d_hbm_traffic.md (FETCH_SIZE + WRITE_SIZE, "
                                        "copy-calibrated; null if the kernel changed since)",
+                     "trace_source": "profiles/k_gram_i8_poisson6d_bench_kernel_trace.md (kernel trace of this "
+                                     "path at these step counts; mean duration of the timed dispatches)",
                      "kernel": "k_gram_i8 (int8 MFMA residue Gram, 13 moduli)",
                      "ops_per_launch": ops8, "avg_kernel_ms": k8},
     }
