@@ -1077,7 +1077,7 @@ Err second_pass_factor(flsq_ctx* c, const double* A, int64_t P, int n, double mu
                        int* retries2, bool* applied) {
   *applied = true;
   hipStream_t st = c->stream;
-  double *Q, *G2, *U, *X2, *Xn, *work, *part;
+  double *Q, *Qt, *G2, *U, *X2, *Xn, *work;
   CHECK_ERR(ws_get(c, "sp_Q", (size_t)P * n, &Q));
   CHECK_ERR(ws_get(c, "sp_G2", (size_t)n * n, &G2));
   CHECK_ERR(ws_get(c, "Ufac", (size_t)n * n, &U));
@@ -1085,10 +1085,8 @@ Err second_pass_factor(flsq_ctx* c, const double* A, int64_t P, int n, double mu
   CHECK_ERR(ws_get(c, "sp_Xn", (size_t)n * n, &Xn));
   const size_t we = (size_t)8 * n * n;
   CHECK_ERR(ws_get(c, "sp_work", we, &work));
-  // row chunks of the Gram of Q: at most 16 partial n x n products
-  const int64_t kc = std::max<int64_t>(256, (P + 15) / 16);
-  const int n_split = (int)((P + kc - 1) / kc);
-  CHECK_ERR(ws_get(c, "sp_part", (size_t)n_split * n * n, &part));
+  CHECK_ERR(ws_get(c, "sp_Qt", (size_t)P * n, &Qt));
+  const int n_split = 1;
   std::vector<GemmDesc> h(n_split + 3);
   for (auto& g : h) memset(&g, 0, sizeof g);
   GemmDesc& dq = h[0];   // Q = A Xi, Xi upper triangular
@@ -1102,18 +1100,17 @@ Err second_pass_factor(flsq_ctx* c, const double* A, int64_t P, int n, double mu
   dq.N = n;
   dq.K = n;
   dq.tri = 1;
-  for (int sp = 0; sp < n_split; ++sp) {   // part[sp] = Q[rows of sp]^T Q[rows of sp]
-    const int64_t k0 = sp * kc;
-    GemmDesc& g = h[1 + sp];
-    g.A = Q + k0 * n;
-    g.lda = n;
-    g.B = Q + k0 * n;
+  {   // G2 = Q^T Q from the transposed copy (K = P split across workgroups)
+    GemmDesc& g = h[1];
+    g.A = Qt;
+    g.lda = (int)P;
+    g.B = Q;
     g.ldb = n;
-    g.C = part + (int64_t)sp * n * n;
+    g.C = G2;
     g.ldc = n;
     g.M = n;
     g.N = n;
-    g.K = (int)std::min<int64_t>(kc, P - k0);
+    g.K = (int)P;
   }
   GemmDesc& dx = h[1 + n_split];   // G2 += mu Xi^T Xi
   dx.A = Xi;
@@ -1140,8 +1137,8 @@ Err second_pass_factor(flsq_ctx* c, const double* A, int64_t P, int n, double mu
   CHECK_ERR(ws_get(c, "sp_descs", h.size(), &d));
   CHECK_HIP(hipMemcpyAsync(d, h.data(), sizeof(GemmDesc) * h.size(), hipMemcpyHostToDevice, st));
   CHECK_HIP(launch_gemm_tri(d, 1, (int)P, n, n, 1.0, work, we, st));
-  CHECK_HIP(launch_gemm_batched(d + 1, n_split, n, n, 1.0, 0.0, 1, st));
-  CHECK_HIP(launch_sum_partials(part, n_split, (int64_t)n * n, G2, st));
+  CHECK_HIP(launch_transpose_f64(Q, P, n, Qt, st));
+  CHECK_HIP(launch_gemm_tri(d + 1, 1, n, n, (int)P, 1.0, work, we, st));
   CHECK_HIP(launch_gemm_batched(d + 1 + n_split, 1, n, n, mu, 1.0, 1, st));
   CHECK_HIP(hipStreamSynchronize(st));   // h leaves scope before the factorisation reuses the descriptors' slots
   Err fe = factor_with_retries(c, G2, U, X2, n, 0.0, 0.0, shift2, retries2);

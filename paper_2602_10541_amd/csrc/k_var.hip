@@ -135,6 +135,34 @@ hipError_t launch_rowdot(const double* M, int64_t R, int64_t len, int64_t ld, co
   return hipGetLastError();
 }
 
+// At (cols x rows) = A^T for a row-major rows x cols matrix: 32 x 32 tiles through LDS, both
+// the reads and the writes with unit stride.
+__global__ __launch_bounds__(256) void k_transpose_f64(const double* __restrict__ A, int64_t rows, int cols,
+                                                       double* __restrict__ At) {
+  __shared__ double t[32][33];
+  const int64_t r0 = (int64_t)blockIdx.x * 32;
+  const int c0 = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+  for (int k = ty; k < 32; k += 8) {
+    const int64_t r = r0 + k;
+    const int c = c0 + tx;
+    if (r < rows && c < cols) t[k][tx] = A[r * cols + c];
+  }
+  __syncthreads();
+  for (int k = ty; k < 32; k += 8) {
+    const int c = c0 + k;
+    const int64_t r = r0 + tx;
+    if (r < rows && c < cols) At[(int64_t)c * rows + r] = t[tx][k];
+  }
+}
+
+hipError_t launch_transpose_f64(const double* A, int64_t rows, int cols, double* At, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_transpose_f64, dim3((unsigned)((rows + 31) / 32), (cols + 31) / 32), dim3(256), 0, s, A, rows,
+                     cols, At);
+  return hipGetLastError();
+}
+
 __global__ void k_fill_f64(double* p, int64_t n, double v) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e < n) p[e] = v;
