@@ -202,11 +202,6 @@ Err read_back(flsq_ctx* c, void* host, const void* dev, size_t bytes) {
   return ok();
 }
 
-Err set_status(flsq_ctx* c, const Err& e) {
-  if (c) c->err = e.msg;
-  return e;
-}
-
 // ------------------------------------------------------------------ validation
 Err check_basis(const flsq_basis* b) {
   if (!b) return fail(FLSQ_EINVAL, "basis is NULL");
@@ -741,12 +736,6 @@ ColScalars cols(const std::vector<double>& h) {
   return c;
 }
 
-ColScalars cols1(double v) {
-  ColScalars c{};
-  c.v[0] = v;
-  return c;
-}
-
 // Bit k set where h[k] != 0 (K <= 64).
 uint64_t col_mask(const std::vector<double>& h) {
   uint64_t m = 0;
@@ -1253,7 +1242,6 @@ Err gram_and_factor(flsq_ctx* c, const System& s, const double* rho, const Solve
 Err solve_on_system(flsq_ctx* c, const System& s, const double* rho, const SolveParams& sp, const double* Yw, int K,
                     double* X, flsq_solve_info* info, bool* converged) {
   const int n = s.n;
-  const double t0 = now_ms();
   double* Xi;
   CHECK_ERR(ws_get(c, "Xinv", (size_t)n * n, &Xi));
   bool eager = false;

@@ -63,7 +63,7 @@ __global__ __launch_bounds__(256) void k_source_grad_stage1(const double* __rest
   red[3][threadIdx.x] = g3;
   __syncthreads();
   for (int st = 128; st > 0; st >>= 1) {
-    if (threadIdx.x < st)
+    if ((int)threadIdx.x < st)
       for (int p = 0; p < 4; ++p) red[p][threadIdx.x] += red[p][threadIdx.x + st];
     __syncthreads();
   }
@@ -105,7 +105,7 @@ __global__ __launch_bounds__(256) void k_misfit(const double* __restrict__ U, co
   red[threadIdx.x] = s;
   __syncthreads();
   for (int st = 128; st > 0; st >>= 1) {
-    if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
     __syncthreads();
   }
   if (threadIdx.x == 0) loss[h] = red[0] * inv;

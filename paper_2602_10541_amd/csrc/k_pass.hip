@@ -19,7 +19,6 @@ namespace flsq {
 
 constexpr int kPassRows = 64;        // rows per run (column pass and the many-column row pass)
 constexpr int kWideRows = 256;       // rows per wide run (row pass, K <= 16: one per workgroup)
-constexpr int kRowSlices = 4;        // feature slices per row-pass workgroup (one per wave)
 constexpr int kColFeat = 256;        // features per workgroup in the split count of the many-column pass
 
 
