@@ -103,11 +103,11 @@ typedef struct {
                              matrix-free passes); otherwise grad_norm repeats grad_norm0 */
     int32_t second_pass;  /* re-factor through the preconditioned matrix [A; sqrt(mu) I] X (A formed in
                              HBM), so that the refinement converges in a few steps on nearly singular
-                             Grams.  0 = automatic: at factorisation when the first Cholesky needed a
-                             diagonal shift, and in the one-call solvers also after 8 refinement steps
-                             that did not converge (FP64 and INT8_CRT Grams, no Newton row coefficient,
-                             2 P N^2 <= 2e11); 1 = always (same precisions, no row coefficient);
-                             -1 = never */
+                             Grams.  0 = automatic (FP64 and INT8_CRT Grams): at factorisation when the
+                             first Cholesky needed a diagonal shift and 2 P N^2 <= 2e11, and in the
+                             one-call solvers also after 8 refinement steps that did not converge when
+                             2 P N^2 <= 4e10; Newton steps take it only when asked for.  1 = always
+                             (same precisions); -1 = never */
 } flsq_solve_opts;
 
 typedef struct {

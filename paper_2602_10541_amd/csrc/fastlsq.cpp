@@ -1141,8 +1141,8 @@ Err second_pass_factor(flsq_ctx* c, const double* A, int64_t P, int n, double mu
   return ok();
 }
 
-bool second_pass_allowed(const SolveParams& sp, const double* rho, int64_t P, int n) {
-  if (sp.second_pass < 0 || rho) return false;
+bool second_pass_allowed(const SolveParams& sp, const double*, int64_t P, int n) {
+  if (sp.second_pass < 0) return false;
   if (sp.prec != FLSQ_PREC_FP64 && sp.prec != FLSQ_PREC_INT8_CRT) return false;
   return sp.second_pass > 0 || 2.0 * (double)P * n * n <= 2e11;
 }
@@ -1154,8 +1154,11 @@ bool want_second_pass(const SolveParams& sp, int retries, const double* rho, int
 }
 
 // Steps of refinement after which an automatic second pass not taken at factorisation is taken
-// anyway (an unshifted factor can still leave tens of CG steps on a nearly singular Gram).
+// anyway (an unshifted factor can still leave tens of CG steps on a nearly singular Gram), when
+// 2 P N^2 is at most kLazySecondPassFlops: the pass costs about 1.5 such products plus a
+// Cholesky, and beyond this size tens of CG steps are cheaper.
 constexpr int kLazySecondPassIters = 8;
+constexpr double kLazySecondPassFlops = 4e10;
 
 // Refinement that takes the automatic second pass late: at most kLazySecondPassIters steps with
 // the first factor; if they do not converge, re-factor through the preconditioned matrix
@@ -1219,6 +1222,7 @@ Err gram_and_factor(flsq_ctx* c, const System& s, const double* rho, const Solve
     double* A;
     CHECK_ERR(ws_get(c, "sp_A", (size_t)s.P * n, &A));
     CHECK_HIP(launch_assemble(s.geo(), 0, A, c->stream));
+    if (rho) CHECK_HIP(launch_add_rho(s.geo(), rho, A, c->stream));
     double shift2 = 0.0;
     int retries2 = 0;
     CHECK_ERR(second_pass_factor(c, A, s.P, n, sp.mu, Xi, &shift2, &retries2, &second));
@@ -1254,13 +1258,15 @@ Err solve_on_system(flsq_ctx* c, const System& s, const double* rho, const Solve
   CHECK_HIP(launch_colpass_runs(s.pass(), rho, Yw, K, nullptr, 1.0, 0.0, cvec, colwork, c->stream));
   CHECK_ERR(chol_solve(c, Xi, n, cvec, X, K));
   RefineOut ro;
-  const bool lazy = sp.second_pass == 0 && !eager && second_pass_allowed(sp, rho, s.P, n);
+  const bool lazy = sp.second_pass == 0 && !eager && second_pass_allowed(sp, rho, s.P, n) &&
+                    2.0 * (double)s.P * n * n <= kLazySecondPassFlops;
   bool second = false;
   double t_second = 0.0;
   auto make_A = [&](const double** A) -> Err {
     double* buf;
     CHECK_ERR(ws_get(c, "sp_A", (size_t)s.P * n, &buf));
     CHECK_HIP(launch_assemble(s.geo(), 0, buf, c->stream));
+    if (rho) CHECK_HIP(launch_add_rho(s.geo(), rho, buf, c->stream));
     *A = buf;
     return ok();
   };
@@ -1781,6 +1787,9 @@ Err newton_impl(flsq_ctx* c, const flsq_basis* basis, const flsq_rows* blocks, i
     CHECK_ERR(solve_on_system(c, s, nullptr, spk, s.rhs_w.as<double>(), 1, beta, &sinfo, nullptr));
     spk.shift_rel = std::max(spk.shift_rel, sinfo.shift);
   }
+  // Newton steps need no fully refined step: the automatic second pass is left to the warm
+  // start (measured: on the reaction-diffusion steps it costs more than the CG steps it saves)
+  if (spk.second_pass == 0) spk.second_pass = -1;
   if (tr) memset(tr, 0, sizeof *tr);
   *converged = false;
   double nR = 0.0;
@@ -2254,7 +2263,8 @@ Err var_linear_solve(flsq_ctx* c, const double* A, const double* At, int n, int6
   CHECK_HIP(launch_rowdot(At, n, P, P, Yw, nullptr, 1.0, 0.0, cvec, c->stream));
   CHECK_ERR(chol_solve(c, Xi, n, cvec, beta, 1));
   RefineOut ro;
-  const bool lazy = sp.second_pass == 0 && !second && second_pass_allowed(sp, nullptr, P, n);
+  const bool lazy = sp.second_pass == 0 && !second && second_pass_allowed(sp, nullptr, P, n) &&
+                    2.0 * (double)P * n * n <= kLazySecondPassFlops;
   double t_second = 0.0;
   auto make_A = [&](const double** Aout) -> Err {
     *Aout = A;

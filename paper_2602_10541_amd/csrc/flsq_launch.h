@@ -54,6 +54,8 @@ hipError_t launch_assemble_var(const VarGeo& g, hipStream_t s);
 hipError_t launch_rowdot(const double* M, int64_t R, int64_t len, int64_t ld, const double* v, const double* Y,
                          double alpha, double beta_y, double* out, hipStream_t s);
 hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t s);
+// A (P x n, an explicit assembly of the linear rows) += rho_i sin(z_ij + ph_gj) where rho_i != 0
+hipError_t launch_add_rho(const Geo& g, const double* rho, double* A, hipStream_t s);
 // At (cols x rows, row-major) = A^T for A rows x cols row-major
 hipError_t launch_transpose_f64(const double* A, int64_t rows, int cols, double* At, hipStream_t s);
 constexpr int kMaxNlTerms = 8;

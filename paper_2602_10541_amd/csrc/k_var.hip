@@ -163,6 +163,32 @@ hipError_t launch_transpose_f64(const double* A, int64_t rows, int cols, double*
   return hipGetLastError();
 }
 
+// A_ij += rho_i sin(z_ij + ph_gj) on the rows with rho_i != 0: the Newton row coefficient of
+// the folded entry (amp_gj + rho_i) sin(z_ij + ph_gj) added to an explicit assembly of the
+// linear rows (z as an FMA chain from zero in k order, as everywhere).  16 rows per workgroup
+// row, 256 features per workgroup column.
+__global__ __launch_bounds__(256) void k_add_rho(Geo g, const double* __restrict__ rho, double* __restrict__ A) {
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j >= g.n) return;
+  for (int r = 0; r < 16; ++r) {
+    const int64_t i = (int64_t)blockIdx.y * 16 + r;
+    if (i >= g.P) return;
+    const double rh = rho[i];
+    if (rh == 0.0) continue;
+    double z = 0.0;
+    for (int k = 0; k < g.d; ++k) z = fma(g.Wt[(int64_t)k * g.n + j], g.Xrm[i * g.d + k], z);
+    const int blk = g.row_block[i];
+    A[i * g.n + j] = fma(rh, sin_f64(z + g.ph[(int64_t)blk * g.n + j]), A[i * g.n + j]);
+  }
+}
+
+hipError_t launch_add_rho(const Geo& g, const double* rho, double* A, hipStream_t s) {
+  if (g.P <= 0 || g.n <= 0) return hipSuccess;
+  if ((g.P + 15) / 16 > 65535) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_add_rho, dim3((g.n + 255) / 256, (unsigned)((g.P + 15) / 16)), dim3(256), 0, s, g, rho, A);
+  return hipGetLastError();
+}
+
 __global__ void k_fill_f64(double* p, int64_t n, double v) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e < n) p[e] = v;

@@ -13,19 +13,23 @@ pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
-def _newton_gpu(prob, max_iter=15, prec=0):
+def _newton_gpu(prob, max_iter=15, prec=0, second_pass=0):
     torch, fl = require_gpu()
     ctx = context()
     dp = fl.DeviceProblem(prob)
     beta = torch.zeros(prob.n_feat, dtype=torch.float64, device="cuda")
     opts = fl.newton_opts(prob.mu, max_iter=max_iter, tol_dbeta=1e-10, prec=prec)
+    opts.lin.second_pass = second_pass
     st, tr = fl.flsq_solve_newton(ctx, dp.basis, dp.rows, prob.nonlin_block, prob.nonlin_poly, opts, beta)
     return st, tr, beta.cpu().numpy()
 
 
-def test_newton_small_matches_oracle():
+@pytest.mark.parametrize("second_pass", [0, 1])
+def test_newton_small_matches_oracle(second_pass):
+    """With second_pass = 1 every step re-factors through an explicit Jacobian that carries the
+    u-dependent row coefficient (A + diag(rho) H, rho = w N'(u) / sqrt(N))."""
     prob = wl.reaction_diffusion(n_feat=300, sigma=4.0, n_int=900, n_bc=200, seed=3, n_test=500)
-    st, tr, beta = _newton_gpu(prob)
+    st, tr, beta = _newton_gpu(prob, second_pass=second_pass)
     ref, trace = oracle.solve_newton(prob, max_iter=15)
     steps = tr.as_list()
     assert len(steps) == len(trace)
