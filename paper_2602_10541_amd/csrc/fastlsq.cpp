@@ -154,6 +154,8 @@ struct flsq_ctx {
   double last_gram_kernel_ms = 0.0;  // duration of the last fused Gram kernel (HIP events on the stream)
   void* pinned = nullptr;            // pinned host staging for the small per-iteration read-backs
   size_t pinned_bytes = 0;
+  flsq_factor* aux_factor = nullptr; // factor and derived system reused by the learnable-bandwidth calls
+  System aux;
 };
 
 struct flsq_factor {
@@ -1289,6 +1291,30 @@ Err solve_on_system(flsq_ctx* c, const System& s, const double* rho, const Solve
   return ok();
 }
 
+// Build the system of `blocks` into F and factor it (the body of flsq_factorize, reusable on an
+// existing factor object so that repeated calls keep its device buffers).
+Err factor_into(flsq_ctx* c, flsq_factor* f, const flsq_basis* basis, const flsq_rows* blocks, int n_blocks,
+                const SolveParams& sp, flsq_solve_info* info) {
+  f->device = c->device;
+  CHECK_ERR(build_system(c, f->sys, basis, blocks, n_blocks, false));
+  if (f->Xinv.ensure(sizeof(double) * f->sys.n * f->sys.n) != hipSuccess)
+    return fail(FLSQ_ENOMEM, "factor allocation failed");
+  flsq_solve_info local;
+  memset(&local, 0, sizeof local);
+  CHECK_ERR(gram_and_factor(c, f->sys, nullptr, sp, f->Xinv.as<double>(), info ? info : &local));
+  f->mu = sp.mu;
+  f->shift = info ? info->shift : local.shift;
+  f->max_refine = sp.max_refine;
+  f->refine_tol = sp.refine_tol;
+  f->report_grad = sp.report_grad;
+  // derived geometries of earlier calls no longer match
+  f->obs_key = nullptr;
+  f->obs_n = -1;
+  f->akap_rows = -1;
+  f->akap_dims = -1;
+  return ok();
+}
+
 flsq_status finish(flsq_ctx* c, const Err& e) {
   if (c) c->err = e.msg;
   return e.st;
@@ -1329,6 +1355,7 @@ void flsq_destroy(flsq_ctx* ctx) {
   if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
   if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  delete ctx->aux_factor;
   delete ctx;
 }
 
@@ -1412,22 +1439,11 @@ flsq_status flsq_factorize(flsq_ctx* ctx, const flsq_basis* basis, const flsq_ro
   if (e.st != FLSQ_OK) return finish(ctx, e);
   if (info) memset(info, 0, sizeof *info);
   flsq_factor* f = new flsq_factor();
-  f->device = ctx->device;
-  e = build_system(ctx, f->sys, basis, blocks, n_blocks, false);
-  if (e.st == FLSQ_OK) {
-    hipError_t he = f->Xinv.ensure(sizeof(double) * f->sys.n * f->sys.n);
-    if (he != hipSuccess) e = fail(FLSQ_ENOMEM, "factor allocation failed");
-  }
-  if (e.st == FLSQ_OK) e = gram_and_factor(ctx, f->sys, nullptr, sp, f->Xinv.as<double>(), info);
+  e = factor_into(ctx, f, basis, blocks, n_blocks, sp, info);
   if (e.st != FLSQ_OK) {
     delete f;
     return finish(ctx, e);
   }
-  f->mu = sp.mu;
-  f->shift = info ? info->shift : 0.0;
-  f->max_refine = sp.max_refine;
-  f->refine_tol = sp.refine_tol;
-  f->report_grad = sp.report_grad;
   *F = f;
   return finish(ctx, ok());
 }
@@ -1979,10 +1995,12 @@ Err bandwidth_impl(flsq_ctx* c, const flsq_basis* base, const double* L, const f
   CHECK_HIP(launch_apply_lower(base->W, n, d, Lm, W, st));
   flsq_basis bs = *base;
   bs.W = W;
-  flsq_factor* F = nullptr;
-  flsq_status fs = flsq_factorize(c, &bs, blocks, n_blocks, opts, &F, nullptr);
-  if (fs != FLSQ_OK) return Err{fs, c->err};
-  std::unique_ptr<flsq_factor, void (*)(flsq_factor*)> guard(F, flsq_factor_free);
+  SolveParams sp = params_of(opts);
+  CHECK_ERR(check_params(sp));
+  if (!c->aux_factor) c->aux_factor = new flsq_factor();
+  flsq_factor* F = c->aux_factor;
+  CHECK_ERR(factor_into(c, F, &bs, blocks, n_blocks, sp, nullptr));
+  flsq_status fs;
   const System& s = F->sys;
   const int64_t P = s.P;
   const int K = 2 * d;
@@ -2012,7 +2030,7 @@ Err bandwidth_impl(flsq_ctx* c, const flsq_basis* base, const double* L, const f
   // T2: the operator itself, a quarter period on; its forms carry the x_ip row weights
   std::vector<double> s3((size_t)d * K), s4((size_t)d * K);
   {
-    System T2;
+    System& T2 = c->aux;
     CHECK_ERR(build_system(c, T2, &bs, blocks, n_blocks, false));
     CHECK_ERR(shift_phase(c, T2, 0.5 * M_PI));
     CHECK_ERR(row_pass(c, T2.pass(), nullptr, V, K, nullptr, 1.0, 0.0, Y));
@@ -2048,7 +2066,7 @@ Err bandwidth_impl(flsq_ctx* c, const flsq_basis* base, const double* L, const f
       rows[i].op.terms = terms[i].data();
       rows[i].op.n_terms = (int32_t)terms[i].size();
     }
-    System T1;
+    System& T1 = c->aux;
     CHECK_ERR(build_system(c, T1, &bs, rows.data(), n_blocks, false));
     CHECK_ERR(shift_phase(c, T1, 0.5 * M_PI));
     CHECK_ERR(row_pass(c, T1.pass(), nullptr, V, K, nullptr, 1.0, 0.0, Y));
