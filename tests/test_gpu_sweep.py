@@ -114,3 +114,17 @@ def test_sweep_second_pass_refactor(sweep, second_pass):
     else:
         assert info.refine_iters >= 20, info.as_dict()
     F.free()
+
+
+def test_sweep_one_call_solve_takes_second_pass(sweep):
+    """flsq_solve_linear on the first data set: the shifted first factor triggers the second pass
+    inside the one-call solver, the refinement needs a few steps, and u matches the oracle."""
+    torch, fl = require_gpu()
+    prob, dp, gold = sweep
+    beta = torch.empty(prob.n_feat, dtype=torch.float64, device="cuda")
+    st, info = fl.flsq_solve_linear(context(), dp.basis, dp.rows, fl.solve_opts(prob.mu, 3, 60, 1e-12), beta)
+    d = info.as_dict()
+    assert d["chol_retries"] >= 1 and d["second_pass"] == 1, d
+    assert d["refine_iters"] <= 8, d
+    u = _u_cols(fl, torch, context(), dp, prob, beta[:, None])[:, 0]
+    assert rel_l2(u, gold["u_test"][:, 0]) <= 1e-7, (rel_l2(u, gold["u_test"][:, 0]), d)
