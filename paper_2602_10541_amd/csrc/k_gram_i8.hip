@@ -337,8 +337,79 @@ hipError_t launch_gram_i8(const I8GemmJob& J, hipStream_t s) {
   return hipGetLastError();
 }
 
+// The same reconstruction for the library's fixed set of 13 moduli, with every modulus,
+// reciprocal and Garner inverse a compile-time constant: the generic kernel reads the 78
+// inverses from its arguments through scalar loads between the dependent multiply-adds.
+// The arithmetic (operations, operands and their order) is the generic kernel's.
+constexpr int kCrtMods[13] = {255, 253, 251, 247, 241, 239, 233, 229, 227, 223, 217, 211, 199};
+
+struct CrtInv {
+  int v[13][13];
+};
+constexpr CrtInv crt_inverses() {
+  CrtInv t{};
+  for (int a = 0; a < 13; ++a)
+    for (int k = a + 1; k < 13; ++k)
+      for (int x = 1; x < kCrtMods[k]; ++x)
+        if ((kCrtMods[a] % kCrtMods[k]) * x % kCrtMods[k] == 1) {
+          t.v[a][k] = x;
+          break;
+        }
+  return t;
+}
+constexpr CrtInv kCrtInv = crt_inverses();
+
+template <int K, int M>
+__device__ __forceinline__ float crt_inner(float x, const float (&v)[13]) {
+  if constexpr (M < K) {
+    constexpr float pk = (float)kCrtMods[K];
+    constexpr float ipk = 1.0f / pk;
+    constexpr float ci = (float)kCrtInv.v[M][K];
+    return crt_inner<K, M + 1>(bal_modf((x - v[M]) * ci, pk, ipk), v);
+  } else {
+    return x;
+  }
+}
+
+template <int K>
+__device__ __forceinline__ void crt_digits(float (&v)[13], const int (&g)[13]) {
+  constexpr double p = (double)kCrtMods[K];
+  constexpr double ip = 1.0 / p;
+  v[K] = crt_inner<K, 0>((float)bal_mod_f64(g[K], p, ip), v);
+  if constexpr (K + 1 < 13) crt_digits<K + 1>(v, g);
+}
+
+__global__ void k_i8_crt13(I8CrtJob J) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (l >= J.n || l < j) return;
+  const int ti = j / kI8Tile, tj = l / kI8Tile;
+  const int tile = ti * J.nt - ti * (ti - 1) / 2 + (tj - ti);
+  const int64_t e = (int64_t)tile * (kI8Tile * kI8Tile) + (j % kI8Tile) * kI8Tile + (l % kI8Tile);
+  const int64_t tstride = (int64_t)J.n_tiles * (kI8Tile * kI8Tile);
+  int g[13];
+#pragma unroll
+  for (int k = 0; k < 13; ++k) g[k] = J.Gt[k * tstride + e];
+  float v[13];
+  crt_digits<0>(v, g);
+  double X = 0.0;
+#pragma unroll
+  for (int k = 12; k >= 0; --k) X = fma(X, (double)kCrtMods[k], (double)v[k]);
+  double gv = X * J.scale[j] * J.scale[l];
+  if (j == l) gv += J.diag_add;
+  J.G[(int64_t)j * J.n + l] = gv;
+  if (J.mirror && j != l) J.G[(int64_t)l * J.n + j] = gv;
+}
+
 hipError_t launch_i8_crt(const I8CrtJob& J, hipStream_t s) {
-  hipLaunchKernelGGL(k_i8_crt, dim3((J.n + 255) / 256, J.n), dim3(256), 0, s, J);
+  bool fixed = J.M.n_mod == 13;
+  for (int t = 0; fixed && t < 13; ++t) fixed = J.M.ip[t] == kCrtMods[t];
+  for (int a = 0; fixed && a < 13; ++a)
+    for (int k = a + 1; k < 13; ++k) fixed = fixed && J.M.cinv[a][k] == kCrtInv.v[a][k];
+  if (fixed)
+    hipLaunchKernelGGL(k_i8_crt13, dim3((J.n + 255) / 256, J.n), dim3(256), 0, s, J);
+  else
+    hipLaunchKernelGGL(k_i8_crt, dim3((J.n + 255) / 256, J.n), dim3(256), 0, s, J);
   return hipGetLastError();
 }
 
