@@ -92,14 +92,15 @@ __device__ __forceinline__ void potrf64_factor(f64x4 acc[4], double* G, int n, i
       if (lane == 0 && bad >= 0 && *sbad < 0) *sbad = bad;
     }
     __syncthreads();
-    if (g + 1 < kNb / 4 && q >= q0) {
-      // rows below the group: tile (q, c) -= U_{L..L+3, rows}^T U_{L..L+3, cols}; rows of the
-      // owner wave at or above the group get a zero operand and stay as they are
+    if (g + 1 < kNb / 4) {
+      // rows below the group: tile (q, c) -= U_{L..L+3, rows}^T U_{L..L+3, cols}.  Rows at or
+      // above the group (all of a wave above the owner) get a zero operand and stay as they
+      // are; tiles below the diagonal (c < q) are never read.  Every wave issues the same four
+      // products with no branch, which keeps the accumulators in place across the loop.
       const double ar = S[(L + k4) * kNb + 16 * q + r16];
       const double a_op = (16 * q + r16 > L + 3) ? -ar : 0.0;
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
-        if (c < q) continue;   // below the diagonal: never read
         const double b_op = S[(L + k4) * kNb + 16 * c + r16];
         acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_op, b_op, acc[c], 0, 0, 0);
       }
@@ -261,14 +262,14 @@ __global__ __launch_bounds__(256, 1) void k_syrk_potrf(double* G, int n, int k0,
     potrf64_load(G, n, k1, acc);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
+    // all four tiles of every wave, with no branch: tiles below the diagonal (c < wave) take
+    // the update too and are never read
 #pragma unroll 4
     for (int kk = 0; kk < kNb / 4; ++kk) {
       const double a = -sP[(kk * 8 + wave) * 64 + lane];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        if (c < wave) continue;
+      for (int c = 0; c < 4; ++c)
         acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, sP[(kk * 8 + c) * 64 + lane], acc[c], 0, 0, 0);
-      }
     }
     potrf64_factor(acc, G, n, k1, info, smem_d + kSyrkPanel, (int*)(smem_d + kSyrkPanel + kNb * kNb));
     return;
@@ -280,13 +281,29 @@ __global__ __launch_bounds__(256, 1) void k_syrk_potrf(double* G, int n, int k0,
   double* sPb = (ti == tj) ? smem_d : smem_d + kSyrkPanel;
   syrk_fetch_panel(G, n, k0, k1 + ti * 128, sPa, wave, lane);
   if (ti != tj) syrk_fetch_panel(G, n, k0, k1 + tj * 128, sPb, wave, lane);
-  __builtin_amdgcn_s_waitcnt(0);   // this wave's loads have landed in LDS
-  __syncthreads();
   const int i0 = k1 + ti * 128 + qi * 64, j0 = k1 + tj * 128 + qj * 64;
   // quadrant (0, 0) of tile (0, 0) is the next diagonal block (workgroup 0)
   const bool active = !(ti == tj && qi > qj) && !(ti == 0 && tj == 0 && qi == 0 && qj == 0) && i0 < n && j0 < n;
+  const int r16 = lane & 15, k4 = lane >> 4;
+  // the 64 old values of the quadrant go out together with the panel loads, so their memory
+  // round trip overlaps the panels' instead of following the products (nothing else in this
+  // launch writes them: workgroup 0 owns only quadrant (0, 0) of tile (0, 0))
+  double old[4][4][4];
   if (active) {
-    const int r16 = lane & 15, k4 = lane >> 4;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = i0 + 16 * r + 4 * v + k4;
+          const int j = j0 + 16 * c + r16;
+          old[r][c][v] = (i < n && j < n && j >= i) ? G[(int64_t)i * n + j] : 0.0;
+        }
+  }
+  __builtin_amdgcn_s_waitcnt(0);   // this wave's loads have landed in LDS
+  __syncthreads();
+  if (active) {
     f64x4 acc[4][4];
 #pragma unroll
     for (int r = 0; r < 4; ++r)
@@ -305,19 +322,6 @@ __global__ __launch_bounds__(256, 1) void k_syrk_potrf(double* G, int n, int k0,
 #pragma unroll
         for (int c = 0; c < 4; ++c) acc[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[r], b[c], acc[r][c], 0, 0, 0);
     }
-    // read all 64 old values first: interleaved loads and stores to G would be kept in
-    // program order (they may alias) and each load would wait out a full memory round trip
-    double old[4][4][4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-      for (int c = 0; c < 4; ++c)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int i = i0 + 16 * r + 4 * v + k4;
-          const int j = j0 + 16 * c + r16;
-          old[r][c][v] = (i < n && j < n && j >= i) ? G[(int64_t)i * n + j] : 0.0;
-        }
 #pragma unroll
     for (int r = 0; r < 4; ++r)
 #pragma unroll
