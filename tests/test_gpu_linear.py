@@ -104,6 +104,27 @@ def test_gram_matches_oracle(prec):
         assert rel_l2(c.cpu().numpy(), cref) <= 1e-13
 
 
+@pytest.mark.parametrize("n_int,n_bc", [(40, 10), (150, 40), (300, 83)])
+def test_int8_gram_few_row_blocks(n_int, n_bc):
+    """INT8_CRT Gram with 2, 4 and 6 K blocks of 64 rows (rows padded to a multiple of 128):
+    fewer blocks than the load ring has slots, so the pipeline's refills past the last block
+    are all that fill some slots; two 256-feature tiles with a ragged tail."""
+    torch, fl = require_gpu()
+    ctx = context()
+    prob = wl.poisson(2, 300, 3.0, n_int, n_bc, seed=9, name="p2few", n_test=10)
+    dp = _dev(prob)
+    N = prob.n_feat
+    G = torch.empty((N, N), dtype=torch.float64, device="cuda")
+    c = torch.empty(N, dtype=torch.float64, device="cuda")
+    fl.flsq_gram(ctx, dp.basis, dp.rows, 3, G, c)
+    A, r = oracle.assemble_system(prob)
+    Gref = A.T @ A
+    Gg = G.cpu().numpy()
+    assert np.linalg.norm(Gg - Gref) / np.linalg.norm(Gref) <= 5e-13
+    np.testing.assert_allclose(Gg, Gg.T, rtol=0, atol=0)
+    assert rel_l2(c.cpu().numpy(), A.T @ r) <= 1e-13
+
+
 def _solve(dp, prob, prec=0, max_refine=10, tol=1e-12):
     torch, fl = require_gpu()
     ctx = context()
