@@ -39,8 +39,15 @@ def gram_flops(P, N):
     return float(P) * N * (N + 1)
 
 
-def int8_gram_ops(P, N):
-    """Algorithmic int8 operations of the residue Gram: per modulus the upper triangle, 2 P N (N + 1) / 2."""
+def method_gram_flops(P, N):
+    """The method's own work in the Gram step: the upper-triangle product A^T A (diagonal included)
+    plus A^T rhs, P N (N + 1) + 2 P N.  Each product of the method counts once, however many
+    hardware operations the arithmetic that carries it out takes."""
+    return float(P) * N * (N + 1) + 2.0 * P * N
+
+
+def int8_emulation_ops(P, N):
+    """Hardware int8 operations the exact residue Gram issues: the upper triangle once per modulus."""
     return float(N_MODULI) * P * N * (N + 1)
 
 
@@ -73,32 +80,81 @@ def householder_flops(m, n):
     return 2.0 * m * n * n - 2.0 * n ** 3 / 3.0
 
 
-def cpu_baseline(prob, rows_int=12288, rows_bc=3072):
-    """The CPU oracle on a bounded sample: all N features, the first rows of each block.
-
-    Sampled time is scaled to the full workload by the Householder flop count of the
-    augmented QR (solve) and by the row count (assembly).
-    """
+def cpu_baseline(prob):
+    """The CPU oracle timed on the full 6D Poisson solve (explicit assembly of the 40960 x 4096
+    matrix + Householder QR of the 45056 x 4096 augmented matrix) on all host cores, and the 2D
+    Poisson solve (N = 500, 2400 rows) on one core, the paper's single-core setting."""
     import oracle
     from paper_2602_10541_amd import workloads as wl
-    blocks = [wl.Block(b.name, b.x[:n], b.terms, b.weight, b.rhs[:n])
-              for b, n in zip(prob.blocks, (rows_int, rows_bc))]
-    sub = wl.Problem(prob.name, prob.d, prob.n_feat, prob.W, prob.b, blocks, prob.mu)
+    cores = os.cpu_count() or 1
+    oracle.set_num_threads(cores)
     t = {}
-    oracle.solve_linear(sub, t)
-    Ps = rows_int + rows_bc
-    P = prob.n_rows
-    N = prob.n_feat
-    est = t["assemble_s"] * P / Ps + t["solve_s"] * householder_flops(P + N, N) / householder_flops(Ps + N, N)
+    t0 = time.perf_counter()
+    oracle.solve_linear(prob, t)
+    full = time.perf_counter() - t0
+    P, N = prob.n_rows, prob.n_feat
+    p1 = wl.config("poisson2d")
+    oracle.set_num_threads(1)
+    t1 = {}
+    t0 = time.perf_counter()
+    oracle.solve_linear(p1, t1)
+    one = time.perf_counter() - t0
+    oracle.set_num_threads(cores)
     return {
-        "value": 1.0 / est, "unit": "solves/s", "cores": oracle.num_threads(), "kind": "oracle",
+        "value": 1.0 / full, "unit": "solves/s", "cores": cores, "kind": "oracle",
         "host_cpu": host_cpu_model(),
-        "sample": (f"oracle solve (explicit assembly + Householder QR of [A; sqrt(mu) I]) on the first {rows_int} "
-                   f"interior + {rows_bc} boundary rows with all {N} features: assemble {t['assemble_s']:.2f} s, "
-                   f"QR {t['solve_s']:.2f} s; scaled to {P} rows by row count (assembly) and Householder flops (QR)"),
-        "entries_per_s": Ps * N / t["assemble_s"],
-        "est_full_solve_s": est,
+        "sample": (f"the full 6D Poisson solve, timed: explicit assembly of all {P} x {N} entries "
+                   f"({t['assemble_s']:.2f} s) + Householder QR of [A; sqrt(mu) I] ({t['solve_s']:.2f} s)"),
+        "s_per_solve": full,
+        "entries_per_s": P * N / t["assemble_s"],
+        "qr_gflop_s": householder_flops(P + N, N) / t["solve_s"] / 1e9,
+        "poisson2d_one_core": {"s_per_solve": one, "assemble_s": t1["assemble_s"], "qr_s": t1["solve_s"],
+                               "workload": "2D Poisson, N=500, 2000 + 400 rows", "cores": 1},
     }
+
+
+def recorded_oracle_times():
+    """Oracle timings recorded when the stored reference values were generated (tests/golden): the
+    3D + t heat solve, the reaction-diffusion Newton steps on one core, the inverse fit's 200 Adam
+    steps.  They were taken on the generating host, named with each."""
+    out = {}
+    g = _gold("heat4d")
+    if g is not None and "solve_s" in g:
+        out["heat4d_solve"] = {"assemble_s": float(g["assemble_s"]), "qr_s": float(g["solve_s"]),
+                               "threads": int(g["threads"])}
+    g = _gold("reaction2d_timing")
+    if g is not None:
+        out["reaction2d_one_core"] = {k: float(g[k]) for k in g.files if k != "host"}
+        out["reaction2d_one_core"]["host"] = str(g["host"])
+    g = _gold("inverse3d_adam")
+    if g is not None:
+        out["inverse3d_adam_200"] = {"factor_s": float(g["factor_s"]), "steps_s": float(g["run_s"]),
+                                     "threads": int(g["threads"])}
+    return out
+
+
+def pde_residual_rel(fl, ctx, dp, prob, beta):
+    """The PDE residual on the test set: interior operator (plus the nonlinearity, if any) of the
+    returned solution minus the data at the 5000 test points, each D^alpha u_N from the library's
+    FP64 evaluation; its 2-norm relative to the exact solution's operator values there."""
+    import torch
+    terms = prob.blocks[0].terms
+    zero = tuple([0] * prob.d)
+    alphas = [a for _, a in terms] + [zero]
+    xq = torch.tensor(prob.x_test, dtype=torch.float64, device="cuda")
+    ev = torch.empty((xq.shape[0], len(alphas)), dtype=torch.float64, device="cuda")
+    fl.flsq_evaluate(ctx, dp.basis, beta, xq, alphas, ev)
+    v = ev.cpu().numpy()
+    r = v[:, :-1] @ np.array([c for c, _ in terms])
+    if prob.nonlin_block == 0:
+        r = r + sum(c * v[:, -1] ** k for k, c in enumerate(prob.nonlin_poly))
+    r = r - prob.extras["f_test"]
+    return float(np.linalg.norm(r) / np.linalg.norm(prob.extras["residual_scale_test"]))
+
+
+def oracle_pde_residual_rel(cfg):
+    g = _gold("pde_residuals")
+    return float(g[f"{cfg}_rel"]) if g is not None else None
 
 
 def time_path(fl, ctx, dp, prob, prec, steps, warmup, max_refine, xq):
@@ -122,6 +178,7 @@ def time_path(fl, ctx, dp, prob, prec, steps, warmup, max_refine, xq):
               ("t_gram_kernel_ms", "t_gram_ms", "t_chol_ms", "t_refine_ms", "t_total_ms")}
     per = [i["t_total_ms"] for i in infos]
     return {"dt": dt, "steps": steps, "status": int(st), "u": u[:, 0].cpu().numpy(), "phases_ms": phases,
+            "pde_residual_rel": pde_residual_rel(fl, ctx, dp, prob, beta),
             "refine_iters": int(infos[-1]["refine_iters"]), "shift": float(infos[-1]["shift"]),
             "ms_median": float(np.median(per)), "ms_min": float(np.min(per))}
 
@@ -177,11 +234,12 @@ def bench_c1(fl, ctx, steps=20):
     res = {"workload": "poisson_2d: N=500 (sigma=3), 2000 interior + 400 boundary rows, mu=1e-10"}
     for name, prec in (("int8_crt", fl.PREC_INT8_CRT), ("fp64", fl.PREC_FP64)):
         r = time_path(fl, ctx, dp, prob, prec, steps, 3, 30, xq)
-        e = {"rel_l2_vs_exact": float(np.linalg.norm(r["u"] - prob.u_test) / np.linalg.norm(prob.u_test))}
+        e = {"rel_l2_vs_exact": float(np.linalg.norm(r["u"] - prob.u_test) / np.linalg.norm(prob.u_test)),
+             "pde_residual_rel": r["pde_residual_rel"], "oracle_pde_residual_rel": oracle_pde_residual_rel("poisson2d")}
         if gold is not None:
             e["rel_l2_vs_oracle"] = float(np.linalg.norm(r["u"] - gold["u_test"]) / np.linalg.norm(gold["u_test"]))
         res[name] = {"us_per_solve": 1e6 * r["dt"] / r["steps"], "solves_per_s": r["steps"] / r["dt"],
-                     "accuracy": e, "refine_iters": r["refine_iters"]}
+                     "accuracy": e, "refine_iters": r["refine_iters"], "status": r["status"]}
     return res
 
 
@@ -198,7 +256,8 @@ def bench_c4(fl, ctx, steps=2):
                        "65536 interior + 16384 initial + 16384 boundary rows, mu=1e-10"}
     for name, prec in (("int8_crt", fl.PREC_INT8_CRT), ("fp64", fl.PREC_FP64)):
         r = time_path(fl, ctx, dp, prob, prec, steps, 1, 30, xq)
-        e = {"rel_l2_vs_exact": float(np.linalg.norm(r["u"] - prob.u_test) / np.linalg.norm(prob.u_test))}
+        e = {"rel_l2_vs_exact": float(np.linalg.norm(r["u"] - prob.u_test) / np.linalg.norm(prob.u_test)),
+             "pde_residual_rel": r["pde_residual_rel"], "oracle_pde_residual_rel": oracle_pde_residual_rel("heat4d")}
         if gold is not None:
             e["rel_l2_vs_oracle"] = float(np.linalg.norm(r["u"] - gold["u_test"]) / np.linalg.norm(gold["u_test"]))
         res[name] = {"ms_per_solve": 1e3 * r["dt"] / r["steps"], "ms_median": r["ms_median"], "ms_min": r["ms_min"],
@@ -288,7 +347,9 @@ def bench_c3(fl, ctx):
         u = torch.empty((xq.shape[0], 1), dtype=torch.float64, device="cuda")
         fl.flsq_evaluate(ctx, dp.basis, beta, xq, [(0, 0)], u)
         u = u[:, 0].cpu().numpy()
-        e = {"rel_l2_vs_exact": float(np.linalg.norm(u - prob.u_test) / np.linalg.norm(prob.u_test))}
+        e = {"rel_l2_vs_exact": float(np.linalg.norm(u - prob.u_test) / np.linalg.norm(prob.u_test)),
+             "pde_residual_rel": pde_residual_rel(fl, ctx, dp, prob, beta),
+             "oracle_pde_residual_rel": oracle_pde_residual_rel("reaction2d")}
         if gold is not None:
             e["rel_l2_vs_oracle"] = float(np.linalg.norm(u - gold["u_test"]) / np.linalg.norm(gold["u_test"]))
         res[name] = {"ms_total": 1e3 * dt, "newton_steps": len(steps), "ms_per_step": 1e3 * dt / max(1, len(steps) + 1),
@@ -570,16 +631,19 @@ def main():
     gold_path = os.path.join(ROOT, "tests", "golden", "poisson6d.npz")
     gold = np.load(gold_path) if os.path.exists(gold_path) else None
 
-    def err(u):
-        e = {"rel_l2_vs_exact": float(np.linalg.norm(u - prob.u_test) / np.linalg.norm(prob.u_test))}
+    def err(r):
+        u = r["u"]
+        e = {"rel_l2_vs_exact": float(np.linalg.norm(u - prob.u_test) / np.linalg.norm(prob.u_test)),
+             "pde_residual_rel": r["pde_residual_rel"], "oracle_pde_residual_rel": oracle_pde_residual_rel("poisson6d")}
         if gold is not None:
             e["rel_l2_vs_oracle"] = float(np.linalg.norm(u - gold["u_test"]) / np.linalg.norm(gold["u_test"]))
         return e
 
     mix = time_path(fl, ctx, dp, prob, fl.PREC_INT8_CRT, args.steps, args.warmup, 30, xq)
     k8 = mix["phases_ms"]["t_gram_kernel_ms"]
-    ops8 = int8_gram_ops(P, N)
-    ach8 = ops8 / (k8 * 1e-3) / 1e12
+    work8 = method_gram_flops(P, N)
+    ach8 = work8 / (k8 * 1e-3) / 1e12
+    emu8 = int8_emulation_ops(P, N)
     out = {
         "metric": METRIC,
         "value": mix["steps"] / mix["dt"],
@@ -600,12 +664,20 @@ def main():
                    "n_feat": N, "n_rows": P,
                    "path": "int8-MFMA Gram of exact residues (13 moduli, CRT to FP64) + FP64 Cholesky + CGLS"},
         "entries_per_s": P * N / (mix["phases_ms"]["t_gram_ms"] * 1e-3),
-        "accuracy": err(mix["u"]),
+        "accuracy": err(mix),
         "status": mix["status"],
         "phases_ms": mix["phases_ms"],
         "refine_iters": mix["refine_iters"],
         "roofline": {"bound": "mfma", "achieved": ach8, "peak": PEAK_INT8_MFMA_TOPS, "unit": "TOP/s",
                      "frac": ach8 / PEAK_INT8_MFMA_TOPS,
+                     "work": "the method's Gram products, P N (N + 1) + 2 P N per launch, each counted once "
+                             "(achieved = that / the kernel's mean duration; peak = dense int8 MFMA)",
+                     "work_per_launch": work8,
+                     "emulation_ops_per_launch": emu8,
+                     "emulation_ops_per_s": emu8 / (k8 * 1e-3),
+                     "emulation_frac_of_int8_peak": emu8 / (k8 * 1e-3) / 1e12 / PEAK_INT8_MFMA_TOPS,
+                     "fp64_mfma_equiv_frac": ach8 / PEAK_FP64_MFMA_TFLOPS,
+                     "fp32_mfma_equiv_frac": ach8 / PEAK_FP32_MFMA_TFLOPS,
                      "traffic": measured_traffic("profiles/k_gram_i8_poisson6d_hbm_traffic.md",
                                                  "paper_2602_10541_amd/csrc/k_gram_i8.hip"),
                      "traffic_source": "profiles/k_gram_i8_poisson6d_hbm_traffic.md (FETCH_SIZE + WRITE_SIZE, "
@@ -613,7 +685,7 @@ def main():
                      "trace_source": "profiles/k_gram_i8_poisson6d_bench_kernel_trace.md (kernel trace of this "
                                      "path at these step counts; mean duration of the timed dispatches)",
                      "kernel": "k_gram_i8 (int8 MFMA residue Gram, 13 moduli)",
-                     "ops_per_launch": ops8, "avg_kernel_ms": k8},
+                     "avg_kernel_ms": k8},
     }
     if not args.skip_fp64:
         f64 = time_path(fl, ctx, dp, prob, fl.PREC_FP64, args.steps, args.warmup, 10, xq)
@@ -621,7 +693,7 @@ def main():
         flops = gram_flops(P, N)
         a64 = flops / (k64 * 1e-3) / 1e12
         out["fp64_path"] = {
-            "solves_per_s": f64["steps"] / f64["dt"], "status": f64["status"], "accuracy": err(f64["u"]),
+            "solves_per_s": f64["steps"] / f64["dt"], "status": f64["status"], "accuracy": err(f64),
             "phases_ms": f64["phases_ms"], "refine_iters": f64["refine_iters"],
             "entries_per_s": P * N / (f64["phases_ms"]["t_gram_ms"] * 1e-3),
             "roofline": {"bound": "mfma", "achieved": a64, "peak": PEAK_FP64_MFMA_TFLOPS, "unit": "TFLOP/s",
@@ -635,7 +707,7 @@ def main():
         k32 = f32["phases_ms"]["t_gram_kernel_ms"]
         a32 = gram_flops(P, N) / (k32 * 1e-3) / 1e12
         out["fp32_mfma_path"] = {
-            "solves_per_s": n32 / f32["dt"], "status": f32["status"], "accuracy": err(f32["u"]),
+            "solves_per_s": n32 / f32["dt"], "status": f32["status"], "accuracy": err(f32),
             "refine_iters": f32["refine_iters"], "shift": f32["shift"], "phases_ms": f32["phases_ms"],
             "entries_per_s": P * N / (f32["phases_ms"]["t_gram_ms"] * 1e-3),
             "gram_tflops": a32, "gram_frac_of_fp32_mfma_peak": a32 / PEAK_FP32_MFMA_TFLOPS,
@@ -645,7 +717,7 @@ def main():
         bf = time_path(fl, ctx, dp, prob, fl.PREC_BF16X3_REFINE, nb, 1, 30, xq)
         kb = bf["phases_ms"]["t_gram_kernel_ms"]
         out["bf16x3_path"] = {
-            "solves_per_s": nb / bf["dt"], "status": bf["status"], "accuracy": err(bf["u"]),
+            "solves_per_s": nb / bf["dt"], "status": bf["status"], "accuracy": err(bf),
             "refine_iters": bf["refine_iters"], "shift": bf["shift"], "phases_ms": bf["phases_ms"],
             "entries_per_s": P * N / (bf["phases_ms"]["t_gram_ms"] * 1e-3),
             "gram_fp32_equiv_tflops": gram_flops(P, N) / (kb * 1e-3) / 1e12,
@@ -663,6 +735,7 @@ def main():
         out["row_coefficients"] = bench_varcoef(fl, ctx)
     if not args.skip_cpu:
         out["cpu_baseline"] = cpu_baseline(prob)
+        out["cpu_baseline"]["recorded"] = recorded_oracle_times()
         if "learnable_bandwidth" in out:
             out["learnable_bandwidth"]["cpu_oracle"] = cpu_bandwidth_baseline()
         if "row_coefficients" in out:

@@ -156,8 +156,8 @@ flsq_status flsq_gram(flsq_ctx* ctx, const flsq_basis* basis, const flsq_rows* b
 flsq_status flsq_solve_linear(flsq_ctx* ctx, const flsq_basis* basis, const flsq_rows* blocks, int32_t n_blocks,
                               const flsq_solve_opts* opts, double* beta_out, flsq_solve_info* info);
 
-/* Factor object (Section 2.5: "gradients flow through the pre-factored linear solve";
- * the inverse application factors once and reuses the factor for every right-hand side).
+/* Factor object (Section 2.5): one factorisation reused for every right-hand side and every
+ * adjoint solve of the same system, as in the inverse application.
  * Copies the basis and block geometry to the device; the caller's arrays may be freed after. */
 flsq_status flsq_factorize(flsq_ctx* ctx, const flsq_basis* basis, const flsq_rows* blocks, int32_t n_blocks,
                            const flsq_solve_opts* opts, flsq_factor** F, flsq_solve_info* info);

@@ -54,8 +54,14 @@ def _load():
         lib.orc_evaluate.restype = None
         lib.orc_tikhonov.argtypes = [C.c_int64, C.c_int, dp, C.c_int, dp, C.c_double, dp, dp]
         lib.orc_tikhonov.restype = C.c_int
+        lib.orc_qr_factor.argtypes = [C.c_int64, C.c_int, dp, C.c_double, dp, dp, dp]
+        lib.orc_qr_factor.restype = C.c_int
+        lib.orc_qr_solve.argtypes = [C.c_int64, C.c_int, dp, dp, dp, C.c_int, dp, dp]
+        lib.orc_qr_solve.restype = C.c_int
         lib.orc_trisolve.argtypes = [C.c_int, dp, C.c_int, dp, C.c_int]
         lib.orc_trisolve.restype = None
+        lib.orc_set_num_threads.argtypes = [C.c_int]
+        lib.orc_set_num_threads.restype = None
         lib.orc_num_threads.argtypes = []
         lib.orc_num_threads.restype = C.c_int
         _lib = lib
@@ -76,6 +82,11 @@ def _f64(a):
 
 def num_threads() -> int:
     return int(_load().orc_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """OpenMP threads for the oracle's later calls (timing runs on one core or on all)."""
+    _load().orc_set_num_threads(int(n))
 
 
 def _terms(terms, d):
@@ -150,6 +161,34 @@ def tikhonov(A, rhs, mu, return_r=False):
         raise np.linalg.LinAlgError(f"orc_tikhonov status {st}")
     out = beta[:, 0] if vec else beta
     return (out, R) if return_r else out
+
+
+class QRFactor:
+    """The Householder QR of [A; sqrt(mu) I] computed once, for a matrix whose data change while
+    the matrix stays (Section 2.5: the inverse application factors once).  ``solve(rhs)`` returns
+    the same bits as ``tikhonov(A, rhs, mu)``; ``R`` satisfies R^T R = A^T A + mu I."""
+
+    def __init__(self, A, mu):
+        A = _f64(A)
+        self.m, self.n = A.shape
+        rows = self.m + self.n
+        self.V = np.zeros(rows * self.n)
+        self.tau = np.empty(self.n)
+        self.R = np.empty((self.n, self.n))
+        st = _load().orc_qr_factor(self.m, self.n, _d(A), float(mu), _d(self.V), _d(self.tau), _d(self.R))
+        if st != 0:
+            raise np.linalg.LinAlgError(f"orc_qr_factor status {st}")
+
+    def solve(self, rhs):
+        rhs = _f64(rhs)
+        vec = rhs.ndim == 1
+        Y = _f64(rhs.reshape(self.m, -1))
+        k = Y.shape[1]
+        beta = np.empty((self.n, k))
+        st = _load().orc_qr_solve(self.m, self.n, _d(self.V), _d(self.tau), _d(self.R), k, _d(Y), _d(beta))
+        if st != 0:
+            raise np.linalg.LinAlgError(f"orc_qr_solve status {st}")
+        return beta[:, 0] if vec else beta
 
 
 def trisolve(R, Y, transpose=False):
@@ -315,7 +354,8 @@ class InverseOracle:
         Ak = np.zeros_like(self.A)
         Ak[:n_int] = assemble(p.W, p.b, blocks[0].x, lap_only, blocks[0].weight, p.normalize)
         self.A_kappa = Ak
-        _, self.R = tikhonov(self.A, np.zeros(self.A.shape[0]), p.mu, return_r=True)
+        self.qr = QRFactor(self.A, p.mu)
+        self.R = self.qr.R
         self.H = assemble(p.W, p.b, p.extras["x_obs"], [(1.0, tuple([0] * d))], 1.0, p.normalize)
 
     def rhs(self, thetas):
@@ -339,8 +379,7 @@ class InverseOracle:
         """Per hypothesis: L_h = mean_k (H beta_h - d)_k^2, dL_h/dtheta_h (4), dL_h/dkappa."""
         thetas = np.atleast_2d(_f64(thetas))
         Rhs, dR = self.rhs(thetas)
-        B = tikhonov(self.A, Rhs, self.prob.mu)                  # N x K, same QR as R
-        B = B.reshape(self.A.shape[1], -1)
+        B = self.qr.solve(Rhs)                                  # N x K, the QR that gave R
         U = self.H @ B                                          # n_obs x K
         res = U - self.data[:, None]
         n_obs = U.shape[0]
@@ -360,8 +399,67 @@ class InverseOracle:
             return other.loss(thetas)
         thetas = np.atleast_2d(_f64(thetas))
         Rhs, _ = self.rhs(thetas)
-        B = tikhonov(self.A, Rhs, self.prob.mu).reshape(self.A.shape[1], -1)
+        B = self.qr.solve(Rhs)
         return np.mean((self.H @ B - self.data[:, None]) ** 2, axis=0)
+
+
+# ---------------------------------------------------------------------------
+# Outer optimisers: Adam (the batched source-parameter fit of the inverse heat-source
+# application) and AdamW (the learnable-bandwidth appendix's hybrid training).  Adam is
+# Kingma and Ba's update with bias correction; AdamW adds Loshchilov and Hutter's
+# decoupled weight decay, applied to the parameters before the Adam step.
+# ---------------------------------------------------------------------------
+
+def adam_update(p, g, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8, weight_decay=0.0, clamp_col=-1, clamp_min=0.0):
+    """One step at step number t >= 1 on arrays p (parameters), m, v (moments), in place:
+    p <- p (1 - lr wd); m <- b1 m + (1 - b1) g; v <- b2 v + (1 - b2) g^2;
+    p <- p - lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps); then, when clamp_col >= 0,
+    p[..., clamp_col] <- max(p[..., clamp_col], clamp_min) (a projection onto w >= w_min)."""
+    if weight_decay:
+        p *= 1.0 - lr * weight_decay
+    m *= b1
+    m += (1.0 - b1) * g
+    v *= b2
+    v += (1.0 - b2) * g * g
+    p -= lr * (m / (1.0 - b1 ** t)) / (np.sqrt(v / (1.0 - b2 ** t)) + eps)
+    if clamp_col >= 0:
+        col = p[..., clamp_col]
+        np.maximum(col, clamp_min, out=col)
+    return p
+
+
+def adam_run(grad_fn, p0, steps, lr, b1=0.9, b2=0.999, eps=1e-8, weight_decay=0.0, clamp_col=-1, clamp_min=0.0):
+    """``steps`` Adam(W) steps from p0 with gradients ``grad_fn(p) -> (loss, grad)``.
+    Returns the parameters at the start of every step (steps x shape(p0)), the losses there,
+    and the final parameters."""
+    p = np.array(p0, dtype=np.float64, copy=True)
+    m = np.zeros_like(p)
+    v = np.zeros_like(p)
+    hist_p, hist_l = [], []
+    for t in range(1, steps + 1):
+        loss, g = grad_fn(p)
+        hist_p.append(p.copy())
+        hist_l.append(np.array(loss, dtype=np.float64, copy=True))
+        adam_update(p, _f64(g), m, v, t, lr, b1, b2, eps, weight_decay, clamp_col, clamp_min)
+    return np.array(hist_p), np.array(hist_l), p
+
+
+def adamw_sigma(grad_fn, sigma0, steps=80, lr=0.1, b1=0.9, b2=0.999, eps=1e-8, wd=0.01):
+    """AdamW on the scalar bandwidth sigma (L = sigma I), ``grad_fn(sigma) -> (loss, dloss/dsigma)``;
+    returns the sigma at each step's start and the loss there."""
+    hist_p, hist_l, _ = adam_run(lambda p: (lambda lo, g: (lo, np.array([g])))(*grad_fn(float(p[0]))),
+                                 np.array([float(sigma0)]), steps, lr, b1, b2, eps, weight_decay=wd)
+    return hist_p[:, 0], hist_l
+
+
+def inverse_adam(orc, theta0, steps=200, lr=1e-2, w_min=0.02):
+    """The inverse heat-source fit: every hypothesis' theta = (a, c_x, c_y, w) follows Adam on its
+    own misfit with the oracle's gradient, w kept >= w_min.  Returns (thetas at each step's start,
+    losses there, final thetas)."""
+    def gfn(th):
+        loss, g, _, _ = orc.loss_and_grad(th)
+        return loss, g
+    return adam_run(gfn, theta0, steps, lr, clamp_col=3, clamp_min=w_min)
 
 
 # ---------------------------------------------------------------------------

@@ -15,6 +15,13 @@
  *                     (the Tikhonov least-squares problem of Section 2.4, the
  *                     least-squares solve of Algorithm 1 / Section 2.3 "via QR"),
  *                     computed by unpivoted Householder QR of [A; sqrt(mu) I].
+ *   orc_qr_factor  -- the same Householder QR of [A; sqrt(mu) I], keeping the
+ *   orc_qr_solve      reflectors, and the same minimiser for right-hand sides
+ *                     supplied later (a system whose matrix stays fixed while
+ *                     its data change, as in the inverse application of
+ *                     Section 2.5): the reflectors reach each right-hand side in
+ *                     the order and arithmetic of orc_tikhonov, so both give the
+ *                     same bits.
  *   orc_trisolve   -- forward / backward substitution with an upper-triangular R
  *                     (used for R^T R = A^T A + mu I in the adjoint).
  *
@@ -198,6 +205,101 @@ int orc_tikhonov(int64_t m, int n, const double* A, int k, const double* rhs, do
 }
 
 /*
+ * Householder QR of [A; sqrt(mu) I] with the reflectors kept (the loop of
+ * orc_tikhonov without right-hand sides).  V (rows x n, column-major, rows =
+ * m + n) receives v_j in V[j * rows + j .. j * rows + rows - 1]; tau[j] = 2 / v_j^T v_j
+ * (0 where column j had nothing to annihilate); R_out the n x n factor
+ * (row-major, zeros below the diagonal).  Returns 0, 1 on a zero pivot, 2 on
+ * allocation failure.
+ */
+int orc_qr_factor(int64_t m, int n, const double* A, double mu, double* V, double* tau, double* R_out)
+{
+    const int64_t rows = m + n;
+    double* M = (double*)malloc(sizeof(double) * (size_t)rows * (size_t)n);  /* column-major */
+    if (!M) return 2;
+    const double smu = sqrt(mu);
+    for (int c = 0; c < n; ++c) {
+        double* col = M + (int64_t)c * rows;
+        for (int64_t i = 0; i < m; ++i) col[i] = A[i * n + c];
+        for (int i = 0; i < n; ++i) col[m + i] = (i == c) ? smu : 0.0;
+    }
+    for (int j = 0; j < n; ++j) {
+        double* x = M + (int64_t)j * rows;
+        double* v = V + (int64_t)j * rows + j;
+        const int64_t len = rows - j;
+        double nrm2 = 0.0;
+        for (int64_t i = 0; i < len; ++i) nrm2 += x[j + i] * x[j + i];
+        const double alpha = sqrt(nrm2);
+        tau[j] = 0.0;
+        if (alpha == 0.0) continue;
+        const double sgn = (x[j] >= 0.0) ? 1.0 : -1.0;
+        for (int64_t i = 0; i < len; ++i) v[i] = x[j + i];
+        v[0] += sgn * alpha;
+        double vtv = 0.0;
+        for (int64_t i = 0; i < len; ++i) vtv += v[i] * v[i];
+        const double t = 2.0 / vtv;
+        tau[j] = t;
+#pragma omp parallel for schedule(dynamic, 8)
+        for (int c = j + 1; c < n; ++c) {
+            double* col = M + (int64_t)c * rows;
+            double s = 0.0;
+            for (int64_t i = 0; i < len; ++i) s += v[i] * col[j + i];
+            s *= t;
+            for (int64_t i = 0; i < len; ++i) col[j + i] -= s * v[i];
+        }
+        x[j] = -sgn * alpha;
+        for (int64_t i = 1; i < len; ++i) x[j + i] = 0.0;
+    }
+    int status = 0;
+    for (int j = 0; j < n; ++j)
+        if (M[(int64_t)j * rows + j] == 0.0) status = 1;
+    for (int i = 0; i < n; ++i)
+        for (int jj = 0; jj < n; ++jj)
+            R_out[(int64_t)i * n + jj] = (jj >= i) ? M[(int64_t)jj * rows + i] : 0.0;
+    free(M);
+    return status;
+}
+
+/*
+ * beta_out (n x k, row-major) = argmin ||A beta - rhs||^2 + mu ||beta||^2 for rhs (m x k,
+ * row-major) with the reflectors and R of orc_qr_factor: Q^T [rhs; 0] reflector by
+ * reflector, then R beta = (Q^T [rhs; 0])[0:n].  Returns 0, or 2 on allocation failure.
+ */
+int orc_qr_solve(int64_t m, int n, const double* V, const double* tau, const double* R, int k,
+                 const double* rhs, double* beta_out)
+{
+    const int64_t rows = m + n;
+    double* Y = (double*)malloc(sizeof(double) * (size_t)rows * (size_t)k);  /* column-major */
+    if (!Y) return 2;
+    for (int c = 0; c < k; ++c) {
+        double* col = Y + (int64_t)c * rows;
+        for (int64_t i = 0; i < m; ++i) col[i] = rhs[i * k + c];
+        for (int i = 0; i < n; ++i) col[m + i] = 0.0;
+    }
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int c = 0; c < k; ++c) {
+        double* col = Y + (int64_t)c * rows;
+        for (int j = 0; j < n; ++j) {
+            const double t = tau[j];
+            if (t == 0.0) continue;
+            const double* v = V + (int64_t)j * rows + j;
+            const int64_t len = rows - j;
+            double s = 0.0;
+            for (int64_t i = 0; i < len; ++i) s += v[i] * col[j + i];
+            s *= t;
+            for (int64_t i = 0; i < len; ++i) col[j + i] -= s * v[i];
+        }
+        for (int i = n - 1; i >= 0; --i) {
+            double s = col[i];
+            for (int jj = i + 1; jj < n; ++jj) s -= R[(int64_t)i * n + jj] * beta_out[(int64_t)jj * k + c];
+            beta_out[(int64_t)i * k + c] = s / R[(int64_t)i * n + i];
+        }
+    }
+    free(Y);
+    return 0;
+}
+
+/*
  * Triangular solves with an upper-triangular R (n x n row-major), k right-hand
  * sides (n x k row-major), in place:
  *   transpose = 0:  R   x = y   (backward substitution)
@@ -220,6 +322,15 @@ void orc_trisolve(int n, const double* R, int k, double* Y, int transpose)
             }
         }
     }
+}
+
+void orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
 }
 
 int orc_num_threads(void)

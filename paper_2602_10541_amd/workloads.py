@@ -175,8 +175,10 @@ def poisson(d: int, n_feat: int, sigma: float, n_int: int, n_bc: int, seed: int 
         Block("boundary", xb, identity_terms(d), LAM_BC, u(xb)),
     ]
     xt = sample_box(np.random.default_rng(seed + 1), n_test, d)
-    return Problem(name, d, n_feat, W, b, blocks, x_test=xt, u_test=u(xt),
-                   extras={"sigma": sigma, "exact": "prod_k sin(pi x_k)"})
+    ut = u(xt)
+    return Problem(name, d, n_feat, W, b, blocks, x_test=xt, u_test=ut,
+                   extras={"sigma": sigma, "exact": "prod_k sin(pi x_k)", "f_test": d * PI * PI * ut,
+                           "residual_scale_test": d * PI * PI * ut})
 
 
 def reaction_diffusion(n_feat: int = 2048, sigma: float = 5.0, n_int: int = 16384,
@@ -200,9 +202,12 @@ def reaction_diffusion(n_feat: int = 2048, sigma: float = 5.0, n_int: int = 1638
         Block("boundary", xb, identity_terms(d), LAM_BC, u(xb)),
     ]
     xt = sample_box(np.random.default_rng(seed + 1), n_test, d)
-    return Problem("reaction_diffusion_2d", d, n_feat, W, b, blocks, x_test=xt, u_test=u(xt),
+    ut = u(xt)
+    ft = 5 * PI * PI * ut + ut ** 3 - ut
+    return Problem("reaction_diffusion_2d", d, n_feat, W, b, blocks, x_test=xt, u_test=ut,
                    nonlin_poly=(0.0, 0.0, 0.0, 1.0), nonlin_block=0,
-                   extras={"sigma": sigma, "exact": "sin(2 pi x) cos(pi y)"})
+                   extras={"sigma": sigma, "exact": "sin(2 pi x) cos(pi y)", "f_test": ft,
+                           "residual_scale_test": ft})
 
 
 def heat(n_feat: int = 8192, sigma=(3.0, 3.0, 3.0, 1.5), n_int: int = 65536, n_ic: int = 16384,
@@ -232,9 +237,12 @@ def heat(n_feat: int = 8192, sigma=(3.0, 3.0, 3.0, 1.5), n_int: int = 65536, n_i
     xq = None
     if n_query:
         xq = np.random.default_rng(seed + 2).uniform(0.0, 1.0, size=(n_query, d))
-    return Problem("heat_3d_t", d, n_feat, W, b, blocks, x_test=xt, u_test=u(xt),
+    ut = u(xt)
+    return Problem("heat_3d_t", d, n_feat, W, b, blocks, x_test=xt, u_test=ut,
                    extras={"sigma": tuple(sigma), "kappa": kappa, "x_query": xq,
-                           "exact": "exp(-0.3 pi^2 t) prod_k sin(pi x_k)"})
+                           "exact": "exp(-0.3 pi^2 t) prod_k sin(pi x_k)", "f_test": np.zeros(n_test),
+                           # u_t of the exact solution: the size of each of the two balancing terms
+                           "residual_scale_test": -0.3 * PI * PI * ut})
 
 
 def gaussian_source(x: np.ndarray, theta) -> np.ndarray:

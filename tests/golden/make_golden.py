@@ -58,6 +58,72 @@ def inverse(name):
     print(name, "loss0[:4]", loss[:4], flush=True)
 
 
+ADAM_CHECKPOINTS = (0, 1, 2, 5, 10, 20, 50, 100, 150, 199)
+
+
+def inverse_adam(name):
+    """The workload's 200 batched Adam steps (lr 1e-2, w >= 0.02) for all 64 hypotheses on the
+    oracle's gradients, from the stored noisy observations: theta at a few step starts, every
+    loss, the final theta."""
+    prob = wl.config("inverse3d")
+    gold = np.load(os.path.join(OUT, "inverse3d.npz"))
+    t0 = time.time()
+    orc = oracle.InverseOracle(prob, gold["data"])
+    t_fac = time.time() - t0
+    t0 = time.time()
+    hist, losses, final = oracle.inverse_adam(orc, prob.extras["theta0"], steps=200, lr=1e-2, w_min=0.02)
+    t_run = time.time() - t0
+    ck = np.array(ADAM_CHECKPOINTS)
+    np.savez(os.path.join(OUT, f"{name}.npz"), checkpoints=ck, theta_at=hist[ck], losses=losses, theta_final=final,
+             factor_s=np.array(t_fac), run_s=np.array(t_run), threads=np.array(oracle.num_threads()))
+    best = int(np.argmin(losses[-1]))
+    print(name, "best hypothesis", best, final[best], "loss", losses[-1][best], "factor", t_fac, "s, 200 steps",
+          t_run, "s", flush=True)
+
+
+def reaction2d_timing(name):
+    """One-core oracle times of the reaction-diffusion workload (the paper's single-core setting): the
+    linear warm start (assembly + Householder QR) and the first Gauss-Newton step."""
+    prob = wl.config("reaction2d")
+    oracle.set_num_threads(1)
+    t = {}
+    t0 = time.time()
+    beta = oracle.solve_linear(prob, t)
+    warm_s = time.time() - t0
+    t0 = time.time()
+    oracle.solve_newton(prob, max_iter=1, beta0=beta)
+    step_s = time.time() - t0
+    host = "unknown"
+    for line in open("/proc/cpuinfo"):
+        if line.startswith("model name"):
+            host = line.split(":", 1)[1].strip()
+            break
+    np.savez(os.path.join(OUT, f"{name}.npz"), warm_start_s=np.array(warm_s), warm_assemble_s=np.array(t["assemble_s"]),
+             warm_qr_s=np.array(t["solve_s"]), first_newton_step_s=np.array(step_s), threads=np.array(1.0),
+             host=np.array(host))
+    print(name, "warm start", warm_s, "s, first Newton step", step_s, "s, one core of", host, flush=True)
+
+
+def pde_residuals(name):
+    """The PDE residual of the oracle's stored solutions at the test points (the interior operator,
+    plus the nonlinearity where there is one, minus the data), per configuration."""
+    out = {}
+    for cfg in ("poisson2d", "poisson6d", "heat4d", "reaction2d"):
+        g = np.load(os.path.join(OUT, f"{cfg}.npz"))
+        prob = wl.config(cfg)
+        terms = prob.blocks[0].terms
+        r = oracle.apply_operator(prob.W, prob.b, g["beta"], prob.x_test, terms, prob.normalize)
+        if prob.nonlin_block == 0:
+            u = oracle.evaluate(prob.W, prob.b, g["beta"], prob.x_test, [tuple([0] * prob.d)], prob.normalize)[:, 0]
+            r = r + sum(c * u ** k for k, c in enumerate(prob.nonlin_poly))
+        r = r - prob.extras["f_test"]
+        scale = np.linalg.norm(prob.extras["residual_scale_test"])
+        out[f"{cfg}_residual"] = r
+        out[f"{cfg}_rel"] = np.array(np.linalg.norm(r) / scale)
+        print(cfg, "oracle PDE residual on the test set (relative)", float(out[f"{cfg}_rel"]), flush=True)
+    np.savez(os.path.join(OUT, f"{name}.npz"), **out)
+
+
 def sweep(name):
     """All right-hand sides of the sweep from one Householder QR of [A; sqrt(mu) I] (the oracle's
     Tikhonov solve with a matrix right-hand side), u at the test points for each."""
@@ -76,22 +142,6 @@ def sweep(name):
     print(name, "rel err vs exact: max", err.max(), "median", np.median(err), "QR + solve", solve_s, "s", flush=True)
 
 
-def adamw_sigma(grad_fn, sigma0, steps=80, lr=0.1, b1=0.9, b2=0.999, eps=1e-8, wd=0.01):
-    """AdamW (decoupled weight decay) on the scalar bandwidth sigma, L = sigma I; returns the sigma
-    at each step's start and the loss there."""
-    sig, m, v = float(sigma0), 0.0, 0.0
-    sigs, losses = [], []
-    for t in range(1, steps + 1):
-        loss, grad = grad_fn(sig)
-        sigs.append(sig)
-        losses.append(loss)
-        sig -= lr * wd * sig
-        m = b1 * m + (1 - b1) * grad
-        v = b2 * v + (1 - b2) * grad * grad
-        sig -= lr * (m / (1 - b1 ** t)) / (np.sqrt(v / (1 - b2 ** t)) + eps)
-    return np.array(sigs), np.array(losses)
-
-
 def bandwidth(name):
     """Loss and L gradient at sigma0 I and at an anisotropic L, and the 80-step AdamW trajectory of
     the scalar bandwidth (lr 0.1, from sigma0), all from the oracle."""
@@ -107,7 +157,7 @@ def bandwidth(name):
     def gfn(sig):
         lo, g, _ = oracle.bandwidth_loss_and_grad(prob, prob.W, sig * np.eye(prob.d))
         return lo, float(g[diag].sum())
-    sigs, losses = adamw_sigma(gfn, prob.extras["sigma0"])
+    sigs, losses = oracle.adamw_sigma(gfn, prob.extras["sigma0"])
     np.savez(os.path.join(OUT, f"{name}.npz"), loss0=np.array(loss0), grad0=grad0, beta0=beta0, L_aniso=La,
              loss_aniso=np.array(lossa), grad_aniso=grada, adamw_sigma=sigs, adamw_loss=losses,
              eval_s=np.array(eval_s), threads=np.array(oracle.num_threads()))
@@ -164,6 +214,8 @@ def bratu(name):
 
 
 KIND = {"poisson2d": linear, "poisson6d": linear, "heat4d": linear, "reaction2d": newton, "inverse3d": inverse,
+        "inverse3d_adam": inverse_adam, "reaction2d_timing": reaction2d_timing,
+        "pde_residuals": pde_residuals,
         "helmholtz_sweep": sweep, "helmholtz_bandwidth": bandwidth,
         "varcoef2d": varcoef, "burgers1d": burgers, "bratu2d": bratu}
 

@@ -13,7 +13,7 @@ import pytest
 
 import oracle
 from paper_2602_10541_amd import workloads as wl
-from tests.gpu_util import amplitude_bound, context, rel_l2, require_gpu
+from tests.gpu_util import pde_residual, amplitude_bound, context, rel_l2, require_gpu
 
 pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
@@ -125,12 +125,25 @@ def test_int8_gram_few_row_blocks(n_int, n_bc):
     assert rel_l2(c.cpu().numpy(), A.T @ r) <= 1e-13
 
 
-def _solve(dp, prob, prec=0, max_refine=10, tol=1e-12):
+def _solve(dp, prob, prec=0, max_refine=10, tol=1e-12, keep=None):
     torch, fl = require_gpu()
     ctx = context()
     beta = torch.empty(prob.n_feat, dtype=torch.float64, device="cuda")
     st, info = fl.flsq_solve_linear(ctx, dp.basis, dp.rows, fl.solve_opts(prob.mu, prec, max_refine, tol), beta)
+    if keep is not None:
+        keep.append(beta)
     return st, info, beta.cpu().numpy()
+
+
+def _check_pde_residual(dp, prob, beta_dev, cfg, tol):
+    """The PDE residual on the test set of the GPU solution against the oracle solution's."""
+    torch, fl = require_gpu()
+    g = np.load(os.path.join(GOLDEN, "pde_residuals.npz"))
+    r = pde_residual(fl, context(), dp, prob, beta_dev)
+    scale = np.linalg.norm(prob.extras["residual_scale_test"])
+    dev = np.linalg.norm(r - g[f"{cfg}_residual"]) / scale
+    assert dev <= tol, (cfg, dev, np.linalg.norm(r) / scale, float(g[f"{cfg}_rel"]))
+    return dev
 
 
 @pytest.mark.parametrize("prec", [0, 3])
@@ -139,6 +152,8 @@ def test_solve_linear_small_matches_oracle(idx, prec):
     prob = _small_problems()[idx]
     dp = _dev(prob)
     st, info, beta = _solve(dp, prob, prec=prec, max_refine=30)
+    torch, fl = require_gpu()
+    assert st == fl.FLSQ_OK, (prob.name, info.as_dict())
     ref = oracle.solve_linear(prob)
     zero = [tuple([0] * prob.d)]
     u = oracle.evaluate(prob.W, prob.b, beta, prob.x_test, zero)[:, 0]
@@ -155,11 +170,15 @@ def test_solve_linear_poisson2d_full(prec):
     """2D Poisson, N = 500, 2000 + 400 rows: FP64 end to end, and the int8-CRT Gram."""
     prob = wl.config("poisson2d")
     dp = _dev(prob)
-    st, info, beta = _solve(dp, prob, prec=prec, max_refine=30)
+    keep = []
+    st, info, beta = _solve(dp, prob, prec=prec, max_refine=30, keep=keep)
+    torch, fl = require_gpu()
+    assert st == fl.FLSQ_OK, info.as_dict()
     gold = np.load(os.path.join(GOLDEN, "poisson2d.npz"))
     u = oracle.evaluate(prob.W, prob.b, beta, prob.x_test, [(0, 0)])[:, 0]
     assert rel_l2(u, gold["u_test"]) <= 1e-7, (rel_l2(u, gold["u_test"]), info.as_dict())
     assert rel_l2(u, prob.u_test) <= 1e-6
+    _check_pde_residual(dp, prob, keep[0], "poisson2d", 1e-6)
 
 
 @pytest.mark.parametrize("prec", [0, 3])
@@ -171,7 +190,11 @@ def test_solve_linear_poisson6d_full(prec):
         pytest.skip("golden values not generated")
     prob = wl.config("poisson6d")
     dp = _dev(prob)
-    st, info, beta = _solve(dp, prob, prec=prec, max_refine=30)
+    keep = []
+    st, info, beta = _solve(dp, prob, prec=prec, max_refine=30, keep=keep)
+    torch, fl = require_gpu()
+    assert st == fl.FLSQ_OK, info.as_dict()
+    _check_pde_residual(dp, prob, keep[0], "poisson6d", 1e-6)
     gold = np.load(path)
     u = oracle.evaluate(prob.W, prob.b, beta, prob.x_test, [tuple([0] * 6)])[:, 0]
     assert rel_l2(u, gold["u_test"]) <= 1e-7, (rel_l2(u, gold["u_test"]), info.as_dict())
