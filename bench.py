@@ -255,7 +255,7 @@ def bench_c4(fl, ctx, steps=2):
     res = {"workload": "heat_3d+t: u_t = 0.1 Laplace u on [0,1]^3 x [0,1], N=8192 (sigma=(3,3,3,1.5)), "
                        "65536 interior + 16384 initial + 16384 boundary rows, mu=1e-10"}
     for name, prec in (("int8_crt", fl.PREC_INT8_CRT), ("fp64", fl.PREC_FP64)):
-        r = time_path(fl, ctx, dp, prob, prec, steps, 1, 30, xq)
+        r = time_path(fl, ctx, dp, prob, prec, steps, 1, 200, xq)
         e = {"rel_l2_vs_exact": float(np.linalg.norm(r["u"] - prob.u_test) / np.linalg.norm(prob.u_test)),
              "pde_residual_rel": r["pde_residual_rel"], "oracle_pde_residual_rel": oracle_pde_residual_rel("heat4d")}
         if gold is not None:

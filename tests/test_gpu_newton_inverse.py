@@ -269,7 +269,9 @@ def test_inverse_full_size_adam_trajectory():
     dev = np.abs(got - gold["theta_at"]).max(axis=(1, 2))
     assert np.all(dev <= 1e-6), dict(zip(ck, dev.tolist()))
     assert np.abs(p.cpu().numpy() - gold["theta_final"]).max() <= 1e-6
-    np.testing.assert_allclose(np.array(losses), gold["losses"], rtol=1e-5, atol=1e-12)
+    # a loss moves by at most |grad L| |d theta| between the two runs: theta within 1e-6 and
+    # gradients of at most ~1e-4 near the optimum put losses of ~1e-7 within 1e-10 of each other
+    np.testing.assert_allclose(np.array(losses), gold["losses"], rtol=1e-5, atol=1e-10)
 
 
 @pytest.mark.parametrize("prec", [0, 3])
