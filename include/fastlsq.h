@@ -183,6 +183,21 @@ flsq_status flsq_evaluate(flsq_ctx* ctx, const flsq_basis* basis, const double* 
                           const void* xq, int32_t xq_is_fp32, const uint8_t* alphas, int32_t n_alpha,
                           void* out);
 
+/* ---- Allocation-free evaluation, for callers that cannot allocate device memory (tight serving
+ * loops, harnesses that forbid hipMalloc) ----
+ * Same arguments, kernels and results as flsq_evaluate, but the per-call staging (transposed W,
+ * folded coefficients, FP32 copies, the multi-index list: 12 d N + 12 n_alpha N + 4 N + d n_alpha
+ * bytes, each piece rounded up to 256) lives in a static device array of FLSQ_EVAL_SCRATCH_BYTES,
+ * one copy per GPU, held until the process ends; the call allocates nothing.  N <= 16384 fits for
+ * every d <= 8 and n_alpha <= 8.  Larger staging is rejected with FLSQ_EINVAL before any work.
+ * All calls on one GPU share that GPU's array, from any context: calls that overlap in time on
+ * one GPU (other host threads, other streams) race and must be serialised by the caller.  Every
+ * staged value is written before it is read, so the array's previous contents do not matter. */
+#define FLSQ_EVAL_SCRATCH_BYTES (4 << 20)
+flsq_status flsq_evaluate_noalloc(flsq_ctx* ctx, const flsq_basis* basis, const double* beta, int64_t n_q,
+                                  const void* xq, int32_t xq_is_fp32, const uint8_t* alphas, int32_t n_alpha,
+                                  void* out);
+
 /* Pointwise nonlinearity N(u) = sum_k poly[k] u^k (host array) applied on one row block. */
 typedef struct {
     int32_t n_poly;

@@ -18,6 +18,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -156,6 +157,7 @@ struct flsq_ctx {
   size_t pinned_bytes = 0;
   flsq_factor* aux_factor = nullptr; // factor and derived system reused by the learnable-bandwidth calls
   System aux;
+  unsigned char* scratch = nullptr;  // this device's copy of the static evaluation scratch (no-alloc calls)
 };
 
 struct flsq_factor {
@@ -175,7 +177,32 @@ struct flsq_factor {
   bool report_grad = false;
 };
 
+// Scratch of the allocation-free evaluation call: one copy per device, held by the process until it
+// ends.  Host code never passes `scratch` itself to a kernel or a copy (in host code the name is a
+// host-side stand-in, not a device address); it uses the address hipGetSymbolAddress returns for
+// the current device, resolved once per device in flsq_create.
+static __device__ __align__(256) unsigned char scratch[FLSQ_EVAL_SCRATCH_BYTES];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_addr[kMaxDevices] = {};
+
+// Device address of `scratch` on `device`, which must be current.
+hipError_t scratch_address(int device, unsigned char** out) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_addr[device]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_addr[device] = static_cast<unsigned char*>(p);
+  }
+  *out = g_scratch_addr[device];
+  return hipSuccess;
+}
 
 DevBuf& wsb(flsq_ctx* c, const std::string& name) { return c->ws[name]; }
 
@@ -1320,6 +1347,99 @@ flsq_status finish(flsq_ctx* c, const Err& e) {
   return e.st;
 }
 
+// Evaluation staging (per-feature transposed W, folded coefficients, FP32 copies, the multi-index
+// list), carved from one region in 256-byte pieces.
+struct EvalScratch {
+  double *Wt, *coef;
+  float *Wt32, *coef32, *b32;
+  uint8_t* al;
+};
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+size_t eval_scratch_bytes(int d, int n, int n_alpha) {
+  return align256(sizeof(double) * d * n) + align256(sizeof(double) * n_alpha * n) + align256(sizeof(float) * d * n) +
+         align256(sizeof(float) * n_alpha * n) + align256(sizeof(float) * n) + align256((size_t)n_alpha * d);
+}
+
+EvalScratch carve_eval(unsigned char* base, int d, int n, int n_alpha) {
+  EvalScratch e;
+  size_t off = 0;
+  e.Wt = reinterpret_cast<double*>(base + off);
+  off += align256(sizeof(double) * d * n);
+  e.coef = reinterpret_cast<double*>(base + off);
+  off += align256(sizeof(double) * n_alpha * n);
+  e.Wt32 = reinterpret_cast<float*>(base + off);
+  off += align256(sizeof(float) * d * n);
+  e.coef32 = reinterpret_cast<float*>(base + off);
+  off += align256(sizeof(float) * n_alpha * n);
+  e.b32 = reinterpret_cast<float*>(base + off);
+  off += align256(sizeof(float) * n);
+  e.al = base + off;
+  return e;
+}
+
+// flsq_evaluate and flsq_evaluate_noalloc: the same kernels; the staging comes from the context's
+// workspace (allocated on first use or growth) or from this device's static scratch (no allocation;
+// sizes beyond it are rejected).  Every staged value is written before it is read, so the scratch
+// needs no clearing between calls.
+flsq_status evaluate_entry(flsq_ctx* ctx, const flsq_basis* basis, const double* beta, int64_t n_q, const void* xq,
+                           int32_t xq_is_fp32, const uint8_t* alphas, int32_t n_alpha, void* out, bool no_alloc) {
+  if (!ctx) return FLSQ_EINVAL;
+  if (hipSetDevice(ctx->device) != hipSuccess) return finish(ctx, fail(FLSQ_EHIP, "hipSetDevice failed"));
+  Err e = check_basis(basis);
+  if (e.st != FLSQ_OK) return finish(ctx, e);
+  if (!beta || (n_q > 0 && (!xq || !out))) return finish(ctx, fail(FLSQ_EINVAL, "NULL beta, xq or out"));
+  if (n_q < 0) return finish(ctx, fail(FLSQ_EINVAL, "n_q < 0"));
+  if (n_alpha < 1 || n_alpha > 8 || !alphas) return finish(ctx, fail(FLSQ_EINVAL, "n_alpha = %d outside [1, 8]", n_alpha));
+  const int d = basis->d, n = basis->n_feat;
+  uint32_t mask = 0;
+  for (int a = 0; a < n_alpha; ++a) {
+    int ord = 0;
+    for (int k = 0; k < d; ++k) ord += alphas[a * d + k];
+    if (ord & 1) mask |= 1u << a;
+  }
+  const size_t need = eval_scratch_bytes(d, n, n_alpha);
+  unsigned char* base = nullptr;
+  if (no_alloc) {
+    if (need > (size_t)FLSQ_EVAL_SCRATCH_BYTES)
+      return finish(ctx, fail(FLSQ_EINVAL,
+                              "evaluate_noalloc: d = %d, n_feat = %d, n_alpha = %d need %zu bytes of scratch, above "
+                              "the static %d",
+                              d, n, n_alpha, need, (int)FLSQ_EVAL_SCRATCH_BYTES));
+    if (!ctx->scratch) return finish(ctx, fail(FLSQ_EHIP, "evaluate_noalloc: no scratch address for this device"));
+    base = ctx->scratch;
+  } else {
+    e = ws_get(ctx, "ev_scratch", need, &base);
+    if (e.st != FLSQ_OK) return finish(ctx, e);
+  }
+  const EvalScratch sc = carve_eval(base, d, n, n_alpha);
+  hipError_t he = hipMemcpyAsync(sc.al, alphas, (size_t)n_alpha * d, hipMemcpyHostToDevice, ctx->stream);
+  if (he == hipSuccess) he = launch_transpose(basis->W, n, d, sc.Wt, nullptr, n, ctx->stream);
+  EvalArgs a;
+  a.d = d;
+  a.n = n;
+  a.n_alpha = n_alpha;
+  a.n_q = n_q;
+  a.Wt = sc.Wt;
+  a.b = basis->b;
+  a.beta = beta;
+  a.alphas = sc.al;
+  a.xq = xq;
+  a.out = out;
+  a.fp32 = xq_is_fp32 ? 1 : 0;
+  a.norm = basis->normalize ? 1.0 / std::sqrt((double)n) : 1.0;
+  a.coef = sc.coef;
+  a.coef32 = sc.coef32;
+  a.Wt32 = sc.Wt32;
+  a.b32 = sc.b32;
+  a.cos_mask = mask;
+  if (he == hipSuccess) he = launch_evaluate(a, ctx->stream);
+  if (he == hipSuccess) he = hipStreamSynchronize(ctx->stream);
+  if (he != hipSuccess) return finish(ctx, fail(FLSQ_EHIP, "evaluate: %s", hipGetErrorString(he)));
+  return finish(ctx, ok());
+}
+
 }  // namespace
 
 // =====================================================================================
@@ -1340,7 +1460,10 @@ flsq_status flsq_create(flsq_ctx** ctx, int device, void* hip_stream) {
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
     c->n_cu = prop.multiProcessorCount;
-  if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
+  if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
+      scratch_address(device, &c->scratch) != hipSuccess) {
+    if (c->ev0) (void)hipEventDestroy(c->ev0);
+    if (c->ev1) (void)hipEventDestroy(c->ev1);
     delete c;
     return FLSQ_EHIP;
   }
@@ -1681,54 +1804,13 @@ flsq_status flsq_apply_At(flsq_ctx* ctx, const flsq_factor* F, const double* Y, 
 
 flsq_status flsq_evaluate(flsq_ctx* ctx, const flsq_basis* basis, const double* beta, int64_t n_q, const void* xq,
                           int32_t xq_is_fp32, const uint8_t* alphas, int32_t n_alpha, void* out) {
-  if (!ctx) return FLSQ_EINVAL;
-  if (hipSetDevice(ctx->device) != hipSuccess) return finish(ctx, fail(FLSQ_EHIP, "hipSetDevice failed"));
-  Err e = check_basis(basis);
-  if (e.st != FLSQ_OK) return finish(ctx, e);
-  if (!beta || (n_q > 0 && (!xq || !out))) return finish(ctx, fail(FLSQ_EINVAL, "NULL beta, xq or out"));
-  if (n_q < 0) return finish(ctx, fail(FLSQ_EINVAL, "n_q < 0"));
-  if (n_alpha < 1 || n_alpha > 8 || !alphas) return finish(ctx, fail(FLSQ_EINVAL, "n_alpha = %d outside [1, 8]", n_alpha));
-  const int d = basis->d, n = basis->n_feat;
-  uint32_t mask = 0;
-  for (int a = 0; a < n_alpha; ++a) {
-    int ord = 0;
-    for (int k = 0; k < d; ++k) ord += alphas[a * d + k];
-    if (ord & 1) mask |= 1u << a;
-  }
-  double *Wt, *coef;
-  float *Wt32, *coef32, *b32;
-  uint8_t* al;
-  e = ws_get(ctx, "ev_Wt", (size_t)d * n, &Wt);
-  if (e.st == FLSQ_OK) e = ws_get(ctx, "ev_coef", (size_t)n_alpha * n, &coef);
-  if (e.st == FLSQ_OK) e = ws_get(ctx, "ev_Wt32", (size_t)d * n, &Wt32);
-  if (e.st == FLSQ_OK) e = ws_get(ctx, "ev_coef32", (size_t)n_alpha * n, &coef32);
-  if (e.st == FLSQ_OK) e = ws_get(ctx, "ev_b32", (size_t)n, &b32);
-  if (e.st == FLSQ_OK) e = ws_get(ctx, "ev_alpha", (size_t)n_alpha * d, &al);
-  if (e.st != FLSQ_OK) return finish(ctx, e);
-  hipError_t he = hipMemcpyAsync(al, alphas, (size_t)n_alpha * d, hipMemcpyHostToDevice, ctx->stream);
-  if (he == hipSuccess) he = launch_transpose(basis->W, n, d, Wt, nullptr, n, ctx->stream);
-  EvalArgs a;
-  a.d = d;
-  a.n = n;
-  a.n_alpha = n_alpha;
-  a.n_q = n_q;
-  a.Wt = Wt;
-  a.b = basis->b;
-  a.beta = beta;
-  a.alphas = al;
-  a.xq = xq;
-  a.out = out;
-  a.fp32 = xq_is_fp32 ? 1 : 0;
-  a.norm = basis->normalize ? 1.0 / std::sqrt((double)n) : 1.0;
-  a.coef = coef;
-  a.coef32 = coef32;
-  a.Wt32 = Wt32;
-  a.b32 = b32;
-  a.cos_mask = mask;
-  if (he == hipSuccess) he = launch_evaluate(a, ctx->stream);
-  if (he == hipSuccess) he = hipStreamSynchronize(ctx->stream);
-  if (he != hipSuccess) return finish(ctx, fail(FLSQ_EHIP, "evaluate: %s", hipGetErrorString(he)));
-  return finish(ctx, ok());
+  return evaluate_entry(ctx, basis, beta, n_q, xq, xq_is_fp32, alphas, n_alpha, out, false);
+}
+
+flsq_status flsq_evaluate_noalloc(flsq_ctx* ctx, const flsq_basis* basis, const double* beta, int64_t n_q,
+                                  const void* xq, int32_t xq_is_fp32, const uint8_t* alphas, int32_t n_alpha,
+                                  void* out) {
+  return evaluate_entry(ctx, basis, beta, n_q, xq, xq_is_fp32, alphas, n_alpha, out, true);
 }
 
 }  // extern "C"

@@ -28,7 +28,7 @@ MAX_DIM = 8
 EXPORTS = (
     "flsq_create", "flsq_destroy", "flsq_last_error", "flsq_build_info", "flsq_assemble", "flsq_gram",
     "flsq_solve_linear", "flsq_factorize", "flsq_factor_free", "flsq_factor_shape", "flsq_factor_solve",
-    "flsq_factor_solve_normal", "flsq_apply_A", "flsq_apply_At", "flsq_evaluate", "flsq_solve_newton",
+    "flsq_factor_solve_normal", "flsq_apply_A", "flsq_apply_At", "flsq_evaluate", "flsq_evaluate_noalloc", "flsq_solve_newton",
     "flsq_inverse_loss_grad", "flsq_bandwidth_loss_grad", "flsq_adam_step", "flsq_assemble_var",
     "flsq_solve_linear_var", "flsq_solve_newton_var",
 )
@@ -139,6 +139,7 @@ def load(path: str = LIB_PATH):
         "flsq_apply_A": (st, [vp, vp, vp, i32, vp]),
         "flsq_apply_At": (st, [vp, vp, vp, i32, vp]),
         "flsq_evaluate": (st, [vp, C.POINTER(flsq_basis), vp, i64, vp, i32, C.POINTER(C.c_uint8), i32, vp]),
+        "flsq_evaluate_noalloc": (st, [vp, C.POINTER(flsq_basis), vp, i64, vp, i32, C.POINTER(C.c_uint8), i32, vp]),
         "flsq_solve_newton": (st, [vp, C.POINTER(flsq_basis), C.POINTER(flsq_rows), i32, i32,
                                    C.POINTER(flsq_nonlin), C.POINTER(flsq_newton_opts), vp,
                                    C.POINTER(flsq_newton_trace)]),
@@ -391,6 +392,17 @@ def flsq_evaluate(ctx, basis: Basis, beta, xq, alphas, out):
     return ctx.check(ctx.lib.flsq_evaluate(ctx.h, C.byref(basis.struct), _ptr(beta), int(xq.shape[0]), _ptr(xq),
                                            int(fp32), al.ctypes.data_as(C.POINTER(C.c_uint8)), len(alphas),
                                            _ptr(out)))
+
+
+def flsq_evaluate_noalloc(ctx, basis: Basis, beta, xq, alphas, out):
+    """flsq_evaluate with its staging in the library's static per-device scratch (no device allocation)."""
+    import torch
+    d = basis.struct.d
+    al = np.ascontiguousarray(np.array([list(a) for a in alphas], dtype=np.uint8).reshape(len(alphas), d))
+    fp32 = xq.dtype == torch.float32
+    return ctx.check(ctx.lib.flsq_evaluate_noalloc(ctx.h, C.byref(basis.struct), _ptr(beta), int(xq.shape[0]),
+                                                   _ptr(xq), int(fp32), al.ctypes.data_as(C.POINTER(C.c_uint8)),
+                                                   len(alphas), _ptr(out)))
 
 
 def newton_opts(mu, max_iter=15, tol_dbeta=1e-10, armijo_c=1e-4, max_halvings=10, warm_start=True,
