@@ -266,6 +266,37 @@ def bench_c4(fl, ctx, steps=2):
     return res
 
 
+def bench_fp32_reach(fl, ctx):
+    """Whether the FP32-MFMA and BF16x3 Gram paths (shifted FP32 factor + FP64 CGLS) reach 1e-7 of
+    the oracle on each linear config, given up to 300 (600 for the 2D case) refinement steps."""
+    import torch
+    from paper_2602_10541_amd import workloads as wl
+    out = {}
+    for cfg, cap in (("poisson2d", 600), ("poisson6d", 300), ("heat4d", 300)):
+        prob = wl.config(cfg)
+        gold = _gold(cfg)
+        dp = fl.DeviceProblem(prob)
+        xq = torch.tensor(prob.x_test, dtype=torch.float64, device="cuda")
+        z = [tuple([0] * prob.d)]
+        r = {}
+        for name, prec in (("fp32_mfma", fl.PREC_FP32_REFINE), ("bf16x3", fl.PREC_BF16X3_REFINE)):
+            beta = torch.empty(prob.n_feat, dtype=torch.float64, device="cuda")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st, info = fl.flsq_solve_linear(ctx, dp.basis, dp.rows, fl.solve_opts(prob.mu, prec, cap, 1e-10), beta)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            u = torch.empty((xq.shape[0], 1), dtype=torch.float64, device="cuda")
+            fl.flsq_evaluate(ctx, dp.basis, beta, xq, z, u)
+            u = u[:, 0].cpu().numpy()
+            e = float(np.linalg.norm(u - gold["u_test"]) / np.linalg.norm(gold["u_test"])) if gold is not None else None
+            r[name] = {"status": int(st), "refine_iters": int(info.refine_iters), "shift": float(info.shift),
+                       "rel_l2_vs_oracle": e, "reaches_1e-7": bool(e is not None and e <= 1e-7),
+                       "ms": 1e3 * dt}
+        out[cfg] = r
+    return out
+
+
 def bench_sweep(fl, ctx, reps=3):
     """Matrix caching on a parametric sweep (Helmholtz 2D, k = 10, N = 1500, 6000 rows, 64 Dirichlet
     data sets): factor once, then solve every right-hand side against the factor, batched and one
@@ -723,6 +754,8 @@ def main():
             "gram_fp32_equiv_tflops": gram_flops(P, N) / (kb * 1e-3) / 1e12,
             "gram_bf16_frac_of_peak": 3 * gram_flops(P, N) / (kb * 1e-3) / 1e12 / PEAK_BF16_MFMA_TFLOPS,
         }
+    if not args.skip_fp32:
+        out["fp32_paths_reach_1e-7"] = bench_fp32_reach(fl, ctx)
     if not args.skip_eval:
         out["evaluate_c4"] = bench_evaluate(fl, ctx)
     if not args.skip_configs:

@@ -108,6 +108,12 @@ typedef struct {
                              one-call solvers also after 8 refinement steps that did not converge when
                              2 P N^2 <= 4e10; Newton steps take it only when asked for.  1 = always
                              (same precisions); -1 = never */
+    double pivot_boost;   /* modified Cholesky (Gill and Murray): > 0 raises pivots of the unit-diagonal
+                             equilibrated Gram below this value to it during the factorisation, so a
+                             Gram that rounding left indefinite factors without a restart unless the
+                             raised pivots make entries overflow; 0 = off: a non-positive pivot
+                             restarts the factorisation with a diagonal shift (see shift_rel);
+                             must be in [0, 1) */
 } flsq_solve_opts;
 
 typedef struct {
@@ -123,6 +129,7 @@ typedef struct {
                                 assembly + Gram kernel for FP64 / FP32, the int8 tile kernel for INT8_CRT */
     int32_t second_pass;     /* 1 if the factor was refined by the second pass (opts.second_pass) */
     double t_second_pass_ms; /* its time (included in t_chol_ms) */
+    int32_t boosted_pivots;  /* pivots raised by opts.pivot_boost in the factor that was kept */
 } flsq_solve_info;
 
 typedef struct flsq_ctx flsq_ctx;

@@ -578,12 +578,15 @@ Err upload_descs(flsq_ctx* c, const std::vector<GemmDesc>& h, GemmDesc** d_out) 
 }
 
 // In-place upper Cholesky of G (only the upper triangle is read), and X = U^{-1} (upper,
-// zero below the diagonal).  info_host > 0 at the first non-positive pivot (1-based).
-Err cholesky_inv(flsq_ctx* c, double* G, double* X, int n, int* info_host) {
+// zero below the diagonal).  Pivots below boost (> 0) are raised to it (their count goes to
+// *boosted_host); info_host > 0 at the first failed pivot (1-based: non-finite, or non-positive
+// when boost = 0).  The status is read before the inverse is formed, and a failed factor
+// returns without it.
+Err cholesky_inv(flsq_ctx* c, double* G, double* X, int n, int* info_host, double boost, int* boosted_host) {
   int* info;
   hipStream_t st = c->stream;
-  CHECK_ERR(ws_get(c, "chol_info", 1, &info));
-  CHECK_HIP(hipMemsetAsync(info, 0, sizeof(int), st));
+  CHECK_ERR(ws_get(c, "chol_info", 2, &info));
+  CHECK_HIP(hipMemsetAsync(info, 0, 2 * sizeof(int), st));
   CHECK_HIP(hipMemsetAsync(X, 0, sizeof(double) * n * n, st));
   const int nblk = (n + kNb - 1) / kNb;
   // X off-diagonal blocks, bottom-up: pairs of adjacent ranges [lo, mid), [mid, hi) of blocks:
@@ -632,11 +635,16 @@ Err cholesky_inv(flsq_ctx* c, double* G, double* X, int n, int* info_host) {
   GemmDesc* dd;
   CHECK_ERR(upload_descs(c, all, &dd));
   // block 0 first; every trailing update also factors the next diagonal block
-  CHECK_HIP(launch_potrf(G, n, 0, info, st));
+  CHECK_HIP(launch_potrf(G, n, 0, info, boost, info + 1, st));
   for (int k0 = 0; k0 + kNb < n; k0 += kNb) {
     CHECK_HIP(launch_trsm_row(G, n, k0, st));
-    CHECK_HIP(launch_syrk_potrf(G, n, k0, info, st));
+    CHECK_HIP(launch_syrk_potrf(G, n, k0, info, boost, info + 1, st));
   }
+  int hinfo[2] = {0, 0};
+  CHECK_ERR(read_back(c, hinfo, info, sizeof hinfo));
+  *info_host = hinfo[0];
+  *boosted_host = hinfo[1];
+  if (hinfo[0] != 0) return ok();
   CHECK_HIP(launch_trinv_diag(G, n, X, st));
   // split-K partials of the sparse levels: at most n^2 doubles (the full-level products hold
   // M N <= n^2 / 4 per pair, up to 4 splits at the top level)
@@ -654,7 +662,6 @@ Err cholesky_inv(flsq_ctx* c, double* G, double* X, int n, int* info_host) {
     CHECK_HIP(launch_gemm_tri(dd + offT[l], (int)lvT[l].size(), maxM, maxN, maxKT, 1.0, gwork, gwork_elems, st));
     CHECK_HIP(launch_gemm_tri(dd + offX[l], (int)lvX[l].size(), maxM, maxN, maxKX, -1.0, gwork, gwork_elems, st));
   }
-  CHECK_ERR(read_back(c, info_host, info, sizeof(int)));
   return ok();
 }
 
@@ -706,9 +713,11 @@ Err chol_solve(flsq_ctx* c, const double* X, int n, const double* Y, double* Z, 
 // Factor the equilibrated system D (G_src + mu I) D + shift I (D = diag(G_src)^{-1/2}, so the
 // scaled Gram has a unit diagonal), form X = U^{-1}, and return D X, whose outer product
 // (D X)(D X)^T approximates (G + mu I)^{-1}.  The first attempt uses shift0 (0 for the FP64
-// Gram); a failed pivot retries with growing shifts.
+// Gram).  Pivots of the equilibrated Gram below boost (> 0) are raised to it in place (their
+// count goes to *boosted); a failed pivot (non-finite, or non-positive when boost = 0) retries
+// the whole factorisation with growing shifts.
 Err factor_with_retries(flsq_ctx* c, const double* Gsrc, double* U, double* X, int n, double mu, double shift0,
-                        double* shift_used, int* retries) {
+                        double* shift_used, int* retries, double boost = 0.0, int* boosted = nullptr) {
   double *dmax, *d;
   CHECK_ERR(ws_get(c, "diag_max", 1, &dmax));
   CHECK_ERR(ws_get(c, "eq_d", (size_t)n, &d));
@@ -720,11 +729,12 @@ Err factor_with_retries(flsq_ctx* c, const double* Gsrc, double* U, double* X, i
   *retries = 0;
   for (int attempt = 0; attempt < 8; ++attempt) {
     CHECK_HIP(launch_equilibrate(Gsrc, U, n, d, mu, rel, c->stream));
-    int info = 0;
-    CHECK_ERR(cholesky_inv(c, U, X, n, &info));
+    int info = 0, nb = 0;
+    CHECK_ERR(cholesky_inv(c, U, X, n, &info, boost, &nb));
     if (info == 0) {
       CHECK_HIP(launch_scale_rows(X, n, d, c->stream));
       *shift_used = rel;
+      if (boosted) *boosted = nb;
       return ok();
     }
     ++*retries;
@@ -1057,7 +1067,11 @@ struct SolveParams {
   double shift_rel = 0.0;
   bool report_grad = false;
   int second_pass = 0;
+  double pivot_boost = 0.0;   // > 0 raises low pivots in place, 0 retries with shifts
 };
+
+// Boost of the second pass's factorisation (its Gram is far better conditioned than the first).
+constexpr double kSecondPassPivotBoost = 0.0;
 
 SolveParams params_of(const flsq_solve_opts* o) {
   SolveParams p;
@@ -1069,6 +1083,7 @@ SolveParams params_of(const flsq_solve_opts* o) {
     p.shift_rel = o->shift_rel;
     p.report_grad = o->report_grad != 0;
     p.second_pass = o->second_pass;
+    p.pivot_boost = o->pivot_boost;
   }
   return p;
 }
@@ -1082,6 +1097,7 @@ Err check_params(const SolveParams& p) {
   if (!(p.refine_tol >= 0.0)) return fail(FLSQ_EINVAL, "refine_tol must be >= 0");
   if (!(p.shift_rel >= 0.0) || p.shift_rel > 1.0) return fail(FLSQ_EINVAL, "shift_rel must be in [0, 1]");
   if (p.second_pass < -1 || p.second_pass > 1) return fail(FLSQ_EINVAL, "second_pass must be -1, 0 or 1");
+  if (!(p.pivot_boost >= 0.0 && p.pivot_boost < 1.0)) return fail(FLSQ_EINVAL, "pivot_boost must be in [0, 1)");
   return ok();
 }
 
@@ -1159,7 +1175,8 @@ Err second_pass_factor(flsq_ctx* c, const double* A, int64_t P, int n, double mu
   CHECK_HIP(launch_gemm_tri(d + 1, 1, n, n, (int)P, 1.0, work, we, st));
   CHECK_HIP(launch_gemm_batched(d + 1 + n_split, 1, n, n, mu, 1.0, 1, st));
   CHECK_HIP(hipStreamSynchronize(st));   // h leaves scope before the factorisation reuses the descriptors' slots
-  Err fe = factor_with_retries(c, G2, U, X2, n, 0.0, 0.0, shift2, retries2);
+  int boosted2 = 0;
+  Err fe = factor_with_retries(c, G2, U, X2, n, 0.0, 0.0, shift2, retries2, kSecondPassPivotBoost, &boosted2);
   if (fe.st == FLSQ_ENOTSPD) {   // the first factor stays in use
     *applied = false;
     return ok();
@@ -1244,10 +1261,11 @@ Err gram_and_factor(flsq_ctx* c, const System& s, const double* rho, const Solve
   int retries = 0;
   const bool exact_gram = sp.prec == FLSQ_PREC_FP64 || sp.prec == FLSQ_PREC_INT8_CRT;
   const double rel0 = exact_gram ? sp.shift_rel : (sp.shift_rel > 0.0 ? sp.shift_rel : 1e-6);
-  CHECK_ERR(factor_with_retries(c, G, U, Xi, n, sp.mu, rel0, &shift, &retries));
+  int boosted = 0;
+  CHECK_ERR(factor_with_retries(c, G, U, Xi, n, sp.mu, rel0, &shift, &retries, sp.pivot_boost, &boosted));
   const double t2a = now_ms();
   bool second = false;
-  if (want_second_pass(sp, retries, rho, s.P, n)) {
+  if (want_second_pass(sp, retries + (boosted > 0 ? 1 : 0), rho, s.P, n)) {
     double* A;
     CHECK_ERR(ws_get(c, "sp_A", (size_t)s.P * n, &A));
     CHECK_HIP(launch_assemble(s.geo(), 0, A, c->stream));
@@ -1259,12 +1277,14 @@ Err gram_and_factor(flsq_ctx* c, const System& s, const double* rho, const Solve
     retries += retries2;
   }
   if (second_out) *second_out = second;
+  CHECK_HIP(hipStreamSynchronize(c->stream));   // the inverse factor's kernels belong to this phase
   const double t2 = now_ms();
   if (info) {
     info->t_gram_ms = t1 - t0;
     info->t_chol_ms = t2 - t1;
     info->shift = shift;
     info->chol_retries = retries;
+    info->boosted_pivots = boosted;
     info->t_gram_kernel_ms = c->last_gram_kernel_ms;
     info->second_pass = second ? 1 : 0;
     info->t_second_pass_ms = second ? t2 - t2a : 0.0;
@@ -2349,10 +2369,11 @@ Err var_linear_solve(flsq_ctx* c, const double* A, const double* At, int n, int6
   c->last_gram_kernel_ms = kms;
   double shift = 0.0;
   int retries = 0;
-  CHECK_ERR(factor_with_retries(c, G, U, Xi, n, sp.mu, sp.shift_rel, &shift, &retries));
+  int boosted = 0;
+  CHECK_ERR(factor_with_retries(c, G, U, Xi, n, sp.mu, sp.shift_rel, &shift, &retries, sp.pivot_boost, &boosted));
   const double t2a = now_ms();
   bool second = false;
-  if (want_second_pass(sp, retries, nullptr, P, n)) {
+  if (want_second_pass(sp, retries + (boosted > 0 ? 1 : 0), nullptr, P, n)) {
     double shift2 = 0.0;
     int retries2 = 0;
     CHECK_ERR(second_pass_factor(c, A, P, n, sp.mu, Xi, &shift2, &retries2, &second));
@@ -2380,6 +2401,7 @@ Err var_linear_solve(flsq_ctx* c, const double* A, const double* At, int n, int6
     info->t_chol_ms = t2 - t1;
     info->shift = shift;
     info->chol_retries = retries;
+    info->boosted_pivots = boosted;
     info->t_gram_kernel_ms = c->last_gram_kernel_ms;
     info->refine_iters = ro.iters;
     info->grad_norm0 = ro.grad0;

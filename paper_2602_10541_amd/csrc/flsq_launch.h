@@ -194,10 +194,11 @@ constexpr int kNb = 64;
 // Blocked Cholesky steps (k_chol.hip): factor the diagonal block at k0 in place; block-row
 // solve U_kj = U_kk^{-T} G_kj for columns >= k0 + kNb; trailing update of [k0 + kNb, n)
 // fused with the factorisation of the next diagonal block; inverses of all diagonal blocks
-// into the diagonal blocks of X.  *info receives the first non-positive pivot (1-based).
-hipError_t launch_potrf(double* G, int n, int k0, int* info, hipStream_t s);
+// into the diagonal blocks of X.  Pivots below boost (> 0) are raised to it and counted in
+// *nboost; with boost = 0, *info receives the first non-positive pivot (1-based).
+hipError_t launch_potrf(double* G, int n, int k0, int* info, double boost, int* nboost, hipStream_t s);
 hipError_t launch_trsm_row(double* G, int n, int k0, hipStream_t s);
-hipError_t launch_syrk_potrf(double* G, int n, int k0, int* info, hipStream_t s);
+hipError_t launch_syrk_potrf(double* G, int n, int k0, int* info, double boost, int* nboost, hipStream_t s);
 hipError_t launch_trinv_diag(const double* G, int n, double* X, hipStream_t s);
 // dst = D src D + (diag_add + mu D^2) on the diagonal (upper triangle), D = diag(src)^{-1/2} -> d.
 hipError_t launch_equilibrate(const double* G, double* dst, int n, double* d, double mu, double diag_add,

@@ -52,17 +52,25 @@ __device__ __forceinline__ void potrf64_load(const double* G, int n, int k0, f64
     }
 }
 
-// Factor the block held in acc (all 256 threads; S: kNb * kNb doubles of LDS, sbad: one int
-// of LDS) and store the upper triangle of U_kk at k0.  A non-positive or non-finite pivot is
-// recorded in *info (1-based global index, first failure) and replaced by 1 so every step
-// completes.  Entries below the diagonal are never stored.
+// Factor the block held in acc (all 256 threads; S: kNb * kNb doubles of LDS, sbad: two ints
+// of LDS) and store the upper triangle of U_kk at k0.
+//
+// Pivots below `boost` (> 0) are raised to it, the modified Cholesky of Gill and Murray: the
+// factor is then exact for G + E with E diagonal, non-zero only at the raised pivots, so a
+// Gram that rounding has pushed out of the positive definite cone still factors in one pass;
+// their number is added to *nboost.  With boost = 0 a non-positive pivot is a failure instead.
+// A failed (or non-finite) pivot is recorded in *info (1-based global index, first failure)
+// and replaced by 1 so every step completes.  Entries below the diagonal are never stored.
 __device__ __forceinline__ void potrf64_factor(f64x4 acc[4], double* G, int n, int k0, int* info, double* S,
-                                               int* sbad) {
+                                               int* sbad, double boost, int* nboost) {
   const int nbk = min(kNb, n - k0);
   const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
   const int r16 = lane & 15, k4 = lane >> 4;
   double* base = G + (int64_t)k0 * n + k0;
-  if (threadIdx.x == 0) *sbad = -1;
+  if (threadIdx.x == 0) {
+    sbad[0] = -1;
+    sbad[1] = 0;
+  }
 #pragma unroll
   for (int g = 0; g < kNb / 4; ++g) {
     const int L = 4 * g, q0 = g >> 2, v0 = g & 3;
@@ -73,14 +81,16 @@ __device__ __forceinline__ void potrf64_factor(f64x4 acc[4], double* G, int n, i
       double x[4];
 #pragma unroll
       for (int a = 0; a < 4; ++a) x[a] = S[(L + a) * kNb + lane];
-      int bad = -1;
+      int bad = -1, raised = 0;
 #pragma unroll
       for (int a = 0; a < 4; ++a) {
         const int l = L + a;
         const double diag = lane_bcast(x[a], l);
-        const bool fail = !(diag > 0.0) || !isfinite(diag);
+        const bool low = !(diag > boost);
+        const bool fail = !isfinite(diag) || (low && !(boost > 0.0));
+        raised += (low && !fail && l < nbk) ? 1 : 0;
         bad = (fail && bad < 0) ? l : bad;
-        const double piv = fail ? 1.0 : diag;
+        const double piv = fail ? 1.0 : (low ? boost : diag);
         const double r = rsqrt_nr(piv);
         const double u = (lane > l) ? x[a] * r : ((lane == l) ? piv * r : 0.0);
         x[a] = u;
@@ -89,7 +99,8 @@ __device__ __forceinline__ void potrf64_factor(f64x4 acc[4], double* G, int n, i
       }
 #pragma unroll
       for (int a = 0; a < 4; ++a) S[(L + a) * kNb + lane] = x[a];
-      if (lane == 0 && bad >= 0 && *sbad < 0) *sbad = bad;
+      if (lane == 0 && bad >= 0 && sbad[0] < 0) sbad[0] = bad;
+      if (lane == 0) sbad[1] += raised;
     }
     __syncthreads();
     if (g + 1 < kNb / 4) {
@@ -113,16 +124,17 @@ __device__ __forceinline__ void potrf64_factor(f64x4 acc[4], double* G, int n, i
     const int i = 4 * r + q;
     if (i < nbk && lane >= i && lane < nbk) base[(int64_t)i * n + lane] = S[i * kNb + lane];
   }
-  const int bad = *sbad;
+  const int bad = sbad[0];
   if (threadIdx.x == 0 && bad >= 0 && bad < nbk && *info == 0) *info = k0 + bad + 1;
+  if (threadIdx.x == 0 && sbad[1] > 0) atomicAdd(nboost, sbad[1]);
 }
 
-__global__ __launch_bounds__(256) void k_potrf(double* G, int n, int k0, int* info) {
+__global__ __launch_bounds__(256) void k_potrf(double* G, int n, int k0, int* info, double boost, int* nboost) {
   __shared__ double S[kNb * kNb];
-  __shared__ int sbad;
+  __shared__ int sbad[2];
   f64x4 acc[4];
   potrf64_load(G, n, k0, acc);
-  potrf64_factor(acc, G, n, k0, info, S, &sbad);
+  potrf64_factor(acc, G, n, k0, info, S, sbad, boost, nboost);
 }
 
 // Block row: y = U_kk^{-T} g for every column j >= k0 + kNb by forward substitution
@@ -249,7 +261,8 @@ __device__ __forceinline__ void syrk_fetch_panel(const double* G, int n, int k0,
   }
 }
 
-__global__ __launch_bounds__(256, 1) void k_syrk_potrf(double* G, int n, int k0, int* info) {
+__global__ __launch_bounds__(256, 1) void k_syrk_potrf(double* G, int n, int k0, int* info, double boost,
+                                                       int* nboost) {
   extern __shared__ __align__(16) double smem_d[];     // A and B panels; diagonal block: panel, then S
   const int k1 = k0 + kNb;
   const int nt = (n - k1 + 127) / 128;
@@ -271,7 +284,8 @@ __global__ __launch_bounds__(256, 1) void k_syrk_potrf(double* G, int n, int k0,
       for (int c = 0; c < 4; ++c)
         acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, sP[(kk * 8 + c) * 64 + lane], acc[c], 0, 0, 0);
     }
-    potrf64_factor(acc, G, n, k1, info, smem_d + kSyrkPanel, (int*)(smem_d + kSyrkPanel + kNb * kNb));
+    potrf64_factor(acc, G, n, k1, info, smem_d + kSyrkPanel, (int*)(smem_d + kSyrkPanel + kNb * kNb), boost,
+                   nboost);
     return;
   }
   int ti, tj;
@@ -368,8 +382,8 @@ __global__ __launch_bounds__(64) void k_trinv(const double* G, int n, double* X)
   }
 }
 
-hipError_t launch_potrf(double* G, int n, int k0, int* info, hipStream_t s) {
-  hipLaunchKernelGGL(k_potrf, dim3(1), dim3(256), 0, s, G, n, k0, info);
+hipError_t launch_potrf(double* G, int n, int k0, int* info, double boost, int* nboost, hipStream_t s) {
+  hipLaunchKernelGGL(k_potrf, dim3(1), dim3(256), 0, s, G, n, k0, info, boost, nboost);
   return hipGetLastError();
 }
 
@@ -380,7 +394,7 @@ hipError_t launch_trsm_row(double* G, int n, int k0, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_syrk_potrf(double* G, int n, int k0, int* info, hipStream_t s) {
+hipError_t launch_syrk_potrf(double* G, int n, int k0, int* info, double boost, int* nboost, hipStream_t s) {
   const int rem = n - k0 - kNb;
   if (rem <= 0) return hipSuccess;
   const size_t lds = sizeof(double) * 2 * kSyrkPanel;   // 128 KB: two panel slices
@@ -391,7 +405,7 @@ hipError_t launch_syrk_potrf(double* G, int n, int k0, int* info, hipStream_t s)
     attr_set = true;
   }
   const int nt = (rem + 127) / 128;
-  hipLaunchKernelGGL(k_syrk_potrf, dim3(1 + nt * (nt + 1) / 2), dim3(256), lds, s, G, n, k0, info);
+  hipLaunchKernelGGL(k_syrk_potrf, dim3(1 + nt * (nt + 1) / 2), dim3(256), lds, s, G, n, k0, info, boost, nboost);
   return hipGetLastError();
 }
 

@@ -60,7 +60,8 @@ class flsq_rows(C.Structure):
 
 class flsq_solve_opts(C.Structure):
     _fields_ = [("mu", C.c_double), ("prec", C.c_int32), ("max_refine", C.c_int32), ("refine_tol", C.c_double),
-                ("shift_rel", C.c_double), ("report_grad", C.c_int32), ("second_pass", C.c_int32)]
+                ("shift_rel", C.c_double), ("report_grad", C.c_int32), ("second_pass", C.c_int32),
+                ("pivot_boost", C.c_double)]
 
 
 class flsq_solve_info(C.Structure):
@@ -68,7 +69,7 @@ class flsq_solve_info(C.Structure):
                 ("grad_norm0", C.c_double), ("grad_norm", C.c_double), ("last_step_rel", C.c_double),
                 ("t_gram_ms", C.c_double), ("t_chol_ms", C.c_double), ("t_refine_ms", C.c_double),
                 ("t_total_ms", C.c_double), ("t_gram_kernel_ms", C.c_double), ("second_pass", C.c_int32),
-                ("t_second_pass_ms", C.c_double)]
+                ("t_second_pass_ms", C.c_double), ("boosted_pivots", C.c_int32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -303,9 +304,9 @@ def make_vrows(blocks, d) -> VRows:
 
 
 def solve_opts(mu, prec=PREC_FP64, max_refine=10, refine_tol=1e-12, shift_rel=0.0, report_grad=False,
-               second_pass=0):
+               second_pass=0, pivot_boost=0.0):
     return flsq_solve_opts(float(mu), int(prec), int(max_refine), float(refine_tol), float(shift_rel),
-                           1 if report_grad else 0, int(second_pass))
+                           1 if report_grad else 0, int(second_pass), float(pivot_boost))
 
 
 # ---------------------------------------------------------------------------- entry points

@@ -182,6 +182,28 @@ def test_solve_linear_poisson2d_full(prec):
 
 
 @pytest.mark.parametrize("prec", [0, 3])
+def test_pivot_boost_factors_without_restart(prec):
+    """The opt-in modified Cholesky on the 2D Poisson Gram (whose equilibrated Gram has pivots
+    below 1e-13): no restart, the raised pivots counted, the automatic second pass taken, and the
+    oracle's solution reached; an out-of-range boost is refused."""
+    torch, fl = require_gpu()
+    prob = wl.config("poisson2d")
+    dp = _dev(prob)
+    ctx = context()
+    beta = torch.empty(prob.n_feat, dtype=torch.float64, device="cuda")
+    st, info = fl.flsq_solve_linear(ctx, dp.basis, dp.rows, fl.solve_opts(prob.mu, prec, 30, 1e-12, pivot_boost=1e-13),
+                                    beta)
+    assert st == fl.FLSQ_OK, info.as_dict()
+    assert info.chol_retries == 0 and info.boosted_pivots > 0 and info.second_pass == 1, info.as_dict()
+    gold = np.load(os.path.join(GOLDEN, "poisson2d.npz"))
+    u = oracle.evaluate(prob.W, prob.b, beta.cpu().numpy(), prob.x_test, [(0, 0)])[:, 0]
+    assert rel_l2(u, gold["u_test"]) <= 1e-7, (rel_l2(u, gold["u_test"]), info.as_dict())
+    with pytest.raises(fl.FlsqError) as ei:
+        fl.flsq_solve_linear(ctx, dp.basis, dp.rows, fl.solve_opts(prob.mu, prec, 30, 1e-12, pivot_boost=1.5), beta)
+    assert ei.value.status == fl.FLSQ_EINVAL
+
+
+@pytest.mark.parametrize("prec", [0, 3])
 def test_solve_linear_poisson6d_full(prec):
     """6D Poisson at full size (N = 4096, 32768 + 8192 rows): FP64 and int8-CRT Gram paths vs the
     oracle's stored solution."""
@@ -214,6 +236,22 @@ def test_fp32_preconditioned_path_well_conditioned(prec):
     u = oracle.evaluate(prob.W, prob.b, beta, prob.x_test, [tuple([0] * 6)])[:, 0]
     uref = oracle.evaluate(prob.W, prob.b, ref, prob.x_test, [tuple([0] * 6)])[:, 0]
     assert rel_l2(u, uref) <= 1e-7, (rel_l2(u, uref), info.as_dict())
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+def test_fp32_paths_reach_the_bar_on_poisson2d(prec):
+    """The FP32-MFMA (and BF16x3) Gram as the preconditioner of FP64 CGLS on the 2D Poisson
+    config: the shifted factor leaves a slowly converging refinement (about 100 steps to 1e-7 for
+    FP32, about 250 for BF16x3), which ends within 1e-7 of the oracle's solution.  On the 6D
+    Poisson and 3D + t heat configs the same paths stall above 1e-3 after 300 steps."""
+    torch, fl = require_gpu()
+    prob = wl.config("poisson2d")
+    dp = _dev(prob)
+    st, info, beta = _solve(dp, prob, prec=prec, max_refine=600, tol=1e-10)
+    assert st == fl.FLSQ_OK, info.as_dict()
+    gold = np.load(os.path.join(GOLDEN, "poisson2d.npz"))
+    u = oracle.evaluate(prob.W, prob.b, beta, prob.x_test, [(0, 0)])[:, 0]
+    assert rel_l2(u, gold["u_test"]) <= 1e-7, (rel_l2(u, gold["u_test"]), info.as_dict())
 
 
 @pytest.mark.parametrize("fp32", [False, True])
