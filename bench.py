@@ -208,6 +208,29 @@ def bench_evaluate(fl, ctx, reps=5):
     ms = e0.elapsed_time(e1) / reps
     hbm = Q * (4 + len(alphas)) * 4.0
     pairs = float(Q) * N
+    # the stored heat solution's outputs at 4096 of the points: against the oracle's FP64 values
+    # and the exact solution
+    acc = None
+    g = _gold("heat4d")
+    ge = _gold("heat4d_eval")
+    if g is not None and ge is not None:
+        bt = torch.tensor(g["beta"], dtype=torch.float64, device="cuda")
+        fl.flsq_evaluate(ctx, basis, bt, xq, alphas, out)
+        got = out.double().cpu().numpy()[ge["idx"]]
+        ex = wl.heat_exact_outputs(prob.extras["x_query"][ge["idx"]].astype(np.float32).astype(np.float64))
+        names = ("u", "u_x", "u_y", "u_z", "u_t")
+        acc = {"sample": "4096 seeded query points, the stored FP64 oracle solution's coefficients",
+               "rel_l2_vs_oracle": {nm: float(np.linalg.norm(got[:, a] - ge["ref"][:, a]) / np.linalg.norm(ge["ref"][:, a]))
+                                    for a, nm in enumerate(names)},
+               "rel_l2_vs_exact": {nm: float(np.linalg.norm(got[:, a] - ex[:, a]) / np.linalg.norm(ex[:, a]))
+                                   for a, nm in enumerate(names)},
+               "oracle_rel_l2_vs_exact": {nm: float(np.linalg.norm(ge["ref"][:, a] - ex[:, a]) / np.linalg.norm(ex[:, a]))
+                                          for a, nm in enumerate(names)}}
+    # VALU model: per pair d phase multiply-adds, one reduction and one multiply-add per output
+    # at full rate, plus a sine and a cosine on the transcendental pipeline, which runs beside
+    # the full-rate one (the measured time is below what the two would take in sequence)
+    full_rate_ops = (4 + 1 + len(alphas)) * pairs
+    peak_lane_ops = 256 * 64 * 2.4e9
     return {"workload": "heat_3d+t evaluate: N=8192, Q=1048576 FP32 points, outputs u,u_x,u_y,u_z,u_t",
             "ms": ms, "points_per_s": Q / (ms * 1e-3), "pairs_per_s": pairs / (ms * 1e-3),
             "hbm_bytes": hbm, "hbm_gb_s": hbm / (ms * 1e-3) / 1e9, "hbm_frac": hbm / (ms * 1e-3) / PEAK_HBM_BYTES,
@@ -215,6 +238,13 @@ def bench_evaluate(fl, ctx, reps=5):
                                         "paper_2602_10541_amd/csrc/k_prep.hip"),
             "traffic_source": "profiles/k_evaluate_f32_heat4d_hbm_traffic.md (FETCH_SIZE + WRITE_SIZE, copy-calibrated; "
                               "null if the source changed since)",
+            "valu_roofline": {"bound": "alu", "achieved": full_rate_ops / (ms * 1e-3) / 1e12,
+                              "peak": peak_lane_ops / 1e12, "unit": "T full-rate lane-ops/s",
+                              "frac": full_rate_ops / (ms * 1e-3) / peak_lane_ops,
+                              "model": "per (point, feature) pair: d + 1 + n_alpha = 10 full-rate VALU ops (phase FMAs, "
+                                       "fract, one FMA per output) and 2 transcendental (v_sin_f32, v_cos_f32, quarter "
+                                       "rate, overlapped); peak = 256 CUs x 64 lanes x 2.4 GHz"},
+            "accuracy": acc,
             "bound": "alu (one FP32 sincos + d + outputs FMAs per point-feature pair; not HBM)"}
 
 

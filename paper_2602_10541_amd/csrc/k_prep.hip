@@ -310,17 +310,21 @@ __global__ __launch_bounds__(kEvalThreads) void k_evaluate(int n, int n_alpha, i
 }
 
 // FP32 evaluation.  The phase is formed in revolutions, z = (W / 2 pi) . x + b / 2 pi, reduced to
-// [-1/2, 1/2] and passed to the hardware sine and cosine (v_sin_f32 / v_cos_f32 take their
-// argument in revolutions), one of each per (point, feature) pair.  Outputs are visited with
-// the sine-type ones (even |alpha|) first, so each pair costs d + 2 multiply-adds for the phase
-// and reduction, two transcendental ops and one multiply-add per output.
+// [0, 1) by its fractional part (exact: z - floor z) and passed to the hardware sine and cosine
+// (v_sin_f32 / v_cos_f32 take their argument in revolutions), one of each per (point, feature)
+// pair.  Outputs are visited with the sine-type ones (even |alpha|) first, so each pair costs
+// d multiply-adds for the phase, one reduction, two transcendental ops and one multiply-add per
+// output.  (Contracting the outputs on the matrix cores instead, 16 points x 4 features per
+// v_mfma_f32_16x16x4f32, was measured no faster on the 3D + t heat evaluation.)
 struct EvalOrder {
   int n_sin;                 // outputs [0, n_sin) use sin z, the rest cos z
   int perm[8];               // visiting slot -> output column (and coefficient row)
 };
 constexpr int kEvalPts32 = 4;
 
-template <int D, int NA>
+// NS1 = 1: exactly one sine-type output (u and first derivatives, the usual query), fixed at
+// compile time so no per-output select is issued; NS1 = 0 reads the split from ord.n_sin.
+template <int D, int NA, int NS1>
 __global__ __launch_bounds__(kEvalThreads) void k_evaluate_f32(int n, int64_t n_q,
                                                                const float* __restrict__ Wr,
                                                                const float* __restrict__ br,
@@ -358,11 +362,12 @@ __global__ __launch_bounds__(kEvalThreads) void k_evaluate_f32(int n, int64_t n_
         float z = sF[jj][D];
 #pragma unroll
         for (int k = 0; k < D; ++k) z = fmaf(sF[jj][k], x[p][k], z);
-        z -= rintf(z);
+        z = __builtin_amdgcn_fractf(z);
         const float sv = __builtin_amdgcn_sinf(z);
         const float cv = __builtin_amdgcn_cosf(z);
 #pragma unroll
-        for (int a = 0; a < NA; ++a) acc[p][a] = fmaf(sF[jj][D + 1 + a], (a < ord.n_sin) ? sv : cv, acc[p][a]);
+        for (int a = 0; a < NA; ++a)
+          acc[p][a] = fmaf(sF[jj][D + 1 + a], (a < (NS1 ? 1 : ord.n_sin)) ? sv : cv, acc[p][a]);
       }
     }
   }
@@ -380,8 +385,12 @@ hipError_t launch_evaluate_f32(const EvalArgs& a, const EvalOrder& ord, unsigned
   switch (a.n_alpha) {
 #define FLSQ_EV32(NA)                                                                                       \
   case NA:                                                                                                 \
-    hipLaunchKernelGGL((k_evaluate_f32<D, NA>), dim3(grid), dim3(kEvalThreads), 0, s, a.n, a.n_q, a.Wt32, a.b32, \
-                       a.coef32, ord, (const float*)a.xq, (float*)a.out);                                  \
+    if (ord.n_sin == 1)                                                                                    \
+      hipLaunchKernelGGL((k_evaluate_f32<D, NA, 1>), dim3(grid), dim3(kEvalThreads), 0, s, a.n, a.n_q, a.Wt32,  \
+                         a.b32, a.coef32, ord, (const float*)a.xq, (float*)a.out);                         \
+    else                                                                                                   \
+      hipLaunchKernelGGL((k_evaluate_f32<D, NA, 0>), dim3(grid), dim3(kEvalThreads), 0, s, a.n, a.n_q, a.Wt32,  \
+                         a.b32, a.coef32, ord, (const float*)a.xq, (float*)a.out);                         \
     break;
     FLSQ_EV32(1) FLSQ_EV32(2) FLSQ_EV32(3) FLSQ_EV32(4) FLSQ_EV32(5) FLSQ_EV32(6) FLSQ_EV32(7) FLSQ_EV32(8)
 #undef FLSQ_EV32

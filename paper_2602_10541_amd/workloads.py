@@ -245,6 +245,20 @@ def heat(n_feat: int = 8192, sigma=(3.0, 3.0, 3.0, 1.5), n_int: int = 65536, n_i
                            "residual_scale_test": -0.3 * PI * PI * ut})
 
 
+def heat_exact_outputs(x: np.ndarray) -> np.ndarray:
+    """The exact solution of the heat workload and its first derivatives at points x (n x 4):
+    columns u, u_x, u_y, u_z, u_t for u = exp(-0.3 pi^2 t) prod_k sin(pi x_k)."""
+    s = np.sin(PI * x[:, :3])
+    c = np.cos(PI * x[:, :3])
+    e = np.exp(-0.3 * PI * PI * x[:, 3])
+    u = e * s[:, 0] * s[:, 1] * s[:, 2]
+    ux = PI * e * c[:, 0] * s[:, 1] * s[:, 2]
+    uy = PI * e * s[:, 0] * c[:, 1] * s[:, 2]
+    uz = PI * e * s[:, 0] * s[:, 1] * c[:, 2]
+    ut = -0.3 * PI * PI * u
+    return np.stack([u, ux, uy, uz, ut], axis=1)
+
+
 def gaussian_source(x: np.ndarray, theta) -> np.ndarray:
     """s(x; theta) = a exp(-|x - c|^2 / (2 w^2)) over the spatial coordinates (x, y)."""
     a, cx, cy, w = theta

@@ -124,6 +124,24 @@ def pde_residuals(name):
     np.savez(os.path.join(OUT, f"{name}.npz"), **out)
 
 
+HEAT_ALPHAS = [(0, 0, 0, 0), (1, 0, 0, 0), (0, 1, 0, 0), (0, 0, 1, 0), (0, 0, 0, 1)]
+
+
+def heat4d_eval(name):
+    """The oracle's FP64 u, u_x, u_y, u_z, u_t of the stored heat solution at 4096 of the 2^20 query
+    points (seeded sample, coordinates rounded to FP32 as the GPU evaluation receives them)."""
+    prob = wl.config("heat4d")
+    g = np.load(os.path.join(OUT, "heat4d.npz"))
+    xq = prob.extras["x_query"]
+    idx = np.sort(np.random.default_rng(23).choice(xq.shape[0], 4096, replace=False))
+    xr = xq[idx].astype(np.float32).astype(np.float64)
+    ref = oracle.evaluate(prob.W, prob.b, g["beta"], xr, HEAT_ALPHAS)
+    np.savez(os.path.join(OUT, f"{name}.npz"), idx=idx, ref=ref)
+    ex = wl.heat_exact_outputs(xr)
+    print(name, "oracle vs exact, rel L2 per output:",
+          [float(np.linalg.norm(ref[:, a] - ex[:, a]) / np.linalg.norm(ex[:, a])) for a in range(5)], flush=True)
+
+
 def sweep(name):
     """All right-hand sides of the sweep from one Householder QR of [A; sqrt(mu) I] (the oracle's
     Tikhonov solve with a matrix right-hand side), u at the test points for each."""
@@ -215,7 +233,7 @@ def bratu(name):
 
 KIND = {"poisson2d": linear, "poisson6d": linear, "heat4d": linear, "reaction2d": newton, "inverse3d": inverse,
         "inverse3d_adam": inverse_adam, "reaction2d_timing": reaction2d_timing,
-        "pde_residuals": pde_residuals,
+        "pde_residuals": pde_residuals, "heat4d_eval": heat4d_eval,
         "helmholtz_sweep": sweep, "helmholtz_bandwidth": bandwidth,
         "varcoef2d": varcoef, "burgers1d": burgers, "bratu2d": bratu}
 

@@ -44,9 +44,10 @@ def test_heat4d_solve_matches_oracle(c4, prec):
 
 
 def test_heat4d_evaluate_1m_points(c4):
-    """FP32 outputs at all 2^20 query points; every output of 4000 sampled points within 2e-5 of
-    norm * sum_j |beta_j| |W_j^alpha| (the FP32 rounding scale of a sum of N products) of the
-    oracle evaluated at the FP32-rounded points."""
+    """FP32 outputs at all 2^20 query points, checked on 2^16 sampled points against the oracle's
+    FP64 evaluation at the FP32-rounded points: per output, relative L2 within 1e-4 (3.4e-5
+    measured, the FP32 rounding of phases near 10 revolutions) and every entry within 1e-6 of
+    norm * sum_j |beta_j| |W_j^alpha| (1.3e-7 measured)."""
     torch, fl = require_gpu()
     prob, dp, gold = c4
     ctx = context()
@@ -59,14 +60,15 @@ def test_heat4d_evaluate_1m_points(c4):
     fl.flsq_evaluate(ctx, dp.basis, bt, xt, ALPHAS, out)
     got = out.double().cpu().numpy()
     assert np.isfinite(got).all()
-    idx = np.random.default_rng(17).choice(xq.shape[0], 4000, replace=False)
+    idx = np.random.default_rng(17).choice(xq.shape[0], 1 << 16, replace=False)
     xr = xq[idx].astype(np.float32).astype(np.float64)
     ref = oracle.evaluate(prob.W, prob.b, beta, xr, ALPHAS)
     for a, al in enumerate(ALPHAS):
         mono = np.prod(np.abs(prob.W) ** np.array(al)[None, :], axis=1)
         scale = np.sum(np.abs(beta) * mono) / math.sqrt(prob.n_feat)
         e = np.abs(got[idx, a] - ref[:, a]).max() / scale
-        assert e <= 2e-5, (al, e)
+        assert e <= 1e-6, (al, e)
+        assert rel_l2(got[idx, a], ref[:, a]) <= 1e-4, (al, rel_l2(got[idx, a], ref[:, a]))
     # the FP64 variant at the test points reproduces the oracle's u to rounding
     xd = torch.tensor(prob.x_test, dtype=torch.float64, device="cuda")
     u64 = torch.empty((prob.x_test.shape[0], 1), dtype=torch.float64, device="cuda")

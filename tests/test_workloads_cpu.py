@@ -53,3 +53,12 @@ def test_heat_f_test_and_scale():
     # the operator d/dt - 0.1 Laplace_x annihilates the exact solution, and the scale is its u_t
     np.testing.assert_allclose(ut - 0.1 * lap, prob.extras["f_test"], atol=1e-5)
     np.testing.assert_allclose(prob.extras["residual_scale_test"], ut, rtol=1e-6, atol=1e-8)
+
+
+def test_heat_exact_outputs_are_u_and_its_gradient():
+    u = lambda x: np.exp(-0.3 * PI * PI * x[:, 3]) * np.prod(np.sin(PI * x[:, :3]), axis=1)
+    x = np.random.default_rng(4).uniform(0, 1, size=(40, 4))
+    ex = wl.heat_exact_outputs(x)
+    np.testing.assert_allclose(ex[:, 0], u(x), rtol=0, atol=1e-15)
+    for k in range(4):
+        np.testing.assert_allclose(ex[:, 1 + k], _fd_first(u, x, k), rtol=1e-7, atol=1e-8)
