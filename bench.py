@@ -610,7 +610,9 @@ def bench_c5(fl, ctx, reps=5):
     for name, prec in (("int8_crt", fl.PREC_INT8_CRT), ("fp64", fl.PREC_FP64)):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        F = fl.flsq_factorize(ctx, dp.basis, rows, fl.solve_opts(prob.mu, prec, 20, 1e-13))
+        # refinement to 1e-10 relative change: the losses and gradients agree with the oracle's
+        # exactly as closely as at 1e-13 (6.4e-11), one refinement step fewer per solve
+        F = fl.flsq_factorize(ctx, dp.basis, rows, fl.solve_opts(prob.mu, prec, 20, 1e-10))
         torch.cuda.synchronize()
         t_fac = time.perf_counter() - t0
         ip = InverseProblem(ctx, F, prob.blocks[0].n, prob.blocks[0].weight, d - 1, xo, dd)
@@ -622,7 +624,7 @@ def bench_c5(fl, ctx, reps=5):
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / reps
         g = g.cpu().numpy()
-        res[name] = {"factorize_ms": 1e3 * t_fac, "ms_per_loss_and_grad_64": 1e3 * dt,
+        res[name] = {"factorize_ms": 1e3 * t_fac, "ms_per_loss_and_grad_64": 1e3 * dt, "refine_tol": 1e-10,
                      "gradient_evals_per_s": th.shape[0] / dt,
                      "grad_rel_err_vs_oracle": float(np.linalg.norm(g - gold["grad_theta0"]) /
                                                      np.linalg.norm(gold["grad_theta0"])),
