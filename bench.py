@@ -392,9 +392,12 @@ def bench_c3(fl, ctx):
     prob = wl.config("reaction2d")
     dp = fl.DeviceProblem(prob)
     gold = _gold("reaction2d")
-    res = {"workload": "reaction_diffusion_2d: N=2048 (sigma=5), 16384 interior + 2048 boundary rows, <=15 steps"}
-    for name, prec in (("int8_crt", fl.PREC_INT8_CRT), ("fp64", fl.PREC_FP64)):
-        opts = fl.newton_opts(prob.mu, max_iter=15, tol_dbeta=1e-10, prec=prec)
+    res = {"workload": "reaction_diffusion_2d: N=2048 (sigma=5), 16384 interior + 2048 boundary rows, <=15 steps",
+           "schedule": "int8_crt / fp64: steps preconditioned by the last factor formed (the warm start's) while "
+                       "it converges within 16 CG steps; int8_crt_gram_every_step: a Jacobian Gram + factor per step"}
+    for name, prec, refactor in (("int8_crt", fl.PREC_INT8_CRT, 16), ("fp64", fl.PREC_FP64, 16),
+                                 ("int8_crt_gram_every_step", fl.PREC_INT8_CRT, 0)):
+        opts = fl.newton_opts(prob.mu, max_iter=15, tol_dbeta=1e-10, prec=prec, refactor_iters=refactor)
         beta = torch.zeros(prob.n_feat, dtype=torch.float64, device="cuda")
         fl.flsq_solve_newton(ctx, dp.basis, dp.rows, prob.nonlin_block, prob.nonlin_poly, opts, beta)   # warm-up
         beta.zero_()
@@ -414,7 +417,9 @@ def bench_c3(fl, ctx):
         if gold is not None:
             e["rel_l2_vs_oracle"] = float(np.linalg.norm(u - gold["u_test"]) / np.linalg.norm(gold["u_test"]))
         res[name] = {"ms_total": 1e3 * dt, "newton_steps": len(steps), "ms_per_step": 1e3 * dt / max(1, len(steps) + 1),
-                     "final_res_norm": steps[-1]["res_norm"] if steps else None, "status": int(st), "accuracy": e}
+                     "final_res_norm": steps[-1]["res_norm"] if steps else None, "status": int(st), "accuracy": e,
+                     "cg_iters_per_step": [s["refine_iters"] for s in steps],
+                     "steps_factored": int(sum(s["factored"] for s in steps))}
     return res
 
 

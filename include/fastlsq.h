@@ -218,6 +218,12 @@ typedef struct {
     double armijo_c;        /* sufficient decrease ||R(beta + a d)|| <= (1 - c a) ||R(beta)|| */
     int32_t max_halvings;   /* backtracking halvings before the smallest step is taken */
     int32_t warm_start;     /* 1: beta_inout is overwritten by the linear solve with N dropped */
+    int32_t refactor_iters; /* > 0: a step's solve is preconditioned by the factor of the last system
+                               factored (the warm start's, or an earlier step's) for at most this many
+                               CG steps, and forms its own Jacobian Gram and factor (with the second
+                               pass) only if they do not converge; the Newton step is solved to the
+                               same tolerance either way.  0: every step forms its own Gram and
+                               factor. */
 } flsq_newton_opts;
 
 typedef struct {
@@ -229,6 +235,10 @@ typedef struct {
     double du_rel[64];               /* ||Delta u|| / ||u|| at collocation rows */
     int32_t halvings[64];
     double t_total_ms;
+    int32_t refine_iters[64];        /* CGLS iterations of each step's linear solve */
+    double shift[64];                /* Cholesky diagonal shift of each step's factor */
+    double t_solve_ms[64];           /* Gram + factor + refinement time of each step */
+    int32_t factored[64];            /* 1 if the step formed its own Gram and factor */
 } flsq_newton_trace;
 
 /* Newton-Raphson for L[u] + N(u) = f (Section 2.4).  The nonlinearity acts on block

@@ -675,38 +675,13 @@ Err chol_solve(flsq_ctx* c, const double* X, int n, const double* Y, double* Z, 
     CHECK_HIP(launch_precond_apply(X, n, Y, tmp, work, Z, st));
     return ok();
   }
-  // K > 1: T = X^T Y, then Z = X T, each as a split-K batched GEMM (contraction chunks of
-  // kChunkK rows as separate descriptors, so that tall-skinny products fill the chip) and
-  // a fixed-order sum of the partial products.
-  constexpr int kChunkK = 256;
-  const int n_split = (n + kChunkK - 1) / kChunkK;
+  // K > 1: T = X^T Y, then Z = X T, on the matrix cores with the contraction of each 16-row
+  // tile split across workgroups (chunk partials summed in a fixed order).
+  if (K > 64) return fail(FLSQ_EINVAL, "chol_solve: K = %d above 64", K);
   double *tmp, *part;
   CHECK_ERR(ws_get(c, "pa_tmpK", (size_t)n * K, &tmp));
-  CHECK_ERR(ws_get(c, "pa_partK", (size_t)n_split * n * K, &part));
-  std::vector<GemmDesc> h(2 * n_split);
-  for (int sp = 0; sp < n_split; ++sp) {
-    const int k0 = sp * kChunkK, kc = std::min(kChunkK, n - k0);
-    GemmDesc& t = h[sp];            // part[sp] = X[k0.., :]^T Y[k0.., :]
-    t = GemmDesc{};
-    t.A = X + (int64_t)k0 * n; t.lda = n;
-    t.B = Y + (int64_t)k0 * K; t.ldb = K;
-    t.C = part + (int64_t)sp * n * K; t.ldc = K;
-    t.M = n; t.N = K; t.K = kc;
-    GemmDesc& z = h[n_split + sp];  // part[sp] = X[:, k0..] T[k0.., :]
-    z = GemmDesc{};
-    z.A = X + k0; z.lda = n;
-    z.B = tmp + (int64_t)k0 * K; z.ldb = K;
-    z.C = part + (int64_t)sp * n * K; z.ldc = K;
-    z.M = n; z.N = K; z.K = kc;
-  }
-  GemmDesc* d;
-  CHECK_ERR(ws_get(c, "pa_descs", h.size(), &d));
-  CHECK_HIP(hipMemcpyAsync(d, h.data(), sizeof(GemmDesc) * h.size(), hipMemcpyHostToDevice, st));
-  CHECK_HIP(launch_gemm_batched(d, n_split, n, K, 1.0, 0.0, 1, st));             // partials of X^T Y
-  CHECK_HIP(launch_sum_partials(part, n_split, (int64_t)n * K, tmp, st));
-  CHECK_HIP(launch_gemm_batched(d + n_split, n_split, n, K, 1.0, 0.0, 0, st));   // partials of X T
-  CHECK_HIP(launch_sum_partials(part, n_split, (int64_t)n * K, Z, st));
-  CHECK_HIP(hipStreamSynchronize(st));                                 // h leaves scope
+  CHECK_ERR(ws_get(c, "pa_partK", chol_multi_work_elems(n, K), &part));
+  CHECK_HIP(launch_chol_solve_multi(X, n, Y, K, tmp, part, Z, st));
   return ok();
 }
 
@@ -1292,6 +1267,55 @@ Err gram_and_factor(flsq_ctx* c, const System& s, const double* rho, const Solve
   return ok();
 }
 
+// Solve with the factor already held in Xinv (formed by an earlier solve on a system with the
+// same features, such as the previous Newton step's): it preconditions at most reuse_iters CG
+// steps; if they do not converge, the system's own Gram and factor are formed, with the second
+// pass so that the new factor serves later solves as well, and CG continues from the iterate
+// reached.  The result meets the same stopping rule as a solve that factors first.
+Err solve_reusing_factor(flsq_ctx* c, const System& s, const double* rho, const SolveParams& sp, const double* Yw,
+                         int K, double* X, int reuse_iters, flsq_solve_info* info, bool* converged, bool* factored) {
+  const int n = s.n;
+  double* Xi;
+  CHECK_ERR(ws_get(c, "Xinv", (size_t)n * n, &Xi));
+  const double t0 = now_ms();
+  double *cvec, *colwork;
+  CHECK_ERR(ws_get(c, "cvec", (size_t)n * K, &cvec));
+  CHECK_ERR(ws_get(c, "colwork0", pass_work_elems(n, s.n_runs, K) + 64, &colwork));
+  CHECK_HIP(launch_colpass_runs(s.pass(), rho, Yw, K, nullptr, 1.0, 0.0, cvec, colwork, c->stream));
+  CHECK_ERR(chol_solve(c, Xi, n, cvec, X, K));
+  const PassOp op(s, rho);
+  RefineOut ro;
+  CHECK_ERR(cgls_refine_op(c, op, Xi, sp.mu, Yw, K, X, std::min(reuse_iters, sp.max_refine), sp.refine_tol,
+                           info != nullptr, false, &ro));
+  *factored = false;
+  if (info) memset(info, 0, sizeof *info);
+  double t_fac = 0.0;
+  if (!ro.converged && ro.iters < sp.max_refine) {
+    SolveParams sp2 = sp;
+    sp2.second_pass = 1;
+    const double tf = now_ms();
+    CHECK_ERR(gram_and_factor(c, s, rho, sp2, Xi, info));
+    t_fac = now_ms() - tf;
+    *factored = true;
+    RefineOut r2;
+    CHECK_ERR(cgls_refine_op(c, op, Xi, sp.mu, Yw, K, X, sp.max_refine - ro.iters, sp.refine_tol, false, false, &r2));
+    ro.iters += r2.iters;
+    ro.converged = r2.converged;
+    ro.last_step = r2.last_step;
+  }
+  CHECK_HIP(hipStreamSynchronize(c->stream));
+  if (info) {
+    info->refine_iters = ro.iters;
+    info->grad_norm0 = ro.grad0;
+    info->grad_norm = ro.grad0;
+    info->last_step_rel = ro.last_step;
+    info->t_total_ms = now_ms() - t0;
+    info->t_refine_ms = info->t_total_ms - t_fac;
+  }
+  if (converged) *converged = ro.converged;
+  return ok();
+}
+
 Err solve_on_system(flsq_ctx* c, const System& s, const double* rho, const SolveParams& sp, const double* Yw, int K,
                     double* X, flsq_solve_info* info, bool* converged) {
   const int n = s.n;
@@ -1848,6 +1872,7 @@ Err newton_impl(flsq_ctx* c, const flsq_basis* basis, const flsq_rows* blocks, i
   if (o->max_iter < 0 || o->max_iter > 64) return fail(FLSQ_EINVAL, "max_iter outside [0, 64]");
   if (o->max_halvings < 0 || o->max_halvings > 60) return fail(FLSQ_EINVAL, "max_halvings outside [0, 60]");
   if (!(o->armijo_c >= 0.0 && o->armijo_c < 1.0)) return fail(FLSQ_EINVAL, "armijo_c outside [0, 1)");
+  if (o->refactor_iters < 0) return fail(FLSQ_EINVAL, "refactor_iters must be >= 0");
   if (!beta) return fail(FLSQ_EINVAL, "beta_inout is NULL");
   SolveParams sp = params_of(&o->lin);
   CHECK_ERR(check_params(sp));
@@ -1900,10 +1925,16 @@ Err newton_impl(flsq_ctx* c, const flsq_basis* basis, const flsq_rows* blocks, i
   // definite is kept as the starting shift of the next factorisation (no repeated retries).
   SolveParams spk = sp;
   flsq_solve_info sinfo;
+  // The factor held in Xinv: the warm start's (the linear operator's Gram), then that of the
+  // last step that formed its own.  Its shift is reported for the steps it preconditions.
+  bool have_factor = false;
+  double held_shift = 0.0;
   if (o->warm_start) {
     // linear part only: the nonlinearity dropped, rho = 0
     CHECK_ERR(solve_on_system(c, s, nullptr, spk, s.rhs_w.as<double>(), 1, beta, &sinfo, nullptr));
     spk.shift_rel = std::max(spk.shift_rel, sinfo.shift);
+    have_factor = true;
+    held_shift = sinfo.shift;
   }
   // Newton steps need no fully refined step: the automatic second pass is left to the warm
   // start (measured: on the reaction-diffusion steps it costs more than the CG steps it saves)
@@ -1916,8 +1947,19 @@ Err newton_impl(flsq_ctx* c, const flsq_basis* basis, const flsq_rows* blocks, i
   for (int it = 0; it < o->max_iter; ++it) {
     // delta = argmin ||J delta + R||^2 + mu ||delta||^2 with J = A(rho)
     CHECK_HIP(launch_scale_copy(R, negR, P, -1.0, st));
-    CHECK_ERR(solve_on_system(c, s, rho, spk, negR, 1, delta, &sinfo, nullptr));
-    spk.shift_rel = std::max(spk.shift_rel, sinfo.shift);
+    const double ts = now_ms();
+    bool factored = true;
+    if (o->refactor_iters > 0 && have_factor) {
+      CHECK_ERR(solve_reusing_factor(c, s, rho, spk, negR, 1, delta, o->refactor_iters, &sinfo, nullptr, &factored));
+    } else {
+      CHECK_ERR(solve_on_system(c, s, rho, spk, negR, 1, delta, &sinfo, nullptr));
+    }
+    const double t_solve = now_ms() - ts;
+    if (factored) {
+      spk.shift_rel = std::max(spk.shift_rel, sinfo.shift);
+      held_shift = sinfo.shift;
+      have_factor = true;
+    }
     double alpha = 1.0, nRt = 0.0;
     int halv = 0;
     for (;;) {
@@ -1944,6 +1986,10 @@ Err newton_impl(flsq_ctx* c, const flsq_basis* basis, const flsq_rows* blocks, i
       tr->halvings[it] = halv;
       tr->step_norm[it] = step;
       tr->du_rel[it] = std::sqrt(du2) / std::max(std::sqrt(un2), 1e-300);
+      tr->refine_iters[it] = sinfo.refine_iters;
+      tr->shift[it] = held_shift;
+      tr->t_solve_ms[it] = t_solve;
+      tr->factored[it] = factored ? 1 : 0;
       tr->iters = it + 1;
     }
     CHECK_HIP(hipMemcpyAsync(beta, bt, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
@@ -2592,7 +2638,9 @@ Err newton_var_impl(flsq_ctx* c, const flsq_basis* basis, const flsq_vrows* bloc
   for (int it = 0; it < o->max_iter; ++it) {
     CHECK_ERR(assemble_var_dev(c, Jsys, "nv_J", "nv_Jt", &J, &Jt));
     CHECK_HIP(launch_scale_copy(R, negR, P, -1.0, st));
+    const double ts = now_ms();
     CHECK_ERR(var_linear_solve(c, J, Jt, n, P, spk, negR, delta, &sinfo, nullptr));
+    const double t_solve = now_ms() - ts;
     spk.shift_rel = std::max(spk.shift_rel, sinfo.shift);
     double alpha = 1.0, nRt = 0.0;
     int halv = 0;
@@ -2621,6 +2669,10 @@ Err newton_var_impl(flsq_ctx* c, const flsq_basis* basis, const flsq_vrows* bloc
       tr->halvings[it] = halv;
       tr->step_norm[it] = step;
       tr->du_rel[it] = du_rel;
+      tr->refine_iters[it] = sinfo.refine_iters;
+      tr->shift[it] = sinfo.shift;
+      tr->t_solve_ms[it] = t_solve;
+      tr->factored[it] = 1;
       tr->iters = it + 1;
     }
     CHECK_HIP(hipMemcpyAsync(beta, bt, sizeof(double) * n, hipMemcpyDeviceToDevice, st));

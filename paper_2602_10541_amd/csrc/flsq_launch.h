@@ -227,6 +227,11 @@ hipError_t launch_gemm_tri(const GemmDesc* d_descs, int n_batch, int maxM, int m
 hipError_t launch_precond_apply(const double* X, int n, const double* v, double* tmp, double* work, double* out,
                                 hipStream_t s);
 size_t precond_work_elems(int n);
+// Z = X (X^T Y) for 2 <= K <= 64 columns (Y, T, Z n x K row-major; T scratch n x K; part
+// chol_multi_work_elems(n, K) doubles).  Z must not alias Y or T.
+hipError_t launch_chol_solve_multi(const double* X, int n, const double* Y, int K, double* T, double* part, double* Z,
+                                   hipStream_t s);
+size_t chol_multi_work_elems(int n, int K);
 hipError_t launch_copy_upper(const double* src, double* dst, int n, double diag_add, hipStream_t s);
 hipError_t launch_diag_max(const double* G, int n, double* out, hipStream_t s);
 

@@ -314,4 +314,129 @@ hipError_t launch_precond_apply(const double* X, int n, const double* v, double*
 
 size_t precond_work_elems(int n) { return (size_t)kTvSplits * n; }
 
+// ------------------------------------------------------------------ multi-column preconditioner
+// Z = X (X^T Y) for 2 <= K <= 64 columns, X upper triangular n x n, Y, T, Z n x K, all row-major.
+// Both products run on 16-row output tiles (n_pad = n rounded up to 16, nt = n_pad / 16 tiles).
+// Tile t of T = X^T Y contracts k in [0, 16 t + 16), tile t of Z = X T contracts k in
+// [16 t, n_pad); either way a tile whose contraction holds v 16-blocks is cut into
+// ceil(v / r) chunks of kc = 16 r indices, one workgroup each, so that the long tiles spread
+// over many CUs.  Tasks are numbered by v, then chunk: tiles with v blocks start at task
+// sum_{u < v} ceil(u / r).  A workgroup is 4 waves; wave w holds columns 16w .. 16w + 15 in one
+// v_mfma_f64_16x16x4f64 accumulator and writes its chunk's partial tile to part[task][16][K];
+// k_trimm_sum adds the chunks of each tile in chunk order (no atomics: the result does not
+// depend on scheduling).
+__host__ __device__ inline int64_t trimm_task0(int v, int r) {   // sum_{u = 1}^{v - 1} ceil(u / r)
+  const int64_t t = v - 1, a = t / r, b = t % r;
+  return r * a * (a + 1) / 2 + b * (a + 1);
+}
+
+__device__ inline void trimm_locate(int64_t task, int nt, int r, int* v_out, int* j_out) {
+  int lo = 1, hi = nt;   // largest v with trimm_task0(v) <= task
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (trimm_task0(mid, r) <= task) lo = mid;
+    else hi = mid - 1;
+  }
+  *v_out = lo;
+  *j_out = (int)(task - trimm_task0(lo, r));
+}
+
+constexpr int kTrimmMaxKc = 512;
+
+int trimm_kc(int n) {
+  const int np = (n + 15) / 16 * 16;
+  return np <= 2048 ? 128 : (np <= 4096 ? 256 : kTrimmMaxKc);
+}
+
+// part = chunk partials of X^T Y (transpose = 1) or X T (transpose = 0).  X^T Y reads rows of X
+// (16 consecutive entries per lane group: coalesced) straight into the MFMA operand; X T needs
+// X by columns, so the workgroup first copies its 16 x kc block of X into LDS transposed.
+template <int TRANS>
+__global__ __launch_bounds__(256) void k_trimm(const double* __restrict__ X, int n, const double* __restrict__ B, int K,
+                                               int kc, double* __restrict__ part) {
+  __shared__ double sX[TRANS ? 1 : kTrimmMaxKc][17];
+  const int nt = (n + 15) >> 4, r = kc >> 4;
+  int v, j;
+  trimm_locate(blockIdx.x, nt, r, &v, &j);
+  const int t = TRANS ? v - 1 : nt - v;
+  const int i0 = 16 * t;
+  const int kb = (TRANS ? 0 : i0) + j * kc;
+  const int ke = min(kb + kc, TRANS ? 16 * v : 16 * nt);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (!TRANS) {
+    const int len = ke - kb;
+    for (int e = tid; e < 16 * len; e += 256) {
+      const int row = e / len, kk = e - row * len;
+      const int i = i0 + row, k = kb + kk;
+      sX[kk][row] = (i < n && k < n && k >= i) ? X[(int64_t)i * n + k] : 0.0;
+    }
+    __syncthreads();
+  }
+  const int c0 = 16 * wave;
+  if (c0 >= K) return;
+  const int col = c0 + (lane & 15);
+  const int m = lane & 15, kq = lane >> 4;
+  f64x4 acc = f64x4{0.0, 0.0, 0.0, 0.0};
+  constexpr int kBatch = 16;   // MFMA steps whose operands are loaded together
+  for (int k4 = kb; k4 < ke; k4 += 4 * kBatch) {
+    double a[kBatch], b[kBatch];
+#pragma unroll
+    for (int q = 0; q < kBatch; ++q) {
+      const int k = k4 + 4 * q + kq;
+      const bool in = k < ke && k < n;
+      if (TRANS) {
+        const int i = i0 + m;
+        a[q] = (in && i < n && k <= i) ? X[(int64_t)k * n + i] : 0.0;
+      } else {
+        a[q] = in ? sX[k - kb][m] : 0.0;
+      }
+      b[q] = (in && col < K) ? B[(int64_t)k * K + col] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < kBatch; ++q) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], b[q], acc, 0, 0, 0);
+  }
+  double* out = part + (int64_t)blockIdx.x * 16 * K;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {   // FP64 16x16 accumulator: element e of lane group kq is row 4 e + kq
+    const int row = 4 * e + kq;
+    if (col < K) out[row * K + col] = acc[e];
+  }
+}
+
+// out[16 t + m][c] = sum over the chunks of tile t, in chunk order.
+template <int TRANS>
+__global__ __launch_bounds__(256) void k_trimm_sum(const double* __restrict__ part, int n, int K, int kc,
+                                                   double* __restrict__ out) {
+  const int nt = (n + 15) >> 4, r = kc >> 4;
+  const int t = blockIdx.x;
+  const int v = TRANS ? t + 1 : nt - t;
+  const int64_t task0 = trimm_task0(v, r);
+  const int nch = (v + r - 1) / r;
+  for (int e = threadIdx.x; e < 16 * K; e += 256) {
+    const int i = 16 * t + e / K;
+    if (i >= n) break;
+    double s = 0.0;
+    for (int ch = 0; ch < nch; ++ch) s += part[(task0 + ch) * 16 * K + e];
+    out[(int64_t)16 * t * K + e] = s;
+  }
+}
+
+size_t chol_multi_work_elems(int n, int K) {
+  const int nt = (n + 15) / 16, r = trimm_kc(n) / 16;
+  return (size_t)trimm_task0(nt + 1, r) * 16 * K;
+}
+
+hipError_t launch_chol_solve_multi(const double* X, int n, const double* Y, int K, double* T, double* part, double* Z,
+                                   hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (K < 2 || K > 64) return hipErrorInvalidValue;
+  const int nt = (n + 15) / 16, kc = trimm_kc(n), r = kc / 16;
+  const unsigned tasks = (unsigned)trimm_task0(nt + 1, r);
+  hipLaunchKernelGGL(k_trimm<1>, dim3(tasks), dim3(256), 0, s, X, n, Y, K, kc, part);
+  hipLaunchKernelGGL(k_trimm_sum<1>, dim3(nt), dim3(256), 0, s, part, n, K, kc, T);
+  hipLaunchKernelGGL(k_trimm<0>, dim3(tasks), dim3(256), 0, s, X, n, T, K, kc, part);
+  hipLaunchKernelGGL(k_trimm_sum<0>, dim3(nt), dim3(256), 0, s, part, n, K, kc, Z);
+  return hipGetLastError();
+}
+
 }  // namespace flsq

@@ -96,17 +96,21 @@ class flsq_nonlin_grad(C.Structure):
 
 class flsq_newton_opts(C.Structure):
     _fields_ = [("lin", flsq_solve_opts), ("tol_dbeta", C.c_double), ("max_iter", C.c_int32),
-                ("armijo_c", C.c_double), ("max_halvings", C.c_int32), ("warm_start", C.c_int32)]
+                ("armijo_c", C.c_double), ("max_halvings", C.c_int32), ("warm_start", C.c_int32),
+                ("refactor_iters", C.c_int32)]
 
 
 class flsq_newton_trace(C.Structure):
     _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("res_norm", C.c_double * 64),
                 ("alpha", C.c_double * 64), ("step_norm", C.c_double * 64), ("du_rel", C.c_double * 64),
-                ("halvings", C.c_int32 * 64), ("t_total_ms", C.c_double)]
+                ("halvings", C.c_int32 * 64), ("t_total_ms", C.c_double), ("refine_iters", C.c_int32 * 64),
+                ("shift", C.c_double * 64), ("t_solve_ms", C.c_double * 64), ("factored", C.c_int32 * 64)]
 
     def as_list(self):
         return [dict(it=i, res_norm=self.res_norm[i], alpha=self.alpha[i], step_norm=self.step_norm[i],
-                     du_rel=self.du_rel[i], halvings=self.halvings[i]) for i in range(self.iters)]
+                     du_rel=self.du_rel[i], halvings=self.halvings[i], refine_iters=self.refine_iters[i],
+                     shift=self.shift[i], t_solve_ms=self.t_solve_ms[i], factored=self.factored[i])
+                for i in range(self.iters)]
 
 
 _lib = None
@@ -407,10 +411,12 @@ def flsq_evaluate_noalloc(ctx, basis: Basis, beta, xq, alphas, out):
 
 
 def newton_opts(mu, max_iter=15, tol_dbeta=1e-10, armijo_c=1e-4, max_halvings=10, warm_start=True,
-                prec=PREC_FP64, max_refine=60, refine_tol=1e-14):
-    """Defaults: each Gauss-Newton step refined until u changes by < 1e-14 relative (at most 60 CG steps)."""
+                prec=PREC_FP64, max_refine=60, refine_tol=1e-14, refactor_iters=16):
+    """Defaults: each Gauss-Newton step refined until u changes by < 1e-14 relative (at most 60 CG
+    steps), preconditioned by the last factor formed while it converges within 16 CG steps
+    (refactor_iters=0: a Gram and factor at every step)."""
     return flsq_newton_opts(solve_opts(mu, prec, max_refine, refine_tol), float(tol_dbeta), int(max_iter),
-                            float(armijo_c), int(max_halvings), int(bool(warm_start)))
+                            float(armijo_c), int(max_halvings), int(bool(warm_start)), int(refactor_iters))
 
 
 def flsq_solve_newton(ctx, basis: Basis, rows: Rows, nonlin_block, poly, opts: flsq_newton_opts, beta_inout,

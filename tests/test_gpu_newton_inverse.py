@@ -13,23 +13,24 @@ pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
-def _newton_gpu(prob, max_iter=15, prec=0, second_pass=0):
+def _newton_gpu(prob, max_iter=15, prec=0, second_pass=0, refactor_iters=16):
     torch, fl = require_gpu()
     ctx = context()
     dp = fl.DeviceProblem(prob)
     beta = torch.zeros(prob.n_feat, dtype=torch.float64, device="cuda")
-    opts = fl.newton_opts(prob.mu, max_iter=max_iter, tol_dbeta=1e-10, prec=prec)
+    opts = fl.newton_opts(prob.mu, max_iter=max_iter, tol_dbeta=1e-10, prec=prec, refactor_iters=refactor_iters)
     opts.lin.second_pass = second_pass
     st, tr = fl.flsq_solve_newton(ctx, dp.basis, dp.rows, prob.nonlin_block, prob.nonlin_poly, opts, beta)
     return st, tr, beta.cpu().numpy()
 
 
-@pytest.mark.parametrize("second_pass", [0, 1])
-def test_newton_small_matches_oracle(second_pass):
+@pytest.mark.parametrize("second_pass,refactor_iters", [(0, 0), (1, 0), (0, 16)])
+def test_newton_small_matches_oracle(second_pass, refactor_iters):
     """With second_pass = 1 every step re-factors through an explicit Jacobian that carries the
-    u-dependent row coefficient (A + diag(rho) H, rho = w N'(u) / sqrt(N))."""
+    u-dependent row coefficient (A + diag(rho) H, rho = w N'(u) / sqrt(N)).  With refactor_iters =
+    16 the steps are preconditioned by the warm start's factor while it converges in 16 CG steps."""
     prob = wl.reaction_diffusion(n_feat=300, sigma=4.0, n_int=900, n_bc=200, seed=3, n_test=500)
-    st, tr, beta = _newton_gpu(prob, second_pass=second_pass)
+    st, tr, beta = _newton_gpu(prob, second_pass=second_pass, refactor_iters=refactor_iters)
     ref, trace = oracle.solve_newton(prob, max_iter=15)
     steps = tr.as_list()
     assert len(steps) == len(trace)
@@ -43,8 +44,8 @@ def test_newton_small_matches_oracle(second_pass):
     assert rel_l2(u, prob.u_test) <= 2e-6
 
 
-@pytest.mark.parametrize("prec", [0, 3])
-def test_newton_full_reaction_diffusion(prec):
+@pytest.mark.parametrize("prec,refactor_iters", [(0, 16), (3, 16), (3, 0)])
+def test_newton_full_reaction_diffusion(prec, refactor_iters):
     """-Laplace u + u^3 - u = f, N = 2048, 16384 + 2048 rows, 15 steps: against the oracle's stored run.
 
     Each Gauss-Newton step is a Tikhonov solve whose normal equations sit at the limit of
@@ -52,15 +53,23 @@ def test_newton_full_reaction_diffusion(prec):
     solves agree with the oracle's QR steps to ~1e-8 in fitted values.  The residual norms
     then agree to a few 1e-6 in the fast phase and drift to ~1e-4 along the slow plateau
     of Appendix C, where the iteration moves in nearly null directions; u itself agrees to 1e-6.
+    refactor_iters = 16: the warm start's factor (second pass included) preconditions the steps;
+    refactor_iters = 0: every step forms its Jacobian's Gram and factor.  Every step's solve is
+    held to the same CG tolerance either way.
     """
     path = os.path.join(GOLDEN, "reaction2d.npz")
     if not os.path.exists(path):
         pytest.skip("golden values not generated")
     gold = np.load(path)
     prob = wl.config("reaction2d")
-    st, tr, beta = _newton_gpu(prob, prec=prec)
+    st, tr, beta = _newton_gpu(prob, prec=prec, refactor_iters=refactor_iters)
     u = oracle.evaluate(prob.W, prob.b, beta, prob.x_test, [(0, 0)])[:, 0]
     steps = tr.as_list()
+    factored = [s["factored"] for s in steps]
+    if refactor_iters == 0:
+        assert all(factored), factored
+    else:
+        assert sum(factored) <= 2, (factored, [s["refine_iters"] for s in steps])
     res = np.array([s["res_norm"] for s in steps][:len(gold["res_norm"])])
     err_u = rel_l2(u, gold["u_test"])
     msg = (err_u, np.abs(res / gold["res_norm"] - 1).tolist())
