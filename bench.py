@@ -353,7 +353,8 @@ def bench_sweep(fl, ctx, reps=3):
         return (time.perf_counter() - t0) / n
 
     for name, prec in (("int8_crt", fl.PREC_INT8_CRT), ("fp64", fl.PREC_FP64)):
-        opts = fl.solve_opts(prob.mu, prec, 30, 1e-12)
+        # the factor keeps A and A^T for the 64-column products (flsq_solve_linear ignores the flag)
+        opts = fl.solve_opts(prob.mu, prec, 30, 1e-12, store_matrix=True)
         fl.flsq_factorize(ctx, dp.basis, dp.rows, opts).free()
         holder = {}
 
@@ -611,16 +612,25 @@ def bench_c5(fl, ctx, reps=5):
     xo = torch.tensor(prob.extras["x_obs"], dtype=torch.float64, device="cuda")
     dd = torch.tensor(gold["data"], dtype=torch.float64, device="cuda")
     th = torch.tensor(prob.extras["theta0"], dtype=torch.float64, device="cuda")
-    res = {"workload": "inverse_heat_2d+t: N=2048 (sigma=4), 12288 rows, 400 observations, 64 hypotheses"}
-    for name, prec in (("int8_crt", fl.PREC_INT8_CRT), ("fp64", fl.PREC_FP64)):
+    res = {"workload": "inverse_heat_2d+t: N=2048 (sigma=4), 12288 rows, 400 observations, 64 hypotheses",
+           "products": "int8_crt / fp64: the factor keeps A and A^T (2 x 201 MB) and the 64-column products "
+                       "stream them through the FP64 matrix cores; *_matrix_free: the entries recomputed per pass; "
+                       "ms_per_loss_and_grad_64 is the full call (theta and kappa gradients: two refined solves); "
+                       "observation_operator: theta gradients through the kept R = H G^-1 A_src^T (the Adam steps)"}
+    for name, prec, store in (("int8_crt", fl.PREC_INT8_CRT, True), ("fp64", fl.PREC_FP64, True),
+                              ("int8_crt_matrix_free", fl.PREC_INT8_CRT, False)):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         # refinement to 1e-10 relative change: the losses and gradients agree with the oracle's
         # exactly as closely as at 1e-13 (6.4e-11), one refinement step fewer per solve
-        F = fl.flsq_factorize(ctx, dp.basis, rows, fl.solve_opts(prob.mu, prec, 20, 1e-10))
+        F = fl.flsq_factorize(ctx, dp.basis, rows, fl.solve_opts(prob.mu, prec, 20, 1e-10, store_matrix=store))
         torch.cuda.synchronize()
         t_fac = time.perf_counter() - t0
-        ip = InverseProblem(ctx, F, prob.blocks[0].n, prob.blocks[0].weight, d - 1, xo, dd)
+        cached = name == "int8_crt"
+        t0 = time.perf_counter()
+        ip = InverseProblem(ctx, F, prob.blocks[0].n, prob.blocks[0].weight, d - 1, xo, dd, cache_observations=cached)
+        torch.cuda.synchronize()
+        t_prep = time.perf_counter() - t0
         ip.loss_and_grad(th)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -635,7 +645,22 @@ def bench_c5(fl, ctx, reps=5):
                                                      np.linalg.norm(gold["grad_theta0"])),
                      "loss_rel_err_vs_oracle": float(np.max(np.abs(loss.cpu().numpy() - gold["loss0"]) /
                                                             np.abs(gold["loss0"])))}
-        if name == "int8_crt":
+        if cached:
+            # theta gradients alone through the kept observation operator (what the Adam steps use)
+            ip.loss_and_grad(th, want_kappa=False)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(4 * reps):
+                lc, gc, _ = ip.loss_and_grad(th, want_kappa=False)
+            torch.cuda.synchronize()
+            dtc = (time.perf_counter() - t0) / (4 * reps)
+            gc = gc.cpu().numpy()
+            res[name]["observation_operator"] = {
+                "prepare_ms": 1e3 * t_prep, "ms_per_theta_grad_64": 1e3 * dtc,
+                "grad_rel_err_vs_oracle": float(np.linalg.norm(gc - gold["grad_theta0"]) /
+                                                np.linalg.norm(gold["grad_theta0"])),
+                "loss_rel_err_vs_oracle": float(np.max(np.abs(lc.cpu().numpy() - gold["loss0"]) /
+                                                       np.abs(gold["loss0"])))}
             # the workload's 200 batched Adam steps (lr 1e-2, width clamped at 0.02) on the device
             p = th.clone()
             m = torch.zeros_like(p)

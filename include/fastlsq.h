@@ -106,14 +106,19 @@ typedef struct {
                              Grams.  0 = automatic (FP64 and INT8_CRT Grams): at factorisation when the
                              first Cholesky needed a diagonal shift and 2 P N^2 <= 2e11, and in the
                              one-call solvers also after 8 refinement steps that did not converge when
-                             2 P N^2 <= 4e10; Newton steps take it only when asked for.  1 = always
-                             (same precisions); -1 = never */
+                             2 P N^2 <= 4e10; Newton steps take it when asked for, and when a step
+                             forms the factor that later steps reuse (flsq_newton_opts.refactor_iters).
+                             1 = always (same precisions); -1 = never */
     double pivot_boost;   /* modified Cholesky (Gill and Murray): > 0 raises pivots of the unit-diagonal
                              equilibrated Gram below this value to it during the factorisation, so a
                              Gram that rounding left indefinite factors without a restart unless the
                              raised pivots make entries overflow; 0 = off: a non-positive pivot
                              restarts the factorisation with a diagonal shift (see shift_rel);
                              must be in [0, 1) */
+    int32_t store_matrix; /* flsq_factorize only: 1 keeps A and A^T (2 P N doubles) in HBM with the
+                             factor, and its products with more than 16 columns (solves, refinement,
+                             flsq_apply_A / _At, the inverse-problem calls) stream them through the
+                             FP64 matrix cores instead of recomputing the entries; 0 = matrix-free */
 } flsq_solve_opts;
 
 typedef struct {
@@ -268,6 +273,20 @@ flsq_status flsq_inverse_loss_grad(flsq_ctx* ctx, const flsq_factor* F, int64_t 
                                    int32_t n_lap_dims, const double* thetas, int32_t K, int64_t n_obs,
                                    const double* x_obs, const double* data, double* loss_out,
                                    double* grad_theta_out, double* grad_kappa_out);
+
+/* Observation operator of the factored system (the cached-solve idea of the paper's
+ * matrix-caching appendix applied to Section 2.5): with Z = (A^T A + mu I)^{-1} H^T (n_obs solves
+ * with the factor, refined like every other solve), keeps
+ *   R = H (A^T A + mu I)^{-1} A_src^T   (n_obs x n_src_rows, A_src = the first n_src_rows rows)
+ * on the factor, in FP64.  Since rhs(theta) vanishes outside those rows, U = H B = R rhs_src, and
+ * since Lam = Z g_u, (A Lam)_src = R^T g_u: afterwards flsq_inverse_loss_grad calls that ask for no
+ * kappa gradient (grad_kappa_out NULL) with the same n_src_rows and x_obs pointer (and n_obs)
+ * take two products with R instead of the two refined solves and the passes over A, with the
+ * same results up to rounding.  Cost: ceil(n_obs / 64) multi-column solves and passes, once;
+ * memory about 2 n_obs n_src_rows doubles.  Re-factoring F drops it.
+ * x_obs: device n_obs x d (the pointer is the cache key); n_obs >= 1. */
+flsq_status flsq_inverse_prepare(flsq_ctx* ctx, flsq_factor* F, int64_t n_src_rows, int64_t n_obs,
+                                 const double* x_obs);
 
 /* ---- Learnable bandwidth (the reparameterisation appendix, Eq. for W_j = L What_j) ----
  * base: the frozen draws, base->W = What (device n_feat x d row-major) and base->b; the

@@ -20,15 +20,23 @@ class InverseProblem:
     ``kappa`` is the operator coefficient the factor was built for.  ``refactor(kappa)``, when
     given, returns a new factor for another kappa (the system matrix depends on kappa, so a new
     kappa needs a new factorisation); without it the problem accepts only its own kappa.
+
+    ``cache_observations``: keep the observation operator R = H (A^T A + mu I)^{-1} A_src^T on
+    the factor (n_obs refined solves, once per factor), so that calls without the kappa
+    gradient are two products with R instead of two refined solves.
     """
 
-    def __init__(self, ctx, factor, n_src_rows, src_weight, n_lap_dims, x_obs, data, kappa=None, refactor=None):
+    def __init__(self, ctx, factor, n_src_rows, src_weight, n_lap_dims, x_obs, data, kappa=None, refactor=None,
+                 cache_observations=False):
         self.ctx, self.F = ctx, factor
         self.n_src_rows, self.src_weight, self.n_lap_dims = int(n_src_rows), float(src_weight), int(n_lap_dims)
         self.x_obs = x_obs.contiguous()
         self.data = data.contiguous()
         self.kappa = None if kappa is None else float(kappa)
         self.refactor = refactor
+        self.cache_observations = bool(cache_observations)
+        if self.cache_observations:
+            fl.flsq_inverse_prepare(self.ctx, self.F, self.n_src_rows, self.x_obs)
 
     def set_kappa(self, kappa):
         kappa = float(kappa)
@@ -38,6 +46,8 @@ class InverseProblem:
             raise ValueError(f"the factor was built for kappa = {self.kappa}; kappa = {kappa} needs a refactor callable")
         self.F = self.refactor(kappa)
         self.kappa = kappa
+        if self.cache_observations:
+            fl.flsq_inverse_prepare(self.ctx, self.F, self.n_src_rows, self.x_obs)
 
     def loss_and_grad(self, thetas, want_kappa=True):
         K = thetas.shape[0]

@@ -170,6 +170,12 @@ struct flsq_factor {
   int akap_dims = -1;
   double akap_weight = 0.0;
   DevBuf Xinv;                       // inverse of the upper Cholesky factor, n x n row-major
+  DevBuf Ad, Atd;                    // A (P x n) and A^T (n x P) in MFMA operand order, when kept
+  bool dense = false;
+  // observation operator R = H (A^T A + mu I)^{-1} A_src^T (n_obs x n_src) and R^T, operand order
+  DevBuf R16, Rt16;
+  const void* rep_key = nullptr;
+  int64_t rep_nobs = -1, rep_nsrc = -1;
   double mu = 0.0;
   double shift = 0.0;
   int max_refine = 0;
@@ -831,6 +837,51 @@ struct DenseOp final : LsqOp {
   }
 };
 
+// A and A^T kept by a factor object in FP64 MFMA operand order (launch_to_t16), for products
+// with 2 .. 64 columns.
+struct KeptOp final : LsqOp {
+  const double* A16;
+  const double* At16;
+  KeptOp(const double* a, const double* at, int n_, int64_t P_) : A16(a), At16(at) {
+    n = n_;
+    P = P_;
+  }
+  bool track_u(int) const override { return false; }
+  Err apply(flsq_ctx* c, const double* V, int K, const double* Y, double alpha, double beta_y, double* out,
+            double*) const override {
+    return many(c, A16, P, n, V, K, Y, alpha, beta_y, out);
+  }
+  Err applyT(flsq_ctx* c, const double* Y, int K, const double* V, double alpha, double beta_v,
+             double* out) const override {
+    return many(c, At16, n, P, Y, K, V, alpha, beta_v, out);
+  }
+  static Err many(flsq_ctx* c, const double* M16, int64_t rows, int64_t len, const double* B, int K, const double* B0,
+                  double alpha, double beta, double* out) {
+    double* part = nullptr;
+    if (const size_t we = gemm_t16_work_elems(rows, len, K)) CHECK_ERR(ws_get(c, "t16_part", we, &part));
+    CHECK_HIP(launch_gemm_t16(M16, rows, len, B, K, B0, alpha, beta, out, part, c->stream));
+    return ok();
+  }
+};
+
+// The operator of a factor object: the kept matrix for more than kDenseMinCols columns, the
+// matrix-free passes otherwise (they also track the solution values the one-column stopping
+// rule uses).
+constexpr int kDenseMinCols = 16;
+struct FactorOp {
+  PassOp pass;
+  KeptOp kept;
+  bool has_kept;
+  explicit FactorOp(const flsq_factor* F)
+      : pass(F->sys, nullptr),
+        kept(F->dense ? F->Ad.as<double>() : nullptr, F->dense ? F->Atd.as<double>() : nullptr, F->sys.n, F->sys.P),
+        has_kept(F->dense) {}
+  const LsqOp& for_k(int K) const {
+    if (has_kept && K > kDenseMinCols) return kept;
+    return pass;
+  }
+};
+
 Err cgls_refine_op(flsq_ctx* c, const LsqOp& op, const double* Xi, double mu, const double* Y, int K, double* X,
                    int max_iter, double tol, bool want_grad0, bool want_grad, RefineOut* ro) {
   const int n = op.n;
@@ -1043,6 +1094,7 @@ struct SolveParams {
   bool report_grad = false;
   int second_pass = 0;
   double pivot_boost = 0.0;   // > 0 raises low pivots in place, 0 retries with shifts
+  bool store_matrix = false;  // factor objects: keep A and A^T in HBM for the many-column products
 };
 
 // Boost of the second pass's factorisation (its Gram is far better conditioned than the first).
@@ -1059,6 +1111,7 @@ SolveParams params_of(const flsq_solve_opts* o) {
     p.report_grad = o->report_grad != 0;
     p.second_pass = o->second_pass;
     p.pivot_boost = o->pivot_boost;
+    p.store_matrix = o->store_matrix != 0;
   }
   return p;
 }
@@ -1373,12 +1426,33 @@ Err factor_into(flsq_ctx* c, flsq_factor* f, const flsq_basis* basis, const flsq
   flsq_solve_info local;
   memset(&local, 0, sizeof local);
   CHECK_ERR(gram_and_factor(c, f->sys, nullptr, sp, f->Xinv.as<double>(), info ? info : &local));
+  f->dense = false;
+  if (sp.store_matrix) {
+    // A assembled row-major into the context's workspace, then kept as A and A^T in MFMA
+    // operand order
+    const System& s = f->sys;
+    const size_t ba = sizeof(double) * t16_elems(s.P, s.n), bt = sizeof(double) * t16_elems(s.n, s.P);
+    if (f->Ad.ensure(ba) != hipSuccess || f->Atd.ensure(bt) != hipSuccess)
+      return fail(FLSQ_ENOMEM, "keeping the %lld x %d matrix needs %zu + %zu bytes", (long long)s.P, s.n, ba, bt);
+    double* A;
+    CHECK_ERR(ws_get(c, "sp_A", (size_t)s.P * s.n, &A));
+    CHECK_HIP(launch_assemble(s.geo(), 0, A, c->stream));
+    CHECK_HIP(launch_to_t16(A, s.P, s.n, 0, f->Ad.as<double>(), c->stream));
+    CHECK_HIP(launch_to_t16(A, s.n, s.P, 1, f->Atd.as<double>(), c->stream));
+    CHECK_HIP(hipStreamSynchronize(c->stream));
+    f->dense = true;
+  } else {
+    f->Ad.release();
+    f->Atd.release();
+  }
   f->mu = sp.mu;
   f->shift = info ? info->shift : local.shift;
   f->max_refine = sp.max_refine;
   f->refine_tol = sp.refine_tol;
   f->report_grad = sp.report_grad;
-  // derived geometries of earlier calls no longer match
+  // derived geometries and the observation operator of earlier calls no longer match
+  f->rep_key = nullptr;
+  f->rep_nobs = f->rep_nsrc = -1;
   f->obs_key = nullptr;
   f->obs_n = -1;
   f->akap_rows = -1;
@@ -1637,19 +1711,20 @@ flsq_status flsq_factor_solve(flsq_ctx* ctx, const flsq_factor* F, const double*
   if (info) memset(info, 0, sizeof *info);
   const double t0 = now_ms();
   const System& s = F->sys;
-  double *cvec, *colwork;
+  double* cvec;
   Err e = ws_get(ctx, "cvec", (size_t)s.n * K, &cvec);
-  if (e.st == FLSQ_OK) e = ws_get(ctx, "colwork0", pass_work_elems(s.n, s.n_runs, K) + 64, &colwork);
   if (e.st != FLSQ_OK) return finish(ctx, e);
-  hipError_t he = launch_colpass_runs(s.pass(), nullptr, rhs_rows, K, nullptr, 1.0, 0.0, cvec, colwork, ctx->stream);
-  if (he != hipSuccess) return finish(ctx, fail(FLSQ_EHIP, "colpass: %s", hipGetErrorString(he)));
+  const FactorOp fop(F);
+  const LsqOp& op = fop.for_k(K);
+  e = op.applyT(ctx, rhs_rows, K, nullptr, 1.0, 0.0, cvec);
+  if (e.st != FLSQ_OK) return finish(ctx, e);
   e = chol_solve(ctx, F->Xinv.as<double>(), s.n, cvec, beta_out, K);
   if (e.st != FLSQ_OK) return finish(ctx, e);
   RefineOut ro;
-  e = cgls_refine(ctx, s, nullptr, F->Xinv.as<double>(), F->mu, rhs_rows, K, beta_out, F->max_refine, F->refine_tol,
-                  info != nullptr, info != nullptr && F->report_grad, &ro);
+  e = cgls_refine_op(ctx, op, F->Xinv.as<double>(), F->mu, rhs_rows, K, beta_out, F->max_refine, F->refine_tol,
+                     info != nullptr, info != nullptr && F->report_grad, &ro);
   if (e.st != FLSQ_OK) return finish(ctx, e);
-  he = hipStreamSynchronize(ctx->stream);
+  hipError_t he = hipStreamSynchronize(ctx->stream);
   if (he != hipSuccess) return finish(ctx, fail(FLSQ_EHIP, "factor_solve: %s", hipGetErrorString(he)));
   if (info) {
     info->refine_iters = ro.iters;
@@ -1669,10 +1744,9 @@ flsq_status flsq_factor_solve_normal(flsq_ctx* ctx, const flsq_factor* F, const 
   if (K < 1 || K > 64) return finish(ctx, fail(FLSQ_EINVAL, "K = %d outside [1, 64]", K));
   const System& s = F->sys;
   const int n = s.n;
-  const PassGeo pg = s.pass();
   hipStream_t st = ctx->stream;
-  // preconditioned CG on (A^T A + mu I) X = V with FP64 matrix-free operator
-  double *r, *z, *p, *ap, *tP, *dots, *dwork, *colwork;
+  // preconditioned CG on (A^T A + mu I) X = V with the factor's FP64 operator
+  double *r, *z, *p, *ap, *tP, *dots, *dwork;
   Err e = ok();
   if (e.st == FLSQ_OK) e = ws_get(ctx, "pcg_r", (size_t)n * K, &r);
   if (e.st == FLSQ_OK) e = ws_get(ctx, "pcg_z", (size_t)n * K, &z);
@@ -1681,11 +1755,12 @@ flsq_status flsq_factor_solve_normal(flsq_ctx* ctx, const flsq_factor* F, const 
   if (e.st == FLSQ_OK) e = ws_get(ctx, "pcg_tp", (size_t)s.P * K, &tP);
   if (e.st == FLSQ_OK) e = ws_get(ctx, "pcg_dots", (size_t)10 * K, &dots);
   if (e.st == FLSQ_OK) e = ws_get(ctx, "pcg_dwork", (size_t)512 * K + 64, &dwork);
-  if (e.st == FLSQ_OK) e = ws_get(ctx, "pcg_colwork", pass_work_elems(n, s.n_runs, K) + 64, &colwork);
   if (e.st != FLSQ_OK) return finish(ctx, e);
+  const FactorOp fop(F);
+  const LsqOp& op = fop.for_k(K);
   auto apply_normal = [&](const double* x, double* y) -> Err {   // y = A^T A x + mu x
-    CHECK_ERR(row_pass(ctx, pg, nullptr, x, K, nullptr, 1.0, 0.0, tP));
-    CHECK_HIP(launch_colpass_runs(pg, nullptr, tP, K, x, 1.0, F->mu, y, colwork, st));
+    CHECK_ERR(op.apply(ctx, x, K, nullptr, 1.0, 0.0, tP, nullptr));
+    CHECK_ERR(op.applyT(ctx, tP, K, x, 1.0, F->mu, y));
     return ok();
   };
   auto body = [&]() -> Err {
@@ -1825,7 +1900,8 @@ flsq_status flsq_apply_A(flsq_ctx* ctx, const flsq_factor* F, const double* V, i
   if (hipSetDevice(ctx->device) != hipSuccess) return finish(ctx, fail(FLSQ_EHIP, "hipSetDevice failed"));
   if (!V || !out) return finish(ctx, fail(FLSQ_EINVAL, "NULL V or out"));
   if (K < 1 || K > 64) return finish(ctx, fail(FLSQ_EINVAL, "K = %d outside [1, 64]", K));
-  Err e = row_pass(ctx, F->sys.pass(), nullptr, V, K, nullptr, 1.0, 0.0, out);
+  const FactorOp fop(F);
+  Err e = fop.for_k(K).apply(ctx, V, K, nullptr, 1.0, 0.0, out, nullptr);
   if (e.st != FLSQ_OK) return finish(ctx, e);
   hipError_t he = hipStreamSynchronize(ctx->stream);
   if (he != hipSuccess) return finish(ctx, fail(FLSQ_EHIP, "apply_A: %s", hipGetErrorString(he)));
@@ -1837,11 +1913,10 @@ flsq_status flsq_apply_At(flsq_ctx* ctx, const flsq_factor* F, const double* Y, 
   if (hipSetDevice(ctx->device) != hipSuccess) return finish(ctx, fail(FLSQ_EHIP, "hipSetDevice failed"));
   if (!Y || !out) return finish(ctx, fail(FLSQ_EINVAL, "NULL Y or out"));
   if (K < 1 || K > 64) return finish(ctx, fail(FLSQ_EINVAL, "K = %d outside [1, 64]", K));
-  double* colwork;
-  Err e = ws_get(ctx, "colwork0", pass_work_elems(F->sys.n, F->sys.n_runs, K) + 64, &colwork);
+  const FactorOp fop(F);
+  Err e = fop.for_k(K).applyT(ctx, Y, K, nullptr, 1.0, 0.0, out);
   if (e.st != FLSQ_OK) return finish(ctx, e);
-  hipError_t he = launch_colpass_runs(F->sys.pass(), nullptr, Y, K, nullptr, 1.0, 0.0, out, colwork, ctx->stream);
-  if (he == hipSuccess) he = hipStreamSynchronize(ctx->stream);
+  hipError_t he = hipStreamSynchronize(ctx->stream);
   if (he != hipSuccess) return finish(ctx, fail(FLSQ_EHIP, "apply_At: %s", hipGetErrorString(he)));
   return finish(ctx, ok());
 }
@@ -2074,8 +2149,20 @@ Err inverse_impl(flsq_ctx* c, flsq_factor* F, int64_t n_src, double src_weight, 
   CHECK_ERR(ws_get(c, "inv_AL", (size_t)P * K, &AL));
   CHECK_ERR(ws_get(c, "inv_gwork", (size_t)K * 64 * 4 + 64, &gwork));
   CHECK_ERR(ws_get(c, "inv_colwork", pass_work_elems(n, F->obs.n_runs, K) + 64, &colwork));
-  // forward: B = (A^T A + mu I)^{-1} A^T rhs(theta), U = H B, misfit
   CHECK_HIP(launch_source(s.Xt.as<double>(), P, n_src, src_weight, thetas, K, Rhs, st));
+  if (!gkappa && F->rep_key == (const void*)x_obs && F->rep_nobs == n_obs && F->rep_nsrc == n_src) {
+    // observation operator kept: U = R rhs_src, (A Lam)_src = R^T (2/n_obs)(U - data)
+    double* part = nullptr;
+    const size_t we = std::max(gemm_t16_work_elems(n_obs, n_src, K), gemm_t16_work_elems(n_src, n_obs, K));
+    if (we) CHECK_ERR(ws_get(c, "inv_t16part", we, &part));
+    CHECK_HIP(launch_gemm_t16(F->R16.as<double>(), n_obs, n_src, Rhs, K, nullptr, 1.0, 0.0, U, part, st));
+    CHECK_HIP(launch_misfit(U, data, n_obs, K, loss, gu, st));
+    CHECK_HIP(launch_gemm_t16(F->Rt16.as<double>(), n_src, n_obs, gu, K, nullptr, 1.0, 0.0, AL, part, st));
+    CHECK_HIP(launch_source_grad_dot(s.Xt.as<double>(), P, n_src, src_weight, thetas, K, AL, gtheta, gwork, st));
+    CHECK_HIP(hipStreamSynchronize(st));
+    return ok();
+  }
+  // forward: B = (A^T A + mu I)^{-1} A^T rhs(theta), U = H B, misfit
   flsq_status fs = flsq_factor_solve(c, F, Rhs, K, B, nullptr);
   if (fs != FLSQ_OK) return Err{fs, c->err};
   CHECK_ERR(row_pass(c, F->obs.pass(), nullptr, B, K, nullptr, 1.0, 0.0, U));
@@ -2084,7 +2171,9 @@ Err inverse_impl(flsq_ctx* c, flsq_factor* F, int64_t n_src, double src_weight, 
   CHECK_HIP(launch_colpass_runs(F->obs.pass(), nullptr, gu, K, nullptr, 1.0, 0.0, Vn, colwork, st));
   fs = flsq_factor_solve_normal(c, F, Vn, K, Lam);
   if (fs != FLSQ_OK) return Err{fs, c->err};
-  CHECK_ERR(row_pass(c, s.pass(), nullptr, Lam, K, nullptr, 1.0, 0.0, AL));
+  const FactorOp fop(F);
+  const LsqOp& op = fop.for_k(K);
+  CHECK_ERR(op.apply(c, Lam, K, nullptr, 1.0, 0.0, AL, nullptr));
   CHECK_HIP(launch_source_grad_dot(s.Xt.as<double>(), P, n_src, src_weight, thetas, K, AL, gtheta, gwork, st));
   if (gkappa) {
     // dL/dkappa = (A_k Lam)^T (rhs - A B) - (A Lam)^T (A_k B), A_k nonzero on the interior rows only
@@ -2094,7 +2183,7 @@ Err inverse_impl(flsq_ctx* c, flsq_factor* F, int64_t n_src, double src_weight, 
     CHECK_ERR(ws_get(c, "inv_AkB", (size_t)n_src * K, &AkB));
     CHECK_ERR(ws_get(c, "inv_dots", (size_t)2 * K, &dots));
     CHECK_ERR(ws_get(c, "inv_dwork", (size_t)512 * K + 64, &dwork));
-    CHECK_ERR(row_pass(c, s.pass(), nullptr, B, K, Rhs, -1.0, 1.0, r));
+    CHECK_ERR(op.apply(c, B, K, Rhs, -1.0, 1.0, r, nullptr));
     CHECK_ERR(row_pass(c, F->akap.pass(), nullptr, Lam, K, nullptr, 1.0, 0.0, AkL));
     CHECK_ERR(row_pass(c, F->akap.pass(), nullptr, B, K, nullptr, 1.0, 0.0, AkB));
     CHECK_HIP(launch_dot_cols(AkL, r, n_src, K, dots, dwork, st));
@@ -2102,6 +2191,54 @@ Err inverse_impl(flsq_ctx* c, flsq_factor* F, int64_t n_src, double src_weight, 
     CHECK_HIP(launch_combine_diff(dots, dots + K, gkappa, K, st));
   }
   CHECK_HIP(hipStreamSynchronize(st));
+  return ok();
+}
+
+// R = H (A^T A + mu I)^{-1} A_src^T, built a block of 64 observations at a time: the block's
+// rows of H transposed (n x kb), the refined normal-equation solve with the factor, A applied
+// to the solutions, and its first n_src rows written into the block's columns of R^T.
+Err inverse_prepare_impl(flsq_ctx* c, flsq_factor* F, int64_t n_src, int64_t n_obs, const double* x_obs) {
+  const System& s = F->sys;
+  if (n_src < 1 || n_src > s.P) return fail(FLSQ_EINVAL, "n_src_rows outside [1, P]");
+  if (n_obs < 1 || !x_obs) return fail(FLSQ_EINVAL, "need n_obs >= 1 observation points");
+  hipStream_t st = c->stream;
+  const int n = s.n;
+  const int64_t P = s.P;
+  flsq_term ident;
+  memset(&ident, 0, sizeof ident);
+  ident.coef = 1.0;
+  if (F->obs_key != (const void*)x_obs || F->obs_n != n_obs) {
+    CHECK_ERR(build_rows_on(c, F->obs, s, x_obs, n_obs, &ident, 1, 1.0));
+    F->obs_key = x_obs;
+    F->obs_n = n_obs;
+  }
+  F->rep_key = nullptr;
+  double *H, *Hb, *Zb, *AZ, *Rt;
+  CHECK_ERR(ws_get(c, "rep_H", (size_t)n_obs * n, &H));
+  CHECK_ERR(ws_get(c, "rep_Hb", (size_t)n * 64, &Hb));
+  CHECK_ERR(ws_get(c, "rep_Zb", (size_t)n * 64, &Zb));
+  CHECK_ERR(ws_get(c, "rep_AZ", (size_t)P * 64, &AZ));
+  CHECK_ERR(ws_get(c, "rep_Rt", (size_t)n_src * n_obs, &Rt));
+  CHECK_HIP(launch_assemble(F->obs.geo(), 0, H, st));
+  const FactorOp fop(F);
+  for (int64_t b0 = 0; b0 < n_obs; b0 += 64) {
+    const int kb = (int)std::min<int64_t>(64, n_obs - b0);
+    CHECK_HIP(launch_transpose_f64(H + b0 * n, kb, n, Hb, st));
+    const flsq_status fs = flsq_factor_solve_normal(c, F, Hb, kb, Zb);
+    if (fs != FLSQ_OK) return Err{fs, c->err};
+    CHECK_ERR(fop.for_k(kb).apply(c, Zb, kb, nullptr, 1.0, 0.0, AZ, nullptr));
+    CHECK_HIP(hipMemcpy2DAsync(Rt + b0, sizeof(double) * n_obs, AZ, sizeof(double) * kb, sizeof(double) * kb, n_src,
+                               hipMemcpyDeviceToDevice, st));
+  }
+  if (F->R16.ensure(sizeof(double) * t16_elems(n_obs, n_src)) != hipSuccess ||
+      F->Rt16.ensure(sizeof(double) * t16_elems(n_src, n_obs)) != hipSuccess)
+    return fail(FLSQ_ENOMEM, "observation operator allocation failed");
+  CHECK_HIP(launch_to_t16(Rt, n_obs, n_src, 1, F->R16.as<double>(), st));
+  CHECK_HIP(launch_to_t16(Rt, n_src, n_obs, 0, F->Rt16.as<double>(), st));
+  CHECK_HIP(hipStreamSynchronize(st));
+  F->rep_key = x_obs;
+  F->rep_nobs = n_obs;
+  F->rep_nsrc = n_src;
   return ok();
 }
 
@@ -2708,6 +2845,13 @@ flsq_status flsq_solve_newton(flsq_ctx* ctx, const flsq_basis* basis, const flsq
     return finish(ctx, fail(FLSQ_ENOCONV, "Newton: ||alpha delta|| did not fall below tol_dbeta in %d steps",
                             opts->max_iter));
   return finish(ctx, ok());
+}
+
+flsq_status flsq_inverse_prepare(flsq_ctx* ctx, flsq_factor* F, int64_t n_src_rows, int64_t n_obs,
+                                 const double* x_obs) {
+  if (!ctx || !F) return FLSQ_EINVAL;
+  if (hipSetDevice(ctx->device) != hipSuccess) return finish(ctx, fail(FLSQ_EHIP, "hipSetDevice failed"));
+  return finish(ctx, inverse_prepare_impl(ctx, F, n_src_rows, n_obs, x_obs));
 }
 
 flsq_status flsq_inverse_loss_grad(flsq_ctx* ctx, const flsq_factor* F, int64_t n_src_rows, double src_weight,

@@ -232,6 +232,16 @@ size_t precond_work_elems(int n);
 hipError_t launch_chol_solve_multi(const double* X, int n, const double* Y, int K, double* T, double* part, double* Z,
                                    hipStream_t s);
 size_t chol_multi_work_elems(int n, int K);
+// Kept matrices in FP64 MFMA operand order (16-row tiles x 4-deep k-groups, zero-padded):
+// t16_elems(M, L) doubles for an M x L matrix; launch_to_t16 converts a row-major M x L matrix
+// (trans = 0) or the transpose of a row-major L x M matrix (trans = 1).
+size_t t16_elems(int64_t M, int64_t L);
+hipError_t launch_to_t16(const double* src, int64_t M, int64_t L, int trans, double* dst, hipStream_t s);
+// out (M x K) = alpha Mt B + beta_y Y for Mt in operand order, B row-major L x K, 1 <= K <= 64;
+// part gemm_t16_work_elems(M, L, K) doubles (may be NULL when that is 0); out may alias Y.
+hipError_t launch_gemm_t16(const double* Mt, int64_t M, int64_t L, const double* B, int K, const double* Y,
+                           double alpha, double beta_y, double* out, double* part, hipStream_t s);
+size_t gemm_t16_work_elems(int64_t M, int64_t L, int K);
 hipError_t launch_copy_upper(const double* src, double* dst, int n, double diag_add, hipStream_t s);
 hipError_t launch_diag_max(const double* G, int n, double* out, hipStream_t s);
 

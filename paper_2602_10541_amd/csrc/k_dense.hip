@@ -439,4 +439,177 @@ hipError_t launch_chol_solve_multi(const double* X, int n, const double* Y, int 
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ kept-matrix products
+// Split-contraction partials of the kept-matrix product summed in split order:
+// out[e] = alpha sum_s part[s][e] + beta_y Y[e].
+__global__ __launch_bounds__(256) void k_split_sum(const double* __restrict__ part, int nsplit, int64_t len,
+                                                   const double* __restrict__ Y, double alpha, double beta_y,
+                                                   double* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= len) return;
+  double s = 0.0;
+  for (int sp = 0; sp < nsplit; ++sp) s += part[(int64_t)sp * len + e];
+  out[e] = fma(alpha, s, Y ? beta_y * Y[e] : 0.0);
+}
+
+// ------------------------------------------------------------------ kept matrix in MFMA-operand order
+// The kept matrices of a factor are stored in the order the FP64 16x16x4 MFMA reads its A
+// operand: for row tile r (16 rows) and k-group q (4 indices), 64 consecutive doubles, lane
+// l = 16 kq + m holding M[16 r + m][4 q + kq].  A wave then loads its operand for one MFMA
+// step as one 512-byte coalesced read straight into registers.  Rows are padded with zeros to a
+// multiple of 16 and the contraction to a multiple of 32 (whole k-slabs).
+int64_t t16_groups(int64_t L) { return (L + 31) / 32 * 8; }   // k-groups of 4, padded to slabs of 32
+
+size_t t16_elems(int64_t M, int64_t L) { return (size_t)((M + 15) / 16) * (size_t)t16_groups(L) * 64; }
+
+__global__ __launch_bounds__(256) void k_to_t16(const double* __restrict__ src, int64_t M, int64_t L, int trans,
+                                                int64_t G, double* __restrict__ dst) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t total = (M + 15) / 16 * G * 64;
+  if (e >= total) return;
+  const int lane = (int)(e & 63);
+  const int64_t grp = e >> 6;
+  const int64_t q = grp % G, r = grp / G;
+  const int64_t row = 16 * r + (lane & 15), k = 4 * q + (lane >> 4);
+  double v = 0.0;
+  if (row < M && k < L) v = trans ? src[k * M + row] : src[row * L + k];
+  dst[e] = v;
+}
+
+hipError_t launch_to_t16(const double* src, int64_t M, int64_t L, int trans, double* dst, hipStream_t s) {
+  const int64_t total = (int64_t)t16_elems(M, L);
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_to_t16, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, src, M, L, trans,
+                     t16_groups(L), dst);
+  return hipGetLastError();
+}
+
+// out (M x K) = alpha Mt B + beta_y Y, Mt a kept matrix in operand order (M x L), B row-major
+// L x K, K <= 64.  Workgroup: 4 waves on 4 row tiles (64 rows) and all 64 columns, one
+// contraction range of kper indices (grid.z splits; with more than one, the unscaled partials
+// go to part[split][M][K] and k_split_sum adds them in split order).  The B slab (32 x 64)
+// goes through LDS, double-buffered, for the 4 waves to share; each wave loads its own A
+// operand from HBM into registers two slabs ahead of its use.
+constexpr int kT16Slab = 32;
+
+__global__ __launch_bounds__(256) void k_gemm_t16(const double* __restrict__ Mt, int64_t M, int64_t L, int64_t G,
+                                                  const double* __restrict__ B, int K, int64_t kper,
+                                                  const double* __restrict__ Y, double alpha, double beta_y,
+                                                  double* __restrict__ out, double* __restrict__ part) {
+  __shared__ double sB[2][kT16Slab][64 + 2];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int m = lane & 15, kq = lane >> 4;
+  const int64_t rt = (int64_t)blockIdx.x * 4 + wave;
+  const bool rows_ok = rt * 16 < M;
+  const int split = blockIdx.z;
+  const int64_t kb = (int64_t)split * kper, ke = min(L, kb + kper);
+  const double* Ap = Mt + (rows_ok ? rt : 0) * G * 64 + lane;
+  double ra0[8], ra1[8], rb[8];
+  auto fetch_a = [&](int64_t k0, double* r) {
+    const int64_t q0 = k0 >> 2;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) r[j] = rows_ok ? Ap[(q0 + j) * 64] : 0.0;
+  };
+  // B slab element f = 256 e + tid (row f / 64, column f % 64): each load instruction of a wave
+  // reads one 512-byte row of B, and the LDS writes hit consecutive banks
+  auto fetch_b = [&](int64_t k0) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int f = 256 * e + tid, c = f & 63;
+      const int64_t gk = k0 + (f >> 6);
+      rb[e] = (gk < ke && c < K) ? B[gk * K + c] : 0.0;
+    }
+  };
+  auto stash_b = [&](int buf) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int f = 256 * e + tid;
+      sB[buf][f >> 6][f & 63] = rb[e];
+    }
+  };
+  f64x4 acc[4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b) acc[b] = f64x4{0.0, 0.0, 0.0, 0.0};
+  auto compute = [&](int buf, const double* r) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int k = 4 * j + kq;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(r[j], sB[buf][k][16 * b + m], acc[b], 0, 0, 0);
+    }
+  };
+  // A entries past ke inside the last slab multiply B rows that were loaded as zeros
+  if (kb < ke) {
+    fetch_a(kb, ra0);
+    fetch_b(kb);
+    stash_b(0);
+    if (kb + kT16Slab < ke) {
+      fetch_b(kb + kT16Slab);
+      fetch_a(kb + kT16Slab, ra1);
+    }
+  }
+  __syncthreads();
+  for (int64_t k0 = kb; k0 < ke; k0 += 2 * kT16Slab) {
+    compute(0, ra0);                                    // slab k0
+    if (k0 + kT16Slab < ke) stash_b(1);                 // slab k0 + 32 (buffer 1 free since the last barrier)
+    if (k0 + 2 * kT16Slab < ke) {
+      fetch_b(k0 + 2 * kT16Slab);
+      fetch_a(k0 + 2 * kT16Slab, ra0);
+    }
+    __syncthreads();
+    if (k0 + kT16Slab >= ke) break;
+    compute(1, ra1);                                    // slab k0 + 32
+    if (k0 + 2 * kT16Slab < ke) stash_b(0);
+    if (k0 + 3 * kT16Slab < ke) {
+      fetch_b(k0 + 3 * kT16Slab);
+      fetch_a(k0 + 3 * kT16Slab, ra1);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int b = 0; b < 4; ++b)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {   // element v of lane group kq: row 4 v + kq of the tile
+      const int64_t row = 16 * rt + 4 * v + kq;
+      const int c = 16 * b + m;
+      if (row < M && c < K) {
+        if (part) part[((int64_t)split * M + row) * K + c] = acc[b][v];
+        else out[row * K + c] = fma(alpha, acc[b][v], Y ? beta_y * Y[row * K + c] : 0.0);
+      }
+    }
+}
+
+static int gemm_t16_splits(int64_t M, int64_t L) {
+  const int64_t wgs = (M + 63) / 64;
+  const int64_t want = (768 + wgs - 1) / wgs;
+  const int64_t cap = std::max<int64_t>(1, L / (4 * kT16Slab));
+  return (int)std::max<int64_t>(1, std::min<int64_t>(std::min(want, cap), 64));
+}
+
+size_t gemm_t16_work_elems(int64_t M, int64_t L, int K) {
+  const int ns = gemm_t16_splits(M, L);
+  return ns > 1 ? (size_t)ns * (size_t)M * (size_t)K : 0;
+}
+
+hipError_t launch_gemm_t16(const double* Mt, int64_t M, int64_t L, const double* B, int K, const double* Y,
+                           double alpha, double beta_y, double* out, double* part, hipStream_t s) {
+  if (M <= 0) return hipSuccess;
+  if (K < 1 || K > 64) return hipErrorInvalidValue;
+  const int ns = gemm_t16_splits(M, L);
+  const int64_t kper = ((L + ns - 1) / ns + kT16Slab - 1) / kT16Slab * kT16Slab;
+  const dim3 grid((unsigned)((M + 63) / 64), 1, (unsigned)ns);
+  const int64_t G = t16_groups(L);
+  if (ns == 1) {
+    hipLaunchKernelGGL(k_gemm_t16, grid, dim3(256), 0, s, Mt, M, L, G, B, K, kper, Y, alpha, beta_y, out,
+                       (double*)nullptr);
+  } else {
+    if (!part) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_gemm_t16, grid, dim3(256), 0, s, Mt, M, L, G, B, K, kper, Y, alpha, beta_y, out, part);
+    const int64_t len = M * K;
+    hipLaunchKernelGGL(k_split_sum, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, s, part, ns, len, Y, alpha,
+                       beta_y, out);
+  }
+  return hipGetLastError();
+}
+
 }  // namespace flsq

@@ -29,7 +29,8 @@ EXPORTS = (
     "flsq_create", "flsq_destroy", "flsq_last_error", "flsq_build_info", "flsq_assemble", "flsq_gram",
     "flsq_solve_linear", "flsq_factorize", "flsq_factor_free", "flsq_factor_shape", "flsq_factor_solve",
     "flsq_factor_solve_normal", "flsq_apply_A", "flsq_apply_At", "flsq_evaluate", "flsq_evaluate_noalloc", "flsq_solve_newton",
-    "flsq_inverse_loss_grad", "flsq_bandwidth_loss_grad", "flsq_adam_step", "flsq_assemble_var",
+    "flsq_inverse_loss_grad", "flsq_inverse_prepare", "flsq_bandwidth_loss_grad", "flsq_adam_step",
+    "flsq_assemble_var",
     "flsq_solve_linear_var", "flsq_solve_newton_var",
 )
 
@@ -61,7 +62,7 @@ class flsq_rows(C.Structure):
 class flsq_solve_opts(C.Structure):
     _fields_ = [("mu", C.c_double), ("prec", C.c_int32), ("max_refine", C.c_int32), ("refine_tol", C.c_double),
                 ("shift_rel", C.c_double), ("report_grad", C.c_int32), ("second_pass", C.c_int32),
-                ("pivot_boost", C.c_double)]
+                ("pivot_boost", C.c_double), ("store_matrix", C.c_int32)]
 
 
 class flsq_solve_info(C.Structure):
@@ -149,6 +150,7 @@ def load(path: str = LIB_PATH):
                                    C.POINTER(flsq_nonlin), C.POINTER(flsq_newton_opts), vp,
                                    C.POINTER(flsq_newton_trace)]),
         "flsq_inverse_loss_grad": (st, [vp, vp, i64, dbl, i32, vp, i32, i64, vp, vp, vp, vp, vp]),
+        "flsq_inverse_prepare": (st, [vp, vp, i64, i64, vp]),
         "flsq_bandwidth_loss_grad": (st, [vp, C.POINTER(flsq_basis), C.POINTER(dbl), C.POINTER(flsq_rows), i32,
                                           C.POINTER(flsq_solve_opts), vp, C.POINTER(dbl), C.POINTER(dbl)]),
         "flsq_adam_step": (st, [vp, vp, vp, vp, vp, i32, i32, i32, dbl, dbl, dbl, dbl, i32, dbl]),
@@ -308,9 +310,9 @@ def make_vrows(blocks, d) -> VRows:
 
 
 def solve_opts(mu, prec=PREC_FP64, max_refine=10, refine_tol=1e-12, shift_rel=0.0, report_grad=False,
-               second_pass=0, pivot_boost=0.0):
+               second_pass=0, pivot_boost=0.0, store_matrix=False):
     return flsq_solve_opts(float(mu), int(prec), int(max_refine), float(refine_tol), float(shift_rel),
-                           1 if report_grad else 0, int(second_pass), float(pivot_boost))
+                           1 if report_grad else 0, int(second_pass), float(pivot_boost), 1 if store_matrix else 0)
 
 
 # ---------------------------------------------------------------------------- entry points
@@ -469,6 +471,12 @@ def flsq_inverse_loss_grad(ctx, F: Factor, n_src_rows, src_weight, n_lap_dims, t
         ctx.h, F.h, int(n_src_rows), float(src_weight), int(n_lap_dims), _ptr(thetas), int(thetas.shape[0]),
         int(x_obs.shape[0]), _ptr(x_obs), _ptr(data), _ptr(loss_out), _ptr(grad_theta_out),
         _ptr(grad_kappa_out)))
+
+
+def flsq_inverse_prepare(ctx, F: Factor, n_src_rows, x_obs):
+    """Keep the observation operator R = H (A^T A + mu I)^{-1} A_src^T on the factor (keyed by
+    n_src_rows and the x_obs tensor's device pointer)."""
+    return ctx.check(ctx.lib.flsq_inverse_prepare(ctx.h, F.h, int(n_src_rows), int(x_obs.shape[0]), _ptr(x_obs)))
 
 
 def flsq_bandwidth_loss_grad(ctx, base: Basis, L, rows: Rows, opts: flsq_solve_opts, beta_out):

@@ -93,14 +93,14 @@ def test_newton_rejects_odd_operator_on_nonlinear_block():
 
 # ----------------------------------------------------------------------------- adjoint
 
-def _inverse_setup(prob, data, refine_tol=1e-13, max_refine=20, prec=0):
+def _inverse_setup(prob, data, refine_tol=1e-13, max_refine=20, prec=0, store_matrix=False, cache=False):
     torch, fl = require_gpu()
     from paper_2602_10541_amd.autograd import InverseProblem
     ctx = context()
     dp = fl.DeviceProblem(prob)
     d = prob.d
     t_axis = tuple([0] * (d - 1) + [1])
-    opts = fl.solve_opts(prob.mu, prec, max_refine, refine_tol)
+    opts = fl.solve_opts(prob.mu, prec, max_refine, refine_tol, store_matrix=store_matrix)
 
     def factor(kappa):
         interior = [(1.0, t_axis)] + [(-kappa, tuple(2 if i == k else 0 for i in range(d))) for k in range(d - 1)]
@@ -111,7 +111,7 @@ def _inverse_setup(prob, data, refine_tol=1e-13, max_refine=20, prec=0):
     xo = torch.tensor(prob.extras["x_obs"], dtype=torch.float64, device="cuda")
     dd = torch.tensor(data, dtype=torch.float64, device="cuda")
     return InverseProblem(ctx, factor(kappa), prob.blocks[0].n, prob.blocks[0].weight, d - 1, xo, dd,
-                          kappa=kappa, refactor=factor), dp
+                          kappa=kappa, refactor=factor, cache_observations=cache), dp
 
 
 def _tiny_inverse():
@@ -248,7 +248,8 @@ def test_adam_matches_reference_formula():
     assert np.any(pr[:, 3] == 0.02)
 
 
-def test_inverse_full_size_adam_trajectory():
+@pytest.mark.parametrize("store_matrix,cache", [(False, False), (True, True)])
+def test_inverse_full_size_adam_trajectory(store_matrix, cache):
     """The workload's 200 batched Adam steps (lr 1e-2, w >= 0.02) for all 64 hypotheses on the
     device gradients and the device Adam, against the oracle's run on its own gradients.
 
@@ -262,7 +263,8 @@ def test_inverse_full_size_adam_trajectory():
     torch, fl = require_gpu()
     gold = np.load(path)
     prob = wl.config("inverse3d")
-    ip, _ = _inverse_setup(prob, np.load(os.path.join(GOLDEN, "inverse3d.npz"))["data"], prec=3)
+    ip, _ = _inverse_setup(prob, np.load(os.path.join(GOLDEN, "inverse3d.npz"))["data"], prec=3,
+                           store_matrix=store_matrix, cache=cache)
     p = torch.tensor(prob.extras["theta0"], dtype=torch.float64, device="cuda")
     m = torch.zeros_like(p)
     v = torch.zeros_like(p)
@@ -283,17 +285,18 @@ def test_inverse_full_size_adam_trajectory():
     np.testing.assert_allclose(np.array(losses), gold["losses"], rtol=1e-5, atol=1e-10)
 
 
-@pytest.mark.parametrize("prec", [0, 3])
-def test_inverse_full_size_gradients(prec):
+@pytest.mark.parametrize("prec,store_matrix", [(0, False), (3, False), (3, True), (0, True)])
+def test_inverse_full_size_gradients(prec, store_matrix):
     """Inverse heat source at full size (N = 2048, 12288 rows, 64 hypotheses, 400 observations),
-    factor from the FP64 and from the int8-CRT Gram."""
+    factor from the FP64 and from the int8-CRT Gram; the 64-column products matrix-free or
+    streamed from the kept matrix."""
     path = os.path.join(GOLDEN, "inverse3d.npz")
     if not os.path.exists(path):
         pytest.skip("golden values not generated")
     torch, fl = require_gpu()
     gold = np.load(path)
     prob = wl.config("inverse3d")
-    ip, _ = _inverse_setup(prob, gold["data"], prec=prec)
+    ip, _ = _inverse_setup(prob, gold["data"], prec=prec, store_matrix=store_matrix)
     th = torch.tensor(prob.extras["theta0"], dtype=torch.float64, device="cuda")
     loss, g, gk = ip.loss_and_grad(th)
     np.testing.assert_allclose(loss.cpu().numpy(), gold["loss0"], rtol=1e-6)
@@ -301,3 +304,48 @@ def test_inverse_full_size_gradients(prec):
     np.testing.assert_allclose(gg, gold["grad_theta0"], rtol=1e-5, atol=1e-7 * np.abs(gold["grad_theta0"]).max())
     gkk = gk.cpu().numpy()
     np.testing.assert_allclose(gkk, gold["grad_kappa0"], rtol=1e-5, atol=1e-7 * np.abs(gold["grad_kappa0"]).max())
+
+
+@pytest.mark.parametrize("prec,store_matrix", [(3, False), (3, True), (0, False)])
+def test_inverse_cached_observation_operator(prec, store_matrix):
+    """Calls without the kappa gradient through the kept observation operator R = H G^{-1} A_src^T
+    against the full call (two refined solves and the passes over A) on the same factor, and
+    against the oracle's stored losses and gradients at full size."""
+    path = os.path.join(GOLDEN, "inverse3d.npz")
+    if not os.path.exists(path):
+        pytest.skip("golden values not generated")
+    torch, fl = require_gpu()
+    gold = np.load(path)
+    prob = wl.config("inverse3d")
+    ip, _ = _inverse_setup(prob, gold["data"], prec=prec, store_matrix=store_matrix, cache=True)
+    th = torch.tensor(prob.extras["theta0"], dtype=torch.float64, device="cuda")
+    lc, gc, gkc = ip.loss_and_grad(th, want_kappa=False)        # kept operator
+    lf, gf, gkf = ip.loss_and_grad(th, want_kappa=True)         # full solves
+    assert gkc is None and gkf is not None
+    lc, gc, lf, gf = (t.cpu().numpy() for t in (lc, gc, lf, gf))
+    np.testing.assert_allclose(lc, lf, rtol=1e-9)
+    np.testing.assert_allclose(gc, gf, rtol=1e-8, atol=1e-10 * np.abs(gf).max())
+    np.testing.assert_allclose(lc, gold["loss0"], rtol=1e-6)
+    np.testing.assert_allclose(gc, gold["grad_theta0"], rtol=1e-5, atol=1e-7 * np.abs(gold["grad_theta0"]).max())
+    # another theta batch (shifted centres, 17 hypotheses): still the full call's values
+    th2 = th[:17].clone()
+    th2[:, 1:3] += 0.05
+    l2c, g2c, _ = ip.loss_and_grad(th2, want_kappa=False)
+    l2f, g2f, _ = ip.loss_and_grad(th2, want_kappa=True)
+    np.testing.assert_allclose(l2c.cpu().numpy(), l2f.cpu().numpy(), rtol=1e-9)
+    np.testing.assert_allclose(g2c.cpu().numpy(), g2f.cpu().numpy(), rtol=1e-8,
+                               atol=1e-10 * np.abs(g2f.cpu().numpy()).max())
+
+
+def test_inverse_cached_tiny_matches_oracle():
+    """The kept observation operator on the small inverse problem (N = 200, 1200 rows, 60
+    observations: one partial block of 64) against the oracle's Householder-QR loss and gradient."""
+    torch, fl = require_gpu()
+    prob, data, orc = _tiny_inverse()
+    ip, _ = _inverse_setup(prob, data, refine_tol=1e-13, max_refine=30, cache=True)
+    th0 = prob.extras["theta0"]
+    th = torch.tensor(th0, dtype=torch.float64, device="cuda")
+    loss, g, _ = ip.loss_and_grad(th, want_kappa=False)
+    lref, gref, _, _ = orc.loss_and_grad(th0)
+    np.testing.assert_allclose(loss.cpu().numpy(), lref, rtol=1e-8)
+    np.testing.assert_allclose(g.cpu().numpy(), gref, rtol=1e-6, atol=1e-9 * np.abs(gref).max())

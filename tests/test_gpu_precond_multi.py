@@ -61,3 +61,41 @@ def test_multi_column_preconditioner(n):
         errs = [rel_l2(got[:, s], ref[:, s]) for s in range(K)]
         assert max(errs) <= 1e-7, (n, K, max(errs))
     F.free()
+
+
+@pytest.mark.parametrize("n", [500, 2049])
+def test_stored_matrix_products(n):
+    """A factor that keeps A and A^T: its 17..64-column products (matrix-core GEMM over the stored
+    rows, split contraction) against the oracle's assembled matrix, entry by entry within 1e-12
+    of |A| |V| (the FP64 rounding scale), and its refined multi-column solves against the
+    matrix-free factor's and the oracle's."""
+    torch, fl = require_gpu()
+    ctx = context()
+    prob = _problem(n, 7000 + n)
+    dp = fl.DeviceProblem(prob)
+    P = dp.n_rows
+    A, _ = oracle.assemble_system(prob)
+    Fd = fl.flsq_factorize(ctx, dp.basis, dp.rows, fl.solve_opts(prob.mu, fl.PREC_FP64, 10, 1e-13, store_matrix=True))
+    Fm = fl.flsq_factorize(ctx, dp.basis, dp.rows, fl.solve_opts(prob.mu, fl.PREC_FP64, 10, 1e-13))
+    rng = np.random.default_rng(n + 1)
+    for K in (17, 40, 64):
+        V = rng.normal(size=(n, K))
+        Y = rng.normal(size=(P, K))
+        Vt = torch.tensor(V, dtype=torch.float64, device="cuda")
+        Yt = torch.tensor(Y, dtype=torch.float64, device="cuda")
+        AV = torch.empty((P, K), dtype=torch.float64, device="cuda")
+        AtY = torch.empty((n, K), dtype=torch.float64, device="cuda")
+        fl.flsq_apply_A(ctx, Fd, Vt, AV)
+        fl.flsq_apply_At(ctx, Fd, Yt, AtY)
+        assert np.abs(AV.cpu().numpy() - A @ V).max() <= 1e-12 * (np.abs(A) @ np.abs(V)).max(), (n, K)
+        assert np.abs(AtY.cpu().numpy() - A.T @ Y).max() <= 1e-12 * (np.abs(A).T @ np.abs(Y)).max(), (n, K)
+        Bd = torch.empty((n, K), dtype=torch.float64, device="cuda")
+        Bm = torch.empty((n, K), dtype=torch.float64, device="cuda")
+        fl.flsq_factor_solve(ctx, Fd, Yt, Bd)
+        fl.flsq_factor_solve(ctx, Fm, Yt, Bm)
+        ref = oracle.tikhonov(A, Y[:, :3], prob.mu)
+        assert rel_l2(Bd.cpu().numpy(), Bm.cpu().numpy()) <= 1e-10, (n, K)
+        for s in range(3):
+            assert rel_l2(Bd.cpu().numpy()[:, s], ref[:, s]) <= 1e-10, (n, K, s)
+    Fd.free()
+    Fm.free()
