@@ -16,6 +16,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <initializer_list>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -155,6 +156,8 @@ struct flsq_ctx {
   double last_gram_kernel_ms = 0.0;  // duration of the last fused Gram kernel (HIP events on the stream)
   void* pinned = nullptr;            // pinned host staging for the small per-iteration read-backs
   size_t pinned_bytes = 0;
+  void* up = nullptr;                // pinned host staging of small uploads (plans, descriptors, tables)
+  size_t up_bytes = 0, up_off = 0;   // bytes in use since the stream was last drained
   flsq_factor* aux_factor = nullptr; // factor and derived system reused by the learnable-bandwidth calls
   System aux;
   unsigned char* scratch = nullptr;  // this device's copy of the static evaluation scratch (no-alloc calls)
@@ -233,7 +236,34 @@ Err read_back(flsq_ctx* c, void* host, const void* dev, size_t bytes) {
   }
   CHECK_HIP(hipMemcpyAsync(c->pinned, dev, bytes, hipMemcpyDeviceToHost, c->stream));
   CHECK_HIP(hipStreamSynchronize(c->stream));
+  c->up_off = 0;   // the stream is drained: every staged upload has completed
   memcpy(host, c->pinned, bytes);
+  return ok();
+}
+
+// Asynchronous host-to-device copy of `bytes` through the context's pinned upload stage: the
+// source is copied into the stage at once, so it may go out of scope right away, and the
+// stream need not be drained.  The stage is reused once the stream has been drained (a
+// read-back); when it is full, the stream is drained here.
+Err stage_upload(flsq_ctx* c, void* dev, const void* host, size_t bytes) {
+  if (bytes == 0) return ok();
+  const size_t need = (bytes + 255) / 256 * 256;
+  if (c->up_off + need > c->up_bytes) {
+    CHECK_HIP(hipStreamSynchronize(c->stream));
+    c->up_off = 0;
+    if (need > c->up_bytes) {
+      if (c->up) (void)hipHostFree(c->up);
+      c->up = nullptr;
+      c->up_bytes = 0;
+      const size_t want = std::max<size_t>(need, 4u << 20);
+      CHECK_HIP(hipHostMalloc(&c->up, want, hipHostMallocDefault));
+      c->up_bytes = want;
+    }
+  }
+  char* dst = (char*)c->up + c->up_off;
+  memcpy(dst, host, bytes);
+  c->up_off += need;
+  CHECK_HIP(hipMemcpyAsync(dev, dst, bytes, hipMemcpyHostToDevice, c->stream));
   return ok();
 }
 
@@ -277,15 +307,36 @@ Err check_blocks(const flsq_rows* blocks, int n_blocks, int d, bool need_rhs) {
   return ok();
 }
 
-Err check_finite_dev(flsq_ctx* c, const double* p, int64_t n, const char* what) {
-  int* flag;
-  CHECK_ERR(ws_get(c, "nf_flag", 1, &flag));
-  CHECK_HIP(hipMemsetAsync(flag, 0, sizeof(int), c->stream));
-  CHECK_HIP(launch_count_nonfinite(p, n, flag, c->stream));
-  int h = 0;
-  CHECK_ERR(read_back(c, &h, flag, sizeof(int)));
-  if (h) return fail(FLSQ_ENONFINITE, "%s contains NaN or Inf", what);
+struct FiniteItem {
+  const double* p;
+  int64_t n;
+  const char* what;
+};
+
+// NaN / Inf scan of several device arrays with one read-back of their counts.
+Err check_finite_many(flsq_ctx* c, std::initializer_list<FiniteItem> items) {
+  int* flags;
+  const int m = (int)items.size();
+  CHECK_ERR(ws_get(c, "nf_flag", (size_t)m, &flags));
+  CHECK_HIP(hipMemsetAsync(flags, 0, sizeof(int) * m, c->stream));
+  int k = 0;
+  for (const FiniteItem& it : items) {
+    if (it.p && it.n > 0) CHECK_HIP(launch_count_nonfinite(it.p, it.n, flags + k, c->stream));
+    ++k;
+  }
+  int h[8] = {0};
+  if (m > 8) return fail(FLSQ_EINVAL, "internal: too many finiteness checks");
+  CHECK_ERR(read_back(c, h, flags, sizeof(int) * m));
+  k = 0;
+  for (const FiniteItem& it : items) {
+    if (h[k]) return fail(FLSQ_ENONFINITE, "%s contains NaN or Inf", it.what);
+    ++k;
+  }
   return ok();
+}
+
+Err check_finite_dev(flsq_ctx* c, const double* p, int64_t n, const char* what) {
+  return check_finite_many(c, {FiniteItem{p, n, what}});
 }
 
 // ------------------------------------------------------------------ system setup
@@ -383,9 +434,9 @@ Err build_system(flsq_ctx* c, System& s, const flsq_basis* basis, const flsq_row
   CHECK_HIP(s.chunks.ensure(sizeof(Chunk) * ch.size()));
   CHECK_HIP(s.runs.ensure(sizeof(Chunk) * rn.size()));
   CHECK_HIP(s.wide.ensure(sizeof(Chunk) * wd.size()));
-  CHECK_HIP(hipMemcpyAsync(s.chunks.p, ch.data(), sizeof(Chunk) * ch.size(), hipMemcpyHostToDevice, st));
-  CHECK_HIP(hipMemcpyAsync(s.runs.p, rn.data(), sizeof(Chunk) * rn.size(), hipMemcpyHostToDevice, st));
-  CHECK_HIP(hipMemcpyAsync(s.wide.p, wd.data(), sizeof(Chunk) * wd.size(), hipMemcpyHostToDevice, st));
+  CHECK_ERR(stage_upload(c, s.chunks.p, ch.data(), sizeof(Chunk) * ch.size()));
+  CHECK_ERR(stage_upload(c, s.runs.p, rn.data(), sizeof(Chunk) * rn.size()));
+  CHECK_ERR(stage_upload(c, s.wide.p, wd.data(), sizeof(Chunk) * wd.size()));
 
   const int T = gram_tile();
   s.nt = (n + T - 1) / T;
@@ -420,14 +471,12 @@ Err build_system(flsq_ctx* c, System& s, const flsq_basis* basis, const flsq_row
   }
   CHECK_HIP(s.slot_ptr.ensure(sizeof(int32_t) * ptr.size()));
   CHECK_HIP(s.slots.ensure(sizeof(int32_t) * std::max<size_t>(1, sl.size())));
-  CHECK_HIP(hipMemcpyAsync(s.slot_ptr.p, ptr.data(), sizeof(int32_t) * ptr.size(), hipMemcpyHostToDevice, st));
-  CHECK_HIP(hipMemcpyAsync(s.slots.p, sl.data(), sizeof(int32_t) * sl.size(), hipMemcpyHostToDevice, st));
-  // the host vectors go out of scope: make the copies complete first
-  CHECK_HIP(hipStreamSynchronize(st));
-  CHECK_ERR(check_finite_dev(c, s.Xt.as<double>(), (int64_t)d * P, "collocation points"));
-  CHECK_ERR(check_finite_dev(c, s.Wt.as<double>(), (int64_t)d * n, "W"));
-  CHECK_ERR(check_finite_dev(c, s.bvec.as<double>(), n, "b"));
-  if (need_rhs) CHECK_ERR(check_finite_dev(c, s.rhs_w.as<double>(), P, "right-hand side"));
+  CHECK_ERR(stage_upload(c, s.slot_ptr.p, ptr.data(), sizeof(int32_t) * ptr.size()));
+  CHECK_ERR(stage_upload(c, s.slots.p, sl.data(), sizeof(int32_t) * sl.size()));
+  CHECK_ERR(check_finite_many(c, {FiniteItem{s.Xt.as<double>(), (int64_t)d * P, "collocation points"},
+                                  FiniteItem{s.Wt.as<double>(), (int64_t)d * n, "W"},
+                                  FiniteItem{s.bvec.as<double>(), n, "b"},
+                                  FiniteItem{need_rhs ? s.rhs_w.as<double>() : nullptr, P, "right-hand side"}}));
   return ok();
 }
 
@@ -501,8 +550,7 @@ Err run_gram_i8(flsq_ctx* c, const System& s, const double* rho, double* G, int 
   {
     std::vector<int2> h(n_tiles);
     i8_tile_order(nt, h.data());
-    CHECK_HIP(hipMemcpyAsync(order, h.data(), sizeof(int2) * n_tiles, hipMemcpyHostToDevice, st));
-    CHECK_HIP(hipStreamSynchronize(st));
+    CHECK_ERR(stage_upload(c, order, h.data(), sizeof(int2) * n_tiles));
   }
   CHECK_HIP(launch_i8_scale(s.amp.as<double>(), s.n_blocks, n, rho, s.P, rho_max, B, inv_scale, scale, st));
   CHECK_HIP(launch_i8_residues(s.geo(), rho, inv_scale, M, n_pad, KB, R, st));
@@ -577,8 +625,7 @@ Err run_gram(flsq_ctx* c, const System& s, int prec, const double* rho, double* 
 Err upload_descs(flsq_ctx* c, const std::vector<GemmDesc>& h, GemmDesc** d_out) {
   GemmDesc* d;
   CHECK_ERR(ws_get(c, "gemm_descs", std::max<size_t>(1, h.size()), &d));
-  CHECK_HIP(hipMemcpyAsync(d, h.data(), sizeof(GemmDesc) * h.size(), hipMemcpyHostToDevice, c->stream));
-  CHECK_HIP(hipStreamSynchronize(c->stream));
+  CHECK_ERR(stage_upload(c, d, h.data(), sizeof(GemmDesc) * h.size()));
   *d_out = d;
   return ok();
 }
@@ -1197,12 +1244,11 @@ Err second_pass_factor(flsq_ctx* c, const double* A, int64_t P, int n, double mu
   dm.tri = 1;
   GemmDesc* d;
   CHECK_ERR(ws_get(c, "sp_descs", h.size(), &d));
-  CHECK_HIP(hipMemcpyAsync(d, h.data(), sizeof(GemmDesc) * h.size(), hipMemcpyHostToDevice, st));
+  CHECK_ERR(stage_upload(c, d, h.data(), sizeof(GemmDesc) * h.size()));
   CHECK_HIP(launch_gemm_tri(d, 1, (int)P, n, n, 1.0, work, we, st));
   CHECK_HIP(launch_transpose_f64(Q, P, n, Qt, st));
   CHECK_HIP(launch_gemm_tri(d + 1, 1, n, n, (int)P, 1.0, work, we, st));
   CHECK_HIP(launch_gemm_batched(d + 1 + n_split, 1, n, n, mu, 1.0, 1, st));
-  CHECK_HIP(hipStreamSynchronize(st));   // h leaves scope before the factorisation reuses the descriptors' slots
   int boosted2 = 0;
   Err fe = factor_with_retries(c, G2, U, X2, n, 0.0, 0.0, shift2, retries2, kSecondPassPivotBoost, &boosted2);
   if (fe.st == FLSQ_ENOTSPD) {   // the first factor stays in use
@@ -1596,6 +1642,7 @@ void flsq_destroy(flsq_ctx* ctx) {
   if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
   if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  if (ctx->up) (void)hipHostFree(ctx->up);
   delete ctx->aux_factor;
   delete ctx;
 }
@@ -2494,18 +2541,15 @@ Err build_var(flsq_ctx* c, VarSys& s, const flsq_basis* basis, const flsq_vrows*
   CHECK_HIP(s.terms.ensure(sizeof(VarTerm) * std::max<size_t>(1, tv.size())));
   CHECK_HIP(s.off.ensure(sizeof(int32_t) * off.size()));
   CHECK_HIP(s.scale.ensure(sizeof(double) * sc.size()));
-  if (!tv.empty())
-    CHECK_HIP(hipMemcpyAsync(s.terms.p, tv.data(), sizeof(VarTerm) * tv.size(), hipMemcpyHostToDevice, st));
-  CHECK_HIP(hipMemcpyAsync(s.off.p, off.data(), sizeof(int32_t) * off.size(), hipMemcpyHostToDevice, st));
-  CHECK_HIP(hipMemcpyAsync(s.scale.p, sc.data(), sizeof(double) * sc.size(), hipMemcpyHostToDevice, st));
+  if (!tv.empty()) CHECK_ERR(stage_upload(c, s.terms.p, tv.data(), sizeof(VarTerm) * tv.size()));
+  CHECK_ERR(stage_upload(c, s.off.p, off.data(), sizeof(int32_t) * off.size()));
+  CHECK_ERR(stage_upload(c, s.scale.p, sc.data(), sizeof(double) * sc.size()));
   CHECK_HIP(launch_fold_var(s.W, n, d, s.terms.as<VarTerm>(), s.off.as<int32_t>(), s.scale.as<double>(), nb * T,
                             s.S.as<double>(), s.C.as<double>(), st));
-  CHECK_HIP(hipStreamSynchronize(st));   // the host tables go out of scope
-  CHECK_ERR(check_finite_dev(c, s.X.as<double>(), P * d, "collocation points"));
-  CHECK_ERR(check_finite_dev(c, s.acoef.as<double>(), (int64_t)T * P, "channel coefficients"));
-  CHECK_ERR(check_finite_dev(c, s.W, (int64_t)n * d, "W"));
-  CHECK_ERR(check_finite_dev(c, s.b, n, "b"));
-  if (need_rhs) CHECK_ERR(check_finite_dev(c, s.rhs_w.as<double>(), P, "right-hand side"));
+  CHECK_ERR(check_finite_many(c, {FiniteItem{s.X.as<double>(), P * d, "collocation points"},
+                                  FiniteItem{s.acoef.as<double>(), (int64_t)T * P, "channel coefficients"},
+                                  FiniteItem{s.W, (int64_t)n * d, "W"}, FiniteItem{s.b, n, "b"},
+                                  FiniteItem{need_rhs ? s.rhs_w.as<double>() : nullptr, P, "right-hand side"}}));
   return ok();
 }
 

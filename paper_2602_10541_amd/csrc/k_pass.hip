@@ -536,12 +536,12 @@ size_t pass_work_elems(int n, int n_runs, int K) {
 static int row_fs(int K) { return K <= 1 ? 4 : (K <= 4 ? 2 : 1); }
 
 // Feature groups (grid.y) of the row pass: 6144 waves in all (2048 to 16384 measured within 5%),
-// but at least 32 features per wave.
+// but at least 8 features per wave (small systems: a few hundred rows get enough workgroups).
 static int row_groups(const PassGeo& pg, int K) {
   const int fs = row_fs(K);
   const int64_t waves = (int64_t)std::max(pg.n_wide, 1) * 4;
   const int64_t want = 6144 / waves;   // about 1.5 rounds of waves at 4 per SIMD
-  const int64_t cap = std::max(1, pg.g.n / (32 * fs));
+  const int64_t cap = std::max(1, pg.g.n / (8 * fs));
   return (int)std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(want, cap), 64));
 }
 
