@@ -348,13 +348,12 @@ int trimm_kc(int n) {
   return np <= 2048 ? 128 : (np <= 4096 ? 256 : kTrimmMaxKc);
 }
 
-// part = chunk partials of X^T Y (transpose = 1) or X T (transpose = 0).  X^T Y reads rows of X
+// part = chunk partials of X^T Y (TRANS = 1) or X T (TRANS = 0).  X^T Y reads rows of X
 // (16 consecutive entries per lane group: coalesced) straight into the MFMA operand; X T needs
 // X by columns, so the workgroup first copies its 16 x kc block of X into LDS transposed.
-template <int TRANS>
-__global__ __launch_bounds__(256) void k_trimm(const double* __restrict__ X, int n, const double* __restrict__ B, int K,
-                                               int kc, double* __restrict__ part) {
-  __shared__ double sX[TRANS ? 1 : kTrimmMaxKc][17];
+template <int TRANS, int KC>
+__device__ __forceinline__ void trimm_body(const double* __restrict__ X, int n, const double* __restrict__ B, int K,
+                                           int kc, double* __restrict__ part, double (*sX)[17]) {
   const int nt = (n + 15) >> 4, r = kc >> 4;
   int v, j;
   trimm_locate(blockIdx.x, nt, r, &v, &j);
@@ -403,22 +402,45 @@ __global__ __launch_bounds__(256) void k_trimm(const double* __restrict__ X, int
   }
 }
 
-// out[16 t + m][c] = sum over the chunks of tile t, in chunk order.
+// X^T Y
+__global__ __launch_bounds__(256) void k_trimm_t(const double* __restrict__ X, int n, const double* __restrict__ B,
+                                                 int K, int kc, double* __restrict__ part) {
+  trimm_body<1, 1>(X, n, B, K, kc, part, nullptr);
+}
+
+// X T: the workgroup's 16 x KC block of X staged transposed in LDS sized for KC
+template <int KC>
+__global__ __launch_bounds__(256) void k_trimm_n(const double* __restrict__ X, int n, const double* __restrict__ B,
+                                                 int K, double* __restrict__ part) {
+  __shared__ double sX[KC][17];
+  trimm_body<0, KC>(X, n, B, K, KC, part, sX);
+}
+
+// out[16 t + m][c] = sum over the chunks of tile t, in chunk order: one thread per entry (grid
+// x: tiles, grid y: 64-entry slices of the tile's 16 K entries), four chunk loads in flight.
 template <int TRANS>
-__global__ __launch_bounds__(256) void k_trimm_sum(const double* __restrict__ part, int n, int K, int kc,
-                                                   double* __restrict__ out) {
+__global__ __launch_bounds__(64) void k_trimm_sum(const double* __restrict__ part, int n, int K, int kc,
+                                                  double* __restrict__ out) {
   const int nt = (n + 15) >> 4, r = kc >> 4;
   const int t = blockIdx.x;
+  const int e = blockIdx.y * 64 + threadIdx.x;
+  if (e >= 16 * K || 16 * t + e / K >= n) return;
   const int v = TRANS ? t + 1 : nt - t;
   const int64_t task0 = trimm_task0(v, r);
   const int nch = (v + r - 1) / r;
-  for (int e = threadIdx.x; e < 16 * K; e += 256) {
-    const int i = 16 * t + e / K;
-    if (i >= n) break;
-    double s = 0.0;
-    for (int ch = 0; ch < nch; ++ch) s += part[(task0 + ch) * 16 * K + e];
-    out[(int64_t)16 * t * K + e] = s;
+  const double* p = part + task0 * 16 * K + e;
+  const int64_t stride = (int64_t)16 * K;
+  double s = 0.0;
+  int ch = 0;
+  for (; ch + 4 <= nch; ch += 4) {
+    const double a = p[(ch + 0) * stride], b = p[(ch + 1) * stride], c = p[(ch + 2) * stride], d = p[(ch + 3) * stride];
+    s += a;
+    s += b;
+    s += c;
+    s += d;
   }
+  for (; ch < nch; ++ch) s += p[ch * stride];
+  out[(int64_t)16 * t * K + e] = s;
 }
 
 size_t chol_multi_work_elems(int n, int K) {
@@ -432,10 +454,13 @@ hipError_t launch_chol_solve_multi(const double* X, int n, const double* Y, int 
   if (K < 2 || K > 64) return hipErrorInvalidValue;
   const int nt = (n + 15) / 16, kc = trimm_kc(n), r = kc / 16;
   const unsigned tasks = (unsigned)trimm_task0(nt + 1, r);
-  hipLaunchKernelGGL(k_trimm<1>, dim3(tasks), dim3(256), 0, s, X, n, Y, K, kc, part);
-  hipLaunchKernelGGL(k_trimm_sum<1>, dim3(nt), dim3(256), 0, s, part, n, K, kc, T);
-  hipLaunchKernelGGL(k_trimm<0>, dim3(tasks), dim3(256), 0, s, X, n, T, K, kc, part);
-  hipLaunchKernelGGL(k_trimm_sum<0>, dim3(nt), dim3(256), 0, s, part, n, K, kc, Z);
+  const dim3 gsum(nt, (16 * K + 63) / 64);
+  hipLaunchKernelGGL(k_trimm_t, dim3(tasks), dim3(256), 0, s, X, n, Y, K, kc, part);
+  hipLaunchKernelGGL(k_trimm_sum<1>, gsum, dim3(64), 0, s, part, n, K, kc, T);
+  if (kc == 128) hipLaunchKernelGGL(k_trimm_n<128>, dim3(tasks), dim3(256), 0, s, X, n, T, K, part);
+  else if (kc == 256) hipLaunchKernelGGL(k_trimm_n<256>, dim3(tasks), dim3(256), 0, s, X, n, T, K, part);
+  else hipLaunchKernelGGL(k_trimm_n<kTrimmMaxKc>, dim3(tasks), dim3(256), 0, s, X, n, T, K, part);
+  hipLaunchKernelGGL(k_trimm_sum<0>, gsum, dim3(64), 0, s, part, n, K, kc, Z);
   return hipGetLastError();
 }
 

@@ -188,19 +188,72 @@ __global__ __launch_bounds__(kDotSmallWg) void k_dot_small(DotBatch b) {
   }
 }
 
+// Large products of a batch in one pair of launches: product p = blockIdx.y, its partials in
+// work[p][c][blk] (the kDotBlocks x K doubles of one product's work are shared out among the
+// batch), then summed per column as in k_dot_stage2.
+__global__ __launch_bounds__(kDotWg) void k_dot_stage1_batch(DotBatch b, int nblk, double* __restrict__ work) {
+  __shared__ double red[kDotWg];
+  const int p = blockIdx.y;
+  const double* __restrict__ x = b.x[p];
+  const double* __restrict__ y = b.y[p];
+  const int64_t n = b.n[p];
+  const int K = b.K;
+  double* w = work + (int64_t)p * K * nblk;
+  const int t = threadIdx.x;
+  for (int cb = 0; cb < K; cb += kDotWg) {
+    const int kc = min(kDotWg, K - cb);
+    const int R = kDotWg / kc;
+    const int c = t % kc, r = t / kc;
+    double s = 0.0;
+    if (r < R)
+      for (int64_t i = (int64_t)blockIdx.x * R + r; i < n; i += (int64_t)nblk * R)
+        s = fma(x[i * K + cb + c], y[i * K + cb + c], s);
+    red[t] = s;
+    __syncthreads();
+    if (t < kc) {
+      double acc = 0.0;
+      for (int rr = 0; rr < R; ++rr) acc += red[rr * kc + t];
+      w[(int64_t)(cb + t) * nblk + blockIdx.x] = acc;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_dot_stage2_batch(DotBatch b, int nblk, const double* __restrict__ work) {
+  __shared__ double red[256];
+  const int c = blockIdx.x, p = blockIdx.y;
+  const double* w = work + ((int64_t)p * b.K + c) * nblk;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += 256) s += w[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) b.out[p][c] = red[0];
+}
+
 hipError_t launch_dot_batch(const DotBatch& b, double* work, hipStream_t s) {
   if (b.count < 1 || b.count > kDotBatchMax || b.K < 1) return hipErrorInvalidValue;
   bool small = true;
-  for (int p = 0; p < b.count; ++p) small = small && b.n[p] * b.K <= kDotSmallMax;
+  int64_t nmax = 0;
+  for (int p = 0; p < b.count; ++p) {
+    small = small && b.n[p] * b.K <= kDotSmallMax;
+    nmax = std::max(nmax, b.n[p] * b.K);
+  }
   if (small) {
     hipLaunchKernelGGL(k_dot_small, dim3(b.count), dim3(kDotSmallWg), 0, s, b);
     return hipGetLastError();
   }
-  for (int p = 0; p < b.count; ++p) {
-    hipError_t e = launch_dot_cols(b.x[p], b.y[p], b.n[p], b.K, b.out[p], work, s);
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
+  if (b.count == 1) return launch_dot_cols(b.x[0], b.y[0], b.n[0], b.K, b.out[0], work, s);
+  // the work of one product (kDotBlocks x K doubles) holds every product's partials
+  const int64_t nb = (nmax + kDotWg - 1) / kDotWg;
+  const int cap = kDotBlocks / b.count;
+  const int nblk = (int)(nb < cap ? (nb > 0 ? nb : 1) : cap);
+  hipLaunchKernelGGL(k_dot_stage1_batch, dim3(nblk, b.count), dim3(kDotWg), 0, s, b, nblk, work);
+  hipLaunchKernelGGL(k_dot_stage2_batch, dim3(b.K, b.count), dim3(256), 0, s, b, nblk, work);
+  return hipGetLastError();
 }
 
 hipError_t launch_dot_cols(const double* x, const double* y, int64_t n, int K, double* out, double* work,
