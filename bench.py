@@ -180,6 +180,7 @@ def time_path(fl, ctx, dp, prob, prec, steps, warmup, max_refine, xq, refine_tol
     return {"dt": dt, "steps": steps, "status": int(st), "u": u[:, 0].cpu().numpy(), "phases_ms": phases,
             "pde_residual_rel": pde_residual_rel(fl, ctx, dp, prob, beta),
             "refine_iters": int(infos[-1]["refine_iters"]), "shift": float(infos[-1]["shift"]),
+            "chol_retries": int(infos[-1]["chol_retries"]), "second_pass": int(infos[-1]["second_pass"]),
             "ms_median": float(np.median(per)), "ms_min": float(np.min(per))}
 
 
@@ -296,7 +297,8 @@ def bench_c4(fl, ctx, steps=2):
             e["rel_l2_vs_oracle"] = float(np.linalg.norm(r["u"] - gold["u_test"]) / np.linalg.norm(gold["u_test"]))
         res[name] = {"ms_per_solve": 1e3 * r["dt"] / r["steps"], "ms_median": r["ms_median"], "ms_min": r["ms_min"],
                      "entries_per_s": P * N / (r["phases_ms"]["t_gram_ms"] * 1e-3), "phases_ms": r["phases_ms"],
-                     "accuracy": e, "refine_iters": r["refine_iters"], "status": r["status"]}
+                     "accuracy": e, "refine_iters": r["refine_iters"], "status": r["status"],
+                     "chol_retries": r["chol_retries"], "shift": r["shift"]}
     return res
 
 
