@@ -370,12 +370,14 @@ flsq_status flsq_solve_newton_var(flsq_ctx* ctx, const flsq_basis* basis, const 
                                   const flsq_newton_opts* opts, double tol_du, double* beta_inout,
                                   flsq_newton_trace* trace);
 
-/* Batched Adam step on K x P parameters (all device arrays, updated in place):
- * m = b1 m + (1 - b1) g; v = b2 v + (1 - b2) g^2; p -= lr * (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps);
- * then p[:, clamp_col] = max(p[:, clamp_col], clamp_min) when clamp_col >= 0. */
+/* Batched Adam step on K x P parameters (all device arrays, updated in place; Kingma and Ba, with
+ * Loshchilov and Hutter's decoupled weight decay):
+ * p *= 1 - lr weight_decay; m = b1 m + (1 - b1) g; v = b2 v + (1 - b2) g^2;
+ * p -= lr * (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps);
+ * then p[:, clamp_col] = max(p[:, clamp_col], clamp_min) when clamp_col >= 0.  t >= 1. */
 flsq_status flsq_adam_step(flsq_ctx* ctx, double* params, const double* grads, double* m, double* v, int32_t K,
                            int32_t P, int32_t t, double lr, double b1, double b2, double eps, int32_t clamp_col,
-                           double clamp_min);
+                           double clamp_min, double weight_decay);
 
 #ifdef __cplusplus
 }

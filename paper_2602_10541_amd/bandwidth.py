@@ -4,8 +4,9 @@ The features are frozen base draws What_j with biases b_j; the weights used are 
 with L lower triangular (the anisotropic covariance L L^T), or L = sigma I for the scalar
 bandwidth.  Each evaluation re-solves the regularised least-squares problem exactly on the GPU
 and returns the outer loss ||A(L) beta* - b||^2 with its gradient in L; the outer optimiser is
-AdamW with decoupled weight decay (the paper's hybrid training procedure), run on the host over
-the d(d+1)/2 (or one) parameters.
+AdamW with decoupled weight decay (the paper's hybrid training procedure) over the d(d+1)/2 (or
+one) parameters, each step one ``flsq_adam_step`` on the device; the parameters come back to the
+host only to form L for the next evaluation.
 """
 from __future__ import annotations
 
@@ -54,19 +55,20 @@ class LearnableBandwidth:
         return loss, g
 
     def fit_adamw(self, params0, steps=80, lr=0.1, betas=(0.9, 0.999), eps=1e-8, weight_decay=0.01):
-        """AdamW: p <- p (1 - lr wd), then the bias-corrected Adam step.  Returns the parameters
-        and the loss at the start of every step, and the final parameters."""
-        p = np.atleast_1d(np.asarray(params0, dtype=np.float64)).copy()
-        m = np.zeros_like(p)
-        v = np.zeros_like(p)
+        """AdamW (p <- p (1 - lr wd), then the bias-corrected Adam step) by ``flsq_adam_step``.
+        Returns the parameters and the loss at the start of every step, and the final parameters."""
+        import torch
+        dev = self.beta.device
+        p = torch.tensor(np.atleast_1d(np.asarray(params0, dtype=np.float64)), dtype=torch.float64, device=dev)
+        m = torch.zeros_like(p)
+        v = torch.zeros_like(p)
         b1, b2 = betas
         hist_p, hist_loss = [], []
         for t in range(1, steps + 1):
-            loss, g = self.loss_and_grad(p)
-            hist_p.append(p.copy())
+            ph = p.cpu().numpy()
+            loss, g = self.loss_and_grad(ph)
+            hist_p.append(ph.copy())
             hist_loss.append(loss)
-            p *= 1.0 - lr * weight_decay
-            m = b1 * m + (1.0 - b1) * g
-            v = b2 * v + (1.0 - b2) * g * g
-            p -= lr * (m / (1.0 - b1 ** t)) / (np.sqrt(v / (1.0 - b2 ** t)) + eps)
-        return np.array(hist_p), np.array(hist_loss), p
+            gt = torch.tensor(g, dtype=torch.float64, device=dev)
+            fl.flsq_adam_step(self.ctx, p, gt, m, v, t, lr, b1, b2, eps, weight_decay=weight_decay)
+        return np.array(hist_p), np.array(hist_loss), p.cpu().numpy()

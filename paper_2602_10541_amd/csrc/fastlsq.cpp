@@ -2964,13 +2964,15 @@ flsq_status flsq_solve_newton_var(flsq_ctx* ctx, const flsq_basis* basis, const 
 
 flsq_status flsq_adam_step(flsq_ctx* ctx, double* params, const double* grads, double* m, double* v, int32_t K,
                            int32_t P, int32_t t, double lr, double b1, double b2, double eps, int32_t clamp_col,
-                           double clamp_min) {
+                           double clamp_min, double weight_decay) {
   if (!ctx) return FLSQ_EINVAL;
   if (hipSetDevice(ctx->device) != hipSuccess) return finish(ctx, fail(FLSQ_EHIP, "hipSetDevice failed"));
   if (!params || !grads || !m || !v) return finish(ctx, fail(FLSQ_EINVAL, "NULL argument"));
   if (K < 1 || P < 1 || t < 1) return finish(ctx, fail(FLSQ_EINVAL, "K, P and t must be >= 1"));
   if (clamp_col >= P) return finish(ctx, fail(FLSQ_EINVAL, "clamp_col >= P"));
-  hipError_t he = launch_adam(params, grads, m, v, K, P, t, lr, b1, b2, eps, clamp_col, clamp_min, ctx->stream);
+  if (!std::isfinite(weight_decay) || weight_decay < 0.0) return finish(ctx, fail(FLSQ_EINVAL, "weight_decay < 0"));
+  hipError_t he = launch_adam(params, grads, m, v, K, P, t, lr, b1, b2, eps, clamp_col, clamp_min, weight_decay,
+                              ctx->stream);
   if (he != hipSuccess) return finish(ctx, fail(FLSQ_EHIP, "adam: %s", hipGetErrorString(he)));
   return finish(ctx, ok());
 }

@@ -309,6 +309,6 @@ hipError_t launch_combine_diff(const double* a, const double* b, double* out, in
 hipError_t launch_misfit(const double* U, const double* data, int64_t n_obs, int K, double* loss, double* gu,
                          hipStream_t s);
 hipError_t launch_adam(double* p, const double* g, double* m, double* v, int K, int P, int t, double lr, double b1,
-                       double b2, double eps, int clamp_col, double clamp_min, hipStream_t s);
+                       double b2, double eps, int clamp_col, double clamp_min, double weight_decay, hipStream_t s);
 
 }  // namespace flsq

@@ -128,7 +128,7 @@ hipError_t launch_combine_diff(const double* a, const double* b, double* out, in
 }
 
 __global__ void k_adam(double* p, const double* g, double* m, double* v, int64_t n, int P, double lr, double b1,
-                       double b2, double c1, double c2, double eps, int clamp_col, double clamp_min) {
+                       double b2, double c1, double c2, double eps, int clamp_col, double clamp_min, double decay) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n) return;
   const double gi = g[e];
@@ -136,17 +136,18 @@ __global__ void k_adam(double* p, const double* g, double* m, double* v, int64_t
   const double vi = b2 * v[e] + (1.0 - b2) * gi * gi;
   m[e] = mi;
   v[e] = vi;
-  double pi = p[e] - lr * (mi / c1) / (sqrt(vi / c2) + eps);
+  double pi = p[e] * decay - lr * (mi / c1) / (sqrt(vi / c2) + eps);
   if (clamp_col >= 0 && (int)(e % P) == clamp_col && pi < clamp_min) pi = clamp_min;
   p[e] = pi;
 }
 
 hipError_t launch_adam(double* p, const double* g, double* m, double* v, int K, int P, int t, double lr, double b1,
-                       double b2, double eps, int clamp_col, double clamp_min, hipStream_t s) {
+                       double b2, double eps, int clamp_col, double clamp_min, double weight_decay, hipStream_t s) {
   const int64_t n = (int64_t)K * P;
   const double c1 = 1.0 - pow(b1, (double)t), c2 = 1.0 - pow(b2, (double)t);
+  const double decay = 1.0 - lr * weight_decay;
   hipLaunchKernelGGL(k_adam, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, g, m, v, n, P, lr, b1, b2, c1, c2,
-                     eps, clamp_col, clamp_min);
+                     eps, clamp_col, clamp_min, decay);
   return hipGetLastError();
 }
 

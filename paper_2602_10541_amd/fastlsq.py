@@ -153,7 +153,7 @@ def load(path: str = LIB_PATH):
         "flsq_inverse_prepare": (st, [vp, vp, i64, i64, vp]),
         "flsq_bandwidth_loss_grad": (st, [vp, C.POINTER(flsq_basis), C.POINTER(dbl), C.POINTER(flsq_rows), i32,
                                           C.POINTER(flsq_solve_opts), vp, C.POINTER(dbl), C.POINTER(dbl)]),
-        "flsq_adam_step": (st, [vp, vp, vp, vp, vp, i32, i32, i32, dbl, dbl, dbl, dbl, i32, dbl]),
+        "flsq_adam_step": (st, [vp, vp, vp, vp, vp, i32, i32, i32, dbl, dbl, dbl, dbl, i32, dbl, dbl]),
         "flsq_assemble_var": (st, [vp, C.POINTER(flsq_basis), C.POINTER(flsq_vrows), i32, vp, vp]),
         "flsq_solve_linear_var": (st, [vp, C.POINTER(flsq_basis), C.POINTER(flsq_vrows), i32,
                                        C.POINTER(flsq_solve_opts), vp, C.POINTER(flsq_solve_info)]),
@@ -493,11 +493,13 @@ def flsq_bandwidth_loss_grad(ctx, base: Basis, L, rows: Rows, opts: flsq_solve_o
     return loss.value, np.array(grad[:], dtype=np.float64)
 
 
-def flsq_adam_step(ctx, params, grads, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8, clamp_col=-1, clamp_min=0.0):
-    K, P = params.shape
+def flsq_adam_step(ctx, params, grads, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8, clamp_col=-1, clamp_min=0.0,
+                   weight_decay=0.0):
+    """Adam (AdamW when weight_decay > 0) on device arrays of shape K x P (a 1-D array is 1 x P)."""
+    K, P = (1, params.shape[0]) if params.dim() == 1 else params.shape
     return ctx.check(ctx.lib.flsq_adam_step(ctx.h, _ptr(params), _ptr(grads), _ptr(m), _ptr(v), int(K), int(P),
                                             int(t), float(lr), float(b1), float(b2), float(eps), int(clamp_col),
-                                            float(clamp_min)))
+                                            float(clamp_min), float(weight_decay)))
 
 
 # ---------------------------------------------------------------------------- workload helpers

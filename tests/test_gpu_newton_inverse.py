@@ -246,6 +246,13 @@ def test_adam_matches_reference_formula():
         oracle.adam_update(pr, gn, mr, vr, t, 0.1, clamp_col=3, clamp_min=0.02)
     np.testing.assert_allclose(p.cpu().numpy(), pr, rtol=1e-13, atol=1e-15)
     assert np.any(pr[:, 3] == 0.02)
+    # 10 AdamW steps (decoupled decay 0.05 before the step, then the projection)
+    for t in range(32, 42):
+        gn = rng.normal(size=(5, 4))
+        fl.flsq_adam_step(ctx, p, torch.tensor(gn, dtype=torch.float64, device="cuda"), m, v, t, 0.1,
+                          clamp_col=3, clamp_min=0.02, weight_decay=0.05)
+        oracle.adam_update(pr, gn, mr, vr, t, 0.1, weight_decay=0.05, clamp_col=3, clamp_min=0.02)
+    np.testing.assert_allclose(p.cpu().numpy(), pr, rtol=1e-13, atol=1e-15)
 
 
 @pytest.mark.parametrize("store_matrix,cache", [(False, False), (True, True)])

@@ -110,20 +110,13 @@ def test_bandwidth_workload_shape():
     assert abs(prob.W.std() - 1.0) < 0.08
 
 
-def test_package_adamw_matches_reference_loop():
-    """The package's host AdamW (scalar and packed-L parameters) against the oracle's AdamW (itself
-    pinned to torch.optim.AdamW) on a smooth stand-in loss; no GPU call is made."""
+def test_package_parameter_packing():
+    """The package's packing of the scalar bandwidth and of the lower-triangular L (its AdamW runs on
+    the device and is checked against the oracle's in the GPU tests); no GPU call is made."""
     from paper_2602_10541_amd.bandwidth import LearnableBandwidth, lower_pairs
-
-    def f(s):
-        return (s - 7.0) ** 4 + 0.3 * s, 4.0 * (s - 7.0) ** 3 + 0.3
 
     lb = LearnableBandwidth.__new__(LearnableBandwidth)
     lb.d, lb.scalar, lb.pairs = 2, True, lower_pairs(2)
-    lb.loss_and_grad = lambda p: (lambda lo, g: (lo, np.array([g])))(*f(float(p[0])))
-    ps, losses, _ = lb.fit_adamw([5.0], steps=30, lr=0.1)
-    ref_s, ref_l = oracle.adamw_sigma(f, 5.0, steps=30)
-    assert np.allclose(ps[:, 0], ref_s, rtol=1e-13, atol=0) and np.allclose(losses, ref_l, rtol=1e-12, atol=0)
     assert np.allclose(lb.L_of([2.5]), 2.5 * np.eye(2))
     lb.scalar = False
     L = np.array([[1.0, 0.0], [2.0, 3.0]])
