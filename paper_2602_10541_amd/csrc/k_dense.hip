@@ -268,12 +268,21 @@ __global__ __launch_bounds__(256) void k_trmv_t(const double* __restrict__ X, in
   const int per = (n + kTvSplits - 1) / kTvSplits;
   const int i0 = split * per;
   const int i1 = min(n, i0 + per);
-  double s = 0.0;
-  if (j < n) {
-    const int iend = min(i1, j + 1);
-    for (int i = i0; i < iend; ++i) s = fma(X[(int64_t)i * n + j], v[i], s);
-    work[(int64_t)split * n + j] = s;
+  if (j >= n) return;
+  // rows i0 .. min(i1, j + 1) - 1 of column j; four independent partial sums keep four loads in
+  // flight (the order of the terms is fixed, so the result does not depend on scheduling)
+  const int iend = min(i1, j + 1);
+  const double* col = X + j;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int i = i0;
+  for (; i + 4 <= iend; i += 4) {
+    s0 = fma(col[(int64_t)i * n], v[i], s0);
+    s1 = fma(col[(int64_t)(i + 1) * n], v[i + 1], s1);
+    s2 = fma(col[(int64_t)(i + 2) * n], v[i + 2], s2);
+    s3 = fma(col[(int64_t)(i + 3) * n], v[i + 3], s3);
   }
+  for (; i < iend; ++i) s0 = fma(col[(int64_t)i * n], v[i], s0);
+  work[(int64_t)split * n + j] = (s0 + s1) + (s2 + s3);
 }
 
 // The kTvSplits partials of k_trmv_t, summed in split order: all loads of a column issued at
@@ -290,15 +299,24 @@ __global__ __launch_bounds__(64) void k_sum_tv_splits(const double* __restrict__
   out[j] = s;
 }
 
-// z = X y: z_i = sum_{j >= i} X[i][j] y_j; one wave per row, lanes stride the row.
+// z = X y: z_i = sum_{j >= i} X[i][j] y_j; one wave per row, lanes stride the row with four
+// independent partial sums, then a fixed butterfly.
 __global__ __launch_bounds__(256) void k_trmv_n(const double* __restrict__ X, int n, const double* __restrict__ y,
                                                 double* __restrict__ z) {
   const int lane = threadIdx.x & 63;
   const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (i >= n) return;
   const double* row = X + (int64_t)i * n;
-  double s = 0.0;
-  for (int j = i + lane; j < n; j += 64) s = fma(row[j], y[j], s);
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int j = i + lane;
+  for (; j + 192 < n; j += 256) {
+    s0 = fma(row[j], y[j], s0);
+    s1 = fma(row[j + 64], y[j + 64], s1);
+    s2 = fma(row[j + 128], y[j + 128], s2);
+    s3 = fma(row[j + 192], y[j + 192], s3);
+  }
+  for (; j < n; j += 64) s0 = fma(row[j], y[j], s0);
+  double s = (s0 + s1) + (s2 + s3);
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off);
   if (lane == 0) z[i] = s;
