@@ -231,121 +231,110 @@ __device__ __forceinline__ void tri_coords(int t, int nt, int* ti, int* tj) {
 // rows and columns [k0 + kNb, n), in 128 x 128 tiles (ti <= tj), one workgroup per tile:
 // wave w computes the 64 x 64 quadrant (w / 2, w % 2) with FP64 MFMA 16x16x4.
 //
-// Both 64 x 128 panel slices of the tile are fetched at once with direct global-to-LDS
-// loads (all in flight together), laid out in the order the matrix cores consume them: the
-// operand of k-step kk and 16-column block c is 64 consecutive doubles, lane l holding
-// panel row 4 kk + l / 16 and column 16 c + l % 16, so every operand read is one
-// contiguous, conflict-free 512-byte access.
+// The operands come straight from the panel (block row k0, just solved) into registers in
+// the order the matrix cores consume them: the operand of k-step kk for 16 columns from c0
+// is one load whose lane l reads panel row 4 kk + l / 16, column c0 + l % 16 (four 128-byte
+// pieces).  Each wave keeps the loads of the next two k-steps in flight while it multiplies,
+// and nothing is staged in LDS, so two workgroups share a CU: one's loads overlap the other's
+// products, and a step with up to twice as many tiles as CUs still runs in one round.
 //
 // Workgroup 0 owns the next diagonal block (quadrant (0, 0) of tile (0, 0), which the tile's
 // own workgroup skips): it loads the block straight into the accumulator layout of the
 // factorisation, applies the update there and factors it without a round trip through
 // memory, so the critical path of a step is one 64-deep update of one block plus its
 // factorisation.
-constexpr int kSyrkPanel = 16 * 8 * 64;   // doubles per 64 x 128 panel slice
+constexpr int kSyrkRing = 3;   // k-steps of operands held in registers (two in flight)
 
-__device__ __forceinline__ void syrk_fetch_panel(const double* G, int n, int k0, int c0, double* dst, int wave,
-                                                 int lane) {
-  // 256 instructions of 256 bytes (64 lanes x 4 bytes) per panel; instruction q fills doubles
-  // [32 q, 32 q + 32) of the operand-ordered slice, lane pairs moving the two halves of a
-  // double (4-byte pieces keep every source in bounds and aligned for any n).  Columns
-  // past n repeat column n - 1: their products are never stored.
-  for (int q = wave; q < kSyrkPanel / 32; q += 4) {
-    const int p = 32 * q + (lane >> 1);
-    const int blk = p >> 6, l = p & 63;              // operand block kk * 8 + c, MFMA lane l
-    const int kk = blk >> 3, c = blk & 7;
-    const int row = 4 * kk + (l >> 4), col = min(c0 + 16 * c + (l & 15), n - 1);
-    const char* src = (const char*)(G + (int64_t)(k0 + row) * n + col) + 4 * (lane & 1);
-    __builtin_amdgcn_global_load_lds((const void*)src, (__attribute__((address_space(3))) void*)(dst + 32 * q), 4, 0,
-                                     0);
-  }
+__device__ __forceinline__ double syrk_operand(const double* P, int n, int kk, int c0, int lane) {
+  return P[(int64_t)(4 * kk + (lane >> 4)) * n + min(c0 + (lane & 15), n - 1)];
 }
 
-__global__ __launch_bounds__(256, 1) void k_syrk_potrf(double* G, int n, int k0, int* info, double boost,
+__global__ __launch_bounds__(256, 2) void k_syrk_potrf(double* G, int n, int k0, int* info, double boost,
                                                        int* nboost) {
-  extern __shared__ __align__(16) double smem_d[];     // A and B panels; diagonal block: panel, then S
+  __shared__ double S[kNb * kNb];
+  __shared__ int sbad[2];
   const int k1 = k0 + kNb;
   const int nt = (n - k1 + 127) / 128;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const double* P = G + (int64_t)k0 * n;   // the panel: rows k0 .. k0 + 63
   if (blockIdx.x == 0) {
-    // the next diagonal block: its update in registers, then its factorisation
-    double* sP = smem_d;
-    syrk_fetch_panel(G, n, k0, k1, sP, wave, lane);
+    // the next diagonal block: its update in registers, then its factorisation.  Columns past
+    // n read column n - 1 (clamped) and only touch the identity padding, which is never stored.
     f64x4 acc[4];
     potrf64_load(G, n, k1, acc);
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
+    double ra[kSyrkRing], rb[kSyrkRing][4];
+    auto fetch = [&](int kk, int slot) {
+      ra[slot] = syrk_operand(P, n, kk, k1 + 16 * wave, lane);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) rb[slot][c] = syrk_operand(P, n, kk, k1 + 16 * c, lane);
+    };
+    fetch(0, 0);
+    fetch(1, 1);
     // all four tiles of every wave, with no branch: tiles below the diagonal (c < wave) take
     // the update too and are never read
-#pragma unroll 4
-    for (int kk = 0; kk < kNb / 4; ++kk) {
-      const double a = -sP[(kk * 8 + wave) * 64 + lane];
 #pragma unroll
-      for (int c = 0; c < 4; ++c)
-        acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, sP[(kk * 8 + c) * 64 + lane], acc[c], 0, 0, 0);
+    for (int kk = 0; kk < kNb / 4; ++kk) {
+      if (kk + 2 < kNb / 4) fetch(kk + 2, (kk + 2) % kSyrkRing);
+      const int s = kk % kSyrkRing;
+      const double a = -ra[s];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, rb[s][c], acc[c], 0, 0, 0);
     }
-    potrf64_factor(acc, G, n, k1, info, smem_d + kSyrkPanel, (int*)(smem_d + kSyrkPanel + kNb * kNb), boost,
-                   nboost);
+    potrf64_factor(acc, G, n, k1, info, S, sbad, boost, nboost);
     return;
   }
   int ti, tj;
   tri_coords(blockIdx.x - 1, nt, &ti, &tj);
   const int qi = wave >> 1, qj = wave & 1;
-  double* sPa = smem_d;
-  double* sPb = (ti == tj) ? smem_d : smem_d + kSyrkPanel;
-  syrk_fetch_panel(G, n, k0, k1 + ti * 128, sPa, wave, lane);
-  if (ti != tj) syrk_fetch_panel(G, n, k0, k1 + tj * 128, sPb, wave, lane);
   const int i0 = k1 + ti * 128 + qi * 64, j0 = k1 + tj * 128 + qj * 64;
   // quadrant (0, 0) of tile (0, 0) is the next diagonal block (workgroup 0)
   const bool active = !(ti == tj && qi > qj) && !(ti == 0 && tj == 0 && qi == 0 && qj == 0) && i0 < n && j0 < n;
+  if (!active) return;
   const int r16 = lane & 15, k4 = lane >> 4;
-  // the 64 old values of the quadrant go out together with the panel loads, so their memory
-  // round trip overlaps the panels' instead of following the products (nothing else in this
-  // launch writes them: workgroup 0 owns only quadrant (0, 0) of tile (0, 0))
-  double old[4][4][4];
-  if (active) {
+  f64x4 acc[4][4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[r][c] = f64x4{0.0, 0.0, 0.0, 0.0};
+  double ra[kSyrkRing][4], rb[kSyrkRing][4];
+  auto fetch = [&](int kk, int slot) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      ra[slot][r] = syrk_operand(P, n, kk, i0 + 16 * r, lane);
+      rb[slot][r] = syrk_operand(P, n, kk, j0 + 16 * r, lane);
+    }
+  };
+  fetch(0, 0);
+  fetch(1, 1);
+#pragma unroll
+  for (int kk = 0; kk < kNb / 4; ++kk) {
+    if (kk + 2 < kNb / 4) fetch(kk + 2, (kk + 2) % kSyrkRing);
+    const int s = kk % kSyrkRing;
 #pragma unroll
     for (int r = 0; r < 4; ++r)
 #pragma unroll
-      for (int c = 0; c < 4; ++c)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int i = i0 + 16 * r + 4 * v + k4;
-          const int j = j0 + 16 * c + r16;
-          old[r][c][v] = (i < n && j < n && j >= i) ? G[(int64_t)i * n + j] : 0.0;
-        }
+      for (int c = 0; c < 4; ++c) acc[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(ra[s][r], rb[s][c], acc[r][c], 0, 0, 0);
   }
-  __builtin_amdgcn_s_waitcnt(0);   // this wave's loads have landed in LDS
-  __syncthreads();
-  if (active) {
-    f64x4 acc[4][4];
+  // one row block at a time: read its 16 old values per lane, subtract, store
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
+  for (int r = 0; r < 4; ++r) {
+    double old[4][4];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) acc[r][c] = f64x4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll 4
-    for (int kk = 0; kk < kNb / 4; ++kk) {
-      double a[4], b[4];
+    for (int c = 0; c < 4; ++c)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        a[r] = sPa[(kk * 8 + qi * 4 + r) * 64 + lane];
-        b[r] = sPb[(kk * 8 + qj * 4 + r) * 64 + lane];
+      for (int v = 0; v < 4; ++v) {
+        const int i = i0 + 16 * r + 4 * v + k4;
+        const int j = j0 + 16 * c + r16;
+        old[c][v] = (i < n && j < n && j >= i) ? G[(int64_t)i * n + j] : 0.0;
       }
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
+    for (int c = 0; c < 4; ++c)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) acc[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[r], b[c], acc[r][c], 0, 0, 0);
-    }
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-      for (int c = 0; c < 4; ++c)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int i = i0 + 16 * r + 4 * v + k4;
-          const int j = j0 + 16 * c + r16;
-          if (i < n && j < n && j >= i) G[(int64_t)i * n + j] = old[r][c][v] - acc[r][c][v];
-        }
+      for (int v = 0; v < 4; ++v) {
+        const int i = i0 + 16 * r + 4 * v + k4;
+        const int j = j0 + 16 * c + r16;
+        if (i < n && j < n && j >= i) G[(int64_t)i * n + j] = old[c][v] - acc[r][c][v];
+      }
   }
 }
 
@@ -397,15 +386,8 @@ hipError_t launch_trsm_row(double* G, int n, int k0, hipStream_t s) {
 hipError_t launch_syrk_potrf(double* G, int n, int k0, int* info, double boost, int* nboost, hipStream_t s) {
   const int rem = n - k0 - kNb;
   if (rem <= 0) return hipSuccess;
-  const size_t lds = sizeof(double) * 2 * kSyrkPanel;   // 128 KB: two panel slices
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_syrk_potrf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
   const int nt = (rem + 127) / 128;
-  hipLaunchKernelGGL(k_syrk_potrf, dim3(1 + nt * (nt + 1) / 2), dim3(256), lds, s, G, n, k0, info, boost, nboost);
+  hipLaunchKernelGGL(k_syrk_potrf, dim3(1 + nt * (nt + 1) / 2), dim3(256), 0, s, G, n, k0, info, boost, nboost);
   return hipGetLastError();
 }
 
