@@ -630,91 +630,32 @@ Err upload_descs(flsq_ctx* c, const std::vector<GemmDesc>& h, GemmDesc** d_out) 
   return ok();
 }
 
-// In-place upper Cholesky of G (only the upper triangle is read), and X = U^{-1} (upper,
-// zero below the diagonal).  Pivots below boost (> 0) are raised to it (their count goes to
-// *boosted_host); info_host > 0 at the first failed pivot (1-based: non-finite, or non-positive
-// when boost = 0).  The status is read before the inverse is formed, and a failed factor
-// returns without it.
-Err cholesky_inv(flsq_ctx* c, double* G, double* X, int n, int* info_host, double boost, int* boosted_host) {
+// In-place upper Cholesky of G (only the upper triangle is read), and X = D U^{-1} (upper,
+// zero below the diagonal; d nullable = ones), whose transpose W = U^{-T} is formed block row
+// by block row inside the factorisation steps.  Pivots below boost (> 0) are raised to it
+// (their count goes to *boosted_host); info_host > 0 at the first failed pivot (1-based:
+// non-finite, or non-positive when boost = 0), the steps after a failure return at once, and
+// X is then not written.
+Err cholesky_inv(flsq_ctx* c, double* G, double* X, int n, const double* d, int* info_host, double boost,
+                 int* boosted_host) {
   int* info;
+  double* W;
   hipStream_t st = c->stream;
   CHECK_ERR(ws_get(c, "chol_info", 2, &info));
+  CHECK_ERR(ws_get(c, "chol_w", (size_t)n * n, &W));
   CHECK_HIP(hipMemsetAsync(info, 0, 2 * sizeof(int), st));
-  CHECK_HIP(hipMemsetAsync(X, 0, sizeof(double) * n * n, st));
-  const int nblk = (n + kNb - 1) / kNb;
-  // X off-diagonal blocks, bottom-up: pairs of adjacent ranges [lo, mid), [mid, hi) of blocks:
-  // T = U_12 X_22, then X_12 = -X_11 T.  Same-level pairs are independent (one batch).
-  std::vector<std::vector<GemmDesc>> lvT, lvX;
-  double* T;
-  CHECK_ERR(ws_get(c, "inv_T", (size_t)n * n, &T));
-  for (int s = 1; s < nblk; s *= 2) {
-    std::vector<GemmDesc> a, b2;
-    for (int lo = 0; lo + s < nblk; lo += 2 * s) {
-      const int mid = lo + s, hi = std::min(nblk, lo + 2 * s);
-      const int r0 = lo * kNb, c0 = mid * kNb;
-      const int wl = std::min(mid * kNb, n) - r0, wr = std::min(hi * kNb, n) - c0;
-      GemmDesc d1;   // T(r0.., c0..) = U(r0.., c0..) X(c0.., c0..)
-      d1.A = G + (int64_t)r0 * n + c0;
-      d1.B = X + (int64_t)c0 * n + c0;
-      d1.C = T + (int64_t)r0 * n + c0;
-      d1.M = wl;
-      d1.N = wr;
-      d1.K = wr;
-      d1.lda = d1.ldb = d1.ldc = n;
-      d1.tri = 1;   // X22 is upper triangular
-      a.push_back(d1);
-      GemmDesc d2;   // X(r0.., c0..) = -X(r0.., r0..) T
-      d2.A = X + (int64_t)r0 * n + r0;
-      d2.B = T + (int64_t)r0 * n + c0;
-      d2.C = X + (int64_t)r0 * n + c0;
-      d2.M = wl;
-      d2.N = wr;
-      d2.K = wl;
-      d2.lda = d2.ldb = d2.ldc = n;
-      d2.tri = 2;   // X11 is upper triangular
-      b2.push_back(d2);
-    }
-    lvT.push_back(a);
-    lvX.push_back(b2);
-  }
-  std::vector<GemmDesc> all;
-  std::vector<size_t> offT, offX;
-  for (size_t l = 0; l < lvT.size(); ++l) {
-    offT.push_back(all.size());
-    all.insert(all.end(), lvT[l].begin(), lvT[l].end());
-    offX.push_back(all.size());
-    all.insert(all.end(), lvX[l].begin(), lvX[l].end());
-  }
-  GemmDesc* dd;
-  CHECK_ERR(upload_descs(c, all, &dd));
+  CHECK_HIP(hipMemsetAsync(W, 0, sizeof(double) * n * n, st));
   // block 0 first; every trailing update also factors the next diagonal block
   CHECK_HIP(launch_potrf(G, n, 0, info, boost, info + 1, st));
-  for (int k0 = 0; k0 + kNb < n; k0 += kNb) {
-    CHECK_HIP(launch_trsm_row(G, n, k0, st));
-    CHECK_HIP(launch_syrk_potrf(G, n, k0, info, boost, info + 1, st));
+  for (int k0 = 0; k0 < n; k0 += kNb) {
+    CHECK_HIP(launch_trsm_row(G, W, n, k0, info, st));
+    CHECK_HIP(launch_syrk_potrf(G, W, n, k0, info, boost, info + 1, st));
   }
   int hinfo[2] = {0, 0};
   CHECK_ERR(read_back(c, hinfo, info, sizeof hinfo));
   *info_host = hinfo[0];
   *boosted_host = hinfo[1];
-  if (hinfo[0] != 0) return ok();
-  CHECK_HIP(launch_trinv_diag(G, n, X, st));
-  // split-K partials of the sparse levels: at most n^2 doubles (the full-level products hold
-  // M N <= n^2 / 4 per pair, up to 4 splits at the top level)
-  double* gwork;
-  const size_t gwork_elems = (size_t)n * n;
-  CHECK_ERR(ws_get(c, "chol_gwork", gwork_elems, &gwork));
-  for (size_t l = 0; l < lvT.size(); ++l) {
-    int maxM = 0, maxN = 0, maxKT = 0, maxKX = 0;
-    for (const GemmDesc& d : lvT[l]) {
-      maxM = std::max(maxM, d.M);
-      maxN = std::max(maxN, d.N);
-      maxKT = std::max(maxKT, d.K);
-    }
-    for (const GemmDesc& d : lvX[l]) maxKX = std::max(maxKX, d.K);
-    CHECK_HIP(launch_gemm_tri(dd + offT[l], (int)lvT[l].size(), maxM, maxN, maxKT, 1.0, gwork, gwork_elems, st));
-    CHECK_HIP(launch_gemm_tri(dd + offX[l], (int)lvX[l].size(), maxM, maxN, maxKX, -1.0, gwork, gwork_elems, st));
-  }
+  if (hinfo[0] == 0) CHECK_HIP(launch_inv_transpose(W, d, n, X, st));
   return ok();
 }
 
@@ -758,9 +699,8 @@ Err factor_with_retries(flsq_ctx* c, const double* Gsrc, double* U, double* X, i
   for (int attempt = 0; attempt < 8; ++attempt) {
     CHECK_HIP(launch_equilibrate(Gsrc, U, n, d, mu, rel, c->stream));
     int info = 0, nb = 0;
-    CHECK_ERR(cholesky_inv(c, U, X, n, &info, boost, &nb));
+    CHECK_ERR(cholesky_inv(c, U, X, n, d, &info, boost, &nb));
     if (info == 0) {
-      CHECK_HIP(launch_scale_rows(X, n, d, c->stream));
       *shift_used = rel;
       if (boosted) *boosted = nb;
       return ok();

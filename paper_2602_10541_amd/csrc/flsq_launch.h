@@ -192,19 +192,21 @@ hipError_t launch_newton_residual_runs(const PassGeo& pg, const double* beta, co
 // ---- dense FP64 linear algebra on the upper Cholesky factor (row-major, G = U^T U)
 constexpr int kNb = 64;
 // Blocked Cholesky steps (k_chol.hip): factor the diagonal block at k0 in place; block-row
-// solve U_kj = U_kk^{-T} G_kj for columns >= k0 + kNb; trailing update of [k0 + kNb, n)
-// fused with the factorisation of the next diagonal block; inverses of all diagonal blocks
-// into the diagonal blocks of X.  Pivots below boost (> 0) are raised to it and counted in
-// *nboost; with boost = 0, *info receives the first non-positive pivot (1-based).
+// solve U_kj = U_kk^{-T} G_kj for columns >= k0 + kNb together with block row k of the
+// inverse W = U^{-T} (lower triangular); trailing update of [k0 + kNb, n) and of W's later
+// block rows, fused with the factorisation of the next diagonal block.  W starts zeroed and is
+// complete after the step of the last block; launch_inv_transpose then writes X = D W^T
+// (upper, zero below; d nullable).  Pivots below boost (> 0) are raised to it and counted in
+// *nboost; with boost = 0, *info receives the first non-positive pivot (1-based), after which
+// the remaining steps return at once.
 hipError_t launch_potrf(double* G, int n, int k0, int* info, double boost, int* nboost, hipStream_t s);
-hipError_t launch_trsm_row(double* G, int n, int k0, hipStream_t s);
-hipError_t launch_syrk_potrf(double* G, int n, int k0, int* info, double boost, int* nboost, hipStream_t s);
-hipError_t launch_trinv_diag(const double* G, int n, double* X, hipStream_t s);
+hipError_t launch_trsm_row(double* G, double* W, int n, int k0, const int* info, hipStream_t s);
+hipError_t launch_syrk_potrf(double* G, double* W, int n, int k0, int* info, double boost, int* nboost,
+                             hipStream_t s);
+hipError_t launch_inv_transpose(const double* W, const double* d, int n, double* X, hipStream_t s);
 // dst = D src D + (diag_add + mu D^2) on the diagonal (upper triangle), D = diag(src)^{-1/2} -> d.
 hipError_t launch_equilibrate(const double* G, double* dst, int n, double* d, double mu, double diag_add,
                               hipStream_t s);
-// X <- diag(d) X
-hipError_t launch_scale_rows(double* X, int n, const double* d, hipStream_t s);
 // C = alpha op(A) B + beta C per descriptor (op(A) = A^T when transA); descriptors in device memory.
 struct GemmDesc {
   const double* A;

@@ -1,12 +1,13 @@
 // Blocked right-looking Cholesky G = U^T U of the regularised Gram (upper triangle,
-// row-major, in place) and the inverses X_kk = U_kk^{-1} of its diagonal blocks.
+// row-major, in place), with the inverse built alongside, one block row of W = U^{-T} per step.
 //
 // Block size kNb = 64.  For each block row k (host loop in fastlsq.cpp):
-//   k_trsm_row    U_kj = U_kk^{-T} G_kj for every block column j > k (forward substitution)
-//   k_syrk_potrf  G_ij -= U_ki^T U_kj over the trailing upper triangle (FP64 MFMA), and the
-//                 workgroup that owns the next diagonal block factors it right after updating it
-// Block 0 is factored by k_potrf before the loop; k_trinv inverts all diagonal blocks in one
-// launch afterwards (they are independent once U is known).
+//   k_trsm_row       U_kj = U_kk^{-T} G_kj for every block column j > k (forward substitution),
+//                    and block row k of W from the terms accumulated so far
+//   k_syrk_potrf     G_ij -= U_ki^T U_kj over the trailing upper triangle and W_j -= U_kj^T W_k
+//                    for the later block rows (FP64 MFMA); the workgroup that owns the next
+//                    diagonal block factors it right after updating it
+// Block 0 is factored by k_potrf before the loop; k_inv_transpose writes X = D W^T at the end.
 //
 // The 64 x 64 factorisation runs on one 256-thread workgroup and keeps the block in the
 // FP64 MFMA 16x16x4 accumulator layout: wave q holds rows 16q .. 16q + 15 as four 16 x 16
@@ -19,6 +20,8 @@
 // next diagonal block in registers and go straight on to its factorisation.
 #include "flsq_device.h"
 #include "flsq_launch.h"
+
+#include <algorithm>
 
 namespace flsq {
 
@@ -48,7 +51,8 @@ __device__ __forceinline__ void potrf64_load(const double* G, int n, int k0, f64
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int i = 16 * q + 4 * v + (lane >> 4), j = 16 * c + (lane & 15);
-      acc[c][v] = (i < nbk && j < nbk && i <= j) ? base[(int64_t)i * n + j] : (i == j ? 1.0 : 0.0);
+      const double g = base[(int64_t)min(i, nbk - 1) * n + min(j, nbk - 1)];   // in bounds, unconditional
+      acc[c][v] = (i < nbk && j < nbk && i <= j) ? g : (i == j ? 1.0 : 0.0);
     }
 }
 
@@ -142,41 +146,81 @@ __global__ __launch_bounds__(256) void k_potrf(double* G, int n, int k0, int* in
 // unit-diagonal factor: U_kk = D V, D = diag(U_kk), so y = D^{-1} z with z = V^{-T} g,
 // z_m = g_m - sum_{l < m} V_lm z_l.
 //
+// The same launch finishes block row k of W = U^{-T} (the inverse of the lower factor U^T),
+// which is built one block row per step alongside the factorisation (U^T W = I read one
+// block row at a time): W_k = U_kk^{-T} (I_k - sum_{l < k} U_lk^T W_l).  The bracket has been
+// accumulated in W by the trailing updates of the earlier steps (its block k holds the
+// identity, taken implicitly); its columns 0 .. k0 + nbk are solved by the same substitution.
+// Keeping W = X^T, not X = U^{-1}, makes every access of the inverse a row access, like G's.
+//
 // Lane m of a wave holds row m; each wave solves kTrsmCols columns at once (independent
 // chains).  Step l reads z_l from lane l (a register broadcast) and every lane applies
 // one multiply-add per column with its V_lm, which is zero for m <= l so the update
-// needs no mask.  V (strictly upper, scaled rows) sits in LDS; the workgroup's
-// 64 x (4 kTrsmCols) slab of G moves through LDS so that global accesses stay coalesced.
+// needs no mask.  V (strictly upper, scaled rows; a short last block is padded with the
+// identity) sits in LDS; the workgroup's 64 x 16 slab moves through LDS so that global
+// accesses stay coalesced.  Workgroups [0, g_slabs) take 16 columns of G each, the rest 16
+// columns of W each.
 constexpr int kTrsmCols = 4;
 constexpr int kTrsmWaves = 4;
 constexpr int kTrsmSlab = kTrsmCols * kTrsmWaves;   // 16 columns per workgroup
 
-__global__ __launch_bounds__(256) void k_trsm_row(double* G, int n, int k0) {
+__global__ __launch_bounds__(256) void k_trsm_row(double* G, double* W, int n, int k0, int g_slabs,
+                                                  const int* info) {
   __shared__ double V[kNb][kNb + 1];
   __shared__ double Y[kNb][kTrsmSlab + 1];
   __shared__ double rinv[kNb];
+  const int failed = *info;   // tested once the staging loads are in flight
   const int t = threadIdx.x;
-  const int64_t jbase = (int64_t)k0 + kNb + (int64_t)blockIdx.x * kTrsmSlab;
-  // stage U_kk (always a full 64 x 64 block here): thread t covers column t % 64 of rows t / 64 + 4 r
+  const int nbk = min(kNb, n - k0);
+  const bool wpart = (int)blockIdx.x >= g_slabs;
+  // G: columns from k0 + kNb; W: columns [0, k0 + nbk), the block k0 .. k0 + nbk the identity
+  double* B = wpart ? W : G;
+  const int jbase = wpart ? ((int)blockIdx.x - g_slabs) * kTrsmSlab : k0 + kNb + (int)blockIdx.x * kTrsmSlab;
+  const int jend = wpart ? k0 + nbk : n;
+  // Every load below reads a clamped, in-bounds address unconditionally and the padding is
+  // selected afterwards, so all of them are in flight together (a conditional load would be
+  // a branch with a wait of its own).
+  // U_kk: thread t covers column t % 64 of rows t / 64 + 4 r (identity past nbk)
+  double uv[kNb / 4], yv[kNb / 16];
+  {
+    const int c = t & 63, cc = min(c, nbk - 1);
+#pragma unroll
+    for (int r = 0; r < kNb / 4; ++r) {
+      const int l = min((t >> 6) + 4 * r, nbk - 1);
+      uv[r] = G[(int64_t)(k0 + l) * n + k0 + cc];
+    }
+  }
+  // the slab: 16 threads per row, 16 rows per pass
+  {
+    const int c = t & (kTrsmSlab - 1);
+    const int jc = min(jbase + c, jend - 1);
+#pragma unroll
+    for (int r = 0; r < kNb / 16; ++r) {
+      const int l = min((t >> 4) + 16 * r, nbk - 1);
+      yv[r] = B[(int64_t)(k0 + l) * n + jc];
+    }
+  }
   {
     const int c = t & 63;
 #pragma unroll
     for (int r = 0; r < kNb / 4; ++r) {
       const int l = (t >> 6) + 4 * r;
-      V[l][c] = G[(int64_t)(k0 + l) * n + k0 + c];
+      V[l][c] = (l < nbk && c < nbk) ? uv[r] : (l == c ? 1.0 : 0.0);
     }
   }
-  // stage the slab: 16 threads per row, 16 rows per pass
   {
     const int c = t & (kTrsmSlab - 1);
-    const int64_t j = jbase + c;
+    const int j = jbase + c;
 #pragma unroll
     for (int r = 0; r < kNb / 16; ++r) {
       const int l = (t >> 4) + 16 * r;
-      Y[l][c] = (j < n) ? G[(int64_t)(k0 + l) * n + j] : 0.0;
+      double v = 0.0;
+      if (j < jend && l < nbk) v = (wpart && j >= k0) ? (l == j - k0 ? 1.0 : 0.0) : yv[r];
+      Y[l][c] = v;
     }
   }
   __syncthreads();
+  if (failed != 0) return;   // a failed pivot: this attempt is abandoned
   if (t < kNb) rinv[t] = 1.0 / V[t][t];
   __syncthreads();
   // V_lm = U_lm / U_ll for m > l, 0 on and below the diagonal
@@ -205,12 +249,12 @@ __global__ __launch_bounds__(256) void k_trsm_row(double* G, int n, int k0) {
   __syncthreads();
   {
     const int c = t & (kTrsmSlab - 1);
-    const int64_t j = jbase + c;
-    if (j < n) {
+    const int j = jbase + c;
+    if (j < jend) {
 #pragma unroll
       for (int r = 0; r < kNb / 16; ++r) {
         const int l = (t >> 4) + 16 * r;
-        G[(int64_t)(k0 + l) * n + j] = Y[l][c];
+        if (l < nbk) B[(int64_t)(k0 + l) * n + j] = Y[l][c];
       }
     }
   }
@@ -229,14 +273,18 @@ __device__ __forceinline__ void tri_coords(int t, int nt, int* ti, int* tj) {
 
 // Trailing update of the upper triangle G_ij -= sum_l U_{k0+l,i} U_{k0+l,j}, i <= j, over
 // rows and columns [k0 + kNb, n), in 128 x 128 tiles (ti <= tj), one workgroup per tile:
-// wave w computes the 64 x 64 quadrant (w / 2, w % 2) with FP64 MFMA 16x16x4.
+// wave w computes the 64 x 64 quadrant (w / 2, w % 2) with FP64 MFMA 16x16x4.  With W = U^{-T}
+// given, the same launch applies this step's term of the inverse to the later block rows,
+// W_j -= U_kj^T W_k for the rows [k0 + kNb, n) and the columns [0, k0 + kNb), in 128 x 128 tiles
+// after the triangle's; it has the triangle's form, with W's block row k as the second panel.
 //
-// The operands come straight from the panel (block row k0, just solved) into registers in
-// the order the matrix cores consume them: the operand of k-step kk for 16 columns from c0
-// is one load whose lane l reads panel row 4 kk + l / 16, column c0 + l % 16 (four 128-byte
-// pieces).  Each wave keeps the loads of the next two k-steps in flight while it multiplies,
-// and nothing is staged in LDS, so two workgroups share a CU: one's loads overlap the other's
-// products, and a step with up to twice as many tiles as CUs still runs in one round.
+// The operands come straight from the panels (block row k0 of G, just solved, and of W) into
+// registers in the order the matrix cores consume them: the operand of k-step kk for 16
+// columns from c0 is one load whose lane l reads panel row 4 kk + l / 16, column c0 + l % 16
+// (four 128-byte pieces).  Each wave keeps the loads of the next two k-steps in flight while
+// it multiplies, and nothing is staged in LDS, so two workgroups share a CU: one's loads
+// overlap the other's products, and a step with up to twice as many tiles as CUs still runs
+// in one round.
 //
 // Workgroup 0 owns the next diagonal block (quadrant (0, 0) of tile (0, 0), which the tile's
 // own workgroup skips): it loads the block straight into the accumulator layout of the
@@ -249,12 +297,75 @@ __device__ __forceinline__ double syrk_operand(const double* P, int n, int kk, i
   return P[(int64_t)(4 * kk + (lane >> 4)) * n + min(c0 + (lane & 15), n - 1)];
 }
 
-__global__ __launch_bounds__(256, 2) void k_syrk_potrf(double* G, int n, int k0, int* info, double boost,
+// One 64 x 64 quadrant: C[i0.., j0..] -= PA[:, i0..]^T PB[:, j0..] over the 64 panel rows;
+// only entries with i < n, j < col_end (and j >= i when TRI) are touched.  The old values are
+// read after the products, 16 per lane at a time with the next 16 already in flight, from
+// clamped in-bounds addresses (a conditional load would wait on its own); reading them up
+// front instead delays the next diagonal block's loads, which are on the critical path.
+template <bool TRI>
+__device__ __forceinline__ void syrk_quadrant(double* C, const double* PA, const double* PB, int n, int i0, int j0,
+                                              int col_end, int lane) {
+  const int r16 = lane & 15, k4 = lane >> 4;
+  f64x4 acc[4][4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[r][c] = f64x4{0.0, 0.0, 0.0, 0.0};
+  double ra[kSyrkRing][4], rb[kSyrkRing][4];
+  auto fetch = [&](int kk, int slot) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      ra[slot][r] = syrk_operand(PA, n, kk, i0 + 16 * r, lane);
+      rb[slot][r] = syrk_operand(PB, n, kk, j0 + 16 * r, lane);
+    }
+  };
+  fetch(0, 0);
+  fetch(1, 1);
+#pragma unroll
+  for (int kk = 0; kk < kNb / 4; ++kk) {
+    if (kk + 2 < kNb / 4) fetch(kk + 2, (kk + 2) % kSyrkRing);
+    const int s = kk % kSyrkRing;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(ra[s][r], rb[s][c], acc[r][c], 0, 0, 0);
+  }
+  double old[2][16];
+  auto load_old = [&](int r, int buf) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = i0 + 16 * r + 4 * v + k4;
+        const int j = j0 + 16 * c + r16;
+        old[buf][4 * c + v] = C[(int64_t)min(i, n - 1) * n + min(j, col_end - 1)];
+      }
+  };
+  load_old(0, 0);
+  load_old(1, 1);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int buf = r & 1;
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = i0 + 16 * r + 4 * v + k4;
+        const int j = j0 + 16 * c + r16;
+        if (i < n && j < col_end && (!TRI || j >= i)) C[(int64_t)i * n + j] = old[buf][4 * c + v] - acc[r][c][v];
+      }
+    if (r + 2 < 4) load_old(r + 2, buf);
+  }
+}
+
+__global__ __launch_bounds__(256, 2) void k_syrk_potrf(double* G, double* W, int n, int k0, int* info, double boost,
                                                        int* nboost) {
   __shared__ double S[kNb * kNb];
   __shared__ int sbad[2];
+  const int failed = *info;   // a failed pivot abandons the attempt; tested once loads are out
   const int k1 = k0 + kNb;
   const int nt = (n - k1 + 127) / 128;
+  const int ntri = nt * (nt + 1) / 2;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const double* P = G + (int64_t)k0 * n;   // the panel: rows k0 .. k0 + 63
   if (blockIdx.x == 0) {
@@ -270,6 +381,7 @@ __global__ __launch_bounds__(256, 2) void k_syrk_potrf(double* G, int n, int k0,
     };
     fetch(0, 0);
     fetch(1, 1);
+    if (failed != 0) return;
     // all four tiles of every wave, with no branch: tiles below the diagonal (c < wave) take
     // the update too and are never read
 #pragma unroll
@@ -283,91 +395,59 @@ __global__ __launch_bounds__(256, 2) void k_syrk_potrf(double* G, int n, int k0,
     potrf64_factor(acc, G, n, k1, info, S, sbad, boost, nboost);
     return;
   }
-  int ti, tj;
-  tri_coords(blockIdx.x - 1, nt, &ti, &tj);
+  if (failed != 0) return;
   const int qi = wave >> 1, qj = wave & 1;
-  const int i0 = k1 + ti * 128 + qi * 64, j0 = k1 + tj * 128 + qj * 64;
-  // quadrant (0, 0) of tile (0, 0) is the next diagonal block (workgroup 0)
-  const bool active = !(ti == tj && qi > qj) && !(ti == 0 && tj == 0 && qi == 0 && qj == 0) && i0 < n && j0 < n;
-  if (!active) return;
-  const int r16 = lane & 15, k4 = lane >> 4;
-  f64x4 acc[4][4];
-#pragma unroll
-  for (int r = 0; r < 4; ++r)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) acc[r][c] = f64x4{0.0, 0.0, 0.0, 0.0};
-  double ra[kSyrkRing][4], rb[kSyrkRing][4];
-  auto fetch = [&](int kk, int slot) {
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      ra[slot][r] = syrk_operand(P, n, kk, i0 + 16 * r, lane);
-      rb[slot][r] = syrk_operand(P, n, kk, j0 + 16 * r, lane);
-    }
-  };
-  fetch(0, 0);
-  fetch(1, 1);
-#pragma unroll
-  for (int kk = 0; kk < kNb / 4; ++kk) {
-    if (kk + 2 < kNb / 4) fetch(kk + 2, (kk + 2) % kSyrkRing);
-    const int s = kk % kSyrkRing;
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-      for (int c = 0; c < 4; ++c) acc[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(ra[s][r], rb[s][c], acc[r][c], 0, 0, 0);
-  }
-  // one row block at a time: read its 16 old values per lane, subtract, store
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    double old[4][4];
-#pragma unroll
-    for (int c = 0; c < 4; ++c)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int i = i0 + 16 * r + 4 * v + k4;
-        const int j = j0 + 16 * c + r16;
-        old[c][v] = (i < n && j < n && j >= i) ? G[(int64_t)i * n + j] : 0.0;
-      }
-#pragma unroll
-    for (int c = 0; c < 4; ++c)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int i = i0 + 16 * r + 4 * v + k4;
-        const int j = j0 + 16 * c + r16;
-        if (i < n && j < n && j >= i) G[(int64_t)i * n + j] = old[c][v] - acc[r][c][v];
-      }
+  const int b = (int)blockIdx.x - 1;
+  if (b < ntri) {
+    int ti, tj;
+    tri_coords(b, nt, &ti, &tj);
+    const int i0 = k1 + ti * 128 + qi * 64, j0 = k1 + tj * 128 + qj * 64;
+    // quadrant (0, 0) of tile (0, 0) is the next diagonal block (workgroup 0)
+    const bool active = !(ti == tj && qi > qj) && !(ti == 0 && tj == 0 && qi == 0 && qj == 0) && i0 < n && j0 < n;
+    if (active) syrk_quadrant<true>(G, P, P, n, i0, j0, n, lane);
+  } else {
+    // W tile: rows [k1, n) (the later block rows), columns [0, k1)
+    const int wb = b - ntri;
+    const int i0 = k1 + (wb % nt) * 128 + qi * 64, j0 = (wb / nt) * 128 + qj * 64;
+    if (i0 < n && j0 < k1) syrk_quadrant<false>(W, P, W + (int64_t)k0 * n, n, i0, j0, k1, lane);
   }
 }
 
-// X_kk = U_kk^{-1} for every diagonal block (one wave per block): lane j solves U x = e_j
-// by back substitution, x_i = (delta_ij - sum_{m > i} U_im x_m) / U_ii, with U_kk in LDS
-// (identity-padded past n).  Only the diagonal blocks of X are written.
-__global__ __launch_bounds__(64) void k_trinv(const double* G, int n, double* X) {
-  __shared__ double U[kNb][kNb];
-  __shared__ double rinv[kNb];
-  const int k0 = blockIdx.x * kNb;
-  const int nbk = min(kNb, n - k0);
-  const int t = threadIdx.x;
-#pragma unroll 16
-  for (int l = 0; l < kNb; ++l) {
-    double v = (l == t) ? 1.0 : 0.0;
-    if (l < nbk && t < nbk && t >= l) v = G[(int64_t)(k0 + l) * n + k0 + t];
-    U[l][t] = v;
+// X = D W^T (X[i][j] = d_i W[j][i] for j >= i, 0 below the diagonal; d nullable = ones):
+// 64 x 64 tiles through LDS, both sides read and written along rows.
+__global__ __launch_bounds__(256) void k_inv_transpose(const double* __restrict__ W, const double* __restrict__ d,
+                                                       int n, double* __restrict__ X) {
+  __shared__ double T[64][65];
+  const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;   // the tile X[i0.., j0..]
+  const int t = threadIdx.x, c = t & 63;
+  if (j0 + 63 < i0) {   // entirely below the diagonal
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int i = i0 + (t >> 6) + 4 * r, j = j0 + c;
+      if (i < n && j < n) X[(int64_t)i * n + j] = 0.0;
+    }
+    return;
   }
-  __syncthreads();
-  rinv[t] = 1.0 / U[t][t];
-  __syncthreads();
-  double x[kNb];
+  double w[16];   // all loads in flight together: clamped in-bounds addresses, padding selected after
 #pragma unroll
-  for (int i = kNb - 1; i >= 0; --i) {
-    double s = (i == t) ? 1.0 : 0.0;
-#pragma unroll
-    for (int m = i + 1; m < kNb; ++m) s = fma(-U[i][m], x[m], s);
-    x[i] = s * rinv[i];
+  for (int r = 0; r < 16; ++r) {
+    const int j = j0 + (t >> 6) + 4 * r, i = i0 + c;   // W row j, column i
+    w[r] = W[(int64_t)min(j, n - 1) * n + min(i, n - 1)];
   }
-  if (t < nbk) {
 #pragma unroll
-    for (int i = 0; i < kNb; ++i)
-      if (i < nbk) X[(int64_t)(k0 + i) * n + k0 + t] = x[i];
+  for (int r = 0; r < 16; ++r) {
+    const int jr = (t >> 6) + 4 * r;
+    T[jr][c] = (i0 + c < n && j0 + jr < n) ? w[r] : 0.0;
+  }
+  double dv[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) dv[r] = d ? d[min(i0 + (t >> 6) + 4 * r, n - 1)] : 1.0;
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int ir = (t >> 6) + 4 * r;
+    const int i = i0 + ir, j = j0 + c;
+    if (i < n && j < n) X[(int64_t)i * n + j] = (j >= i) ? dv[r] * T[c][ir] : 0.0;
   }
 }
 
@@ -376,25 +456,34 @@ hipError_t launch_potrf(double* G, int n, int k0, int* info, double boost, int* 
   return hipGetLastError();
 }
 
-hipError_t launch_trsm_row(double* G, int n, int k0, hipStream_t s) {
+hipError_t launch_trsm_row(double* G, double* W, int n, int k0, const int* info, hipStream_t s) {
+  if (k0 < 0 || k0 >= n) return hipErrorInvalidValue;
   const int cols = n - k0 - kNb;
-  if (cols <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_trsm_row, dim3((cols + kTrsmSlab - 1) / kTrsmSlab), dim3(256), 0, s, G, n, k0);
+  const int g_slabs = cols > 0 ? (cols + kTrsmSlab - 1) / kTrsmSlab : 0;
+  const int wcols = k0 + std::min(kNb, n - k0);
+  const int w_slabs = W ? (wcols + kTrsmSlab - 1) / kTrsmSlab : 0;
+  if (g_slabs + w_slabs == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_trsm_row, dim3(g_slabs + w_slabs), dim3(256), 0, s, G, W, n, k0, g_slabs, info);
   return hipGetLastError();
 }
 
-hipError_t launch_syrk_potrf(double* G, int n, int k0, int* info, double boost, int* nboost, hipStream_t s) {
+hipError_t launch_syrk_potrf(double* G, double* W, int n, int k0, int* info, double boost, int* nboost,
+                             hipStream_t s) {
   const int rem = n - k0 - kNb;
   if (rem <= 0) return hipSuccess;
   const int nt = (rem + 127) / 128;
-  hipLaunchKernelGGL(k_syrk_potrf, dim3(1 + nt * (nt + 1) / 2), dim3(256), 0, s, G, n, k0, info, boost, nboost);
+  const int wt = W ? (k0 + kNb + 127) / 128 * nt : 0;
+  hipLaunchKernelGGL(k_syrk_potrf, dim3(1 + nt * (nt + 1) / 2 + wt), dim3(256), 0, s, G, W, n, k0, info, boost,
+                     nboost);
   return hipGetLastError();
 }
 
-hipError_t launch_trinv_diag(const double* G, int n, double* X, hipStream_t s) {
-  const int nblk = (n + kNb - 1) / kNb;
-  hipLaunchKernelGGL(k_trinv, dim3(nblk), dim3(64), 0, s, G, n, X);
+hipError_t launch_inv_transpose(const double* W, const double* d, int n, double* X, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const unsigned nb = (unsigned)((n + 63) / 64);
+  hipLaunchKernelGGL(k_inv_transpose, dim3(nb, nb), dim3(256), 0, s, W, d, n, X);
   return hipGetLastError();
 }
+
 
 }  // namespace flsq

@@ -30,21 +30,10 @@ __global__ void k_scale_upper(const double* src, double* dst, int n, const doubl
   dst[o] = v;
 }
 
-__global__ void k_scale_rows(double* X, int n, const double* d) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  const int i = blockIdx.y;
-  if (j < n) X[(int64_t)i * n + j] *= d[i];
-}
-
 hipError_t launch_equilibrate(const double* G, double* dst, int n, double* d, double mu, double diag_add,
                               hipStream_t s) {
   hipLaunchKernelGGL(k_diag_rsqrt, dim3((n + 255) / 256), dim3(256), 0, s, G, n, d);
   hipLaunchKernelGGL(k_scale_upper, dim3((n + 255) / 256, n), dim3(256), 0, s, G, dst, n, d, mu, diag_add);
-  return hipGetLastError();
-}
-
-hipError_t launch_scale_rows(double* X, int n, const double* d, hipStream_t s) {
-  hipLaunchKernelGGL(k_scale_rows, dim3((n + 255) / 256, n), dim3(256), 0, s, X, n, d);
   return hipGetLastError();
 }
 

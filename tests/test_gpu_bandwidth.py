@@ -100,10 +100,15 @@ def test_bandwidth_3d_poisson_matches_oracle():
     _check(prob, L, _gpu(fl, torch, dp, prob, L))
 
 
-def test_bandwidth_grad_central_differences_of_gpu_loss(helm):
-    """The gradient against central differences of the GPU's own loss, entry by entry."""
+def test_bandwidth_grad_central_differences_of_gpu_loss():
+    """The gradient against central differences of the GPU's own loss, entry by entry, at
+    mu = 1e-6: at the workload's mu = 1e-10 the FP64 rounding envelope of the gradient (up to
+    2e-4 of max |grad|, see above) exceeds the 1e-4 bar, which then tests the rounding rather
+    than the derivative."""
     torch, fl = require_gpu()
-    prob, dp = helm
+    prob = wl.config("helmholtz_bandwidth")
+    prob.mu = 1e-6
+    dp = fl.DeviceProblem(prob)
     L = L_ANISO
     _, grad, _ = _gpu(fl, torch, dp, prob, L)
     h = 1e-4
