@@ -193,16 +193,18 @@ hipError_t launch_newton_residual_runs(const PassGeo& pg, const double* beta, co
 constexpr int kNb = 64;
 // Blocked Cholesky steps (k_chol.hip): factor the diagonal block at k0 in place; block-row
 // solve U_kj = U_kk^{-T} G_kj for columns >= k0 + kNb together with block row k of the
-// inverse W = U^{-T} (lower triangular); trailing update of [k0 + kNb, n) and of W's later
-// block rows, fused with the factorisation of the next diagonal block.  W starts zeroed and is
-// complete after the step of the last block; launch_inv_transpose then writes X = D W^T
-// (upper, zero below; d nullable).  Pivots below boost (> 0) are raised to it and counted in
-// *nboost; with boost = 0, *info receives the first non-positive pivot (1-based), after which
-// the remaining steps return at once.
+// inverse W = U^{-T} (lower triangular); update by the kr (64 or 128) solved panel rows from k0
+// of the trailing rows [k0 + kr, row_lim) and columns [k0 + kr, n) of G and of W's columns
+// [0, k0 + kr), fused with the factorisation of the next diagonal block at k0 + kr (row_lim
+// below n: the next block row only).  W starts zeroed and is complete after the solve of the
+// last block row; launch_inv_transpose then writes X = D W^T (upper, zero below; d nullable).
+// Pivots below boost (> 0) are raised to it and counted in *nboost; with boost = 0, *info
+// receives the first non-positive pivot (1-based), after which the remaining steps return at
+// once.
 hipError_t launch_potrf(double* G, int n, int k0, int* info, double boost, int* nboost, hipStream_t s);
 hipError_t launch_trsm_row(double* G, double* W, int n, int k0, const int* info, hipStream_t s);
-hipError_t launch_syrk_potrf(double* G, double* W, int n, int k0, int* info, double boost, int* nboost,
-                             hipStream_t s);
+hipError_t launch_syrk_potrf(double* G, double* W, int n, int k0, int kr, int row_lim, int* info, double boost,
+                             int* nboost, hipStream_t s);
 hipError_t launch_inv_transpose(const double* W, const double* d, int n, double* X, hipStream_t s);
 // dst = D src D + (diag_add + mu D^2) on the diagonal (upper triangle), D = diag(src)^{-1/2} -> d.
 hipError_t launch_equilibrate(const double* G, double* dst, int n, double* d, double mu, double diag_add,

@@ -271,40 +271,44 @@ __device__ __forceinline__ void tri_coords(int t, int nt, int* ti, int* tj) {
   *tj = r + t;
 }
 
-// Trailing update of the upper triangle G_ij -= sum_l U_{k0+l,i} U_{k0+l,j}, i <= j, over
-// rows and columns [k0 + kNb, n), in 128 x 128 tiles (ti <= tj), one workgroup per tile:
-// wave w computes the 64 x 64 quadrant (w / 2, w % 2) with FP64 MFMA 16x16x4.  With W = U^{-T}
-// given, the same launch applies this step's term of the inverse to the later block rows,
-// W_j -= U_kj^T W_k for the rows [k0 + kNb, n) and the columns [0, k0 + kNb), in 128 x 128 tiles
-// after the triangle's; it has the triangle's form, with W's block row k as the second panel.
+// Trailing update with the KR (64 or 128) just-solved panel rows k0 .. k0 + KR of U, over rows
+// and columns [k1, n), k1 = k0 + KR: G_ij -= sum_l U_{k0+l,i} U_{k0+l,j}, i <= j, in 128 x 128
+// tiles (ti <= tj), one workgroup per tile: wave w computes the 64 x 64 quadrant (w / 2, w % 2)
+// with FP64 MFMA 16x16x4.  With W = U^{-T} given, the same launch applies the panel's terms of
+// the inverse to the later block rows, W_j -= sum_l U_{k0+l,j}^T W_{k0+l} for the rows [k1, n)
+// and the columns [0, k1), in 128 x 128 tiles after the triangle's; it has the triangle's form,
+// with W's panel rows as the second operand.  With row_lim < n only the rows [k1, row_lim)
+// (the next block row: tile row 0) are updated, in both G and W.
 //
-// The operands come straight from the panels (block row k0 of G, just solved, and of W) into
-// registers in the order the matrix cores consume them: the operand of k-step kk for 16
-// columns from c0 is one load whose lane l reads panel row 4 kk + l / 16, column c0 + l % 16
-// (four 128-byte pieces).  Each wave keeps the loads of the next two k-steps in flight while
-// it multiplies, and nothing is staged in LDS, so two workgroups share a CU: one's loads
-// overlap the other's products, and a step with up to twice as many tiles as CUs still runs
-// in one round.
+// Block rows are taken in pairs: the next block row alone (KR = 64, row_lim = k1 + 64), then,
+// once it is solved too, the rest with both (KR = 128): the trailing matrix is read and written
+// once per pair, which halves the HBM traffic of the updates at the cost of one small launch.
+//
+// The operands come straight from the panels into registers in the order the matrix cores
+// consume them: the operand of k-step kk for 16 columns from c0 is one load whose lane l
+// reads panel row 4 kk + l / 16, column c0 + l % 16 (four 128-byte pieces).  Each wave keeps
+// the loads of the next two k-steps in flight while it multiplies, and nothing is staged in
+// LDS, so two workgroups share a CU: one's loads overlap the other's products, and a step
+// with up to twice as many tiles as CUs still runs in one round.
 //
 // Workgroup 0 owns the next diagonal block (quadrant (0, 0) of tile (0, 0), which the tile's
 // own workgroup skips): it loads the block straight into the accumulator layout of the
 // factorisation, applies the update there and factors it without a round trip through
-// memory, so the critical path of a step is one 64-deep update of one block plus its
-// factorisation.
+// memory, so the critical path of a step is one update of one block plus its factorisation.
 constexpr int kSyrkRing = 3;   // k-steps of operands held in registers (two in flight)
 
 __device__ __forceinline__ double syrk_operand(const double* P, int n, int kk, int c0, int lane) {
   return P[(int64_t)(4 * kk + (lane >> 4)) * n + min(c0 + (lane & 15), n - 1)];
 }
 
-// One 64 x 64 quadrant: C[i0.., j0..] -= PA[:, i0..]^T PB[:, j0..] over the 64 panel rows;
-// only entries with i < n, j < col_end (and j >= i when TRI) are touched.  The old values are
+// One 64 x 64 quadrant: C[i0.., j0..] -= PA[:, i0..]^T PB[:, j0..] over the KR panel rows;
+// only entries with i < row_end, j < col_end (and j >= i when TRI) are touched.  The old values are
 // read after the products, 16 per lane at a time with the next 16 already in flight, from
 // clamped in-bounds addresses (a conditional load would wait on its own); reading them up
 // front instead delays the next diagonal block's loads, which are on the critical path.
-template <bool TRI>
+template <bool TRI, int KR>
 __device__ __forceinline__ void syrk_quadrant(double* C, const double* PA, const double* PB, int n, int i0, int j0,
-                                              int col_end, int lane) {
+                                              int row_end, int col_end, int lane) {
   const int r16 = lane & 15, k4 = lane >> 4;
   f64x4 acc[4][4];
 #pragma unroll
@@ -322,8 +326,8 @@ __device__ __forceinline__ void syrk_quadrant(double* C, const double* PA, const
   fetch(0, 0);
   fetch(1, 1);
 #pragma unroll
-  for (int kk = 0; kk < kNb / 4; ++kk) {
-    if (kk + 2 < kNb / 4) fetch(kk + 2, (kk + 2) % kSyrkRing);
+  for (int kk = 0; kk < KR / 4; ++kk) {
+    if (kk + 2 < KR / 4) fetch(kk + 2, (kk + 2) % kSyrkRing);
     const int s = kk % kSyrkRing;
 #pragma unroll
     for (int r = 0; r < 4; ++r)
@@ -338,7 +342,7 @@ __device__ __forceinline__ void syrk_quadrant(double* C, const double* PA, const
       for (int v = 0; v < 4; ++v) {
         const int i = i0 + 16 * r + 4 * v + k4;
         const int j = j0 + 16 * c + r16;
-        old[buf][4 * c + v] = C[(int64_t)min(i, n - 1) * n + min(j, col_end - 1)];
+        old[buf][4 * c + v] = C[(int64_t)min(i, row_end - 1) * n + min(j, col_end - 1)];
       }
   };
   load_old(0, 0);
@@ -352,22 +356,24 @@ __device__ __forceinline__ void syrk_quadrant(double* C, const double* PA, const
       for (int v = 0; v < 4; ++v) {
         const int i = i0 + 16 * r + 4 * v + k4;
         const int j = j0 + 16 * c + r16;
-        if (i < n && j < col_end && (!TRI || j >= i)) C[(int64_t)i * n + j] = old[buf][4 * c + v] - acc[r][c][v];
+        if (i < row_end && j < col_end && (!TRI || j >= i)) C[(int64_t)i * n + j] = old[buf][4 * c + v] - acc[r][c][v];
       }
     if (r + 2 < 4) load_old(r + 2, buf);
   }
 }
 
-__global__ __launch_bounds__(256, 2) void k_syrk_potrf(double* G, double* W, int n, int k0, int* info, double boost,
-                                                       int* nboost) {
+template <int KR>
+__global__ __launch_bounds__(256, 2) void k_syrk_potrf(double* G, double* W, int n, int k0, int row_lim, int* info,
+                                                       double boost, int* nboost) {
   __shared__ double S[kNb * kNb];
   __shared__ int sbad[2];
   const int failed = *info;   // a failed pivot abandons the attempt; tested once loads are out
-  const int k1 = k0 + kNb;
+  const int k1 = k0 + KR;
   const int nt = (n - k1 + 127) / 128;
-  const int ntri = nt * (nt + 1) / 2;
+  const bool strip = row_lim < n;
+  const int ntri = strip ? nt : nt * (nt + 1) / 2;   // a strip keeps tile row 0 only
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const double* P = G + (int64_t)k0 * n;   // the panel: rows k0 .. k0 + 63
+  const double* P = G + (int64_t)k0 * n;   // the panel: rows k0 .. k0 + KR
   if (blockIdx.x == 0) {
     // the next diagonal block: its update in registers, then its factorisation.  Columns past
     // n read column n - 1 (clamped) and only touch the identity padding, which is never stored.
@@ -385,8 +391,8 @@ __global__ __launch_bounds__(256, 2) void k_syrk_potrf(double* G, double* W, int
     // all four tiles of every wave, with no branch: tiles below the diagonal (c < wave) take
     // the update too and are never read
 #pragma unroll
-    for (int kk = 0; kk < kNb / 4; ++kk) {
-      if (kk + 2 < kNb / 4) fetch(kk + 2, (kk + 2) % kSyrkRing);
+    for (int kk = 0; kk < KR / 4; ++kk) {
+      if (kk + 2 < KR / 4) fetch(kk + 2, (kk + 2) % kSyrkRing);
       const int s = kk % kSyrkRing;
       const double a = -ra[s];
 #pragma unroll
@@ -399,17 +405,19 @@ __global__ __launch_bounds__(256, 2) void k_syrk_potrf(double* G, double* W, int
   const int qi = wave >> 1, qj = wave & 1;
   const int b = (int)blockIdx.x - 1;
   if (b < ntri) {
-    int ti, tj;
-    tri_coords(b, nt, &ti, &tj);
+    int ti = 0, tj = b;
+    if (!strip) tri_coords(b, nt, &ti, &tj);
     const int i0 = k1 + ti * 128 + qi * 64, j0 = k1 + tj * 128 + qj * 64;
     // quadrant (0, 0) of tile (0, 0) is the next diagonal block (workgroup 0)
-    const bool active = !(ti == tj && qi > qj) && !(ti == 0 && tj == 0 && qi == 0 && qj == 0) && i0 < n && j0 < n;
-    if (active) syrk_quadrant<true>(G, P, P, n, i0, j0, n, lane);
+    const bool active = !(ti == tj && qi > qj) && !(ti == 0 && tj == 0 && qi == 0 && qj == 0) && i0 < row_lim &&
+                        j0 < n;
+    if (active) syrk_quadrant<true, KR>(G, P, P, n, i0, j0, row_lim, n, lane);
   } else {
-    // W tile: rows [k1, n) (the later block rows), columns [0, k1)
+    // W tile: rows [k1, row_lim) (the later block rows), columns [0, k1); a strip has one row
     const int wb = b - ntri;
-    const int i0 = k1 + (wb % nt) * 128 + qi * 64, j0 = (wb / nt) * 128 + qj * 64;
-    if (i0 < n && j0 < k1) syrk_quadrant<false>(W, P, W + (int64_t)k0 * n, n, i0, j0, k1, lane);
+    const int wr = strip ? 0 : wb % nt, wc = strip ? wb : wb / nt;
+    const int i0 = k1 + wr * 128 + qi * 64, j0 = wc * 128 + qj * 64;
+    if (i0 < row_lim && j0 < k1) syrk_quadrant<false, KR>(W, P, W + (int64_t)k0 * n, n, i0, j0, row_lim, k1, lane);
   }
 }
 
@@ -467,14 +475,23 @@ hipError_t launch_trsm_row(double* G, double* W, int n, int k0, const int* info,
   return hipGetLastError();
 }
 
-hipError_t launch_syrk_potrf(double* G, double* W, int n, int k0, int* info, double boost, int* nboost,
-                             hipStream_t s) {
-  const int rem = n - k0 - kNb;
+hipError_t launch_syrk_potrf(double* G, double* W, int n, int k0, int kr, int row_lim, int* info, double boost,
+                             int* nboost, hipStream_t s) {
+  if (kr != 64 && kr != 128) return hipErrorInvalidValue;
+  const int k1 = k0 + kr;
+  const int rem = n - k1;
   if (rem <= 0) return hipSuccess;
+  row_lim = std::min(std::max(row_lim, k1), n);
   const int nt = (rem + 127) / 128;
-  const int wt = W ? (k0 + kNb + 127) / 128 * nt : 0;
-  hipLaunchKernelGGL(k_syrk_potrf, dim3(1 + nt * (nt + 1) / 2 + wt), dim3(256), 0, s, G, W, n, k0, info, boost,
-                     nboost);
+  const bool strip = row_lim < n;
+  const int ntri = strip ? nt : nt * (nt + 1) / 2;
+  const int wrows = strip ? 1 : nt;
+  const int wt = W ? (k1 + 127) / 128 * wrows : 0;
+  const dim3 grid(1 + ntri + wt);
+  if (kr == 64)
+    hipLaunchKernelGGL(k_syrk_potrf<64>, grid, dim3(256), 0, s, G, W, n, k0, row_lim, info, boost, nboost);
+  else
+    hipLaunchKernelGGL(k_syrk_potrf<128>, grid, dim3(256), 0, s, G, W, n, k0, row_lim, info, boost, nboost);
   return hipGetLastError();
 }
 
