@@ -135,6 +135,13 @@ typedef struct {
     int32_t second_pass;     /* 1 if the factor was refined by the second pass (opts.second_pass) */
     double t_second_pass_ms; /* its time (included in t_chol_ms) */
     int32_t boosted_pivots;  /* pivots raised by opts.pivot_boost in the factor that was kept */
+    int32_t shift_recalled;  /* 1 if the factorisation started at the shift this context kept from an
+                                earlier factorisation of a Gram with the same size, settings and 64-bit
+                                fingerprint (its upper triangle), skipping the attempts that failed then;
+                                chol_retries then counts only retries beyond that shift.  The factor is
+                                the one the retries would reach (the kernels are deterministic).  A context
+                                keeps up to four such shifts; nothing is fingerprinted for a size whose last
+                                factorisation needed no retry. */
 } flsq_solve_info;
 
 typedef struct flsq_ctx flsq_ctx;

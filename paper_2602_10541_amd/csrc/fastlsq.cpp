@@ -145,6 +145,15 @@ struct System {
 
 }  // namespace
 
+// The shift a factorisation needed, with the fingerprint of its Gram (see factor_with_retries).
+struct ShiftMemo {
+  bool valid = false;
+  int n = 0;
+  double mu = 0.0, shift0 = 0.0, boost = 0.0;
+  unsigned long long fp = 0;
+  double shift = 0.0;
+};
+
 struct flsq_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -161,6 +170,8 @@ struct flsq_ctx {
   flsq_factor* aux_factor = nullptr; // factor and derived system reused by the learnable-bandwidth calls
   System aux;
   unsigned char* scratch = nullptr;  // this device's copy of the static evaluation scratch (no-alloc calls)
+  ShiftMemo shift_memo[4];           // recent factorisations that needed a shift retry (one per key)
+  int shift_memo_next = 0;           // the entry a new key replaces
 };
 
 struct flsq_factor {
@@ -702,16 +713,41 @@ Err chol_solve(flsq_ctx* c, const double* X, int n, const double* Y, double* Z, 
 // Gram).  Pivots of the equilibrated Gram below boost (> 0) are raised to it in place (their
 // count goes to *boosted); a failed pivot (non-finite, or non-positive when boost = 0) retries
 // the whole factorisation with growing shifts.
+//
+// Shift memory: when a factorisation needed retries, the context keeps a 64-bit fingerprint of
+// the Gram's upper triangle with the shift that succeeded.  A later factorisation with the same
+// size and settings whose Gram has the same fingerprint starts at that shift (*recalled = 1):
+// the kernels are deterministic, so the attempts below it would fail as they did, and the
+// result is the one the retries would reach.  Nothing is fingerprinted unless the last
+// factorisation of this size needed a retry.
 Err factor_with_retries(flsq_ctx* c, const double* Gsrc, double* U, double* X, int n, double mu, double shift0,
-                        double* shift_used, int* retries, double boost = 0.0, int* boosted = nullptr) {
+                        double* shift_used, int* retries, double boost = 0.0, int* boosted = nullptr,
+                        int* recalled = nullptr) {
   double *dmax, *d;
-  CHECK_ERR(ws_get(c, "diag_max", 1, &dmax));
+  unsigned long long* fp_part;
+  CHECK_ERR(ws_get(c, "diag_max", 2, &dmax));   // [0] the largest diagonal entry, [1] the fingerprint
   CHECK_ERR(ws_get(c, "eq_d", (size_t)n, &d));
+  CHECK_ERR(ws_get(c, "fp_part", (size_t)n, &fp_part));
+  unsigned long long* d_fp = reinterpret_cast<unsigned long long*>(dmax + 1);
+  // the entry for this size and these settings, if any (else the one a new entry replaces)
+  ShiftMemo* memo = nullptr;
+  for (ShiftMemo& m : c->shift_memo)
+    if (m.valid && m.n == n && m.mu == mu && m.shift0 == shift0 && m.boost == boost) memo = &m;
+  const bool memo_applies = memo && memo->shift > shift0;
   CHECK_HIP(launch_diag_max(Gsrc, n, dmax, c->stream));
-  double dm = 0.0;
-  CHECK_ERR(read_back(c, &dm, dmax, sizeof(double)));
-  if (!std::isfinite(dm)) return fail(FLSQ_ENONFINITE, "Gram diagonal is not finite");
-  double rel = shift0;
+  if (memo_applies) CHECK_HIP(launch_fingerprint_upper(Gsrc, n, fp_part, d_fp, c->stream));
+  double hv[2] = {0.0, 0.0};
+  CHECK_ERR(read_back(c, hv, dmax, memo_applies ? sizeof hv : sizeof(double)));
+  if (!std::isfinite(hv[0])) return fail(FLSQ_ENONFINITE, "Gram diagonal is not finite");
+  unsigned long long fp = 0;
+  bool have_fp = false;
+  if (memo_applies) {
+    memcpy(&fp, &hv[1], sizeof fp);
+    have_fp = true;
+  }
+  const bool recall = memo_applies && fp == memo->fp;
+  if (recalled) *recalled = recall ? 1 : 0;
+  double rel = recall ? memo->shift : shift0;
   *retries = 0;
   for (int attempt = 0; attempt < 8; ++attempt) {
     CHECK_HIP(launch_equilibrate(Gsrc, U, n, d, mu, rel, c->stream));
@@ -720,6 +756,23 @@ Err factor_with_retries(flsq_ctx* c, const double* Gsrc, double* U, double* X, i
     if (info == 0) {
       *shift_used = rel;
       if (boosted) *boosted = nb;
+      if (*retries > 0) {
+        if (!have_fp) {
+          CHECK_HIP(launch_fingerprint_upper(Gsrc, n, fp_part, d_fp, c->stream));
+          CHECK_ERR(read_back(c, &fp, d_fp, sizeof fp));
+        }
+        if (!memo) {
+          memo = &c->shift_memo[c->shift_memo_next];
+          c->shift_memo_next = (c->shift_memo_next + 1) % 4;
+        }
+        memo->valid = true;
+        memo->n = n;
+        memo->mu = mu;
+        memo->shift0 = shift0;
+        memo->boost = boost;
+        memo->fp = fp;
+        memo->shift = rel;
+      }
       return ok();
     }
     ++*retries;
@@ -1292,11 +1345,12 @@ Err gram_and_factor(flsq_ctx* c, const System& s, const double* rho, const Solve
   int retries = 0;
   const bool exact_gram = sp.prec == FLSQ_PREC_FP64 || sp.prec == FLSQ_PREC_INT8_CRT;
   const double rel0 = exact_gram ? sp.shift_rel : (sp.shift_rel > 0.0 ? sp.shift_rel : 1e-6);
-  int boosted = 0;
-  CHECK_ERR(factor_with_retries(c, G, U, Xi, n, sp.mu, rel0, &shift, &retries, sp.pivot_boost, &boosted));
+  int boosted = 0, recalled = 0;
+  CHECK_ERR(factor_with_retries(c, G, U, Xi, n, sp.mu, rel0, &shift, &retries, sp.pivot_boost, &boosted, &recalled));
   const double t2a = now_ms();
   bool second = false;
-  if (want_second_pass(sp, retries + (boosted > 0 ? 1 : 0), rho, s.P, n)) {
+  // a recalled shift counts as the retries it skipped (the same factor, so the same decision)
+  if (want_second_pass(sp, retries + recalled + (boosted > 0 ? 1 : 0), rho, s.P, n)) {
     double* A;
     CHECK_ERR(ws_get(c, "sp_A", (size_t)s.P * n, &A));
     CHECK_HIP(launch_assemble(s.geo(), 0, A, c->stream));
@@ -1316,6 +1370,7 @@ Err gram_and_factor(flsq_ctx* c, const System& s, const double* rho, const Solve
     info->shift = shift;
     info->chol_retries = retries;
     info->boosted_pivots = boosted;
+    info->shift_recalled = recalled;
     info->t_gram_kernel_ms = c->last_gram_kernel_ms;
     info->second_pass = second ? 1 : 0;
     info->t_second_pass_ms = second ? t2 - t2a : 0.0;
@@ -2553,11 +2608,12 @@ Err var_linear_solve(flsq_ctx* c, const double* A, const double* At, int n, int6
   c->last_gram_kernel_ms = kms;
   double shift = 0.0;
   int retries = 0;
-  int boosted = 0;
-  CHECK_ERR(factor_with_retries(c, G, U, Xi, n, sp.mu, sp.shift_rel, &shift, &retries, sp.pivot_boost, &boosted));
+  int boosted = 0, recalled = 0;
+  CHECK_ERR(factor_with_retries(c, G, U, Xi, n, sp.mu, sp.shift_rel, &shift, &retries, sp.pivot_boost, &boosted,
+                                &recalled));
   const double t2a = now_ms();
   bool second = false;
-  if (want_second_pass(sp, retries + (boosted > 0 ? 1 : 0), nullptr, P, n)) {
+  if (want_second_pass(sp, retries + recalled + (boosted > 0 ? 1 : 0), nullptr, P, n)) {
     double shift2 = 0.0;
     int retries2 = 0;
     CHECK_ERR(second_pass_factor(c, A, P, n, sp.mu, Xi, &shift2, &retries2, &second));
@@ -2586,6 +2642,7 @@ Err var_linear_solve(flsq_ctx* c, const double* A, const double* At, int n, int6
     info->shift = shift;
     info->chol_retries = retries;
     info->boosted_pivots = boosted;
+    info->shift_recalled = recalled;
     info->t_gram_kernel_ms = c->last_gram_kernel_ms;
     info->refine_iters = ro.iters;
     info->grad_norm0 = ro.grad0;

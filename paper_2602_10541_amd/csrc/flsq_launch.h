@@ -248,6 +248,9 @@ hipError_t launch_gemm_t16(const double* Mt, int64_t M, int64_t L, const double*
 size_t gemm_t16_work_elems(int64_t M, int64_t L, int K);
 hipError_t launch_copy_upper(const double* src, double* dst, int n, double diag_add, hipStream_t s);
 hipError_t launch_diag_max(const double* G, int n, double* out, hipStream_t s);
+// *out = a reproducible 64-bit fingerprint of the upper triangle of G (n x n); part: n words.
+hipError_t launch_fingerprint_upper(const double* G, int n, unsigned long long* part, unsigned long long* out,
+                                    hipStream_t s);
 
 // ---- small vector kernels
 // out[c] = sum_i x[i][c] * y[i][c] over n rows, K columns (deterministic two-stage).

@@ -69,6 +69,56 @@ hipError_t launch_diag_max(const double* G, int n, double* out, hipStream_t s) {
   return hipGetLastError();
 }
 
+// 64-bit fingerprint of the upper triangle of G (n x n row-major): the sum, modulo 2^64, of a
+// mix (the splitmix64 finaliser) of each entry's bit pattern and its position.  Integer sums
+// do not depend on their order, so the value is reproducible; stage 1 writes one partial per
+// row (a workgroup per row), stage 2 sums them.
+__device__ __forceinline__ unsigned long long fp_mix(unsigned long long z) {
+  z += 0x9e3779b97f4a7c15ull;
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+__global__ __launch_bounds__(256) void k_fingerprint_rows(const double* G, int n, unsigned long long* part) {
+  __shared__ unsigned long long red[256];
+  const int i = blockIdx.x;
+  unsigned long long h = 0;
+  for (int j = i + (int)threadIdx.x; j < n; j += 256) {
+    const unsigned long long bits = (unsigned long long)__double_as_longlong(G[(int64_t)i * n + j]);
+    h += fp_mix(bits ^ ((unsigned long long)i << 32 | (unsigned)j));
+  }
+  red[threadIdx.x] = h;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[i] = red[0];
+}
+
+__global__ __launch_bounds__(256) void k_fingerprint_sum(const unsigned long long* part, int n,
+                                                         unsigned long long* out) {
+  __shared__ unsigned long long red[256];
+  unsigned long long h = 0;
+  for (int i = threadIdx.x; i < n; i += 256) h += part[i];
+  red[threadIdx.x] = h;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = red[0];
+}
+
+hipError_t launch_fingerprint_upper(const double* G, int n, unsigned long long* part, unsigned long long* out,
+                                    hipStream_t s) {
+  if (n <= 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_fingerprint_rows, dim3(n), dim3(256), 0, s, G, n, part);
+  hipLaunchKernelGGL(k_fingerprint_sum, dim3(1), dim3(256), 0, s, part, n, out);
+  return hipGetLastError();
+}
+
 // Column dot products sum_i x[i][c] y[i][c]: stage 1 writes one partial per workgroup
 // and column, stage 2 sums the partials in order (deterministic).
 constexpr int kDotWg = 256;

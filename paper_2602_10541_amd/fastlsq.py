@@ -70,7 +70,8 @@ class flsq_solve_info(C.Structure):
                 ("grad_norm0", C.c_double), ("grad_norm", C.c_double), ("last_step_rel", C.c_double),
                 ("t_gram_ms", C.c_double), ("t_chol_ms", C.c_double), ("t_refine_ms", C.c_double),
                 ("t_total_ms", C.c_double), ("t_gram_kernel_ms", C.c_double), ("second_pass", C.c_int32),
-                ("t_second_pass_ms", C.c_double), ("boosted_pivots", C.c_int32)]
+                ("t_second_pass_ms", C.c_double), ("boosted_pivots", C.c_int32),
+                ("shift_recalled", C.c_int32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

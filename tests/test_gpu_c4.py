@@ -75,3 +75,33 @@ def test_heat4d_evaluate_1m_points(c4):
     fl.flsq_evaluate(ctx, dp.basis, bt, xd, [ALPHAS[0]], u64)
     scale0 = np.sum(np.abs(beta)) / math.sqrt(prob.n_feat)
     assert np.abs(u64[:, 0].cpu().numpy() - gold["u_test"]).max() <= 1e-13 * scale0
+
+
+def test_heat4d_shift_memory(c4):
+    """This Gram needs shift retries.  A second solve of the same system in the same context starts
+    at the shift the context kept with the Gram's fingerprint (shift_recalled = 1, no retries) and
+    returns the same beta bit for bit (the factor is the one the retries reached); a different Gram
+    of the same size and settings (the initial-condition rows weighted 1.5 times) is not recalled."""
+    import copy
+    torch, fl = require_gpu()
+    prob, dp, gold = c4
+    ctx = fl.Context(0)   # a fresh context: no shift kept yet
+    try:
+        opts = fl.solve_opts(prob.mu, 3, 200, 1e-12)
+        b1 = torch.empty(prob.n_feat, dtype=torch.float64, device="cuda")
+        st1, i1 = fl.flsq_solve_linear(ctx, dp.basis, dp.rows, opts, b1)
+        assert st1 == fl.FLSQ_OK and i1.chol_retries >= 1 and i1.shift_recalled == 0, i1.as_dict()
+        b2 = torch.empty_like(b1)
+        st2, i2 = fl.flsq_solve_linear(ctx, dp.basis, dp.rows, opts, b2)
+        assert st2 == fl.FLSQ_OK, i2.as_dict()
+        assert i2.shift_recalled == 1 and i2.chol_retries == 0 and i2.shift == i1.shift, i2.as_dict()
+        assert i2.refine_iters == i1.refine_iters
+        assert torch.equal(b1, b2)
+        other = copy.deepcopy(prob)
+        other.blocks[1].weight *= 1.5
+        dpo = fl.DeviceProblem(other)
+        b3 = torch.empty_like(b1)
+        st3, i3 = fl.flsq_solve_linear(ctx, dpo.basis, dpo.rows, opts, b3)
+        assert st3 == fl.FLSQ_OK and i3.shift_recalled == 0, i3.as_dict()
+    finally:
+        ctx.close()

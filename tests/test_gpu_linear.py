@@ -333,7 +333,7 @@ def test_duplicated_features_without_tikhonov():
     st, info = fl.flsq_solve_linear(ctx, dp.basis, dp.rows, fl.solve_opts(0.0, 0, 5, 1e-12), beta, check=False)
     assert st in (fl.FLSQ_OK, fl.FLSQ_ENOTSPD, fl.FLSQ_ENOCONV)
     if st != fl.FLSQ_ENOTSPD:
-        assert info.chol_retries >= 1 and info.shift > 0
+        assert (info.chol_retries >= 1 or info.shift_recalled == 1) and info.shift > 0
         assert np.all(np.isfinite(beta.cpu().numpy()))
 
 

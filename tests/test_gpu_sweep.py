@@ -102,7 +102,8 @@ def test_sweep_second_pass_refactor(sweep, second_pass):
     prob, dp, gold = sweep
     ctx = context()
     F = fl.flsq_factorize(ctx, dp.basis, dp.rows, fl.solve_opts(prob.mu, 3, 60, 1e-12, second_pass=second_pass))
-    assert F.info.chol_retries >= 1
+    # the shift came from retries, or from the context's memory of this Gram (an earlier test)
+    assert F.info.shift > 0 and (F.info.chol_retries >= 1 or F.info.shift_recalled == 1), F.info.as_dict()
     assert F.info.second_pass == (1 if second_pass == 0 else 0)
     Y = torch.tensor(prob.extras["rhs_rows"][:, 5].copy(), dtype=torch.float64, device="cuda")
     b1 = torch.empty(prob.n_feat, dtype=torch.float64, device="cuda")
@@ -124,7 +125,7 @@ def test_sweep_one_call_solve_takes_second_pass(sweep):
     beta = torch.empty(prob.n_feat, dtype=torch.float64, device="cuda")
     st, info = fl.flsq_solve_linear(context(), dp.basis, dp.rows, fl.solve_opts(prob.mu, 3, 60, 1e-12), beta)
     d = info.as_dict()
-    assert d["chol_retries"] >= 1 and d["second_pass"] == 1, d
+    assert d["shift"] > 0 and (d["chol_retries"] >= 1 or d["shift_recalled"] == 1) and d["second_pass"] == 1, d
     assert d["refine_iters"] <= 8, d
     u = _u_cols(fl, torch, context(), dp, prob, beta[:, None])[:, 0]
     assert rel_l2(u, gold["u_test"][:, 0]) <= 1e-7, (rel_l2(u, gold["u_test"][:, 0]), d)
