@@ -63,14 +63,16 @@ __device__ __forceinline__ void potrf64_load(const double* G, int n, int k0, f64
 // factor is then exact for G + E with E diagonal, non-zero only at the raised pivots, so a
 // Gram that rounding has pushed out of the positive definite cone still factors in one pass;
 // their number is added to *nboost.  With boost = 0 a non-positive pivot is a failure instead.
-// A failed (or non-finite) pivot is recorded in *info (1-based global index, first failure)
-// and replaced by 1 so every step completes.  Entries below the diagonal are never stored.
+// A failed (or non-finite) pivot is recorded in *info (1-based global index, first failure);
+// the rows from it on are then not meaningful (the steps after the failure return at once and
+// the attempt is repeated with a shift).  Entries below the diagonal are never stored.
 __device__ __forceinline__ void potrf64_factor(f64x4 acc[4], double* G, int n, int k0, int* info, double* S,
                                                int* sbad, double boost, int* nboost) {
   const int nbk = min(kNb, n - k0);
   const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
   const int r16 = lane & 15, k4 = lane >> 4;
   double* base = G + (int64_t)k0 * n + k0;
+  const bool boosting = boost > 0.0;
   if (threadIdx.x == 0) {
     sbad[0] = -1;
     sbad[1] = 0;
@@ -85,24 +87,51 @@ __device__ __forceinline__ void potrf64_factor(f64x4 acc[4], double* G, int n, i
       double x[4];
 #pragma unroll
       for (int a = 0; a < 4; ++a) x[a] = S[(L + a) * kNb + lane];
+      // the group's 4 x 4 pivot block as wave-uniform scalars: its factor is a short scalar chain
+      // (one reciprocal square root per pivot), and the four rows follow from it lane-wise
+      const double a00 = lane_bcast(x[0], L), a01 = lane_bcast(x[0], L + 1);
+      const double a02 = lane_bcast(x[0], L + 2), a03 = lane_bcast(x[0], L + 3);
+      const double a11 = lane_bcast(x[1], L + 1), a12 = lane_bcast(x[1], L + 2), a13 = lane_bcast(x[1], L + 3);
+      const double a22 = lane_bcast(x[2], L + 2), a23 = lane_bcast(x[2], L + 3);
+      const double a33 = lane_bcast(x[3], L + 3);
+      // a pivot is raised to boost (boost > 0) or taken as it is: a failed one (non-finite, or
+      // non-positive with boost = 0) is recorded below, off the chain, and the attempt abandoned
+      const double d0 = a00;
+      const double p0 = boosting ? fmax(d0, boost) : d0;
+      const double r0 = rsqrt_nr(p0);
+      const double u01 = a01 * r0, u02 = a02 * r0, u03 = a03 * r0;
+      const double d1 = fma(-u01, u01, a11);
+      const double p1 = boosting ? fmax(d1, boost) : d1;
+      const double r1 = rsqrt_nr(p1);
+      const double u12 = (a12 - u01 * u02) * r1, u13 = (a13 - u01 * u03) * r1;
+      const double d2 = fma(-u12, u12, fma(-u02, u02, a22));
+      const double p2 = boosting ? fmax(d2, boost) : d2;
+      const double r2 = rsqrt_nr(p2);
+      const double u23 = (a23 - u02 * u03 - u12 * u13) * r2;
+      const double d3 = fma(-u23, u23, fma(-u13, u13, fma(-u03, u03, a33)));
+      const double p3 = boosting ? fmax(d3, boost) : d3;
+      const double r3 = rsqrt_nr(p3);
+      // rows, lane = column: 0 left of the pivot, the pivot's square root on it
+      const double U0 = x[0] * r0;
+      const double U1 = (x[1] - u01 * U0) * r1;
+      const double U2 = (x[2] - u02 * U0 - u12 * U1) * r2;
+      const double U3 = (x[3] - u03 * U0 - u13 * U1 - u23 * U2) * r3;
+      const double pr[4] = {p0 * r0, p1 * r1, p2 * r2, p3 * r3};
+      const double Uv[4] = {U0, U1, U2, U3};
+#pragma unroll
+      for (int a = 0; a < 4; ++a) x[a] = (lane > L + a) ? Uv[a] : (lane == L + a ? pr[a] : 0.0);
+#pragma unroll
+      for (int a = 0; a < 4; ++a) S[(L + a) * kNb + lane] = x[a];
+      const double dv[4] = {d0, d1, d2, d3};
       int bad = -1, raised = 0;
 #pragma unroll
       for (int a = 0; a < 4; ++a) {
         const int l = L + a;
-        const double diag = lane_bcast(x[a], l);
-        const bool low = !(diag > boost);
-        const bool fail = !isfinite(diag) || (low && !(boost > 0.0));
+        const bool low = !(dv[a] > boost);
+        const bool fail = !isfinite(dv[a]) || (low && !boosting);
         raised += (low && !fail && l < nbk) ? 1 : 0;
         bad = (fail && bad < 0) ? l : bad;
-        const double piv = fail ? 1.0 : (low ? boost : diag);
-        const double r = rsqrt_nr(piv);
-        const double u = (lane > l) ? x[a] * r : ((lane == l) ? piv * r : 0.0);
-        x[a] = u;
-#pragma unroll
-        for (int b = a + 1; b < 4; ++b) x[b] = fma(-lane_bcast(u, L + b), u, x[b]);
       }
-#pragma unroll
-      for (int a = 0; a < 4; ++a) S[(L + a) * kNb + lane] = x[a];
       if (lane == 0 && bad >= 0 && sbad[0] < 0) sbad[0] = bad;
       if (lane == 0) sbad[1] += raised;
     }
