@@ -647,12 +647,15 @@ Err upload_descs(flsq_ctx* c, const std::vector<GemmDesc>& h, GemmDesc** d_out) 
 // (their count goes to *boosted_host); info_host > 0 at the first failed pivot (1-based:
 // non-finite, or non-positive when boost = 0), the steps after a failure return at once, and
 // X is then not written.
-Err cholesky_inv(flsq_ctx* c, double* G, double* X, int n, const double* d, int* info_host, double boost,
-                 int* boosted_host) {
-  int* info;
+//
+// status: device words, [0] the pivot status and [1] the raised pivots (ints), then `extra`
+// more bytes that the same read-back brings to host_extra (the caller's values computed
+// before the factorisation, so that it need not wait for them separately).
+Err cholesky_inv(flsq_ctx* c, double* G, double* X, int n, const double* d, int* status, size_t extra,
+                 void* host_extra, int* info_host, double boost, int* boosted_host) {
+  int* info = status;
   double* W;
   hipStream_t st = c->stream;
-  CHECK_ERR(ws_get(c, "chol_info", 2, &info));
   CHECK_ERR(ws_get(c, "chol_w", (size_t)n * n, &W));
   CHECK_HIP(hipMemsetAsync(info, 0, 2 * sizeof(int), st));
   CHECK_HIP(hipMemsetAsync(W, 0, sizeof(double) * n * n, st));
@@ -679,8 +682,12 @@ Err cholesky_inv(flsq_ctx* c, double* G, double* X, int n, const double* d, int*
       k0 += kNb;
     }
   }
-  int hinfo[2] = {0, 0};
-  CHECK_ERR(read_back(c, hinfo, info, sizeof hinfo));
+  unsigned char hbuf[2 * sizeof(int) + 64];
+  if (extra > 64) return fail(FLSQ_EINVAL, "internal: status read-back too long");
+  CHECK_ERR(read_back(c, hbuf, info, 2 * sizeof(int) + extra));
+  int hinfo[2];
+  memcpy(hinfo, hbuf, sizeof hinfo);
+  if (extra) memcpy(host_extra, hbuf + sizeof hinfo, extra);
   *info_host = hinfo[0];
   *boosted_host = hinfo[1];
   if (hinfo[0] == 0) CHECK_HIP(launch_inv_transpose(W, d, n, X, st));
@@ -723,25 +730,28 @@ Err chol_solve(flsq_ctx* c, const double* X, int n, const double* Y, double* Z, 
 Err factor_with_retries(flsq_ctx* c, const double* Gsrc, double* U, double* X, int n, double mu, double shift0,
                         double* shift_used, int* retries, double boost = 0.0, int* boosted = nullptr,
                         int* recalled = nullptr) {
-  double *dmax, *d;
+  double *stat, *d;
   unsigned long long* fp_part;
-  CHECK_ERR(ws_get(c, "diag_max", 2, &dmax));   // [0] the largest diagonal entry, [1] the fingerprint
+  // [0] the pivot status (two ints), [1] the largest diagonal entry, [2] the fingerprint
+  CHECK_ERR(ws_get(c, "chol_status", 3, &stat));
   CHECK_ERR(ws_get(c, "eq_d", (size_t)n, &d));
   CHECK_ERR(ws_get(c, "fp_part", (size_t)n, &fp_part));
-  unsigned long long* d_fp = reinterpret_cast<unsigned long long*>(dmax + 1);
+  int* status = reinterpret_cast<int*>(stat);
+  double* dmax = stat + 1;
+  unsigned long long* d_fp = reinterpret_cast<unsigned long long*>(stat + 2);
   // the entry for this size and these settings, if any (else the one a new entry replaces)
   ShiftMemo* memo = nullptr;
   for (ShiftMemo& m : c->shift_memo)
     if (m.valid && m.n == n && m.mu == mu && m.shift0 == shift0 && m.boost == boost) memo = &m;
   const bool memo_applies = memo && memo->shift > shift0;
   CHECK_HIP(launch_diag_max(Gsrc, n, dmax, c->stream));
-  if (memo_applies) CHECK_HIP(launch_fingerprint_upper(Gsrc, n, fp_part, d_fp, c->stream));
-  double hv[2] = {0.0, 0.0};
-  CHECK_ERR(read_back(c, hv, dmax, memo_applies ? sizeof hv : sizeof(double)));
-  if (!std::isfinite(hv[0])) return fail(FLSQ_ENONFINITE, "Gram diagonal is not finite");
   unsigned long long fp = 0;
   bool have_fp = false;
-  if (memo_applies) {
+  if (memo_applies) {   // the starting shift depends on the fingerprint: wait for it
+    CHECK_HIP(launch_fingerprint_upper(Gsrc, n, fp_part, d_fp, c->stream));
+    double hv[2] = {0.0, 0.0};
+    CHECK_ERR(read_back(c, hv, dmax, sizeof hv));
+    if (!std::isfinite(hv[0])) return fail(FLSQ_ENONFINITE, "Gram diagonal is not finite");
     memcpy(&fp, &hv[1], sizeof fp);
     have_fp = true;
   }
@@ -752,7 +762,11 @@ Err factor_with_retries(flsq_ctx* c, const double* Gsrc, double* U, double* X, i
   for (int attempt = 0; attempt < 8; ++attempt) {
     CHECK_HIP(launch_equilibrate(Gsrc, U, n, d, mu, rel, c->stream));
     int info = 0, nb = 0;
-    CHECK_ERR(cholesky_inv(c, U, X, n, d, &info, boost, &nb));
+    double dm = 0.0;   // the diagonal's largest entry comes back with the first attempt's status
+    CHECK_ERR(cholesky_inv(c, U, X, n, d, status, attempt == 0 && !memo_applies ? sizeof(double) : 0, &dm, &info,
+                           boost, &nb));
+    if (attempt == 0 && !memo_applies && !std::isfinite(dm))
+      return fail(FLSQ_ENONFINITE, "Gram diagonal is not finite");
     if (info == 0) {
       *shift_used = rel;
       if (boosted) *boosted = nb;
@@ -954,7 +968,7 @@ Err cgls_refine_op(flsq_ctx* c, const LsqOp& op, const double* Xi, double mu, co
   CHECK_ERR(ws_get(c, "cg_g", (size_t)n * K, &g));
   CHECK_ERR(ws_get(c, "cg_z", (size_t)n * K, &z));
   CHECK_ERR(ws_get(c, "cg_p", (size_t)n * K, &p));
-  CHECK_ERR(ws_get(c, "cg_dots", (size_t)12 * K, &dots));
+  CHECK_ERR(ws_get(c, "cg_dots", (size_t)14 * K, &dots));
   CHECK_ERR(ws_get(c, "cg_dwork", (size_t)512 * K + 64, &dwork));
   hipStream_t st = c->stream;
   std::vector<double> tmp, stepn(K);
@@ -962,16 +976,25 @@ Err cgls_refine_op(flsq_ctx* c, const LsqOp& op, const double* Xi, double mu, co
   // s = Y - A X ; g = A^T s - mu X ; u = H X
   CHECK_ERR(op.apply(c, X, K, Y, -1.0, 1.0, sres, uu));
   CHECK_ERR(op.applyT(c, sres, K, X, 1.0, -mu, g));
-  if (want_grad0) {
-    CHECK_HIP(launch_dot_cols(g, g, n, K, dots, dwork, st));
-    CHECK_ERR(host_cols(c, dots, K, tmp));
-    double m = 0;
-    for (double v : tmp) m = std::max(m, std::sqrt(v));
-    ro->grad0 = m;
-  }
+  // Per-column scalars on the device: gam | alpha | beta | qq | pp | hq.hq | u.u | s.s | X.X |
+  // gam_new, then the starting values Y.Y | s.s | X.X | g.g.  The host reads alpha, the step
+  // norms and the objective once per iteration (the first read also brings the starting
+  // values); the step lengths and the direction update never wait for it.
+  double* d_gam = dots;
+  double *d_alpha = dots + K, *d_beta = dots + 2 * K, *d_qq = dots + 3 * K, *d_pp = dots + 4 * K;
+  double *d_hh = dots + 5 * K, *d_uu = dots + 6 * K, *d_ss = dots + 7 * K, *d_xx = dots + 8 * K;
+  double* d_gnew = dots + 9 * K;
+  double* d_start = dots + 10 * K;
+  if (want_grad0) CHECK_HIP(launch_dot_cols(g, g, n, K, d_start + 3 * K, dwork, st));
   ro->iters = 0;
   ro->converged = (max_iter == 0);
   if (max_iter == 0) {
+    if (want_grad0) {
+      CHECK_ERR(host_cols(c, d_start + 3 * K, K, tmp));
+      double m = 0;
+      for (double v : tmp) m = std::max(m, std::sqrt(v));
+      ro->grad0 = m;
+    }
     ro->grad = ro->grad0;
     return ok();
   }
@@ -985,27 +1008,15 @@ Err cgls_refine_op(flsq_ctx* c, const LsqOp& op, const double* Xi, double mu, co
   double* Xbest;
   CHECK_ERR(ws_get(c, "cg_xbest", (size_t)n * K, &Xbest));
   CHECK_HIP(hipMemcpyAsync(Xbest, X, sizeof(double) * n * K, hipMemcpyDeviceToDevice, st));
-  CHECK_HIP(launch_dot_cols(Y, Y, P, K, dots, dwork, st));
-  CHECK_HIP(launch_dot_cols(sres, sres, P, K, dots + K, dwork, st));
-  CHECK_HIP(launch_dot_cols(X, X, n, K, dots + 2 * K, dwork, st));
-  CHECK_ERR(host_cols(c, dots, 3 * K, tmp));
+  CHECK_HIP(launch_dot_cols(Y, Y, P, K, d_start, dwork, st));
+  CHECK_HIP(launch_dot_cols(sres, sres, P, K, d_start + K, dwork, st));
+  CHECK_HIP(launch_dot_cols(X, X, n, K, d_start + 2 * K, dwork, st));
   ynorm.resize(K);
-  for (int k = 0; k < K; ++k) {
-    ynorm[k] = std::max(std::sqrt(tmp[k]), 1e-300);
-    Jbest[k] = tmp[K + k] + mu * tmp[2 * K + k];
-  }
-  // Per-column scalars stay on the device: gam | alpha | beta | qq | pp | hq.hq | u.u | s.s | X.X |
-  // gam_new.  The host reads alpha, the step norms and the objective once per iteration; the
-  // step lengths and the direction update never wait for it.
-  double* d_gam = dots;
-  double *d_alpha = dots + K, *d_beta = dots + 2 * K, *d_qq = dots + 3 * K, *d_pp = dots + 4 * K;
-  double *d_hh = dots + 5 * K, *d_uu = dots + 6 * K, *d_ss = dots + 7 * K, *d_xx = dots + 8 * K;
-  double* d_gnew = dots + 9 * K;
   CHECK_ERR(chol_solve(c, Xi, n, g, z, K));
   CHECK_HIP(hipMemcpyAsync(p, z, sizeof(double) * n * K, hipMemcpyDeviceToDevice, st));
   CHECK_HIP(launch_dot_cols(g, z, n, K, d_gam, dwork, st));
   bool stalled_all = false;
-  std::vector<double> hs(8 * K);
+  std::vector<double> hs(13 * K);
   for (int it = 0; it < max_iter; ++it) {
     // q = A p ; delta = ||q||^2 + mu ||p||^2 ; hq = H p ; alpha = gam / delta
     CHECK_ERR(op.apply(c, p, K, nullptr, 1.0, 0.0, q, hq));
@@ -1059,7 +1070,20 @@ Err cgls_refine_op(flsq_ctx* c, const LsqOp& op, const double* Xi, double mu, co
       db.out[1] = d_xx;
       CHECK_HIP(launch_dot_batch(db, dwork, st));
     }
-    CHECK_ERR(read_back(c, hs.data(), d_alpha, sizeof(double) * 8 * K));
+    // alpha .. X.X (8 K values), on the first iteration also the starting values (13 K)
+    CHECK_ERR(read_back(c, hs.data(), d_alpha, sizeof(double) * (it == 0 ? 13 : 8) * K));
+    if (it == 0) {
+      const double* h0 = hs.data() + 9 * K;   // Y.Y | s.s | X.X | g.g
+      for (int k = 0; k < K; ++k) {
+        ynorm[k] = std::max(std::sqrt(h0[k]), 1e-300);
+        Jbest[k] = h0[K + k] + mu * h0[2 * K + k];
+      }
+      if (want_grad0) {
+        double m = 0;
+        for (int k = 0; k < K; ++k) m = std::max(m, std::sqrt(h0[3 * K + k]));
+        ro->grad0 = m;
+      }
+    }
     const double* h_alpha = hs.data();
     const double *h_qq = hs.data() + 2 * K, *h_hh = hs.data() + 4 * K, *h_uu = hs.data() + 5 * K;
     const double *h_ss = hs.data() + 6 * K, *h_xx = hs.data() + 7 * K;
