@@ -624,7 +624,7 @@ __global__ __launch_bounds__(256) void k_gemm_t16(const double* __restrict__ Mt,
 
 static int gemm_t16_splits(int64_t M, int64_t L) {
   const int64_t wgs = (M + 63) / 64;
-  const int64_t want = (768 + wgs - 1) / wgs;
+  const int64_t want = (1536 + wgs - 1) / wgs;
   const int64_t cap = std::max<int64_t>(1, L / (4 * kT16Slab));
   return (int)std::max<int64_t>(1, std::min<int64_t>(std::min(want, cap), 64));
 }
