@@ -536,7 +536,10 @@ int i8_bits(int64_t P_pad) {
 
 constexpr int64_t kI8MaxRows = 133000;   // 127^2 * rows < 2^31: exact int32 sums
 
-Err run_gram_i8(flsq_ctx* c, const System& s, const double* rho, double* G, int mirror, double diag_add) {
+// Y, cvec (nullable, both or neither): also form cvec = A^T Y from the entries the residue pass
+// evaluates anyway.
+Err run_gram_i8(flsq_ctx* c, const System& s, const double* rho, double* G, int mirror, double diag_add,
+                const double* Y = nullptr, double* cvec = nullptr) {
   const int T = i8_tile(), KBR = i8_kblock();
   const int n = s.n;
   const int nt = (n + T - 1) / T, n_pad = nt * T, n_tiles = nt * (nt + 1) / 2;
@@ -564,7 +567,9 @@ Err run_gram_i8(flsq_ctx* c, const System& s, const double* rho, double* G, int 
     CHECK_ERR(stage_upload(c, order, h.data(), sizeof(int2) * n_tiles));
   }
   CHECK_HIP(launch_i8_scale(s.amp.as<double>(), s.n_blocks, n, rho, s.P, rho_max, B, inv_scale, scale, st));
-  CHECK_HIP(launch_i8_residues(s.geo(), rho, inv_scale, M, n_pad, KB, R, st));
+  double* cpart = nullptr;
+  if (cvec) CHECK_ERR(ws_get(c, "i8_cpart", (size_t)KB * n_pad, &cpart));
+  CHECK_HIP(launch_i8_residues(s.geo(), rho, inv_scale, M, n_pad, KB, R, cvec ? Y : nullptr, cpart, cvec, st));
   I8GemmJob J;
   J.R = R;
   J.n_pad = n_pad;
@@ -976,14 +981,14 @@ Err cgls_refine_op(flsq_ctx* c, const LsqOp& op, const double* Xi, double mu, co
   // s = Y - A X ; g = A^T s - mu X ; u = H X
   CHECK_ERR(op.apply(c, X, K, Y, -1.0, 1.0, sres, uu));
   CHECK_ERR(op.applyT(c, sres, K, X, 1.0, -mu, g));
-  // Per-column scalars on the device: gam | alpha | beta | qq | pp | hq.hq | u.u | s.s | X.X |
-  // gam_new, then the starting values Y.Y | s.s | X.X | g.g.  The host reads alpha, the step
+  // Per-column scalars on the device: gam | alpha | (unused) | qq | pp | hq.hq | u.u | s.s | X.X |
+  // gam_new, then the starting values Y.Y | s.s | X.X | g.g (gam and gam_new alternate).  The host reads alpha, the step
   // norms and the objective once per iteration (the first read also brings the starting
   // values); the step lengths and the direction update never wait for it.
   double* d_gam = dots;
-  double *d_alpha = dots + K, *d_beta = dots + 2 * K, *d_qq = dots + 3 * K, *d_pp = dots + 4 * K;
+  double *d_alpha = dots + K, *d_qq = dots + 3 * K, *d_pp = dots + 4 * K;
   double *d_hh = dots + 5 * K, *d_uu = dots + 6 * K, *d_ss = dots + 7 * K, *d_xx = dots + 8 * K;
-  double* d_gnew = dots + 9 * K;
+  double* d_gnew = dots + 9 * K;   // gam and gam_new trade places after every direction update
   double* d_start = dots + 10 * K;
   if (want_grad0) CHECK_HIP(launch_dot_cols(g, g, n, K, d_start + 3 * K, dwork, st));
   ro->iters = 0;
@@ -1016,6 +1021,7 @@ Err cgls_refine_op(flsq_ctx* c, const LsqOp& op, const double* Xi, double mu, co
   CHECK_HIP(hipMemcpyAsync(p, z, sizeof(double) * n * K, hipMemcpyDeviceToDevice, st));
   CHECK_HIP(launch_dot_cols(g, z, n, K, d_gam, dwork, st));
   bool stalled_all = false;
+  uint64_t keep_mask = 0;
   std::vector<double> hs(13 * K);
   for (int it = 0; it < max_iter; ++it) {
     // q = A p ; delta = ||q||^2 + mu ||p||^2 ; hq = H p ; alpha = gam / delta
@@ -1038,8 +1044,8 @@ Err cgls_refine_op(flsq_ctx* c, const LsqOp& op, const double* Xi, double mu, co
       }
       CHECK_HIP(launch_dot_batch(db, dwork, st));
     }
-    CHECK_HIP(launch_cg_alpha(d_gam, d_qq, d_pp, mu, col_mask(active), K, d_alpha, st));
     {
+      // alpha = gam / delta and the step; X's columns improved by the previous step go to Xbest first
       AxpyBatch ab{};
       ab.K = K;
       ab.count = track_u ? 3 : 2;
@@ -1055,7 +1061,8 @@ Err cgls_refine_op(flsq_ctx* c, const LsqOp& op, const double* Xi, double mu, co
       ab.y[2] = uu;
       ab.n[2] = P;
       ab.sign[2] = 1.0;
-      CHECK_HIP(launch_axpy_batch_dev(d_alpha, ab, st));
+      CHECK_HIP(launch_cg_step(d_gam, d_qq, d_pp, mu, col_mask(active), d_alpha, ab, Xbest, keep_mask, st));
+      keep_mask = 0;
     }
     // objective after the step
     {
@@ -1128,7 +1135,7 @@ Err cgls_refine_op(flsq_ctx* c, const LsqOp& op, const double* Xi, double mu, co
       if (stagnant[k] >= 2) active[k] = 0.0;
       if (active[k] > 0.0) ++n_active;
     }
-    CHECK_HIP(launch_select_cols(X, Xbest, n, K, col_mask(improved), st));
+    keep_mask = col_mask(improved);   // copied by the next step's launch, or below
     if (worst_pred <= tol) {
       ro->converged = true;
       break;
@@ -1141,10 +1148,10 @@ Err cgls_refine_op(flsq_ctx* c, const LsqOp& op, const double* Xi, double mu, co
     // g = A^T s - mu X ; z = M^{-1} g ; beta = (g.z) / gam ; p = z + beta p
     CHECK_ERR(op.applyT(c, sres, K, X, 1.0, -mu, g));
     CHECK_ERR(chol_solve(c, Xi, n, g, z, K));
-    CHECK_HIP(launch_dot_cols(g, z, n, K, d_gnew, dwork, st));
-    CHECK_HIP(launch_cg_beta(d_gnew, d_gam, K, d_beta, st));
-    CHECK_HIP(launch_xpby_cols_dev(z, d_beta, p, n, K, st));
+    CHECK_HIP(launch_cg_direction(g, z, p, n, K, d_gam, d_gnew, dwork, st));
+    std::swap(d_gam, d_gnew);
   }
+  if (keep_mask) CHECK_HIP(launch_select_cols(X, Xbest, n, K, keep_mask, st));
   // return the best iterate of every column; the recurrence residual is recomputed
   CHECK_HIP(hipMemcpyAsync(X, Xbest, sizeof(double) * n * K, hipMemcpyDeviceToDevice, st));
   if (stalled_all) ro->converged = true;   // no further progress is possible in FP64
@@ -1352,14 +1359,22 @@ Err refine_lazy(flsq_ctx* c, const LsqOp& op, const SolveParams& sp, bool lazy, 
 }
 
 // Gram, Cholesky, and the inverse factor Xi = U^{-1} (the preconditioner is Xi Xi^T).
+// Y1, c1 (nullable): a single right-hand side whose c1 = A^T Y1 the INT8_CRT Gram forms on the way
+// (*c1_formed tells whether it did; other precisions leave it to the caller).
 Err gram_and_factor(flsq_ctx* c, const System& s, const double* rho, const SolveParams& sp, double* Xi,
-                    flsq_solve_info* info, bool* second_out = nullptr) {
+                    flsq_solve_info* info, bool* second_out = nullptr, const double* Y1 = nullptr,
+                    double* c1 = nullptr, bool* c1_formed = nullptr) {
   const int n = s.n;
   double *G, *U;
   CHECK_ERR(ws_get(c, "G", (size_t)n * n, &G));
   CHECK_ERR(ws_get(c, "Ufac", (size_t)n * n, &U));
   const double t0 = now_ms();
-  CHECK_ERR(run_gram(c, s, sp.prec, rho, G, 0, 0.0));
+  const bool fold_c = sp.prec == FLSQ_PREC_INT8_CRT && Y1 && c1;
+  if (fold_c)
+    CHECK_ERR(run_gram_i8(c, s, rho, G, 0, 0.0, Y1, c1));
+  else
+    CHECK_ERR(run_gram(c, s, sp.prec, rho, G, 0, 0.0));
+  if (c1_formed) *c1_formed = fold_c;
   CHECK_HIP(hipStreamSynchronize(c->stream));
   const double t1 = now_ms();
   float kms = 0.f;
@@ -1456,14 +1471,17 @@ Err solve_on_system(flsq_ctx* c, const System& s, const double* rho, const Solve
   const int n = s.n;
   double* Xi;
   CHECK_ERR(ws_get(c, "Xinv", (size_t)n * n, &Xi));
-  bool eager = false;
-  CHECK_ERR(gram_and_factor(c, s, rho, sp, Xi, info, &eager));
-  const double t1 = now_ms();
-  // X0 = (U^T U)^{-1} A^T Y
+  // X0 = (U^T U)^{-1} A^T Y; with one right-hand side the INT8_CRT Gram's residue pass forms A^T Y
   double *cvec, *colwork;
   CHECK_ERR(ws_get(c, "cvec", (size_t)n * K, &cvec));
-  CHECK_ERR(ws_get(c, "colwork0", pass_work_elems(n, s.n_runs, K) + 64, &colwork));
-  CHECK_HIP(launch_colpass_runs(s.pass(), rho, Yw, K, nullptr, 1.0, 0.0, cvec, colwork, c->stream));
+  bool eager = false, c_formed = false;
+  CHECK_ERR(gram_and_factor(c, s, rho, sp, Xi, info, &eager, K == 1 ? Yw : nullptr, K == 1 ? cvec : nullptr,
+                            &c_formed));
+  const double t1 = now_ms();
+  if (!c_formed) {
+    CHECK_ERR(ws_get(c, "colwork0", pass_work_elems(n, s.n_runs, K) + 64, &colwork));
+    CHECK_HIP(launch_colpass_runs(s.pass(), rho, Yw, K, nullptr, 1.0, 0.0, cvec, colwork, c->stream));
+  }
   CHECK_ERR(chol_solve(c, Xi, n, cvec, X, K));
   RefineOut ro;
   const bool lazy = sp.second_pass == 0 && !eager && second_pass_allowed(sp, rho, s.P, n) &&
@@ -1854,10 +1872,10 @@ flsq_status flsq_factor_solve_normal(flsq_ctx* ctx, const flsq_factor* F, const 
     CHECK_HIP(hipMemcpyAsync(r, V, sizeof(double) * n * K, hipMemcpyDeviceToDevice, st));
     std::vector<double> ones(K, 1.0);
     CHECK_HIP(launch_axpy_cols(cols(ones), ap, r, n, K, -1.0, st));
-    // Per-column scalars stay on the device: gam | alpha | beta | p.Mp | x.V before the step |
-    // x.V | x.r | gam_new; the host reads them once per iteration.
+    // Per-column scalars stay on the device: gam | alpha | (unused) | p.Mp | x.V before the step |
+    // x.V | x.r | gam_new (gam and gam_new alternate); the host reads them once per iteration.
     double* d_gam = dots;
-    double *d_alpha = dots + K, *d_beta = dots + 2 * K, *d_pap = dots + 3 * K, *d_xv0 = dots + 4 * K;
+    double *d_alpha = dots + K, *d_pap = dots + 3 * K, *d_xv0 = dots + 4 * K;
     double *d_xv = dots + 5 * K, *d_xr = dots + 6 * K, *d_gnew = dots + 7 * K;
     CHECK_ERR(chol_solve(ctx, F->Xinv.as<double>(), n, r, z, K));
     CHECK_HIP(hipMemcpyAsync(p, z, sizeof(double) * n * K, hipMemcpyDeviceToDevice, st));
@@ -1877,6 +1895,7 @@ flsq_status flsq_factor_solve_normal(flsq_ctx* ctx, const flsq_factor* F, const 
     std::vector<int> stagnant(K, 0);
     for (int k = 0; k < K; ++k) phibest[k] = -0.5 * (tmp[k] + tmp[K + k]);
     std::vector<double> hs(6 * K);
+    uint64_t keep_mask = 0;
     for (int it = 0; it < F->max_refine; ++it) {
       CHECK_ERR(apply_normal(p, ap));
       {
@@ -1893,7 +1912,6 @@ flsq_status flsq_factor_solve_normal(flsq_ctx* ctx, const flsq_factor* F, const 
         db.out[1] = d_xv0;
         CHECK_HIP(launch_dot_batch(db, dwork, st));
       }
-      CHECK_HIP(launch_cg_alpha(d_gam, d_pap, nullptr, 0.0, col_mask(active), K, d_alpha, st));
       {
         AxpyBatch ab{};
         ab.K = K;
@@ -1906,7 +1924,8 @@ flsq_status flsq_factor_solve_normal(flsq_ctx* ctx, const flsq_factor* F, const 
         ab.y[1] = r;
         ab.n[1] = n;
         ab.sign[1] = -1.0;
-        CHECK_HIP(launch_axpy_batch_dev(d_alpha, ab, st));
+        CHECK_HIP(launch_cg_step(d_gam, d_pap, nullptr, 0.0, col_mask(active), d_alpha, ab, xbest, keep_mask, st));
+        keep_mask = 0;
       }
       {
         DotBatch db{};
@@ -1961,13 +1980,13 @@ flsq_status flsq_factor_solve_normal(flsq_ctx* ctx, const flsq_factor* F, const 
         if (stagnant[k] >= 2) active[k] = 0.0;
         if (active[k] > 0.0) ++n_active;
       }
-      CHECK_HIP(launch_select_cols(out, xbest, n, K, col_mask(improved), st));
+      keep_mask = col_mask(improved);   // copied by the next step's launch, or below
       if (worst <= F->refine_tol || n_active == 0 || it + 1 == F->max_refine) break;
       CHECK_ERR(chol_solve(ctx, F->Xinv.as<double>(), n, r, z, K));
-      CHECK_HIP(launch_dot_cols(r, z, n, K, d_gnew, dwork, st));
-      CHECK_HIP(launch_cg_beta(d_gnew, d_gam, K, d_beta, st));
-      CHECK_HIP(launch_xpby_cols_dev(z, d_beta, p, n, K, st));
+      CHECK_HIP(launch_cg_direction(r, z, p, n, K, d_gam, d_gnew, dwork, st));
+      std::swap(d_gam, d_gnew);
     }
+    if (keep_mask) CHECK_HIP(launch_select_cols(out, xbest, n, K, keep_mask, st));
     CHECK_HIP(hipMemcpyAsync(out, xbest, sizeof(double) * n * K, hipMemcpyDeviceToDevice, st));
     return ok();
   };

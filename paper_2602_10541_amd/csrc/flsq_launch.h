@@ -155,8 +155,10 @@ size_t i8_gemm_lds_bytes();
 // c_j = max_g |amp_gj| + max_i |rho_i| (rho nullable; rho_max: device scalar workspace)
 hipError_t launch_i8_scale(const double* amp, int n_blocks, int n, const double* rho, int64_t P, double* rho_max,
                            int B, double* inv_scale, double* scale, hipStream_t s);
+// With Y (P doubles), cpart (KB * n_pad doubles of workspace) and c (n doubles) all given, the
+// same pass also writes c = A^T Y, summed in a fixed order; all three null otherwise.
 hipError_t launch_i8_residues(const Geo& g, const double* rho, const double* inv_scale, const I8Moduli& M, int n_pad,
-                              int KB, int8_t* R, hipStream_t s);
+                              int KB, int8_t* R, const double* Y, double* cpart, double* c, hipStream_t s);
 hipError_t launch_gram_i8(const I8GemmJob& J, hipStream_t s);
 hipError_t launch_i8_crt(const I8CrtJob& J, hipStream_t s);
 
@@ -266,7 +268,7 @@ struct DotBatch {
   int K;
 };
 hipError_t launch_dot_batch(const DotBatch& b, double* work, hipStream_t s);
-// Up to kAxpyBatchMax updates y_q[i][c] += sign_q a[c] x_q[i][c] (a: device, K entries) in one launch.
+// Up to kAxpyBatchMax updates y_q[i][c] += sign_q a[c] x_q[i][c] in one launch (launch_cg_step).
 constexpr int kAxpyBatchMax = 3;
 struct AxpyBatch {
   const double* x[kAxpyBatchMax];
@@ -276,7 +278,6 @@ struct AxpyBatch {
   int count;
   int K;
 };
-hipError_t launch_axpy_batch_dev(const double* a, const AxpyBatch& b, hipStream_t s);
 hipError_t launch_dot_cols(const double* x, const double* y, int64_t n, int K, double* out, double* work,
                            hipStream_t s);
 // out[c] = sum_i u_i s_i Y[i][c] (Y n x K row-major), s_i = X[i * ldx + xcol] or 1 when X is NULL
@@ -294,17 +295,19 @@ hipError_t launch_axpy_cols(const ColScalars& a, const double* x, double* y, int
 // p[i][c] = z[i][c] + b[c] * p[i][c]
 hipError_t launch_xpby_cols(const double* z, const ColScalars& b, double* p, int64_t n, int K, hipStream_t s);
 hipError_t launch_count_nonfinite(const double* x, int64_t n, int* flag, hipStream_t s);
-// The same with the scalars in device memory (K doubles), for the device-resident CG scalars.
-hipError_t launch_axpy_cols_dev(const double* a, const double* x, double* y, int64_t n, int K, double sign,
-                                hipStream_t s);
-hipError_t launch_xpby_cols_dev(const double* z, const double* b, double* p, int64_t n, int K, hipStream_t s);
-// alpha[k] = gam[k] / (d1[k] + mu d2[k]) on the columns set in active with both positive, else 0
-// (d2 nullable); beta[k] = gam_new[k] / gam[k] (0 if gam[k] <= 0), then gam[k] = gam_new[k].
-hipError_t launch_cg_alpha(const double* gam, const double* d1, const double* d2, double mu, uint64_t active, int K,
-                           double* alpha, hipStream_t s);
-hipError_t launch_cg_beta(const double* gam_new, double* gam, int K, double* beta, hipStream_t s);
 // dst[i][c] = src[i][c] for the columns c whose bit is set in mask
 hipError_t launch_select_cols(const double* src, double* dst, int64_t n, int K, uint64_t mask, hipStream_t s);
+// CG steps with device-resident scalars.  alpha_k = gam_k / (d1_k + mu d2_k) (columns set in
+// active with both positive, else 0; d2 nullable), then y_q += sign_q alpha x_q for the batch, in
+// one launch; alpha_out (K doubles) receives alpha.  keep (nullable): the columns of y_0 set in
+// keep_mask are copied to keep before the update.  K <= 64.
+hipError_t launch_cg_step(const double* gam, const double* d1, const double* d2, double mu, uint64_t active,
+                          double* alpha_out, const AxpyBatch& b, double* keep, uint64_t keep_mask, hipStream_t s);
+// gam_new = g . z per column (n x K row-major), p = z + (gam_new / gam_old) p (0 where
+// gam_old <= 0); work as for launch_dot_cols.  gam_old is only read: the caller alternates the
+// two buffers between iterations.  K <= 64.
+hipError_t launch_cg_direction(const double* g, const double* z, double* p, int64_t n, int K, const double* gam_old,
+                               double* gam_new, double* work, hipStream_t s);
 
 
 // ---- inverse heat-source support

@@ -54,13 +54,41 @@ __global__ __launch_bounds__(1024) void k_absmax(const double* x, int64_t n, dou
 }
 
 // ------------------------------------------------------------------ residues
-// Workgroup: 64 features x one 64-row K block; thread (feature tid / 4, rows 16 (tid % 4) ..).
+// Workgroup: 32 features x one 64-row K block; thread (feature tid / 8, rows 8 (tid % 8) ..),
+// so the eight threads of a feature store its 64 bytes per modulus side by side.
 // R layout: R[((t * KB + kb) * n_pad + f) * 64 + r], zero for padded rows and features.
+//
+// Residue bytes: for the integer a (|a| <= 2^46, as B <= 46 for every admissible row count) and
+// an odd modulus p, q = rint(a / p) is fma(a, 1/p, 1.5 * 2^52) - 1.5 * 2^52: the exact product
+// lies within 2^-14 of a / p, which itself is at least 1 / (2p) away from any half-integer, so
+// the single rounding of the fma gives q, and the low 32 bits of the biased double are q
+// modulo 2^32.  The balanced residue a - p q lies in [-(p-1)/2, (p-1)/2], so its int8 byte is
+// (a - p q) mod 256 = (a mod 2^32 + (256 - p) (q mod 2^24)) mod 256: one FP64 fma and one
+// 24-bit integer multiply-add per entry and modulus.
+//
+// With Y given (P doubles), the same pass also forms the block's part of c = A^T Y from the
+// FP64 entries before they are scaled: cpart[kb * n_pad + f] = sum over the block's rows (8
+// rows per thread in order, then the eight threads of a feature pairwise), summed over kb by
+// k_colsum_parts.
+constexpr double kBias52 = 6755399441055744.0;   // 1.5 * 2^52
+
+__device__ __forceinline__ unsigned low_word(double x) { return (unsigned)__double_as_longlong(x); }
+
+// a * b + c on the low 24 bits of a and b (full-rate v_mad_u32_u24; written out because the
+// compiler, seeing that only the low byte of the result is used, would otherwise widen the
+// product to a quarter-rate 32-bit multiply).
+__device__ __forceinline__ unsigned mad_u24(unsigned a, unsigned b, unsigned c) {
+  unsigned d;
+  asm("v_mad_u32_u24 %0, %1, %2, %3" : "=v"(d) : "v"(a), "s"(b), "v"(c));
+  return d;
+}
+
 template <int D>
-__global__ __launch_bounds__(256) void k_i8_residues(Geo g, const double* rho, const double* inv_scale,
-                                                     I8Moduli M, int n_pad, int KB, int8_t* R) {
+__global__ __launch_bounds__(256) void k_i8_residues(Geo g, const double* rho, const double* inv_scale, I8Moduli M,
+                                                     int n_pad, int KB, int8_t* R, const double* Y, double* cpart) {
   __shared__ double sX[D][kI8Kb];
   __shared__ double sRho[kI8Kb];
+  __shared__ double sY[kI8Kb];
   __shared__ int sBlk[kI8Kb];
   const int kb = blockIdx.x;
   const int tid = threadIdx.x;
@@ -72,47 +100,61 @@ __global__ __launch_bounds__(256) void k_i8_residues(Geo g, const double* rho, c
   if (tid < kI8Kb) {
     const bool in = i0 + tid < g.P;
     sRho[tid] = (rho && in) ? rho[i0 + tid] : 0.0;
+    sY[tid] = (Y && in) ? Y[i0 + tid] : 0.0;
     sBlk[tid] = in ? g.row_block[i0 + tid] : -1;
   }
   __syncthreads();
-  const int f = blockIdx.y * 64 + tid / 4;
-  const int r0 = 16 * (tid % 4);
+  const int f = blockIdx.y * 32 + tid / 8;
+  const int r0 = 8 * (tid % 8);
   const bool fvalid = f < g.n;
   double w[D];
 #pragma unroll
   for (int k = 0; k < D; ++k) w[k] = fvalid ? g.Wt[(int64_t)k * g.n + f] : 0.0;
   const double isc = fvalid ? inv_scale[f] : 0.0;
-  double a[16];
+  double a[8];
+  unsigned alo[8];
+  double cy = 0.0;
+  const int fc = min(f, g.n - 1);
 #pragma unroll
-  for (int r = 0; r < 16; ++r) {
+  for (int r = 0; r < 8; ++r) {   // branch-free: padded rows and features read a valid entry, then drop it
     const int blk = sBlk[r0 + r];
-    double v = 0.0;
-    if (fvalid && blk >= 0) {
-      double z = g.ph[(int64_t)blk * g.n + f];
+    const int64_t o = (int64_t)max(blk, 0) * g.n + fc;
+    double z = g.ph[o];
 #pragma unroll
-      for (int k = 0; k < D; ++k) z = fma(w[k], sX[k][r0 + r], z);
-      v = rint((g.amp[(int64_t)blk * g.n + f] + sRho[r0 + r]) * sin_f64(z) * isc);
-    }
+    for (int k = 0; k < D; ++k) z = fma(w[k], sX[k][r0 + r], z);
+    const double e = (fvalid && blk >= 0) ? (g.amp[o] + sRho[r0 + r]) * sin_f64(z) : 0.0;
+    cy = fma(e, sY[r0 + r], cy);
+    const double v = rint(e * isc);
     a[r] = v;
+    alo[r] = low_word(v + kBias52);
   }
-  for (int t = 0; t < M.n_mod; ++t) {
-    const double p = M.p[t], ip = M.inv_p[t];
-    unsigned pk[4];
+  if (cpart) {   // the eight threads of a feature are adjacent lanes
+    cy += __shfl_xor(cy, 1);
+    cy += __shfl_xor(cy, 2);
+    cy += __shfl_xor(cy, 4);
+    if ((tid & 7) == 0) cpart[(int64_t)kb * n_pad + f] = cy;
+  }
+  int8_t* dst = R + ((int64_t)kb * n_pad + f) * kI8Kb + r0;
+  const int64_t tstride = (int64_t)KB * n_pad * kI8Kb;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      unsigned word = 0;
+  for (int t = 0; t < kI8MaxMod; ++t) {   // unrolled: the moduli's scalar loads are issued up front
+    if (t < M.n_mod) {
+      const double ip = M.inv_p[t];
+      const unsigned pc = 256u - (unsigned)M.ip[t];
+      unsigned pk[2];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        // a / p is never within 1/(2p) of a half-integer (a integer, p odd), so rint of the
-        // rounded quotient is exact and the remainder is exact in FP64.
-        const double x = a[4 * q + e];
-        const double rr = fma(-p, rint(x * ip), x);
-        word |= ((unsigned)(int)rr & 0xffu) << (8 * e);
+      for (int h = 0; h < 2; ++h) {
+        unsigned word = 0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const unsigned q = low_word(fma(a[4 * h + e], ip, kBias52));
+          const unsigned b = mad_u24(q, pc, alo[4 * h + e]);
+          word |= (b & 0xffu) << (8 * e);
+        }
+        pk[h] = word;
       }
-      pk[q] = word;
+      *(uint2*)(dst + t * tstride) = make_uint2(pk[0], pk[1]);
     }
-    int8_t* dst = R + (((int64_t)t * KB + kb) * n_pad + f) * kI8Kb + r0;
-    *(i32x4*)dst = i32x4{(int)pk[0], (int)pk[1], (int)pk[2], (int)pk[3]};
   }
 }
 
@@ -306,18 +348,42 @@ hipError_t launch_i8_scale(const double* amp, int n_blocks, int n, const double*
   return hipGetLastError();
 }
 
+// c[f] = sum over kb of cpart[kb * n_pad + f], f < n: 64 features per workgroup, sixteen waves
+// each summing every sixteenth kb, the sixteen sums then added in a fixed order.
+__global__ __launch_bounds__(1024) void k_colsum_parts(const double* __restrict__ cpart, int KB, int n_pad, int n,
+                                                       double* __restrict__ c) {
+  __shared__ double red[16][64];
+  const int fl = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  const int f = blockIdx.x * 64 + fl;
+  double acc = 0.0;
+  if (f < n) {
+#pragma unroll 4
+    for (int kb = grp; kb < KB; kb += 16) acc += cpart[(int64_t)kb * n_pad + f];
+  }
+  red[grp][fl] = acc;
+  __syncthreads();
+  if (grp == 0 && f < n) {
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) t += red[q][fl];
+    c[f] = t;
+  }
+}
+
 hipError_t launch_i8_residues(const Geo& g, const double* rho, const double* inv_scale, const I8Moduli& M, int n_pad,
-                              int KB, int8_t* R, hipStream_t s) {
-  const dim3 grid(KB, n_pad / 64);
+                              int KB, int8_t* R, const double* Y, double* cpart, double* c, hipStream_t s) {
+  const dim3 grid(KB, n_pad / 32);
+  if ((Y == nullptr) != (cpart == nullptr) || (cpart == nullptr) != (c == nullptr)) return hipErrorInvalidValue;
   switch (g.d) {
 #define FLSQ_I8R(D) \
   case D:           \
-    hipLaunchKernelGGL(k_i8_residues<D>, grid, dim3(256), 0, s, g, rho, inv_scale, M, n_pad, KB, R); break;
+    hipLaunchKernelGGL(k_i8_residues<D>, grid, dim3(256), 0, s, g, rho, inv_scale, M, n_pad, KB, R, Y, cpart); break;
     FLSQ_I8R(1) FLSQ_I8R(2) FLSQ_I8R(3) FLSQ_I8R(4) FLSQ_I8R(5) FLSQ_I8R(6) FLSQ_I8R(7) FLSQ_I8R(8)
 #undef FLSQ_I8R
     default:
       return hipErrorInvalidValue;
   }
+  if (c) hipLaunchKernelGGL(k_colsum_parts, dim3((g.n + 63) / 64), dim3(1024), 0, s, cpart, KB, n_pad, g.n, c);
   return hipGetLastError();
 }
 

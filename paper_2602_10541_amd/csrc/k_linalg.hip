@@ -353,80 +353,97 @@ hipError_t launch_xpby_cols(const double* z, const ColScalars& b, double* p, int
   return hipGetLastError();
 }
 
-// Device-resident per-column scalars of the CG recurrences (the host reads them once per
-// iteration for its stopping decisions instead of round-tripping each one).
-__global__ void k_axpy_cols_dev(const double* __restrict__ a, const double* x, double* y, int64_t n, int K,
-                                double sign) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n * K) return;
-  y[e] = fma(sign * a[e % K], x[e], y[e]);
+// CG steps with their scalars kept on the device (the host reads them once per iteration for
+// its stopping decisions instead of round-tripping each one).  The step length of column k:
+// alpha_k = gam_k / (d1_k + mu d2_k) for active columns with both positive, else 0 (d2 nullable).
+__device__ __forceinline__ double cg_alpha_of(int k, const double* gam, const double* d1, const double* d2, double mu,
+                                              uint64_t active) {
+  const double dl = d1[k] + (d2 ? mu * d2[k] : 0.0);
+  return (((active >> k) & 1ull) && dl > 0.0 && gam[k] > 0.0) ? gam[k] / dl : 0.0;
 }
 
-hipError_t launch_axpy_cols_dev(const double* a, const double* x, double* y, int64_t n, int K, double sign,
-                                hipStream_t s) {
-  const int64_t tot = n * K;
-  if (tot == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_axpy_cols_dev, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, a, x, y, n, K, sign);
-  return hipGetLastError();
-}
-
-// Several y_q += sign_q a[c] x_q updates with one device scalar vector a (one launch; grid.y = q).
-__global__ void k_axpy_batch_dev(const double* __restrict__ a, AxpyBatch b) {
+// y_q += sign_q alpha_c x_q (grid.y = q) with alpha from the device dots; alpha_out receives the
+// step lengths for the host.  With keep given, the columns
+// of y_0 selected by keep_mask are first copied to keep: the best-iterate copy the host decided
+// after the previous step, taken before this step changes y_0.
+__global__ void k_cg_step(const double* __restrict__ gam, const double* __restrict__ d1, const double* d2, double mu,
+                          uint64_t active, double* __restrict__ alpha_out, AxpyBatch b, double* keep,
+                          uint64_t keep_mask) {
   const int q = blockIdx.y;
+  if (q == 0 && blockIdx.x == 0 && (int)threadIdx.x < b.K)
+    alpha_out[threadIdx.x] = cg_alpha_of(threadIdx.x, gam, d1, d2, mu, active);
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= b.n[q] * b.K) return;
-  b.y[q][e] = fma(b.sign[q] * a[e % b.K], b.x[q][e], b.y[q][e]);
+  const int k = (int)(e % b.K);
+  const double a = cg_alpha_of(k, gam, d1, d2, mu, active);
+  const double yo = b.y[q][e];
+  if (q == 0 && keep && ((keep_mask >> k) & 1ull)) keep[e] = yo;
+  b.y[q][e] = fma(b.sign[q] * a, b.x[q][e], yo);
 }
 
-hipError_t launch_axpy_batch_dev(const double* a, const AxpyBatch& b, hipStream_t s) {
-  if (b.count < 1 || b.count > kAxpyBatchMax || b.K < 1) return hipErrorInvalidValue;
+hipError_t launch_cg_step(const double* gam, const double* d1, const double* d2, double mu, uint64_t active,
+                          double* alpha_out, const AxpyBatch& b, double* keep, uint64_t keep_mask, hipStream_t s) {
+  if (b.count < 1 || b.count > kAxpyBatchMax || b.K < 1 || b.K > 64) return hipErrorInvalidValue;
   int64_t mx = 0;
   for (int q = 0; q < b.count; ++q) mx = std::max<int64_t>(mx, b.n[q] * b.K);
-  if (mx == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_axpy_batch_dev, dim3((unsigned)((mx + 255) / 256), b.count), dim3(256), 0, s, a, b);
+  const unsigned bx = (unsigned)std::max<int64_t>((mx + 255) / 256, 1);
+  hipLaunchKernelGGL(k_cg_step, dim3(bx, b.count), dim3(256), 0, s, gam, d1, d2, mu, active, alpha_out, b, keep,
+                     keep_mask);
   return hipGetLastError();
 }
 
-__global__ void k_xpby_cols_dev(const double* z, const double* __restrict__ b, double* p, int64_t n, int K) {
+// gam_new = g . z per column, beta = gam_new / gam_old (0 when gam_old <= 0), p = z + beta p.
+// Small vectors (n K <= kDotSmallMax): one workgroup does all three, with k_dot_small's
+// reduction order; larger ones take launch_dot_cols and one update launch.
+__global__ __launch_bounds__(kDotSmallWg) void k_cg_direction_small(const double* __restrict__ g,
+                                                                    const double* __restrict__ z, double* p, int64_t n,
+                                                                    int K, const double* __restrict__ gam_old,
+                                                                    double* __restrict__ gam_new) {
+  __shared__ double red[kDotSmallWg];
+  __shared__ double sbeta[64];
+  const int t = threadIdx.x;
+  int R = 1;
+  while (R * 2 * K <= kDotSmallWg) R *= 2;
+  const int c = t % K, r = t / K;
+  double s = 0.0;
+  if (r < R)
+    for (int64_t i = r; i < n; i += R) s = fma(g[i * K + c], z[i * K + c], s);
+  red[t] = s;
+  __syncthreads();
+  for (int h = R / 2; h > 0; h >>= 1) {
+    if (r < h) red[r * K + c] += red[(r + h) * K + c];
+    __syncthreads();
+  }
+  if (t < K) {
+    const double gn = red[t], go = gam_old[t];
+    gam_new[t] = gn;
+    sbeta[t] = go > 0.0 ? gn / go : 0.0;
+  }
+  __syncthreads();
+  for (int64_t e = t; e < n * K; e += kDotSmallWg) p[e] = fma(sbeta[e % K], p[e], z[e]);
+}
+
+__global__ void k_xpby_ratio(const double* __restrict__ z, const double* __restrict__ gam_new,
+                             const double* __restrict__ gam_old, double* p, int64_t n, int K) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n * K) return;
-  p[e] = fma(b[e % K], p[e], z[e]);
+  const int k = (int)(e % K);
+  const double go = gam_old[k];
+  const double beta = go > 0.0 ? gam_new[k] / go : 0.0;
+  p[e] = fma(beta, p[e], z[e]);
 }
 
-hipError_t launch_xpby_cols_dev(const double* z, const double* b, double* p, int64_t n, int K, hipStream_t s) {
-  const int64_t tot = n * K;
-  if (tot == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_xpby_cols_dev, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, z, b, p, n, K);
-  return hipGetLastError();
-}
-
-// alpha_k = gam_k / (d1_k + mu d2_k) for active columns with both positive, else 0 (d2 nullable).
-__global__ void k_cg_alpha(const double* gam, const double* d1, const double* d2, double mu, uint64_t active, int K,
-                           double* alpha) {
-  const int k = threadIdx.x;
-  if (k >= K) return;
-  const double dl = d1[k] + (d2 ? mu * d2[k] : 0.0);
-  alpha[k] = (((active >> k) & 1ull) && dl > 0.0 && gam[k] > 0.0) ? gam[k] / dl : 0.0;
-}
-
-// beta_k = gam_new_k / gam_k (0 when gam_k <= 0), then gam_k = gam_new_k.
-__global__ void k_cg_beta(const double* gam_new, double* gam, int K, double* beta) {
-  const int k = threadIdx.x;
-  if (k >= K) return;
-  beta[k] = gam[k] > 0.0 ? gam_new[k] / gam[k] : 0.0;
-  gam[k] = gam_new[k];
-}
-
-hipError_t launch_cg_alpha(const double* gam, const double* d1, const double* d2, double mu, uint64_t active, int K,
-                           double* alpha, hipStream_t s) {
+hipError_t launch_cg_direction(const double* g, const double* z, double* p, int64_t n, int K, const double* gam_old,
+                               double* gam_new, double* work, hipStream_t s) {
   if (K < 1 || K > 64) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(64), 0, s, gam, d1, d2, mu, active, K, alpha);
-  return hipGetLastError();
-}
-
-hipError_t launch_cg_beta(const double* gam_new, double* gam, int K, double* beta, hipStream_t s) {
-  if (K < 1 || K > 64) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(64), 0, s, gam_new, gam, K, beta);
+  if (n * K <= kDotSmallMax) {
+    hipLaunchKernelGGL(k_cg_direction_small, dim3(1), dim3(kDotSmallWg), 0, s, g, z, p, n, K, gam_old, gam_new);
+    return hipGetLastError();
+  }
+  hipError_t e = launch_dot_cols(g, z, n, K, gam_new, work, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_xpby_ratio, dim3((unsigned)((n * K + 255) / 256)), dim3(256), 0, s, z, gam_new, gam_old, p, n,
+                     K);
   return hipGetLastError();
 }
 

@@ -94,3 +94,42 @@ def test_bench_refuses_more_than_one_gpu():
     assert r.returncode == 2
     assert "one GPU" in r.stderr
     assert r.stdout.strip() == ""
+
+
+def test_int8_residue_byte_identity():
+    """The residue bytes of k_i8_residues (csrc/k_gram_i8.hip): for an integer a with
+    |a| <= 2^46 and each modulus p of the int8 CRT set, q = low word of fma(a, 1/p, 1.5 * 2^52)
+    and a_lo = low word of a + 1.5 * 2^52 give (a_lo + (256 - p) (q mod 2^24)) mod 256, which
+    must be the two's-complement byte of the balanced residue a - p rint(a / p).  The fma is
+    emulated exactly (one rounding of the exact rational), on random a and on the edge cases
+    (0, +-2^46, values next to multiples of p and to the half-way points)."""
+    import random
+    import struct
+    from fractions import Fraction
+    from pathlib import Path
+    src = (Path(__file__).resolve().parents[1] / "paper_2602_10541_amd" / "csrc" / "fastlsq.cpp").read_text()
+    moduli = [int(v) for v in re.search(r"const int list\[13\] = \{([0-9, ]+)\}", src).group(1).split(",")]
+    assert len(moduli) == 13
+    bias = 6755399441055744.0
+
+    def low_word(x):
+        return struct.unpack("<Q", struct.pack("<d", x))[0] & 0xffffffff
+
+    rng = random.Random(7)
+    lim = 1 << 46
+    values = [0, lim, -lim, lim - 1, -lim + 1] + [rng.randint(-lim, lim) for _ in range(600)]
+    for p in moduli:
+        for k in (1, 3, 12345, (lim // p) - 1):
+            for s in (-1, 1):
+                base = s * k * p
+                values += [base + (p - 1) // 2, base - (p - 1) // 2, base + (p + 1) // 2, base - (p + 1) // 2]
+    values = [v for v in values if abs(v) <= lim]
+    for p in moduli:
+        ip = 1.0 / p
+        for a in values:
+            q = low_word(float(Fraction(a) * Fraction(ip) + Fraction(bias)))
+            a_lo = low_word(float(Fraction(a) + Fraction(bias)))
+            got = (a_lo + (256 - p) * (q & 0xffffff)) & 0xff
+            r = a - p * round(Fraction(a, p))
+            assert 2 * abs(r) < p
+            assert got == r & 0xff, (p, a, got, r)
