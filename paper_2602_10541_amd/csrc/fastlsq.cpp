@@ -547,6 +547,9 @@ Err run_gram_i8(flsq_ctx* c, const System& s, const double* rho, double* G, int 
   if (P_pad > kI8MaxRows)
     return fail(FLSQ_EINVAL, "INT8_CRT Gram supports at most %lld rows (got %lld)", (long long)kI8MaxRows,
                 (long long)s.P);
+  if ((int64_t)s.n_blocks * s.n >= INT32_MAX)
+    return fail(FLSQ_EINVAL, "INT8_CRT Gram supports blocks x features below 2^31 (got %lld)",
+                (long long)s.n_blocks * s.n);
   const int KB = (int)(P_pad / KBR);
   const I8Moduli& M = i8_moduli();
   const int B = i8_bits(P_pad);
@@ -990,11 +993,11 @@ Err cgls_refine_op(flsq_ctx* c, const LsqOp& op, const double* Xi, double mu, co
   double *d_hh = dots + 5 * K, *d_uu = dots + 6 * K, *d_ss = dots + 7 * K, *d_xx = dots + 8 * K;
   double* d_gnew = dots + 9 * K;   // gam and gam_new trade places after every direction update
   double* d_start = dots + 10 * K;
-  if (want_grad0) CHECK_HIP(launch_dot_cols(g, g, n, K, d_start + 3 * K, dwork, st));
   ro->iters = 0;
   ro->converged = (max_iter == 0);
   if (max_iter == 0) {
     if (want_grad0) {
+      CHECK_HIP(launch_dot_cols(g, g, n, K, d_start + 3 * K, dwork, st));
       CHECK_ERR(host_cols(c, d_start + 3 * K, K, tmp));
       double m = 0;
       for (double v : tmp) m = std::max(m, std::sqrt(v));
@@ -1013,13 +1016,23 @@ Err cgls_refine_op(flsq_ctx* c, const LsqOp& op, const double* Xi, double mu, co
   double* Xbest;
   CHECK_ERR(ws_get(c, "cg_xbest", (size_t)n * K, &Xbest));
   CHECK_HIP(hipMemcpyAsync(Xbest, X, sizeof(double) * n * K, hipMemcpyDeviceToDevice, st));
-  CHECK_HIP(launch_dot_cols(Y, Y, P, K, d_start, dwork, st));
-  CHECK_HIP(launch_dot_cols(sres, sres, P, K, d_start + K, dwork, st));
-  CHECK_HIP(launch_dot_cols(X, X, n, K, d_start + 2 * K, dwork, st));
+  {
+    // starting values Y.Y | s.s | X.X | g.g in one batch
+    DotBatch db{};
+    db.K = K;
+    db.count = want_grad0 ? 4 : 3;
+    const double* v[4] = {Y, sres, X, g};
+    const int64_t len[4] = {P, P, n, n};
+    for (int b = 0; b < db.count; ++b) {
+      db.x[b] = db.y[b] = v[b];
+      db.n[b] = len[b];
+      db.out[b] = d_start + b * K;
+    }
+    CHECK_HIP(launch_dot_batch(db, dwork, st));
+  }
   ynorm.resize(K);
   CHECK_ERR(chol_solve(c, Xi, n, g, z, K));
-  CHECK_HIP(hipMemcpyAsync(p, z, sizeof(double) * n * K, hipMemcpyDeviceToDevice, st));
-  CHECK_HIP(launch_dot_cols(g, z, n, K, d_gam, dwork, st));
+  CHECK_HIP(launch_cg_direction(g, z, p, n, K, nullptr, d_gam, dwork, st));   // gam = g.z, p = z
   bool stalled_all = false;
   uint64_t keep_mask = 0;
   std::vector<double> hs(13 * K);
@@ -1878,8 +1891,7 @@ flsq_status flsq_factor_solve_normal(flsq_ctx* ctx, const flsq_factor* F, const 
     double *d_alpha = dots + K, *d_pap = dots + 3 * K, *d_xv0 = dots + 4 * K;
     double *d_xv = dots + 5 * K, *d_xr = dots + 6 * K, *d_gnew = dots + 7 * K;
     CHECK_ERR(chol_solve(ctx, F->Xinv.as<double>(), n, r, z, K));
-    CHECK_HIP(hipMemcpyAsync(p, z, sizeof(double) * n * K, hipMemcpyDeviceToDevice, st));
-    CHECK_HIP(launch_dot_cols(r, z, n, K, d_gam, dwork, st));
+    CHECK_HIP(launch_cg_direction(r, z, p, n, K, nullptr, d_gam, dwork, st));   // gam = r.z, p = z
     // Stop when the step's energy norm |alpha| (p^T M p)^{1/2} (M = G + mu I) is below tol
     // times the solution's, estimated by (out^T V)^{1/2}.  The energy functional
     // phi(x) = x^T M x / 2 - x^T V = -(x^T V + x^T r) / 2 decreases monotonically in exact
@@ -1888,8 +1900,18 @@ flsq_status flsq_factor_solve_normal(flsq_ctx* ctx, const flsq_factor* F, const 
     double* xbest;
     CHECK_ERR(ws_get(ctx, "pcg_xbest", (size_t)n * K, &xbest));
     CHECK_HIP(hipMemcpyAsync(xbest, out, sizeof(double) * n * K, hipMemcpyDeviceToDevice, st));
-    CHECK_HIP(launch_dot_cols(out, V, n, K, d_xv, dwork, st));
-    CHECK_HIP(launch_dot_cols(out, r, n, K, d_xr, dwork, st));
+    {
+      DotBatch db{};
+      db.K = K;
+      db.count = 2;
+      db.x[0] = db.x[1] = out;
+      db.y[0] = V;
+      db.y[1] = r;
+      db.n[0] = db.n[1] = n;
+      db.out[0] = d_xv;
+      db.out[1] = d_xr;
+      CHECK_HIP(launch_dot_batch(db, dwork, st));
+    }
     CHECK_ERR(host_cols(ctx, d_xv, 2 * K, tmp));
     std::vector<double> phibest(K), active(K, 1.0), improved(K, 0.0), relstep(K, 0.0), minstep(K, HUGE_VAL);
     std::vector<int> stagnant(K, 0);

@@ -30,7 +30,25 @@ constexpr int kMaxDim = 8;
 // evaluation error in double at most 1.9e-16 on [0, pi/2], as for the Taylor series to r^21
 // with two multiply-adds fewer.
 // ---------------------------------------------------------------------------------
-__device__ __forceinline__ double sin_f64(double x) {
+// The coefficients of g, highest degree first.
+struct SinPoly {
+  double c[8];
+};
+__device__ __forceinline__ SinPoly sin_poly() {
+  return SinPoly{{2.7314447669863995e-15, -7.643970296798572e-13, 1.6058977312464087e-10, -2.5052107616996182e-08,
+                  2.7557319219163234e-06, -0.00019841269841254974, 0.008333333333333316, -0.16666666666666666}};
+}
+// The same values, held in scalar registers: in straight-line code with many sines the compiler
+// would otherwise rebuild each 64-bit constant in vector registers at every use (two moves per
+// coefficient and sine).
+__device__ __forceinline__ SinPoly sin_poly_sgpr() {
+  SinPoly q = sin_poly();
+#pragma unroll
+  for (int i = 0; i < 8; ++i) asm volatile("" : "+s"(q.c[i]));
+  return q;
+}
+
+__device__ __forceinline__ double sin_f64(double x, const SinPoly& q) {
   const double kInvPi = 0.31830988618379067154;    // 1/pi rounded to double
   const double kPiA = 3.141592653589793116;        // pi rounded to double
   const double kPiB = 1.2246467991473532072e-16;   // pi - kPiA
@@ -38,17 +56,14 @@ __device__ __forceinline__ double sin_f64(double x) {
   double r = fma(-k, kPiA, x);
   r = fma(-k, kPiB, r);
   const double r2 = r * r;
-  double p = 2.7314447669863995e-15;
-  p = fma(p, r2, -7.643970296798572e-13);
-  p = fma(p, r2, 1.6058977312464087e-10);
-  p = fma(p, r2, -2.5052107616996182e-08);
-  p = fma(p, r2, 2.7557319219163234e-06);
-  p = fma(p, r2, -0.00019841269841254974);
-  p = fma(p, r2, 0.008333333333333316);
-  p = fma(p, r2, -0.16666666666666666);
+  double p = q.c[0];
+#pragma unroll
+  for (int i = 1; i < 8; ++i) p = fma(p, r2, q.c[i]);
   const double s = fma(r * r2, p, r);
   return (static_cast<int>(k) & 1) ? -s : s;   // |k| < 2^31 for |x| < 2^30: the conversion is exact
 }
+
+__device__ __forceinline__ double sin_f64(double x) { return sin_f64(x, sin_poly()); }
 
 // sin and cos together for |x| < 2^30: x = k pi/2 + r, |r| <= pi/4.
 // sin to r^17 (omitted (pi/4)^19/19! < 1e-19), cos to r^18 (omitted (pi/4)^20/20! < 1e-21).

@@ -304,8 +304,8 @@ hipError_t launch_select_cols(const double* src, double* dst, int64_t n, int K, 
 hipError_t launch_cg_step(const double* gam, const double* d1, const double* d2, double mu, uint64_t active,
                           double* alpha_out, const AxpyBatch& b, double* keep, uint64_t keep_mask, hipStream_t s);
 // gam_new = g . z per column (n x K row-major), p = z + (gam_new / gam_old) p (0 where
-// gam_old <= 0); work as for launch_dot_cols.  gam_old is only read: the caller alternates the
-// two buffers between iterations.  K <= 64.
+// gam_old <= 0), or p = z when gam_old is null; work as for launch_dot_cols.  gam_old is only
+// read: the caller alternates the two buffers between iterations.  K <= 64.
 hipError_t launch_cg_direction(const double* g, const double* z, double* p, int64_t n, int K, const double* gam_old,
                                double* gam_new, double* work, hipStream_t s);
 

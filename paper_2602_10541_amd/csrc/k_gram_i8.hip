@@ -89,7 +89,7 @@ __global__ __launch_bounds__(256) void k_i8_residues(Geo g, const double* rho, c
   __shared__ double sX[D][kI8Kb];
   __shared__ double sRho[kI8Kb];
   __shared__ double sY[kI8Kb];
-  __shared__ int sBlk[kI8Kb];
+  __shared__ int sOff[kI8Kb];   // the row's block offset blk * n into amp and ph, -1 past the rows
   const int kb = blockIdx.x;
   const int tid = threadIdx.x;
   const int64_t i0 = (int64_t)kb * kI8Kb;
@@ -101,9 +101,10 @@ __global__ __launch_bounds__(256) void k_i8_residues(Geo g, const double* rho, c
     const bool in = i0 + tid < g.P;
     sRho[tid] = (rho && in) ? rho[i0 + tid] : 0.0;
     sY[tid] = (Y && in) ? Y[i0 + tid] : 0.0;
-    sBlk[tid] = in ? g.row_block[i0 + tid] : -1;
+    sOff[tid] = in ? g.row_block[i0 + tid] * g.n : -1;   // n_blocks * n < 2^31 (checked by the host)
   }
   __syncthreads();
+  const SinPoly sp = sin_poly_sgpr();
   const int f = blockIdx.y * 32 + tid / 8;
   const int r0 = 8 * (tid % 8);
   const bool fvalid = f < g.n;
@@ -115,14 +116,16 @@ __global__ __launch_bounds__(256) void k_i8_residues(Geo g, const double* rho, c
   unsigned alo[8];
   double cy = 0.0;
   const int fc = min(f, g.n - 1);
+  const double* __restrict__ ph_f = g.ph + fc;
+  const double* __restrict__ amp_f = g.amp + fc;
 #pragma unroll
   for (int r = 0; r < 8; ++r) {   // branch-free: padded rows and features read a valid entry, then drop it
-    const int blk = sBlk[r0 + r];
-    const int64_t o = (int64_t)max(blk, 0) * g.n + fc;
-    double z = g.ph[o];
+    const int off = sOff[r0 + r];
+    const unsigned o = (unsigned)max(off, 0);
+    double z = ph_f[o];
 #pragma unroll
     for (int k = 0; k < D; ++k) z = fma(w[k], sX[k][r0 + r], z);
-    const double e = (fvalid && blk >= 0) ? (g.amp[o] + sRho[r0 + r]) * sin_f64(z) : 0.0;
+    const double e = (fvalid && off >= 0) ? (amp_f[o] + sRho[r0 + r]) * sin_f64(z, sp) : 0.0;
     cy = fma(e, sY[r0 + r], cy);
     const double v = rint(e * isc);
     a[r] = v;

@@ -392,9 +392,10 @@ hipError_t launch_cg_step(const double* gam, const double* d1, const double* d2,
   return hipGetLastError();
 }
 
-// gam_new = g . z per column, beta = gam_new / gam_old (0 when gam_old <= 0), p = z + beta p.
-// Small vectors (n K <= kDotSmallMax): one workgroup does all three, with k_dot_small's
-// reduction order; larger ones take launch_dot_cols and one update launch.
+// gam_new = g . z per column, beta = gam_new / gam_old (0 when gam_old <= 0), p = z + beta p;
+// with gam_old null, p = z (the first direction; p is not read).  Small vectors
+// (n K <= kDotSmallMax): one workgroup does all three, with k_dot_small's reduction order;
+// larger ones take launch_dot_cols and one update launch.
 __global__ __launch_bounds__(kDotSmallWg) void k_cg_direction_small(const double* __restrict__ g,
                                                                     const double* __restrict__ z, double* p, int64_t n,
                                                                     int K, const double* __restrict__ gam_old,
@@ -415,18 +416,25 @@ __global__ __launch_bounds__(kDotSmallWg) void k_cg_direction_small(const double
     __syncthreads();
   }
   if (t < K) {
-    const double gn = red[t], go = gam_old[t];
+    const double gn = red[t], go = gam_old ? gam_old[t] : 0.0;
     gam_new[t] = gn;
     sbeta[t] = go > 0.0 ? gn / go : 0.0;
   }
   __syncthreads();
-  for (int64_t e = t; e < n * K; e += kDotSmallWg) p[e] = fma(sbeta[e % K], p[e], z[e]);
+  if (gam_old)
+    for (int64_t e = t; e < n * K; e += kDotSmallWg) p[e] = fma(sbeta[e % K], p[e], z[e]);
+  else
+    for (int64_t e = t; e < n * K; e += kDotSmallWg) p[e] = z[e];
 }
 
 __global__ void k_xpby_ratio(const double* __restrict__ z, const double* __restrict__ gam_new,
                              const double* __restrict__ gam_old, double* p, int64_t n, int K) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n * K) return;
+  if (!gam_old) {
+    p[e] = z[e];
+    return;
+  }
   const int k = (int)(e % K);
   const double go = gam_old[k];
   const double beta = go > 0.0 ? gam_new[k] / go : 0.0;

@@ -381,7 +381,7 @@ def test_kernel_limit_has_half_factor():
 
 
 def test_device_sine_polynomial_constants():
-    """The FP64 sine polynomial in csrc/flsq_device.h (sin_f64), read from the header and
+    """The FP64 sine polynomial in csrc/flsq_device.h (sin_poly, used by sin_f64), read from the header and
     evaluated in double as the kernel does (Horner in r^2, then r + (r r^2) p): within 2.5e-16
     of math.sin on the reduced interval [-pi/2, pi/2]; its two lowest coefficients are the
     Taylor ones to rounding (-1/3!, 1/5!), as a fit of (sin r - r) / r^3 must give."""
@@ -389,8 +389,8 @@ def test_device_sine_polynomial_constants():
     import re
     from pathlib import Path
     src = (Path(__file__).resolve().parents[1] / "paper_2602_10541_amd" / "csrc" / "flsq_device.h").read_text()
-    body = src[src.index("double sin_f64(double x)"):src.index("void sincos_f64(")]
-    coef = [float(m) for m in re.findall(r"p = (?:fma\(p, r2, )?(-?[0-9.]+e?-?[0-9]*)\)?;", body)]
+    body = src[src.index("SinPoly sin_poly()"):src.index("SinPoly sin_poly_sgpr()")]
+    coef = [float(m) for m in re.findall(r"(-?[0-9]+\.[0-9]+(?:e-?[0-9]+)?)", body)]
     assert len(coef) == 8, coef
     assert abs(coef[-1] + 1 / 6) < 1e-16 and abs(coef[-2] - 1 / 120) < 1e-15
     worst = 0.0
