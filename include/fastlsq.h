@@ -129,7 +129,9 @@ typedef struct {
     double grad_norm0;      /* ||A^T (rhs - A beta) - mu beta|| after the Cholesky solve */
     double grad_norm;       /* same, at the returned beta (when opts.report_grad is set) */
     double last_step_rel;   /* relative size of the last refinement step, in the measure refine_tol uses */
-    double t_gram_ms, t_chol_ms, t_refine_ms, t_total_ms;
+    double t_gram_ms, t_chol_ms, t_refine_ms, t_total_ms; /* phases: the Gram phase's device time (HIP
+                                events around its kernels), the factorisation from the Gram's end to the
+                                inverse factor (host clock), the refinement and the whole call */
     double t_gram_kernel_ms; /* the matrix-core Gram kernel alone (HIP events on the stream): the fused
                                 assembly + Gram kernel for FP64 / FP32, the int8 tile kernel for INT8_CRT */
     int32_t second_pass;     /* 1 if the factor was refined by the second pass (opts.second_pass) */

@@ -162,6 +162,7 @@ struct flsq_ctx {
   std::map<std::string, DevBuf> ws;
   System sys;                        // cached system of the last solve_linear / gram / newton call
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipEvent_t ev_g0 = nullptr, ev_g1 = nullptr;   // around a solve's whole Gram phase
   double last_gram_kernel_ms = 0.0;  // duration of the last fused Gram kernel (HIP events on the stream)
   void* pinned = nullptr;            // pinned host staging for the small per-iteration read-backs
   size_t pinned_bytes = 0;
@@ -329,10 +330,9 @@ Err check_finite_many(flsq_ctx* c, std::initializer_list<FiniteItem> items) {
   int* flags;
   const int m = (int)items.size();
   CHECK_ERR(ws_get(c, "nf_flag", (size_t)m, &flags));
-  CHECK_HIP(hipMemsetAsync(flags, 0, sizeof(int) * m, c->stream));
   int k = 0;
   for (const FiniteItem& it : items) {
-    if (it.p && it.n > 0) CHECK_HIP(launch_count_nonfinite(it.p, it.n, flags + k, c->stream));
+    CHECK_HIP(launch_nonfinite_flag(it.p, it.p ? it.n : 0, flags + k, c->stream));
     ++k;
   }
   int h[8] = {0};
@@ -690,6 +690,8 @@ Err cholesky_inv(flsq_ctx* c, double* G, double* X, int n, const double* d, int*
       k0 += kNb;
     }
   }
+  // X = D W^T is queued ahead of the status read; the kernel leaves X alone after a failed pivot
+  CHECK_HIP(launch_inv_transpose(W, d, n, info, X, st));
   unsigned char hbuf[2 * sizeof(int) + 64];
   if (extra > 64) return fail(FLSQ_EINVAL, "internal: status read-back too long");
   CHECK_ERR(read_back(c, hbuf, info, 2 * sizeof(int) + extra));
@@ -698,7 +700,6 @@ Err cholesky_inv(flsq_ctx* c, double* G, double* X, int n, const double* d, int*
   if (extra) memcpy(host_extra, hbuf + sizeof hinfo, extra);
   *info_host = hinfo[0];
   *boosted_host = hinfo[1];
-  if (hinfo[0] == 0) CHECK_HIP(launch_inv_transpose(W, d, n, X, st));
   return ok();
 }
 
@@ -1383,22 +1384,26 @@ Err gram_and_factor(flsq_ctx* c, const System& s, const double* rho, const Solve
   CHECK_ERR(ws_get(c, "Ufac", (size_t)n * n, &U));
   const double t0 = now_ms();
   const bool fold_c = sp.prec == FLSQ_PREC_INT8_CRT && Y1 && c1;
+  // No host wait between the Gram and the factorisation: their kernels queue back to back, and
+  // the first wait is the factorisation's status read (the phase times come from events).
+  CHECK_HIP(hipEventRecord(c->ev_g0, c->stream));
   if (fold_c)
     CHECK_ERR(run_gram_i8(c, s, rho, G, 0, 0.0, Y1, c1));
   else
     CHECK_ERR(run_gram(c, s, sp.prec, rho, G, 0, 0.0));
+  CHECK_HIP(hipEventRecord(c->ev_g1, c->stream));
   if (c1_formed) *c1_formed = fold_c;
-  CHECK_HIP(hipStreamSynchronize(c->stream));
-  const double t1 = now_ms();
-  float kms = 0.f;
-  CHECK_HIP(hipEventElapsedTime(&kms, c->ev0, c->ev1));
-  c->last_gram_kernel_ms = kms;
   double shift = 0.0;
   int retries = 0;
   const bool exact_gram = sp.prec == FLSQ_PREC_FP64 || sp.prec == FLSQ_PREC_INT8_CRT;
   const double rel0 = exact_gram ? sp.shift_rel : (sp.shift_rel > 0.0 ? sp.shift_rel : 1e-6);
   int boosted = 0, recalled = 0;
   CHECK_ERR(factor_with_retries(c, G, U, Xi, n, sp.mu, rel0, &shift, &retries, sp.pivot_boost, &boosted, &recalled));
+  // the status read waited for the Gram's events
+  float gms = 0.f, kms = 0.f;
+  CHECK_HIP(hipEventElapsedTime(&gms, c->ev_g0, c->ev_g1));
+  CHECK_HIP(hipEventElapsedTime(&kms, c->ev0, c->ev1));
+  c->last_gram_kernel_ms = kms;
   const double t2a = now_ms();
   bool second = false;
   // a recalled shift counts as the retries it skipped (the same factor, so the same decision)
@@ -1417,8 +1422,8 @@ Err gram_and_factor(flsq_ctx* c, const System& s, const double* rho, const Solve
   CHECK_HIP(hipStreamSynchronize(c->stream));   // the inverse factor's kernels belong to this phase
   const double t2 = now_ms();
   if (info) {
-    info->t_gram_ms = t1 - t0;
-    info->t_chol_ms = t2 - t1;
+    info->t_gram_ms = gms;
+    info->t_chol_ms = std::max(t2 - t0 - gms, 0.0);
     info->shift = shift;
     info->chol_retries = retries;
     info->boosted_pivots = boosted;
@@ -1511,7 +1516,8 @@ Err solve_on_system(flsq_ctx* c, const System& s, const double* rho, const Solve
   };
   CHECK_ERR(refine_lazy(c, PassOp(s, rho), sp, lazy, make_A, Xi, Yw, K, X, info != nullptr,
                         info != nullptr && sp.report_grad, &ro, &second, &t_second));
-  CHECK_HIP(hipStreamSynchronize(c->stream));
+  // no wait here: the refinement's last read-back waited for its passes, and the best-iterate
+  // copies queued after it complete before the caller's next read (every caller ends in one)
   const double t2 = now_ms();
   if (info) {
     info->refine_iters = ro.iters;
@@ -1692,9 +1698,10 @@ flsq_status flsq_create(flsq_ctx** ctx, int device, void* hip_stream) {
   if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
     c->n_cu = prop.multiProcessorCount;
   if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
+      hipEventCreate(&c->ev_g0) != hipSuccess || hipEventCreate(&c->ev_g1) != hipSuccess ||
       scratch_address(device, &c->scratch) != hipSuccess) {
-    if (c->ev0) (void)hipEventDestroy(c->ev0);
-    if (c->ev1) (void)hipEventDestroy(c->ev1);
+    for (hipEvent_t e : {c->ev0, c->ev1, c->ev_g0, c->ev_g1})
+      if (e) (void)hipEventDestroy(e);
     delete c;
     return FLSQ_EHIP;
   }
@@ -1706,8 +1713,8 @@ void flsq_destroy(flsq_ctx* ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
-  if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
-  if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+  for (hipEvent_t e : {ctx->ev0, ctx->ev1, ctx->ev_g0, ctx->ev_g1})
+    if (e) (void)hipEventDestroy(e);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   if (ctx->up) (void)hipHostFree(ctx->up);
   delete ctx->aux_factor;

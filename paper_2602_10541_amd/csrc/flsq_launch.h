@@ -207,7 +207,8 @@ hipError_t launch_potrf(double* G, int n, int k0, int* info, double boost, int* 
 hipError_t launch_trsm_row(double* G, double* W, int n, int k0, const int* info, hipStream_t s);
 hipError_t launch_syrk_potrf(double* G, double* W, int n, int k0, int kr, int row_lim, int* info, double boost,
                              int* nboost, hipStream_t s);
-hipError_t launch_inv_transpose(const double* W, const double* d, int n, double* X, hipStream_t s);
+// (nothing is written when *info, the factorisation's device status, is nonzero)
+hipError_t launch_inv_transpose(const double* W, const double* d, int n, const int* info, double* X, hipStream_t s);
 // dst = D src D + (diag_add + mu D^2) on the diagonal (upper triangle), D = diag(src)^{-1/2} -> d.
 hipError_t launch_equilibrate(const double* G, double* dst, int n, double* d, double mu, double diag_add,
                               hipStream_t s);
@@ -295,6 +296,8 @@ hipError_t launch_axpy_cols(const ColScalars& a, const double* x, double* y, int
 // p[i][c] = z[i][c] + b[c] * p[i][c]
 hipError_t launch_xpby_cols(const double* z, const ColScalars& b, double* p, int64_t n, int K, hipStream_t s);
 hipError_t launch_count_nonfinite(const double* x, int64_t n, int* flag, hipStream_t s);
+// *flag = 1 if x[0 .. n) holds a NaN or Inf, else 0 (sets the flag itself; no clearing needed)
+hipError_t launch_nonfinite_flag(const double* x, int64_t n, int* flag, hipStream_t s);
 // dst[i][c] = src[i][c] for the columns c whose bit is set in mask
 hipError_t launch_select_cols(const double* src, double* dst, int64_t n, int K, uint64_t mask, hipStream_t s);
 // CG steps with device-resident scalars.  alpha_k = gam_k / (d1_k + mu d2_k) (columns set in

@@ -451,10 +451,12 @@ __global__ __launch_bounds__(256, 2) void k_syrk_potrf(double* G, double* W, int
 }
 
 // X = D W^T (X[i][j] = d_i W[j][i] for j >= i, 0 below the diagonal; d nullable = ones):
-// 64 x 64 tiles through LDS, both sides read and written along rows.
+// 64 x 64 tiles through LDS, both sides read and written along rows.  Nothing is written when
+// the factorisation's status (*info) reports a failed pivot.
 __global__ __launch_bounds__(256) void k_inv_transpose(const double* __restrict__ W, const double* __restrict__ d,
-                                                       int n, double* __restrict__ X) {
+                                                       int n, const int* __restrict__ info, double* __restrict__ X) {
   __shared__ double T[64][65];
+  if (*info != 0) return;
   const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;   // the tile X[i0.., j0..]
   const int t = threadIdx.x, c = t & 63;
   if (j0 + 63 < i0) {   // entirely below the diagonal
@@ -524,10 +526,10 @@ hipError_t launch_syrk_potrf(double* G, double* W, int n, int k0, int kr, int ro
   return hipGetLastError();
 }
 
-hipError_t launch_inv_transpose(const double* W, const double* d, int n, double* X, hipStream_t s) {
+hipError_t launch_inv_transpose(const double* W, const double* d, int n, const int* info, double* X, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const unsigned nb = (unsigned)((n + 63) / 64);
-  hipLaunchKernelGGL(k_inv_transpose, dim3(nb, nb), dim3(256), 0, s, W, d, n, X);
+  hipLaunchKernelGGL(k_inv_transpose, dim3(nb, nb), dim3(256), 0, s, W, d, n, info, X);
   return hipGetLastError();
 }
 

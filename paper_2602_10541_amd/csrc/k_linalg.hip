@@ -480,4 +480,24 @@ hipError_t launch_count_nonfinite(const double* x, int64_t n, int* flag, hipStre
   return hipGetLastError();
 }
 
+// *flag = 1 if any of x[0 .. n) is NaN or Inf, else 0 (one workgroup: short arrays, no clearing
+// launch needed).
+constexpr int64_t kFiniteFlagMax = 1 << 16;
+__global__ __launch_bounds__(1024) void k_finite_flag(const double* __restrict__ x, int64_t n, int* __restrict__ flag) {
+  int bad = 0;
+  for (int64_t i = threadIdx.x; i < n; i += 1024) bad |= !isfinite(x[i]);
+  bad = __syncthreads_or(bad);
+  if (threadIdx.x == 0) *flag = bad ? 1 : 0;
+}
+
+hipError_t launch_nonfinite_flag(const double* x, int64_t n, int* flag, hipStream_t s) {
+  if (n <= kFiniteFlagMax) {
+    hipLaunchKernelGGL(k_finite_flag, dim3(1), dim3(1024), 0, s, x, n, flag);
+    return hipGetLastError();
+  }
+  hipError_t e = hipMemsetAsync(flag, 0, sizeof(int), s);
+  if (e != hipSuccess) return e;
+  return launch_count_nonfinite(x, n, flag, s);
+}
+
 }  // namespace flsq
