@@ -329,18 +329,24 @@ struct FiniteItem {
 Err check_finite_many(flsq_ctx* c, std::initializer_list<FiniteItem> items) {
   int* flags;
   const int m = (int)items.size();
-  CHECK_ERR(ws_get(c, "nf_flag", (size_t)m, &flags));
+  if (m > kFiniteBatchMax) return fail(FLSQ_EINVAL, "internal: too many finiteness checks");
+  FiniteBatch fb{};
+  fb.count = m;
   int k = 0;
   for (const FiniteItem& it : items) {
-    CHECK_HIP(launch_nonfinite_flag(it.p, it.p ? it.n : 0, flags + k, c->stream));
+    fb.p[k] = it.n > 0 ? it.p : nullptr;
+    fb.n[k] = it.n;
     ++k;
   }
-  int h[8] = {0};
-  if (m > 8) return fail(FLSQ_EINVAL, "internal: too many finiteness checks");
-  CHECK_ERR(read_back(c, h, flags, sizeof(int) * m));
+  const int wgs = finite_batch_wgs(fb);
+  CHECK_ERR(ws_get(c, "nf_flag", (size_t)kFiniteBatchMax * kFiniteBatchWgs, &flags));
+  CHECK_HIP(launch_finite_batch(fb, flags, c->stream));
+  int h[kFiniteBatchMax * kFiniteBatchWgs];
+  CHECK_ERR(read_back(c, h, flags, sizeof(int) * m * wgs));
   k = 0;
   for (const FiniteItem& it : items) {
-    if (h[k]) return fail(FLSQ_ENONFINITE, "%s contains NaN or Inf", it.what);
+    for (int w = 0; w < wgs; ++w)
+      if (h[k * wgs + w]) return fail(FLSQ_ENONFINITE, "%s contains NaN or Inf", it.what);
     ++k;
   }
   return ok();
@@ -423,14 +429,21 @@ Err build_system(flsq_ctx* c, System& s, const flsq_basis* basis, const flsq_row
     CHECK_HIP(launch_prep_block(op, r.weight, s.norm, d, n, basis->W, basis->b, s.amp.as<double>() + (int64_t)i * n,
                                 s.ph.as<double>() + (int64_t)i * n, s.amp32.as<float>() + (int64_t)i * n,
                                 s.ph32.as<float>() + (int64_t)i * n, st));
-    if (r.n_rows > 0) {
-      CHECK_HIP(launch_transpose(r.x, r.n_rows, d, s.Xt.as<double>() + s.row0[i], s.Xt32.as<float>() + s.row0[i], P,
-                                 st));
-      CHECK_HIP(launch_fill_i32(s.row_block.as<int32_t>() + s.row0[i], r.n_rows, i, st));
-      CHECK_HIP(hipMemcpyAsync(s.Xrm.as<double>() + s.row0[i] * d, r.x, sizeof(double) * d * r.n_rows,
-                               hipMemcpyDeviceToDevice, st));
-      CHECK_HIP(launch_scale_copy(r.rhs, s.rhs_w.as<double>() + s.row0[i], r.n_rows, r.weight, st));  // NULL -> 0
+  }
+  for (int b0 = 0; b0 < n_blocks; b0 += kRowStageMax) {   // the rows of all blocks, a group per launch
+    RowStage rs{};
+    rs.block0 = b0;
+    rs.count = std::min(kRowStageMax, n_blocks - b0);
+    for (int b = 0; b < rs.count; ++b) {
+      const flsq_rows& r = blocks[b0 + b];
+      rs.x[b] = r.x;
+      rs.rhs[b] = r.rhs;
+      rs.weight[b] = r.weight;
+      rs.row0[b] = s.row0[b0 + b];
+      rs.rows[b] = r.n_rows;
     }
+    CHECK_HIP(launch_stage_rows(rs, d, P, s.Xt.as<double>(), s.Xt32.as<float>(), s.Xrm.as<double>(),
+                                s.row_block.as<int32_t>(), s.rhs_w.as<double>(), st));
   }
   CHECK_HIP(s.frec.ensure(sizeof(double) * n_blocks * n * frec_stride(d)));
   CHECK_HIP(launch_pack_features(s.Wrm.as<double>(), s.amp.as<double>(), s.ph.as<double>(), n_blocks, n, d,

@@ -17,6 +17,20 @@ struct OpTerms {
 hipError_t launch_prep_block(const OpTerms& op, double weight, double norm, int d, int n, const double* W,
                              const double* b, double* amp, double* ph, float* amp32, float* ph32,
                              hipStream_t s);
+// Rows of up to kRowStageMax blocks (block0 + b is the global index of group member b):
+// Xt / Xt32 (d x P), Xrm (P x d), row_block and rhs_w = weight * rhs (0 for a NULL rhs).
+constexpr int kRowStageMax = 16;
+struct RowStage {
+  const double* x[kRowStageMax];     // n_rows x d row-major
+  const double* rhs[kRowStageMax];   // nullable
+  double weight[kRowStageMax];
+  int64_t row0[kRowStageMax];
+  int64_t rows[kRowStageMax];
+  int block0;
+  int count;
+};
+hipError_t launch_stage_rows(const RowStage& rs, int d, int64_t P, double* Xt, float* Xt32, double* Xrm,
+                             int32_t* row_block, double* rhs_w, hipStream_t s);
 hipError_t launch_transpose(const double* X, int64_t rows, int d, double* Xt, float* Xt32, int64_t ld_out,
                             hipStream_t s);
 hipError_t launch_pack_features(const double* Wrm, const double* amp, const double* ph, int n_blocks, int n, int d,
@@ -296,8 +310,18 @@ hipError_t launch_axpy_cols(const ColScalars& a, const double* x, double* y, int
 // p[i][c] = z[i][c] + b[c] * p[i][c]
 hipError_t launch_xpby_cols(const double* z, const ColScalars& b, double* p, int64_t n, int K, hipStream_t s);
 hipError_t launch_count_nonfinite(const double* x, int64_t n, int* flag, hipStream_t s);
-// *flag = 1 if x[0 .. n) holds a NaN or Inf, else 0 (sets the flag itself; no clearing needed)
-hipError_t launch_nonfinite_flag(const double* x, int64_t n, int* flag, hipStream_t s);
+// NaN / Inf scans of several arrays in one launch: flags[q * wgs + w] for item q and its
+// workgroups w < wgs = finite_batch_wgs(fb) (each written, 0 or 1, so nothing needs clearing;
+// an item is bad if any of its flags is).
+constexpr int kFiniteBatchMax = 8;
+constexpr int kFiniteBatchWgs = 64;
+struct FiniteBatch {
+  const double* p[kFiniteBatchMax];   // nullable: no entries
+  int64_t n[kFiniteBatchMax];
+  int count;
+};
+int finite_batch_wgs(const FiniteBatch& fb);
+hipError_t launch_finite_batch(const FiniteBatch& fb, int* flags, hipStream_t s);
 // dst[i][c] = src[i][c] for the columns c whose bit is set in mask
 hipError_t launch_select_cols(const double* src, double* dst, int64_t n, int K, uint64_t mask, hipStream_t s);
 // CG steps with device-resident scalars.  alpha_k = gam_k / (d1_k + mu d2_k) (columns set in

@@ -480,24 +480,31 @@ hipError_t launch_count_nonfinite(const double* x, int64_t n, int* flag, hipStre
   return hipGetLastError();
 }
 
-// *flag = 1 if any of x[0 .. n) is NaN or Inf, else 0 (one workgroup: short arrays, no clearing
-// launch needed).
-constexpr int64_t kFiniteFlagMax = 1 << 16;
-__global__ __launch_bounds__(1024) void k_finite_flag(const double* __restrict__ x, int64_t n, int* __restrict__ flag) {
+// NaN / Inf scan of several arrays in one launch: workgroup w of item q (grid.y) strides over
+// the item's entries and writes flags[q * wgs + w] (0 or 1) itself, so nothing needs clearing.
+__global__ __launch_bounds__(256) void k_finite_batch(FiniteBatch fb, int wgs, int* __restrict__ flags) {
+  const int q = blockIdx.y, w = blockIdx.x;
+  const double* __restrict__ x = fb.p[q];
+  const int64_t n = x ? fb.n[q] : 0;
   int bad = 0;
-  for (int64_t i = threadIdx.x; i < n; i += 1024) bad |= !isfinite(x[i]);
+  for (int64_t i = (int64_t)w * 256 + threadIdx.x; i < n; i += (int64_t)wgs * 256) bad |= !isfinite(x[i]);
   bad = __syncthreads_or(bad);
-  if (threadIdx.x == 0) *flag = bad ? 1 : 0;
+  if (threadIdx.x == 0) flags[q * wgs + w] = bad ? 1 : 0;
 }
 
-hipError_t launch_nonfinite_flag(const double* x, int64_t n, int* flag, hipStream_t s) {
-  if (n <= kFiniteFlagMax) {
-    hipLaunchKernelGGL(k_finite_flag, dim3(1), dim3(1024), 0, s, x, n, flag);
-    return hipGetLastError();
-  }
-  hipError_t e = hipMemsetAsync(flag, 0, sizeof(int), s);
-  if (e != hipSuccess) return e;
-  return launch_count_nonfinite(x, n, flag, s);
+int finite_batch_wgs(const FiniteBatch& fb) {
+  int64_t mx = 1;
+  for (int q = 0; q < fb.count; ++q)
+    if (fb.p[q]) mx = std::max<int64_t>(mx, (fb.n[q] + 255) / 256);
+  return (int)std::min<int64_t>(mx, kFiniteBatchWgs);
 }
+
+hipError_t launch_finite_batch(const FiniteBatch& fb, int* flags, hipStream_t s) {
+  if (fb.count < 1 || fb.count > kFiniteBatchMax) return hipErrorInvalidValue;
+  const int wgs = finite_batch_wgs(fb);
+  hipLaunchKernelGGL(k_finite_batch, dim3(wgs, fb.count), dim3(256), 0, s, fb, wgs, flags);
+  return hipGetLastError();
+}
+
 
 }  // namespace flsq

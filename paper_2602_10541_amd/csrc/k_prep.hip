@@ -2,6 +2,8 @@
 #include "flsq_device.h"
 #include "flsq_launch.h"
 
+#include <algorithm>
+
 namespace flsq {
 
 // Per feature j of one row block with weight w and operator sum_t c_t D^{alpha_t}:
@@ -96,6 +98,37 @@ __global__ void k_scale_copy(const double* src, double* dst, int64_t n, double s
 hipError_t launch_scale_copy(const double* src, double* dst, int64_t n, double scale, hipStream_t s) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_scale_copy, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src, dst, n, scale);
+  return hipGetLastError();
+}
+
+// The rows of up to kRowStageMax blocks in one launch (grid.y = block of the group): the
+// transposed points in FP64 and FP32, the row-major copy, each row's block index and the
+// weighted right-hand side (0 where a block has none).
+__global__ void k_stage_rows(RowStage rs, int d, int64_t P, double* __restrict__ Xt, float* __restrict__ Xt32,
+                             double* __restrict__ Xrm, int32_t* __restrict__ row_block, double* __restrict__ rhs_w) {
+  const int b = blockIdx.y;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= rs.rows[b]) return;
+  const int64_t g = rs.row0[b] + i;
+  const double* __restrict__ x = rs.x[b];
+  for (int k = 0; k < d; ++k) {
+    const double v = x[i * d + k];
+    Xt[(int64_t)k * P + g] = v;
+    Xt32[(int64_t)k * P + g] = (float)v;
+    Xrm[g * d + k] = v;
+  }
+  row_block[g] = rs.block0 + b;
+  rhs_w[g] = rs.rhs[b] ? rs.weight[b] * rs.rhs[b][i] : 0.0;
+}
+
+hipError_t launch_stage_rows(const RowStage& rs, int d, int64_t P, double* Xt, float* Xt32, double* Xrm,
+                             int32_t* row_block, double* rhs_w, hipStream_t s) {
+  if (rs.count < 1 || rs.count > kRowStageMax) return hipErrorInvalidValue;
+  int64_t mx = 0;
+  for (int b = 0; b < rs.count; ++b) mx = std::max(mx, rs.rows[b]);
+  if (mx == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_stage_rows, dim3((unsigned)((mx + 255) / 256), rs.count), dim3(256), 0, s, rs, d, P, Xt, Xt32,
+                     Xrm, row_block, rhs_w);
   return hipGetLastError();
 }
 
