@@ -1053,46 +1053,70 @@ Err cgls_refine_op(flsq_ctx* c, const LsqOp& op, const double* Xi, double mu, co
   for (int it = 0; it < max_iter; ++it) {
     // q = A p ; delta = ||q||^2 + mu ||p||^2 ; hq = H p ; alpha = gam / delta
     CHECK_ERR(op.apply(c, p, K, nullptr, 1.0, 0.0, q, hq));
+    AxpyBatch ab{};
+    ab.K = K;
+    ab.count = track_u ? 3 : 2;
+    ab.x[0] = p;
+    ab.y[0] = X;
+    ab.n[0] = n;
+    ab.sign[0] = 1.0;
+    ab.x[1] = q;
+    ab.y[1] = sres;
+    ab.n[1] = P;
+    ab.sign[1] = -1.0;
+    ab.x[2] = hq;
+    ab.y[2] = uu;
+    ab.n[2] = P;
+    ab.sign[2] = 1.0;
+    CgStepSmall cs{};
     {
-      DotBatch db{};
-      db.K = K;
-      auto add = [&](const double* a, int64_t len, double* o) {
-        db.x[db.count] = a;
-        db.y[db.count] = a;
-        db.n[db.count] = len;
-        db.out[db.count] = o;
-        ++db.count;
-      };
-      add(q, P, d_qq);
-      add(p, n, d_pp);
-      if (track_u) {
-        add(hq, P, d_hh);
-        add(uu, P, d_uu);
+      const double* pre[4] = {q, p, hq, uu};
+      const int64_t pre_n[4] = {P, n, P, P};
+      double* pre_out[4] = {d_qq, d_pp, d_hh, d_uu};
+      cs.n_pre = track_u ? 4 : 2;
+      for (int b = 0; b < cs.n_pre; ++b) {
+        cs.pre[b] = pre[b];
+        cs.pre_n[b] = pre_n[b];
+        cs.pre_out[b] = pre_out[b];
       }
-      CHECK_HIP(launch_dot_batch(db, dwork, st));
+      cs.n_post = 2;
+      cs.post[0] = sres;
+      cs.post_n[0] = P;
+      cs.post_out[0] = d_ss;
+      cs.post[1] = X;
+      cs.post_n[1] = n;
+      cs.post_out[1] = d_xx;
+      cs.gam = d_gam;
+      cs.d1 = d_qq;
+      cs.d2 = d_pp;
+      cs.mu = mu;
+      cs.active = col_mask(active);
+      cs.alpha_out = d_alpha;
+      cs.step = ab;
+      cs.keep = Xbest;
+      cs.keep_mask = keep_mask;
+      cs.K = K;
     }
-    {
+    if (cg_step_small_fits(cs)) {
+      // small systems: the dots, the step and the dots after it in one workgroup
+      CHECK_HIP(launch_cg_step_small(cs, st));
+      keep_mask = 0;
+    } else {
+      {
+        DotBatch db{};
+        db.K = K;
+        for (int b = 0; b < cs.n_pre; ++b) {
+          db.x[b] = db.y[b] = cs.pre[b];
+          db.n[b] = cs.pre_n[b];
+          db.out[b] = cs.pre_out[b];
+        }
+        db.count = cs.n_pre;
+        CHECK_HIP(launch_dot_batch(db, dwork, st));
+      }
       // alpha = gam / delta and the step; X's columns improved by the previous step go to Xbest first
-      AxpyBatch ab{};
-      ab.K = K;
-      ab.count = track_u ? 3 : 2;
-      ab.x[0] = p;
-      ab.y[0] = X;
-      ab.n[0] = n;
-      ab.sign[0] = 1.0;
-      ab.x[1] = q;
-      ab.y[1] = sres;
-      ab.n[1] = P;
-      ab.sign[1] = -1.0;
-      ab.x[2] = hq;
-      ab.y[2] = uu;
-      ab.n[2] = P;
-      ab.sign[2] = 1.0;
       CHECK_HIP(launch_cg_step(d_gam, d_qq, d_pp, mu, col_mask(active), d_alpha, ab, Xbest, keep_mask, st));
       keep_mask = 0;
-    }
-    // objective after the step
-    {
+      // objective after the step
       DotBatch db{};
       db.K = K;
       db.count = 2;

@@ -330,6 +330,30 @@ hipError_t launch_select_cols(const double* src, double* dst, int64_t n, int K, 
 // keep_mask are copied to keep before the update.  K <= 64.
 hipError_t launch_cg_step(const double* gam, const double* d1, const double* d2, double mu, uint64_t active,
                           double* alpha_out, const AxpyBatch& b, double* keep, uint64_t keep_mask, hipStream_t s);
+// A whole CG step of a small system in one workgroup (every vector at most 32768 entries, K <= 64):
+// the dots pre[q] . pre[q] -> pre_out[q] (q < n_pre <= 4), alpha as launch_cg_step (to
+// alpha_out), the batch's updates with the best-iterate copy into keep, then the dots
+// post[q] . post[q] -> post_out[q] (q < n_post <= 2); each dot in k_dot_small's order.
+struct CgStepSmall {
+  const double* pre[4];
+  int64_t pre_n[4];
+  double* pre_out[4];
+  int n_pre;
+  const double* post[2];
+  int64_t post_n[2];
+  double* post_out[2];
+  int n_post;
+  const double *gam, *d1, *d2;
+  double mu;
+  uint64_t active;
+  double* alpha_out;
+  AxpyBatch step;
+  double* keep;
+  uint64_t keep_mask;
+  int K;
+};
+bool cg_step_small_fits(const CgStepSmall& a);
+hipError_t launch_cg_step_small(const CgStepSmall& a, hipStream_t s);
 // gam_new = g . z per column (n x K row-major), p = z + (gam_new / gam_old) p (0 where
 // gam_old <= 0), or p = z when gam_old is null; work as for launch_dot_cols.  gam_old is only
 // read: the caller alternates the two buffers between iterations.  K <= 64.

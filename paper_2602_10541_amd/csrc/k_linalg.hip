@@ -392,6 +392,74 @@ hipError_t launch_cg_step(const double* gam, const double* d1, const double* d2,
   return hipGetLastError();
 }
 
+// One workgroup's column dots of an n x K product in k_dot_small's order (K <= 64): column c's
+// partials over rows r, r + R, ... (R the largest power of two with R K <= 1024), then a fixed
+// pairwise tree; out[c] written by thread c, and the block synchronised on return.
+__device__ void dot_cols_wg(const double* __restrict__ x, const double* __restrict__ y, int64_t n, int K,
+                            double* __restrict__ out, double* red) {
+  const int t = threadIdx.x;
+  int R = 1;
+  while (R * 2 * K <= kDotSmallWg) R *= 2;
+  const int c = t % K, r = t / K;
+  double s = 0.0;
+  if (r < R)
+    for (int64_t i = r; i < n; i += R) s = fma(x[i * K + c], y[i * K + c], s);
+  red[t] = s;
+  __syncthreads();
+  for (int h = R / 2; h > 0; h >>= 1) {
+    if (r < h) red[r * K + c] += red[(r + h) * K + c];
+    __syncthreads();
+  }
+  if (t < K) out[t] = red[t];
+  __syncthreads();
+}
+
+// The whole CG step of small systems in one workgroup: the dots of the step's products (the
+// first launch_dot_batch), alpha and the updates (launch_cg_step), then the dots after the step
+// (the second launch_dot_batch), each in the order the separate launches use.
+__global__ __launch_bounds__(kDotSmallWg) void k_cg_step_small(CgStepSmall a) {
+  __shared__ double red[kDotSmallWg];
+  __shared__ double salpha[64];
+  const int K = a.K, t = threadIdx.x;
+  for (int q = 0; q < a.n_pre; ++q) dot_cols_wg(a.pre[q], a.pre[q], a.pre_n[q], K, a.pre_out[q], red);
+  if (t < K) {
+    const double al = cg_alpha_of(t, a.gam, a.d1, a.d2, a.mu, a.active);
+    salpha[t] = al;
+    a.alpha_out[t] = al;
+  }
+  __syncthreads();
+  for (int q = 0; q < a.step.count; ++q) {
+    const int64_t tot = a.step.n[q] * K;
+    const double sg = a.step.sign[q];
+    for (int64_t e = t; e < tot; e += kDotSmallWg) {
+      const int k = (int)(e % K);
+      const double yo = a.step.y[q][e];
+      if (q == 0 && a.keep && ((a.keep_mask >> k) & 1ull)) a.keep[e] = yo;
+      a.step.y[q][e] = fma(sg * salpha[k], a.step.x[q][e], yo);
+    }
+  }
+  __syncthreads();
+  for (int q = 0; q < a.n_post; ++q) dot_cols_wg(a.post[q], a.post[q], a.post_n[q], K, a.post_out[q], red);
+}
+
+bool cg_step_small_fits(const CgStepSmall& a) {
+  if (a.K < 1 || a.K > 64) return false;
+  for (int q = 0; q < a.n_pre; ++q)
+    if (a.pre_n[q] * a.K > kDotSmallMax) return false;
+  for (int q = 0; q < a.n_post; ++q)
+    if (a.post_n[q] * a.K > kDotSmallMax) return false;
+  for (int q = 0; q < a.step.count; ++q)
+    if (a.step.n[q] * a.K > kDotSmallMax) return false;
+  return true;
+}
+
+hipError_t launch_cg_step_small(const CgStepSmall& a, hipStream_t s) {
+  if (!cg_step_small_fits(a) || a.n_pre > 4 || a.n_post > 2 || a.step.count < 1 || a.step.count > kAxpyBatchMax)
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_cg_step_small, dim3(1), dim3(kDotSmallWg), 0, s, a);
+  return hipGetLastError();
+}
+
 // gam_new = g . z per column, beta = gam_new / gam_old (0 when gam_old <= 0), p = z + beta p;
 // with gam_old null, p = z (the first direction; p is not read).  Small vectors
 // (n K <= kDotSmallMax): one workgroup does all three, with k_dot_small's reduction order;
