@@ -307,9 +307,7 @@ struct ColScalars {
 // y[i][c] += sign * a[c] * x[i][c]
 hipError_t launch_axpy_cols(const ColScalars& a, const double* x, double* y, int64_t n, int K, double sign,
                             hipStream_t s);
-// p[i][c] = z[i][c] + b[c] * p[i][c]
-hipError_t launch_xpby_cols(const double* z, const ColScalars& b, double* p, int64_t n, int K, hipStream_t s);
-hipError_t launch_count_nonfinite(const double* x, int64_t n, int* flag, hipStream_t s);
+
 // NaN / Inf scans of several arrays in one launch: flags[q * wgs + w] for item q and its
 // workgroups w < wgs = finite_batch_wgs(fb) (each written, 0 or 1, so nothing needs clearing;
 // an item is bad if any of its flags is).

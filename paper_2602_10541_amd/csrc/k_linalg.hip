@@ -339,20 +339,6 @@ hipError_t launch_axpy_cols(const ColScalars& a, const double* x, double* y, int
   return hipGetLastError();
 }
 
-__global__ void k_xpby_cols(const double* z, ColScalars b, double* p, int64_t n, int K) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n * K) return;
-  p[e] = fma(b.v[e % K], p[e], z[e]);
-}
-
-hipError_t launch_xpby_cols(const double* z, const ColScalars& b, double* p, int64_t n, int K, hipStream_t s) {
-  const int64_t tot = n * K;
-  if (tot == 0) return hipSuccess;
-  if (K < 1 || K > 64) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_xpby_cols, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, z, b, p, n, K);
-  return hipGetLastError();
-}
-
 // CG steps with their scalars kept on the device (the host reads them once per iteration for
 // its stopping decisions instead of round-tripping each one).  The step length of column k:
 // alpha_k = gam_k / (d1_k + mu d2_k) for active columns with both positive, else 0 (d2 nullable).
@@ -534,17 +520,6 @@ hipError_t launch_select_cols(const double* src, double* dst, int64_t n, int K, 
   if (tot == 0 || mask == 0) return hipSuccess;
   if (K < 1 || K > 64) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_select_cols, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, src, dst, n, K, mask);
-  return hipGetLastError();
-}
-
-__global__ void k_nonfinite(const double* x, int64_t n, int* flag) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n && !isfinite(x[i])) atomicOr(flag, 1);
-}
-
-hipError_t launch_count_nonfinite(const double* x, int64_t n, int* flag, hipStream_t s) {
-  if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_nonfinite, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, n, flag);
   return hipGetLastError();
 }
 
